@@ -1,0 +1,133 @@
+"""Truncated SVD by definition (O-def) and by RRSVD step by step (O-alg).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
+
+All arithmetic is complex128 / float64 on the CPU through numpy and scipy's
+LAPACK.  No blocking, fusion or reordering beyond what the definitions state.
+
+Paper: Tamascelli, Rosenbach, Plenio, arXiv:1504.00992.
+"""
+import numpy as np
+import scipy.linalg
+
+# Per-problem status bits (same meaning on both sides; the values are part of
+# the published C interface, restated here so the oracle needs no header).
+STATUS_CHI_BOUND = 16
+
+
+def lapack_svd(a):
+    """Thin SVD by LAPACK's gesvd; singular values sorted descending.
+
+    Sec. IV: A = U Sigma V^H with sigma_1 >= sigma_2 >= ...
+    """
+    u, s, vh = scipy.linalg.svd(np.asarray(a, dtype=np.complex128),
+                                full_matrices=False, lapack_driver="gesvd")
+    return u, s, vh
+
+
+def truncation_rank(weights, chi_max, eps):
+    """Bond dimension kept after truncation, its discarded weight, status.
+
+    weights[c-1] = w(c), the relative discarded weight of keeping the first c
+    singular values (Sec. II.C, Eq. defdiscweigt, divided by ||A||_F^2).
+    Rule: chi' = min(chi_max, smallest c >= 1 with w(c) <= eps), c ranging
+    over the available values.  eps <= 0 means fixed rank
+    chi' = min(chi_max, len(weights)).  Returns (chi', w(chi'), status) with
+    status = STATUS_CHI_BOUND when no c <= chi_max meets a positive eps.
+    """
+    w = np.asarray(weights, dtype=np.float64)
+    cap = min(int(chi_max), len(w))
+    if eps <= 0.0:
+        return cap, float(max(w[cap - 1], 0.0)), 0
+    ok = np.nonzero(w <= eps)[0]
+    if len(ok) and ok[0] + 1 <= cap:
+        c = int(ok[0]) + 1
+        return c, float(max(w[c - 1], 0.0)), 0
+    return cap, float(max(w[cap - 1], 0.0)), STATUS_CHI_BOUND
+
+
+def tail_weights(sig):
+    """w(c) = sum_{j>c} sigma_j^2 / sum_j sigma_j^2 (the plain definition)."""
+    s2 = np.asarray(sig, dtype=np.float64) ** 2
+    total = np.sum(s2)
+    if total <= 0.0:
+        return np.zeros(len(s2))
+    tails = np.array([np.sum(s2[c:]) for c in range(1, len(s2) + 1)])
+    return tails / total
+
+
+def frobenius_weights(sig, frob2):
+    """w(c) = (||A||_F^2 - sum_{j<=c} sigma_j^2) / ||A||_F^2.
+
+    The Frobenius-norm identity of Sec. IV (||(I - QQ^H)A||_F^2 =
+    ||A||_F^2 - ||Q^H A||_F^2, with Q the kept left singular vectors) turns
+    the l values an RRSVD returns, plus ||A||_F^2 from the entries of A,
+    into the discarded weight of every rank c <= l.
+    """
+    s2 = np.asarray(sig, dtype=np.float64) ** 2
+    if frob2 <= 0.0:
+        return np.zeros(len(s2))
+    return (frob2 - np.cumsum(s2)) / frob2
+
+
+def truncate_full_svd(a, chi_max, eps):
+    """O-def: best rank-chi' factors of A from a full LAPACK SVD.
+
+    Sec. IV: keep the chi' largest singular triplets (Eckart-Young).  The
+    discarded weight is the plain definition sum_{j>chi'} sigma_j^2 divided
+    by ||A||_F^2 = sum_j sigma_j^2.
+    Returns (U[:, :chi'], s[:chi'], Vh[:chi', :], chi', w, status).
+    """
+    u, s, vh = lapack_svd(a)
+    chi, w, status = truncation_rank(tail_weights(s), chi_max, eps)
+    return u[:, :chi], s[:chi], vh[:chi, :], chi, w, status
+
+
+def sketch_width(k, p, m, n):
+    """l = min(k + p, m, n): Alg. 1 needs l columns, at most the rank bound."""
+    return int(min(k + p, m, n))
+
+
+def rrsvd_range(a, omega, q):
+    """Alg. 1 (randomized range finder with q power iterations).
+
+    Y0 = A Omega, Y0 = Q0 R0; for j = 1..q: Yt_j = A^H Q_{j-1} = Qt_j Rt_j,
+    Y_j = A Qt_j = Q_j R_j.  Returns Q_q (m x l, orthonormal columns).
+    QR factorisations are Householder (LAPACK geqrf/ungqr via numpy).
+    """
+    a = np.asarray(a, dtype=np.complex128)
+    y = a @ omega
+    qmat, _ = np.linalg.qr(y)
+    for _ in range(q):
+        yt = a.conj().T @ qmat
+        qt, _ = np.linalg.qr(yt)
+        y = a @ qt
+        qmat, _ = np.linalg.qr(y)
+    return qmat
+
+
+def rrsvd(a, omega, q):
+    """Alg. 1 followed by steps i-iii of Sec. IV.
+
+    i) B = Q^H A;  ii) B = Ut Sigma V^H (LAPACK gesvd);  iii) U = Q Ut.
+    Returns (U, s, Vh) with l = omega.shape[1] triplets.
+    """
+    a = np.asarray(a, dtype=np.complex128)
+    qmat = rrsvd_range(a, omega, q)
+    b = qmat.conj().T @ a
+    ut, s, vh = lapack_svd(b)
+    return qmat @ ut, s, vh
+
+
+def truncate_rrsvd(a, omega, q, chi_max, eps):
+    """O-alg: RRSVD with the given Omega, then the truncation rule.
+
+    The discarded weight uses the Frobenius identity of Sec. IV with
+    ||A||_F^2 taken from the entries of A (the RRSVD only sees l values).
+    Returns (U[:, :chi'], s[:chi'], Vh[:chi', :], chi', w, status).
+    """
+    a = np.asarray(a, dtype=np.complex128)
+    u, s, vh = rrsvd(a, omega, q)
+    frob2 = float(np.vdot(a, a).real)
+    chi, w, status = truncation_rank(frobenius_weights(s, frob2), chi_max, eps)
+    return u[:, :chi], s[:chi], vh[:chi, :], chi, w, status
