@@ -1,0 +1,192 @@
+/*
+ * tebd_rrsvd.h -- C interface of the MI355X TEBD bond-update library.
+ *
+ * Method: Tamascelli, Rosenbach, Plenio, "Improved scaling of Time-Evolving
+ * Block-Decimation algorithm through Reduced-Rank Randomized Singular Value
+ * Decomposition", arXiv:1504.00992.  The two-site TEBD update (Sec. II.B:
+ * Theta of Eq. deftheta, the gate update of Eq. defupdatetheta, the blocked
+ * matrix, extraction of the new Gamma and lambda) with the SVD replaced by
+ * the reduced-rank randomized SVD (Sec. IV: Alg. 1 and steps i-iii).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Scalars: complex values are tebd_z, two interleaved IEEE doubles
+ *   (re, im), the layout of C99 double _Complex and torch.complex128.
+ * Memory: every pointer named "device" is HIP device memory on the current
+ *   device, allocated and owned by the caller.  The library never allocates,
+ *   frees or keeps device memory; scratch comes from the caller's workspace
+ *   (size from tebd_workspace_size).  "host" pointers are read during the
+ *   call only.
+ * Streams: calls only enqueue work on `stream` (a hipStream_t, NULL = the
+ *   null stream) and return; outputs are valid once the stream has been
+ *   synchronised.  Calls on one stream run in order; concurrent calls need
+ *   distinct workspaces.
+ * Errors: arguments are checked on the host before anything is enqueued.  A
+ *   non-zero tebd_status means nothing was enqueued; tebd_last_error() then
+ *   names the offending argument (thread-local text).  Conditions found on
+ *   the device never abort: they are OR-ed into per-problem status words
+ *   (TEBD_DEV_* bits).
+ * Layouts: matrices are row-major with a leading dimension (elements between
+ *   rows).  Two-site gates are indexed row = i_k * d_{k+1} + i_{k+1}
+ *   (Kronecker order); the blocked Theta has row i_k * chi_l + alpha and
+ *   column i_{k+1} * chi_r + beta.
+ * Randomness: the Gaussian test matrix Omega (Sec. IV, Alg. 1, first step)
+ *   is drawn by Philox4x32-10 (Salmon et al., SC'11).  Entry (r, c) of
+ *   problem `pid` uses counter (r, c, pid, params.stream_id) and key
+ *   (seed & 0xffffffff, seed >> 32); the first two output words x give
+ *   u = (x + 1/2) 2^-32 and the complex normal
+ *   z = sqrt(-2 ln u1) exp(2 pi i u2) / sqrt(2).
+ */
+#ifndef TEBD_RRSVD_H
+#define TEBD_RRSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  double re, im;
+} tebd_z;
+
+/* Host-detected errors; nothing is enqueued when one is returned. */
+typedef enum {
+  TEBD_OK = 0,
+  TEBD_ERR_ARG = 1,       /* null pointer or value out of range          */
+  TEBD_ERR_SHAPE = 2,     /* inconsistent dimensions / leading dims      */
+  TEBD_ERR_WORKSPACE = 3, /* workspace missing, too small or misaligned  */
+  TEBD_ERR_DEVICE = 4     /* a HIP call failed while enqueuing           */
+} tebd_status;
+
+/* Per-problem device status bits. */
+enum {
+  TEBD_DEV_NONFINITE = 1,     /* NaN/Inf met in the input or the factors     */
+  TEBD_DEV_QR_FALLBACK = 2,   /* reserved: fast QR refused, fallback taken   */
+  TEBD_DEV_JACOBI_NOCONV = 4, /* small SVD hit its sweep limit               */
+  TEBD_DEV_LAMBDA_FLOOR = 8,  /* a lambda <= lambda_floor was not inverted   */
+  TEBD_DEV_CHI_BOUND = 16,    /* chi_max (or l) binds before w <= trunc_eps  */
+  TEBD_DEV_BAD_STATE = 32     /* chi or d on the device out of range: the
+                                 problem was skipped, the MPS left as it was */
+};
+
+typedef struct {
+  int32_t chi_max;      /* k: target rank and bond capacity, >= 1              */
+  int32_t p;            /* oversampling, >= 0; sketch width l = min(k+p, m, n) */
+  int32_t q;            /* power iterations of Alg. 1, >= 0                     */
+  int32_t precision;    /* 0: FP64 throughout; 1: sketch and power-iteration
+                           products in complex FP32 (QR, projection, small SVD
+                           stay FP64)                                          */
+  double trunc_eps;     /* keep the smallest chi' whose relative discarded
+                           weight w = 1 - sum_{j<=chi'} s_j^2 / ||A||_F^2 is
+                           <= trunc_eps (Sec. II.C, Eq. defdiscweigt); <= 0:
+                           fixed rank min(chi_max, l)                          */
+  double lambda_floor;  /* lambda <= floor is not inverted (its inverse is 0)  */
+  uint64_t seed;        /* Philox key                                          */
+  uint32_t stream_id;   /* Philox counter word 3 (e.g. a running sweep count)  */
+  uint32_t reserved;    /* must be 0                                           */
+} tebd_params;
+
+/* Fixed-capacity batch of MPS chains in Vidal form (Sec. II.A, Eq. defmps).
+ * Site k of chain c holds d[k] matrices Gamma^[k]i of size chi_k x chi_{k+1},
+ * stored padded at gamma[((c * n_sites + k) * d_max + i) * chi_max^2
+ * + alpha * chi_max + beta].  Bond b (sites b, b+1) holds lambda^[b] at
+ * lambda[(c * (n_sites - 1) + b) * chi_max + j], zero beyond chi_{b+1}.
+ * chi[c * (n_sites + 1) + k] = chi_k with chi_0 = chi_N = 1.  Entries outside
+ * the current chi are kept at zero by the library. */
+typedef struct {
+  int32_t n_chains, n_sites, d_max, chi_max;
+  const int32_t* d; /* device [n_sites], 1 <= d[k] <= d_max                    */
+  tebd_z* gamma;    /* device, see above                                       */
+  double* lambda;   /* device, see above                                       */
+  int32_t* chi;     /* device [n_chains][n_sites + 1]                          */
+} tebd_mps;
+
+/* Text of the last error on this thread ("" if none). */
+const char* tebd_last_error(void);
+
+/* Library version string. */
+const char* tebd_version(void);
+
+/* Bytes of workspace needed.
+ *  - For tebd_bond_update / tebd_sweep: pass mps (non-NULL), batch = 0,
+ *    m = n = NULL.  The size covers one sweep over every chain.
+ *  - For rrsvd_truncate: pass mps = NULL, the batch size and the host arrays
+ *    m[batch], n[batch].
+ * Returns TEBD_ERR_ARG / TEBD_ERR_SHAPE for invalid input. */
+tebd_status tebd_workspace_size(const tebd_mps* mps, int64_t batch, const int64_t* m,
+                                const int64_t* n, const tebd_params* prm, size_t* bytes);
+
+/* Batched truncated SVD by RRSVD (Sec. IV: Alg. 1 with q power iterations
+ * re-orthonormalised by Householder QR, then B = Q^H A, the SVD of B and
+ * U = Q U_B; singular values sorted descending), followed by the truncation
+ * rule on the relative discarded weight.  Drop-in for a truncated SVD call.
+ *
+ *  batch          number of problems (>= 1)
+ *  m, n           host [batch]: rows / columns of problem b (>= 1)
+ *  A              host [batch] of device pointers: m_b x n_b row-major,
+ *                 leading dimension lda[b] >= n_b; read only
+ *  lda            host [batch]
+ *  omega          NULL: draw Omega from prm->seed (problem id b);
+ *                 else host [batch] of device pointers to n_b x l_b row-major
+ *                 test matrices (l_b = min(chi_max + p, m_b, n_b))
+ *  U              host [batch] of device pointers: m_b x chi_max row-major,
+ *                 leading dimension ldu >= chi_max; columns >= chi' zeroed
+ *  S              host [batch] of device pointers: chi_max doubles, sorted
+ *                 descending (not renormalised); entries >= chi' zeroed
+ *  VH             host [batch] of device pointers: chi_max x n_b row-major,
+ *                 leading dimension ldvh >= max n_b; rows >= chi' zeroed
+ *  chi_kept       device [batch]: chi'
+ *  disc_weight    device [batch]: relative discarded weight w of chi'
+ *  dev_status     device [batch]: TEBD_DEV_* bits (overwritten)
+ *  workspace      device, 256-byte aligned, ws_bytes from tebd_workspace_size
+ */
+tebd_status rrsvd_truncate(int64_t batch, const int64_t* m, const int64_t* n,
+                           const tebd_z* const* A, const int64_t* lda,
+                           const tebd_z* const* omega, const tebd_params* prm,
+                           tebd_z* const* U, int64_t ldu, double* const* S,
+                           tebd_z* const* VH, int64_t ldvh, int32_t* chi_kept,
+                           double* disc_weight, int32_t* dev_status, void* workspace,
+                           size_t ws_bytes, void* stream);
+
+/* One two-site update of bond `bond` (sites bond, bond+1) of chain `chain`
+ * (Sec. II.B): Theta from Gamma-lambda-Gamma (Eq. deftheta), the gate
+ * (Eq. defupdatetheta), the blocked matrix, its RRSVD truncation to chi',
+ * lambda' = s / ||s|| (renormalised, Sec. II.C) and the new Gamma by
+ * lambda^-1 reabsorption: Gamma'^[k]i_{a g} = U_{(i a), g} / lambda^[k-1]_a,
+ * Gamma'^[k+1]j_{g b} = V^H_{g, (j b)} / lambda^[k+1]_b (lambda outside the
+ * chain = 1; lambda <= lambda_floor gives 0 and sets TEBD_DEV_LAMBDA_FLOOR).
+ *
+ *  mps          the chain batch (updated in place on the device)
+ *  gate         device: (d_k d_{k+1}) x (d_k d_{k+1}) complex, row-major
+ *               with leading dimension d_max^2
+ *  disc_weight  device [1]: relative discarded weight
+ *  dev_status   device [1]: TEBD_DEV_* bits (overwritten)
+ *  Omega problem id: chain * (n_sites - 1) + bond. */
+tebd_status tebd_bond_update(const tebd_mps* mps, int32_t chain, int32_t bond,
+                             const tebd_z* gate, const tebd_params* prm, double* disc_weight,
+                             int32_t* dev_status, void* workspace, size_t ws_bytes,
+                             void* stream);
+
+/* One sweep of non-overlapping two-site gates (Sec. II.C, Eq. defst3rd: the
+ * bonds of one parity commute and are updated together), over every chain.
+ *
+ *  parity             0: bonds 0, 2, 4, ...;  1: bonds 1, 3, 5, ...
+ *  gates              device: gate of bond b of chain c at
+ *                     gates + c * gate_chain_stride + b * d_max^4, each laid
+ *                     out as in tebd_bond_update
+ *  gate_chain_stride  elements between chains' gate sets (0: shared)
+ *  disc_weight        device [n_chains][n_sites - 1]: written for the bonds
+ *                     of this parity
+ *  dev_status         device [n_chains][n_sites - 1]: same
+ *  Omega problem id of bond b of chain c: c * (n_sites - 1) + b. */
+tebd_status tebd_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate_chain_stride,
+                       int32_t parity, const tebd_params* prm, double* disc_weight,
+                       int32_t* dev_status, void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TEBD_RRSVD_H */

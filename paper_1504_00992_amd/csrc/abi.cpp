@@ -1,0 +1,385 @@
+// Host side of the C interface declared in include/tebd_rrsvd.h: argument
+// validation, workspace planning and the launch sequence of the bond update.
+//
+// Launch sequence of one batch (Tamascelli, Rosenbach, Plenio,
+// arXiv:1504.00992): [TEBD: Theta build, Eq. deftheta, and gate,
+// Eq. defupdatetheta] -> Omega -> Alg. 1 (Y0 = A Omega, QR; q times
+// A^H Q, QR, A Q~, QR) -> B^H = A^H Q and its QR (Sec. IV step i) -> small
+// SVD (step ii) -> truncation rule (Sec. II.C) -> U = Q X, V^H = (Q_B W)^H
+// with lambda^-1 reabsorption (step iii and Sec. II.B).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace tebd;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+tebd_status fail(tebd_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+tebd_status ok() {
+  g_err[0] = '\0';
+  return TEBD_OK;
+}
+
+tebd_status check_params(const tebd_params* prm) {
+  if (!prm) return fail(TEBD_ERR_ARG, "argument prm is NULL");
+  if (prm->chi_max < 1) return fail(TEBD_ERR_ARG, "prm->chi_max = %d must be >= 1", prm->chi_max);
+  if (prm->p < 0) return fail(TEBD_ERR_ARG, "prm->p = %d must be >= 0", prm->p);
+  if (prm->q < 0 || prm->q > 64) return fail(TEBD_ERR_ARG, "prm->q = %d must be in [0, 64]", prm->q);
+  if (prm->precision != 0 && prm->precision != 1)
+    return fail(TEBD_ERR_ARG, "prm->precision = %d must be 0 or 1", prm->precision);
+  if (!std::isfinite(prm->trunc_eps))
+    return fail(TEBD_ERR_ARG, "prm->trunc_eps must be finite");
+  if (!(prm->lambda_floor >= 0.0) || !std::isfinite(prm->lambda_floor))
+    return fail(TEBD_ERR_ARG, "prm->lambda_floor must be finite and >= 0");
+  if (prm->reserved != 0) return fail(TEBD_ERR_ARG, "prm->reserved must be 0");
+  return TEBD_OK;
+}
+
+tebd_status check_mps(const tebd_mps* mps, const tebd_params* prm) {
+  if (!mps) return fail(TEBD_ERR_ARG, "argument mps is NULL");
+  if (mps->n_chains < 1) return fail(TEBD_ERR_SHAPE, "mps->n_chains = %d must be >= 1", mps->n_chains);
+  if (mps->n_sites < 2) return fail(TEBD_ERR_SHAPE, "mps->n_sites = %d must be >= 2", mps->n_sites);
+  if (mps->d_max < 1) return fail(TEBD_ERR_SHAPE, "mps->d_max = %d must be >= 1", mps->d_max);
+  if (mps->chi_max < 1) return fail(TEBD_ERR_SHAPE, "mps->chi_max = %d must be >= 1", mps->chi_max);
+  if (!mps->d) return fail(TEBD_ERR_ARG, "mps->d is NULL");
+  if (!mps->gamma) return fail(TEBD_ERR_ARG, "mps->gamma is NULL");
+  if (!mps->lambda) return fail(TEBD_ERR_ARG, "mps->lambda is NULL");
+  if (!mps->chi) return fail(TEBD_ERR_ARG, "mps->chi is NULL");
+  if (int64_t(mps->d_max) * mps->chi_max > kMaxRows)
+    return fail(TEBD_ERR_SHAPE, "d_max * chi_max = %lld exceeds the supported %d",
+                (long long)(int64_t(mps->d_max) * mps->chi_max), kMaxRows);
+  if (prm && prm->chi_max > mps->chi_max)
+    return fail(TEBD_ERR_SHAPE, "prm->chi_max = %d exceeds the MPS capacity mps->chi_max = %d",
+                prm->chi_max, mps->chi_max);
+  if (prm) {
+    const int64_t mc = int64_t(mps->d_max) * mps->chi_max;
+    const int64_t l = int64_t(prm->chi_max) + prm->p < mc ? int64_t(prm->chi_max) + prm->p : mc;
+    if (l > kMaxL) return fail(TEBD_ERR_SHAPE, "sketch width %lld exceeds the supported %d", (long long)l, kMaxL);
+  }
+  return TEBD_OK;
+}
+
+int sketch_l(int64_t k, int64_t p, int64_t m, int64_t n) {
+  int64_t l = k + p;
+  if (l > m) l = m;
+  if (l > n) l = n;
+  return int(l);
+}
+
+// Workspace plan of a TEBD sweep: descriptors for the largest parity, then
+// one capacity-sized slab per problem.
+struct SweepPlan {
+  int64_t pmax;
+  int64_t mcap, lcap, npart;
+  size_t desc_bytes, slab_sz, total;
+};
+
+SweepPlan plan_sweep(const tebd_mps& mps, const tebd_params& prm) {
+  SweepPlan s;
+  const int64_t nb = mps.n_sites / 2;  // bonds of parity 0 (the larger set)
+  s.pmax = int64_t(mps.n_chains) * nb;
+  s.mcap = int64_t(mps.d_max) * mps.chi_max;
+  s.lcap = sketch_l(prm.chi_max, prm.p, s.mcap, s.mcap);
+  s.npart = int64_t((mps.d_max * mps.d_max + 63) / 64) * ((int64_t(mps.chi_max) * mps.chi_max + 63) / 64);
+  s.desc_bytes = align256(size_t(s.pmax) * sizeof(Prob));
+  s.slab_sz = slab_bytes(s.mcap, s.mcap, s.lcap, 1, prm.precision, s.npart);
+  s.total = s.desc_bytes + size_t(s.pmax) * s.slab_sz;
+  return s;
+}
+
+// Pinned staging ring for descriptor uploads of the standalone RRSVD.  Each
+// slot is reused only after the copy that last read it has completed.
+struct Staging {
+  std::mutex mu;
+  static constexpr int kSlots = 4;
+  char* buf[kSlots] = {nullptr, nullptr, nullptr, nullptr};
+  size_t cap[kSlots] = {0, 0, 0, 0};
+  hipEvent_t ev[kSlots] = {nullptr, nullptr, nullptr, nullptr};
+  int next = 0;
+};
+Staging g_stage;
+
+hipError_t upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_stage.mu);
+  const int k = g_stage.next;
+  g_stage.next = (k + 1) % Staging::kSlots;
+  hipError_t e;
+  if (g_stage.ev[k]) {
+    e = hipEventSynchronize(g_stage.ev[k]);
+    if (e != hipSuccess) return e;
+  } else {
+    e = hipEventCreateWithFlags(&g_stage.ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  if (g_stage.cap[k] < bytes) {
+    if (g_stage.buf[k]) {
+      e = hipHostFree(g_stage.buf[k]);
+      if (e != hipSuccess) return e;
+      g_stage.buf[k] = nullptr;
+      g_stage.cap[k] = 0;
+    }
+    size_t want = bytes < (1u << 16) ? (1u << 16) : bytes;
+    e = hipHostMalloc(reinterpret_cast<void**>(&g_stage.buf[k]), want, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    g_stage.cap[k] = want;
+  }
+  std::memcpy(g_stage.buf[k], src, bytes);
+  e = hipMemcpyAsync(dst, g_stage.buf[k], bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(g_stage.ev[k], s);
+}
+
+hipError_t run_pipeline(Prob* probs, const Common& c, hipStream_t s) {
+  hipError_t e;
+#define TRY(x)                     \
+  do {                             \
+    e = (x);                       \
+    if (e != hipSuccess) return e; \
+  } while (0)
+  if (c.tebd)
+    TRY(launch_theta_gate(probs, c, s));
+  else
+    TRY(launch_frob(probs, c, s));
+  TRY(launch_omega(probs, c, s));
+  TRY(launch_sketch(probs, c, SK_Y_FROM_OMEGA, s));
+  TRY(launch_qr(probs, c, 0, 0, s));
+  for (int j = 0; j < c.q; ++j) {
+    TRY(launch_sketch(probs, c, SK_YT_FROM_Y, s));
+    TRY(launch_qr(probs, c, 1, 0, s));
+    TRY(launch_sketch(probs, c, SK_Y_FROM_YT, s));
+    TRY(launch_qr(probs, c, 0, 0, s));
+  }
+  TRY(launch_sketch(probs, c, SK_YT_FROM_Y, s));  // B^H = A^H Q
+  TRY(launch_qr(probs, c, 1, 1, s));               // B^H = Q_B R_B
+  TRY(launch_small_svd(probs, c, s));
+  TRY(launch_truncate(probs, c, s));
+  TRY(launch_form_uv(probs, c, s));
+#undef TRY
+  return hipSuccess;
+}
+
+tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate_chain_stride,
+                          int32_t parity, int32_t single_chain, int32_t single_bond,
+                          const tebd_params* prm, double* disc, int32_t* status, void* ws,
+                          size_t ws_bytes, void* stream) {
+  const SweepPlan pl = plan_sweep(*mps, *prm);
+  if (!ws) return fail(TEBD_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(TEBD_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < pl.total)
+    return fail(TEBD_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, pl.total);
+  Common c;
+  const int64_t nb = (mps->n_sites - parity) / 2;
+  c.nprob = single_chain >= 0 ? 1 : int32_t(int64_t(mps->n_chains) * nb);
+  c.q = prm->q;
+  c.eps = prm->trunc_eps;
+  c.seed = prm->seed;
+  c.stream_id = prm->stream_id;
+  c.mmax = int32_t(pl.mcap);
+  c.nmax = int32_t(pl.mcap);
+  c.lmax = int32_t(pl.lcap);
+  c.kcap = prm->chi_max;
+  c.tebd = 1;
+  c.dmax = mps->d_max;
+  c.chimax = mps->chi_max;
+  if (c.nprob == 0) return ok();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Prob* probs = reinterpret_cast<Prob*>(ws);
+  char* slabs = reinterpret_cast<char*>(ws) + pl.desc_bytes;
+  hipError_t e = launch_plan_sweep(probs, c, *mps, reinterpret_cast<const zt*>(gates),
+                                   gate_chain_stride, parity, single_chain, single_bond, prm->p,
+                                   slabs, pl.slab_sz, disc, status, prm->lambda_floor,
+                                   prm->precision, s);
+  if (e == hipSuccess) e = run_pipeline(probs, c, s);
+  if (e != hipSuccess) return fail(TEBD_ERR_DEVICE, "HIP error while enqueuing: %s", hipGetErrorString(e));
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tebd_last_error(void) { return g_err; }
+
+const char* tebd_version(void) { return "tebd_rrsvd 0.1 (gfx950, complex128)"; }
+
+tebd_status tebd_workspace_size(const tebd_mps* mps, int64_t batch, const int64_t* m,
+                                const int64_t* n, const tebd_params* prm, size_t* bytes) {
+  if (!bytes) return fail(TEBD_ERR_ARG, "argument bytes is NULL");
+  tebd_status st = check_params(prm);
+  if (st != TEBD_OK) return st;
+  if (mps) {
+    st = check_mps(mps, prm);
+    if (st != TEBD_OK) return st;
+    *bytes = plan_sweep(*mps, *prm).total;
+    return ok();
+  }
+  if (batch < 1) return fail(TEBD_ERR_ARG, "batch = %lld must be >= 1", (long long)batch);
+  if (!m || !n) return fail(TEBD_ERR_ARG, "m and n must be host arrays when mps is NULL");
+  size_t total = align256(size_t(batch) * sizeof(Prob));
+  for (int64_t b = 0; b < batch; ++b) {
+    if (m[b] < 1 || n[b] < 1 || m[b] > kMaxRows || n[b] > kMaxRows)
+      return fail(TEBD_ERR_SHAPE, "problem %lld: m = %lld, n = %lld out of range [1, %d]",
+                  (long long)b, (long long)m[b], (long long)n[b], kMaxRows);
+    const int l = sketch_l(prm->chi_max, prm->p, m[b], n[b]);
+    if (l > kMaxL) return fail(TEBD_ERR_SHAPE, "problem %lld: sketch width %d > %d", (long long)b, l, kMaxL);
+    total += slab_bytes(m[b], n[b], l, 0, prm->precision, 0);
+  }
+  *bytes = total;
+  return ok();
+}
+
+tebd_status rrsvd_truncate(int64_t batch, const int64_t* m, const int64_t* n,
+                           const tebd_z* const* A, const int64_t* lda,
+                           const tebd_z* const* omega, const tebd_params* prm,
+                           tebd_z* const* U, int64_t ldu, double* const* S,
+                           tebd_z* const* VH, int64_t ldvh, int32_t* chi_kept,
+                           double* disc_weight, int32_t* dev_status, void* workspace,
+                           size_t ws_bytes, void* stream) {
+  tebd_status st = check_params(prm);
+  if (st != TEBD_OK) return st;
+  if (batch < 1) return fail(TEBD_ERR_ARG, "argument 1 (batch) = %lld must be >= 1", (long long)batch);
+  if (!m) return fail(TEBD_ERR_ARG, "argument 2 (m) is NULL");
+  if (!n) return fail(TEBD_ERR_ARG, "argument 3 (n) is NULL");
+  if (!A) return fail(TEBD_ERR_ARG, "argument 4 (A) is NULL");
+  if (!lda) return fail(TEBD_ERR_ARG, "argument 5 (lda) is NULL");
+  if (!U) return fail(TEBD_ERR_ARG, "argument 8 (U) is NULL");
+  if (!S) return fail(TEBD_ERR_ARG, "argument 10 (S) is NULL");
+  if (!VH) return fail(TEBD_ERR_ARG, "argument 11 (VH) is NULL");
+  if (!chi_kept) return fail(TEBD_ERR_ARG, "argument 13 (chi_kept) is NULL");
+  if (!disc_weight) return fail(TEBD_ERR_ARG, "argument 14 (disc_weight) is NULL");
+  if (!dev_status) return fail(TEBD_ERR_ARG, "argument 15 (dev_status) is NULL");
+  if (ldu < prm->chi_max)
+    return fail(TEBD_ERR_SHAPE, "argument 9 (ldu) = %lld < chi_max = %d", (long long)ldu, prm->chi_max);
+  int64_t nmax = 0;
+  for (int64_t b = 0; b < batch; ++b) nmax = n[b] > nmax ? n[b] : nmax;
+  if (ldvh < nmax)
+    return fail(TEBD_ERR_SHAPE, "argument 12 (ldvh) = %lld < max n = %lld", (long long)ldvh, (long long)nmax);
+  for (int64_t b = 0; b < batch; ++b) {
+    if (m[b] < 1 || n[b] < 1 || m[b] > kMaxRows || n[b] > kMaxRows)
+      return fail(TEBD_ERR_SHAPE, "problem %lld: m = %lld, n = %lld out of range [1, %d]",
+                  (long long)b, (long long)m[b], (long long)n[b], kMaxRows);
+    if (lda[b] < n[b])
+      return fail(TEBD_ERR_SHAPE, "problem %lld: lda = %lld < n = %lld", (long long)b,
+                  (long long)lda[b], (long long)n[b]);
+    if (!A[b] || !U[b] || !S[b] || !VH[b])
+      return fail(TEBD_ERR_ARG, "problem %lld: a device pointer in A/U/S/VH is NULL", (long long)b);
+    if (omega && !omega[b])
+      return fail(TEBD_ERR_ARG, "problem %lld: omega[b] is NULL", (long long)b);
+  }
+  size_t need = 0;
+  st = tebd_workspace_size(nullptr, batch, m, n, prm, &need);
+  if (st != TEBD_OK) return st;
+  if (!workspace) return fail(TEBD_ERR_WORKSPACE, "argument 16 (workspace) is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(TEBD_ERR_WORKSPACE, "argument 16 (workspace) must be 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(TEBD_ERR_WORKSPACE, "argument 17 (ws_bytes) = %zu < %zu needed", ws_bytes, need);
+
+  std::vector<Prob> host(batch);
+  char* base = reinterpret_cast<char*>(workspace);
+  char* slab = base + align256(size_t(batch) * sizeof(Prob));
+  Common c;
+  c.nprob = int32_t(batch);
+  c.q = prm->q;
+  c.eps = prm->trunc_eps;
+  c.seed = prm->seed;
+  c.stream_id = prm->stream_id;
+  c.mmax = c.nmax = c.lmax = 0;
+  c.kcap = prm->chi_max;
+  c.tebd = 0;
+  c.dmax = 0;
+  c.chimax = 0;
+  for (int64_t b = 0; b < batch; ++b) {
+    Prob& P = host[b];
+    std::memset(&P, 0, sizeof(Prob));
+    P.m = int32_t(m[b]);
+    P.n = int32_t(n[b]);
+    P.l = sketch_l(prm->chi_max, prm->p, m[b], n[b]);
+    P.kcap = prm->chi_max;
+    P.pid = int32_t(b);
+    P.mixed = prm->precision;
+    carve_slab(P, slab, m[b], n[b], P.l, 0, prm->precision, 0);
+    slab += slab_bytes(m[b], n[b], P.l, 0, prm->precision, 0);
+    P.A = const_cast<zt*>(reinterpret_cast<const zt*>(A[b]));
+    P.lda = lda[b];
+    if (omega) {
+      P.om = reinterpret_cast<const zt*>(omega[b]);
+      P.om_ext = 1;
+    }
+    P.ldom = P.l;
+    P.U = reinterpret_cast<zt*>(U[b]);
+    P.ldu = ldu;
+    P.S = S[b];
+    P.VH = reinterpret_cast<zt*>(VH[b]);
+    P.ldvh = ldvh;
+    P.chi_out = chi_kept + b;
+    P.disc = disc_weight + b;
+    P.status = dev_status + b;
+    c.mmax = P.m > c.mmax ? P.m : c.mmax;
+    c.nmax = P.n > c.nmax ? P.n : c.nmax;
+    c.lmax = P.l > c.lmax ? P.l : c.lmax;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = upload(workspace, host.data(), host.size() * sizeof(Prob), s);
+  if (e == hipSuccess) e = run_pipeline(reinterpret_cast<Prob*>(workspace), c, s);
+  if (e != hipSuccess) return fail(TEBD_ERR_DEVICE, "HIP error while enqueuing: %s", hipGetErrorString(e));
+  return ok();
+}
+
+tebd_status tebd_bond_update(const tebd_mps* mps, int32_t chain, int32_t bond,
+                             const tebd_z* gate, const tebd_params* prm, double* disc_weight,
+                             int32_t* dev_status, void* workspace, size_t ws_bytes,
+                             void* stream) {
+  tebd_status st = check_params(prm);
+  if (st != TEBD_OK) return st;
+  st = check_mps(mps, prm);
+  if (st != TEBD_OK) return st;
+  if (chain < 0 || chain >= mps->n_chains)
+    return fail(TEBD_ERR_ARG, "argument 2 (chain) = %d out of range [0, %d)", chain, mps->n_chains);
+  if (bond < 0 || bond >= mps->n_sites - 1)
+    return fail(TEBD_ERR_ARG, "argument 3 (bond) = %d out of range [0, %d)", bond, mps->n_sites - 1);
+  if (!gate) return fail(TEBD_ERR_ARG, "argument 4 (gate) is NULL");
+  if (!disc_weight) return fail(TEBD_ERR_ARG, "argument 6 (disc_weight) is NULL");
+  if (!dev_status) return fail(TEBD_ERR_ARG, "argument 7 (dev_status) is NULL");
+  return enqueue_sweep(mps, gate, 0, bond & 1, chain, bond, prm, disc_weight, dev_status,
+                       workspace, ws_bytes, stream);
+}
+
+tebd_status tebd_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate_chain_stride,
+                       int32_t parity, const tebd_params* prm, double* disc_weight,
+                       int32_t* dev_status, void* workspace, size_t ws_bytes, void* stream) {
+  tebd_status st = check_params(prm);
+  if (st != TEBD_OK) return st;
+  st = check_mps(mps, prm);
+  if (st != TEBD_OK) return st;
+  if (!gates) return fail(TEBD_ERR_ARG, "argument 2 (gates) is NULL");
+  if (gate_chain_stride < 0)
+    return fail(TEBD_ERR_ARG, "argument 3 (gate_chain_stride) = %lld must be >= 0",
+                (long long)gate_chain_stride);
+  if (parity != 0 && parity != 1)
+    return fail(TEBD_ERR_ARG, "argument 4 (parity) = %d must be 0 or 1", parity);
+  if (!disc_weight) return fail(TEBD_ERR_ARG, "argument 6 (disc_weight) is NULL");
+  if (!dev_status) return fail(TEBD_ERR_ARG, "argument 7 (dev_status) is NULL");
+  return enqueue_sweep(mps, gates, gate_chain_stride, parity, -1, -1, prm, disc_weight,
+                       dev_status, workspace, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,519 @@
+// Wavefront-level kernels of the RRSVD pipeline (one workgroup per problem):
+// planning of a TEBD sweep, ||A||_F^2, the Gaussian test matrix, Householder
+// QR with explicit Q, the small SVD by one-sided Jacobi, and the truncation
+// rule with lambda renormalisation.
+//
+// Paper: Tamascelli, Rosenbach, Plenio, arXiv:1504.00992.  QR steps of Alg. 1
+// (the paper leaves the QR method open; Householder reflections are used
+// because the sketch of a TEBD Theta is often rank deficient), the SVD of
+// B = Q^H A of Sec. IV step ii (computed as B^H = Q_B R_B, then a one-sided
+// Jacobi SVD of R_B^H, which keeps small singular values to high relative
+// accuracy), and the discarded weight of Sec. II.C, Eq. (defdiscweigt),
+// evaluated with the Frobenius identity of Sec. IV.
+#include <cfloat>
+
+#include "zdev.hpp"
+
+namespace tebd {
+
+// --------------------------------------------------------------------------
+// TEBD sweep planning: one thread per (chain, bond of the parity).
+__global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gates,
+                             int64_t gate_chain_stride, int parity, int single_chain,
+                             int single_bond, int kcap, int p_over, char* slab_base,
+                             size_t slab_sz, int64_t mcap, int64_t ncap, int64_t lcap,
+                             int64_t npart_cap, double* disc, int32_t* status,
+                             double lambda_floor, int mixed) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  const int N = mps.n_sites, cap = mps.chi_max, dmax = mps.d_max;
+  const int nb = (N - 1 - parity + 1) / 2;
+  int chain, bond;
+  if (single_chain >= 0) {
+    chain = single_chain;
+    bond = single_bond;
+  } else {
+    chain = p / nb;
+    bond = parity + 2 * (p - chain * nb);
+  }
+  Prob P;
+  const int32_t* chi = mps.chi + size_t(chain) * (N + 1);
+  const int cl = chi[bond], cm = chi[bond + 1], cr = chi[bond + 2];
+  const int dl = mps.d[bond], dr = mps.d[bond + 1];
+  const bool bad = cl < 1 || cl > cap || cm < 1 || cm > cap || cr < 1 || cr > cap || dl < 1 ||
+                   dl > dmax || dr < 1 || dr > dmax;
+  P.chi_l = cl;
+  P.chi_m = cm;
+  P.chi_r = cr;
+  P.dl = dl;
+  P.dr = dr;
+  P.m = dl * cl;
+  P.n = dr * cr;
+  int l = kcap + p_over;
+  if (l > P.m) l = P.m;
+  if (l > P.n) l = P.n;
+  P.l = bad ? 0 : l;
+  P.kcap = kcap;
+  P.pid = chain * (N - 1) + bond;
+  P.chi_new = 0;
+  P.flags = bad ? TEBD_DEV_BAD_STATE : 0;
+  P.npart = 0;
+  P.mixed = mixed;
+  P.om_ext = 0;
+  P.pad0 = 0;
+  P.frob2 = 0.0;
+  carve_slab(P, slab_base + size_t(p) * slab_sz, mcap, ncap, lcap, 1, mixed, npart_cap);
+  P.lda = P.n;
+  P.ldom = P.l;
+  P.U = nullptr;
+  P.ldu = 0;
+  P.S = nullptr;
+  P.VH = nullptr;
+  P.ldvh = 0;
+  P.chi_out = nullptr;
+  const size_t site_stride = size_t(dmax) * cap * cap;
+  P.gk = mps.gamma ? reinterpret_cast<zt*>(mps.gamma) + (size_t(chain) * N + bond) * site_stride
+                   : nullptr;
+  P.gk1 = P.gk + site_stride;
+  double* lam_chain = mps.lambda + size_t(chain) * (N - 1) * cap;
+  P.lam_l = bond >= 1 ? lam_chain + size_t(bond - 1) * cap : nullptr;
+  P.lam_mid = lam_chain + size_t(bond) * cap;
+  P.lam_r = bond + 1 <= N - 2 ? lam_chain + size_t(bond + 1) * cap : nullptr;
+  P.chi_slot = mps.chi + size_t(chain) * (N + 1) + bond + 1;
+  // single-bond mode: `gates` is that bond's gate
+  P.gate = single_chain >= 0 ? gates
+                             : gates + size_t(chain) * gate_chain_stride +
+                                   size_t(bond) * dmax * dmax * dmax * dmax;
+  P.gate_ld = dmax * dmax;
+  P.chi_cap = cap;
+  P.lambda_floor = lambda_floor;
+  if (single_chain >= 0) {
+    P.disc = disc;
+    P.status = status;
+  } else {
+    P.disc = disc + size_t(chain) * (N - 1) + bond;
+    P.status = status + size_t(chain) * (N - 1) + bond;
+  }
+  probs[p] = P;
+  if (bad) {
+    *P.status = TEBD_DEV_BAD_STATE;
+    *P.disc = 0.0;
+  }
+}
+
+hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, const zt* gates,
+                             int64_t gate_chain_stride, int32_t parity, int32_t single_chain,
+                             int32_t single_bond, int32_t p_over, char* slab_base,
+                             size_t slab_sz, double* disc, int32_t* status, double lambda_floor,
+                             int32_t mixed, hipStream_t s) {
+  const int64_t mcap = int64_t(c.dmax) * c.chimax;
+  const int64_t lcap = c.lmax;
+  const int64_t npart_cap = int64_t((c.dmax * c.dmax + 63) / 64) * ((c.chimax * c.chimax + 63) / 64);
+  hipLaunchKernelGGL(k_plan_sweep, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob, mps,
+                     gates, gate_chain_stride, parity, single_chain, single_bond, c.kcap, p_over,
+                     slab_base, slab_sz, mcap, mcap, lcap, npart_cap, disc, status, lambda_floor,
+                     mixed);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// ||A||_F^2 for caller-supplied matrices (fixed summation order).
+__global__ __launch_bounds__(256) void k_frob(Prob* probs) {
+  __shared__ double red[4];
+  Prob& P = probs[blockIdx.x];
+  if (P.l == 0) return;
+  double s = 0.0;
+  const int64_t total = int64_t(P.m) * P.n;
+  for (int64_t e = threadIdx.x; e < total; e += 256) {
+    const int64_t r = e / P.n, c = e - r * P.n;
+    s += zabs2(P.A[r * P.lda + c]);
+  }
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) P.frob2 = s;
+}
+
+hipError_t launch_frob(Prob* probs, const Common& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_frob, dim3(c.nprob), dim3(256), 0, s, probs);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and the complex Gaussian Omega.
+__device__ __forceinline__ void philox10(uint32_t x[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint32_t hi0 = __umulhi(M0, x[0]), lo0 = M0 * x[0];
+    const uint32_t hi1 = __umulhi(M1, x[2]), lo1 = M1 * x[2];
+    const uint32_t y0 = hi1 ^ x[1] ^ k0, y2 = hi0 ^ x[3] ^ k1;
+    x[0] = y0;
+    x[1] = lo1;
+    x[2] = y2;
+    x[3] = lo0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_omega(Prob* probs, uint64_t seed, uint32_t sid) {
+  const Prob& P = probs[blockIdx.y];
+  if (P.l == 0 || P.om_ext) return;
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t total = int64_t(P.n) * P.l;
+  if (e >= total) return;
+  const int r = int(e / P.l), c = int(e - int64_t(r) * P.l);
+  uint32_t x[4] = {uint32_t(r), uint32_t(c), uint32_t(P.pid), sid};
+  philox10(x, uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32));
+  const double u1 = (double(x[0]) + 0.5) * 0x1p-32;
+  const double u2 = (double(x[1]) + 0.5) * 0x1p-32;
+  const double rad = sqrt(-2.0 * log(u1)) * 0.70710678118654752440;
+  double sn, cs;
+  sincos(2.0 * M_PI * u2, &sn, &cs);
+  const_cast<zt*>(P.om)[size_t(r) * P.ldom + c] = make_double2(rad * cs, rad * sn);
+}
+
+hipError_t launch_omega(Prob* probs, const Common& c, hipStream_t s) {
+  const int64_t total = int64_t(c.nmax) * c.lmax;
+  dim3 g(unsigned((total + 255) / 256), c.nprob);
+  hipLaunchKernelGGL(k_omega, g, dim3(256), 0, s, probs, c.seed, c.stream_id);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Householder QR of a rows x l column-major matrix (ld = rows), in place,
+// followed by the explicit thin Q (backward accumulation).  Reflector j is
+// H_j = I - 2 u u^H with ||u|| = 1, u supported on rows >= j, chosen so that
+// H_j x = beta e_j with beta = -phase(x_j) ||x||; a zero column gives H_j = I.
+// With want_r the l x l upper factor (column-major) is written to P.Rb first.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_qr(Prob* probs, int which, int want_r) {
+  extern __shared__ zt u_s[];  // rows
+  __shared__ double red[NT / 64];
+  __shared__ zt rdiag[kMaxL];
+  Prob& P = probs[blockIdx.x];
+  const int l = P.l;
+  if (l == 0) return;
+  const int rows = which ? P.n : P.m;
+  zt* Y = which ? P.Yt : P.Y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = NT / 64;
+
+  for (int j = 0; j < l; ++j) {
+    zt* yj = Y + size_t(j) * rows;
+    double s = 0.0;
+    for (int r = j + 1 + tid; r < rows; r += NT) s += zabs2(yj[r]);
+    s = block_sum<NT>(s, red);
+    const zt alpha = yj[j];
+    const double aa = sqrt(zabs2(alpha));
+    const double xnorm = sqrt(aa * aa + s);
+    zt beta;
+    double vinv;  // 1 / ||x - beta e_j||
+    zt v0;
+    if (xnorm == 0.0) {
+      beta = make_double2(0.0, 0.0);
+      vinv = 0.0;
+      v0 = make_double2(0.0, 0.0);
+    } else {
+      const zt ph = aa > 0.0 ? zscale(alpha, 1.0 / aa) : make_double2(1.0, 0.0);
+      beta = zscale(ph, -xnorm);
+      v0 = zsub(alpha, beta);
+      vinv = 1.0 / sqrt(2.0 * xnorm * (xnorm + aa));
+    }
+    __syncthreads();  // everyone has read yj[j] before it is overwritten
+    for (int r = j + tid; r < rows; r += NT) {
+      const zt u = zscale(r == j ? v0 : yj[r], vinv);
+      u_s[r] = u;
+      yj[r] = u;
+    }
+    if (tid == 0) rdiag[j] = beta;
+    __syncthreads();
+    if (vinv != 0.0) {
+      for (int c = j + 1 + wave; c < l; c += NW) {
+        zt* yc = Y + size_t(c) * rows;
+        double dr = 0.0, di = 0.0;
+        for (int r = j + lane; r < rows; r += 64) {
+          const zt t = zcmul(u_s[r], yc[r]);
+          dr += t.x;
+          di += t.y;
+        }
+        dr = wave_sum(dr);
+        di = wave_sum(di);
+        const zt d2 = make_double2(2.0 * dr, 2.0 * di);
+        for (int r = j + lane; r < rows; r += 64) yc[r] = zsub(yc[r], zmul(u_s[r], d2));
+      }
+    }
+    __syncthreads();
+  }
+
+  if (want_r) {
+    for (int e = tid; e < l * l; e += NT) {
+      const int c = e / l, i = e - c * l;
+      zt v;
+      if (i < c)
+        v = Y[size_t(c) * rows + i];
+      else if (i == c)
+        v = rdiag[c];
+      else
+        v = make_double2(0.0, 0.0);
+      P.Rb[e] = v;
+    }
+    __syncthreads();
+  }
+
+  // Q = H_0 H_1 ... H_{l-1} [I; 0], accumulated from the last reflector.
+  for (int j = l - 1; j >= 0; --j) {
+    zt* yj = Y + size_t(j) * rows;
+    for (int r = j + tid; r < rows; r += NT) u_s[r] = yj[r];
+    __syncthreads();
+    // trailing columns: row j is treated as zero (it held R entries)
+    for (int c = j + 1 + wave; c < l; c += NW) {
+      zt* yc = Y + size_t(c) * rows;
+      double dr = 0.0, di = 0.0;
+      for (int r = j + 1 + lane; r < rows; r += 64) {
+        const zt t = zcmul(u_s[r], yc[r]);
+        dr += t.x;
+        di += t.y;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      const zt d2 = make_double2(2.0 * dr, 2.0 * di);
+      for (int r = j + lane; r < rows; r += 64) {
+        const zt old = (r == j) ? make_double2(0.0, 0.0) : yc[r];
+        yc[r] = zsub(old, zmul(u_s[r], d2));
+      }
+    }
+    // column j = H_j e_j
+    const zt uj = u_s[j];
+    for (int r = tid; r < rows; r += NT) {
+      zt v;
+      if (r < j) {
+        v = make_double2(0.0, 0.0);
+      } else {
+        v = zscale(zmul(u_s[r], zconj(uj)), -2.0);
+        if (r == j) v.x += 1.0;
+      }
+      yj[r] = v;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStream_t s) {
+  const int rows = which ? c.nmax : c.mmax;
+  const size_t lds = size_t(rows) * sizeof(zt);
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&k_qr<256>), hipFuncAttributeMaxDynamicSharedMemorySize,
+      int(size_t(kMaxRows) * sizeof(zt)));
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL(k_qr<256>, dim3(c.nprob), dim3(256), lds, s, probs, which, want_r);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Small SVD of B (l x n) from B^H = Q_B R_B: one-sided Jacobi on C = R_B^H
+// (l x l).  Column pairs are rotated in the round-robin order of the circle
+// method, l/2 disjoint pairs per round, one pair per wavefront at a time.
+// A pair (p, q) with Gram entries a = |c_p|^2, b = |c_q|^2, g = c_p^H c_q is
+// rotated when |g| > tol sqrt(a b):  phi = arg g, zeta = (b - a) / (2|g|),
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), cs = 1/sqrt(1+t^2), sn = t cs,
+//   c_p <- cs c_p - sn e^{-i phi} c_q,  c_q <- sn c_p + cs e^{-i phi} c_q,
+// which zeroes the (p, q) Gram entry.  The same rotation accumulates into J.
+// At convergence C J... = X Sigma with orthogonal columns, so
+// B = X Sigma (Q_B J)^H: left vectors X (normalised columns), values Sigma,
+// right vectors Q_B J (formed later).  Outputs are sorted descending.
+__device__ __forceinline__ int circle_player(int pos, int round, int lp) {
+  if (pos == 0) return 0;
+  return 1 + (pos - 1 + round) % (lp - 1);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
+  __shared__ double sig_s[kMaxL];
+  __shared__ int perm_s[kMaxL];
+  __shared__ int rotated;
+  Prob& P = probs[blockIdx.x];
+  const int l = P.l;
+  if (l == 0) return;
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  zt* C = P.C;
+  zt* J = P.J;
+  for (int e = tid; e < l * l; e += NT) {
+    const int c = e / l, r = e - c * l;
+    C[e] = zconj(P.Rb[size_t(r) * l + c]);
+    J[e] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  const int lp = l + (l & 1);
+  const double tol = DBL_EPSILON * sqrt(double(l));
+  constexpr int kMaxSweeps = 40;
+  int sweep = 0;
+  bool converged = (l == 1);
+  for (; sweep < kMaxSweeps && !converged; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < lp - 1; ++round) {
+      for (int pr = wave; pr < lp / 2; pr += NW) {
+        const int a = circle_player(pr, round, lp), b = circle_player(lp - 1 - pr, round, lp);
+        const int p = a < b ? a : b, q = a < b ? b : a;
+        if (q >= l) continue;
+        zt* cp = C + size_t(p) * l;
+        zt* cq = C + size_t(q) * l;
+        double app = 0.0, aqq = 0.0, gr = 0.0, gi = 0.0;
+        for (int r = lane; r < l; r += 64) {
+          const zt x = cp[r], y = cq[r];
+          app += zabs2(x);
+          aqq += zabs2(y);
+          const zt t = zcmul(x, y);
+          gr += t.x;
+          gi += t.y;
+        }
+        app = wave_sum(app);
+        aqq = wave_sum(aqq);
+        gr = wave_sum(gr);
+        gi = wave_sum(gi);
+        const double ag = sqrt(gr * gr + gi * gi);
+        if (!(ag > tol * sqrt(app * aqq)) || ag == 0.0) continue;
+        const double zeta = (aqq - app) / (2.0 * ag);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+        const zt em = make_double2(gr / ag, -gi / ag);  // e^{-i phi}
+        for (int r = lane; r < l; r += 64) {
+          const zt x = cp[r], y = zmul(em, cq[r]);
+          cp[r] = zsub(zscale(x, cs), zscale(y, sn));
+          cq[r] = zadd(zscale(x, sn), zscale(y, cs));
+        }
+        zt* jp = J + size_t(p) * l;
+        zt* jq = J + size_t(q) * l;
+        for (int r = lane; r < l; r += 64) {
+          const zt x = jp[r], y = zmul(em, jq[r]);
+          jp[r] = zsub(zscale(x, cs), zscale(y, sn));
+          jq[r] = zadd(zscale(x, sn), zscale(y, cs));
+        }
+        if (lane == 0) rotated = 1;
+      }
+      __syncthreads();
+    }
+    converged = (rotated == 0);
+    __syncthreads();
+  }
+  if (!converged && tid == 0) P.flags |= TEBD_DEV_JACOBI_NOCONV;
+  // column norms
+  for (int c = wave; c < l; c += NW) {
+    double s = 0.0;
+    for (int r = lane; r < l; r += 64) s += zabs2(C[size_t(c) * l + r]);
+    s = wave_sum(s);
+    if (lane == 0) sig_s[c] = sqrt(s);
+  }
+  __syncthreads();
+  for (int j = tid; j < l; j += NT) {
+    const double sj = sig_s[j];
+    int rank = 0;
+    for (int i = 0; i < l; ++i) {
+      const double si = sig_s[i];
+      rank += (si > sj) || (si == sj && i < j);
+    }
+    perm_s[rank] = j;
+  }
+  __syncthreads();
+  for (int e = tid; e < l * l; e += NT) {
+    const int c = e / l, r = e - c * l;
+    const int src = perm_s[c];
+    const double sv = sig_s[src];
+    const zt x = C[size_t(src) * l + r];
+    P.X[e] = sv > 0.0 ? zscale(x, 1.0 / sv) : make_double2(0.0, 0.0);
+    P.W[e] = J[size_t(src) * l + r];
+  }
+  for (int c = tid; c < l; c += NT) P.sig[c] = sig_s[perm_s[c]];
+}
+
+hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_small_svd<256>, dim3(c.nprob), dim3(256), 0, s, probs);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Truncation: chi' = min(chi_max, smallest c with w(c) <= eps), where
+// w(c) = (||A||_F^2 - sum_{j<=c} s_j^2) / ||A||_F^2; eps <= 0 keeps
+// min(chi_max, l).  TEBD: lambda' = s / ||s_{1..chi'}|| and chi' are written
+// into the MPS.  One wavefront per problem; the scans run on lane 0 so the
+// summation order is fixed.
+__global__ __launch_bounds__(64) void k_truncate(Prob* probs, double eps, int tebd) {
+  Prob& P = probs[blockIdx.x];
+  const int l = P.l;
+  if (l == 0) return;
+  const int lane = threadIdx.x;
+  __shared__ int chi_s;
+  __shared__ double norm_s;
+  __shared__ int flags_s;
+  if (lane == 0) {
+    int flags = P.flags;
+    double frob2 = P.frob2;
+    if (tebd) {
+      const int N = P.chi_l * P.chi_r, M = P.dl * P.dr;
+      const int npart = ((M + 63) / 64) * ((N + 63) / 64);
+      frob2 = 0.0;
+      for (int i = 0; i < npart; ++i) frob2 += P.part[i];
+      P.frob2 = frob2;
+    }
+    const int cap = P.kcap < l ? P.kcap : l;
+    double kept = 0.0;
+    int chi = cap;
+    double w = 0.0;
+    bool found = false;
+    bool finite = isfinite(frob2);
+    for (int c = 1; c <= l; ++c) {
+      const double s = P.sig[c - 1];
+      finite = finite && isfinite(s);
+      kept += s * s;
+      const double wc = frob2 > 0.0 ? (frob2 - kept) / frob2 : 0.0;
+      if (eps > 0.0 && !found && c <= cap && wc <= eps) {
+        chi = c;
+        w = wc;
+        found = true;
+      }
+      if (c == cap && !found) w = wc;
+    }
+    if (eps > 0.0 && !found) flags |= TEBD_DEV_CHI_BOUND;
+    if (!finite) flags |= TEBD_DEV_NONFINITE;
+    if (w < 0.0) w = 0.0;
+    double nk = 0.0;
+    for (int c = 0; c < chi; ++c) nk += P.sig[c] * P.sig[c];
+    if (tebd) {
+      bool floor_hit = false;
+      if (P.lam_l)
+        for (int a = 0; a < P.chi_l; ++a) floor_hit |= !(P.lam_l[a] > P.lambda_floor);
+      if (P.lam_r)
+        for (int b = 0; b < P.chi_r; ++b) floor_hit |= !(P.lam_r[b] > P.lambda_floor);
+      if (floor_hit) flags |= TEBD_DEV_LAMBDA_FLOOR;
+    }
+    P.chi_new = chi;
+    P.flags = flags;
+    *P.disc = w;
+    *P.status = flags;
+    if (P.chi_out) *P.chi_out = chi;
+    chi_s = chi;
+    norm_s = sqrt(nk);
+    flags_s = flags;
+  }
+  __syncthreads();
+  const int chi = chi_s;
+  if (tebd) {
+    const double inv = norm_s > 0.0 ? 1.0 / norm_s : 0.0;
+    for (int j = lane; j < P.chi_cap; j += 64) P.lam_mid[j] = j < chi ? P.sig[j] * inv : 0.0;
+    if (lane == 0) *P.chi_slot = chi;
+  } else {
+    for (int j = lane; j < P.kcap; j += 64) P.S[j] = j < chi ? P.sig[j] : 0.0;
+  }
+  (void)flags_s;
+}
+
+hipError_t launch_truncate(Prob* probs, const Common& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_truncate, dim3(c.nprob), dim3(64), 0, s, probs, c.eps, c.tebd);
+  return hipGetLastError();
+}
+
+}  // namespace tebd

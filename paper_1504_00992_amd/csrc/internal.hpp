@@ -1,0 +1,188 @@
+// Internal declarations shared by the HIP translation units of the library.
+//
+// The library runs the two-site TEBD update with RRSVD truncation
+// (Tamascelli, Rosenbach, Plenio, arXiv:1504.00992, Sec. II.B and Sec. IV)
+// as a pipeline of batched kernels.  Every kernel reads its per-problem
+// geometry from a device-resident descriptor (Prob), so problem sizes chosen
+// on the device (bond dimensions after truncation) never travel to the host.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "tebd_rrsvd.h"
+
+namespace tebd {
+
+typedef double2 zt;  // complex128 as (re, im)
+
+// ---------------------------------------------------------------------------
+// Per-problem descriptor.  Written by the host (standalone RRSVD) or by the
+// planning kernel (TEBD sweeps); a few fields are updated by later kernels.
+struct Prob {
+  // geometry
+  int32_t m, n, l, kcap;             // rows, cols, sketch width, kept capacity (chi_max)
+  int32_t chi_l, chi_m, chi_r;       // TEBD: left, middle (old), right bond dims
+  int32_t dl, dr;                    // TEBD: local dims of the two sites
+  int32_t pid;                       // Philox problem id
+  int32_t chi_new;                   // written by the truncation kernel
+  int32_t flags;                     // TEBD_DEV_* bits accumulated on the device
+  int32_t npart;                     // number of Frobenius partial sums
+  int32_t mixed;                     // 1: sketch / power products in complex FP32
+  int32_t om_ext;                    // 1: Omega supplied by the caller
+  int32_t pad0;
+  double frob2;                      // ||A||_F^2, written on the device
+  // input matrix (row-major, leading dim lda) and test matrix (row-major n x l)
+  zt* A;
+  int64_t lda;
+  const zt* om;
+  int64_t ldom;
+  // scratch (inside the caller's workspace)
+  zt* T;         // TEBD: Theta before the gate, [(i' j')][(alpha beta)]
+  zt* Y;         // m x l column-major (ld m): sketch, then Q
+  zt* Yt;        // n x l column-major (ld n): A^H Q, then Q~ / Q_B
+  zt* Rb;        // l x l column-major: R factor of B^H
+  zt* C;         // l x l column-major: Jacobi working matrix
+  zt* J;         // l x l column-major: accumulated Jacobi rotations
+  zt* X;         // l x l column-major: left vectors of the small SVD, sorted
+  zt* W;         // l x l column-major: right rotation, sorted
+  double* sig;   // l: singular values sorted descending
+  double* part;  // npart Frobenius partial sums
+  float2* Af;    // mixed: complex64 copy of A (row-major, ld n)
+  float2* Yf;    // mixed: complex64 copy of the current Q or Q~ (column-major)
+  // outputs of the standalone RRSVD
+  zt* U;
+  int64_t ldu;
+  double* S;
+  zt* VH;
+  int64_t ldvh;
+  int32_t* chi_out;
+  double* disc;
+  int32_t* status;
+  // TEBD state around the bond
+  zt* gk;              // Gamma of site k   (padded [d_max][chi_cap][chi_cap])
+  zt* gk1;             // Gamma of site k+1
+  const double* lam_l; // lambda left of site k (nullptr: chain edge, 1)
+  const double* lam_r; // lambda right of site k+1 (nullptr: chain edge, 1)
+  double* lam_mid;     // lambda of the updated bond
+  int32_t* chi_slot;   // chi entry of the updated bond
+  const zt* gate;      // (dl dr) x (dl dr), leading dim gate_ld
+  int32_t gate_ld;
+  int32_t chi_cap;     // padding capacity of the MPS arrays
+  double lambda_floor;
+};
+
+// Parameters of a launch sequence that are common to all problems.
+struct Common {
+  int32_t nprob;
+  int32_t q;
+  double eps;
+  uint64_t seed;
+  uint32_t stream_id;
+  // capacities (grid sizing): max over problems
+  int32_t mmax, nmax, lmax, kcap;
+  int32_t tebd;      // 1: TEBD problems (Theta/gate/reabsorb kernels run)
+  int32_t dmax;      // TEBD: max local dim
+  int32_t chimax;    // TEBD: chi capacity
+};
+
+// Launchers (defined in the .hip files).  All enqueue on `s` and return the
+// first HIP error met, or hipSuccess.
+hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, const zt* gates,
+                             int64_t gate_chain_stride, int32_t parity, int32_t single_chain,
+                             int32_t single_bond, int32_t p_over, char* slab_base,
+                             size_t slab_bytes, double* disc, int32_t* status, double lambda_floor,
+                             int32_t mixed, hipStream_t s);
+hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s);
+hipError_t launch_frob(Prob* probs, const Common& c, hipStream_t s);
+hipError_t launch_omega(Prob* probs, const Common& c, hipStream_t s);
+hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s);
+hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStream_t s);
+hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s);
+hipError_t launch_truncate(Prob* probs, const Common& c, hipStream_t s);
+hipError_t launch_form_uv(Prob* probs, const Common& c, hipStream_t s);
+hipError_t launch_mixed_cast(Prob* probs, const Common& c, int which, hipStream_t s);
+
+// Sketch-product selectors for launch_sketch.
+enum {
+  SK_Y_FROM_OMEGA = 0,  // Y  = A Omega
+  SK_YT_FROM_Y = 1,     // Yt = A^H Y
+  SK_Y_FROM_YT = 2      // Y  = A Yt
+};
+
+// Workspace carving helpers (host and device).
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Bytes of one problem's scratch slab for the given capacities.
+__host__ __device__ inline size_t slab_bytes(int64_t m, int64_t n, int64_t l, int tebd, int mixed,
+                                             int64_t npart) {
+  size_t b = 0;
+  const size_t z = sizeof(zt);
+  if (tebd) {
+    b += align256(m * n * z);  // A
+    b += align256(m * n * z);  // T
+  }
+  b += align256(n * l * z);          // Omega
+  b += align256(m * l * z);          // Y
+  b += align256(n * l * z);          // Yt
+  b += 5 * align256(l * l * z);      // Rb, C, J, X, W
+  b += align256(l * sizeof(double)); // sig
+  b += align256(npart * sizeof(double));
+  if (mixed) {
+    b += align256(m * n * sizeof(float2));
+    b += align256((m > n ? m : n) * l * sizeof(float2));
+  }
+  return b;
+}
+
+// Carve one slab into the scratch pointers of a descriptor.
+__host__ __device__ inline void carve_slab(Prob& p, char* base, int64_t m, int64_t n, int64_t l,
+                                           int tebd, int mixed, int64_t npart) {
+  const size_t z = sizeof(zt);
+  char* c = base;
+  if (tebd) {
+    p.A = reinterpret_cast<zt*>(c);
+    c += align256(m * n * z);
+    p.T = reinterpret_cast<zt*>(c);
+    c += align256(m * n * z);
+  } else {
+    p.T = nullptr;
+  }
+  p.om = reinterpret_cast<const zt*>(c);
+  c += align256(n * l * z);
+  p.Y = reinterpret_cast<zt*>(c);
+  c += align256(m * l * z);
+  p.Yt = reinterpret_cast<zt*>(c);
+  c += align256(n * l * z);
+  p.Rb = reinterpret_cast<zt*>(c);
+  c += align256(l * l * z);
+  p.C = reinterpret_cast<zt*>(c);
+  c += align256(l * l * z);
+  p.J = reinterpret_cast<zt*>(c);
+  c += align256(l * l * z);
+  p.X = reinterpret_cast<zt*>(c);
+  c += align256(l * l * z);
+  p.W = reinterpret_cast<zt*>(c);
+  c += align256(l * l * z);
+  p.sig = reinterpret_cast<double*>(c);
+  c += align256(l * sizeof(double));
+  p.part = reinterpret_cast<double*>(c);
+  c += align256(npart * sizeof(double));
+  if (mixed) {
+    p.Af = reinterpret_cast<float2*>(c);
+    c += align256(m * n * sizeof(float2));
+    p.Yf = reinterpret_cast<float2*>(c);
+    c += align256((m > n ? m : n) * l * sizeof(float2));
+  } else {
+    p.Af = nullptr;
+    p.Yf = nullptr;
+  }
+}
+
+// Largest l (sketch width) and m supported by the factorisation kernels.
+constexpr int kMaxL = 512;
+constexpr int kMaxRows = 8192;
+
+}  // namespace tebd

@@ -1,0 +1,161 @@
+"""GPU parity of tebd_bond_update / tebd_sweep (HIP path) against the oracle.
+
+The oracle runs the same updates with the step-by-step RRSVD and the same
+Philox test matrices (problem id chain * (N - 1) + bond, call id = sweep
+count).  Compared: chi' (exact), lambda' (1e-10 absolute; lambda is
+normalised so this is normwise relative), discarded weights (1e-12), and
+gauge-invariant quantities: the two-site block lam_l Gamma' lam' Gamma'
+lam_r (1e-10) and local observables <Z_i> by exact contraction (1e-10).
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import models as om
+from oracle import mps as omps
+from oracle import philox, rrsvd as orr, statevector
+
+pytestmark = pytest.mark.gpu
+SEED = 1504
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+
+
+def _random_chain(dims, chis, seed):
+    gen = wl.rng(seed)
+    gammas = [wl.ginibre(d * chis[k], chis[k + 1], gen).reshape(d, chis[k], chis[k + 1])
+              for k, d in enumerate(dims)]
+    lambdas = []
+    for b in range(len(dims) - 1):
+        v = np.sort(gen.uniform(0.05, 1.0, size=chis[b + 1]))[::-1]
+        lambdas.append(v / np.linalg.norm(v))
+    return gammas, lambdas
+
+
+def _two_site_block(gammas, lambdas, b):
+    m = omps.MPS(gammas, lambdas)
+    return omps.blocked(omps.theta(m, b))
+
+
+@pytest.mark.parametrize("dims,chis,bond,chi_max,p", [
+    ([3, 3, 2, 3], [1, 3, 5, 4, 1], 1, 16, 10),        # l clamps: exact SVD
+    ([4, 4, 4, 4], [1, 4, 16, 18, 1], 1, 10, 4),       # RRSVD with l < n
+    ([2, 5, 5, 2], [1, 2, 9, 2, 1], 0, 6, 3),          # left edge bond
+    ([2, 5, 5, 2], [1, 2, 9, 2, 1], 2, 6, 3),          # right edge bond
+])
+def test_bond_update_matches_oracle(dims, chis, bond, chi_max, p):
+    from paper_1504_00992_amd import api
+    gam, lam = _random_chain(dims, chis, 21 + bond)
+    gate = wl.random_unitary(dims[bond] * dims[bond + 1], wl.rng(3))
+    cap = max(max(chis), chi_max)
+    dev = api.DeviceMPS.from_host([(gam, lam)], dims, cap)
+    prm = api._lib.params(chi_max, p, 2, 1e-10, 1e-14, SEED, 5)
+    ws = api.BondWorkspace(dev, prm)
+    dmax = max(dims)
+    g = np.zeros((dmax * dmax, dmax * dmax), dtype=np.complex128)
+    g[:gate.shape[0], :gate.shape[0]] = gate
+    gd = torch.from_numpy(g).cuda()
+    api.tebd_bond_update(dev, 0, bond, gd, prm, ws)
+    torch.cuda.synchronize()
+    ref = omps.MPS(gam, lam)
+    m = dims[bond] * chis[bond]
+    n = dims[bond + 1] * chis[bond + 2]
+    l = orr.sketch_width(chi_max, p, m, n)
+    omega = philox.gaussian_omega(n, l, SEED, bond, 5)
+    info = omps.bond_update(ref, bond, gate, chi_max, 1e-10, "rrsvd", omega, 2)
+    g_gam, g_lam = dev.to_host(0)
+    assert len(g_lam[bond]) == info["chi"]
+    assert np.max(np.abs(g_lam[bond] - ref.lambdas[bond])) < 1e-10
+    assert abs(ws.disc[0, bond].item() - info["w"]) < 1e-12
+    assert ws.status[0, bond].item() == info["status"]
+    blk_g = _two_site_block(g_gam, g_lam, bond)
+    blk_o = _two_site_block(ref.gammas, ref.lambdas, bond)
+    assert np.max(np.abs(blk_g - blk_o)) < 1e-10
+    # untouched sites and bonds
+    for k in range(len(dims)):
+        if k not in (bond, bond + 1):
+            assert np.array_equal(g_gam[k], gam[k])
+    # padding beyond chi' is zero
+    cap_g = dev.gamma[0, bond].cpu().numpy()
+    assert np.all(cap_g[:, :, info["chi"]:] == 0)
+
+
+def _oracle_tebd(dims, hb, levels, dt, steps, chi_max, p, eps, chain=0):
+    gates = {}
+
+    def gfn(b, tau):
+        key = (b, tau)
+        if key not in gates:
+            gates[key] = om.gate(hb[b], tau)
+        return gates[key]
+    m = omps.basis_product_state(dims, levels)
+    drv = omps.TEBD(m, gfn, dt, chi_max, eps, method="rrsvd", p=p, q=2, seed=SEED, chain=chain)
+    for _ in range(steps):
+        drv.step()
+    return drv
+
+
+def _gpu_tebd(n_chains, dims, hb, levels, dt, steps, chi_max, p, eps):
+    from paper_1504_00992_amd import api
+    dev = api.DeviceMPS.product_state(n_chains, dims, levels, chi_max)
+    drv = api.TEBD(dev, hb, dt, chi_max, p=p, q=2, trunc_eps=eps, seed=SEED)
+    for _ in range(steps):
+        drv.step()
+    torch.cuda.synchronize()
+    return drv
+
+
+def test_tfim_sweeps_match_oracle_and_state_vector():
+    n, dt, steps, chi_max = 12, 0.05, 10, 16
+    dims, hb = om.tfim(n, 1.0, 1.0)
+    g = _gpu_tebd(1, dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10)
+    o = _oracle_tebd(dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10)
+    gam, lam = g.mps.to_host(0)
+    gm = omps.MPS(gam, lam)
+    assert gm.chis() == o.mps.chis()
+    for b in range(n - 1):
+        assert np.max(np.abs(lam[b] - o.mps.lambdas[b])) < 1e-10
+    psi = statevector.trotter_evolve(statevector.product_vector(dims, [0] * n), hb, dims, dt, steps)
+    for i in range(n):
+        zg = omps.expectation(gm, om.Z, i).real
+        zo = omps.expectation(o.mps, om.Z, i).real
+        zs = statevector.local_expectation(psi, om.Z, i, dims).real
+        assert abs(zg - zo) < 1e-10
+        # both carry the same truncation error (w <= 1e-10 per bond) against the
+        # untruncated circuit; it is O(sqrt(sum w)), not a parity quantity
+        assert abs(abs(zg - zs) - abs(zo - zs)) < 1e-10 and abs(zg - zs) < 1e-5
+    assert abs(omps.norm2(gm) - 1.0) < 1e-10
+
+
+def test_spin_boson_two_chains_match_oracle():
+    n, d, dt, steps, chi_max = 8, 4, 0.05, 6, 20
+    dims, hb = om.spin_boson_chain(n, d, 1.0, 0.5, 1.0, 0.5)
+    g = _gpu_tebd(2, dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10)
+    for c in range(2):
+        o = _oracle_tebd(dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10, chain=c)
+        gam, lam = g.mps.to_host(c)
+        gm = omps.MPS(gam, lam)
+        assert gm.chis() == o.mps.chis()
+        for i in (0, 1, 4):
+            op = om.Z if i == 0 else np.diag(np.arange(d)).astype(np.complex128)
+            assert abs(omps.expectation(gm, op, i).real - omps.expectation(o.mps, op, i).real) < 1e-10
+
+
+def test_bad_device_state_is_skipped_and_flagged():
+    from paper_1504_00992_amd import api
+    n = 6
+    dims, hb = om.tfim(n, 1.0, 1.0)
+    dev = api.DeviceMPS.product_state(1, dims, [0] * n, 8)
+    drv = api.TEBD(dev, hb, 0.05, 8, seed=SEED)
+    dev.chi[0, 3] = 99  # out of range for capacity 8: bonds 2 (left) and 3 (mid) see it
+    before = dev.gamma.clone()
+    drv.sweep(0, drv.g_half)
+    drv.sweep(1, drv.g_full)
+    torch.cuda.synchronize()
+    st = drv.ws.status[0].cpu().numpy()
+    assert st[2] & 32 and st[1] & 32
+    assert torch.equal(dev.gamma[0, 2:4], before[0, 2:4])

@@ -64,6 +64,29 @@ def batched_rrsvd_matrix(n, index, seed=BASE_SEED):
     return known_spectrum(n, n, exp_spectrum(n), gen)
 
 
+def batched_rrsvd_matrices_device(sizes, seed=BASE_SEED, device="cuda"):
+    """The batched workload drawn on the device (same construction, faster).
+
+    Haar factors from torch's QR of complex Ginibre matrices with the phase
+    fix, spectrum s_i = exp(-i/25).  Returns a list of complex128 tensors.
+    """
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    out = []
+    for n in sizes:
+        fac = []
+        for _ in range(2):
+            z = torch.randn((n, n), dtype=torch.complex128, device=device, generator=gen)
+            q, r = torch.linalg.qr(z)
+            d = torch.diagonal(r)
+            fac.append(q * (d / d.abs())[None, :])
+        s = torch.exp(-torch.arange(n, dtype=torch.float64, device=device) / 25.0)
+        vh = fac[1].conj().transpose(0, 1).contiguous()
+        out.append(((fac[0] * s[None, :]) @ vh).contiguous())
+    return out
+
+
 def random_vidal_bond(dl, dr, chi_l, chi_m, chi_r, gen, decay=0.3):
     """Random tensors around one bond: Gamma_k, Gamma_k+1 and three lambdas.
 
