@@ -1,0 +1,352 @@
+"""Throughput of the batched TEBD bond update with RRSVD on one MI355X.
+
+Workload (default): 16 independent chain-mapped spin-boson chains (Eq. H_1D:
+spin-1/2 plus 99 oscillators truncated to d = 10, t_n = 0.5, omega_n = 1),
+chi_max = 100, RRSVD with p = 10, q = 2, per-bond discarded weight
+<= 1e-10, dt = 0.05, symmetric Trotter steps from |up>|0...0>.  One step is
+three sweeps (even, odd, even bonds) over all 16 chains = 2384 bond updates.
+W warm-up steps, then K timed steps, continue one run of W + K = 200 steps
+by default, so the timed region covers the whole evolution.
+
+The JSON line also carries:
+* roofline   -- the kernel kind with the largest event time in the timed
+                region; algorithmic flops from the recorded bond dimensions
+                of every problem, divided by its event-timed duration;
+* cpu_baseline -- the FP64 CPU oracle (full-SVD TEBD of chain 0 of the same
+                workload) timed on the host for a bounded sample;
+* full_svd   -- the same TEBD steps with the vendor full SVD
+                (torch.linalg.svd) in a torch-only comparator on this GPU;
+* batched_rrsvd -- the 256-matrix standalone RRSVD workload (sizes
+                256..2048, s_i = exp(-i/25), k = 64, p = 10, q = 2).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=190)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--chains", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--full-svd-steps", type=int, default=-1,
+                    help="steps of the torch full-SVD comparator (-1: same as --steps)")
+    ap.add_argument("--full-svd-seconds", type=float, default=90.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full-svd", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# algorithmic flop counts (complex arithmetic: one multiply-add = 8 flops)
+def sketch_flops(m, n, l):
+    return 8.0 * m * n * l
+
+
+def qr_flops(rows, l):
+    # Householder factorisation plus explicit thin Q, complex: 2 x 4 (2 r l^2 - 2 l^3 / 3)
+    return 16.0 * rows * l * l - 16.0 / 3.0 * l ** 3
+
+
+def theta_gate_flops(dl, dr, cl, cm, cr):
+    return 8.0 * (dl * cl * cm * dr * cr + (dl * dr) ** 2 * cl * cr)
+
+
+def sweep_problems(chi_row, dims, parity, chi_max, p):
+    """(dl, dr, cl, cm, cr, m, n, l) of every bond of one chain in a sweep."""
+    out = []
+    for b in range(parity, len(dims) - 1, 2):
+        cl, cm, cr = int(chi_row[b]), int(chi_row[b + 1]), int(chi_row[b + 2])
+        dl, dr = dims[b], dims[b + 1]
+        m, n = dl * cl, dr * cr
+        out.append((dl, dr, cl, cm, cr, m, n, min(chi_max + p, m, n)))
+    return out
+
+
+def kind_flops(chi_hist, parities, dims, chi_max, p, q):
+    """Algorithmic flops per profiled kernel kind over the recorded sweeps."""
+    tot = {"theta_gate": 0.0, "sketch_A_Omega": 0.0, "sketch_AH_Q": 0.0, "sketch_A_Qt": 0.0,
+           "qr": 0.0, "qr_with_r": 0.0}
+    for chi, parity in zip(chi_hist, parities):
+        for c in range(chi.shape[0]):
+            for (dl, dr, cl, cm, cr, m, n, l) in sweep_problems(chi[c], dims, parity, chi_max, p):
+                tot["theta_gate"] += theta_gate_flops(dl, dr, cl, cm, cr)
+                tot["sketch_A_Omega"] += sketch_flops(m, n, l)
+                tot["sketch_AH_Q"] += (q + 1) * sketch_flops(m, n, l)
+                tot["sketch_A_Qt"] += q * sketch_flops(m, n, l)
+                tot["qr"] += (q + 1) * qr_flops(m, l) + q * qr_flops(n, l)
+                tot["qr_with_r"] += qr_flops(n, l)
+    return tot
+
+
+KIND_BOUND = {"theta_gate": "mfma", "sketch_A_Omega": "mfma", "sketch_AH_Q": "mfma",
+              "sketch_A_Qt": "mfma", "qr": "alu", "qr_with_r": "alu"}
+
+
+def roofline(prof, flops):
+    """Roofline entry for the kind with the largest event time."""
+    kind = max(prof, key=lambda k: prof[k][0])
+    ms, launches = prof[kind]
+    entry = {"kernel": kind, "launches": launches, "event_ms_total": round(ms, 3)}
+    if kind in flops and ms > 0:
+        ach = flops[kind] / (ms * 1e-3) / 1e12
+        entry.update({"bound": KIND_BOUND[kind], "achieved": round(ach, 4),
+                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                      "frac": round(ach / PEAK_FP64_TFLOPS, 5), "traffic": None})
+    else:
+        entry.update({"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS,
+                      "unit": "TFLOP/s", "frac": None, "traffic": None,
+                      "note": "iterative kernel: no fixed algorithmic flop count"})
+    return entry
+
+
+# ---------------------------------------------------------------------------
+def run_gpu_tebd(args, torch, api, models, prof_on=True):
+    N, d, chi_max, p, q = 100, 10, 100, 10, 2
+    dims, hb = models.spin_boson(N, d, 1.0, 0.5, 1.0, 0.5)
+    mps = api.DeviceMPS.product_state(args.chains, dims, [0] * N, chi_max)
+    drv = api.TEBD(mps, hb, 0.05, chi_max, p=p, q=q, trunc_eps=1e-10, seed=1504)
+    for _ in range(args.warmup):
+        drv.step()
+    torch.cuda.synchronize()
+    chi_hist = torch.empty((3 * args.steps, args.chains, N + 1), dtype=torch.int32, device="cuda")
+    parities = []
+    api._lib.tebd_profile_enable(prof_on)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k = 0
+    for _ in range(args.steps):
+        for parity, gates in ((0, drv.g_half), (1, drv.g_full), (0, drv.g_half)):
+            chi_hist[k].copy_(mps.chi)
+            parities.append(parity)
+            drv.sweep(parity, gates)
+            k += 1
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = api._lib.tebd_profile_read() if prof_on else {}
+    api._lib.tebd_profile_enable(False)
+    status = drv.ws.status.cpu().numpy()
+    return dict(seconds=t1 - t0, prof=prof, chi_hist=chi_hist.cpu().numpy(), parities=parities,
+                dims=dims, hb=hb, chi_final=mps.chi.cpu().numpy(), status=status)
+
+
+def updates_per_step(n_sites):
+    even = (n_sites - 1 + 1) // 2
+    odd = (n_sites - 1) // 2
+    return 2 * even + odd
+
+
+def full_svd_tebd(args, torch, models, dims, hb, warmup, steps):
+    """torch-only TEBD with torch.linalg.svd (full SVD) on the same workload.
+
+    Runs `warmup` untimed steps, then times up to `steps` steps (stopping
+    early after --full-svd-seconds, which only flatters the comparator since
+    later steps carry larger bonds)."""
+    N, chi_max, eps, floor_ = len(dims), 100, 1e-10, 1e-14
+    dev = "cuda"
+    nch = args.chains
+    dmax = max(dims)
+    gam = torch.zeros((nch, N, dmax, chi_max, chi_max), dtype=torch.complex128, device=dev)
+    lam = torch.zeros((nch, N - 1, chi_max), dtype=torch.float64, device=dev)
+    gam[:, :, 0, 0, 0] = 1.0
+    lam[:, :, 0] = 1.0
+    chi = [[1] * (N + 1) for _ in range(nch)]
+    gh = [torch.from_numpy(models.propagator(h, 0.025)).to(dev) for h in hb]
+    gf = [torch.from_numpy(models.propagator(h, 0.05)).to(dev) for h in hb]
+
+    def bond(b, g):
+        groups = {}
+        for c in range(nch):
+            groups.setdefault((chi[c][b], chi[c][b + 1], chi[c][b + 2]), []).append(c)
+        dl, dr = dims[b], dims[b + 1]
+        for (cl, cm, cr), chains in groups.items():
+            idx = torch.tensor(chains, device=dev)
+            gk = gam[idx, b, :dl, :cl, :cm]
+            gk1 = gam[idx, b + 1, :dr, :cm, :cr]
+            ll = lam[idx, b - 1, :cl] if b >= 1 else torch.ones((len(chains), cl), dtype=torch.float64, device=dev)
+            lm = lam[idx, b, :cm]
+            lr = lam[idx, b + 1, :cr] if b + 1 <= N - 2 else torch.ones((len(chains), cr), dtype=torch.float64, device=dev)
+            left = (gk * ll[:, None, :, None] * lm[:, None, None, :]).contiguous()
+            right = (gk1 * lr[:, None, None, :]).contiguous()
+            th = torch.einsum("biag,bjgc->bijac", left, right).reshape(len(chains), dl * dr, cl * cr)
+            tt = torch.matmul(g, th)
+            a = tt.reshape(len(chains), dl, dr, cl, cr).permute(0, 1, 3, 2, 4).reshape(len(chains), dl * cl, dr * cr)
+            u, s, vh = torch.linalg.svd(a, full_matrices=False)
+            s2 = (s * s).cpu().numpy()
+            for j, c in enumerate(chains):
+                tot = s2[j].sum()
+                tails = (tot - s2[j].cumsum()) / tot
+                ok = [i for i in range(len(tails)) if tails[i] <= eps]
+                cp = min(chi_max, (ok[0] + 1) if ok else len(tails))
+                nrm = float(s2[j][:cp].sum()) ** 0.5
+                inv_l = torch.where(ll[j] > floor_, 1.0 / ll[j], torch.zeros_like(ll[j]))
+                inv_r = torch.where(lr[j] > floor_, 1.0 / lr[j], torch.zeros_like(lr[j]))
+                gam[c, b, :, :, :] = 0
+                gam[c, b + 1, :, :, :] = 0
+                gam[c, b, :dl, :cl, :cp] = u[j, :, :cp].reshape(dl, cl, cp) * inv_l[None, :, None]
+                gam[c, b + 1, :dr, :cp, :cr] = vh[j, :cp, :].reshape(cp, dr, cr).permute(1, 0, 2) * inv_r[None, None, :]
+                lam[c, b, :] = 0
+                lam[c, b, :cp] = s[j, :cp] / nrm
+                chi[c][b + 1] = cp
+
+    def step():
+        for parity, gs in ((0, gh), (1, gf), (0, gh)):
+            for b in range(parity, N - 1, 2):
+                bond(b, gs[b])
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    for _ in range(steps):
+        step()
+        done += 1
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 > args.full_svd_seconds:
+            break
+    torch.cuda.synchronize()
+    return done, time.perf_counter() - t0
+
+
+def cpu_oracle_baseline(args, dims, budget_s):
+    """FP64 oracle TEBD (full LAPACK SVD) of chain 0, bounded by wall time."""
+    import numpy as np
+    from oracle import models as om, mps as omps
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    N = len(dims)
+    _, hb = om.spin_boson_chain(N, dims[1], 1.0, 0.5, 1.0, 0.5)
+    cache = {}
+
+    def gfn(b, tau):
+        key = (b, tau)
+        if key not in cache:
+            cache[key] = om.gate(hb[b], tau)
+        return cache[key]
+    m = omps.basis_product_state(dims, [0] * N)
+    drv = omps.TEBD(m, gfn, 0.05, 100, 1e-10, method="full")
+    for b in range(N - 1):  # gates outside the timed sample
+        gfn(b, 0.025), gfn(b, 0.05)
+    t0 = time.perf_counter()
+    steps = 0
+    while time.perf_counter() - t0 < budget_s:
+        drv.step()
+        steps += 1
+    dt = time.perf_counter() - t0
+    upd = steps * updates_per_step(N)
+    return {"value": round(upd / dt, 2), "unit": "bond updates/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"chain 0 of the same workload, steps 1..{steps} of the run "
+                      f"({upd} bond updates, {dt:.1f} s), FP64 full LAPACK SVD per bond"}
+
+
+def batched_rrsvd(torch, api, wl):
+    sizes = wl.batched_rrsvd_sizes()
+    mats = wl.batched_rrsvd_matrices_device(sizes)
+    from paper_1504_00992_amd import _lib
+    api.rrsvd_truncate(mats, 64, 10, 2, 1e-10, 1504, 0)  # warm-up (workspace, code)
+    torch.cuda.synchronize()
+    reps = 3
+    _lib.tebd_profile_enable(True)
+    t0 = time.perf_counter()
+    for r in range(reps):
+        out = api.rrsvd_truncate(mats, 64, 10, 2, 1e-10, 1504, r + 1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = _lib.tebd_profile_read()
+    _lib.tebd_profile_enable(False)
+    l = 74
+    f_sk = sum(sketch_flops(n, n, l) for n in sizes)
+    sk_ms = sum(prof.get(k, (0.0, 0))[0] for k in ("sketch_A_Omega", "sketch_AH_Q", "sketch_A_Qt")) / reps
+    sk_fl = 6 * f_sk
+    ach = sk_fl / (sk_ms * 1e-3) / 1e12 if sk_ms > 0 else None
+    return {"metric": "RRSVD truncations/s", "value": round(len(sizes) * reps / (t1 - t0), 2),
+            "ms_per_batch": round(1e3 * (t1 - t0) / reps, 3),
+            "config": {"workload": "256 complex128 square matrices, n in {256,512,1024,2048}, "
+                                   "s_i=exp(-i/25), k=64, p=10, q=2, one call"},
+            "sketch_gemms": {"bound": "mfma", "achieved": round(ach, 3) if ach else None,
+                             "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                             "frac": round(ach / PEAK_FP64_TFLOPS, 4) if ach else None,
+                             "ms_per_batch": round(sk_ms, 3)},
+            "phase_ms_per_batch": {k: round(v[0] / reps, 3) for k, v in prof.items()}}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
+              f"described in DESIGN.md and not launched here.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    from paper_1504_00992_amd import api, models, _lib
+    import workloads as wl
+    _lib.load()
+
+    res = run_gpu_tebd(args, torch, api, models)
+    N = 100
+    per_step = updates_per_step(N) * args.chains
+    total_updates = per_step * args.steps
+    sec = res["seconds"]
+    value = total_updates / sec
+    flops = kind_flops(res["chi_hist"], res["parities"], res["dims"], 100, 10, 2)
+    prof = res["prof"]
+    line = {
+        "metric": "TEBD bond updates/s, RRSVD vs full SVD on 1 GPU at <=1e-10 trunc err",
+        "value": round(value, 2),
+        "unit": "bond updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * sec / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128 (f64)",
+        "data": "synthetic",
+        "config": {"workload": "batched TEBD sweep: 16 chain-mapped spin-boson chains, N=100 "
+                               "(spin + 99 oscillators, d=10), t_n=0.5, w_n=1, dt=0.05, chi_max=100, "
+                               "RRSVD p=10 q=2, w<=1e-10 per bond",
+                   "chains": args.chains, "bond_updates_per_step": per_step,
+                   "chi_final_max": int(res["chi_final"].max()),
+                   "status_bits_seen": sorted(set(int(x) for x in np.unique(res["status"])))},
+        "phase_ms": {k: round(v[0], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
+        "roofline": roofline(prof, flops),
+    }
+    if not args.no_full_svd:
+        nsteps = args.steps if args.full_svd_steps < 0 else args.full_svd_steps
+        done, fsec = full_svd_tebd(args, torch, models, res["dims"], res["hb"], args.warmup, nsteps)
+        fval = done * per_step / fsec if fsec > 0 else None
+        line["full_svd"] = {"value": round(fval, 2), "unit": "bond updates/s",
+                            "steps": done, "seconds": round(fsec, 2),
+                            "note": "torch.linalg.svd (vendor full SVD) in a torch-only TEBD step on "
+                                    "the same GPU, same warm-up, timed steps after it"}
+        line["speedup_vs_full_svd"] = round(value / fval, 3) if fval else None
+    if not args.no_batched:
+        line["batched_rrsvd"] = batched_rrsvd(torch, api, wl)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_oracle_baseline(args, res["dims"], args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -185,6 +185,19 @@ tebd_status tebd_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate_ch
                        int32_t parity, const tebd_params* prm, double* disc_weight,
                        int32_t* dev_status, void* workspace, size_t ws_bytes, void* stream);
 
+/* Per-kernel timing with HIP events, for the per-phase split of the update
+ * (the paper's profile of the two-site update, Sec. V.B).  Off by default.
+ * While on, each kernel launch of the library is bracketed by two events
+ * recorded on the launch stream.  tebd_profile_enable(0 or 1) also discards
+ * what was recorded so far.
+ * tebd_profile_read waits for the recorded events and writes, for up to
+ * `capacity` kernel kinds, the kind's name (static string), the summed
+ * elapsed milliseconds and the number of launches; *count receives the
+ * number of kinds written.  The records are then discarded. */
+tebd_status tebd_profile_enable(int32_t on);
+tebd_status tebd_profile_read(int32_t capacity, const char** names, double* ms, int64_t* launches,
+                              int32_t* count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ DEV_CHI_BOUND = 16
 DEV_BAD_STATE = 32
 
 EXPORTED = ("tebd_last_error", "tebd_version", "tebd_workspace_size", "rrsvd_truncate",
-            "tebd_bond_update", "tebd_sweep")
+            "tebd_bond_update", "tebd_sweep", "tebd_profile_enable", "tebd_profile_read")
 
 
 class TebdParams(ctypes.Structure):
@@ -79,6 +79,12 @@ def load():
     lib.tebd_sweep.restype = ctypes.c_int
     lib.tebd_sweep.argtypes = [ctypes.POINTER(TebdMps), vp, i64, i32, ctypes.POINTER(TebdParams),
                                vp, vp, vp, sz, vp]
+    lib.tebd_profile_enable.restype = ctypes.c_int
+    lib.tebd_profile_enable.argtypes = [i32]
+    lib.tebd_profile_read.restype = ctypes.c_int
+    lib.tebd_profile_read.argtypes = [i32, ctypes.POINTER(ctypes.c_char_p),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int32)]
     _lib = lib
     return lib
 
@@ -150,3 +156,18 @@ def tebd_sweep(mps, gates_ptr, gate_chain_stride, parity, prm, disc_ptr, status_
     lib = load()
     return lib.tebd_sweep(ctypes.byref(mps), gates_ptr, int(gate_chain_stride), int(parity),
                           ctypes.byref(prm), disc_ptr, status_ptr, ws_ptr, int(ws_bytes), stream)
+
+
+def tebd_profile_enable(on):
+    check(load().tebd_profile_enable(1 if on else 0))
+
+
+def tebd_profile_read(capacity=32):
+    """{kind: (milliseconds, launches)} recorded since profiling was enabled."""
+    lib = load()
+    names = (ctypes.c_char_p * capacity)()
+    ms = (ctypes.c_double * capacity)()
+    launches = (ctypes.c_int64 * capacity)()
+    count = ctypes.c_int32(0)
+    check(lib.tebd_profile_read(capacity, names, ms, launches, ctypes.byref(count)))
+    return {names[i].decode(): (ms[i], int(launches[i])) for i in range(count.value)}

@@ -98,7 +98,7 @@ SweepPlan plan_sweep(const tebd_mps& mps, const tebd_params& prm) {
   s.mcap = int64_t(mps.d_max) * mps.chi_max;
   s.lcap = sketch_l(prm.chi_max, prm.p, s.mcap, s.mcap);
   s.npart = int64_t((mps.d_max * mps.d_max + 63) / 64) * ((int64_t(mps.chi_max) * mps.chi_max + 63) / 64);
-  s.desc_bytes = align256(size_t(s.pmax) * sizeof(Prob));
+  s.desc_bytes = align256(size_t(s.pmax) * sizeof(Prob)) + align256(sched_bytes(s.pmax));
   s.slab_sz = slab_bytes(s.mcap, s.mcap, s.lcap, 1, prm.precision, s.npart);
   s.total = s.desc_bytes + size_t(s.pmax) * s.slab_sz;
   return s;
@@ -146,6 +146,70 @@ hipError_t upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
   return hipEventRecord(g_stage.ev[k], s);
 }
 
+// Optional per-kernel event timing (tebd_profile_enable / tebd_profile_read).
+enum ProfKind {
+  PK_PLAN, PK_SCHEDULE, PK_THETA_GATE, PK_FROB, PK_OMEGA, PK_SKETCH_AOM, PK_SKETCH_AHQ,
+  PK_SKETCH_AQT, PK_QR, PK_QR_R, PK_SMALL_SVD, PK_TRUNCATE, PK_FORM_UV, PK_COUNT
+};
+const char* const kProfNames[PK_COUNT] = {
+    "plan_sweep", "schedule",  "theta_gate", "frobenius",  "omega",    "sketch_A_Omega",
+    "sketch_AH_Q", "sketch_A_Qt", "qr",       "qr_with_r", "small_svd", "truncate",
+    "form_u_vh"};
+
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void recycle() {
+    for (auto& r : recs) {
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    recs.clear();
+  }
+};
+Profiler g_prof;
+
+// Run one launcher, bracketed by events when profiling is on.
+template <class F>
+hipError_t timed(int kind, hipStream_t s, F&& launch) {
+  if (!g_prof.on) return launch();
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  hipEvent_t a = g_prof.get(), b = g_prof.get();
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, s);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, s);
+  if (e != hipSuccess) return e;
+  g_prof.recs.push_back({kind, a, b});
+  return hipSuccess;
+}
+
+// Workgroups of the persistent contraction launches: enough to fill the 256
+// CUs several times over, never more than the largest possible tile count.
+int32_t persistent_grid(int64_t cap_tiles) {
+  int64_t g = cap_tiles < 2048 ? cap_tiles : 2048;
+  g = (g + 7) / 8 * 8;
+  return int32_t(g < 8 ? 8 : g);
+}
+
 hipError_t run_pipeline(Prob* probs, const Common& c, hipStream_t s) {
   hipError_t e;
 #define TRY(x)                     \
@@ -153,24 +217,27 @@ hipError_t run_pipeline(Prob* probs, const Common& c, hipStream_t s) {
     e = (x);                       \
     if (e != hipSuccess) return e; \
   } while (0)
+#define TIMED(kind, call) TRY(timed(kind, s, [&]() { return (call); }))
+  TIMED(PK_SCHEDULE, launch_schedule(probs, c, s));
   if (c.tebd)
-    TRY(launch_theta_gate(probs, c, s));
+    TIMED(PK_THETA_GATE, launch_theta_gate(probs, c, s));
   else
-    TRY(launch_frob(probs, c, s));
-  TRY(launch_omega(probs, c, s));
-  TRY(launch_sketch(probs, c, SK_Y_FROM_OMEGA, s));
-  TRY(launch_qr(probs, c, 0, 0, s));
+    TIMED(PK_FROB, launch_frob(probs, c, s));
+  TIMED(PK_OMEGA, launch_omega(probs, c, s));
+  TIMED(PK_SKETCH_AOM, launch_sketch(probs, c, SK_Y_FROM_OMEGA, s));
+  TIMED(PK_QR, launch_qr(probs, c, 0, 0, s));
   for (int j = 0; j < c.q; ++j) {
-    TRY(launch_sketch(probs, c, SK_YT_FROM_Y, s));
-    TRY(launch_qr(probs, c, 1, 0, s));
-    TRY(launch_sketch(probs, c, SK_Y_FROM_YT, s));
-    TRY(launch_qr(probs, c, 0, 0, s));
+    TIMED(PK_SKETCH_AHQ, launch_sketch(probs, c, SK_YT_FROM_Y, s));
+    TIMED(PK_QR, launch_qr(probs, c, 1, 0, s));
+    TIMED(PK_SKETCH_AQT, launch_sketch(probs, c, SK_Y_FROM_YT, s));
+    TIMED(PK_QR, launch_qr(probs, c, 0, 0, s));
   }
-  TRY(launch_sketch(probs, c, SK_YT_FROM_Y, s));  // B^H = A^H Q
-  TRY(launch_qr(probs, c, 1, 1, s));               // B^H = Q_B R_B
-  TRY(launch_small_svd(probs, c, s));
-  TRY(launch_truncate(probs, c, s));
-  TRY(launch_form_uv(probs, c, s));
+  TIMED(PK_SKETCH_AHQ, launch_sketch(probs, c, SK_YT_FROM_Y, s));  // B^H = A^H Q
+  TIMED(PK_QR_R, launch_qr(probs, c, 1, 1, s));                    // B^H = Q_B R_B
+  TIMED(PK_SMALL_SVD, launch_small_svd(probs, c, s));
+  TIMED(PK_TRUNCATE, launch_truncate(probs, c, s));
+  TIMED(PK_FORM_UV, launch_form_uv(probs, c, s));
+#undef TIMED
 #undef TRY
   return hipSuccess;
 }
@@ -199,14 +266,23 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   c.tebd = 1;
   c.dmax = mps->d_max;
   c.chimax = mps->chi_max;
+  c.offs = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) +
+                                      align256(size_t(pl.pmax) * sizeof(Prob)));
+  {
+    const int64_t t = (pl.mcap + 63) / 64;
+    const int64_t tq = int64_t((mps->d_max * mps->d_max + 63) / 64) *
+                       ((int64_t(mps->chi_max) * mps->chi_max + 63) / 64);
+    c.grid = persistent_grid(int64_t(c.nprob) * (t * t > tq ? t * t : tq));
+  }
   if (c.nprob == 0) return ok();
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Prob* probs = reinterpret_cast<Prob*>(ws);
   char* slabs = reinterpret_cast<char*>(ws) + pl.desc_bytes;
-  hipError_t e = launch_plan_sweep(probs, c, *mps, reinterpret_cast<const zt*>(gates),
-                                   gate_chain_stride, parity, single_chain, single_bond, prm->p,
-                                   slabs, pl.slab_sz, disc, status, prm->lambda_floor,
-                                   prm->precision, s);
+  hipError_t e = timed(PK_PLAN, s, [&]() {
+    return launch_plan_sweep(probs, c, *mps, reinterpret_cast<const zt*>(gates), gate_chain_stride,
+                             parity, single_chain, single_bond, prm->p, slabs, pl.slab_sz, disc,
+                             status, prm->lambda_floor, prm->precision, s);
+  });
   if (e == hipSuccess) e = run_pipeline(probs, c, s);
   if (e != hipSuccess) return fail(TEBD_ERR_DEVICE, "HIP error while enqueuing: %s", hipGetErrorString(e));
   return ok();
@@ -219,6 +295,45 @@ extern "C" {
 const char* tebd_last_error(void) { return g_err; }
 
 const char* tebd_version(void) { return "tebd_rrsvd 0.1 (gfx950, complex128)"; }
+
+tebd_status tebd_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  for (auto& r : g_prof.recs) {
+    hipEventSynchronize(r.b);
+  }
+  g_prof.recycle();
+  g_prof.on = on != 0;
+  return ok();
+}
+
+tebd_status tebd_profile_read(int32_t capacity, const char** names, double* ms, int64_t* launches,
+                              int32_t* count) {
+  if (!names || !ms || !launches || !count)
+    return fail(TEBD_ERR_ARG, "tebd_profile_read: output arrays must not be NULL");
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  double tot[PK_COUNT] = {0};
+  int64_t cnt[PK_COUNT] = {0};
+  for (auto& r : g_prof.recs) {
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e != hipSuccess) return fail(TEBD_ERR_DEVICE, "event wait failed: %s", hipGetErrorString(e));
+    float t = 0.0f;
+    e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess) return fail(TEBD_ERR_DEVICE, "event timing failed: %s", hipGetErrorString(e));
+    tot[r.kind] += t;
+    cnt[r.kind] += 1;
+  }
+  g_prof.recycle();
+  int32_t k = 0;
+  for (int i = 0; i < PK_COUNT && k < capacity; ++i) {
+    if (!cnt[i]) continue;
+    names[k] = kProfNames[i];
+    ms[k] = tot[i];
+    launches[k] = cnt[i];
+    ++k;
+  }
+  *count = k;
+  return ok();
+}
 
 tebd_status tebd_workspace_size(const tebd_mps* mps, int64_t batch, const int64_t* m,
                                 const int64_t* n, const tebd_params* prm, size_t* bytes) {
@@ -233,7 +348,7 @@ tebd_status tebd_workspace_size(const tebd_mps* mps, int64_t batch, const int64_
   }
   if (batch < 1) return fail(TEBD_ERR_ARG, "batch = %lld must be >= 1", (long long)batch);
   if (!m || !n) return fail(TEBD_ERR_ARG, "m and n must be host arrays when mps is NULL");
-  size_t total = align256(size_t(batch) * sizeof(Prob));
+  size_t total = align256(size_t(batch) * sizeof(Prob)) + align256(sched_bytes(batch));
   for (int64_t b = 0; b < batch; ++b) {
     if (m[b] < 1 || n[b] < 1 || m[b] > kMaxRows || n[b] > kMaxRows)
       return fail(TEBD_ERR_SHAPE, "problem %lld: m = %lld, n = %lld out of range [1, %d]",
@@ -295,7 +410,7 @@ tebd_status rrsvd_truncate(int64_t batch, const int64_t* m, const int64_t* n,
 
   std::vector<Prob> host(batch);
   char* base = reinterpret_cast<char*>(workspace);
-  char* slab = base + align256(size_t(batch) * sizeof(Prob));
+  char* slab = base + align256(size_t(batch) * sizeof(Prob)) + align256(sched_bytes(batch));
   Common c;
   c.nprob = int32_t(batch);
   c.q = prm->q;
@@ -336,6 +451,16 @@ tebd_status rrsvd_truncate(int64_t batch, const int64_t* m, const int64_t* n,
     c.mmax = P.m > c.mmax ? P.m : c.mmax;
     c.nmax = P.n > c.nmax ? P.n : c.nmax;
     c.lmax = P.l > c.lmax ? P.l : c.lmax;
+  }
+  c.offs = reinterpret_cast<int32_t*>(base + align256(size_t(batch) * sizeof(Prob)));
+  {
+    int64_t tiles = 0;
+    for (int64_t b = 0; b < batch; ++b) {
+      const int64_t tm = (host[b].m + 63) / 64, tn = (host[b].n + 63) / 64;
+      const int64_t tk = (prm->chi_max + 63) / 64;
+      tiles += (tm > tn ? tm : tn) * (tk > 3 ? tk : 3);
+    }
+    c.grid = persistent_grid(tiles);
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e = upload(workspace, host.data(), host.size() * sizeof(Prob), s);

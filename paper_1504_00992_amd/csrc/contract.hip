@@ -11,6 +11,12 @@
 // * Singular vectors, Sec. IV steps i-iii: U = Q X and V^H = (Q_B W)^H for the
 //   kept chi' columns, with the lambda^-1 reabsorption of the TEBD update
 //   folded into the store.
+//
+// Scheduling: problem sizes live on the device, so every contraction kind
+// runs as one persistent launch over a global queue of 64 x 64 output tiles
+// (prefix sums over problems built by k_schedule).  Workgroup i takes the
+// virtual index (i mod 8) * G/8 + i / 8, so the consecutive tiles of one
+// problem, which share operand rows, land on the same XCD and its L2.
 #include "zgemm.hpp"
 
 namespace tebd {
@@ -21,6 +27,131 @@ __device__ __forceinline__ double inv_floor(const double* lam, int idx, double f
   if (lam == nullptr) return 1.0;
   const double v = lam[idx];
   return v > floor_ ? 1.0 / v : 0.0;
+}
+
+__device__ __forceinline__ int tiles_of(int M, int N) {
+  return (M <= 0 || N <= 0) ? 0 : ((M + 63) / 64) * ((N + 63) / 64);
+}
+
+// Output shape of each contraction kind for problem P (0 x 0 when skipped).
+template <int KIND>
+__device__ __forceinline__ void kind_shape(const Prob& P, int tebd, int& M, int& N) {
+  M = N = 0;
+  if (P.l == 0) return;
+  if (KIND == TK_THETA) {
+    if (tebd) {
+      M = P.dl * P.chi_l;
+      N = P.dr * P.chi_r;
+    }
+  } else if (KIND == TK_GATE) {
+    if (tebd) {
+      M = P.dl * P.dr;
+      N = P.chi_l * P.chi_r;
+    }
+  } else if (KIND == TK_SKM) {
+    M = P.m;
+    N = P.l;
+  } else if (KIND == TK_SKN) {
+    M = P.n;
+    N = P.l;
+  } else if (KIND == TK_FORMU) {
+    M = P.m;
+    N = tebd ? P.chi_cap : P.kcap;
+  } else {
+    M = tebd ? P.chi_cap : P.kcap;
+    N = P.n;
+  }
+}
+
+__device__ __forceinline__ int kind_tiles(int kind, const Prob& P, int tebd) {
+  int M, N;
+  switch (kind) {
+    case TK_THETA: kind_shape<TK_THETA>(P, tebd, M, N); break;
+    case TK_GATE: kind_shape<TK_GATE>(P, tebd, M, N); break;
+    case TK_SKM: kind_shape<TK_SKM>(P, tebd, M, N); break;
+    case TK_SKN: kind_shape<TK_SKN>(P, tebd, M, N); break;
+    case TK_FORMU: kind_shape<TK_FORMU>(P, tebd, M, N); break;
+    default: kind_shape<TK_FORMV>(P, tebd, M, N); break;
+  }
+  return tiles_of(M, N);
+}
+
+// Exclusive prefix sums of tile counts for every kind (one workgroup):
+// thread t sums a contiguous chunk of problems, thread 0 scans the chunk
+// sums, then every thread writes its chunk's offsets.
+__global__ __launch_bounds__(256) void k_schedule(const Prob* probs, int nprob, int tebd,
+                                                  int32_t* offs) {
+  __shared__ int32_t part[256];
+  __shared__ int32_t total;
+  const int tid = threadIdx.x;
+  const int chunk = (nprob + 255) / 256;
+  const int p0 = min(nprob, tid * chunk), p1 = min(nprob, p0 + chunk);
+  for (int kind = 0; kind < TK_COUNT; ++kind) {
+    int32_t s = 0;
+    for (int p = p0; p < p1; ++p) s += kind_tiles(kind, probs[p], tebd);
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+      int32_t run = 0;
+      for (int i = 0; i < 256; ++i) {
+        const int32_t v = part[i];
+        part[i] = run;
+        run += v;
+      }
+      total = run;
+    }
+    __syncthreads();
+    int32_t* o = offs + size_t(kind) * (nprob + 1);
+    int32_t run = part[tid];
+    for (int p = p0; p < p1; ++p) {
+      o[p] = run;
+      run += kind_tiles(kind, probs[p], tebd);
+    }
+    if (tid == 0) o[nprob] = total;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_schedule(Prob* probs, const Common& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_schedule, dim3(1), dim3(256), 0, s, probs, c.nprob, c.tebd, c.offs);
+  return hipGetLastError();
+}
+
+// Problem owning global tile t: the largest p with off[p] <= t.
+__device__ __forceinline__ int find_problem(const int32_t* off, int nprob, int t) {
+  int lo = 0, hi = nprob;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= t)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int virtual_block() {
+  const int g = gridDim.x, i = blockIdx.x;
+  return (i & 7) * (g >> 3) + (i >> 3);
+}
+
+// Iterate over this workgroup's tiles of one kind:
+// body(P, M, N, m0, n0, tile_index_within_problem, tiles_n).
+template <int KIND, class Body>
+__device__ __forceinline__ void for_each_tile(Prob* probs, const int32_t* offs, int nprob,
+                                              int tebd, Body body) {
+  const int32_t* off = offs + size_t(KIND) * (nprob + 1);
+  const int total = off[nprob];
+  for (int t = virtual_block(); t < total; t += gridDim.x) {
+    const int p = find_problem(off, nprob, t);
+    Prob& P = probs[p];
+    int M, N;
+    kind_shape<KIND>(P, tebd, M, N);
+    const int local = t - off[p];
+    const int tiles_n = (N + 63) / 64;
+    const int tm = local / tiles_n, tn = local - tm * tiles_n;
+    body(P, M, N, tm * 64, tn * 64, local);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -59,17 +190,14 @@ struct StTheta {
   }
 };
 
-__global__ __launch_bounds__(256) void k_theta(Prob* probs) {
+__global__ __launch_bounds__(256) void k_theta(Prob* probs, const int32_t* offs, int nprob) {
   __shared__ zt smem[Cfg64::lds_elems];
-  const Prob& P = probs[blockIdx.z];
-  if (P.l == 0) return;
-  const int M = P.dl * P.chi_l, N = P.dr * P.chi_r, K = P.chi_m;
-  const int m0 = blockIdx.y * Cfg64::BM, n0 = blockIdx.x * Cfg64::BN;
-  if (m0 >= M || n0 >= N) return;
-  LdThetaA la{P.gk, P.lam_l, P.lam_mid, P.chi_l, P.chi_cap};
-  LdThetaB lb{P.gk1, P.lam_r, P.chi_r, P.chi_cap};
-  StTheta st{P.T, P.chi_l, P.chi_r, P.dr};
-  zgemm_tile<Cfg64>(M, N, K, m0, n0, la, lb, st, smem);
+  for_each_tile<TK_THETA>(probs, offs, nprob, 1, [&](Prob& P, int M, int N, int m0, int n0, int) {
+    LdThetaA la{P.gk, P.lam_l, P.lam_mid, P.chi_l, P.chi_cap};
+    LdThetaB lb{P.gk1, P.lam_r, P.chi_r, P.chi_cap};
+    StTheta st{P.T, P.chi_l, P.chi_r, P.dr};
+    zgemm_tile<Cfg64>(M, N, P.chi_m, m0, n0, la, lb, st, smem);
+  });
 }
 
 // --------------------------------------------------------------------------
@@ -98,34 +226,25 @@ struct StGate {
   }
 };
 
-__global__ __launch_bounds__(256) void k_gate(Prob* probs) {
+__global__ __launch_bounds__(256) void k_gate(Prob* probs, const int32_t* offs, int nprob) {
   __shared__ zt smem[Cfg64::lds_elems];
   __shared__ double red[4];
-  const Prob& P = probs[blockIdx.z];
-  if (P.l == 0) return;
-  const int M = P.dl * P.dr, N = P.chi_l * P.chi_r, K = P.dl * P.dr;
-  const int m0 = blockIdx.y * Cfg64::BM, n0 = blockIdx.x * Cfg64::BN;
-  if (m0 >= M || n0 >= N) return;
-  LdGate la{P.gate, P.gate_ld};
-  LdRowB lb{P.T, N};
-  StGate st{P.A, P.chi_l, P.chi_r, P.dr, P.n, 0.0};
-  zgemm_tile<Cfg64>(M, N, K, m0, n0, la, lb, st, smem);
-  const double s = block_sum<256>(st.acc, red);
-  if (threadIdx.x == 0) {
-    const int tiles_n = (N + Cfg64::BN - 1) / Cfg64::BN;
-    P.part[blockIdx.y * tiles_n + blockIdx.x] = s;
-  }
+  for_each_tile<TK_GATE>(probs, offs, nprob, 1,
+                         [&](Prob& P, int M, int N, int m0, int n0, int local) {
+                           LdGate la{P.gate, P.gate_ld};
+                           LdRowB lb{P.T, N};
+                           StGate st{P.A, P.chi_l, P.chi_r, P.dr, P.n, 0.0};
+                           zgemm_tile<Cfg64>(M, N, P.dl * P.dr, m0, n0, la, lb, st, smem);
+                           const double s = block_sum<256>(st.acc, red);
+                           if (threadIdx.x == 0) P.part[local] = s;
+                         });
 }
 
 hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s) {
-  const int cap = c.dmax * c.chimax;
-  dim3 g1((cap + 63) / 64, (cap + 63) / 64, c.nprob);
-  hipLaunchKernelGGL(k_theta, g1, dim3(256), 0, s, probs);
+  hipLaunchKernelGGL(k_theta, dim3(c.grid), dim3(256), 0, s, probs, c.offs, c.nprob);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int d2 = c.dmax * c.dmax, x2 = c.chimax * c.chimax;
-  dim3 g2((x2 + 63) / 64, (d2 + 63) / 64, c.nprob);
-  hipLaunchKernelGGL(k_gate, g2, dim3(256), 0, s, probs);
+  hipLaunchKernelGGL(k_gate, dim3(c.grid), dim3(256), 0, s, probs, c.offs, c.nprob);
   return hipGetLastError();
 }
 
@@ -156,44 +275,41 @@ struct StCol {  // C[r][c] -> p[c*ld + r]
 };
 
 template <int WHICH>
-__global__ __launch_bounds__(256) void k_sketch(Prob* probs) {
+__global__ __launch_bounds__(256) void k_sketch(Prob* probs, const int32_t* offs, int nprob,
+                                                int tebd) {
   __shared__ zt smem[Cfg64::lds_elems];
-  const Prob& P = probs[blockIdx.z];
-  if (P.l == 0) return;
-  const int m0 = blockIdx.y * Cfg64::BM, n0 = blockIdx.x * Cfg64::BN;
   if (WHICH == SK_Y_FROM_OMEGA) {
-    const int M = P.m, N = P.l, K = P.n;
-    if (m0 >= M || n0 >= N) return;
-    LdRowA la{P.A, P.lda};
-    LdRowB lb{P.om, P.ldom};
-    StCol st{P.Y, P.m};
-    zgemm_tile<Cfg64>(M, N, K, m0, n0, la, lb, st, smem);
+    for_each_tile<TK_SKM>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdRowA la{P.A, P.lda};
+      LdRowB lb{P.om, P.ldom};
+      StCol st{P.Y, P.m};
+      zgemm_tile<Cfg64>(M, N, P.n, m0, n0, la, lb, st, smem);
+    });
   } else if (WHICH == SK_YT_FROM_Y) {
-    const int M = P.n, N = P.l, K = P.m;
-    if (m0 >= M || n0 >= N) return;
-    LdAdjA la{P.A, P.lda};
-    LdColB lb{P.Y, P.m};
-    StCol st{P.Yt, P.n};
-    zgemm_tile<Cfg64>(M, N, K, m0, n0, la, lb, st, smem);
+    for_each_tile<TK_SKN>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdAdjA la{P.A, P.lda};
+      LdColB lb{P.Y, P.m};
+      StCol st{P.Yt, P.n};
+      zgemm_tile<Cfg64>(M, N, P.m, m0, n0, la, lb, st, smem);
+    });
   } else {
-    const int M = P.m, N = P.l, K = P.n;
-    if (m0 >= M || n0 >= N) return;
-    LdRowA la{P.A, P.lda};
-    LdColB lb{P.Yt, P.n};
-    StCol st{P.Y, P.m};
-    zgemm_tile<Cfg64>(M, N, K, m0, n0, la, lb, st, smem);
+    for_each_tile<TK_SKM>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdRowA la{P.A, P.lda};
+      LdColB lb{P.Yt, P.n};
+      StCol st{P.Y, P.m};
+      zgemm_tile<Cfg64>(M, N, P.n, m0, n0, la, lb, st, smem);
+    });
   }
 }
 
 hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s) {
-  const int rows = (which == SK_YT_FROM_Y) ? c.nmax : c.mmax;
-  dim3 g((c.lmax + 63) / 64, (rows + 63) / 64, c.nprob);
+  dim3 g(c.grid);
   if (which == SK_Y_FROM_OMEGA)
-    hipLaunchKernelGGL(k_sketch<SK_Y_FROM_OMEGA>, g, dim3(256), 0, s, probs);
+    hipLaunchKernelGGL(k_sketch<SK_Y_FROM_OMEGA>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
   else if (which == SK_YT_FROM_Y)
-    hipLaunchKernelGGL(k_sketch<SK_YT_FROM_Y>, g, dim3(256), 0, s, probs);
+    hipLaunchKernelGGL(k_sketch<SK_YT_FROM_Y>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
   else
-    hipLaunchKernelGGL(k_sketch<SK_Y_FROM_YT>, g, dim3(256), 0, s, probs);
+    hipLaunchKernelGGL(k_sketch<SK_Y_FROM_YT>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
   return hipGetLastError();
 }
 
@@ -267,60 +383,52 @@ struct StGammaR {  // Gamma'_k+1[j][g][b] = V^H[g, (j,b)] / lam_r[b]
   }
 };
 
-// Tiles entirely beyond chi' only write zeros (no contraction).
+// Tiles entirely beyond chi' only write zeros (no contraction).  In TEBD the
+// column range is the padded MPS capacity, so stale entries are cleared.
 template <int TEBD_>
-__global__ __launch_bounds__(256) void k_form_u(Prob* probs) {
+__global__ __launch_bounds__(256) void k_form_u(Prob* probs, const int32_t* offs, int nprob) {
   __shared__ zt smem[Cfg64::lds_elems];
-  const Prob& P = probs[blockIdx.z];
-  if (P.l == 0) return;
-  // TEBD: clear every padded column of Gamma'_k beyond chi'
-  const int M = P.m, N = TEBD_ ? P.chi_cap : P.kcap, K = P.l;
-  const int m0 = blockIdx.y * Cfg64::BM, n0 = blockIdx.x * Cfg64::BN;
-  if (m0 >= M || n0 >= N) return;
-  const int chi = P.chi_new;
-  const int Keff = (n0 >= chi) ? 0 : K;
-  LdQ la{P.Y, P.m};
-  LdSmallColB lb{P.X, P.l};
-  if (TEBD_) {
-    StGammaL st{P.gk, P.lam_l, P.lambda_floor, P.chi_l, P.chi_cap, chi};
-    zgemm_tile<Cfg64>(M, N, Keff, m0, n0, la, lb, st, smem);
-  } else {
-    StU st{P.U, P.ldu, chi};
-    zgemm_tile<Cfg64>(M, N, Keff, m0, n0, la, lb, st, smem);
-  }
+  for_each_tile<TK_FORMU>(probs, offs, nprob, TEBD_, [&](Prob& P, int M, int N, int m0, int n0, int) {
+    const int chi = P.chi_new;
+    const int Keff = (n0 >= chi) ? 0 : P.l;
+    LdQ la{P.Y, P.m};
+    LdSmallColB lb{P.X, P.l};
+    if (TEBD_) {
+      StGammaL st{P.gk, P.lam_l, P.lambda_floor, P.chi_l, P.chi_cap, chi};
+      zgemm_tile<Cfg64>(M, N, Keff, m0, n0, la, lb, st, smem);
+    } else {
+      StU st{P.U, P.ldu, chi};
+      zgemm_tile<Cfg64>(M, N, Keff, m0, n0, la, lb, st, smem);
+    }
+  });
 }
 
 template <int TEBD_>
-__global__ __launch_bounds__(256) void k_form_vh(Prob* probs) {
+__global__ __launch_bounds__(256) void k_form_vh(Prob* probs, const int32_t* offs, int nprob) {
   __shared__ zt smem[Cfg64::lds_elems];
-  const Prob& P = probs[blockIdx.z];
-  if (P.l == 0) return;
-  const int M = TEBD_ ? P.chi_cap : P.kcap, N = P.n, K = P.l;
-  const int m0 = blockIdx.y * Cfg64::BM, n0 = blockIdx.x * Cfg64::BN;
-  if (m0 >= M || n0 >= N) return;
-  const int chi = P.chi_new;
-  const int Keff = (m0 >= chi) ? 0 : K;
-  LdSmallAdjA la{P.W, P.l};
-  LdQbAdjB lb{P.Yt, P.n};
-  if (TEBD_) {
-    StGammaR st{P.gk1, P.lam_r, P.lambda_floor, P.chi_r, P.chi_cap, chi};
-    zgemm_tile<Cfg64>(M, N, Keff, m0, n0, la, lb, st, smem);
-  } else {
-    StVH st{P.VH, P.ldvh, chi};
-    zgemm_tile<Cfg64>(M, N, Keff, m0, n0, la, lb, st, smem);
-  }
+  for_each_tile<TK_FORMV>(probs, offs, nprob, TEBD_, [&](Prob& P, int M, int N, int m0, int n0, int) {
+    const int chi = P.chi_new;
+    const int Keff = (m0 >= chi) ? 0 : P.l;
+    LdSmallAdjA la{P.W, P.l};
+    LdQbAdjB lb{P.Yt, P.n};
+    if (TEBD_) {
+      StGammaR st{P.gk1, P.lam_r, P.lambda_floor, P.chi_r, P.chi_cap, chi};
+      zgemm_tile<Cfg64>(M, N, Keff, m0, n0, la, lb, st, smem);
+    } else {
+      StVH st{P.VH, P.ldvh, chi};
+      zgemm_tile<Cfg64>(M, N, Keff, m0, n0, la, lb, st, smem);
+    }
+  });
 }
 
 hipError_t launch_form_uv(Prob* probs, const Common& c, hipStream_t s) {
-  const int kc = c.tebd ? c.chimax : c.kcap;
-  dim3 gu((kc + 63) / 64, (c.mmax + 63) / 64, c.nprob);
-  dim3 gv((c.nmax + 63) / 64, (kc + 63) / 64, c.nprob);
+  dim3 g(c.grid);
   if (c.tebd) {
-    hipLaunchKernelGGL(k_form_u<1>, gu, dim3(256), 0, s, probs);
-    hipLaunchKernelGGL(k_form_vh<1>, gv, dim3(256), 0, s, probs);
+    hipLaunchKernelGGL(k_form_u<1>, g, dim3(256), 0, s, probs, c.offs, c.nprob);
+    hipLaunchKernelGGL(k_form_vh<1>, g, dim3(256), 0, s, probs, c.offs, c.nprob);
   } else {
-    hipLaunchKernelGGL(k_form_u<0>, gu, dim3(256), 0, s, probs);
-    hipLaunchKernelGGL(k_form_vh<0>, gv, dim3(256), 0, s, probs);
+    hipLaunchKernelGGL(k_form_u<0>, g, dim3(256), 0, s, probs, c.offs, c.nprob);
+    hipLaunchKernelGGL(k_form_vh<0>, g, dim3(256), 0, s, probs, c.offs, c.nprob);
   }
   return hipGetLastError();
 }

@@ -86,7 +86,24 @@ struct Common {
   int32_t tebd;      // 1: TEBD problems (Theta/gate/reabsorb kernels run)
   int32_t dmax;      // TEBD: max local dim
   int32_t chimax;    // TEBD: chi capacity
+  int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
+  int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
 };
+
+// Contraction kinds scheduled through a global tile queue: every kind has
+// its own prefix sum over problems of the number of 64 x 64 output tiles.
+enum {
+  TK_THETA = 0,  // Theta build: (dl chi_l) x (dr chi_r)
+  TK_GATE = 1,   // gate: (dl dr) x (chi_l chi_r)
+  TK_SKM = 2,    // m x l products (A Omega, A Q~)
+  TK_SKN = 3,    // n x l products (A^H Q)
+  TK_FORMU = 4,  // m x (kept capacity)
+  TK_FORMV = 5,  // (kept capacity) x n
+  TK_COUNT = 6
+};
+
+inline size_t sched_bytes(int64_t nprob) { return size_t(TK_COUNT) * size_t(nprob + 1) * sizeof(int32_t); }
+
 
 // Launchers (defined in the .hip files).  All enqueue on `s` and return the
 // first HIP error met, or hipSuccess.
@@ -95,6 +112,7 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
                              int32_t single_bond, int32_t p_over, char* slab_base,
                              size_t slab_bytes, double* disc, int32_t* status, double lambda_floor,
                              int32_t mixed, hipStream_t s);
+hipError_t launch_schedule(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_frob(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_omega(Prob* probs, const Common& c, hipStream_t s);
