@@ -262,6 +262,7 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   c.mmax = int32_t(pl.mcap);
   c.nmax = int32_t(pl.mcap);
   c.lmax = int32_t(pl.lcap);
+  c.mmin = c.nmin = c.lmin = 1;  // bond dimensions are only known on the device
   c.kcap = prm->chi_max;
   c.tebd = 1;
   c.dmax = mps->d_max;
@@ -418,6 +419,7 @@ tebd_status rrsvd_truncate(int64_t batch, const int64_t* m, const int64_t* n,
   c.seed = prm->seed;
   c.stream_id = prm->stream_id;
   c.mmax = c.nmax = c.lmax = 0;
+  c.mmin = c.nmin = c.lmin = 1 << 30;
   c.kcap = prm->chi_max;
   c.tebd = 0;
   c.dmax = 0;
@@ -451,6 +453,9 @@ tebd_status rrsvd_truncate(int64_t batch, const int64_t* m, const int64_t* n,
     c.mmax = P.m > c.mmax ? P.m : c.mmax;
     c.nmax = P.n > c.nmax ? P.n : c.nmax;
     c.lmax = P.l > c.lmax ? P.l : c.lmax;
+    c.mmin = P.m < c.mmin ? P.m : c.mmin;
+    c.nmin = P.n < c.nmin ? P.n : c.nmin;
+    c.lmin = P.l < c.lmin ? P.l : c.lmin;
   }
   c.offs = reinterpret_cast<int32_t*>(base + align256(size_t(batch) * sizeof(Prob)));
   {

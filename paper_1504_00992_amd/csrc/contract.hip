@@ -155,6 +155,58 @@ __device__ __forceinline__ void for_each_tile(Prob* probs, const int32_t* offs, 
 }
 
 // --------------------------------------------------------------------------
+// Gaussian test matrix Omega (Alg. 1, first step), generated tile by tile
+// over the n x l tile queue.  Philox4x32-10 (Salmon et al., SC'11): ten
+// rounds on the counter (r, c, problem id, stream id) with key
+// (seed low, seed high), the key advanced by the Weyl constants before every
+// round but the first; the first two output words give u = (x + 1/2) 2^-32
+// and z = sqrt(-2 ln u1) exp(2 pi i u2) / sqrt(2).
+__device__ __forceinline__ void philox10(uint32_t x[4], uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint32_t hi0 = __umulhi(M0, x[0]), lo0 = M0 * x[0];
+    const uint32_t hi1 = __umulhi(M1, x[2]), lo1 = M1 * x[2];
+    const uint32_t y0 = hi1 ^ x[1] ^ k0, y2 = hi0 ^ x[3] ^ k1;
+    x[0] = y0;
+    x[1] = lo1;
+    x[2] = y2;
+    x[3] = lo0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_omega(Prob* probs, const int32_t* offs, int nprob,
+                                               int tebd, uint64_t seed, uint32_t sid) {
+  for_each_tile<TK_SKN>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+    if (P.om_ext) return;
+    zt* om = const_cast<zt*>(P.om);
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+      const int r = m0 + e / 64, c = n0 + (e & 63);
+      if (r >= M || c >= N) continue;
+      uint32_t x[4] = {uint32_t(r), uint32_t(c), uint32_t(P.pid), sid};
+      philox10(x, uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32));
+      const double u1 = (double(x[0]) + 0.5) * 0x1p-32;
+      const double u2 = (double(x[1]) + 0.5) * 0x1p-32;
+      const double rad = sqrt(-2.0 * log(u1)) * 0.70710678118654752440;
+      double sn, cs;
+      sincos(2.0 * M_PI * u2, &sn, &cs);
+      om[size_t(r) * P.ldom + c] = make_double2(rad * cs, rad * sn);
+    }
+  });
+}
+
+hipError_t launch_omega(Prob* probs, const Common& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_omega, dim3(c.grid), dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd,
+                     c.seed, c.stream_id);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
 // Theta build
 struct LdThetaA {  // (r = i*chi_l + a, k = g)
   const zt* gk;

@@ -1,6 +1,5 @@
 // Wavefront-level kernels of the RRSVD pipeline (one workgroup per problem):
-// planning of a TEBD sweep, ||A||_F^2, the Gaussian test matrix, Householder
-// QR with explicit Q, the small SVD by one-sided Jacobi, and the truncation
+// planning of a TEBD sweep, ||A||_F^2, Householder QR with explicit Q, the small SVD by one-sided Jacobi, and the truncation
 // rule with lambda renormalisation.
 //
 // Paper: Tamascelli, Rosenbach, Plenio, arXiv:1504.00992.  QR steps of Alg. 1
@@ -138,69 +137,73 @@ hipError_t launch_frob(Prob* probs, const Common& c, hipStream_t s) {
 }
 
 // --------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC'11) and the complex Gaussian Omega.
-__device__ __forceinline__ void philox10(uint32_t x[4], uint32_t k0, uint32_t k1) {
-  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
-  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += W0;
-      k1 += W1;
-    }
-    const uint32_t hi0 = __umulhi(M0, x[0]), lo0 = M0 * x[0];
-    const uint32_t hi1 = __umulhi(M1, x[2]), lo1 = M1 * x[2];
-    const uint32_t y0 = hi1 ^ x[1] ^ k0, y2 = hi0 ^ x[3] ^ k1;
-    x[0] = y0;
-    x[1] = lo1;
-    x[2] = y2;
-    x[3] = lo0;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_omega(Prob* probs, uint64_t seed, uint32_t sid) {
-  const Prob& P = probs[blockIdx.y];
-  if (P.l == 0 || P.om_ext) return;
-  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  const int64_t total = int64_t(P.n) * P.l;
-  if (e >= total) return;
-  const int r = int(e / P.l), c = int(e - int64_t(r) * P.l);
-  uint32_t x[4] = {uint32_t(r), uint32_t(c), uint32_t(P.pid), sid};
-  philox10(x, uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32));
-  const double u1 = (double(x[0]) + 0.5) * 0x1p-32;
-  const double u2 = (double(x[1]) + 0.5) * 0x1p-32;
-  const double rad = sqrt(-2.0 * log(u1)) * 0.70710678118654752440;
-  double sn, cs;
-  sincos(2.0 * M_PI * u2, &sn, &cs);
-  const_cast<zt*>(P.om)[size_t(r) * P.ldom + c] = make_double2(rad * cs, rad * sn);
-}
-
-hipError_t launch_omega(Prob* probs, const Common& c, hipStream_t s) {
-  const int64_t total = int64_t(c.nmax) * c.lmax;
-  dim3 g(unsigned((total + 255) / 256), c.nprob);
-  hipLaunchKernelGGL(k_omega, g, dim3(256), 0, s, probs, c.seed, c.stream_id);
-  return hipGetLastError();
-}
-
-// --------------------------------------------------------------------------
 // Householder QR of a rows x l column-major matrix (ld = rows), in place,
 // followed by the explicit thin Q (backward accumulation).  Reflector j is
 // H_j = I - 2 u u^H with ||u|| = 1, u supported on rows >= j, chosen so that
 // H_j x = beta e_j with beta = -phase(x_j) ||x||; a zero column gives H_j = I.
 // With want_r the l x l upper factor (column-major) is written to P.Rb first.
-template <int NT>
-__global__ __launch_bounds__(NT) void k_qr(Prob* probs, int which, int want_r) {
-  extern __shared__ zt u_s[];  // rows
-  __shared__ double red[NT / 64];
-  __shared__ zt rdiag[kMaxL];
-  Prob& P = probs[blockIdx.x];
-  const int l = P.l;
-  if (l == 0) return;
-  const int rows = which ? P.n : P.m;
-  zt* Y = which ? P.Yt : P.Y;
+//
+// Two variants share one body: problems with (l + 1) rows <= kLdsElems keep
+// the whole matrix in LDS (small bonds are latency-bound); larger ones work
+// on the matrix in global memory (L2-resident) with one wavefront per
+// trailing column, the column held in registers between its dot product and
+// its update when it has at most 64 * kRegRows rows left.
+constexpr int kLdsElems = 9600;  // complex elements of LDS a workgroup may claim (150 KiB)
+constexpr int kRegRows = 16;
+
+__device__ __forceinline__ bool qr_in_lds(int rows, int l) {
+  return int64_t(l + 1) * rows <= kLdsElems;
+}
+
+// y_c[j0..rows) -= 2 u (u^H y_c) for one column, by one wavefront.  Rows
+// below `skip` are treated as zero on input (they held R entries).
+template <int REG>
+__device__ __forceinline__ void reflect_column(const zt* __restrict__ u, zt* yc, int j0, int skip,
+                                               int rows, int lane) {
+  const int nr = rows - j0;
+  double dr = 0.0, di = 0.0;
+  if (REG > 0 && nr <= 64 * REG) {
+    zt cache[REG > 0 ? REG : 1];
+#pragma unroll
+    for (int i = 0; i < REG; ++i) {
+      const int r = j0 + lane + 64 * i;
+      cache[i] = (r < rows && r >= skip) ? yc[r] : make_double2(0.0, 0.0);
+      if (r < rows) {
+        const zt t = zcmul(u[r], cache[i]);
+        dr += t.x;
+        di += t.y;
+      }
+    }
+    dr = wave_sum(dr);
+    di = wave_sum(di);
+    const zt d2 = make_double2(2.0 * dr, 2.0 * di);
+#pragma unroll
+    for (int i = 0; i < REG; ++i) {
+      const int r = j0 + lane + 64 * i;
+      if (r < rows) yc[r] = zsub(cache[i], zmul(u[r], d2));
+    }
+  } else {
+    for (int r = j0 + lane; r < rows; r += 64) {
+      if (r < skip) continue;
+      const zt t = zcmul(u[r], yc[r]);
+      dr += t.x;
+      di += t.y;
+    }
+    dr = wave_sum(dr);
+    di = wave_sum(di);
+    const zt d2 = make_double2(2.0 * dr, 2.0 * di);
+    for (int r = j0 + lane; r < rows; r += 64) {
+      const zt old = r < skip ? make_double2(0.0, 0.0) : yc[r];
+      yc[r] = zsub(old, zmul(u[r], d2));
+    }
+  }
+}
+
+template <int NT, int REG>
+__device__ __forceinline__ void qr_core(zt* Y, int rows, int l, zt* u_s, zt* rdiag, double* red,
+                                        zt* Rb) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = NT / 64;
-
   for (int j = 0; j < l; ++j) {
     zt* yj = Y + size_t(j) * rows;
     double s = 0.0;
@@ -209,14 +212,9 @@ __global__ __launch_bounds__(NT) void k_qr(Prob* probs, int which, int want_r) {
     const zt alpha = yj[j];
     const double aa = sqrt(zabs2(alpha));
     const double xnorm = sqrt(aa * aa + s);
-    zt beta;
-    double vinv;  // 1 / ||x - beta e_j||
-    zt v0;
-    if (xnorm == 0.0) {
-      beta = make_double2(0.0, 0.0);
-      vinv = 0.0;
-      v0 = make_double2(0.0, 0.0);
-    } else {
+    zt beta = make_double2(0.0, 0.0), v0 = make_double2(0.0, 0.0);
+    double vinv = 0.0;  // 1 / ||x - beta e_j||
+    if (xnorm > 0.0) {
       const zt ph = aa > 0.0 ? zscale(alpha, 1.0 / aa) : make_double2(1.0, 0.0);
       beta = zscale(ph, -xnorm);
       v0 = zsub(alpha, beta);
@@ -230,25 +228,11 @@ __global__ __launch_bounds__(NT) void k_qr(Prob* probs, int which, int want_r) {
     }
     if (tid == 0) rdiag[j] = beta;
     __syncthreads();
-    if (vinv != 0.0) {
-      for (int c = j + 1 + wave; c < l; c += NW) {
-        zt* yc = Y + size_t(c) * rows;
-        double dr = 0.0, di = 0.0;
-        for (int r = j + lane; r < rows; r += 64) {
-          const zt t = zcmul(u_s[r], yc[r]);
-          dr += t.x;
-          di += t.y;
-        }
-        dr = wave_sum(dr);
-        di = wave_sum(di);
-        const zt d2 = make_double2(2.0 * dr, 2.0 * di);
-        for (int r = j + lane; r < rows; r += 64) yc[r] = zsub(yc[r], zmul(u_s[r], d2));
-      }
-    }
+    if (vinv != 0.0)
+      for (int c = j + 1 + wave; c < l; c += NW) reflect_column<REG>(u_s, Y + size_t(c) * rows, j, j, rows, lane);
     __syncthreads();
   }
-
-  if (want_r) {
+  if (Rb) {
     for (int e = tid; e < l * l; e += NT) {
       const int c = e / l, i = e - c * l;
       zt v;
@@ -258,40 +242,23 @@ __global__ __launch_bounds__(NT) void k_qr(Prob* probs, int which, int want_r) {
         v = rdiag[c];
       else
         v = make_double2(0.0, 0.0);
-      P.Rb[e] = v;
+      Rb[e] = v;
     }
     __syncthreads();
   }
-
   // Q = H_0 H_1 ... H_{l-1} [I; 0], accumulated from the last reflector.
   for (int j = l - 1; j >= 0; --j) {
     zt* yj = Y + size_t(j) * rows;
     for (int r = j + tid; r < rows; r += NT) u_s[r] = yj[r];
     __syncthreads();
-    // trailing columns: row j is treated as zero (it held R entries)
-    for (int c = j + 1 + wave; c < l; c += NW) {
-      zt* yc = Y + size_t(c) * rows;
-      double dr = 0.0, di = 0.0;
-      for (int r = j + 1 + lane; r < rows; r += 64) {
-        const zt t = zcmul(u_s[r], yc[r]);
-        dr += t.x;
-        di += t.y;
-      }
-      dr = wave_sum(dr);
-      di = wave_sum(di);
-      const zt d2 = make_double2(2.0 * dr, 2.0 * di);
-      for (int r = j + lane; r < rows; r += 64) {
-        const zt old = (r == j) ? make_double2(0.0, 0.0) : yc[r];
-        yc[r] = zsub(old, zmul(u_s[r], d2));
-      }
-    }
+    // trailing columns: row j held an R entry and is treated as zero
+    for (int c = j + 1 + wave; c < l; c += NW)
+      reflect_column<REG>(u_s, Y + size_t(c) * rows, j, j + 1, rows, lane);
     // column j = H_j e_j
     const zt uj = u_s[j];
     for (int r = tid; r < rows; r += NT) {
-      zt v;
-      if (r < j) {
-        v = make_double2(0.0, 0.0);
-      } else {
+      zt v = make_double2(0.0, 0.0);
+      if (r >= j) {
         v = zscale(zmul(u_s[r], zconj(uj)), -2.0);
         if (r == j) v.x += 1.0;
       }
@@ -301,14 +268,72 @@ __global__ __launch_bounds__(NT) void k_qr(Prob* probs, int which, int want_r) {
   }
 }
 
+// Size classes: a problem of measure (l + 1) * rows in (LO, HI] runs in the
+// LDS variant of that class (HI complex elements of LDS, NT threads):
+// (0, 1024] with 64 threads, (1024, 3072] with 256, (3072, 9600] with 1024;
+// above that it runs on global memory with 1024 threads.  Every class is one
+// launch over all problems; workgroups of other classes return at once.
+template <int NT, int HI, int LO>
+__global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_r) {
+  extern __shared__ zt lds[];  // rows * l matrix, then rows for u
+  __shared__ double red[NT / 64];
+  __shared__ zt rdiag[kMaxL];
+  Prob& P = probs[blockIdx.x];
+  const int l = P.l;
+  const int rows = which ? P.n : P.m;
+  const int64_t meas = int64_t(l + 1) * rows;
+  if (l == 0 || meas <= LO || meas > HI) return;
+  zt* Yg = which ? P.Yt : P.Y;
+  const int tot = rows * l;
+  for (int e = threadIdx.x; e < tot; e += NT) lds[e] = Yg[e];
+  __syncthreads();
+  qr_core<NT, 0>(lds, rows, l, lds + tot, rdiag, red, want_r ? P.Rb : nullptr);
+  for (int e = threadIdx.x; e < tot; e += NT) Yg[e] = lds[e];
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_r) {
+  extern __shared__ zt u_s[];  // rows
+  __shared__ double red[NT / 64];
+  __shared__ zt rdiag[kMaxL];
+  Prob& P = probs[blockIdx.x];
+  const int l = P.l;
+  const int rows = which ? P.n : P.m;
+  if (l == 0 || qr_in_lds(rows, l)) return;
+  qr_core<NT, kRegRows>(which ? P.Yt : P.Y, rows, l, u_s, rdiag, red, want_r ? P.Rb : nullptr);
+}
+
+// Whether any problem with measure in [mlo, mhi] can fall in (lo, hi].
+inline bool class_reached(int64_t mlo, int64_t mhi, int64_t lo, int64_t hi) {
+  return mhi > lo && (hi == 0 || mlo <= hi);
+}
+
 hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStream_t s) {
   const int rows = which ? c.nmax : c.mmax;
-  const size_t lds = size_t(rows) * sizeof(zt);
-  static const hipError_t attr = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(&k_qr<256>), hipFuncAttributeMaxDynamicSharedMemorySize,
-      int(size_t(kMaxRows) * sizeof(zt)));
+  const int rows_min = which ? c.nmin : c.mmin;
+  const int64_t mhi = int64_t(c.lmax + 1) * rows, mlo = int64_t(c.lmin + 1) * rows_min;
+  static const hipError_t attr = []() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_qr_glb<1024>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       int(size_t(kMaxRows) * sizeof(zt)));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_qr_lds<1024, kLdsElems, 3072>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               int(size_t(kLdsElems) * sizeof(zt)));
+  }();
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL(k_qr<256>, dim3(c.nprob), dim3(256), lds, s, probs, which, want_r);
+  const dim3 g(c.nprob);
+  if (class_reached(mlo, mhi, 0, 1024))
+    hipLaunchKernelGGL((k_qr_lds<64, 1024, 0>), g, dim3(64), 1024 * sizeof(zt), s, probs, which, want_r);
+  if (class_reached(mlo, mhi, 1024, 3072))
+    hipLaunchKernelGGL((k_qr_lds<256, 3072, 1024>), g, dim3(256), 3072 * sizeof(zt), s, probs, which,
+                       want_r);
+  if (class_reached(mlo, mhi, 3072, kLdsElems))
+    hipLaunchKernelGGL((k_qr_lds<1024, kLdsElems, 3072>), g, dim3(1024), size_t(kLdsElems) * sizeof(zt),
+                       s, probs, which, want_r);
+  if (class_reached(mlo, mhi, kLdsElems, 0))
+    hipLaunchKernelGGL(k_qr_glb<1024>, g, dim3(1024), size_t(rows) * sizeof(zt), s, probs, which,
+                       want_r);
   return hipGetLastError();
 }
 
@@ -321,39 +346,29 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStr
 // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), cs = 1/sqrt(1+t^2), sn = t cs,
 //   c_p <- cs c_p - sn e^{-i phi} c_q,  c_q <- sn c_p + cs e^{-i phi} c_q,
 // which zeroes the (p, q) Gram entry.  The same rotation accumulates into J.
-// At convergence C J... = X Sigma with orthogonal columns, so
+// At convergence C J = X Sigma with orthogonal columns, so
 // B = X Sigma (Q_B J)^H: left vectors X (normalised columns), values Sigma,
 // right vectors Q_B J (formed later).  Outputs are sorted descending.
+// C and J live in LDS when 2 l^2 fits, else in global memory; a pair's
+// columns are held in registers (l <= 64 * REGS) for the whole rotation.
+
 __device__ __forceinline__ int circle_player(int pos, int round, int lp) {
   if (pos == 0) return 0;
   return 1 + (pos - 1 + round) % (lp - 1);
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
-  __shared__ double sig_s[kMaxL];
-  __shared__ int perm_s[kMaxL];
-  __shared__ int rotated;
-  Prob& P = probs[blockIdx.x];
-  const int l = P.l;
-  if (l == 0) return;
+
+template <int NT, int REGS>
+__device__ __forceinline__ void jacobi_core(zt* C, zt* J, int l, int& converged_out,
+                                            int* rotated) {
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  zt* C = P.C;
-  zt* J = P.J;
-  for (int e = tid; e < l * l; e += NT) {
-    const int c = e / l, r = e - c * l;
-    C[e] = zconj(P.Rb[size_t(r) * l + c]);
-    J[e] = make_double2(r == c ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
   const int lp = l + (l & 1);
   const double tol = DBL_EPSILON * sqrt(double(l));
   constexpr int kMaxSweeps = 40;
-  int sweep = 0;
   bool converged = (l == 1);
-  for (; sweep < kMaxSweeps && !converged; ++sweep) {
-    if (tid == 0) rotated = 0;
+  for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
+    if (tid == 0) *rotated = 0;
     __syncthreads();
     for (int round = 0; round < lp - 1; ++round) {
       for (int pr = wave; pr < lp / 2; pr += NW) {
@@ -362,12 +377,16 @@ __global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
         if (q >= l) continue;
         zt* cp = C + size_t(p) * l;
         zt* cq = C + size_t(q) * l;
+        zt xp[REGS], xq[REGS];
         double app = 0.0, aqq = 0.0, gr = 0.0, gi = 0.0;
-        for (int r = lane; r < l; r += 64) {
-          const zt x = cp[r], y = cq[r];
-          app += zabs2(x);
-          aqq += zabs2(y);
-          const zt t = zcmul(x, y);
+#pragma unroll
+        for (int i = 0; i < REGS; ++i) {
+          const int r = lane + 64 * i;
+          xp[i] = r < l ? cp[r] : make_double2(0.0, 0.0);
+          xq[i] = r < l ? cq[r] : make_double2(0.0, 0.0);
+          app += zabs2(xp[i]);
+          aqq += zabs2(xq[i]);
+          const zt t = zcmul(xp[i], xq[i]);
           gr += t.x;
           gi += t.y;
         }
@@ -381,27 +400,42 @@ __global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
         const zt em = make_double2(gr / ag, -gi / ag);  // e^{-i phi}
-        for (int r = lane; r < l; r += 64) {
-          const zt x = cp[r], y = zmul(em, cq[r]);
-          cp[r] = zsub(zscale(x, cs), zscale(y, sn));
-          cq[r] = zadd(zscale(x, sn), zscale(y, cs));
+#pragma unroll
+        for (int i = 0; i < REGS; ++i) {
+          const int r = lane + 64 * i;
+          if (r < l) {
+            const zt x = xp[i], y = zmul(em, xq[i]);
+            cp[r] = zsub(zscale(x, cs), zscale(y, sn));
+            cq[r] = zadd(zscale(x, sn), zscale(y, cs));
+          }
         }
         zt* jp = J + size_t(p) * l;
         zt* jq = J + size_t(q) * l;
-        for (int r = lane; r < l; r += 64) {
-          const zt x = jp[r], y = zmul(em, jq[r]);
-          jp[r] = zsub(zscale(x, cs), zscale(y, sn));
-          jq[r] = zadd(zscale(x, sn), zscale(y, cs));
+#pragma unroll
+        for (int i = 0; i < REGS; ++i) {
+          const int r = lane + 64 * i;
+          if (r < l) {
+            const zt x = jp[r], y = zmul(em, jq[r]);
+            jp[r] = zsub(zscale(x, cs), zscale(y, sn));
+            jq[r] = zadd(zscale(x, sn), zscale(y, cs));
+          }
         }
-        if (lane == 0) rotated = 1;
+        if (lane == 0) *rotated = 1;
       }
       __syncthreads();
     }
-    converged = (rotated == 0);
+    converged = (*rotated == 0);
     __syncthreads();
   }
-  if (!converged && tid == 0) P.flags |= TEBD_DEV_JACOBI_NOCONV;
-  // column norms
+  converged_out = converged ? 1 : 0;
+}
+
+// Column norms, descending order, and the sorted outputs X, W, sig.
+template <int NT>
+__device__ __forceinline__ void jacobi_finish(Prob& P, const zt* C, const zt* J, int l,
+                                              double* sig_s, int* perm_s) {
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int c = wave; c < l; c += NW) {
     double s = 0.0;
     for (int r = lane; r < l; r += 64) s += zabs2(C[size_t(c) * l + r]);
@@ -430,8 +464,47 @@ __global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
   for (int c = tid; c < l; c += NT) P.sig[c] = sig_s[perm_s[c]];
 }
 
+// Size classes on 2 l^2 (C and J together), as for the QR.
+template <int NT, int HI, int LO, int REGS>
+__global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
+  extern __shared__ zt lds[];
+  __shared__ double sig_s[kMaxL];
+  __shared__ int perm_s[kMaxL];
+  __shared__ int rotated;
+  Prob& P = probs[blockIdx.x];
+  const int l = P.l;
+  const int meas = 2 * l * l;
+  if (l == 0 || meas <= LO || (HI > 0 && meas > HI)) return;
+  zt* C = HI > 0 ? lds : P.C;
+  zt* J = HI > 0 ? lds + l * l : P.J;
+  for (int e = threadIdx.x; e < l * l; e += NT) {
+    const int c = e / l, r = e - c * l;
+    C[e] = zconj(P.Rb[size_t(r) * l + c]);
+    J[e] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  int converged;
+  jacobi_core<NT, REGS>(C, J, l, converged, &rotated);
+  if (!converged && threadIdx.x == 0) P.flags |= TEBD_DEV_JACOBI_NOCONV;
+  jacobi_finish<NT>(P, C, J, l, sig_s, perm_s);
+}
+
 hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_small_svd<256>, dim3(c.nprob), dim3(256), 0, s, probs);
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&k_small_svd<1024, kLdsElems, 3072, 2>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, int(size_t(kLdsElems) * sizeof(zt)));
+  if (attr != hipSuccess) return attr;
+  const int64_t mhi = 2 * int64_t(c.lmax) * c.lmax, mlo = 2 * int64_t(c.lmin) * c.lmin;
+  const dim3 g(c.nprob);
+  if (class_reached(mlo, mhi, 0, 1024))
+    hipLaunchKernelGGL((k_small_svd<64, 1024, 0, 1>), g, dim3(64), 1024 * sizeof(zt), s, probs);
+  if (class_reached(mlo, mhi, 1024, 3072))
+    hipLaunchKernelGGL((k_small_svd<256, 3072, 1024, 1>), g, dim3(256), 3072 * sizeof(zt), s, probs);
+  if (class_reached(mlo, mhi, 3072, kLdsElems))
+    hipLaunchKernelGGL((k_small_svd<1024, kLdsElems, 3072, 2>), g, dim3(1024),
+                       size_t(kLdsElems) * sizeof(zt), s, probs);
+  if (class_reached(mlo, mhi, kLdsElems, 0))
+    hipLaunchKernelGGL((k_small_svd<1024, 0, kLdsElems, 4>), g, dim3(1024), 0, s, probs);
   return hipGetLastError();
 }
 

@@ -83,6 +83,7 @@ struct Common {
   uint32_t stream_id;
   // capacities (grid sizing): max over problems
   int32_t mmax, nmax, lmax, kcap;
+  int32_t mmin, nmin, lmin;  // smallest possible sizes (size-class launches)
   int32_t tebd;      // 1: TEBD problems (Theta/gate/reabsorb kernels run)
   int32_t dmax;      // TEBD: max local dim
   int32_t chimax;    // TEBD: chi capacity
@@ -200,7 +201,7 @@ __host__ __device__ inline void carve_slab(Prob& p, char* base, int64_t m, int64
 }
 
 // Largest l (sketch width) and m supported by the factorisation kernels.
-constexpr int kMaxL = 512;
+constexpr int kMaxL = 256;
 constexpr int kMaxRows = 8192;
 
 }  // namespace tebd
