@@ -46,6 +46,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full-svd", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--rank", choices=("adaptive", "fixed"), default="adaptive",
+                    help="rank of the timed run: two-stage adaptive (k1 from the bond dimension, "
+                         "k = chi_max when needed) or fixed k = chi_max")
+    ap.add_argument("--no-other-rank", action="store_true",
+                    help="skip the run with the other rank mode")
     return ap.parse_args()
 
 
@@ -113,11 +118,12 @@ def roofline(prof, flops):
 
 
 # ---------------------------------------------------------------------------
-def run_gpu_tebd(args, torch, api, models, prof_on=True):
+def run_gpu_tebd(args, torch, api, models, adaptive, prof_on=True):
     N, d, chi_max, p, q = 100, 10, 100, 10, 2
     dims, hb = models.spin_boson(N, d, 1.0, 0.5, 1.0, 0.5)
     mps = api.DeviceMPS.product_state(args.chains, dims, [0] * N, chi_max)
-    drv = api.TEBD(mps, hb, 0.05, chi_max, p=p, q=q, trunc_eps=1e-10, seed=1504)
+    drv = api.TEBD(mps, hb, 0.05, chi_max, p=p, q=q, trunc_eps=1e-10, seed=1504,
+                   adaptive=1 if adaptive else 0)
     for _ in range(args.warmup):
         drv.step()
     torch.cuda.synchronize()
@@ -302,7 +308,8 @@ def main():
     import workloads as wl
     _lib.load()
 
-    res = run_gpu_tebd(args, torch, api, models)
+    adaptive = args.rank == "adaptive"
+    res = run_gpu_tebd(args, torch, api, models, adaptive)
     N = 100
     per_step = updates_per_step(N) * args.chains
     total_updates = per_step * args.steps
@@ -326,12 +333,23 @@ def main():
         "config": {"workload": "batched TEBD sweep: 16 chain-mapped spin-boson chains, N=100 "
                                "(spin + 99 oscillators, d=10), t_n=0.5, w_n=1, dt=0.05, chi_max=100, "
                                "RRSVD p=10 q=2, w<=1e-10 per bond",
+                   "rank": ("two-stage adaptive: k1 = chi + max(4, chi/2), k = chi_max when the "
+                            "Frobenius residual needs it" if adaptive else "fixed k = chi_max"),
                    "chains": args.chains, "bond_updates_per_step": per_step,
                    "chi_final_max": int(res["chi_final"].max()),
                    "status_bits_seen": sorted(set(int(x) for x in np.unique(res["status"])))},
         "phase_ms": {k: round(v[0], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
         "roofline": roofline(prof, flops),
     }
+    if not args.no_other_rank:
+        other = run_gpu_tebd(args, torch, api, models, not adaptive, prof_on=True)
+        oval = total_updates / other["seconds"]
+        line["other_rank_mode"] = {
+            "rank": "fixed k = chi_max" if adaptive else "two-stage adaptive",
+            "value": round(oval, 2), "unit": "bond updates/s",
+            "ms_per_step": round(1e3 * other["seconds"] / args.steps, 4),
+            "phase_ms": {k: round(v[0], 3) for k, v in sorted(other["prof"].items(), key=lambda kv: -kv[1][0])},
+            "chi_final_max": int(other["chi_final"].max())}
     if not args.no_full_svd:
         nsteps = args.steps if args.full_svd_steps < 0 else args.full_svd_steps
         done, fsec = full_svd_tebd(args, torch, models, res["dims"], res["hb"], args.warmup, nsteps)

@@ -30,6 +30,9 @@
  *   rows).  Two-site gates are indexed row = i_k * d_{k+1} + i_{k+1}
  *   (Kronecker order); the blocked Theta has row i_k * chi_l + alpha and
  *   column i_{k+1} * chi_r + beta.
+ * Sketch width: l = min(k + p, m, n).  The QR steps of Alg. 1 pivot columns
+ *   and keep the numerical range of the sketch (|R_jj| > 1e-13 |R_00|), so
+ *   at most that many singular values are returned.
  * Randomness: the Gaussian test matrix Omega (Sec. IV, Alg. 1, first step)
  *   is drawn by Philox4x32-10 (Salmon et al., SC'11).  Entry (r, c) of
  *   problem `pid` uses counter (r, c, pid, params.stream_id) and key
@@ -67,8 +70,9 @@ enum {
   TEBD_DEV_JACOBI_NOCONV = 4, /* small SVD hit its sweep limit               */
   TEBD_DEV_LAMBDA_FLOOR = 8,  /* a lambda <= lambda_floor was not inverted   */
   TEBD_DEV_CHI_BOUND = 16,    /* chi_max (or l) binds before w <= trunc_eps  */
-  TEBD_DEV_BAD_STATE = 32     /* chi or d on the device out of range: the
+  TEBD_DEV_BAD_STATE = 32,    /* chi or d on the device out of range: the
                                  problem was skipped, the MPS left as it was */
+  TEBD_DEV_RANK_RETRY = 64    /* adaptive rank: stage 2 was needed (info)    */
 };
 
 typedef struct {
@@ -85,7 +89,15 @@ typedef struct {
   double lambda_floor;  /* lambda <= floor is not inverted (its inverse is 0)  */
   uint64_t seed;        /* Philox key                                          */
   uint32_t stream_id;   /* Philox counter word 3 (e.g. a running sweep count)  */
-  uint32_t reserved;    /* must be 0                                           */
+  int32_t adaptive;     /* 0: fixed rank k = chi_max (Sec. IV, fixed-rank
+                           problem).  1 (TEBD entry points only, trunc_eps > 0):
+                           two-stage rank.  Stage 1 uses k1 = min(chi_max,
+                           chi + max(4, ceil(chi/2))) with chi the bond
+                           dimension before the update, and is kept when some
+                           c <= k1 has w(c) <= trunc_eps; otherwise stage 2
+                           repeats with k = chi_max, reusing the first Omega
+                           columns (the paper's adaptive TEBD, Sec. IV and
+                           Alg. 2, with the exact Frobenius residual)          */
 } tebd_params;
 
 /* Fixed-capacity batch of MPS chains in Vidal form (Sec. II.A, Eq. defmps).

@@ -112,11 +112,14 @@ def safe_inverse(lam, floor):
 
 
 def bond_update(mps, b, gate, chi_max, eps, method="full", omega=None, q=2,
-                lambda_floor=1e-14):
+                lambda_floor=1e-14, p=10):
     """Apply the gate to bond b and truncate; updates mps in place.
 
     method "full": O-def (LAPACK SVD of the blocked Theta~).
     method "rrsvd": O-alg with the given Omega and q power iterations.
+    method "rrsvd_adaptive": two-stage adaptive rank; `omega` is then a
+    function l -> n x l test matrix, the first-stage rank follows the bond
+    dimension before the update (rrsvd.first_stage_rank).
     Returns a dict with chi', discarded weight w, status bits, and the
     singular values before renormalisation.
     """
@@ -128,6 +131,9 @@ def bond_update(mps, b, gate, chi_max, eps, method="full", omega=None, q=2,
         u, s, vh, chi, w, status = rr.truncate_full_svd(a, chi_max, eps)
     elif method == "rrsvd":
         u, s, vh, chi, w, status = rr.truncate_rrsvd(a, omega, q, chi_max, eps)
+    elif method == "rrsvd_adaptive":
+        k1 = rr.first_stage_rank(len(mps.lambdas[b]), chi_max)
+        u, s, vh, chi, w, status, stage = rr.truncate_rrsvd_adaptive(a, omega, q, chi_max, eps, k1, p)
     else:
         raise ValueError(method)
     norm = np.sqrt(np.sum(s ** 2))
@@ -177,16 +183,21 @@ class TEBD:
         n = self.mps.n_sites
         for b in range(parity, n - 1, 2):
             omega = None
+            chis = self.mps.chis()
+            dims = self.mps.dims
+            ncol = dims[b + 1] * chis[b + 2]
+            pid = self.chain * (n - 1) + b
             if self.method == "rrsvd":
-                chis = self.mps.chis()
-                dims = self.mps.dims
                 m = dims[b] * chis[b]
-                ncol = dims[b + 1] * chis[b + 2]
                 l = rr.sketch_width(self.chi_max, self.p, m, ncol)
-                omega = gaussian_omega(ncol, l, self.seed,
-                                       self.chain * (n - 1) + b, self.sweeps_done)
+                omega = gaussian_omega(ncol, l, self.seed, pid, self.sweeps_done)
+            elif self.method == "rrsvd_adaptive":
+                sweep_id = self.sweeps_done
+
+                def omega(l, ncol=ncol, pid=pid, sweep_id=sweep_id):
+                    return gaussian_omega(ncol, l, self.seed, pid, sweep_id)
             info = bond_update(self.mps, b, self.gate_fn(b, tau), self.chi_max, self.eps,
-                               self.method, omega, self.q, self.lambda_floor)
+                               self.method, omega, self.q, self.lambda_floor, self.p)
             info["bond"] = b
             info["sweep"] = self.sweeps_done
             self.log.append(info)

@@ -88,21 +88,41 @@ def sketch_width(k, p, m, n):
     return int(min(k + p, m, n))
 
 
+RANK_TOL = 1e-13
+
+
+def range_basis(y, tol=RANK_TOL):
+    """Orthonormal basis of the numerical range of Y (the QR steps of Alg. 1).
+
+    Householder QR with column pivoting (LAPACK geqp3), Y P = Q R with
+    |R_00| >= |R_11| >= ...; the basis keeps the r leading columns of Q with
+    |R_jj| > tol |R_00| (r >= 1).  For a well-conditioned Y this is span(Y);
+    for a numerically rank-deficient sketch it drops the directions that
+    carry no information about A.  The paper leaves the QR method open.
+    """
+    q, r, _ = scipy.linalg.qr(np.asarray(y, dtype=np.complex128), mode="economic", pivoting=True)
+    d = np.abs(np.diag(r))
+    if len(d) == 0:
+        return q
+    keep = max(1, int(np.sum(d > tol * d[0])))
+    return q[:, :keep]
+
+
 def rrsvd_range(a, omega, q):
     """Alg. 1 (randomized range finder with q power iterations).
 
     Y0 = A Omega, Y0 = Q0 R0; for j = 1..q: Yt_j = A^H Q_{j-1} = Qt_j Rt_j,
-    Y_j = A Qt_j = Q_j R_j.  Returns Q_q (m x l, orthonormal columns).
-    QR factorisations are Householder (LAPACK geqrf/ungqr via numpy).
+    Y_j = A Qt_j = Q_j R_j.  Returns Q_q (m x r, orthonormal columns, r <= l
+    the numerical rank kept by range_basis).
     """
     a = np.asarray(a, dtype=np.complex128)
     y = a @ omega
-    qmat, _ = np.linalg.qr(y)
+    qmat = range_basis(y)
     for _ in range(q):
         yt = a.conj().T @ qmat
-        qt, _ = np.linalg.qr(yt)
+        qt = range_basis(yt)
         y = a @ qt
-        qmat, _ = np.linalg.qr(y)
+        qmat = range_basis(y)
     return qmat
 
 
@@ -110,13 +130,54 @@ def rrsvd(a, omega, q):
     """Alg. 1 followed by steps i-iii of Sec. IV.
 
     i) B = Q^H A;  ii) B = Ut Sigma V^H (LAPACK gesvd);  iii) U = Q Ut.
-    Returns (U, s, Vh) with l = omega.shape[1] triplets.
+    Returns (U, s, Vh) with r <= l = omega.shape[1] triplets (r: the
+    numerical rank kept by the range finder).
     """
     a = np.asarray(a, dtype=np.complex128)
     qmat = rrsvd_range(a, omega, q)
     b = qmat.conj().T @ a
     ut, s, vh = lapack_svd(b)
     return qmat @ ut, s, vh
+
+
+def first_stage_rank(chi_mid, chi_max):
+    """Target rank of the first stage of the adaptive scheme.
+
+    The bond dimension before the update plus a margin of max(4, chi_mid/2)
+    (rounded up), capped by chi_max.
+    """
+    return int(min(chi_max, chi_mid + max(4, (chi_mid + 1) // 2)))
+
+
+def truncate_rrsvd_adaptive(a, omega_of, q, chi_max, eps, k1, p):
+    """Two-stage adaptive-rank RRSVD truncation (TEBD with a tolerance).
+
+    The paper grows the sketch until the range error meets the tolerance
+    (Sec. IV, Alg. 2) and notes that ||(I - QQ^H)A||_F is available exactly
+    from Q.  Here: stage 1 runs the RRSVD with l1 = min(k1 + p, m, n) and is
+    accepted when some c <= k1 has relative discarded weight w(c) <= eps
+    (w from the Frobenius identity, so the bound is exact for the factors
+    returned).  Otherwise stage 2 repeats with the fixed-rank width
+    l2 = min(chi_max + p, m, n).  omega_of(l) returns the n x l test matrix;
+    the first l1 columns of the stage-2 matrix are those of stage 1.
+    Returns (U, s, Vh, chi', w, status, stage) with stage = 1 or 2.
+    """
+    a = np.asarray(a, dtype=np.complex128)
+    m, n = a.shape
+    l1 = sketch_width(k1, p, m, n)
+    l2 = sketch_width(chi_max, p, m, n)
+    u, s, vh = rrsvd(a, omega_of(l1), q)
+    frob2 = float(np.vdot(a, a).real)
+    wts = frobenius_weights(s, frob2)
+    if l1 >= l2:
+        chi, w, status = truncation_rank(wts, chi_max, eps)
+        return u[:, :chi], s[:chi], vh[:chi, :], chi, w, status, 1
+    chi, w, status = truncation_rank(wts, min(k1, chi_max), eps)
+    if status == 0 and eps > 0.0:
+        return u[:, :chi], s[:chi], vh[:chi, :], chi, w, status, 1
+    u, s, vh = rrsvd(a, omega_of(l2), q)
+    chi, w, status = truncation_rank(frobenius_weights(s, frob2), chi_max, eps)
+    return u[:, :chi], s[:chi], vh[:chi, :], chi, w, status, 2
 
 
 def truncate_rrsvd(a, omega, q, chi_max, eps):

@@ -24,6 +24,7 @@ DEV_JACOBI_NOCONV = 4
 DEV_LAMBDA_FLOOR = 8
 DEV_CHI_BOUND = 16
 DEV_BAD_STATE = 32
+DEV_RANK_RETRY = 64
 
 EXPORTED = ("tebd_last_error", "tebd_version", "tebd_workspace_size", "rrsvd_truncate",
             "tebd_bond_update", "tebd_sweep", "tebd_profile_enable", "tebd_profile_read")
@@ -33,7 +34,7 @@ class TebdParams(ctypes.Structure):
     _fields_ = [("chi_max", ctypes.c_int32), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("trunc_eps", ctypes.c_double),
                 ("lambda_floor", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("stream_id", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("stream_id", ctypes.c_uint32), ("adaptive", ctypes.c_int32)]
 
 
 class TebdMps(ctypes.Structure):
@@ -96,9 +97,9 @@ def check(status):
 
 
 def params(chi_max, p=10, q=2, trunc_eps=1e-10, lambda_floor=1e-14, seed=1504, stream_id=0,
-           precision=0):
+           precision=0, adaptive=0):
     return TebdParams(int(chi_max), int(p), int(q), int(precision), float(trunc_eps),
-                      float(lambda_floor), int(seed), int(stream_id) & 0xFFFFFFFF, 0)
+                      float(lambda_floor), int(seed), int(stream_id) & 0xFFFFFFFF, int(adaptive))
 
 
 def _i64_array(values):

@@ -181,13 +181,13 @@ class TEBD:
     """
 
     def __init__(self, mps, bond_hams, dt, chi_max, p=10, q=2, trunc_eps=1e-10, seed=1504,
-                 lambda_floor=1e-14, precision=0):
+                 lambda_floor=1e-14, precision=0, adaptive=0):
         self.mps = mps
         self.dt = dt
         dev = mps.gamma.device
         self.g_half = torch.from_numpy(models.gate_stack(mps.dims, bond_hams, 0.5 * dt)).to(dev)
         self.g_full = torch.from_numpy(models.gate_stack(mps.dims, bond_hams, dt)).to(dev)
-        self.prm = _lib.params(chi_max, p, q, trunc_eps, lambda_floor, seed, 0, precision)
+        self.prm = _lib.params(chi_max, p, q, trunc_eps, lambda_floor, seed, 0, precision, adaptive)
         self.ws = BondWorkspace(mps, self.prm)
         self.sweeps_done = 0
         self.history = []

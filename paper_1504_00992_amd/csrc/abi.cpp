@@ -48,7 +48,10 @@ tebd_status check_params(const tebd_params* prm) {
     return fail(TEBD_ERR_ARG, "prm->trunc_eps must be finite");
   if (!(prm->lambda_floor >= 0.0) || !std::isfinite(prm->lambda_floor))
     return fail(TEBD_ERR_ARG, "prm->lambda_floor must be finite and >= 0");
-  if (prm->reserved != 0) return fail(TEBD_ERR_ARG, "prm->reserved must be 0");
+  if (prm->adaptive != 0 && prm->adaptive != 1)
+    return fail(TEBD_ERR_ARG, "prm->adaptive = %d must be 0 or 1", prm->adaptive);
+  if (prm->adaptive && !(prm->trunc_eps > 0.0))
+    return fail(TEBD_ERR_ARG, "prm->adaptive = 1 needs prm->trunc_eps > 0");
   return TEBD_OK;
 }
 
@@ -149,12 +152,12 @@ hipError_t upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
 // Optional per-kernel event timing (tebd_profile_enable / tebd_profile_read).
 enum ProfKind {
   PK_PLAN, PK_SCHEDULE, PK_THETA_GATE, PK_FROB, PK_OMEGA, PK_SKETCH_AOM, PK_SKETCH_AHQ,
-  PK_SKETCH_AQT, PK_QR, PK_QR_R, PK_SMALL_SVD, PK_TRUNCATE, PK_FORM_UV, PK_COUNT
+  PK_SKETCH_AQT, PK_QR, PK_QR_R, PK_SMALL_SVD, PK_TRUNCATE, PK_FORM_UV, PK_STAGE2, PK_COUNT
 };
 const char* const kProfNames[PK_COUNT] = {
     "plan_sweep", "schedule",  "theta_gate", "frobenius",  "omega",    "sketch_A_Omega",
     "sketch_AH_Q", "sketch_A_Qt", "qr",       "qr_with_r", "small_svd", "truncate",
-    "form_u_vh"};
+    "form_u_vh", "stage2_prep"};
 
 struct Profiler {
   std::mutex mu;
@@ -219,10 +222,11 @@ hipError_t run_pipeline(Prob* probs, const Common& c, hipStream_t s) {
   } while (0)
 #define TIMED(kind, call) TRY(timed(kind, s, [&]() { return (call); }))
   TIMED(PK_SCHEDULE, launch_schedule(probs, c, s));
-  if (c.tebd)
-    TIMED(PK_THETA_GATE, launch_theta_gate(probs, c, s));
-  else
+  if (c.tebd) {
+    if (!c.pass2) TIMED(PK_THETA_GATE, launch_theta_gate(probs, c, s));
+  } else {
     TIMED(PK_FROB, launch_frob(probs, c, s));
+  }
   TIMED(PK_OMEGA, launch_omega(probs, c, s));
   TIMED(PK_SKETCH_AOM, launch_sketch(probs, c, SK_Y_FROM_OMEGA, s));
   TIMED(PK_QR, launch_qr(probs, c, 0, 0, s));
@@ -265,6 +269,8 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   c.mmin = c.nmin = c.lmin = 1;  // bond dimensions are only known on the device
   c.kcap = prm->chi_max;
   c.tebd = 1;
+  c.adaptive = prm->adaptive;
+  c.pass2 = 0;
   c.dmax = mps->d_max;
   c.chimax = mps->chi_max;
   c.offs = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) +
@@ -282,9 +288,15 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   hipError_t e = timed(PK_PLAN, s, [&]() {
     return launch_plan_sweep(probs, c, *mps, reinterpret_cast<const zt*>(gates), gate_chain_stride,
                              parity, single_chain, single_bond, prm->p, slabs, pl.slab_sz, disc,
-                             status, prm->lambda_floor, prm->precision, s);
+                             status, prm->lambda_floor, prm->precision, prm->adaptive, s);
   });
   if (e == hipSuccess) e = run_pipeline(probs, c, s);
+  if (e == hipSuccess && c.adaptive) {
+    // second pass: only problems whose first stage was rejected do any work
+    e = timed(PK_STAGE2, s, [&]() { return launch_stage2(probs, c, s); });
+    c.pass2 = 1;
+    if (e == hipSuccess) e = run_pipeline(probs, c, s);
+  }
   if (e != hipSuccess) return fail(TEBD_ERR_DEVICE, "HIP error while enqueuing: %s", hipGetErrorString(e));
   return ok();
 }
@@ -371,6 +383,9 @@ tebd_status rrsvd_truncate(int64_t batch, const int64_t* m, const int64_t* n,
                            size_t ws_bytes, void* stream) {
   tebd_status st = check_params(prm);
   if (st != TEBD_OK) return st;
+  if (prm->adaptive)
+    return fail(TEBD_ERR_ARG, "prm->adaptive: the two-stage rank needs a bond dimension and is "
+                              "available in the TEBD entry points only");
   if (batch < 1) return fail(TEBD_ERR_ARG, "argument 1 (batch) = %lld must be >= 1", (long long)batch);
   if (!m) return fail(TEBD_ERR_ARG, "argument 2 (m) is NULL");
   if (!n) return fail(TEBD_ERR_ARG, "argument 3 (n) is NULL");
@@ -422,6 +437,8 @@ tebd_status rrsvd_truncate(int64_t batch, const int64_t* m, const int64_t* n,
   c.mmin = c.nmin = c.lmin = 1 << 30;
   c.kcap = prm->chi_max;
   c.tebd = 0;
+  c.adaptive = 0;
+  c.pass2 = 0;
   c.dmax = 0;
   c.chimax = 0;
   for (int64_t b = 0; b < batch; ++b) {
@@ -431,6 +448,8 @@ tebd_status rrsvd_truncate(int64_t batch, const int64_t* m, const int64_t* n,
     P.n = int32_t(n[b]);
     P.l = sketch_l(prm->chi_max, prm->p, m[b], n[b]);
     P.kcap = prm->chi_max;
+    P.k1 = prm->chi_max;
+    P.l1 = P.l2 = P.l;
     P.pid = int32_t(b);
     P.mixed = prm->precision;
     carve_slab(P, slab, m[b], n[b], P.l, 0, prm->precision, 0);

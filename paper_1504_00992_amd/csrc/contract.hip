@@ -148,8 +148,12 @@ __device__ __forceinline__ void for_each_tile(Prob* probs, const int32_t* offs, 
     int M, N;
     kind_shape<KIND>(P, tebd, M, N);
     const int local = t - off[p];
+    // the range finder may have shrunk l since the queue was built: tiles of
+    // the old shape that now lie outside the output are skipped
     const int tiles_n = (N + 63) / 64;
+    if (tiles_n == 0) continue;
     const int tm = local / tiles_n, tn = local - tm * tiles_n;
+    if (tm * 64 >= M) continue;
     body(P, M, N, tm * 64, tn * 64, local);
   }
 }
@@ -441,6 +445,7 @@ template <int TEBD_>
 __global__ __launch_bounds__(256) void k_form_u(Prob* probs, const int32_t* offs, int nprob) {
   __shared__ zt smem[Cfg64::lds_elems];
   for_each_tile<TK_FORMU>(probs, offs, nprob, TEBD_, [&](Prob& P, int M, int N, int m0, int n0, int) {
+    if (P.retry) return;  // adaptive rank: stage 2 will write this problem
     const int chi = P.chi_new;
     const int Keff = (n0 >= chi) ? 0 : P.l;
     LdQ la{P.Y, P.m};
@@ -459,6 +464,7 @@ template <int TEBD_>
 __global__ __launch_bounds__(256) void k_form_vh(Prob* probs, const int32_t* offs, int nprob) {
   __shared__ zt smem[Cfg64::lds_elems];
   for_each_tile<TK_FORMV>(probs, offs, nprob, TEBD_, [&](Prob& P, int M, int N, int m0, int n0, int) {
+    if (P.retry) return;  // adaptive rank: stage 2 will write this problem
     const int chi = P.chi_new;
     const int Keff = (m0 >= chi) ? 0 : P.l;
     LdSmallAdjA la{P.W, P.l};

@@ -22,7 +22,7 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
                              int single_bond, int kcap, int p_over, char* slab_base,
                              size_t slab_sz, int64_t mcap, int64_t ncap, int64_t lcap,
                              int64_t npart_cap, double* disc, int32_t* status,
-                             double lambda_floor, int mixed) {
+                             double lambda_floor, int mixed, int adaptive) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nprob) return;
   const int N = mps.n_sites, cap = mps.chi_max, dmax = mps.d_max;
@@ -48,10 +48,22 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
   P.dr = dr;
   P.m = dl * cl;
   P.n = dr * cr;
-  int l = kcap + p_over;
-  if (l > P.m) l = P.m;
-  if (l > P.n) l = P.n;
+  int l2 = kcap + p_over;
+  if (l2 > P.m) l2 = P.m;
+  if (l2 > P.n) l2 = P.n;
+  int k1 = kcap, l = l2;
+  if (adaptive) {  // first stage: the current bond dimension plus a margin
+    const int margin = (cm + 1) / 2 > 4 ? (cm + 1) / 2 : 4;
+    k1 = cm + margin < kcap ? cm + margin : kcap;
+    l = k1 + p_over;
+    if (l > P.m) l = P.m;
+    if (l > P.n) l = P.n;
+  }
   P.l = bad ? 0 : l;
+  P.k1 = k1;
+  P.l1 = l;
+  P.l2 = l2;
+  P.retry = 0;
   P.kcap = kcap;
   P.pid = chain * (N - 1) + bond;
   P.chi_new = 0;
@@ -104,14 +116,14 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
                              int64_t gate_chain_stride, int32_t parity, int32_t single_chain,
                              int32_t single_bond, int32_t p_over, char* slab_base,
                              size_t slab_sz, double* disc, int32_t* status, double lambda_floor,
-                             int32_t mixed, hipStream_t s) {
+                             int32_t mixed, int32_t adaptive, hipStream_t s) {
   const int64_t mcap = int64_t(c.dmax) * c.chimax;
   const int64_t lcap = c.lmax;
   const int64_t npart_cap = int64_t((c.dmax * c.dmax + 63) / 64) * ((c.chimax * c.chimax + 63) / 64);
   hipLaunchKernelGGL(k_plan_sweep, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob, mps,
                      gates, gate_chain_stride, parity, single_chain, single_bond, c.kcap, p_over,
                      slab_base, slab_sz, mcap, mcap, lcap, npart_cap, disc, status, lambda_floor,
-                     mixed);
+                     mixed, adaptive);
   return hipGetLastError();
 }
 
@@ -159,7 +171,8 @@ __device__ __forceinline__ bool qr_in_lds(int rows, int l) {
 // below `skip` are treated as zero on input (they held R entries).
 template <int REG>
 __device__ __forceinline__ void reflect_column(const zt* __restrict__ u, zt* yc, int j0, int skip,
-                                               int rows, int lane) {
+                                               int rows, int lane, double* nrm_out = nullptr) {
+  double nn = 0.0;  // sum |y_c[r]|^2 over r > j0 after the update
   const int nr = rows - j0;
   double dr = 0.0, di = 0.0;
   if (REG > 0 && nr <= 64 * REG) {
@@ -180,7 +193,11 @@ __device__ __forceinline__ void reflect_column(const zt* __restrict__ u, zt* yc,
 #pragma unroll
     for (int i = 0; i < REG; ++i) {
       const int r = j0 + lane + 64 * i;
-      if (r < rows) yc[r] = zsub(cache[i], zmul(u[r], d2));
+      if (r < rows) {
+        const zt v = zsub(cache[i], zmul(u[r], d2));
+        yc[r] = v;
+        if (r > j0) nn += zabs2(v);
+      }
     }
   } else {
     for (int r = j0 + lane; r < rows; r += 64) {
@@ -194,17 +211,91 @@ __device__ __forceinline__ void reflect_column(const zt* __restrict__ u, zt* yc,
     const zt d2 = make_double2(2.0 * dr, 2.0 * di);
     for (int r = j0 + lane; r < rows; r += 64) {
       const zt old = r < skip ? make_double2(0.0, 0.0) : yc[r];
-      yc[r] = zsub(old, zmul(u[r], d2));
+      const zt v = zsub(old, zmul(u[r], d2));
+      yc[r] = v;
+      if (r > j0) nn += zabs2(v);
     }
+  }
+  if (nrm_out) {
+    nn = wave_sum(nn);
+    if (lane == 0) *nrm_out = nn;
   }
 }
 
+// Column pivoting for the range-finder QRs of Alg. 1: before step j the
+// remaining column with the largest trailing norm is swapped into place
+// (ties: lowest index), and the factorisation stops at the first j >= 1 whose
+// pivot norm |R_jj| is <= kRankTol |R_00|.  The kept rank r replaces the
+// sketch width l of the problem, so later products and the small SVD work on
+// the numerical range only.  Returns r (= l without pivoting).
+constexpr double kRankTol = 1e-13;
+
 template <int NT, int REG>
-__device__ __forceinline__ void qr_core(zt* Y, int rows, int l, zt* u_s, zt* rdiag, double* red,
-                                        zt* Rb) {
+__device__ __forceinline__ int qr_core(zt* Y, int rows, int l, zt* u_s, zt* rdiag, double* red,
+                                       zt* Rb, bool piv, double* nrm, int* sh_i, double* sh_d) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = NT / 64;
+  int rank = l;
+  double r00 = 0.0;
+  if (piv) {
+    for (int c = wave; c < l; c += NW) {
+      double s = 0.0;
+      for (int r = lane; r < rows; r += 64) s += zabs2(Y[size_t(c) * rows + r]);
+      s = wave_sum(s);
+      if (lane == 0) nrm[c] = s;
+    }
+    __syncthreads();
+  }
   for (int j = 0; j < l; ++j) {
+    if (piv) {
+      if (wave == 0) {
+        double best = -1.0;
+        int bi = j;
+        for (int c = j + lane; c < l; c += 64) {
+          const double v = nrm[c];
+          if (v > best) {
+            best = v;
+            bi = c;
+          }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off, 64);
+          const int oi = __shfl_xor(bi, off, 64);
+          if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+          }
+        }
+        if (lane == 0) {
+          sh_i[0] = bi;
+          sh_d[0] = best;
+        }
+      }
+      __syncthreads();
+      const int pc = sh_i[0];
+      const double pn = sqrt(fmax(sh_d[0], 0.0));
+      if (j == 0) r00 = pn;
+      if (j > 0 && !(pn > kRankTol * r00)) {
+        rank = j;
+        break;
+      }
+      if (pc != j) {
+        zt* a = Y + size_t(j) * rows;
+        zt* b = Y + size_t(pc) * rows;
+        for (int r = tid; r < rows; r += NT) {
+          const zt t = a[r];
+          a[r] = b[r];
+          b[r] = t;
+        }
+        if (tid == 0) {
+          const double t = nrm[j];
+          nrm[j] = nrm[pc];
+          nrm[pc] = t;
+        }
+      }
+      __syncthreads();
+    }
     zt* yj = Y + size_t(j) * rows;
     double s = 0.0;
     for (int r = j + 1 + tid; r < rows; r += NT) s += zabs2(yj[r]);
@@ -228,13 +319,23 @@ __device__ __forceinline__ void qr_core(zt* Y, int rows, int l, zt* u_s, zt* rdi
     }
     if (tid == 0) rdiag[j] = beta;
     __syncthreads();
-    if (vinv != 0.0)
-      for (int c = j + 1 + wave; c < l; c += NW) reflect_column<REG>(u_s, Y + size_t(c) * rows, j, j, rows, lane);
+    if (vinv != 0.0) {
+      for (int c = j + 1 + wave; c < l; c += NW)
+        reflect_column<REG>(u_s, Y + size_t(c) * rows, j, j, rows, lane, piv ? nrm + c : nullptr);
+    } else if (piv) {
+      // H_j = I: trailing norms lose row j only
+      for (int c = j + 1 + wave; c < l; c += NW) {
+        double nn = 0.0;
+        for (int r = j + 1 + lane; r < rows; r += 64) nn += zabs2(Y[size_t(c) * rows + r]);
+        nn = wave_sum(nn);
+        if (lane == 0) nrm[c] = nn;
+      }
+    }
     __syncthreads();
   }
   if (Rb) {
-    for (int e = tid; e < l * l; e += NT) {
-      const int c = e / l, i = e - c * l;
+    for (int e = tid; e < rank * rank; e += NT) {
+      const int c = e / rank, i = e - c * rank;
       zt v;
       if (i < c)
         v = Y[size_t(c) * rows + i];
@@ -246,13 +347,13 @@ __device__ __forceinline__ void qr_core(zt* Y, int rows, int l, zt* u_s, zt* rdi
     }
     __syncthreads();
   }
-  // Q = H_0 H_1 ... H_{l-1} [I; 0], accumulated from the last reflector.
-  for (int j = l - 1; j >= 0; --j) {
+  // Q = H_0 H_1 ... H_{r-1} [I; 0], accumulated from the last reflector.
+  for (int j = rank - 1; j >= 0; --j) {
     zt* yj = Y + size_t(j) * rows;
     for (int r = j + tid; r < rows; r += NT) u_s[r] = yj[r];
     __syncthreads();
     // trailing columns: row j held an R entry and is treated as zero
-    for (int c = j + 1 + wave; c < l; c += NW)
+    for (int c = j + 1 + wave; c < rank; c += NW)
       reflect_column<REG>(u_s, Y + size_t(c) * rows, j, j + 1, rows, lane);
     // column j = H_j e_j
     const zt uj = u_s[j];
@@ -266,6 +367,7 @@ __device__ __forceinline__ void qr_core(zt* Y, int rows, int l, zt* u_s, zt* rdi
     }
     __syncthreads();
   }
+  return rank;
 }
 
 // Size classes: a problem of measure (l + 1) * rows in (LO, HI] runs in the
@@ -283,12 +385,18 @@ __global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_
   const int rows = which ? P.n : P.m;
   const int64_t meas = int64_t(l + 1) * rows;
   if (l == 0 || meas <= LO || meas > HI) return;
+  __shared__ double nrm[kMaxL];
+  __shared__ int sh_i[1];
+  __shared__ double sh_d[1];
   zt* Yg = which ? P.Yt : P.Y;
   const int tot = rows * l;
   for (int e = threadIdx.x; e < tot; e += NT) lds[e] = Yg[e];
   __syncthreads();
-  qr_core<NT, 0>(lds, rows, l, lds + tot, rdiag, red, want_r ? P.Rb : nullptr);
-  for (int e = threadIdx.x; e < tot; e += NT) Yg[e] = lds[e];
+  const int rank = qr_core<NT, 0>(lds, rows, l, lds + tot, rdiag, red, want_r ? P.Rb : nullptr,
+                                  !want_r, nrm, sh_i, sh_d);
+  const int keep = rows * rank;
+  for (int e = threadIdx.x; e < keep; e += NT) Yg[e] = lds[e];
+  if (threadIdx.x == 0) P.l = rank;
 }
 
 template <int NT>
@@ -300,7 +408,12 @@ __global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_
   const int l = P.l;
   const int rows = which ? P.n : P.m;
   if (l == 0 || qr_in_lds(rows, l)) return;
-  qr_core<NT, kRegRows>(which ? P.Yt : P.Y, rows, l, u_s, rdiag, red, want_r ? P.Rb : nullptr);
+  __shared__ double nrm[kMaxL];
+  __shared__ int sh_i[1];
+  __shared__ double sh_d[1];
+  const int rank = qr_core<NT, kRegRows>(which ? P.Yt : P.Y, rows, l, u_s, rdiag, red,
+                                         want_r ? P.Rb : nullptr, !want_r, nrm, sh_i, sh_d);
+  if (threadIdx.x == 0) P.l = rank;
 }
 
 // Whether any problem with measure in [mlo, mhi] can fall in (lo, hi].
@@ -532,7 +645,10 @@ __global__ __launch_bounds__(64) void k_truncate(Prob* probs, double eps, int te
       for (int i = 0; i < npart; ++i) frob2 += P.part[i];
       P.frob2 = frob2;
     }
-    const int cap = P.kcap < l ? P.kcap : l;
+    // A first stage that may still be retried only accepts a rank <= k1.
+    const bool can_retry = P.l2 > P.l1;
+    int cap = P.kcap < l ? P.kcap : l;
+    if (can_retry && P.k1 < cap) cap = P.k1;
     double kept = 0.0;
     int chi = cap;
     double w = 0.0;
@@ -550,6 +666,11 @@ __global__ __launch_bounds__(64) void k_truncate(Prob* probs, double eps, int te
       }
       if (c == cap && !found) w = wc;
     }
+    if (can_retry && !(eps > 0.0 && found)) {
+      // stage 1 rejected: leave every output untouched, run stage 2
+      P.retry = 1;
+      chi_s = -1;
+    }
     if (eps > 0.0 && !found) flags |= TEBD_DEV_CHI_BOUND;
     if (!finite) flags |= TEBD_DEV_NONFINITE;
     if (w < 0.0) w = 0.0;
@@ -563,17 +684,20 @@ __global__ __launch_bounds__(64) void k_truncate(Prob* probs, double eps, int te
         for (int b = 0; b < P.chi_r; ++b) floor_hit |= !(P.lam_r[b] > P.lambda_floor);
       if (floor_hit) flags |= TEBD_DEV_LAMBDA_FLOOR;
     }
-    P.chi_new = chi;
-    P.flags = flags;
-    *P.disc = w;
-    *P.status = flags;
-    if (P.chi_out) *P.chi_out = chi;
-    chi_s = chi;
+    if (!P.retry) {
+      P.chi_new = chi;
+      P.flags = flags;
+      *P.disc = w;
+      *P.status = flags;
+      if (P.chi_out) *P.chi_out = chi;
+      chi_s = chi;
+    }
     norm_s = sqrt(nk);
     flags_s = flags;
   }
   __syncthreads();
   const int chi = chi_s;
+  if (chi < 0) return;
   if (tebd) {
     const double inv = norm_s > 0.0 ? 1.0 / norm_s : 0.0;
     for (int j = lane; j < P.chi_cap; j += 64) P.lam_mid[j] = j < chi ? P.sig[j] * inv : 0.0;
@@ -586,6 +710,30 @@ __global__ __launch_bounds__(64) void k_truncate(Prob* probs, double eps, int te
 
 hipError_t launch_truncate(Prob* probs, const Common& c, hipStream_t s) {
   hipLaunchKernelGGL(k_truncate, dim3(c.nprob), dim3(64), 0, s, probs, c.eps, c.tebd);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Adaptive rank, between the passes: problems whose first stage was rejected
+// get the fixed-rank width (and are marked), every other problem is skipped.
+__global__ void k_stage2(Prob* probs, int nprob) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  Prob& P = probs[p];
+  if (P.retry) {
+    P.l = P.l2;
+    P.l1 = P.l2;
+    P.k1 = P.kcap;
+    P.ldom = P.l2;
+    P.retry = 0;
+    P.flags |= TEBD_DEV_RANK_RETRY;
+  } else {
+    P.l = 0;
+  }
+}
+
+hipError_t launch_stage2(Prob* probs, const Common& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_stage2, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob);
   return hipGetLastError();
 }
 

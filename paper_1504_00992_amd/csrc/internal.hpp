@@ -32,6 +32,10 @@ struct Prob {
   int32_t npart;                     // number of Frobenius partial sums
   int32_t mixed;                     // 1: sketch / power products in complex FP32
   int32_t om_ext;                    // 1: Omega supplied by the caller
+  int32_t k1;                        // kept-rank cap of the current stage
+  int32_t l1;                        // sketch width this stage started with
+  int32_t l2;                        // sketch width of the fixed-rank stage
+  int32_t retry;                     // 1: stage 1 rejected, stage 2 pending
   int32_t pad0;
   double frob2;                      // ||A||_F^2, written on the device
   // input matrix (row-major, leading dim lda) and test matrix (row-major n x l)
@@ -87,6 +91,8 @@ struct Common {
   int32_t tebd;      // 1: TEBD problems (Theta/gate/reabsorb kernels run)
   int32_t dmax;      // TEBD: max local dim
   int32_t chimax;    // TEBD: chi capacity
+  int32_t adaptive;  // two-stage adaptive rank (TEBD only)
+  int32_t pass2;     // 1: second (fixed-rank) pass of the adaptive scheme
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
 };
@@ -112,7 +118,8 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
                              int64_t gate_chain_stride, int32_t parity, int32_t single_chain,
                              int32_t single_bond, int32_t p_over, char* slab_base,
                              size_t slab_bytes, double* disc, int32_t* status, double lambda_floor,
-                             int32_t mixed, hipStream_t s);
+                             int32_t mixed, int32_t adaptive, hipStream_t s);
+hipError_t launch_stage2(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_schedule(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_frob(Prob* probs, const Common& c, hipStream_t s);

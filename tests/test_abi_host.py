@@ -35,6 +35,7 @@ def test_struct_layouts_match_header():
     # tebd_params: 4 x int32, 2 x double, uint64, 2 x uint32 = 48 bytes
     assert ctypes.sizeof(_lib.TebdParams) == 48
     assert _lib.TebdParams.trunc_eps.offset == 16 and _lib.TebdParams.seed.offset == 32
+    assert _lib.TebdParams.adaptive.offset == 44
     # tebd_mps: 4 x int32 then 4 pointers
     assert ctypes.sizeof(_lib.TebdMps) == 48 and _lib.TebdMps.d.offset == 16
 
@@ -57,9 +58,12 @@ def test_workspace_size_and_validation():
         _ws(prm, [0], [8])
     assert e.value.status == _lib.TEBD_ERR_SHAPE
     bad = _lib.params(8, 10, 2)
-    bad.reserved = 1
+    bad.adaptive = 2
     with pytest.raises(_lib.TebdError):
         _ws(bad, [8], [8])
+    with pytest.raises(_lib.TebdError) as e:
+        _ws(_lib.params(8, trunc_eps=0.0, adaptive=1), [8], [8])
+    assert "trunc_eps" in str(e.value)
     with pytest.raises(_lib.TebdError) as e:
         _ws(_lib.params(8, q=-1), [8], [8])
     assert "q" in str(e.value)
@@ -140,6 +144,8 @@ def test_rrsvd_rejects_bad_arguments_before_enqueue():
     assert call(ws_ptr=f + 8) == _lib.TEBD_ERR_WORKSPACE
     assert call(m=[0]) == _lib.TEBD_ERR_SHAPE
     assert call(omega_ptrs=[None]) == _lib.TEBD_ERR_ARG
+    assert call(prm=_lib.params(4, adaptive=1)) == _lib.TEBD_ERR_ARG
+    assert "TEBD entry points" in _lib.tebd_last_error()
 
 
 def test_product_gates_match_oracle_gates():

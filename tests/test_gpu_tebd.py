@@ -84,7 +84,7 @@ def test_bond_update_matches_oracle(dims, chis, bond, chi_max, p):
     assert np.all(cap_g[:, :, info["chi"]:] == 0)
 
 
-def _oracle_tebd(dims, hb, levels, dt, steps, chi_max, p, eps, chain=0):
+def _oracle_tebd(dims, hb, levels, dt, steps, chi_max, p, eps, chain=0, method="rrsvd"):
     gates = {}
 
     def gfn(b, tau):
@@ -93,27 +93,29 @@ def _oracle_tebd(dims, hb, levels, dt, steps, chi_max, p, eps, chain=0):
             gates[key] = om.gate(hb[b], tau)
         return gates[key]
     m = omps.basis_product_state(dims, levels)
-    drv = omps.TEBD(m, gfn, dt, chi_max, eps, method="rrsvd", p=p, q=2, seed=SEED, chain=chain)
+    drv = omps.TEBD(m, gfn, dt, chi_max, eps, method=method, p=p, q=2, seed=SEED, chain=chain)
     for _ in range(steps):
         drv.step()
     return drv
 
 
-def _gpu_tebd(n_chains, dims, hb, levels, dt, steps, chi_max, p, eps):
+def _gpu_tebd(n_chains, dims, hb, levels, dt, steps, chi_max, p, eps, adaptive=0):
     from paper_1504_00992_amd import api
     dev = api.DeviceMPS.product_state(n_chains, dims, levels, chi_max)
-    drv = api.TEBD(dev, hb, dt, chi_max, p=p, q=2, trunc_eps=eps, seed=SEED)
+    drv = api.TEBD(dev, hb, dt, chi_max, p=p, q=2, trunc_eps=eps, seed=SEED, adaptive=adaptive)
     for _ in range(steps):
         drv.step()
     torch.cuda.synchronize()
     return drv
 
 
-def test_tfim_sweeps_match_oracle_and_state_vector():
+@pytest.mark.parametrize("adaptive", [0, 1])
+def test_tfim_sweeps_match_oracle_and_state_vector(adaptive):
     n, dt, steps, chi_max = 12, 0.05, 10, 16
     dims, hb = om.tfim(n, 1.0, 1.0)
-    g = _gpu_tebd(1, dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10)
-    o = _oracle_tebd(dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10)
+    method = "rrsvd_adaptive" if adaptive else "rrsvd"
+    g = _gpu_tebd(1, dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10, adaptive)
+    o = _oracle_tebd(dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10, method=method)
     gam, lam = g.mps.to_host(0)
     gm = omps.MPS(gam, lam)
     assert gm.chis() == o.mps.chis()
@@ -131,12 +133,14 @@ def test_tfim_sweeps_match_oracle_and_state_vector():
     assert abs(omps.norm2(gm) - 1.0) < 1e-10
 
 
-def test_spin_boson_two_chains_match_oracle():
+@pytest.mark.parametrize("adaptive", [0, 1])
+def test_spin_boson_two_chains_match_oracle(adaptive):
     n, d, dt, steps, chi_max = 8, 4, 0.05, 6, 20
     dims, hb = om.spin_boson_chain(n, d, 1.0, 0.5, 1.0, 0.5)
-    g = _gpu_tebd(2, dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10)
+    method = "rrsvd_adaptive" if adaptive else "rrsvd"
+    g = _gpu_tebd(2, dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10, adaptive)
     for c in range(2):
-        o = _oracle_tebd(dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10, chain=c)
+        o = _oracle_tebd(dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10, chain=c, method=method)
         gam, lam = g.mps.to_host(c)
         gm = omps.MPS(gam, lam)
         assert gm.chis() == o.mps.chis()
@@ -159,3 +163,40 @@ def test_bad_device_state_is_skipped_and_flagged():
     st = drv.ws.status[0].cpu().numpy()
     assert st[2] & 32 and st[1] & 32
     assert torch.equal(dev.gamma[0, 2:4], before[0, 2:4])
+
+
+@pytest.mark.parametrize("chis,decay,expect_stage", [
+    ([1, 4, 3, 16, 1], 3.0, 1),     # fast-decaying spectrum: stage 1 (k1 = 7) suffices
+    ([1, 4, 2, 16, 1], 0.02, 2),    # nearly flat: stage 2 with k = chi_max
+])
+def test_adaptive_bond_update_matches_oracle(chis, decay, expect_stage):
+    from paper_1504_00992_amd import api
+    dims = [4, 4, 4, 4]
+    bond, chi_max, p = 1, 12, 5
+    gen = wl.rng(77)
+    gam = [wl.ginibre(d * chis[k], chis[k + 1], gen).reshape(d, chis[k], chis[k + 1])
+           for k, d in enumerate(dims)]
+    lam = []
+    for b in range(3):
+        v = np.exp(-decay * np.arange(chis[b + 1]))
+        lam.append(v / np.linalg.norm(v))
+    gate = wl.random_unitary(16, wl.rng(4)) if expect_stage == 2 else np.eye(16, dtype=np.complex128)
+    dev = api.DeviceMPS.from_host([(gam, lam)], dims, 16)
+    prm = api._lib.params(chi_max, p, 2, 1e-10, 1e-14, SEED, 9, adaptive=1)
+    ws = api.BondWorkspace(dev, prm)
+    api.tebd_bond_update(dev, 0, bond, torch.from_numpy(gate).cuda(), prm, ws)
+    torch.cuda.synchronize()
+    ref = omps.MPS(gam, lam)
+    n_cols = dims[bond + 1] * chis[bond + 2]
+    omega_of = lambda l: philox.gaussian_omega(n_cols, l, SEED, bond, 9)
+    info = omps.bond_update(ref, bond, gate, chi_max, 1e-10, "rrsvd_adaptive", omega_of, 2, p=p)
+    g_gam, g_lam = dev.to_host(0)
+    st = ws.status[0, bond].item()
+    assert bool(st & 64) == (expect_stage == 2)
+    assert (st & ~64) == info["status"]
+    assert len(g_lam[bond]) == info["chi"]
+    assert np.max(np.abs(g_lam[bond] - ref.lambdas[bond])) < 1e-10
+    assert abs(ws.disc[0, bond].item() - info["w"]) < 1e-12
+    blk_g = _two_site_block(g_gam, g_lam, bond)
+    blk_o = _two_site_block(ref.gammas, ref.lambdas, bond)
+    assert np.max(np.abs(blk_g - blk_o)) < 1e-10

@@ -38,16 +38,17 @@ def test_rrsvd_exact_when_sketch_spans_range():
 
 
 def test_rrsvd_rank_deficient_input():
-    # Rank 5 < l: Y is exactly rank deficient; Householder QR still yields an
-    # orthonormal basis and the 5 nonzero singular values are exact.
+    # Rank 5 < l: Y is exactly rank deficient; the range finder keeps the 5
+    # informative directions and the 5 nonzero singular values are exact.
     s = np.array([1.0, 0.7, 0.3, 0.1, 0.01])
     a = _known(40, 40, s, 3)
     om = philox.gaussian_omega(40, 15, 9, 1, 0)
     q = rrsvd.rrsvd_range(a, om, 2)
-    assert np.allclose(q.conj().T @ q, np.eye(15), atol=1e-13)
+    assert q.shape == (40, 5)
+    assert np.allclose(q.conj().T @ q, np.eye(5), atol=1e-13)
     u, sv, vh = rrsvd.rrsvd(a, om, 2)
-    assert np.allclose(sv[:5], s, atol=1e-14)
-    assert np.all(sv[5:] < 1e-14)
+    assert len(sv) == 5 and np.allclose(sv, s, atol=1e-14)
+    assert np.allclose((u * sv[None, :]) @ vh, a, atol=1e-13)
 
 
 def test_power_iteration_subspace_matches_unorthogonalised_product():
@@ -109,3 +110,47 @@ def test_truncate_rrsvd_weight_uses_frobenius_identity():
     assert w * np.sum(s ** 2) == pytest.approx(np.linalg.norm(resid) ** 2, rel=1e-6, abs=1e-24)
     chi_def = rrsvd.truncate_full_svd(a, 30, 1e-10)[3]
     assert chi == chi_def
+
+
+def test_range_basis_keeps_the_numerical_rank():
+    gen = wl.rng(12)
+    # exact rank 7 sketch of 40 columns: 7 directions kept, and they span Y
+    y = wl.ginibre(60, 7, gen) @ wl.ginibre(7, 40, gen)
+    q = rrsvd.range_basis(y)
+    assert q.shape == (60, 7)
+    assert np.allclose(q.conj().T @ q, np.eye(7), atol=1e-13)
+    assert np.allclose(q @ (q.conj().T @ y), y, atol=1e-12 * np.linalg.norm(y))
+    # full-rank, well-conditioned: same subspace as the unpivoted QR
+    y = wl.ginibre(50, 12, gen)
+    q = rrsvd.range_basis(y)
+    q0, _ = np.linalg.qr(y)
+    assert q.shape == (50, 12) and np.allclose(q @ q.conj().T, q0 @ q0.conj().T, atol=1e-12)
+    # graded columns below the tolerance are dropped, above it kept
+    u = haar = wl.haar_isometry(30, 6, gen)
+    sv = np.array([1.0, 1e-3, 1e-8, 1e-12, 1e-15, 1e-17])
+    y = (u * sv[None, :]) @ wl.haar_isometry(6, 6, gen).conj().T
+    assert rrsvd.range_basis(y).shape[1] == 4
+    # the zero matrix keeps one (arbitrary) direction
+    assert rrsvd.range_basis(np.zeros((5, 3), dtype=np.complex128)).shape[1] == 1
+
+
+def test_adaptive_two_stage_rule():
+    # A spectrum whose tolerance is met at rank 9: a first stage with k1 = 12
+    # suffices; with k1 = 6 the rule must fall back to the fixed-rank width and
+    # reproduce the fixed-rank result exactly (same test-matrix columns).
+    s = np.exp(-np.arange(80) / 0.8)
+    a = _known(90, 80, s, 13)
+    omega_of = lambda l: philox.gaussian_omega(80, l, 5, 1, 2)
+    eps = 1e-10
+    chi_def = rrsvd.truncate_full_svd(a, 40, eps)[3]
+    u, sv, vh, chi, w, st, stage = rrsvd.truncate_rrsvd_adaptive(a, omega_of, 2, 40, eps, 12, 10)
+    assert stage == 1 and chi == chi_def <= 12 and w <= eps
+    # the Frobenius identity carries an absolute rounding error of ~1e-14
+    assert np.linalg.norm(a - (u * sv[None, :]) @ vh) ** 2 / np.sum(s ** 2) == pytest.approx(w, abs=1e-13)
+    u2, sv2, vh2, chi2, w2, st2, stage2 = rrsvd.truncate_rrsvd_adaptive(a, omega_of, 2, 40, eps, 6, 10)
+    assert stage2 == 2
+    fixed = rrsvd.truncate_rrsvd(a, omega_of(50), 2, 40, eps)
+    assert chi2 == fixed[3] and np.array_equal(sv2, fixed[1]) and w2 == fixed[4]
+    # first-stage rank: chi + max(4, ceil(chi/2)), capped
+    assert rrsvd.first_stage_rank(1, 100) == 5 and rrsvd.first_stage_rank(19, 100) == 29
+    assert rrsvd.first_stage_rank(90, 100) == 100
