@@ -471,9 +471,12 @@ __device__ __forceinline__ int circle_player(int pos, int round, int lp) {
 }
 
 
+// Column norms are recomputed exactly at the start of every sweep and then
+// carried through the rotations analytically (a' = a - t|g|, b' = b + t|g|),
+// so each pair needs a single complex reduction, g = c_p^H c_q.
 template <int NT, int REGS>
 __device__ __forceinline__ void jacobi_core(zt* C, zt* J, int l, int& converged_out,
-                                            int* rotated) {
+                                            int* rotated, double* nrm) {
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lp = l + (l & 1);
@@ -481,6 +484,16 @@ __device__ __forceinline__ void jacobi_core(zt* C, zt* J, int l, int& converged_
   constexpr int kMaxSweeps = 40;
   bool converged = (l == 1);
   for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
+    for (int c = wave; c < l; c += NW) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < REGS; ++i) {
+        const int r = lane + 64 * i;
+        if (r < l) s += zabs2(C[size_t(c) * l + r]);
+      }
+      s = wave_sum(s);
+      if (lane == 0) nrm[c] = s;
+    }
     if (tid == 0) *rotated = 0;
     __syncthreads();
     for (int round = 0; round < lp - 1; ++round) {
@@ -491,22 +504,19 @@ __device__ __forceinline__ void jacobi_core(zt* C, zt* J, int l, int& converged_
         zt* cp = C + size_t(p) * l;
         zt* cq = C + size_t(q) * l;
         zt xp[REGS], xq[REGS];
-        double app = 0.0, aqq = 0.0, gr = 0.0, gi = 0.0;
+        double gr = 0.0, gi = 0.0;
 #pragma unroll
         for (int i = 0; i < REGS; ++i) {
           const int r = lane + 64 * i;
           xp[i] = r < l ? cp[r] : make_double2(0.0, 0.0);
           xq[i] = r < l ? cq[r] : make_double2(0.0, 0.0);
-          app += zabs2(xp[i]);
-          aqq += zabs2(xq[i]);
           const zt t = zcmul(xp[i], xq[i]);
           gr += t.x;
           gi += t.y;
         }
-        app = wave_sum(app);
-        aqq = wave_sum(aqq);
         gr = wave_sum(gr);
         gi = wave_sum(gi);
+        const double app = nrm[p], aqq = nrm[q];
         const double ag = sqrt(gr * gr + gi * gi);
         if (!(ag > tol * sqrt(app * aqq)) || ag == 0.0) continue;
         const double zeta = (aqq - app) / (2.0 * ag);
@@ -533,7 +543,11 @@ __device__ __forceinline__ void jacobi_core(zt* C, zt* J, int l, int& converged_
             jq[r] = zadd(zscale(x, sn), zscale(y, cs));
           }
         }
-        if (lane == 0) *rotated = 1;
+        if (lane == 0) {
+          nrm[p] = fmax(app - t * ag, 0.0);
+          nrm[q] = aqq + t * ag;
+          *rotated = 1;
+        }
       }
       __syncthreads();
     }
@@ -584,6 +598,7 @@ __global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
   __shared__ double sig_s[kMaxL];
   __shared__ int perm_s[kMaxL];
   __shared__ int rotated;
+  __shared__ double nrm[kMaxL];
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int meas = 2 * l * l;
@@ -597,7 +612,7 @@ __global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
   }
   __syncthreads();
   int converged;
-  jacobi_core<NT, REGS>(C, J, l, converged, &rotated);
+  jacobi_core<NT, REGS>(C, J, l, converged, &rotated, nrm);
   if (!converged && threadIdx.x == 0) P.flags |= TEBD_DEV_JACOBI_NOCONV;
   jacobi_finish<NT>(P, C, J, l, sig_s, perm_s);
 }

@@ -20,10 +20,34 @@ __device__ __forceinline__ zt zcmul(zt a, zt b) {
 }
 __device__ __forceinline__ double zabs2(zt a) { return a.x * a.x + a.y * a.y; }
 
+// Wavefront sum of a double, result in every lane.  DPP moves on the two
+// 32-bit halves: quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror and
+// row_mirror give every lane its 16-lane row sum; row_bcast15 into rows 1, 3
+// and row_bcast31 into rows 2, 3 leave the total in lane 63, which is read
+// back as a uniform value.  (GFX9 DPP controls; no LDS traffic.)
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
+#ifdef TEBD_SHFL_REDUCE
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+#else
+  v += dpp_move<0xb1>(v);
+  v += dpp_move<0x4e>(v);
+  v += dpp_move<0x141>(v);
+  v += dpp_move<0x140>(v);
+  v += dpp_move<0x142, 0xa>(v);
+  v += dpp_move<0x143, 0xc>(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+#endif
 }
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
