@@ -164,7 +164,7 @@ constexpr int kLdsElems = 9600;  // complex elements of LDS a workgroup may clai
 constexpr int kRegRows = 16;
 
 __device__ __forceinline__ bool qr_in_lds(int rows, int l) {
-  return int64_t(l + 1) * rows <= kLdsElems;
+  return int64_t(l + 2) * rows <= kLdsElems;
 }
 
 // y_c[j0..rows) -= 2 u (u^H y_c) for one column, by one wavefront.  Rows
@@ -227,12 +227,20 @@ __device__ __forceinline__ void reflect_column(const zt* __restrict__ u, zt* yc,
 // (ties: lowest index), and the factorisation stops at the first j >= 1 whose
 // pivot norm |R_jj| is <= kRankTol |R_00|.  The kept rank r replaces the
 // sketch width l of the problem, so later products and the small SVD work on
-// the numerical range only.  Returns r (= l without pivoting).
+// the numerical range only.
+//
+// Work split: column c belongs to wavefront c mod NW.  Step j is prepared by
+// the owner of column j alone (pivot search, swap, reflector), published in
+// a double-buffered LDS vector, and applied by every wavefront to its own
+// trailing columns, which also yields their new trailing norms (double-
+// buffered, so the next pivot search reads a stable copy).  One barrier per
+// step, two with pivoting; the thin Q is accumulated the same way backwards.
 constexpr double kRankTol = 1e-13;
 
 template <int NT, int REG>
-__device__ __forceinline__ int qr_core(zt* Y, int rows, int l, zt* u_s, zt* rdiag, double* red,
-                                       zt* Rb, bool piv, double* nrm, int* sh_i, double* sh_d) {
+__device__ __forceinline__ int qr_core(zt* Y, int rows, int l, zt* u_s /* 2 * rows */,
+                                       zt* rdiag, zt* Rb, bool piv, double* nrm /* 2 * kMaxL */,
+                                       int* sh_i) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = NT / 64;
   int rank = l;
@@ -244,15 +252,19 @@ __device__ __forceinline__ int qr_core(zt* Y, int rows, int l, zt* u_s, zt* rdia
       s = wave_sum(s);
       if (lane == 0) nrm[c] = s;
     }
-    __syncthreads();
   }
   for (int j = 0; j < l; ++j) {
-    if (piv) {
-      if (wave == 0) {
+    double* ncur = nrm + (j & 1) * kMaxL;
+    double* nnext = nrm + ((j + 1) & 1) * kMaxL;
+    zt* u = u_s + (j & 1) * rows;
+    if (piv) __syncthreads();  // trailing norms of step j-1 are complete
+    if (wave == (j % NW)) {
+      int stop = 0;
+      if (piv) {
         double best = -1.0;
         int bi = j;
         for (int c = j + lane; c < l; c += 64) {
-          const double v = nrm[c];
+          const double v = ncur[c];
           if (v > best) {
             best = v;
             bi = c;
@@ -267,72 +279,53 @@ __device__ __forceinline__ int qr_core(zt* Y, int rows, int l, zt* u_s, zt* rdia
             bi = oi;
           }
         }
-        if (lane == 0) {
-          sh_i[0] = bi;
-          sh_d[0] = best;
+        const double pn = sqrt(fmax(best, 0.0));
+        if (j == 0) r00 = pn;
+        if (j > 0 && !(pn > kRankTol * r00)) stop = 1;
+        if (!stop && bi != j) {
+          zt* ya = Y + size_t(j) * rows;
+          zt* yb = Y + size_t(bi) * rows;
+          for (int r = lane; r < rows; r += 64) {
+            const zt t = ya[r];
+            ya[r] = yb[r];
+            yb[r] = t;
+          }
         }
       }
-      __syncthreads();
-      const int pc = sh_i[0];
-      const double pn = sqrt(fmax(sh_d[0], 0.0));
-      if (j == 0) r00 = pn;
-      if (j > 0 && !(pn > kRankTol * r00)) {
-        rank = j;
-        break;
-      }
-      if (pc != j) {
-        zt* a = Y + size_t(j) * rows;
-        zt* b = Y + size_t(pc) * rows;
-        for (int r = tid; r < rows; r += NT) {
-          const zt t = a[r];
-          a[r] = b[r];
-          b[r] = t;
+      if (!stop) {
+        zt* yj = Y + size_t(j) * rows;
+        double s = 0.0;
+        for (int r = j + 1 + lane; r < rows; r += 64) s += zabs2(yj[r]);
+        s = wave_sum(s);
+        const zt alpha = yj[j];
+        const double aa = sqrt(zabs2(alpha));
+        const double xnorm = sqrt(aa * aa + s);
+        zt beta = make_double2(0.0, 0.0), v0 = make_double2(0.0, 0.0);
+        double vinv = 0.0;  // 1 / ||x - beta e_j||
+        if (xnorm > 0.0) {
+          const zt ph = aa > 0.0 ? zscale(alpha, 1.0 / aa) : make_double2(1.0, 0.0);
+          beta = zscale(ph, -xnorm);
+          v0 = zsub(alpha, beta);
+          vinv = 1.0 / sqrt(2.0 * xnorm * (xnorm + aa));
         }
-        if (tid == 0) {
-          const double t = nrm[j];
-          nrm[j] = nrm[pc];
-          nrm[pc] = t;
+        for (int r = j + lane; r < rows; r += 64) {
+          const zt uu = zscale(r == j ? v0 : yj[r], vinv);
+          u[r] = uu;
+          yj[r] = uu;
         }
+        if (lane == 0) rdiag[j] = beta;
       }
-      __syncthreads();
+      if (lane == 0) sh_i[j & 1] = stop;
     }
-    zt* yj = Y + size_t(j) * rows;
-    double s = 0.0;
-    for (int r = j + 1 + tid; r < rows; r += NT) s += zabs2(yj[r]);
-    s = block_sum<NT>(s, red);
-    const zt alpha = yj[j];
-    const double aa = sqrt(zabs2(alpha));
-    const double xnorm = sqrt(aa * aa + s);
-    zt beta = make_double2(0.0, 0.0), v0 = make_double2(0.0, 0.0);
-    double vinv = 0.0;  // 1 / ||x - beta e_j||
-    if (xnorm > 0.0) {
-      const zt ph = aa > 0.0 ? zscale(alpha, 1.0 / aa) : make_double2(1.0, 0.0);
-      beta = zscale(ph, -xnorm);
-      v0 = zsub(alpha, beta);
-      vinv = 1.0 / sqrt(2.0 * xnorm * (xnorm + aa));
+    __syncthreads();  // reflector j (or the stop decision) is published
+    if (sh_i[j & 1]) {
+      rank = j;
+      break;
     }
-    __syncthreads();  // everyone has read yj[j] before it is overwritten
-    for (int r = j + tid; r < rows; r += NT) {
-      const zt u = zscale(r == j ? v0 : yj[r], vinv);
-      u_s[r] = u;
-      yj[r] = u;
-    }
-    if (tid == 0) rdiag[j] = beta;
-    __syncthreads();
-    if (vinv != 0.0) {
-      for (int c = j + 1 + wave; c < l; c += NW)
-        reflect_column<REG>(u_s, Y + size_t(c) * rows, j, j, rows, lane, piv ? nrm + c : nullptr);
-    } else if (piv) {
-      // H_j = I: trailing norms lose row j only
-      for (int c = j + 1 + wave; c < l; c += NW) {
-        double nn = 0.0;
-        for (int r = j + 1 + lane; r < rows; r += 64) nn += zabs2(Y[size_t(c) * rows + r]);
-        nn = wave_sum(nn);
-        if (lane == 0) nrm[c] = nn;
-      }
-    }
-    __syncthreads();
+    for (int c = j + 1 + ((wave - (j + 1) % NW + NW) % NW); c < l; c += NW)
+      reflect_column<REG>(u, Y + size_t(c) * rows, j, j, rows, lane, piv ? nnext + c : nullptr);
   }
+  __syncthreads();
   if (Rb) {
     for (int e = tid; e < rank * rank; e += NT) {
       const int c = e / rank, i = e - c * rank;
@@ -347,53 +340,54 @@ __device__ __forceinline__ int qr_core(zt* Y, int rows, int l, zt* u_s, zt* rdia
     }
     __syncthreads();
   }
-  // Q = H_0 H_1 ... H_{r-1} [I; 0], accumulated from the last reflector.
+  // Q = H_0 H_1 ... H_{r-1} [I; 0], accumulated from the last reflector: the
+  // owner of column j publishes u_j and turns its column into H_j e_j, then
+  // every wavefront applies H_j to its columns c > j (row j treated as 0).
   for (int j = rank - 1; j >= 0; --j) {
-    zt* yj = Y + size_t(j) * rows;
-    for (int r = j + tid; r < rows; r += NT) u_s[r] = yj[r];
-    __syncthreads();
-    // trailing columns: row j held an R entry and is treated as zero
-    for (int c = j + 1 + wave; c < rank; c += NW)
-      reflect_column<REG>(u_s, Y + size_t(c) * rows, j, j + 1, rows, lane);
-    // column j = H_j e_j
-    const zt uj = u_s[j];
-    for (int r = tid; r < rows; r += NT) {
-      zt v = make_double2(0.0, 0.0);
-      if (r >= j) {
-        v = zscale(zmul(u_s[r], zconj(uj)), -2.0);
-        if (r == j) v.x += 1.0;
+    zt* u = u_s + (j & 1) * rows;
+    if (wave == (j % NW)) {
+      zt* yj = Y + size_t(j) * rows;
+      for (int r = j + lane; r < rows; r += 64) u[r] = yj[r];
+      const zt uj = yj[j];
+      for (int r = lane; r < rows; r += 64) {
+        zt v = make_double2(0.0, 0.0);
+        if (r >= j) {
+          v = zscale(zmul(r == j ? uj : yj[r], zconj(uj)), -2.0);
+          if (r == j) v.x += 1.0;
+        }
+        yj[r] = v;
       }
-      yj[r] = v;
     }
     __syncthreads();
+    for (int c = j + 1 + ((wave - (j + 1) % NW + NW) % NW); c < rank; c += NW)
+      reflect_column<REG>(u, Y + size_t(c) * rows, j, j + 1, rows, lane);
   }
+  __syncthreads();
   return rank;
 }
 
-// Size classes: a problem of measure (l + 1) * rows in (LO, HI] runs in the
+// Size classes: a problem of measure (l + 2) * rows in (LO, HI] runs in the
 // LDS variant of that class (HI complex elements of LDS, NT threads):
 // (0, 1024] with 64 threads, (1024, 3072] with 256, (3072, 9600] with 1024;
 // above that it runs on global memory with 1024 threads.  Every class is one
 // launch over all problems; workgroups of other classes return at once.
 template <int NT, int HI, int LO>
 __global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_r) {
-  extern __shared__ zt lds[];  // rows * l matrix, then rows for u
-  __shared__ double red[NT / 64];
+  extern __shared__ zt lds[];  // rows * l matrix, then 2 * rows for u
   __shared__ zt rdiag[kMaxL];
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
-  const int64_t meas = int64_t(l + 1) * rows;
+  const int64_t meas = int64_t(l + 2) * rows;
   if (l == 0 || meas <= LO || meas > HI) return;
-  __shared__ double nrm[kMaxL];
-  __shared__ int sh_i[1];
-  __shared__ double sh_d[1];
+  __shared__ double nrm[2 * kMaxL];
+  __shared__ int sh_i[2];
   zt* Yg = which ? P.Yt : P.Y;
   const int tot = rows * l;
   for (int e = threadIdx.x; e < tot; e += NT) lds[e] = Yg[e];
   __syncthreads();
-  const int rank = qr_core<NT, 0>(lds, rows, l, lds + tot, rdiag, red, want_r ? P.Rb : nullptr,
-                                  !want_r, nrm, sh_i, sh_d);
+  const int rank = qr_core<NT, 0>(lds, rows, l, lds + tot, rdiag, want_r ? P.Rb : nullptr,
+                                  !want_r, nrm, sh_i);
   const int keep = rows * rank;
   for (int e = threadIdx.x; e < keep; e += NT) Yg[e] = lds[e];
   if (threadIdx.x == 0) P.l = rank;
@@ -401,18 +395,16 @@ __global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_r) {
-  extern __shared__ zt u_s[];  // rows
-  __shared__ double red[NT / 64];
+  extern __shared__ zt u_s[];  // 2 * rows
   __shared__ zt rdiag[kMaxL];
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
   if (l == 0 || qr_in_lds(rows, l)) return;
-  __shared__ double nrm[kMaxL];
-  __shared__ int sh_i[1];
-  __shared__ double sh_d[1];
-  const int rank = qr_core<NT, kRegRows>(which ? P.Yt : P.Y, rows, l, u_s, rdiag, red,
-                                         want_r ? P.Rb : nullptr, !want_r, nrm, sh_i, sh_d);
+  __shared__ double nrm[2 * kMaxL];
+  __shared__ int sh_i[2];
+  const int rank = qr_core<NT, kRegRows>(which ? P.Yt : P.Y, rows, l, u_s, rdiag,
+                                         want_r ? P.Rb : nullptr, !want_r, nrm, sh_i);
   if (threadIdx.x == 0) P.l = rank;
 }
 
@@ -424,11 +416,11 @@ inline bool class_reached(int64_t mlo, int64_t mhi, int64_t lo, int64_t hi) {
 hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStream_t s) {
   const int rows = which ? c.nmax : c.mmax;
   const int rows_min = which ? c.nmin : c.mmin;
-  const int64_t mhi = int64_t(c.lmax + 1) * rows, mlo = int64_t(c.lmin + 1) * rows_min;
+  const int64_t mhi = int64_t(c.lmax + 2) * rows, mlo = int64_t(c.lmin + 2) * rows_min;
   static const hipError_t attr = []() {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_qr_glb<1024>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       int(size_t(kMaxRows) * sizeof(zt)));
+                                       int(2 * size_t(kMaxRows) * sizeof(zt)));
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_qr_lds<1024, kLdsElems, 3072>),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -445,7 +437,7 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStr
     hipLaunchKernelGGL((k_qr_lds<1024, kLdsElems, 3072>), g, dim3(1024), size_t(kLdsElems) * sizeof(zt),
                        s, probs, which, want_r);
   if (class_reached(mlo, mhi, kLdsElems, 0))
-    hipLaunchKernelGGL(k_qr_glb<1024>, g, dim3(1024), size_t(rows) * sizeof(zt), s, probs, which,
+    hipLaunchKernelGGL(k_qr_glb<1024>, g, dim3(1024), 2 * size_t(rows) * sizeof(zt), s, probs, which,
                        want_r);
   return hipGetLastError();
 }

@@ -209,6 +209,6 @@ __host__ __device__ inline void carve_slab(Prob& p, char* base, int64_t m, int64
 
 // Largest l (sketch width) and m supported by the factorisation kernels.
 constexpr int kMaxL = 256;
-constexpr int kMaxRows = 8192;
+constexpr int kMaxRows = 4096;
 
 }  // namespace tebd
