@@ -228,12 +228,17 @@ hipError_t run_pipeline(Prob* probs, const Common& c, hipStream_t s) {
     TIMED(PK_FROB, launch_frob(probs, c, s));
   }
   TIMED(PK_OMEGA, launch_omega(probs, c, s));
-  TIMED(PK_SKETCH_AOM, launch_sketch(probs, c, SK_Y_FROM_OMEGA, s));
+  // mixed precision: sketch and power-iteration products in complex FP32;
+  // the QRs, the final projection and everything after stay FP64
+  auto sketch = [&](int which) {
+    return c.mixed ? launch_sketch_f32(probs, c, which, s) : launch_sketch(probs, c, which, s);
+  };
+  TIMED(PK_SKETCH_AOM, sketch(SK_Y_FROM_OMEGA));
   TIMED(PK_QR, launch_qr(probs, c, 0, 0, s));
   for (int j = 0; j < c.q; ++j) {
-    TIMED(PK_SKETCH_AHQ, launch_sketch(probs, c, SK_YT_FROM_Y, s));
+    TIMED(PK_SKETCH_AHQ, sketch(SK_YT_FROM_Y));
     TIMED(PK_QR, launch_qr(probs, c, 1, 0, s));
-    TIMED(PK_SKETCH_AQT, launch_sketch(probs, c, SK_Y_FROM_YT, s));
+    TIMED(PK_SKETCH_AQT, sketch(SK_Y_FROM_YT));
     TIMED(PK_QR, launch_qr(probs, c, 0, 0, s));
   }
   TIMED(PK_SKETCH_AHQ, launch_sketch(probs, c, SK_YT_FROM_Y, s));  // B^H = A^H Q
@@ -271,6 +276,7 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   c.tebd = 1;
   c.adaptive = prm->adaptive;
   c.pass2 = 0;
+  c.mixed = prm->precision;
   c.dmax = mps->d_max;
   c.chimax = mps->chi_max;
   c.offs = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) +
@@ -439,6 +445,7 @@ tebd_status rrsvd_truncate(int64_t batch, const int64_t* m, const int64_t* n,
   c.tebd = 0;
   c.adaptive = 0;
   c.pass2 = 0;
+  c.mixed = prm->precision;
   c.dmax = 0;
   c.chimax = 0;
   for (int64_t b = 0; b < batch; ++b) {

@@ -358,6 +358,47 @@ __global__ __launch_bounds__(256) void k_sketch(Prob* probs, const int32_t* offs
   }
 }
 
+// Mixed precision (sketch and power-iteration products only): complex FP32
+// MFMA with FP32 accumulation; Y and Yt stay FP64 for the QR that follows.
+template <int WHICH>
+__global__ __launch_bounds__(256) void k_sketch_f32(Prob* probs, const int32_t* offs, int nprob,
+                                                    int tebd) {
+  __shared__ float2 smem[Cfg64::lds_elems];
+  if (WHICH == SK_Y_FROM_OMEGA) {
+    for_each_tile<TK_SKM>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdRowA la{P.A, P.lda};
+      LdRowB lb{P.om, P.ldom};
+      StCol st{P.Y, P.m};
+      cgemm_tile<Cfg64>(M, N, P.n, m0, n0, la, lb, st, smem);
+    });
+  } else if (WHICH == SK_YT_FROM_Y) {
+    for_each_tile<TK_SKN>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdAdjA la{P.A, P.lda};
+      LdColB lb{P.Y, P.m};
+      StCol st{P.Yt, P.n};
+      cgemm_tile<Cfg64>(M, N, P.m, m0, n0, la, lb, st, smem);
+    });
+  } else {
+    for_each_tile<TK_SKM>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdRowA la{P.A, P.lda};
+      LdColB lb{P.Yt, P.n};
+      StCol st{P.Y, P.m};
+      cgemm_tile<Cfg64>(M, N, P.n, m0, n0, la, lb, st, smem);
+    });
+  }
+}
+
+hipError_t launch_sketch_f32(Prob* probs, const Common& c, int which, hipStream_t s) {
+  dim3 g(c.grid);
+  if (which == SK_Y_FROM_OMEGA)
+    hipLaunchKernelGGL(k_sketch_f32<SK_Y_FROM_OMEGA>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+  else if (which == SK_YT_FROM_Y)
+    hipLaunchKernelGGL(k_sketch_f32<SK_YT_FROM_Y>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+  else
+    hipLaunchKernelGGL(k_sketch_f32<SK_Y_FROM_YT>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+  return hipGetLastError();
+}
+
 hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s) {
   dim3 g(c.grid);
   if (which == SK_Y_FROM_OMEGA)

@@ -93,6 +93,7 @@ struct Common {
   int32_t chimax;    // TEBD: chi capacity
   int32_t adaptive;  // two-stage adaptive rank (TEBD only)
   int32_t pass2;     // 1: second (fixed-rank) pass of the adaptive scheme
+  int32_t mixed;     // 1: complex FP32 sketch and power-iteration products
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
 };
@@ -125,11 +126,11 @@ hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_frob(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_omega(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s);
+hipError_t launch_sketch_f32(Prob* probs, const Common& c, int which, hipStream_t s);
 hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStream_t s);
 hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_truncate(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_form_uv(Prob* probs, const Common& c, hipStream_t s);
-hipError_t launch_mixed_cast(Prob* probs, const Common& c, int which, hipStream_t s);
 
 // Sketch-product selectors for launch_sketch.
 enum {
@@ -156,10 +157,7 @@ __host__ __device__ inline size_t slab_bytes(int64_t m, int64_t n, int64_t l, in
   b += 5 * align256(l * l * z);      // Rb, C, J, X, W
   b += align256(l * sizeof(double)); // sig
   b += align256(npart * sizeof(double));
-  if (mixed) {
-    b += align256(m * n * sizeof(float2));
-    b += align256((m > n ? m : n) * l * sizeof(float2));
-  }
+  (void)mixed;
   return b;
 }
 
@@ -196,15 +194,9 @@ __host__ __device__ inline void carve_slab(Prob& p, char* base, int64_t m, int64
   c += align256(l * sizeof(double));
   p.part = reinterpret_cast<double*>(c);
   c += align256(npart * sizeof(double));
-  if (mixed) {
-    p.Af = reinterpret_cast<float2*>(c);
-    c += align256(m * n * sizeof(float2));
-    p.Yf = reinterpret_cast<float2*>(c);
-    c += align256((m > n ? m : n) * l * sizeof(float2));
-  } else {
-    p.Af = nullptr;
-    p.Yf = nullptr;
-  }
+  (void)mixed;
+  p.Af = nullptr;
+  p.Yf = nullptr;
 }
 
 // Largest l (sketch width) and m supported by the factorisation kernels.

@@ -173,4 +173,112 @@ __device__ void zgemm_tile(int M, int N, int K, int m0, int n0, const LA& la, co
       }
 }
 
+// Complex FP32 variant for the mixed-precision sketch and power-iteration
+// products: the same tiles and loaders (FP64 operands are rounded to FP32
+// when staged into LDS), v_mfma_f32_16x16x4_f32 with FP32 accumulation.
+// This instruction's 16 x 16 result keeps lane t's four rows contiguous:
+// element r of lane t is C[4 (t/16) + r][t % 16].  Results are widened to
+// FP64 when stored.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <class Cfg, class LA, class LB>
+__device__ __forceinline__ void cgemm_stage(float2* As, float2* Bs, const zt (&ra)[Cfg::NA],
+                                            const zt (&rb)[Cfg::NB]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < Cfg::NA; ++s) {
+    const int e = tid + s * Cfg::NT;
+    int r, k;
+    if (LA::contig_k) {
+      k = e % Cfg::BK;
+      r = e / Cfg::BK;
+    } else {
+      r = e % Cfg::BM;
+      k = e / Cfg::BM;
+    }
+    As[k * Cfg::LDA + r] = make_float2(float(ra[s].x), float(ra[s].y));
+  }
+#pragma unroll
+  for (int s = 0; s < Cfg::NB; ++s) {
+    const int e = tid + s * Cfg::NT;
+    int k, c;
+    if (LB::contig_n) {
+      c = e % Cfg::BN;
+      k = e / Cfg::BN;
+    } else {
+      k = e % Cfg::BK;
+      c = e / Cfg::BK;
+    }
+    Bs[k * Cfg::LDB + c] = make_float2(float(rb[s].x), float(rb[s].y));
+  }
+}
+
+template <class Cfg, class LA, class LB, class ST>
+__device__ void cgemm_tile(int M, int N, int K, int m0, int n0, const LA& la, const LB& lb,
+                           ST& st, float2* smem) {
+  float2* As = smem;
+  float2* Bs = smem + Cfg::BK * Cfg::LDA;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave / Cfg::WGN, wc = wave % Cfg::WGN;
+  v4f accr[Cfg::FM][Cfg::FN], acci[Cfg::FM][Cfg::FN];
+#pragma unroll
+  for (int i = 0; i < Cfg::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < Cfg::FN; ++j) {
+      accr[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+      acci[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+  zt ra[Cfg::NA], rb[Cfg::NB];
+  if (K > 0) zgemm_load<Cfg>(M, N, K, m0, n0, 0, la, lb, ra, rb);
+  for (int k0 = 0; k0 < K; k0 += Cfg::BK) {
+    cgemm_stage<Cfg, LA, LB>(As, Bs, ra, rb);
+    __syncthreads();
+    if (k0 + Cfg::BK < K) zgemm_load<Cfg>(M, N, K, m0, n0, k0 + Cfg::BK, la, lb, ra, rb);
+#pragma unroll
+    for (int kk = 0; kk < Cfg::BK; kk += 4) {
+      const int ka = kk + (lane >> 4);
+      float ar[Cfg::FM], ai[Cfg::FM], nai[Cfg::FM], br[Cfg::FN], bi[Cfg::FN];
+#pragma unroll
+      for (int i = 0; i < Cfg::FM; ++i) {
+        const float2 a = As[ka * Cfg::LDA + wr * Cfg::WM + i * 16 + (lane & 15)];
+        ar[i] = a.x;
+        ai[i] = a.y;
+        nai[i] = -a.y;
+      }
+#pragma unroll
+      for (int j = 0; j < Cfg::FN; ++j) {
+        const float2 b = Bs[ka * Cfg::LDB + wc * Cfg::WN + j * 16 + (lane & 15)];
+        br[j] = b.x;
+        bi[j] = b.y;
+      }
+#pragma unroll
+      for (int i = 0; i < Cfg::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::FN; ++j) {
+          accr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], br[j], accr[i][j], 0, 0, 0);
+          acci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bi[j], acci[i][j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int i = 0; i < Cfg::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < Cfg::FN; ++j) {
+          accr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[i], bi[j], accr[i][j], 0, 0, 0);
+          acci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], br[j], acci[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < Cfg::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < Cfg::FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wr * Cfg::WM + i * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wc * Cfg::WN + j * 16 + (lane & 15);
+        if (row < M && col < N)
+          st(row, col, make_double2(double(accr[i][j][r]), double(acci[i][j][r])));
+      }
+}
+
 }  // namespace tebd
