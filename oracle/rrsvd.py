@@ -149,8 +149,8 @@ def first_stage_rank(chi_mid, chi_max):
     return int(min(chi_max, chi_mid + max(4, (chi_mid + 1) // 2)))
 
 
-def truncate_rrsvd_adaptive(a, omega_of, q, chi_max, eps, k1, p):
-    """Two-stage adaptive-rank RRSVD truncation (TEBD with a tolerance).
+def adaptive_factors(a, omega_of, q, chi_max, eps, k1, p):
+    """Two-stage adaptive-rank RRSVD (TEBD with a tolerance), all factors.
 
     The paper grows the sketch until the range error meets the tolerance
     (Sec. IV, Alg. 2) and notes that ||(I - QQ^H)A||_F is available exactly
@@ -160,7 +160,8 @@ def truncate_rrsvd_adaptive(a, omega_of, q, chi_max, eps, k1, p):
     returned).  Otherwise stage 2 repeats with the fixed-rank width
     l2 = min(chi_max + p, m, n).  omega_of(l) returns the n x l test matrix;
     the first l1 columns of the stage-2 matrix are those of stage 1.
-    Returns (U, s, Vh, chi', w, status, stage) with stage = 1 or 2.
+    Returns (U, s, Vh, chi', w, status, stage) with every triplet of the
+    accepted stage (chi' of them are kept) and stage = 1 or 2.
     """
     a = np.asarray(a, dtype=np.complex128)
     m, n = a.shape
@@ -171,13 +172,22 @@ def truncate_rrsvd_adaptive(a, omega_of, q, chi_max, eps, k1, p):
     wts = frobenius_weights(s, frob2)
     if l1 >= l2:
         chi, w, status = truncation_rank(wts, chi_max, eps)
-        return u[:, :chi], s[:chi], vh[:chi, :], chi, w, status, 1
+        return u, s, vh, chi, w, status, 1
     chi, w, status = truncation_rank(wts, min(k1, chi_max), eps)
     if status == 0 and eps > 0.0:
-        return u[:, :chi], s[:chi], vh[:chi, :], chi, w, status, 1
+        return u, s, vh, chi, w, status, 1
     u, s, vh = rrsvd(a, omega_of(l2), q)
     chi, w, status = truncation_rank(frobenius_weights(s, frob2), chi_max, eps)
-    return u[:, :chi], s[:chi], vh[:chi, :], chi, w, status, 2
+    return u, s, vh, chi, w, status, 2
+
+
+def truncate_rrsvd_adaptive(a, omega_of, q, chi_max, eps, k1, p):
+    """``adaptive_factors`` cut to the kept triplets.
+
+    Returns (U[:, :chi'], s[:chi'], Vh[:chi', :], chi', w, status, stage).
+    """
+    u, s, vh, chi, w, status, stage = adaptive_factors(a, omega_of, q, chi_max, eps, k1, p)
+    return u[:, :chi], s[:chi], vh[:chi, :], chi, w, status, stage
 
 
 def truncate_rrsvd(a, omega, q, chi_max, eps):
