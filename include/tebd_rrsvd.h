@@ -122,8 +122,9 @@ const char* tebd_last_error(void);
 const char* tebd_version(void);
 
 /* Bytes of workspace needed.
- *  - For tebd_bond_update / tebd_sweep: pass mps (non-NULL), batch = 0,
- *    m = n = NULL.  The size covers one sweep over every chain.
+ *  - For tebd_bond_update / tebd_sweep / tebd_sweep_record /
+ *    tebd_sweep_adjoint: pass mps (non-NULL), batch = 0, m = n = NULL.  The
+ *    size covers one sweep (or its adjoint) over every chain.
  *  - For rrsvd_truncate: pass mps = NULL, the batch size and the host arrays
  *    m[batch], n[batch].
  * Returns TEBD_ERR_ARG / TEBD_ERR_SHAPE for invalid input. */
@@ -196,6 +197,67 @@ tebd_status tebd_bond_update(const tebd_mps* mps, int32_t chain, int32_t bond,
 tebd_status tebd_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate_chain_stride,
                        int32_t parity, const tebd_params* prm, double* disc_weight,
                        int32_t* dev_status, void* workspace, size_t ws_bytes, void* stream);
+
+/* Reverse mode.  The paper does not differentiate the bond update; these
+ * entry points give the derivative of the map it defines, for gradients of
+ * observables with respect to the gates (and, through exp(-i tau h_b), the
+ * Hamiltonian couplings).  Cotangent convention: for a real loss L and a
+ * complex entry z = x + i y the cotangent is dL/dx + i dL/dy; for a real
+ * entry it is dL/dx.  Cotangent arrays use the layouts of tebd_mps and of
+ * the gates.
+ *
+ * A time step is replayed sweep by sweep with tebd_sweep_record, which keeps
+ * a copy of the state before each sweep (made by the caller) and the tape,
+ * then undone in reverse order with tebd_sweep_adjoint. */
+
+/* Bytes of the tape of one recorded sweep of `mps` under `prm` (either
+ * parity). */
+tebd_status tebd_tape_size(const tebd_mps* mps, const tebd_params* prm, size_t* bytes);
+
+/* tebd_sweep (same arguments, same results, same random stream) that also
+ * writes, for every bond, what its adjoint needs into `tape` (device,
+ * 256-byte aligned, tape_bytes >= tebd_tape_size): the bond's geometry and
+ * every singular triplet its RRSVD computed, kept or not, as plain U, s and
+ * V^H before renormalisation and reabsorption. */
+tebd_status tebd_sweep_record(const tebd_mps* mps, const tebd_z* gates, int64_t gate_chain_stride,
+                              int32_t parity, const tebd_params* prm, double* disc_weight,
+                              int32_t* dev_status, void* tape, size_t tape_bytes,
+                              void* workspace, size_t ws_bytes, void* stream);
+
+/* Adjoint of one recorded sweep (every bond of the parity, every chain).
+ *
+ *  mps_in        the state before the recorded sweep (read only; the
+ *                caller's copy), with the same capacities as when recorded
+ *  gates, gate_chain_stride, parity, prm
+ *                as passed to tebd_sweep_record (prm->lambda_floor, chi_max
+ *                and p are used)
+ *  tape          device: written by tebd_sweep_record for this sweep
+ *  gamma_bar     device, layout of mps.gamma: on entry the cotangent of the
+ *                state after the sweep, on return that of the state before
+ *                it (sites the sweep did not touch are left as they are;
+ *                entries outside the bond dimensions are written as zero)
+ *  lambda_bar    device, layout of mps.lambda: same
+ *  gate_bar      device, layout of the gates: the cotangent of each bond's
+ *                gate is added to it (with a zero chain stride every chain
+ *                adds to the shared gate)
+ *  dev_status    device [n_chains][n_sites - 1]: for the bonds of this
+ *                parity 0, or TEBD_DEV_BAD_STATE when the tape does not
+ *                describe that bond of mps_in (the bond is then skipped)
+ *
+ * Per bond (Sec. II.B undone): the cotangents of Gamma'_k, Gamma'_k+1 are
+ * divided by lambda_l, lambda_r (the reabsorption), that of lambda' goes
+ * through the renormalisation; the SVD adjoint couples the kept triplets
+ * to every triplet the RRSVD computed (those enter with zero cotangent),
+ * with 1/(s_j^2 - s_i^2) broadened to D/(D^2 + eta^2), eta = 1e-12 s_1^2,
+ * and the rest of the spectrum through the projector terms
+ * (I - U U^H) Ubar S^-1 V^H + U S^-1 Vbar^H (I - V V^H); then
+ * Theta-bar = G^H Abar, Gbar += Abar Theta^H, and back through Eq. deftheta.
+ * Bonds are independent within a sweep; all sums have a fixed order. */
+tebd_status tebd_sweep_adjoint(const tebd_mps* mps_in, const tebd_z* gates,
+                               int64_t gate_chain_stride, int32_t parity, const tebd_params* prm,
+                               const void* tape, size_t tape_bytes, tebd_z* gamma_bar,
+                               double* lambda_bar, tebd_z* gate_bar, int32_t* dev_status,
+                               void* workspace, size_t ws_bytes, void* stream);
 
 /* Per-kernel timing with HIP events, for the per-phase split of the update
  * (the paper's profile of the two-site update, Sec. V.B).  Off by default.

@@ -138,9 +138,10 @@ def recorded_bond_update(mps, b, gate, chi_max, eps, method="full", omega_of=Non
 
     method "full": O-def, the same arithmetic as ``mps.bond_update``; every
     triplet of the LAPACK SVD is recorded; chi_fixed forces the kept rank
-    (replay of a recorded schedule).  method "rrsvd_adaptive": O-alg with
-    the two-stage rank (``rrsvd.adaptive_factors``); the triplets of the
-    accepted stage are recorded.
+    (replay of a recorded schedule).  method "rrsvd": O-alg at the fixed
+    sketch width min(chi_max + p, m, n); method "rrsvd_adaptive": O-alg with
+    the two-stage rank (``rrsvd.adaptive_factors``).  The RRSVD methods
+    record every triplet the accepted sketch gave.
     """
     lam_l, lam_r = om.outer_lambdas(mps, b)
     rec = {"b": b, "gk": mps.gammas[b].copy(), "gk1": mps.gammas[b + 1].copy(),
@@ -155,6 +156,10 @@ def recorded_bond_update(mps, b, gate, chi_max, eps, method="full", omega_of=Non
             chi, _, _ = rr.truncation_rank(rr.tail_weights(s), chi_max, eps)
         else:
             chi = int(chi_fixed)
+    elif method == "rrsvd":
+        u, s, vh = rr.rrsvd(a, omega_of(rr.sketch_width(chi_max, p, *a.shape)), q)
+        chi, _, _ = rr.truncation_rank(rr.frobenius_weights(s, float(np.vdot(a, a).real)),
+                                       chi_max, eps)
     elif method == "rrsvd_adaptive":
         k1 = rr.first_stage_rank(len(mps.lambdas[b]), chi_max)
         u, s, vh, chi, _, _, _ = rr.adaptive_factors(a, omega_of, q, chi_max, eps, k1, p)
@@ -188,7 +193,7 @@ def run_recorded(mps0, gate_fn, dt, steps, chi_max, eps, method="full", q=2, p=1
             tau = frac * dt
             for b in range(parity, n - 1, 2):
                 omega_of = None
-                if method == "rrsvd_adaptive":
+                if method in ("rrsvd", "rrsvd_adaptive"):
                     ncol = state.dims[b + 1] * state.chis()[b + 2]
 
                     def omega_of(l, ncol=ncol, pid=chain * (n - 1) + b, sid=sweep_id):

@@ -27,7 +27,8 @@ DEV_BAD_STATE = 32
 DEV_RANK_RETRY = 64
 
 EXPORTED = ("tebd_last_error", "tebd_version", "tebd_workspace_size", "rrsvd_truncate",
-            "tebd_bond_update", "tebd_sweep", "tebd_profile_enable", "tebd_profile_read")
+            "tebd_bond_update", "tebd_sweep", "tebd_tape_size", "tebd_sweep_record",
+            "tebd_sweep_adjoint", "tebd_profile_enable", "tebd_profile_read")
 
 
 class TebdParams(ctypes.Structure):
@@ -80,6 +81,16 @@ def load():
     lib.tebd_sweep.restype = ctypes.c_int
     lib.tebd_sweep.argtypes = [ctypes.POINTER(TebdMps), vp, i64, i32, ctypes.POINTER(TebdParams),
                                vp, vp, vp, sz, vp]
+    lib.tebd_tape_size.restype = ctypes.c_int
+    lib.tebd_tape_size.argtypes = [ctypes.POINTER(TebdMps), ctypes.POINTER(TebdParams),
+                                   ctypes.POINTER(sz)]
+    lib.tebd_sweep_record.restype = ctypes.c_int
+    lib.tebd_sweep_record.argtypes = [ctypes.POINTER(TebdMps), vp, i64, i32,
+                                      ctypes.POINTER(TebdParams), vp, vp, vp, sz, vp, sz, vp]
+    lib.tebd_sweep_adjoint.restype = ctypes.c_int
+    lib.tebd_sweep_adjoint.argtypes = [ctypes.POINTER(TebdMps), vp, i64, i32,
+                                       ctypes.POINTER(TebdParams), vp, sz, vp, vp, vp, vp, vp, sz,
+                                       vp]
     lib.tebd_profile_enable.restype = ctypes.c_int
     lib.tebd_profile_enable.argtypes = [i32]
     lib.tebd_profile_read.restype = ctypes.c_int
@@ -157,6 +168,28 @@ def tebd_sweep(mps, gates_ptr, gate_chain_stride, parity, prm, disc_ptr, status_
     lib = load()
     return lib.tebd_sweep(ctypes.byref(mps), gates_ptr, int(gate_chain_stride), int(parity),
                           ctypes.byref(prm), disc_ptr, status_ptr, ws_ptr, int(ws_bytes), stream)
+
+
+def tebd_tape_size(mps, prm):
+    out = ctypes.c_size_t(0)
+    check(load().tebd_tape_size(ctypes.byref(mps), ctypes.byref(prm), ctypes.byref(out)))
+    return out.value
+
+
+def tebd_sweep_record(mps, gates_ptr, gate_chain_stride, parity, prm, disc_ptr, status_ptr,
+                      tape_ptr, tape_bytes, ws_ptr, ws_bytes, stream):
+    return load().tebd_sweep_record(ctypes.byref(mps), gates_ptr, int(gate_chain_stride),
+                                    int(parity), ctypes.byref(prm), disc_ptr, status_ptr, tape_ptr,
+                                    int(tape_bytes), ws_ptr, int(ws_bytes), stream)
+
+
+def tebd_sweep_adjoint(mps_in, gates_ptr, gate_chain_stride, parity, prm, tape_ptr, tape_bytes,
+                       gamma_bar_ptr, lambda_bar_ptr, gate_bar_ptr, status_ptr, ws_ptr, ws_bytes,
+                       stream):
+    return load().tebd_sweep_adjoint(ctypes.byref(mps_in), gates_ptr, int(gate_chain_stride),
+                                     int(parity), ctypes.byref(prm), tape_ptr, int(tape_bytes),
+                                     gamma_bar_ptr, lambda_bar_ptr, gate_bar_ptr, status_ptr,
+                                     ws_ptr, int(ws_bytes), stream)
 
 
 def tebd_profile_enable(on):

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtebd_rrsvd.so")
-SOURCES = ["contract.hip", "factor.hip", "abi.cpp"]
+SOURCES = ["contract.hip", "factor.hip", "adjoint.hip", "abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled on purpose: the compiler may not
 # form v_pk_* FP32 operations in any kernel of this library.

@@ -91,7 +91,12 @@ int sketch_l(int64_t k, int64_t p, int64_t m, int64_t n) {
 struct SweepPlan {
   int64_t pmax;
   int64_t mcap, lcap, npart;
-  size_t desc_bytes, slab_sz, total;
+  size_t desc_bytes, slab_sz;
+  // reverse mode of a sweep (same workspace)
+  int64_t nchunk;
+  size_t adj_desc_bytes, adj_slab_sz;
+  size_t tape_slot;
+  size_t total;  // bytes serving the forward and the adjoint
 };
 
 SweepPlan plan_sweep(const tebd_mps& mps, const tebd_params& prm) {
@@ -103,7 +108,15 @@ SweepPlan plan_sweep(const tebd_mps& mps, const tebd_params& prm) {
   s.npart = int64_t((mps.d_max * mps.d_max + 63) / 64) * ((int64_t(mps.chi_max) * mps.chi_max + 63) / 64);
   s.desc_bytes = align256(size_t(s.pmax) * sizeof(Prob)) + align256(sched_bytes(s.pmax));
   s.slab_sz = slab_bytes(s.mcap, s.mcap, s.lcap, 1, prm.precision, s.npart);
-  s.total = s.desc_bytes + size_t(s.pmax) * s.slab_sz;
+  const int64_t cap = mps.chi_max, d2 = int64_t(mps.d_max) * mps.d_max;
+  s.nchunk = (cap * cap + kGateChunk - 1) / kGateChunk;
+  s.adj_desc_bytes = align256(size_t(s.pmax) * sizeof(AdjProb)) +
+                     align256(size_t(TA_COUNT) * size_t(s.pmax + 1) * sizeof(int32_t));
+  s.adj_slab_sz = adj_slab_bytes(s.mcap, s.mcap, s.lcap, cap, d2, s.nchunk);
+  s.tape_slot = tape_slot_bytes(s.mcap, s.mcap, s.lcap);
+  const size_t fwd = s.desc_bytes + size_t(s.pmax) * s.slab_sz;
+  const size_t adj = s.adj_desc_bytes + size_t(s.pmax) * s.adj_slab_sz;
+  s.total = fwd > adj ? fwd : adj;
   return s;
 }
 
@@ -152,12 +165,13 @@ hipError_t upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
 // Optional per-kernel event timing (tebd_profile_enable / tebd_profile_read).
 enum ProfKind {
   PK_PLAN, PK_SCHEDULE, PK_THETA_GATE, PK_FROB, PK_OMEGA, PK_SKETCH_AOM, PK_SKETCH_AHQ,
-  PK_SKETCH_AQT, PK_QR, PK_QR_R, PK_SMALL_SVD, PK_TRUNCATE, PK_FORM_UV, PK_STAGE2, PK_COUNT
+  PK_SKETCH_AQT, PK_QR, PK_QR_R, PK_SMALL_SVD, PK_TRUNCATE, PK_FORM_UV, PK_STAGE2, PK_TAPE,
+  PK_ADJOINT, PK_COUNT
 };
 const char* const kProfNames[PK_COUNT] = {
     "plan_sweep", "schedule",  "theta_gate", "frobenius",  "omega",    "sketch_A_Omega",
     "sketch_AH_Q", "sketch_A_Qt", "qr",       "qr_with_r", "small_svd", "truncate",
-    "form_u_vh", "stage2_prep"};
+    "form_u_vh", "stage2_prep", "tape", "adjoint_sweep"};
 
 struct Profiler {
   std::mutex mu;
@@ -246,6 +260,7 @@ hipError_t run_pipeline(Prob* probs, const Common& c, hipStream_t s) {
   TIMED(PK_SMALL_SVD, launch_small_svd(probs, c, s));
   TIMED(PK_TRUNCATE, launch_truncate(probs, c, s));
   TIMED(PK_FORM_UV, launch_form_uv(probs, c, s));
+  if (c.record) TIMED(PK_TAPE, launch_tape(probs, c, s));
 #undef TIMED
 #undef TRY
   return hipSuccess;
@@ -254,7 +269,7 @@ hipError_t run_pipeline(Prob* probs, const Common& c, hipStream_t s) {
 tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate_chain_stride,
                           int32_t parity, int32_t single_chain, int32_t single_bond,
                           const tebd_params* prm, double* disc, int32_t* status, void* ws,
-                          size_t ws_bytes, void* stream) {
+                          size_t ws_bytes, void* stream, void* tape = nullptr) {
   const SweepPlan pl = plan_sweep(*mps, *prm);
   if (!ws) return fail(TEBD_ERR_WORKSPACE, "workspace is NULL");
   if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
@@ -277,6 +292,8 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   c.adaptive = prm->adaptive;
   c.pass2 = 0;
   c.mixed = prm->precision;
+  c.record = tape != nullptr;
+  c.nsites = mps->n_sites;
   c.dmax = mps->d_max;
   c.chimax = mps->chi_max;
   c.offs = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) +
@@ -294,7 +311,8 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   hipError_t e = timed(PK_PLAN, s, [&]() {
     return launch_plan_sweep(probs, c, *mps, reinterpret_cast<const zt*>(gates), gate_chain_stride,
                              parity, single_chain, single_bond, prm->p, slabs, pl.slab_sz, disc,
-                             status, prm->lambda_floor, prm->precision, prm->adaptive, s);
+                             status, prm->lambda_floor, prm->precision, prm->adaptive,
+                             reinterpret_cast<char*>(tape), pl.tape_slot, s);
   });
   if (e == hipSuccess) e = run_pipeline(probs, c, s);
   if (e == hipSuccess && c.adaptive) {
@@ -318,7 +336,7 @@ const char* tebd_version(void) { return "tebd_rrsvd 0.1 (gfx950, complex128)"; }
 tebd_status tebd_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   for (auto& r : g_prof.recs) {
-    hipEventSynchronize(r.b);
+    (void)hipEventSynchronize(r.b);
   }
   g_prof.recycle();
   g_prof.on = on != 0;
@@ -446,6 +464,8 @@ tebd_status rrsvd_truncate(int64_t batch, const int64_t* m, const int64_t* n,
   c.adaptive = 0;
   c.pass2 = 0;
   c.mixed = prm->precision;
+  c.record = 0;
+  c.nsites = 0;
   c.dmax = 0;
   c.chimax = 0;
   for (int64_t b = 0; b < batch; ++b) {
@@ -536,6 +556,103 @@ tebd_status tebd_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate_ch
   if (!dev_status) return fail(TEBD_ERR_ARG, "argument 7 (dev_status) is NULL");
   return enqueue_sweep(mps, gates, gate_chain_stride, parity, -1, -1, prm, disc_weight,
                        dev_status, workspace, ws_bytes, stream);
+}
+
+tebd_status tebd_tape_size(const tebd_mps* mps, const tebd_params* prm, size_t* bytes) {
+  if (!bytes) return fail(TEBD_ERR_ARG, "argument 3 (bytes) is NULL");
+  tebd_status st = check_params(prm);
+  if (st != TEBD_OK) return st;
+  st = check_mps(mps, prm);
+  if (st != TEBD_OK) return st;
+  const SweepPlan pl = plan_sweep(*mps, *prm);
+  *bytes = size_t(pl.pmax) * pl.tape_slot;
+  return ok();
+}
+
+tebd_status tebd_sweep_record(const tebd_mps* mps, const tebd_z* gates, int64_t gate_chain_stride,
+                              int32_t parity, const tebd_params* prm, double* disc_weight,
+                              int32_t* dev_status, void* tape, size_t tape_bytes,
+                              void* workspace, size_t ws_bytes, void* stream) {
+  tebd_status st = check_params(prm);
+  if (st != TEBD_OK) return st;
+  st = check_mps(mps, prm);
+  if (st != TEBD_OK) return st;
+  if (!gates) return fail(TEBD_ERR_ARG, "argument 2 (gates) is NULL");
+  if (gate_chain_stride < 0)
+    return fail(TEBD_ERR_ARG, "argument 3 (gate_chain_stride) = %lld must be >= 0",
+                (long long)gate_chain_stride);
+  if (parity != 0 && parity != 1)
+    return fail(TEBD_ERR_ARG, "argument 4 (parity) = %d must be 0 or 1", parity);
+  if (!disc_weight) return fail(TEBD_ERR_ARG, "argument 6 (disc_weight) is NULL");
+  if (!dev_status) return fail(TEBD_ERR_ARG, "argument 7 (dev_status) is NULL");
+  if (!tape) return fail(TEBD_ERR_ARG, "argument 8 (tape) is NULL");
+  if (reinterpret_cast<uintptr_t>(tape) % 256 != 0)
+    return fail(TEBD_ERR_WORKSPACE, "argument 8 (tape) must be 256-byte aligned");
+  const SweepPlan pl = plan_sweep(*mps, *prm);
+  if (tape_bytes < size_t(pl.pmax) * pl.tape_slot)
+    return fail(TEBD_ERR_WORKSPACE, "argument 9 (tape_bytes) = %zu < %zu needed", tape_bytes,
+                size_t(pl.pmax) * pl.tape_slot);
+  return enqueue_sweep(mps, gates, gate_chain_stride, parity, -1, -1, prm, disc_weight,
+                       dev_status, workspace, ws_bytes, stream, tape);
+}
+
+tebd_status tebd_sweep_adjoint(const tebd_mps* mps_in, const tebd_z* gates,
+                               int64_t gate_chain_stride, int32_t parity, const tebd_params* prm,
+                               const void* tape, size_t tape_bytes, tebd_z* gamma_bar,
+                               double* lambda_bar, tebd_z* gate_bar, int32_t* dev_status,
+                               void* workspace, size_t ws_bytes, void* stream) {
+  tebd_status st = check_params(prm);
+  if (st != TEBD_OK) return st;
+  st = check_mps(mps_in, prm);
+  if (st != TEBD_OK) return st;
+  if (!gates) return fail(TEBD_ERR_ARG, "argument 2 (gates) is NULL");
+  if (gate_chain_stride < 0)
+    return fail(TEBD_ERR_ARG, "argument 3 (gate_chain_stride) = %lld must be >= 0",
+                (long long)gate_chain_stride);
+  if (parity != 0 && parity != 1)
+    return fail(TEBD_ERR_ARG, "argument 4 (parity) = %d must be 0 or 1", parity);
+  if (!tape) return fail(TEBD_ERR_ARG, "argument 6 (tape) is NULL");
+  if (!gamma_bar) return fail(TEBD_ERR_ARG, "argument 8 (gamma_bar) is NULL");
+  if (!lambda_bar) return fail(TEBD_ERR_ARG, "argument 9 (lambda_bar) is NULL");
+  if (!gate_bar) return fail(TEBD_ERR_ARG, "argument 10 (gate_bar) is NULL");
+  if (!dev_status) return fail(TEBD_ERR_ARG, "argument 11 (dev_status) is NULL");
+  const SweepPlan pl = plan_sweep(*mps_in, *prm);
+  if (reinterpret_cast<uintptr_t>(tape) % 256 != 0)
+    return fail(TEBD_ERR_WORKSPACE, "argument 6 (tape) must be 256-byte aligned");
+  if (tape_bytes < size_t(pl.pmax) * pl.tape_slot)
+    return fail(TEBD_ERR_WORKSPACE, "argument 7 (tape_bytes) = %zu < %zu needed", tape_bytes,
+                size_t(pl.pmax) * pl.tape_slot);
+  if (!workspace) return fail(TEBD_ERR_WORKSPACE, "argument 12 (workspace) is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(TEBD_ERR_WORKSPACE, "argument 12 (workspace) must be 256-byte aligned");
+  if (ws_bytes < pl.total)
+    return fail(TEBD_ERR_WORKSPACE, "argument 13 (ws_bytes) = %zu < %zu needed", ws_bytes,
+                pl.total);
+  AdjCommon c;
+  c.n_chains = mps_in->n_chains;
+  c.n_sites = mps_in->n_sites;
+  c.parity = parity;
+  c.nb = (mps_in->n_sites - parity) / 2;
+  c.nprob = int32_t(int64_t(c.n_chains) * c.nb);
+  c.gate_chain_stride = gate_chain_stride;
+  char* base = reinterpret_cast<char*>(workspace);
+  c.offs = reinterpret_cast<int32_t*>(base + align256(size_t(pl.pmax) * sizeof(AdjProb)));
+  {
+    const int64_t t = (pl.mcap + 63) / 64;
+    c.grid = persistent_grid(int64_t(c.nprob) * t * t * 2);
+  }
+  if (c.nprob == 0) return ok();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = timed(PK_ADJOINT, s, [&]() {
+    return launch_adjoint(reinterpret_cast<AdjProb*>(base), c, *mps_in,
+                          reinterpret_cast<const zt*>(gates), reinterpret_cast<const char*>(tape),
+                          pl.tape_slot, pl.mcap, pl.lcap, reinterpret_cast<zt*>(gamma_bar),
+                          lambda_bar, reinterpret_cast<zt*>(gate_bar), dev_status,
+                          prm->lambda_floor, base + pl.adj_desc_bytes, pl.adj_slab_sz, pl.nchunk,
+                          s);
+  });
+  if (e != hipSuccess) return fail(TEBD_ERR_DEVICE, "HIP error while enqueuing: %s", hipGetErrorString(e));
+  return ok();
 }
 
 }  // extern "C"

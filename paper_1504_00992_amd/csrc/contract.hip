@@ -17,145 +17,70 @@
 // (prefix sums over problems built by k_schedule).  Workgroup i takes the
 // virtual index (i mod 8) * G/8 + i / 8, so the consecutive tiles of one
 // problem, which share operand rows, land on the same XCD and its L2.
-#include "zgemm.hpp"
+#include "loaders.hpp"
+#include "tilequeue.hpp"
 
 namespace tebd {
 
 using Cfg64 = ZCfg<64, 64, 16, 2, 2>;
 
-__device__ __forceinline__ double inv_floor(const double* lam, int idx, double floor_) {
-  if (lam == nullptr) return 1.0;
-  const double v = lam[idx];
-  return v > floor_ ? 1.0 / v : 0.0;
-}
-
-__device__ __forceinline__ int tiles_of(int M, int N) {
-  return (M <= 0 || N <= 0) ? 0 : ((M + 63) / 64) * ((N + 63) / 64);
-}
-
 // Output shape of each contraction kind for problem P (0 x 0 when skipped).
-template <int KIND>
-__device__ __forceinline__ void kind_shape(const Prob& P, int tebd, int& M, int& N) {
-  M = N = 0;
-  if (P.l == 0) return;
-  if (KIND == TK_THETA) {
-    if (tebd) {
-      M = P.dl * P.chi_l;
-      N = P.dr * P.chi_r;
+template <>
+struct TileKinds<Prob> {
+  static constexpr int count = TK_COUNT;
+  __device__ static __forceinline__ void shape(int kind, const Prob& P, int tebd, int& M, int& N) {
+    M = N = 0;
+    if (P.l == 0) return;
+    switch (kind) {
+      case TK_THETA:
+        if (tebd) {
+          M = P.dl * P.chi_l;
+          N = P.dr * P.chi_r;
+        }
+        break;
+      case TK_GATE:
+        if (tebd) {
+          M = P.dl * P.dr;
+          N = P.chi_l * P.chi_r;
+        }
+        break;
+      case TK_SKM:
+        M = P.m;
+        N = P.l;
+        break;
+      case TK_SKN:
+        M = P.n;
+        N = P.l;
+        break;
+      case TK_FORMU:
+        M = P.m;
+        N = tebd ? P.chi_cap : P.kcap;
+        break;
+      case TK_FORMV:
+        M = tebd ? P.chi_cap : P.kcap;
+        N = P.n;
+        break;
+      case TK_TAPEU:
+        if (P.tape_u) {
+          M = P.m;
+          N = P.l;
+        }
+        break;
+      case TK_TAPEV:
+        if (P.tape_u) {
+          M = P.l;
+          N = P.n;
+        }
+        break;
+      default:
+        break;
     }
-  } else if (KIND == TK_GATE) {
-    if (tebd) {
-      M = P.dl * P.dr;
-      N = P.chi_l * P.chi_r;
-    }
-  } else if (KIND == TK_SKM) {
-    M = P.m;
-    N = P.l;
-  } else if (KIND == TK_SKN) {
-    M = P.n;
-    N = P.l;
-  } else if (KIND == TK_FORMU) {
-    M = P.m;
-    N = tebd ? P.chi_cap : P.kcap;
-  } else {
-    M = tebd ? P.chi_cap : P.kcap;
-    N = P.n;
   }
-}
-
-__device__ __forceinline__ int kind_tiles(int kind, const Prob& P, int tebd) {
-  int M, N;
-  switch (kind) {
-    case TK_THETA: kind_shape<TK_THETA>(P, tebd, M, N); break;
-    case TK_GATE: kind_shape<TK_GATE>(P, tebd, M, N); break;
-    case TK_SKM: kind_shape<TK_SKM>(P, tebd, M, N); break;
-    case TK_SKN: kind_shape<TK_SKN>(P, tebd, M, N); break;
-    case TK_FORMU: kind_shape<TK_FORMU>(P, tebd, M, N); break;
-    default: kind_shape<TK_FORMV>(P, tebd, M, N); break;
-  }
-  return tiles_of(M, N);
-}
-
-// Exclusive prefix sums of tile counts for every kind (one workgroup):
-// thread t sums a contiguous chunk of problems, thread 0 scans the chunk
-// sums, then every thread writes its chunk's offsets.
-__global__ __launch_bounds__(256) void k_schedule(const Prob* probs, int nprob, int tebd,
-                                                  int32_t* offs) {
-  __shared__ int32_t part[256];
-  __shared__ int32_t total;
-  const int tid = threadIdx.x;
-  const int chunk = (nprob + 255) / 256;
-  const int p0 = min(nprob, tid * chunk), p1 = min(nprob, p0 + chunk);
-  for (int kind = 0; kind < TK_COUNT; ++kind) {
-    int32_t s = 0;
-    for (int p = p0; p < p1; ++p) s += kind_tiles(kind, probs[p], tebd);
-    part[tid] = s;
-    __syncthreads();
-    if (tid == 0) {
-      int32_t run = 0;
-      for (int i = 0; i < 256; ++i) {
-        const int32_t v = part[i];
-        part[i] = run;
-        run += v;
-      }
-      total = run;
-    }
-    __syncthreads();
-    int32_t* o = offs + size_t(kind) * (nprob + 1);
-    int32_t run = part[tid];
-    for (int p = p0; p < p1; ++p) {
-      o[p] = run;
-      run += kind_tiles(kind, probs[p], tebd);
-    }
-    if (tid == 0) o[nprob] = total;
-    __syncthreads();
-  }
-}
+};
 
 hipError_t launch_schedule(Prob* probs, const Common& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_schedule, dim3(1), dim3(256), 0, s, probs, c.nprob, c.tebd, c.offs);
+  hipLaunchKernelGGL(k_schedule<Prob>, dim3(1), dim3(256), 0, s, probs, c.nprob, c.tebd, c.offs);
   return hipGetLastError();
-}
-
-// Problem owning global tile t: the largest p with off[p] <= t.
-__device__ __forceinline__ int find_problem(const int32_t* off, int nprob, int t) {
-  int lo = 0, hi = nprob;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (off[mid] <= t)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ int virtual_block() {
-  const int g = gridDim.x, i = blockIdx.x;
-  return (i & 7) * (g >> 3) + (i >> 3);
-}
-
-// Iterate over this workgroup's tiles of one kind:
-// body(P, M, N, m0, n0, tile_index_within_problem, tiles_n).
-template <int KIND, class Body>
-__device__ __forceinline__ void for_each_tile(Prob* probs, const int32_t* offs, int nprob,
-                                              int tebd, Body body) {
-  const int32_t* off = offs + size_t(KIND) * (nprob + 1);
-  const int total = off[nprob];
-  for (int t = virtual_block(); t < total; t += gridDim.x) {
-    const int p = find_problem(off, nprob, t);
-    Prob& P = probs[p];
-    int M, N;
-    kind_shape<KIND>(P, tebd, M, N);
-    const int local = t - off[p];
-    // the range finder may have shrunk l since the queue was built: tiles of
-    // the old shape that now lie outside the output are skipped
-    const int tiles_n = (N + 63) / 64;
-    if (tiles_n == 0) continue;
-    const int tm = local / tiles_n, tn = local - tm * tiles_n;
-    if (tm * 64 >= M) continue;
-    body(P, M, N, tm * 64, tn * 64, local);
-  }
 }
 
 // --------------------------------------------------------------------------
@@ -212,39 +137,6 @@ hipError_t launch_omega(Prob* probs, const Common& c, hipStream_t s) {
 
 // --------------------------------------------------------------------------
 // Theta build
-struct LdThetaA {  // (r = i*chi_l + a, k = g)
-  const zt* gk;
-  const double* lam_l;
-  const double* lam_m;
-  int chi_l, cap;
-  static constexpr bool contig_k = true;
-  __device__ zt operator()(int r, int k) const {
-    const int i = r / chi_l, a = r - i * chi_l;
-    double s = lam_m[k];
-    if (lam_l) s *= lam_l[a];
-    return zscale(gk[(size_t(i) * cap + a) * cap + k], s);
-  }
-};
-struct LdThetaB {  // (k = g, c = j*chi_r + b)
-  const zt* gk1;
-  const double* lam_r;
-  int chi_r, cap;
-  static constexpr bool contig_n = true;
-  __device__ zt operator()(int k, int c) const {
-    const int j = c / chi_r, b = c - j * chi_r;
-    const zt v = gk1[(size_t(j) * cap + k) * cap + b];
-    return lam_r ? zscale(v, lam_r[b]) : v;
-  }
-};
-struct StTheta {
-  zt* T;
-  int chi_l, chi_r, dr;
-  __device__ void operator()(int r, int c, zt v) {
-    const int i = r / chi_l, a = r - i * chi_l;
-    const int j = c / chi_r, b = c - j * chi_r;
-    T[(size_t(i) * dr + j) * (size_t(chi_l) * chi_r) + size_t(a) * chi_r + b] = v;
-  }
-};
 
 __global__ __launch_bounds__(256) void k_theta(Prob* probs, const int32_t* offs, int nprob) {
   __shared__ zt smem[Cfg64::lds_elems];
@@ -263,12 +155,6 @@ struct LdGate {
   int ld;
   static constexpr bool contig_k = true;
   __device__ zt operator()(int r, int k) const { return g[size_t(r) * ld + k]; }
-};
-struct LdRowB {  // B[k][c] = p[k*ld + c]
-  const zt* p;
-  int64_t ld;
-  static constexpr bool contig_n = true;
-  __device__ zt operator()(int k, int c) const { return p[size_t(k) * ld + c]; }
 };
 struct StGate {
   zt* A;
@@ -306,29 +192,6 @@ hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s) {
 
 // --------------------------------------------------------------------------
 // Sketch / power iteration / projection products
-struct LdRowA {  // A[r][k] = p[r*ld + k]
-  const zt* p;
-  int64_t ld;
-  static constexpr bool contig_k = true;
-  __device__ zt operator()(int r, int k) const { return p[size_t(r) * ld + k]; }
-};
-struct LdAdjA {  // (r, k) -> conj(p[k*ld + r]): the adjoint of a row-major matrix
-  const zt* p;
-  int64_t ld;
-  static constexpr bool contig_k = false;
-  __device__ zt operator()(int r, int k) const { return zconj(p[size_t(k) * ld + r]); }
-};
-struct LdColB {  // B[k][c] = p[c*ld + k] (column-major)
-  const zt* p;
-  int64_t ld;
-  static constexpr bool contig_n = false;
-  __device__ zt operator()(int k, int c) const { return p[size_t(c) * ld + k]; }
-};
-struct StCol {  // C[r][c] -> p[c*ld + r]
-  zt* p;
-  int64_t ld;
-  __device__ void operator()(int r, int c, zt v) { p[size_t(c) * ld + r] = v; }
-};
 
 template <int WHICH>
 __global__ __launch_bounds__(256) void k_sketch(Prob* probs, const int32_t* offs, int nprob,
@@ -529,6 +392,65 @@ hipError_t launch_form_uv(Prob* probs, const Common& c, hipStream_t s) {
     hipLaunchKernelGGL(k_form_u<0>, g, dim3(256), 0, s, probs, c.offs, c.nprob);
     hipLaunchKernelGGL(k_form_vh<0>, g, dim3(256), 0, s, probs, c.offs, c.nprob);
   }
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Recording for the adjoint: every triplet the RRSVD computed (not only the
+// kept ones) with plain U and V^H (no reabsorption), the singular values and
+// the geometry, written once per bond in the pass that finishes it.
+__global__ __launch_bounds__(256) void k_tape_uv(Prob* probs, const int32_t* offs, int nprob) {
+  __shared__ zt smem[Cfg64::lds_elems];
+  for_each_tile<TK_TAPEU>(probs, offs, nprob, 1, [&](Prob& P, int M, int N, int m0, int n0, int) {
+    if (P.retry) return;
+    LdQ la{P.Y, P.m};
+    LdSmallColB lb{P.X, P.l};
+    StRow st{P.tape_u, P.tape_ldu};
+    zgemm_tile<Cfg64>(M, N, P.l, m0, n0, la, lb, st, smem);
+  });
+  for_each_tile<TK_TAPEV>(probs, offs, nprob, 1, [&](Prob& P, int M, int N, int m0, int n0, int) {
+    if (P.retry) return;
+    LdSmallAdjA la{P.W, P.l};
+    LdQbAdjB lb{P.Yt, P.n};
+    StRow st{P.tape_vh, P.tape_ldvh};
+    zgemm_tile<Cfg64>(M, N, P.l, m0, n0, la, lb, st, smem);
+  });
+}
+
+// One wavefront per problem: header and singular values.  A problem the
+// planner rejected (l = 0 in the first pass) gets an invalid header; in the
+// second pass of the adaptive scheme only re-run problems write.
+__global__ __launch_bounds__(64) void k_tape_meta(Prob* probs, int pass2, int n_sites) {
+  Prob& P = probs[blockIdx.x];
+  if (!P.tape_hdr) return;
+  const int lane = threadIdx.x;
+  const bool done = P.l > 0 && !P.retry;
+  const bool bad = !pass2 && P.l == 0;
+  if (!done && !bad) return;
+  for (int j = lane; j < P.l; j += 64) P.tape_sig[j] = P.sig[j];
+  if (lane == 0) {
+    int32_t* h = P.tape_hdr;
+    h[TH_VALID] = done ? 1 : 0;
+    h[TH_L] = P.l;
+    h[TH_K] = done ? P.chi_new : 0;
+    h[TH_M] = P.m;
+    h[TH_N] = P.n;
+    h[TH_CHI_L] = P.chi_l;
+    h[TH_CHI_M] = P.chi_m;
+    h[TH_CHI_R] = P.chi_r;
+    h[TH_DL] = P.dl;
+    h[TH_DR] = P.dr;
+    h[TH_CHAIN] = P.pid / (n_sites - 1);
+    h[TH_BOND] = P.pid % (n_sites - 1);
+    h[TH_LCAP] = P.tape_ldu;
+  }
+}
+
+hipError_t launch_tape(Prob* probs, const Common& c, hipStream_t s) {
+  hipLaunchKernelGGL(k_tape_uv, dim3(c.grid), dim3(256), 0, s, probs, c.offs, c.nprob);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tape_meta, dim3(c.nprob), dim3(64), 0, s, probs, c.pass2, c.nsites);
   return hipGetLastError();
 }
 

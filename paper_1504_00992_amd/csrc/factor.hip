@@ -22,7 +22,8 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
                              int single_bond, int kcap, int p_over, char* slab_base,
                              size_t slab_sz, int64_t mcap, int64_t ncap, int64_t lcap,
                              int64_t npart_cap, double* disc, int32_t* status,
-                             double lambda_floor, int mixed, int adaptive) {
+                             double lambda_floor, int mixed, int adaptive, char* tape,
+                             size_t tape_stride) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nprob) return;
   const int N = mps.n_sites, cap = mps.chi_max, dmax = mps.d_max;
@@ -98,6 +99,17 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
   P.gate_ld = dmax * dmax;
   P.chi_cap = cap;
   P.lambda_floor = lambda_floor;
+  if (tape) {
+    tape_slot(tape + size_t(p) * tape_stride, mcap, lcap, P.tape_hdr, P.tape_sig, P.tape_u,
+              P.tape_vh);
+    P.tape_ldu = int32_t(lcap);
+    P.tape_ldvh = int32_t(ncap);
+  } else {
+    P.tape_u = P.tape_vh = nullptr;
+    P.tape_sig = nullptr;
+    P.tape_hdr = nullptr;
+    P.tape_ldu = P.tape_ldvh = 0;
+  }
   if (single_chain >= 0) {
     P.disc = disc;
     P.status = status;
@@ -116,14 +128,15 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
                              int64_t gate_chain_stride, int32_t parity, int32_t single_chain,
                              int32_t single_bond, int32_t p_over, char* slab_base,
                              size_t slab_sz, double* disc, int32_t* status, double lambda_floor,
-                             int32_t mixed, int32_t adaptive, hipStream_t s) {
+                             int32_t mixed, int32_t adaptive, char* tape, size_t tape_stride,
+                             hipStream_t s) {
   const int64_t mcap = int64_t(c.dmax) * c.chimax;
   const int64_t lcap = c.lmax;
   const int64_t npart_cap = int64_t((c.dmax * c.dmax + 63) / 64) * ((c.chimax * c.chimax + 63) / 64);
   hipLaunchKernelGGL(k_plan_sweep, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob, mps,
                      gates, gate_chain_stride, parity, single_chain, single_bond, c.kcap, p_over,
                      slab_base, slab_sz, mcap, mcap, lcap, npart_cap, disc, status, lambda_floor,
-                     mixed, adaptive);
+                     mixed, adaptive, tape, tape_stride);
   return hipGetLastError();
 }
 

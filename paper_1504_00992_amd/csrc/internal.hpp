@@ -76,6 +76,12 @@ struct Prob {
   int32_t gate_ld;
   int32_t chi_cap;     // padding capacity of the MPS arrays
   double lambda_floor;
+  // recording for the adjoint (nullptr: not recording)
+  zt* tape_u;          // U of every computed triplet, m x l row-major (ld tape_ldu)
+  zt* tape_vh;         // V^H of every computed triplet, l x n row-major (ld tape_ldvh)
+  double* tape_sig;    // the l singular values
+  int32_t* tape_hdr;   // TH_* fields
+  int32_t tape_ldu, tape_ldvh;
 };
 
 // Parameters of a launch sequence that are common to all problems.
@@ -94,6 +100,8 @@ struct Common {
   int32_t adaptive;  // two-stage adaptive rank (TEBD only)
   int32_t pass2;     // 1: second (fixed-rank) pass of the adaptive scheme
   int32_t mixed;     // 1: complex FP32 sketch and power-iteration products
+  int32_t record;    // 1: write the adjoint's tape
+  int32_t nsites;    // TEBD: sites per chain
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
 };
@@ -107,7 +115,9 @@ enum {
   TK_SKN = 3,    // n x l products (A^H Q)
   TK_FORMU = 4,  // m x (kept capacity)
   TK_FORMV = 5,  // (kept capacity) x n
-  TK_COUNT = 6
+  TK_TAPEU = 6,  // recording: m x l, U of every computed triplet
+  TK_TAPEV = 7,  // recording: l x n, V^H of every computed triplet
+  TK_COUNT = 8
 };
 
 inline size_t sched_bytes(int64_t nprob) { return size_t(TK_COUNT) * size_t(nprob + 1) * sizeof(int32_t); }
@@ -119,7 +129,8 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
                              int64_t gate_chain_stride, int32_t parity, int32_t single_chain,
                              int32_t single_bond, int32_t p_over, char* slab_base,
                              size_t slab_bytes, double* disc, int32_t* status, double lambda_floor,
-                             int32_t mixed, int32_t adaptive, hipStream_t s);
+                             int32_t mixed, int32_t adaptive, char* tape, size_t tape_stride,
+                             hipStream_t s);
 hipError_t launch_stage2(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_schedule(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s);
@@ -131,6 +142,7 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStr
 hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_truncate(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_form_uv(Prob* probs, const Common& c, hipStream_t s);
+hipError_t launch_tape(Prob* probs, const Common& c, hipStream_t s);
 
 // Sketch-product selectors for launch_sketch.
 enum {
@@ -198,6 +210,119 @@ __host__ __device__ inline void carve_slab(Prob& p, char* base, int64_t m, int64
   p.Af = nullptr;
   p.Yf = nullptr;
 }
+
+// ---------------------------------------------------------------------------
+// Tape of one recorded sweep: one fixed-size slot per problem, in the order
+// of the sweep's problems (chain-major, bonds of the parity ascending).
+// Slot: 256-byte header of int32 TH_* fields, the l singular values, U
+// (mcap x lcap row-major), V^H (lcap x ncap row-major).
+enum {
+  TH_VALID = 0,  // 1: the slot holds a finished bond update
+  TH_L,          // triplets computed (sketch width after the range finder)
+  TH_K,          // triplets kept (chi')
+  TH_M,
+  TH_N,
+  TH_CHI_L,
+  TH_CHI_M,      // bond dimension before the update
+  TH_CHI_R,
+  TH_DL,
+  TH_DR,
+  TH_CHAIN,
+  TH_BOND,
+  TH_LCAP,
+  TH_COUNT
+};
+
+__host__ __device__ inline size_t tape_slot_bytes(int64_t mcap, int64_t ncap, int64_t lcap) {
+  return 256 + align256(size_t(lcap) * sizeof(double)) + align256(size_t(mcap * lcap) * sizeof(zt)) +
+         align256(size_t(lcap * ncap) * sizeof(zt));
+}
+__host__ __device__ inline void tape_slot(char* base, int64_t mcap, int64_t lcap, int32_t*& hdr,
+                                          double*& sig, zt*& u, zt*& vh) {
+  hdr = reinterpret_cast<int32_t*>(base);
+  sig = reinterpret_cast<double*>(base + 256);
+  u = reinterpret_cast<zt*>(base + 256 + align256(size_t(lcap) * sizeof(double)));
+  vh = u + align256(size_t(mcap * lcap) * sizeof(zt)) / sizeof(zt);
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of one bond update (reverse mode), per problem.
+struct AdjProb {
+  int32_t m, n, L, k;              // blocked matrix, triplets computed / kept
+  int32_t chi_l, chi_m, chi_r, dl, dr;
+  int32_t nchunk;                  // K-chunks of the gate cotangent product
+  int32_t chain, bond;
+  int32_t ldu, ldvh, ldl, chi_cap, gate_ld, dmax;
+  double lambda_floor, eta;        // eta: broadening of 1/(s_j^2 - s_i^2)
+  // tape of the recorded update
+  const zt* U;                     // m x L (ld ldu)
+  const zt* VH;                    // L x n (ld ldvh)
+  const double* sig;               // L, descending
+  // state before the update
+  const zt* gk;
+  const zt* gk1;
+  const double* lam_l;             // nullptr at the chain edge (1)
+  const double* lam_m;
+  const double* lam_r;             // nullptr at the chain edge (1)
+  const zt* gate;
+  // cotangents (in: of the update's outputs; out: of its inputs)
+  zt* gbk;
+  zt* gbk1;
+  double* lbar_m;
+  zt* gate_bar;
+  int32_t* status;
+  // scratch
+  double* sbar;                    // L
+  double* sinv;                    // L
+  double* lamL;                    // chi_l: contribution to the cotangent of lambda_l
+  double* lamR;                    // chi_r
+  zt* M1;                          // L x k: U^H Ubar        (ld ldl)
+  zt* M2;                          // L x k: V^H Vbar        (ld ldl)
+  zt* D;                           // L x L core matrix      (ld ldl)
+  zt* X;                           // m x L: U D + Ubar S^-1 (ld ldl)
+  zt* AbT;                         // Abar as [(i j)][(a c)]
+  zt* T;                           // Theta as [(i j)][(a c)]
+  zt* Thb;                         // Theta-bar, blocked [(i a)][(j c)]
+  zt* R1;                          // m x chi_m (ld chi_cap)
+  zt* R2;                          // chi_m x n (ld ldvh)
+  zt* gpart;                       // nchunk x (dl dr)^2 partial gate cotangents
+};
+
+enum {
+  TA_M1 = 0,     // L x k
+  TA_M2 = 1,     // L x k
+  TA_THETA = 2,  // (dl chi_l) x (dr chi_r)
+  TA_X = 3,      // m x L
+  TA_ABAR = 4,   // m x n
+  TA_GADJ = 5,   // (dl dr) x (chi_l chi_r)
+  TA_GBAR = 6,   // per K-chunk: (dl dr) x (dl dr), chunks stacked on 64-row boundaries
+  TA_R1 = 7,     // m x chi_m
+  TA_R2 = 8,     // chi_m x n
+  TA_COUNT = 9
+};
+constexpr int kGateChunk = 1024;  // K-chunk of the gate cotangent product
+
+struct AdjCommon {
+  int32_t nprob;
+  int32_t n_chains, n_sites, parity, nb;
+  int64_t gate_chain_stride;
+  int32_t* offs;
+  int32_t grid;
+};
+
+__host__ __device__ inline size_t adj_slab_bytes(int64_t mcap, int64_t ncap, int64_t lcap,
+                                                 int64_t chicap, int64_t d2, int64_t nchunk) {
+  const size_t z = sizeof(zt), d = sizeof(double);
+  return 2 * align256(lcap * d) + 2 * align256(chicap * d) + 3 * align256(lcap * lcap * z) +
+         align256(mcap * lcap * z) + 3 * align256(mcap * ncap * z) + align256(mcap * chicap * z) +
+         align256(chicap * ncap * z) + align256(nchunk * d2 * d2 * z);
+}
+
+hipError_t launch_adjoint(AdjProb* probs, const AdjCommon& c, const tebd_mps& mps_in,
+                          const zt* gates, const char* tape, size_t slot_bytes, int64_t mcap,
+                          int64_t lcap, zt* gamma_bar, double* lambda_bar, zt* gate_bar,
+                          int32_t* status, double lambda_floor, char* slab_base, size_t slab_sz,
+                          int64_t nchunk_cap, hipStream_t s);
 
 // Largest l (sketch width) and m supported by the factorisation kernels.
 constexpr int kMaxL = 256;

@@ -1,0 +1,113 @@
+// Persistent tile queues over batches of problems whose sizes live on the
+// device.
+//
+// Every contraction kind k has, per batch, an exclusive prefix sum over
+// problems of its 64 x 64 output-tile counts (offs[k][p], offs[k][nprob] =
+// total), built on the device by k_schedule.  A persistent launch then walks
+// the global tile index t = vb, vb + G, ... where vb = (i mod 8) * G/8 + i / 8
+// for workgroup i of G: consecutive tiles of one problem, which share
+// operand rows, are taken by workgroups of the same XCD and hit its L2.
+//
+// A descriptor type PT plugs in through TileKinds<PT>:
+//   static constexpr int count;   number of kinds
+//   static __device__ void shape(int kind, const PT&, int flag, int& M, int& N);
+// (M x N = 0 x 0 when the problem has no tiles of that kind).
+#pragma once
+
+#include "zdev.hpp"
+
+namespace tebd {
+
+template <class PT>
+struct TileKinds;
+
+__device__ __forceinline__ int tiles_of(int M, int N) {
+  return (M <= 0 || N <= 0) ? 0 : ((M + 63) / 64) * ((N + 63) / 64);
+}
+
+template <class PT>
+__device__ __forceinline__ int kind_tiles(int kind, const PT& P, int flag) {
+  int M, N;
+  TileKinds<PT>::shape(kind, P, flag, M, N);
+  return tiles_of(M, N);
+}
+
+// Exclusive prefix sums of tile counts for every kind (one workgroup):
+// thread t sums a contiguous chunk of problems, thread 0 scans the chunk
+// sums, then every thread writes its chunk's offsets.
+template <class PT>
+__global__ __launch_bounds__(256) void k_schedule(const PT* probs, int nprob, int flag,
+                                                  int32_t* offs) {
+  __shared__ int32_t part[256];
+  __shared__ int32_t total;
+  const int tid = threadIdx.x;
+  const int chunk = (nprob + 255) / 256;
+  const int p0 = min(nprob, tid * chunk), p1 = min(nprob, p0 + chunk);
+  for (int kind = 0; kind < TileKinds<PT>::count; ++kind) {
+    int32_t s = 0;
+    for (int p = p0; p < p1; ++p) s += kind_tiles(kind, probs[p], flag);
+    part[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+      int32_t run = 0;
+      for (int i = 0; i < 256; ++i) {
+        const int32_t v = part[i];
+        part[i] = run;
+        run += v;
+      }
+      total = run;
+    }
+    __syncthreads();
+    int32_t* o = offs + size_t(kind) * (nprob + 1);
+    int32_t run = part[tid];
+    for (int p = p0; p < p1; ++p) {
+      o[p] = run;
+      run += kind_tiles(kind, probs[p], flag);
+    }
+    if (tid == 0) o[nprob] = total;
+    __syncthreads();
+  }
+}
+
+// Problem owning global tile t: the largest p with off[p] <= t.
+__device__ __forceinline__ int find_problem(const int32_t* off, int nprob, int t) {
+  int lo = 0, hi = nprob;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= t)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int virtual_block() {
+  const int g = gridDim.x, i = blockIdx.x;
+  return (i & 7) * (g >> 3) + (i >> 3);
+}
+
+// Iterate over this workgroup's tiles of one kind:
+// body(P, M, N, m0, n0, tile_index_within_problem).
+template <int KIND, class PT, class Body>
+__device__ __forceinline__ void for_each_tile(PT* probs, const int32_t* offs, int nprob, int flag,
+                                              Body body) {
+  const int32_t* off = offs + size_t(KIND) * (nprob + 1);
+  const int total = off[nprob];
+  for (int t = virtual_block(); t < total; t += gridDim.x) {
+    const int p = find_problem(off, nprob, t);
+    PT& P = probs[p];
+    int M, N;
+    TileKinds<PT>::shape(KIND, P, flag, M, N);
+    const int local = t - off[p];
+    // a size may have shrunk since the queue was built (the range finder
+    // lowers l): tiles of the old shape that now lie outside are skipped
+    const int tiles_n = (N + 63) / 64;
+    if (tiles_n == 0) continue;
+    const int tm = local / tiles_n, tn = local - tm * tiles_n;
+    if (tm * 64 >= M) continue;
+    body(P, M, N, tm * 64, tn * 64, local);
+  }
+}
+
+}  // namespace tebd

@@ -167,3 +167,60 @@ def test_product_gates_match_oracle_gates():
         assert np.allclose(a, b, atol=1e-14)
     for a, b in zip(om.tfim(6, 0.8, 1.1)[1], pm.transverse_ising(6, 0.8, 1.1)[1]):
         assert np.allclose(a, b, atol=1e-14)
+
+
+def test_adjoint_entry_points_validate_before_enqueue():
+    prm = _lib.params(8)
+    mps = _mps_struct()
+    f = 0x100000
+    tb = _lib.tebd_tape_size(mps, prm)
+    assert tb > 0
+    need = _lib.tebd_workspace_size(prm, mps=mps)
+    lib = _lib.load()
+
+    def rec(**kw):
+        a = dict(gates=f, parity=0, tape=f, tape_bytes=tb, ws=f, ws_bytes=need)
+        a.update(kw)
+        return _lib.tebd_sweep_record(mps, a["gates"], 0, a["parity"], prm, f, f, a["tape"],
+                                      a["tape_bytes"], a["ws"], a["ws_bytes"], None)
+    assert rec(tape=None) == _lib.TEBD_ERR_ARG and "tape" in _lib.tebd_last_error()
+    assert rec(tape=f + 8) == _lib.TEBD_ERR_WORKSPACE
+    assert rec(tape_bytes=tb - 1) == _lib.TEBD_ERR_WORKSPACE
+    assert rec(parity=3) == _lib.TEBD_ERR_ARG
+
+    def adj(**kw):
+        a = dict(tape=f, tape_bytes=tb, gb=f, lb=f, gbar=f, status=f, ws=f, ws_bytes=need,
+                 parity=1)
+        a.update(kw)
+        return _lib.tebd_sweep_adjoint(mps, f, 0, a["parity"], prm, a["tape"], a["tape_bytes"],
+                                       a["gb"], a["lb"], a["gbar"], a["status"], a["ws"],
+                                       a["ws_bytes"], None)
+    assert adj(tape=None) == _lib.TEBD_ERR_ARG
+    assert adj(gb=None) == _lib.TEBD_ERR_ARG and "gamma_bar" in _lib.tebd_last_error()
+    assert adj(lb=None) == _lib.TEBD_ERR_ARG and "lambda_bar" in _lib.tebd_last_error()
+    assert adj(gbar=None) == _lib.TEBD_ERR_ARG and "gate_bar" in _lib.tebd_last_error()
+    assert adj(status=None) == _lib.TEBD_ERR_ARG
+    assert adj(tape_bytes=16) == _lib.TEBD_ERR_WORKSPACE
+    assert adj(ws_bytes=need - 1) == _lib.TEBD_ERR_WORKSPACE
+    assert adj(ws=f + 8) == _lib.TEBD_ERR_WORKSPACE
+    assert adj(parity=-1) == _lib.TEBD_ERR_ARG
+    # the tape grows with the chain batch; the workspace covers the adjoint too
+    assert _lib.tebd_tape_size(_mps_struct(n_chains=4), prm) == 2 * tb
+    del lib
+
+
+def test_propagator_derivative_matches_finite_differences():
+    from paper_1504_00992_amd import gradient, models as pm
+    gen = np.random.default_rng(4)
+    h = gen.standard_normal((4, 4)) + 1j * gen.standard_normal((4, 4))
+    h = h + h.conj().T
+    h[0, 0] = h[1, 1]  # a near-degenerate pair is handled
+    dh = gen.standard_normal((4, 4)) + 1j * gen.standard_normal((4, 4))
+    dh = dh + dh.conj().T
+    tau = 0.37
+    got = gradient.propagator_derivative(h, tau, dh)
+    fd = (pm.propagator(h + 1e-6 * dh, tau) - pm.propagator(h - 1e-6 * dh, tau)) / 2e-6
+    assert np.max(np.abs(got - fd)) < 1e-9
+    gbar = gen.standard_normal((4, 4)) + 1j * gen.standard_normal((4, 4))
+    assert gradient.coupling_gradient(gbar, h, tau, dh) == pytest.approx(
+        float(np.real(np.sum(gbar.conj() * fd))), abs=1e-8)

@@ -102,6 +102,22 @@ def random_vidal_bond(dl, dr, chi_l, chi_m, chi_r, gen, decay=0.3):
     return gk, gk1, lam(chi_l), lam(chi_m), lam(chi_r)
 
 
+def random_vidal_chain(dims, chis, gen, decay=0.3):
+    """Random Gammas and lambdas of one chain with bond dimensions chis.
+
+    chis has length N + 1 with chis[0] = chis[N] = 1.  Gammas are complex
+    Gaussian of shape (d_k, chi_k, chi_k+1); each lambda is positive,
+    decreasing and unit-norm (exp(-decay * i)).  No canonical form.
+    """
+    gammas = [ginibre(d * chis[k], chis[k + 1], gen).reshape(d, chis[k], chis[k + 1])
+              for k, d in enumerate(dims)]
+    lambdas = []
+    for b in range(len(dims) - 1):
+        v = np.exp(-decay * np.arange(chis[b + 1]))
+        lambdas.append(v / np.linalg.norm(v))
+    return gammas, lambdas
+
+
 def random_unitary(n, gen):
     """n x n Haar unitary (used as a generic two-site gate)."""
     return haar_isometry(n, n, gen)
