@@ -1,10 +1,13 @@
 """GPU parity of the reverse mode (tebd_sweep_record / tebd_sweep_adjoint).
 
 * One sweep: the cotangents of every Gamma and lambda and of every gate,
-  for random states, gates and output cotangents, against the oracle's
-  ``bond_adjoint`` applied to the oracle's own step-by-step RRSVD of the same
-  bonds (same Philox test matrices): element by element, 1e-9 relative to
-  the largest entry of each array; padding exactly zero.
+  for random states and gates, against the oracle's ``bond_adjoint``
+  applied to the oracle's own step-by-step RRSVD of the same bonds (same
+  Philox test matrices): element by element, 1e-9 relative to the largest
+  entry of each array; padding exactly zero.  The output cotangents come
+  from a loss that does not depend on the phase of a singular pair,
+  evaluated on each side's own result (the two sides may choose different
+  phases; a real observable never sees them).
 * Whole runs of the XX chain with random fields: d<Z_0(T)>/dJ_b against the
   oracle's reverse mode over the same algorithm (1e-9), and, at N = 40 with
   50 steps, against the stored references of tests/golden (reverse mode
@@ -47,6 +50,43 @@ def _gate_stack(dims, gen):
     return gates, stack
 
 
+def _loss_weights(dims, chis, gen):
+    """Random weights of a loss that does not depend on the phase of any
+    singular pair: sum_k W_k o |Gamma_k|^2 + sum_b w_b . lambda_b
+    + sum_b Re <V_b, Theta_b> with Theta_b the two-site block of bond b, for
+    the bonds of the sweep (their outer bonds keep their gauge)."""
+    n = len(dims)
+    w_gam = [gen.standard_normal((d, chis[k], chis[k + 1])) for k, d in enumerate(dims)]
+    w_lam = [gen.standard_normal(chis[b + 1]) for b in range(n - 1)]
+    w_th = [wl.ginibre(dims[b] * chis[b], dims[b + 1] * chis[b + 2], gen)
+            for b in range(n - 1)]
+    return w_gam, w_lam, w_th
+
+
+def _loss_cotangents(gammas, lambdas, weights, parity):
+    """Cotangents of that loss (torch CPU autograd) at the given state."""
+    w_gam, w_lam, w_th = weights
+    n = len(gammas)
+    gs = [torch.tensor(np.array(g), requires_grad=True) for g in gammas]
+    ls = [torch.tensor(np.array(l), requires_grad=True) for l in lambdas]
+    one = torch.ones(1, dtype=torch.float64)
+    loss = torch.zeros((), dtype=torch.float64)
+    for k in range(n):
+        loss = loss + (torch.from_numpy(w_gam[k]) * gs[k].abs() ** 2).sum()
+    for b in range(n - 1):
+        loss = loss + (torch.from_numpy(w_lam[b]) * ls[b]).sum()
+        if b % 2 != parity:
+            continue
+        ll = ls[b - 1] if b >= 1 else one
+        lr = ls[b + 1] if b + 1 <= n - 2 else one
+        th = torch.einsum("a,iag,g,jgc,c->iajc", ll.to(torch.complex128), gs[b],
+                          ls[b].to(torch.complex128), gs[b + 1], lr.to(torch.complex128))
+        th = th.reshape(w_th[b].shape)
+        loss = loss + (torch.from_numpy(w_th[b]).conj() * th).real.sum()
+    loss.backward()
+    return [g.grad.numpy().copy() for g in gs], [l.grad.numpy().copy() for l in ls]
+
+
 def _rel(a, b):
     scale = max(np.max(np.abs(b)), 1e-300)
     return float(np.max(np.abs(a - b)) / scale)
@@ -80,14 +120,17 @@ def test_sweep_adjoint_matches_oracle(dims, chis, parity, chi_max, p, adaptive):
                                       ws.ptr, ws.nbytes, api._stream()))
     torch.cuda.synchronize()
     after = dev.chi[0].cpu().numpy()
-    # random cotangents of the state after the sweep (valid regions only)
+    # cotangents of a gauge-invariant loss of the state after the sweep,
+    # evaluated on each side's own state
+    g_gam, g_lam = dev.to_host(0)
+    weights = _loss_weights(dims, after, gen)
+    gbar_g, lbar_g = _loss_cotangents(g_gam, g_lam, weights, parity)
     cg = np.zeros(tuple(dev.gamma.shape), dtype=np.complex128)
     cl = np.zeros(tuple(dev.lam.shape), dtype=np.float64)
     for k, d in enumerate(dims):
-        cg[0, k, :d, :after[k], :after[k + 1]] = wl.ginibre(d * after[k], after[k + 1],
-                                                            gen).reshape(d, after[k], after[k + 1])
+        cg[0, k, :d, :after[k], :after[k + 1]] = gbar_g[k]
     for b in range(n - 1):
-        cl[0, b, :after[b + 1]] = gen.standard_normal(after[b + 1])
+        cl[0, b, :after[b + 1]] = lbar_g[b]
     gbar = torch.from_numpy(cg).cuda()
     lbar = torch.from_numpy(cl).cuda()
     gate_bar = torch.zeros_like(gd)
@@ -101,9 +144,6 @@ def test_sweep_adjoint_matches_oracle(dims, chis, parity, chi_max, p, adaptive):
     torch.cuda.synchronize()
     # oracle: the same bond updates, then bond_adjoint on each
     ref = omps.MPS(gam, lam)
-    exp_g = [cg[0, k, :d, :after[k], :after[k + 1]].copy() for k, d in enumerate(dims)]
-    exp_l = [cl[0, b, :after[b + 1]].copy() for b in range(n - 1)]
-    exp_gate = {}
     method = "rrsvd_adaptive" if adaptive else "rrsvd"
     recs = []
     for b in range(parity, n - 1, 2):
@@ -113,6 +153,11 @@ def test_sweep_adjoint_matches_oracle(dims, chis, parity, chi_max, p, adaptive):
             return philox.gaussian_omega(ncol, l, SEED, b, sid)
         recs.append(oa.recorded_bond_update(ref, b, gates[b], chi_max, eps, method, omega_of, 2,
                                             p))
+    assert ref.chis() == list(after)
+    exp_g, exp_l = _loss_cotangents(ref.gammas, ref.lambdas, weights, parity)
+    cot_g = [x.copy() for x in exp_g]
+    cot_l = [x.copy() for x in exp_l]
+    exp_gate = {}
     for rec in recs:
         b = rec["b"]
         assert rec["chi"] == after[b + 1], (b, rec["chi"], after[b + 1])
@@ -125,9 +170,7 @@ def test_sweep_adjoint_matches_oracle(dims, chis, parity, chi_max, p, adaptive):
         b = rec["b"]
         out = oa.bond_adjoint(rec["gk"], rec["gk1"], rec["lam_l"], rec["lam_m"], rec["lam_r"],
                               rec["gate"], rec["u"], rec["s"], rec["vh"], rec["chi"],
-                              cg[0, b, :dims[b], :after[b], :after[b + 1]],
-                              cg[0, b + 1, :dims[b + 1], :after[b + 1], :after[b + 2]],
-                              cl[0, b, :after[b + 1]])
+                              cot_g[b], cot_g[b + 1], cot_l[b])
         if b >= 1:
             exp_l[b - 1] = exp_l[b - 1] + out["lam_l_bar"]
         if b + 1 <= n - 2:
