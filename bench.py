@@ -17,7 +17,15 @@ The JSON line also carries:
 * full_svd   -- the same TEBD steps with the vendor full SVD
                 (torch.linalg.svd) in a torch-only comparator on this GPU;
 * batched_rrsvd -- the 256-matrix standalone RRSVD workload (sizes
-                256..2048, s_i = exp(-i/25), k = 64, p = 10, q = 2).
+                256..2048, s_i = exp(-i/25), k = 64, p = 10, q = 2);
+* mixed_precision -- the spin-boson workload at chi_max = 128 with the
+                sketch and power-iteration GEMMs in complex FP32, beside the
+                FP64 path on the same inputs (errors of lambda and <sigma_z>);
+* adjoint    -- d<Z_0(T)>/dJ_b of the XX chain with random fields (N = 40,
+                chi_max = 64, 50 steps of dt = 0.02, checkpoints every 10
+                steps): time per gradient and its error against the stored
+                references (exact-SVD reverse mode, central differences,
+                free fermions).
 """
 import argparse
 import json
@@ -46,6 +54,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full-svd", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--mixed-steps", type=int, default=100)
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--rank", choices=("adaptive", "fixed"), default="adaptive",
                     help="rank of the timed run: two-stage adaptive (k1 from the bond dimension, "
                          "k = chi_max when needed) or fixed k = chi_max")
@@ -293,6 +304,104 @@ def batched_rrsvd(torch, api, wl):
             "phase_ms_per_batch": {k: round(v[0] / reps, 3) for k, v in prof.items()}}
 
 
+def _spin_z(torch, gamma, lam, chains):
+    from paper_1504_00992_amd import gradient
+    z = torch.zeros((gamma.shape[2], gamma.shape[2]), dtype=torch.complex128, device="cuda")
+    z[0, 0], z[1, 1] = 1.0, -1.0
+    return [float(gradient.expectation(gamma[c], lam[c], z, 0).item()) for c in range(chains)]
+
+
+def mixed_precision(args, torch, api, models):
+    """Spin-boson chains at chi_max = 128: complex FP32 sketch / power GEMMs
+    (precision = 1) against the FP64 path on the same inputs and seeds."""
+    import numpy as np
+    N, d, chi_max, steps = 100, 10, 128, args.mixed_steps
+    dims, hb = models.spin_boson(N, d, 1.0, 0.5, 1.0, 0.5)
+    out = {}
+    for prec in (0, 1):
+        mps = api.DeviceMPS.product_state(args.chains, dims, [0] * N, chi_max)
+        drv = api.TEBD(mps, hb, 0.05, chi_max, p=10, q=2, trunc_eps=1e-10, seed=1504,
+                       precision=prec, adaptive=1)
+        for _ in range(min(args.warmup, 2)):
+            drv.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            drv.step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out[prec] = dict(sec=t1 - t0, chi=mps.chi.cpu().numpy(), lam=mps.lam.cpu().numpy(),
+                         z=_spin_z(torch, mps.gamma, mps.lam, args.chains))
+    same = bool(np.array_equal(out[0]["chi"], out[1]["chi"]))
+    lam_err = float(np.max(np.abs(out[0]["lam"] - out[1]["lam"]))) if same else None
+    z_err = float(np.max(np.abs(np.array(out[0]["z"]) - np.array(out[1]["z"]))))
+    per = updates_per_step(N) * args.chains * steps
+    return {"config": {"workload": f"{args.chains} spin-boson chains N=100 d=10, chi_max=128, "
+                                   f"dt=0.05, {steps} steps after warm-up, adaptive rank"},
+            "mixed_value": round(per / out[1]["sec"], 2), "fp64_value": round(per / out[0]["sec"], 2),
+            "unit": "bond updates/s",
+            "bond_dims_identical": same,
+            "max_abs_lambda_diff": lam_err,
+            "max_abs_sigma_z_diff": z_err,
+            "reference": "the FP64 path on the same inputs (its own parity with the CPU oracle "
+                         "is checked in the GPU tests)"}
+
+
+def adjoint_gradient(torch, api, models, wl, reps=3):
+    """Time per gradient of <Z_0(T)> w.r.t. the 39 couplings (XX + fields, N=40)."""
+    import numpy as np
+    from paper_1504_00992_amd import gradient
+    n, steps, dt, chi_max = 40, 50, 0.02, 64
+    J, h = wl.xx_couplings(n, seed=1504)
+    dims, hb = models.xx_chain(J, h)
+    hop = 0.5 * (np.kron(models.PAULI_X, models.PAULI_X) + np.kron(models.PAULI_Y, models.PAULI_Y))
+    g_half = torch.from_numpy(models.gate_stack(dims, hb, 0.5 * dt)).cuda()
+    g_full = torch.from_numpy(models.gate_stack(dims, hb, dt)).cuda()
+    z = torch.tensor([[1.0, 0.0], [0.0, -1.0]], dtype=torch.complex128, device="cuda")
+    timings = []
+    grad = None
+    for rep in range(reps + 1):
+        mps = api.DeviceMPS.product_state(1, dims, wl.neel_levels(n), chi_max)
+        drv = gradient.CheckpointedTEBD(mps, g_half, g_full, chi_max, 10, 2, 1e-10, 1504,
+                                        adaptive=1, checkpoint=10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        drv.forward(steps)
+        gam = mps.gamma[0].clone().requires_grad_(True)
+        lam = mps.lam[0].clone().requires_grad_(True)
+        val = gradient.expectation(gam, lam, z, 0)
+        val.backward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gb = torch.zeros_like(mps.gamma)
+        lb = torch.zeros_like(mps.lam)
+        gb[0] = gam.grad
+        lb[0] = lam.grad
+        gh, gf, _, _ = drv.backward(gb, lb)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        gh, gf = gh.cpu().numpy(), gf.cpu().numpy()
+        grad = np.array([gradient.coupling_gradient(gh[b], hb[b], 0.5 * dt, hop)
+                         + gradient.coupling_gradient(gf[b], hb[b], dt, hop) for b in range(n - 1)])
+        t3 = time.perf_counter()
+        if rep > 0:  # the first is a warm-up
+            timings.append((t1 - t0, t2 - t1, t3 - t2))
+    ref = np.loadtxt(os.path.join(ROOT, "tests", "golden", "xx_n40_gradient.txt"))
+    scale = float(np.max(np.abs(ref[:, 3])))
+    fw, bw, host = (float(np.median([t[i] for t in timings])) for i in range(3))
+    return {"config": {"workload": "XX chain + random fields, N=40, J_b~U[0.8,1.2], h_i~U[-1,1], "
+                                   "Neel start, 50 steps dt=0.02, chi_max=64, w<=1e-10, "
+                                   "checkpoint every 10 steps; gradient of <Z_0(T=1)> w.r.t. "
+                                   "all 39 J_b"},
+            "ms_per_gradient": round(1e3 * (fw + bw + host), 2),
+            "forward_ms": round(1e3 * fw, 2), "reverse_ms": round(1e3 * bw, 2),
+            "host_frechet_ms": round(1e3 * host, 2),
+            "rel_err_vs_exact_svd_reverse": float(np.max(np.abs(grad - ref[:, 2])) / scale),
+            "rel_err_vs_finite_differences": float(np.max(np.abs(grad - ref[:, 3])) / scale),
+            "rel_err_vs_free_fermions": float(np.max(np.abs(grad - ref[:, 4])) / scale),
+            "note": "errors relative to max|dL/dJ_b|; references in tests/golden/xx_n40_gradient.txt"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -361,6 +470,10 @@ def main():
         line["speedup_vs_full_svd"] = round(value / fval, 3) if fval else None
     if not args.no_batched:
         line["batched_rrsvd"] = batched_rrsvd(torch, api, wl)
+    if not args.no_mixed:
+        line["mixed_precision"] = mixed_precision(args, torch, api, models)
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_gradient(torch, api, models, wl)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_oracle_baseline(args, res["dims"], args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -122,9 +122,9 @@ const char* tebd_last_error(void);
 const char* tebd_version(void);
 
 /* Bytes of workspace needed.
- *  - For tebd_bond_update / tebd_sweep / tebd_sweep_record /
- *    tebd_sweep_adjoint: pass mps (non-NULL), batch = 0, m = n = NULL.  The
- *    size covers one sweep (or its adjoint) over every chain.
+ *  - For tebd_bond_update / tebd_sweep / tebd_sweep_record: pass mps
+ *    (non-NULL), batch = 0, m = n = NULL.  The size covers one sweep over
+ *    every chain.  (tebd_sweep_adjoint: tebd_adjoint_workspace_size.)
  *  - For rrsvd_truncate: pass mps = NULL, the batch size and the host arrays
  *    m[batch], n[batch].
  * Returns TEBD_ERR_ARG / TEBD_ERR_SHAPE for invalid input. */
@@ -209,6 +209,11 @@ tebd_status tebd_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate_ch
  * A time step is replayed sweep by sweep with tebd_sweep_record, which keeps
  * a copy of the state before each sweep (made by the caller) and the tape,
  * then undone in reverse order with tebd_sweep_adjoint. */
+
+/* Bytes of workspace for tebd_sweep_adjoint on `mps` under `prm`; a
+ * workspace of this size also serves tebd_sweep and tebd_sweep_record. */
+tebd_status tebd_adjoint_workspace_size(const tebd_mps* mps, const tebd_params* prm,
+                                        size_t* bytes);
 
 /* Bytes of the tape of one recorded sweep of `mps` under `prm` (either
  * parity). */

@@ -27,7 +27,7 @@ DEV_BAD_STATE = 32
 DEV_RANK_RETRY = 64
 
 EXPORTED = ("tebd_last_error", "tebd_version", "tebd_workspace_size", "rrsvd_truncate",
-            "tebd_bond_update", "tebd_sweep", "tebd_tape_size", "tebd_sweep_record",
+            "tebd_bond_update", "tebd_sweep", "tebd_adjoint_workspace_size", "tebd_tape_size", "tebd_sweep_record",
             "tebd_sweep_adjoint", "tebd_profile_enable", "tebd_profile_read")
 
 
@@ -81,6 +81,9 @@ def load():
     lib.tebd_sweep.restype = ctypes.c_int
     lib.tebd_sweep.argtypes = [ctypes.POINTER(TebdMps), vp, i64, i32, ctypes.POINTER(TebdParams),
                                vp, vp, vp, sz, vp]
+    lib.tebd_adjoint_workspace_size.restype = ctypes.c_int
+    lib.tebd_adjoint_workspace_size.argtypes = [ctypes.POINTER(TebdMps), ctypes.POINTER(TebdParams),
+                                                ctypes.POINTER(sz)]
     lib.tebd_tape_size.restype = ctypes.c_int
     lib.tebd_tape_size.argtypes = [ctypes.POINTER(TebdMps), ctypes.POINTER(TebdParams),
                                    ctypes.POINTER(sz)]
@@ -168,6 +171,13 @@ def tebd_sweep(mps, gates_ptr, gate_chain_stride, parity, prm, disc_ptr, status_
     lib = load()
     return lib.tebd_sweep(ctypes.byref(mps), gates_ptr, int(gate_chain_stride), int(parity),
                           ctypes.byref(prm), disc_ptr, status_ptr, ws_ptr, int(ws_bytes), stream)
+
+
+def tebd_adjoint_workspace_size(mps, prm):
+    out = ctypes.c_size_t(0)
+    check(load().tebd_adjoint_workspace_size(ctypes.byref(mps), ctypes.byref(prm),
+                                             ctypes.byref(out)))
+    return out.value
 
 
 def tebd_tape_size(mps, prm):

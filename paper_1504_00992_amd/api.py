@@ -143,10 +143,14 @@ class DeviceMPS:
 
 
 class BondWorkspace:
-    """Workspace and per-bond outputs sized for sweeps over one DeviceMPS."""
+    """Workspace and per-bond outputs sized for sweeps over one DeviceMPS
+    (adjoint=True: also for the reverse sweeps)."""
 
-    def __init__(self, mps, prm):
-        self.nbytes = _lib.tebd_workspace_size(prm, mps=mps.struct())
+    def __init__(self, mps, prm, adjoint=False):
+        if adjoint:
+            self.nbytes = _lib.tebd_adjoint_workspace_size(mps.struct(), prm)
+        else:
+            self.nbytes = _lib.tebd_workspace_size(prm, mps=mps.struct())
         self.buf, self.ptr = workspace(self.nbytes, mps.gamma.device)
         dev = mps.gamma.device
         self.disc = torch.zeros((mps.n_chains, mps.n_sites - 1), dtype=torch.float64, device=dev)

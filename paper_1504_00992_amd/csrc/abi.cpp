@@ -96,7 +96,8 @@ struct SweepPlan {
   int64_t nchunk;
   size_t adj_desc_bytes, adj_slab_sz;
   size_t tape_slot;
-  size_t total;  // bytes serving the forward and the adjoint
+  size_t total;      // forward sweep
+  size_t adj_total;  // adjoint sweep (and the recorded forward): max of both
 };
 
 SweepPlan plan_sweep(const tebd_mps& mps, const tebd_params& prm) {
@@ -114,9 +115,9 @@ SweepPlan plan_sweep(const tebd_mps& mps, const tebd_params& prm) {
                      align256(size_t(TA_COUNT) * size_t(s.pmax + 1) * sizeof(int32_t));
   s.adj_slab_sz = adj_slab_bytes(s.mcap, s.mcap, s.lcap, cap, d2, s.nchunk);
   s.tape_slot = tape_slot_bytes(s.mcap, s.mcap, s.lcap);
-  const size_t fwd = s.desc_bytes + size_t(s.pmax) * s.slab_sz;
+  s.total = s.desc_bytes + size_t(s.pmax) * s.slab_sz;
   const size_t adj = s.adj_desc_bytes + size_t(s.pmax) * s.adj_slab_sz;
-  s.total = fwd > adj ? fwd : adj;
+  s.adj_total = s.total > adj ? s.total : adj;
   return s;
 }
 
@@ -558,6 +559,17 @@ tebd_status tebd_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate_ch
                        dev_status, workspace, ws_bytes, stream);
 }
 
+tebd_status tebd_adjoint_workspace_size(const tebd_mps* mps, const tebd_params* prm,
+                                        size_t* bytes) {
+  if (!bytes) return fail(TEBD_ERR_ARG, "argument 3 (bytes) is NULL");
+  tebd_status st = check_params(prm);
+  if (st != TEBD_OK) return st;
+  st = check_mps(mps, prm);
+  if (st != TEBD_OK) return st;
+  *bytes = plan_sweep(*mps, *prm).adj_total;
+  return ok();
+}
+
 tebd_status tebd_tape_size(const tebd_mps* mps, const tebd_params* prm, size_t* bytes) {
   if (!bytes) return fail(TEBD_ERR_ARG, "argument 3 (bytes) is NULL");
   tebd_status st = check_params(prm);
@@ -625,9 +637,9 @@ tebd_status tebd_sweep_adjoint(const tebd_mps* mps_in, const tebd_z* gates,
   if (!workspace) return fail(TEBD_ERR_WORKSPACE, "argument 12 (workspace) is NULL");
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
     return fail(TEBD_ERR_WORKSPACE, "argument 12 (workspace) must be 256-byte aligned");
-  if (ws_bytes < pl.total)
+  if (ws_bytes < pl.adj_total)
     return fail(TEBD_ERR_WORKSPACE, "argument 13 (ws_bytes) = %zu < %zu needed", ws_bytes,
-                pl.total);
+                pl.adj_total);
   AdjCommon c;
   c.n_chains = mps_in->n_chains;
   c.n_sites = mps_in->n_sites;

@@ -56,7 +56,7 @@ class CheckpointedTEBD:
         self.gates = {"half": gates_half.contiguous(), "full": gates_full.contiguous()}
         self.prm = _lib.params(chi_max, p, q, trunc_eps, lambda_floor, seed, 0, precision,
                                adaptive)
-        self.ws = BondWorkspace(mps, self.prm)
+        self.ws = BondWorkspace(mps, self.prm, adjoint=True)
         self.tape_bytes = _lib.tebd_tape_size(mps.struct(), self.prm)
         self.checkpoint = int(checkpoint)
         self.ckpts = {}

@@ -175,7 +175,8 @@ def test_adjoint_entry_points_validate_before_enqueue():
     f = 0x100000
     tb = _lib.tebd_tape_size(mps, prm)
     assert tb > 0
-    need = _lib.tebd_workspace_size(prm, mps=mps)
+    need = _lib.tebd_adjoint_workspace_size(mps, prm)
+    assert need >= _lib.tebd_workspace_size(prm, mps=mps)
     lib = _lib.load()
 
     def rec(**kw):
@@ -204,7 +205,7 @@ def test_adjoint_entry_points_validate_before_enqueue():
     assert adj(ws_bytes=need - 1) == _lib.TEBD_ERR_WORKSPACE
     assert adj(ws=f + 8) == _lib.TEBD_ERR_WORKSPACE
     assert adj(parity=-1) == _lib.TEBD_ERR_ARG
-    # the tape grows with the chain batch; the workspace covers the adjoint too
+    # the tape grows with the chain batch
     assert _lib.tebd_tape_size(_mps_struct(n_chains=4), prm) == 2 * tb
     del lib
 

@@ -110,7 +110,7 @@ def test_sweep_adjoint_matches_oracle(dims, chis, parity, chi_max, p, adaptive):
     dev = api.DeviceMPS.from_host([(gam, lam)], dims, cap)
     before = (dev.gamma.clone(), dev.lam.clone(), dev.chi.clone())
     prm = _lib.params(chi_max, p, 2, eps, 1e-14, SEED, sid, 0, adaptive)
-    ws = api.BondWorkspace(dev, prm)
+    ws = api.BondWorkspace(dev, prm, adjoint=True)
     tbytes = _lib.tebd_tape_size(dev.struct(), prm)
     tape = api.workspace(tbytes)
     gd = torch.from_numpy(stack).cuda()
@@ -206,7 +206,7 @@ def test_adjoint_refuses_a_tape_of_another_sweep():
     dev = api.DeviceMPS.from_host([(gam, lam)], dims, 8)
     before = (dev.gamma.clone(), dev.lam.clone(), dev.chi.clone())
     prm = _lib.params(8, 4, 2, 1e-10)
-    ws = api.BondWorkspace(dev, prm)
+    ws = api.BondWorkspace(dev, prm, adjoint=True)
     tbytes = _lib.tebd_tape_size(dev.struct(), prm)
     tape = api.workspace(tbytes)
     gd = torch.from_numpy(stack).cuda()
@@ -347,3 +347,28 @@ def test_gradient_n40_matches_references():
     assert err_rev < 1e-8
     assert err_fd < 1e-7
     assert err_ff < 2e-5
+
+
+def test_recording_does_not_change_the_sweep():
+    from paper_1504_00992_amd import _lib, api
+    dims, chis = [2, 3, 3, 3, 2], [1, 2, 6, 6, 2, 1]
+    gen = wl.rng(17)
+    gam, lam = wl.random_vidal_chain(dims, chis, gen)
+    _, stack = _gate_stack(dims, gen)
+    gd = torch.from_numpy(stack).cuda()
+    prm = _lib.params(5, 3, 2, 1e-10, 1e-14, SEED, 3, 0, 1)
+    a = api.DeviceMPS.from_host([(gam, lam)] * 2, dims, 8)
+    b = api.DeviceMPS.from_host([(gam, lam)] * 2, dims, 8)
+    wa = api.BondWorkspace(a, prm)
+    wb = api.BondWorkspace(b, prm, adjoint=True)
+    tbytes = _lib.tebd_tape_size(b.struct(), prm)
+    tape = api.workspace(tbytes)
+    for parity in (0, 1, 0):
+        api.tebd_sweep(a, gd, parity, prm, wa)
+        _lib.check(_lib.tebd_sweep_record(b.struct(), gd.data_ptr(), 0, parity, prm,
+                                          wb.disc.data_ptr(), wb.status.data_ptr(), tape[1],
+                                          tbytes, wb.ptr, wb.nbytes, api._stream()))
+    torch.cuda.synchronize()
+    assert torch.equal(a.gamma, b.gamma) and torch.equal(a.lam, b.lam)
+    assert torch.equal(a.chi, b.chi) and torch.equal(wa.disc, wb.disc)
+    assert torch.equal(wa.status, wb.status)
