@@ -228,11 +228,16 @@ def full_svd_tebd(args, torch, models, dims, hb, warmup, steps):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
+    last = t0
     for _ in range(steps):
         step()
         done += 1
         torch.cuda.synchronize()
-        if time.perf_counter() - t0 > args.full_svd_seconds:
+        now = time.perf_counter()
+        if now - last > 20.0:
+            _progress(f"full-SVD comparator: {done} steps, {now - t0:.0f} s")
+            last = now
+        if now - t0 > args.full_svd_seconds:
             break
     torch.cuda.synchronize()
     return done, time.perf_counter() - t0
@@ -402,6 +407,10 @@ def adjoint_gradient(torch, api, models, wl, reps=3):
             "note": "errors relative to max|dL/dJ_b|; references in tests/golden/xx_n40_gradient.txt"}
 
 
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -419,6 +428,7 @@ def main():
 
     adaptive = args.rank == "adaptive"
     res = run_gpu_tebd(args, torch, api, models, adaptive)
+    _progress(f"timed TEBD run: {res['seconds']:.2f} s")
     N = 100
     per_step = updates_per_step(N) * args.chains
     total_updates = per_step * args.steps
@@ -453,6 +463,7 @@ def main():
     if not args.no_other_rank:
         other = run_gpu_tebd(args, torch, api, models, not adaptive, prof_on=True)
         oval = total_updates / other["seconds"]
+        _progress(f"other rank mode: {other['seconds']:.2f} s")
         line["other_rank_mode"] = {
             "rank": "fixed k = chi_max" if adaptive else "two-stage adaptive",
             "value": round(oval, 2), "unit": "bond updates/s",
@@ -463,6 +474,7 @@ def main():
         nsteps = args.steps if args.full_svd_steps < 0 else args.full_svd_steps
         done, fsec = full_svd_tebd(args, torch, models, res["dims"], res["hb"], args.warmup, nsteps)
         fval = done * per_step / fsec if fsec > 0 else None
+        _progress(f"full-SVD comparator: {done} steps in {fsec:.1f} s")
         line["full_svd"] = {"value": round(fval, 2), "unit": "bond updates/s",
                             "steps": done, "seconds": round(fsec, 2),
                             "note": "torch.linalg.svd (vendor full SVD) in a torch-only TEBD step on "
@@ -470,10 +482,13 @@ def main():
         line["speedup_vs_full_svd"] = round(value / fval, 3) if fval else None
     if not args.no_batched:
         line["batched_rrsvd"] = batched_rrsvd(torch, api, wl)
+        _progress("batched RRSVD done")
     if not args.no_mixed:
         line["mixed_precision"] = mixed_precision(args, torch, api, models)
+        _progress("mixed precision done")
     if not args.no_adjoint:
         line["adjoint"] = adjoint_gradient(torch, api, models, wl)
+        _progress("adjoint done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_oracle_baseline(args, res["dims"], args.cpu_seconds)
     print(json.dumps(line), flush=True)
