@@ -291,11 +291,10 @@ __global__ __launch_bounds__(256) void k_adj_core(AdjProb* probs) {
     const double si = P.sig[i], sj = P.sig[j];
     const double dd = sj * sj - si * si;
     const double f = i == j ? 0.0 : dd / (dd * dd + eta2);  // F_ij; F_ji = -F_ij
-    const zt zero = make_double2(0.0, 0.0);
-    const zt m1ij = j < k ? P.M1[size_t(i) * ld + j] : zero;
-    const zt m1ji = i < k ? P.M1[size_t(j) * ld + i] : zero;
-    const zt m2ij = j < k ? P.M2[size_t(i) * ld + j] : zero;
-    const zt m2ji = i < k ? P.M2[size_t(j) * ld + i] : zero;
+    const zt m1ij = zload_if(j < k, P.M1 + size_t(i) * ld + j);
+    const zt m1ji = zload_if(i < k, P.M1 + size_t(j) * ld + i);
+    const zt m2ij = zload_if(j < k, P.M2 + size_t(i) * ld + j);
+    const zt m2ji = zload_if(i < k, P.M2 + size_t(j) * ld + i);
     // (J_ij + conj(J_ji)) s_j + s_i (K_ij + conj(K_ji)), J = F o M1, K = F o M2
     const zt jj = zsub(zscale(m1ij, f), zscale(zconj(m1ji), f));
     const zt kk = zsub(zscale(m2ij, f), zscale(zconj(m2ji), f));

@@ -379,6 +379,156 @@ __device__ __forceinline__ int qr_core(zt* Y, int rows, int l, zt* u_s /* 2 * ro
   return rank;
 }
 
+// Tiny problems (rows <= 64, l <= 32), the bulk of a TEBD run's bonds: one
+// wavefront, the matrix in LDS with an odd column stride, and lane c owning
+// column c for the column operations: the dot products u^H y_c and the
+// updates y_c -= 2 u (u^H y_c) run down each column in a loop, so a step
+// needs no cross-lane reduction except the reflector norm and the pivot
+// search.  Lane r owns row r when a reflector is built or a column swapped.
+// Same arithmetic, pivoting rule and rank tolerance as qr_core.
+constexpr int kTinyRows = 64, kTinyL = 32, kTinyStride = kTinyRows + 1;
+
+__host__ __device__ __forceinline__ bool qr_tiny(int rows, int l) {
+  return rows <= kTinyRows && l <= kTinyL;
+}
+
+__global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want_r) {
+  __shared__ zt Ys[kTinyL * kTinyStride];
+  __shared__ zt us[kTinyRows];
+  __shared__ zt rdiag[kTinyL];
+  Prob& P = probs[blockIdx.x];
+  const int l = P.l;
+  const int rows = which ? P.n : P.m;
+  if (l == 0 || !qr_tiny(rows, l)) return;
+  constexpr int S = kTinyStride;
+  const int lane = threadIdx.x;
+  zt* Yg = which ? P.Yt : P.Y;
+  const bool piv = !want_r;
+  const zt zero = make_double2(0.0, 0.0);  // value, never addressed
+  for (int e = lane; e < rows * l; e += 64) {
+    const int c = e / rows, r = e - c * rows;
+    Ys[c * S + r] = Yg[e];
+  }
+  __syncthreads();
+  double nrm = 0.0;  // lane c: squared norm of the trailing part of column c
+  if (piv && lane < l)
+    for (int r = 0; r < rows; ++r) nrm += zabs2(Ys[lane * S + r]);
+  double r00 = 0.0;
+  int rank = l;
+  for (int j = 0; j < l; ++j) {
+    if (piv) {
+      double best = (lane >= j && lane < l) ? nrm : -1.0;
+      int bi = lane;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      const double pn = sqrt(fmax(best, 0.0));
+      if (j == 0) r00 = pn;
+      if (j > 0 && !(pn > kRankTol * r00)) {
+        rank = j;
+        break;
+      }
+      if (bi != j) {
+        if (lane < rows) {
+          const zt t = Ys[j * S + lane];
+          Ys[j * S + lane] = Ys[bi * S + lane];
+          Ys[bi * S + lane] = t;
+        }
+        const double nj = __shfl(nrm, j, 64), nb = __shfl(nrm, bi, 64);
+        if (lane == j) nrm = nb;
+        if (lane == bi) nrm = nj;
+        __syncthreads();
+      }
+    }
+    // reflector from column j (lane = row)
+    const zt x = zload_if(lane >= j && lane < rows, Ys + j * S + lane);
+    double s2 = (lane > j && lane < rows) ? zabs2(x) : 0.0;
+    s2 = wave_sum(s2);
+    const zt alpha = Ys[j * S + j];
+    const double aa = sqrt(zabs2(alpha));
+    const double xnorm = sqrt(aa * aa + s2);
+    zt beta = zero, v0 = zero;
+    double vinv = 0.0;
+    if (xnorm > 0.0) {
+      const zt ph = aa > 0.0 ? zscale(alpha, 1.0 / aa) : make_double2(1.0, 0.0);
+      beta = zscale(ph, -xnorm);
+      v0 = zsub(alpha, beta);
+      vinv = 1.0 / sqrt(2.0 * xnorm * (xnorm + aa));
+    }
+    if (lane >= j && lane < rows) {
+      const zt uu = zscale(lane == j ? v0 : x, vinv);
+      us[lane] = uu;
+      Ys[j * S + lane] = uu;
+    }
+    if (lane == 0) rdiag[j] = beta;
+    __syncthreads();
+    // trailing columns (lane = column)
+    if (lane > j && lane < l) {
+      zt* yc = Ys + lane * S;
+      double dr = 0.0, di = 0.0;
+      for (int r = j; r < rows; ++r) {
+        const zt t = zcmul(us[r], yc[r]);
+        dr += t.x;
+        di += t.y;
+      }
+      const zt d2 = make_double2(2.0 * dr, 2.0 * di);
+      double nn = 0.0;
+      for (int r = j; r < rows; ++r) {
+        const zt v = zsub(yc[r], zmul(us[r], d2));
+        yc[r] = v;
+        if (r > j) nn += zabs2(v);
+      }
+      nrm = nn;
+    }
+    __syncthreads();
+  }
+  if (want_r) {
+    if (lane < rank)
+      for (int i = 0; i < rank; ++i)
+        P.Rb[lane * rank + i] = i == lane ? rdiag[lane] : zload_if(i < lane, Ys + lane * S + i);
+    __syncthreads();
+  }
+  // Q = H_0 ... H_{rank-1} [I; 0] from the last reflector backwards
+  for (int j = rank - 1; j >= 0; --j) {
+    const zt uj = Ys[j * S + j];
+    if (lane < rows) {
+      const zt ur = zload_if(lane >= j, Ys + j * S + lane);
+      us[lane] = ur;
+      zt v = zero;
+      if (lane >= j) {
+        v = zscale(zmul(ur, zconj(uj)), -2.0);
+        if (lane == j) v.x += 1.0;
+      }
+      Ys[j * S + lane] = v;
+    }
+    __syncthreads();
+    if (lane > j && lane < rank) {
+      zt* yc = Ys + lane * S;
+      double dr = 0.0, di = 0.0;  // row j of this column holds an R entry: taken as 0
+      for (int r = j + 1; r < rows; ++r) {
+        const zt t = zcmul(us[r], yc[r]);
+        dr += t.x;
+        di += t.y;
+      }
+      const zt d2 = make_double2(2.0 * dr, 2.0 * di);
+      yc[j] = zsub(zero, zmul(us[j], d2));
+      for (int r = j + 1; r < rows; ++r) yc[r] = zsub(yc[r], zmul(us[r], d2));
+    }
+    __syncthreads();
+  }
+  for (int e = lane; e < rows * rank; e += 64) {
+    const int c = e / rows, r = e - c * rows;
+    Yg[e] = Ys[c * S + r];
+  }
+  if (lane == 0) P.l = rank;
+}
+
 // Size classes: a problem of measure (l + 2) * rows in (LO, HI] runs in the
 // LDS variant of that class (HI complex elements of LDS, NT threads):
 // (0, 1024] with 64 threads, (1024, 3072] with 256, (3072, 9600] with 1024;
@@ -392,7 +542,7 @@ __global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_
   const int l = P.l;
   const int rows = which ? P.n : P.m;
   const int64_t meas = int64_t(l + 2) * rows;
-  if (l == 0 || meas <= LO || meas > HI) return;
+  if (l == 0 || meas <= LO || meas > HI || qr_tiny(rows, l)) return;
   __shared__ double nrm[2 * kMaxL];
   __shared__ int sh_i[2];
   zt* Yg = which ? P.Yt : P.Y;
@@ -413,7 +563,7 @@ __global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
-  if (l == 0 || qr_in_lds(rows, l)) return;
+  if (l == 0 || qr_in_lds(rows, l) || qr_tiny(rows, l)) return;
   __shared__ double nrm[2 * kMaxL];
   __shared__ int sh_i[2];
   const int rank = qr_core<NT, kRegRows>(which ? P.Yt : P.Y, rows, l, u_s, rdiag,
@@ -441,6 +591,8 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStr
   }();
   if (attr != hipSuccess) return attr;
   const dim3 g(c.nprob);
+  if (rows_min <= kTinyRows && c.lmin <= kTinyL)
+    hipLaunchKernelGGL(k_qr_tiny, g, dim3(64), 0, s, probs, which, want_r);
   if (class_reached(mlo, mhi, 0, 1024))
     hipLaunchKernelGGL((k_qr_lds<64, 1024, 0>), g, dim3(64), 1024 * sizeof(zt), s, probs, which, want_r);
   if (class_reached(mlo, mhi, 1024, 3072))
@@ -596,6 +748,120 @@ __device__ __forceinline__ void jacobi_finish(Prob& P, const zt* C, const zt* J,
   for (int c = tid; c < l; c += NT) P.sig[c] = sig_s[perm_s[c]];
 }
 
+// Tiny problems (l <= 32): one wavefront, C and J in LDS (odd column
+// stride), and all l/2 pairs of a round rotated at once: four lanes per pair
+// each sum a quarter of the rows of g = c_p^H c_q, two xor-shuffles combine
+// them, and the same lanes rotate their rows of C and J.  Same rotation,
+// tolerance, carried norms and sweep limit as jacobi_core.
+constexpr int kTinySvdL = 32, kTinySvdStride = kTinySvdL + 1;
+
+__global__ __launch_bounds__(64) void k_small_svd_tiny(Prob* probs) {
+  constexpr int S = kTinySvdStride;
+  __shared__ zt Cs[kTinySvdL * S];
+  __shared__ zt Js[kTinySvdL * S];
+  __shared__ double nrm[kTinySvdL];
+  __shared__ double sig_s[kTinySvdL];
+  __shared__ int perm_s[kTinySvdL];
+  Prob& P = probs[blockIdx.x];
+  const int l = P.l;
+  if (l == 0 || l > kTinySvdL) return;
+  const int lane = threadIdx.x;
+  const zt zero = make_double2(0.0, 0.0);  // value, never addressed
+  for (int e = lane; e < l * l; e += 64) {
+    const int c = e / l, r = e - c * l;
+    Cs[c * S + r] = zconj(P.Rb[size_t(r) * l + c]);
+    Js[c * S + r] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  const int lp = l + (l & 1);
+  const int k = lane >> 2, h = lane & 3;
+  const double tol = DBL_EPSILON * sqrt(double(l));
+  constexpr int kMaxSweeps = 40;
+  bool converged = (l == 1);
+  for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
+    if (lane < l) {
+      double sn2 = 0.0;
+      for (int r = 0; r < l; ++r) sn2 += zabs2(Cs[lane * S + r]);
+      nrm[lane] = sn2;
+    }
+    __syncthreads();
+    bool any = false;
+    for (int round = 0; round < lp - 1; ++round) {
+      int p = 0, q = 0;
+      bool act = k < lp / 2;
+      if (act) {
+        const int a = circle_player(k, round, lp), b = circle_player(lp - 1 - k, round, lp);
+        p = a < b ? a : b;
+        q = a < b ? b : a;
+        act = q < l;
+      }
+      double gr = 0.0, gi = 0.0;
+      if (act)
+        for (int r = h; r < l; r += 4) {
+          const zt t = zcmul(Cs[p * S + r], Cs[q * S + r]);
+          gr += t.x;
+          gi += t.y;
+        }
+      gr += __shfl_xor(gr, 1, 64);
+      gi += __shfl_xor(gi, 1, 64);
+      gr += __shfl_xor(gr, 2, 64);
+      gi += __shfl_xor(gi, 2, 64);
+      if (act) {
+        const double app = nrm[p], aqq = nrm[q];
+        const double ag = sqrt(gr * gr + gi * gi);
+        if (ag > tol * sqrt(app * aqq) && ag != 0.0) {
+          const double zeta = (aqq - app) / (2.0 * ag);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+          const zt em = make_double2(gr / ag, -gi / ag);  // e^{-i phi}
+          for (int r = h; r < l; r += 4) {
+            const zt x = Cs[p * S + r], y = zmul(em, Cs[q * S + r]);
+            Cs[p * S + r] = zsub(zscale(x, cs), zscale(y, sn));
+            Cs[q * S + r] = zadd(zscale(x, sn), zscale(y, cs));
+            const zt xj = Js[p * S + r], yj = zmul(em, Js[q * S + r]);
+            Js[p * S + r] = zsub(zscale(xj, cs), zscale(yj, sn));
+            Js[q * S + r] = zadd(zscale(xj, sn), zscale(yj, cs));
+          }
+          if (h == 0) {
+            nrm[p] = fmax(app - t * ag, 0.0);
+            nrm[q] = aqq + t * ag;
+          }
+          any = true;
+        }
+      }
+      __syncthreads();
+    }
+    converged = __ballot(any) == 0;
+  }
+  if (!converged && lane == 0) P.flags |= TEBD_DEV_JACOBI_NOCONV;
+  // singular values, descending order, sorted outputs
+  if (lane < l) {
+    double sn2 = 0.0;
+    for (int r = 0; r < l; ++r) sn2 += zabs2(Cs[lane * S + r]);
+    sig_s[lane] = sqrt(sn2);
+  }
+  __syncthreads();
+  if (lane < l) {
+    const double sj = sig_s[lane];
+    int rank = 0;
+    for (int i = 0; i < l; ++i) {
+      const double si = sig_s[i];
+      rank += (si > sj) || (si == sj && i < lane);
+    }
+    perm_s[rank] = lane;
+  }
+  __syncthreads();
+  for (int e = lane; e < l * l; e += 64) {
+    const int c = e / l, r = e - c * l;
+    const int src = perm_s[c];
+    const double sv = sig_s[src];
+    const zt x = Cs[src * S + r];
+    P.X[e] = sv > 0.0 ? zscale(x, 1.0 / sv) : zero;
+    P.W[e] = Js[src * S + r];
+  }
+  if (lane < l) P.sig[lane] = sig_s[perm_s[lane]];
+}
+
 // Size classes on 2 l^2 (C and J together), as for the QR.
 template <int NT, int HI, int LO, int REGS>
 __global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
@@ -607,7 +873,7 @@ __global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int meas = 2 * l * l;
-  if (l == 0 || meas <= LO || (HI > 0 && meas > HI)) return;
+  if (l == 0 || l <= kTinySvdL || meas <= LO || (HI > 0 && meas > HI)) return;
   zt* C = HI > 0 ? lds : P.C;
   zt* J = HI > 0 ? lds + l * l : P.J;
   for (int e = threadIdx.x; e < l * l; e += NT) {
@@ -627,16 +893,17 @@ hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s) {
       reinterpret_cast<const void*>(&k_small_svd<1024, kLdsElems, 3072, 2>),
       hipFuncAttributeMaxDynamicSharedMemorySize, int(size_t(kLdsElems) * sizeof(zt)));
   if (attr != hipSuccess) return attr;
-  const int64_t mhi = 2 * int64_t(c.lmax) * c.lmax, mlo = 2 * int64_t(c.lmin) * c.lmin;
+  // l <= kTinySvdL runs in k_small_svd_tiny; the classes below see larger l
+  const int64_t lo_l = c.lmin > kTinySvdL ? c.lmin : kTinySvdL + 1;
+  const int64_t mhi = 2 * int64_t(c.lmax) * c.lmax, mlo = 2 * lo_l * lo_l;
   const dim3 g(c.nprob);
-  if (class_reached(mlo, mhi, 0, 1024))
-    hipLaunchKernelGGL((k_small_svd<64, 1024, 0, 1>), g, dim3(64), 1024 * sizeof(zt), s, probs);
-  if (class_reached(mlo, mhi, 1024, 3072))
+  if (c.lmin <= kTinySvdL) hipLaunchKernelGGL(k_small_svd_tiny, g, dim3(64), 0, s, probs);
+  if (c.lmax > kTinySvdL && class_reached(mlo, mhi, 1024, 3072))
     hipLaunchKernelGGL((k_small_svd<256, 3072, 1024, 1>), g, dim3(256), 3072 * sizeof(zt), s, probs);
-  if (class_reached(mlo, mhi, 3072, kLdsElems))
+  if (c.lmax > kTinySvdL && class_reached(mlo, mhi, 3072, kLdsElems))
     hipLaunchKernelGGL((k_small_svd<1024, kLdsElems, 3072, 2>), g, dim3(1024),
                        size_t(kLdsElems) * sizeof(zt), s, probs);
-  if (class_reached(mlo, mhi, kLdsElems, 0))
+  if (c.lmax > kTinySvdL && class_reached(mlo, mhi, kLdsElems, 0))
     hipLaunchKernelGGL((k_small_svd<1024, 0, kLdsElems, 4>), g, dim3(1024), 0, s, probs);
   return hipGetLastError();
 }

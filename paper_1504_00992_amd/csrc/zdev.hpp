@@ -19,6 +19,14 @@ __device__ __forceinline__ zt zcmul(zt a, zt b) {
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 __device__ __forceinline__ double zabs2(zt a) { return a.x * a.x + a.y * a.y; }
+// *p when c holds, else 0, without selecting between addresses (a select of
+// an LDS or global address with a local's address would put the local in
+// scratch memory).
+__device__ __forceinline__ zt zload_if(bool c, const zt* p) {
+  zt v = make_double2(0.0, 0.0);
+  if (c) v = *p;
+  return v;
+}
 
 // Wavefront sum of a double, result in every lane.  DPP moves on the two
 // 32-bit halves: quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror and
