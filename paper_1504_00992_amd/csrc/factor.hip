@@ -380,16 +380,23 @@ __device__ __forceinline__ int qr_core(zt* Y, int rows, int l, zt* u_s /* 2 * ro
 }
 
 // Tiny problems (rows <= 64, l <= 32), the bulk of a TEBD run's bonds: one
-// wavefront, the matrix in LDS with an odd column stride, and lane c owning
-// column c for the column operations: the dot products u^H y_c and the
-// updates y_c -= 2 u (u^H y_c) run down each column in a loop, so a step
-// needs no cross-lane reduction except the reflector norm and the pivot
-// search.  Lane r owns row r when a reflector is built or a column swapped.
-// Same arithmetic, pivoting rule and rank tolerance as qr_core.
+// wavefront, the matrix in LDS with an odd column stride.  Column work
+// (dot products u^H y_c, updates y_c -= 2 u (u^H y_c), trailing norms) gives
+// each column G = 64 / (l rounded up to a power of two) lanes, lane h of a
+// column taking rows h, h + G, ...; the G partial sums meet in xor-shuffles,
+// so a step has no full-wavefront reduction except the reflector norm and
+// the pivot search.  Lane r owns row r when a reflector is built or a
+// column swapped.  Same arithmetic, pivoting rule and rank tolerance as
+// qr_core.
 constexpr int kTinyRows = 64, kTinyL = 32, kTinyStride = kTinyRows + 1;
 
 __host__ __device__ __forceinline__ bool qr_tiny(int rows, int l) {
   return rows <= kTinyRows && l <= kTinyL;
+}
+
+__device__ __forceinline__ double group_sum(double v, int g) {
+  for (int off = 1; off < g; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
 __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want_r) {
@@ -399,26 +406,35 @@ __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
-  if (l == 0 || !qr_tiny(rows, l)) return;
+  // class membership from the width the pass started with: the size classes
+  // run concurrently and P.l shrinks under them
+  if (l == 0 || !qr_tiny(rows, P.l1)) return;
   constexpr int S = kTinyStride;
   const int lane = threadIdx.x;
+  int lp2 = 1;
+  while (lp2 < l) lp2 <<= 1;
+  const int G = 64 / lp2;                    // lanes per column
+  const int col = lane / G, h = lane - col * G;
   zt* Yg = which ? P.Yt : P.Y;
   const bool piv = !want_r;
-  const zt zero = make_double2(0.0, 0.0);  // value, never addressed
+  const zt zero = make_double2(0.0, 0.0);
   for (int e = lane; e < rows * l; e += 64) {
     const int c = e / rows, r = e - c * rows;
     Ys[c * S + r] = Yg[e];
   }
   __syncthreads();
-  double nrm = 0.0;  // lane c: squared norm of the trailing part of column c
-  if (piv && lane < l)
-    for (int r = 0; r < rows; ++r) nrm += zabs2(Ys[lane * S + r]);
+  double nrm = 0.0;  // lanes of column c: squared norm of its trailing part
+  if (piv) {
+    if (col < l)
+      for (int r = h; r < rows; r += G) nrm += zabs2(Ys[col * S + r]);
+    nrm = group_sum(nrm, G);
+  }
   double r00 = 0.0;
   int rank = l;
   for (int j = 0; j < l; ++j) {
     if (piv) {
-      double best = (lane >= j && lane < l) ? nrm : -1.0;
-      int bi = lane;
+      double best = (h == 0 && col >= j && col < l) ? nrm : -1.0;
+      int bi = col;
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
         const double ob = __shfl_xor(best, off, 64);
@@ -440,9 +456,9 @@ __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want
           Ys[j * S + lane] = Ys[bi * S + lane];
           Ys[bi * S + lane] = t;
         }
-        const double nj = __shfl(nrm, j, 64), nb = __shfl(nrm, bi, 64);
-        if (lane == j) nrm = nb;
-        if (lane == bi) nrm = nj;
+        const double nj = __shfl(nrm, j * G, 64), nb = __shfl(nrm, bi * G, 64);
+        if (col == j) nrm = nb;
+        if (col == bi) nrm = nj;
         __syncthreads();
       }
     }
@@ -468,24 +484,29 @@ __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want
     }
     if (lane == 0) rdiag[j] = beta;
     __syncthreads();
-    // trailing columns (lane = column)
-    if (lane > j && lane < l) {
-      zt* yc = Ys + lane * S;
-      double dr = 0.0, di = 0.0;
-      for (int r = j; r < rows; ++r) {
+    // trailing columns: G lanes per column
+    const bool mine = col > j && col < l;
+    zt* yc = Ys + col * S;
+    double dr = 0.0, di = 0.0;
+    if (mine)
+      for (int r = j + h; r < rows; r += G) {
         const zt t = zcmul(us[r], yc[r]);
         dr += t.x;
         di += t.y;
       }
+    dr = group_sum(dr, G);
+    di = group_sum(di, G);
+    double nn = 0.0;
+    if (mine) {
       const zt d2 = make_double2(2.0 * dr, 2.0 * di);
-      double nn = 0.0;
-      for (int r = j; r < rows; ++r) {
+      for (int r = j + h; r < rows; r += G) {
         const zt v = zsub(yc[r], zmul(us[r], d2));
         yc[r] = v;
         if (r > j) nn += zabs2(v);
       }
-      nrm = nn;
     }
+    nn = group_sum(nn, G);
+    if (mine) nrm = nn;
     __syncthreads();
   }
   if (want_r) {
@@ -508,17 +529,21 @@ __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want
       Ys[j * S + lane] = v;
     }
     __syncthreads();
-    if (lane > j && lane < rank) {
-      zt* yc = Ys + lane * S;
-      double dr = 0.0, di = 0.0;  // row j of this column holds an R entry: taken as 0
-      for (int r = j + 1; r < rows; ++r) {
+    const bool mine = col > j && col < rank;
+    zt* yc = Ys + col * S;
+    double dr = 0.0, di = 0.0;  // row j of these columns holds an R entry: taken as 0
+    if (mine)
+      for (int r = j + 1 + h; r < rows; r += G) {
         const zt t = zcmul(us[r], yc[r]);
         dr += t.x;
         di += t.y;
       }
+    dr = group_sum(dr, G);
+    di = group_sum(di, G);
+    if (mine) {
       const zt d2 = make_double2(2.0 * dr, 2.0 * di);
-      yc[j] = zsub(zero, zmul(us[j], d2));
-      for (int r = j + 1; r < rows; ++r) yc[r] = zsub(yc[r], zmul(us[r], d2));
+      if (h == 0) yc[j] = zsub(zero, zmul(us[j], d2));
+      for (int r = j + 1 + h; r < rows; r += G) yc[r] = zsub(yc[r], zmul(us[r], d2));
     }
     __syncthreads();
   }
@@ -529,33 +554,177 @@ __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want
   if (lane == 0) P.l = rank;
 }
 
-// Size classes: a problem of measure (l + 2) * rows in (LO, HI] runs in the
-// LDS variant of that class (HI complex elements of LDS, NT threads):
-// (0, 1024] with 64 threads, (1024, 3072] with 256, (3072, 9600] with 1024;
-// above that it runs on global memory with 1024 threads.  Every class is one
-// launch over all problems; workgroups of other classes return at once.
+// Larger LDS-resident problems, (l + 2) * rows in (LO, HI], not tiny: the
+// same column ownership with NT threads.  Column c gets G lanes of one
+// wavefront (G = NT / (l rounded up to a power of two), at most 64); row
+// work (swap, reflector, Q columns) is strided over all NT threads, and
+// each thread swaps and reads the same rows, so a step needs three barriers:
+// after the reflector-norm partials, after the reflector is written, and
+// after the trailing update.  The pivot is read by every thread from the
+// trailing norms in LDS, which the owners of the columns rewrite each step.
 template <int NT, int HI, int LO>
-__global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_r) {
-  extern __shared__ zt lds[];  // rows * l matrix, then 2 * rows for u
+__global__ __launch_bounds__(NT) void k_qr_lpc(Prob* probs, int which, int want_r) {
+  extern __shared__ zt lds[];
   __shared__ zt rdiag[kMaxL];
+  __shared__ double nrm_s[kMaxL];
+  __shared__ double red[NT / 64];
+  constexpr int NW = NT / 64;
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
-  const int64_t meas = int64_t(l + 2) * rows;
-  if (l == 0 || meas <= LO || meas > HI || qr_tiny(rows, l)) return;
-  __shared__ double nrm[2 * kMaxL];
-  __shared__ int sh_i[2];
+  const int64_t meas = int64_t(P.l1 + 2) * rows;  // class of the pass's starting width
+  if (l == 0 || meas <= LO || meas > HI || qr_tiny(rows, P.l1)) return;
+  const int S = rows | 1;  // odd column stride; l * S + rows <= (l + 2) * rows
+  zt* Ys = lds;
+  zt* us = lds + size_t(l) * S;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int lp2 = 1;
+  while (lp2 < l) lp2 <<= 1;
+  const int G = NT / lp2 < 64 ? NT / lp2 : 64;
+  const int col = tid / G, h = tid - col * G;
   zt* Yg = which ? P.Yt : P.Y;
-  const int tot = rows * l;
-  for (int e = threadIdx.x; e < tot; e += NT) lds[e] = Yg[e];
+  const bool piv = !want_r;
+  const zt zero = make_double2(0.0, 0.0);
+  for (int e = tid; e < rows * l; e += NT) {
+    const int c = e / rows, r = e - c * rows;
+    Ys[c * S + r] = Yg[e];
+  }
   __syncthreads();
-  const int rank = qr_core<NT, 0>(lds, rows, l, lds + tot, rdiag, want_r ? P.Rb : nullptr,
-                                  !want_r, nrm, sh_i);
-  const int keep = rows * rank;
-  for (int e = threadIdx.x; e < keep; e += NT) Yg[e] = lds[e];
-  if (threadIdx.x == 0) P.l = rank;
+  if (piv) {
+    double nn = 0.0;
+    if (col < l)
+      for (int r = h; r < rows; r += G) nn += zabs2(Ys[col * S + r]);
+    nn = group_sum(nn, G);
+    if (col < l && h == 0) nrm_s[col] = nn;
+    __syncthreads();
+  }
+  double r00 = 0.0;
+  int rank = l;
+  for (int j = 0; j < l; ++j) {
+    if (piv) {
+      int bi = j;
+      double best = nrm_s[j];
+      for (int c = j + 1; c < l; ++c) {
+        const double v = nrm_s[c];
+        if (v > best) {
+          best = v;
+          bi = c;
+        }
+      }
+      const double pn = sqrt(fmax(best, 0.0));
+      if (j == 0) r00 = pn;
+      if (j > 0 && !(pn > kRankTol * r00)) {
+        rank = j;
+        break;
+      }
+      if (bi != j)
+        for (int r = tid; r < rows; r += NT) {
+          const zt t = Ys[j * S + r];
+          Ys[j * S + r] = Ys[bi * S + r];
+          Ys[bi * S + r] = t;
+        }
+    }
+    // reflector from column j: every thread reads the rows it swapped
+    double s2 = 0.0;
+    for (int r = tid; r < rows; r += NT)
+      if (r > j) s2 += zabs2(Ys[j * S + r]);
+    s2 = wave_sum(s2);
+    if (lane == 0) red[wave] = s2;
+    __syncthreads();
+    s2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s2 += red[w];
+    const zt alpha = Ys[j * S + j];
+    const double aa = sqrt(zabs2(alpha));
+    const double xnorm = sqrt(aa * aa + s2);
+    zt beta = zero, v0 = zero;
+    double vinv = 0.0;
+    if (xnorm > 0.0) {
+      const zt ph = aa > 0.0 ? zscale(alpha, 1.0 / aa) : make_double2(1.0, 0.0);
+      beta = zscale(ph, -xnorm);
+      v0 = zsub(alpha, beta);
+      vinv = 1.0 / sqrt(2.0 * xnorm * (xnorm + aa));
+    }
+    for (int r = j + tid; r < rows; r += NT) {
+      const zt uu = zscale(r == j ? v0 : Ys[j * S + r], vinv);
+      us[r] = uu;
+      Ys[j * S + r] = uu;
+    }
+    if (tid == 0) rdiag[j] = beta;
+    __syncthreads();
+    const bool mine = col > j && col < l;
+    zt* yc = Ys + col * S;
+    double dr = 0.0, di = 0.0;
+    if (mine)
+      for (int r = j + h; r < rows; r += G) {
+        const zt t = zcmul(us[r], yc[r]);
+        dr += t.x;
+        di += t.y;
+      }
+    dr = group_sum(dr, G);
+    di = group_sum(di, G);
+    double nn = 0.0;
+    if (mine) {
+      const zt d2 = make_double2(2.0 * dr, 2.0 * di);
+      for (int r = j + h; r < rows; r += G) {
+        const zt v = zsub(yc[r], zmul(us[r], d2));
+        yc[r] = v;
+        if (r > j) nn += zabs2(v);
+      }
+    }
+    nn = group_sum(nn, G);
+    if (mine && h == 0) nrm_s[col] = nn;
+    __syncthreads();
+  }
+  if (want_r) {
+    for (int e = tid; e < rank * rank; e += NT) {
+      const int c = e / rank, i = e - c * rank;
+      P.Rb[e] = i == c ? rdiag[c] : zload_if(i < c, Ys + c * S + i);
+    }
+    __syncthreads();
+  }
+  for (int j = rank - 1; j >= 0; --j) {
+    const zt uj = Ys[j * S + j];
+    __syncthreads();  // every thread has read u_j before column j is rewritten
+    for (int r = tid; r < rows; r += NT) {
+      const zt ur = zload_if(r >= j, Ys + j * S + r);
+      us[r] = ur;
+      zt v = zero;
+      if (r >= j) {
+        v = zscale(zmul(ur, zconj(uj)), -2.0);
+        if (r == j) v.x += 1.0;
+      }
+      Ys[j * S + r] = v;
+    }
+    __syncthreads();
+    const bool mine = col > j && col < rank;
+    zt* yc = Ys + col * S;
+    double dr = 0.0, di = 0.0;  // row j of these columns holds an R entry: taken as 0
+    if (mine)
+      for (int r = j + 1 + h; r < rows; r += G) {
+        const zt t = zcmul(us[r], yc[r]);
+        dr += t.x;
+        di += t.y;
+      }
+    dr = group_sum(dr, G);
+    di = group_sum(di, G);
+    if (mine) {
+      const zt d2 = make_double2(2.0 * dr, 2.0 * di);
+      if (h == 0) yc[j] = zsub(zero, zmul(us[j], d2));
+      for (int r = j + 1 + h; r < rows; r += G) yc[r] = zsub(yc[r], zmul(us[r], d2));
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < rows * rank; e += NT) {
+    const int c = e / rows, r = e - c * rows;
+    Yg[e] = Ys[c * S + r];
+  }
+  if (tid == 0) P.l = rank;
 }
 
+// Problems beyond the LDS classes run on global memory (L2-resident) with
+// 1024 threads, qr_core's column ownership, and each column held in
+// registers between its dot product and its update.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_r) {
   extern __shared__ zt u_s[];  // 2 * rows
@@ -563,7 +732,7 @@ __global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
-  if (l == 0 || qr_in_lds(rows, l) || qr_tiny(rows, l)) return;
+  if (l == 0 || qr_in_lds(rows, P.l1) || qr_tiny(rows, P.l1)) return;
   __shared__ double nrm[2 * kMaxL];
   __shared__ int sh_i[2];
   const int rank = qr_core<NT, kRegRows>(which ? P.Yt : P.Y, rows, l, u_s, rdiag,
@@ -576,6 +745,85 @@ inline bool class_reached(int64_t mlo, int64_t mhi, int64_t lo, int64_t hi) {
   return mhi > lo && (hi == 0 || mlo <= hi);
 }
 
+// --------------------------------------------------------------------------
+// The size classes of one batched factorisation touch disjoint problems and
+// each fills only a few waves per CU, so they run side by side: the first
+// class on the caller's stream, the others on side streams (default
+// priority) forked from it and joined back with events.  Side streams and
+// events are per host thread and device, created on first use.
+namespace {
+constexpr int kSide = 3;
+struct SideStreams {
+  bool ready = false;
+  hipStream_t st[kSide];
+  hipEvent_t fork, join[kSide];
+};
+
+hipError_t side_streams(SideStreams*& out) {
+  static thread_local SideStreams tab[16];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 16) {
+    out = nullptr;
+    return hipSuccess;
+  }
+  SideStreams& ss = tab[dev];
+  if (!ss.ready) {
+    e = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming);
+    for (int i = 0; i < kSide && e == hipSuccess; ++i) {
+      e = hipStreamCreateWithFlags(&ss.st[i], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ss.join[i], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) return e;
+    ss.ready = true;
+  }
+  out = &ss;
+  return hipSuccess;
+}
+
+// Run launches[0..n) (each a callable taking a stream) concurrently after
+// everything already enqueued on s; s continues after all of them.  Small
+// batches run them in order on s: there the fork and join cost more than
+// the overlap gains.
+constexpr int kForkMinProblems = 64;
+
+template <class L>
+hipError_t fork_join(hipStream_t s, L* launches, int n, int nprob) {
+  if (n == 0) return hipSuccess;
+  SideStreams* ss = nullptr;
+  hipError_t e = (n > 1 && nprob >= kForkMinProblems) ? side_streams(ss) : hipSuccess;
+  if (e != hipSuccess) return e;
+  if (n == 1 || !ss) {
+    for (int i = 0; i < n; ++i) {
+      launches[i](s);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  e = hipEventRecord(ss->fork, s);
+  if (e != hipSuccess) return e;
+  const int side = n - 1 < kSide ? n - 1 : kSide;
+  for (int i = 0; i < side; ++i) {
+    e = hipStreamWaitEvent(ss->st[i], ss->fork, 0);
+    if (e != hipSuccess) return e;
+  }
+  for (int i = 0; i < n; ++i) {
+    hipStream_t t = i == 0 ? s : ss->st[(i - 1) % side];
+    launches[i](t);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  for (int i = 0; i < side; ++i) {
+    e = hipEventRecord(ss->join[i], ss->st[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, ss->join[i], 0);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+}  // namespace
+
 hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStream_t s) {
   const int rows = which ? c.nmax : c.mmax;
   const int rows_min = which ? c.nmin : c.mmin;
@@ -585,26 +833,40 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStr
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        int(2 * size_t(kMaxRows) * sizeof(zt)));
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_qr_lds<1024, kLdsElems, 3072>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_qr_lpc<1024, kLdsElems, 3072>),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                int(size_t(kLdsElems) * sizeof(zt)));
   }();
   if (attr != hipSuccess) return attr;
-  const dim3 g(c.nprob);
+  typedef void (*Launch)(hipStream_t, Prob*, int, int, int, int);
+  struct Item {
+    Launch fn;
+    Prob* probs;
+    int which, want_r, nprob, rows;
+    void operator()(hipStream_t t) const { fn(t, probs, which, want_r, nprob, rows); }
+  };
+  Item items[4];
+  int n = 0;
   if (rows_min <= kTinyRows && c.lmin <= kTinyL)
-    hipLaunchKernelGGL(k_qr_tiny, g, dim3(64), 0, s, probs, which, want_r);
-  if (class_reached(mlo, mhi, 0, 1024))
-    hipLaunchKernelGGL((k_qr_lds<64, 1024, 0>), g, dim3(64), 1024 * sizeof(zt), s, probs, which, want_r);
-  if (class_reached(mlo, mhi, 1024, 3072))
-    hipLaunchKernelGGL((k_qr_lds<256, 3072, 1024>), g, dim3(256), 3072 * sizeof(zt), s, probs, which,
-                       want_r);
+    items[n++] = {[](hipStream_t t, Prob* p, int w, int r, int np, int) {
+                    hipLaunchKernelGGL(k_qr_tiny, dim3(np), dim3(64), 0, t, p, w, r);
+                  }, probs, which, want_r, c.nprob, rows};
+  if (class_reached(mlo, mhi, 0, 3072))
+    items[n++] = {[](hipStream_t t, Prob* p, int w, int r, int np, int) {
+                    hipLaunchKernelGGL((k_qr_lpc<256, 3072, 0>), dim3(np), dim3(256),
+                                       3072 * sizeof(zt), t, p, w, r);
+                  }, probs, which, want_r, c.nprob, rows};
   if (class_reached(mlo, mhi, 3072, kLdsElems))
-    hipLaunchKernelGGL((k_qr_lds<1024, kLdsElems, 3072>), g, dim3(1024), size_t(kLdsElems) * sizeof(zt),
-                       s, probs, which, want_r);
+    items[n++] = {[](hipStream_t t, Prob* p, int w, int r, int np, int) {
+                    hipLaunchKernelGGL((k_qr_lpc<1024, kLdsElems, 3072>), dim3(np), dim3(1024),
+                                       size_t(kLdsElems) * sizeof(zt), t, p, w, r);
+                  }, probs, which, want_r, c.nprob, rows};
   if (class_reached(mlo, mhi, kLdsElems, 0))
-    hipLaunchKernelGGL(k_qr_glb<1024>, g, dim3(1024), 2 * size_t(rows) * sizeof(zt), s, probs, which,
-                       want_r);
-  return hipGetLastError();
+    items[n++] = {[](hipStream_t t, Prob* p, int w, int r, int np, int rw) {
+                    hipLaunchKernelGGL(k_qr_glb<1024>, dim3(np), dim3(1024), 2 * size_t(rw) * sizeof(zt),
+                                       t, p, w, r);
+                  }, probs, which, want_r, c.nprob, rows};
+  return fork_join(s, items, n, c.nprob);
 }
 
 // --------------------------------------------------------------------------
@@ -749,9 +1011,10 @@ __device__ __forceinline__ void jacobi_finish(Prob& P, const zt* C, const zt* J,
 }
 
 // Tiny problems (l <= 32): one wavefront, C and J in LDS (odd column
-// stride), and all l/2 pairs of a round rotated at once: four lanes per pair
-// each sum a quarter of the rows of g = c_p^H c_q, two xor-shuffles combine
-// them, and the same lanes rotate their rows of C and J.  Same rotation,
+// stride), and all l/2 pairs of a round rotated at once: G lanes per pair
+// (64 / (l/2 rounded up to a power of two), at least 4) each sum every G-th
+// row of g = c_p^H c_q, xor-shuffles combine them, and the same lanes
+// rotate their rows of C and J.  Same rotation,
 // tolerance, carried norms and sweep limit as jacobi_core.
 constexpr int kTinySvdL = 32, kTinySvdStride = kTinySvdL + 1;
 
@@ -774,7 +1037,10 @@ __global__ __launch_bounds__(64) void k_small_svd_tiny(Prob* probs) {
   }
   __syncthreads();
   const int lp = l + (l & 1);
-  const int k = lane >> 2, h = lane & 3;
+  int np2 = 1;
+  while (np2 < lp / 2) np2 <<= 1;
+  const int G = 64 / np2;  // lanes per pair: 4 for l <= 32, more for smaller l
+  const int k = lane / G, h = lane - k * G;
   const double tol = DBL_EPSILON * sqrt(double(l));
   constexpr int kMaxSweeps = 40;
   bool converged = (l == 1);
@@ -797,15 +1063,13 @@ __global__ __launch_bounds__(64) void k_small_svd_tiny(Prob* probs) {
       }
       double gr = 0.0, gi = 0.0;
       if (act)
-        for (int r = h; r < l; r += 4) {
+        for (int r = h; r < l; r += G) {
           const zt t = zcmul(Cs[p * S + r], Cs[q * S + r]);
           gr += t.x;
           gi += t.y;
         }
-      gr += __shfl_xor(gr, 1, 64);
-      gi += __shfl_xor(gi, 1, 64);
-      gr += __shfl_xor(gr, 2, 64);
-      gi += __shfl_xor(gi, 2, 64);
+      gr = group_sum(gr, G);
+      gi = group_sum(gi, G);
       if (act) {
         const double app = nrm[p], aqq = nrm[q];
         const double ag = sqrt(gr * gr + gi * gi);
@@ -814,7 +1078,7 @@ __global__ __launch_bounds__(64) void k_small_svd_tiny(Prob* probs) {
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
           const zt em = make_double2(gr / ag, -gi / ag);  // e^{-i phi}
-          for (int r = h; r < l; r += 4) {
+          for (int r = h; r < l; r += G) {
             const zt x = Cs[p * S + r], y = zmul(em, Cs[q * S + r]);
             Cs[p * S + r] = zsub(zscale(x, cs), zscale(y, sn));
             Cs[q * S + r] = zadd(zscale(x, sn), zscale(y, cs));
@@ -896,16 +1160,35 @@ hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s) {
   // l <= kTinySvdL runs in k_small_svd_tiny; the classes below see larger l
   const int64_t lo_l = c.lmin > kTinySvdL ? c.lmin : kTinySvdL + 1;
   const int64_t mhi = 2 * int64_t(c.lmax) * c.lmax, mlo = 2 * lo_l * lo_l;
-  const dim3 g(c.nprob);
-  if (c.lmin <= kTinySvdL) hipLaunchKernelGGL(k_small_svd_tiny, g, dim3(64), 0, s, probs);
+  typedef void (*Launch)(hipStream_t, Prob*, int);
+  struct Item {
+    Launch fn;
+    Prob* probs;
+    int nprob;
+    void operator()(hipStream_t t) const { fn(t, probs, nprob); }
+  };
+  Item items[4];
+  int n = 0;
+  if (c.lmin <= kTinySvdL)
+    items[n++] = {[](hipStream_t t, Prob* p, int np) {
+                    hipLaunchKernelGGL(k_small_svd_tiny, dim3(np), dim3(64), 0, t, p);
+                  }, probs, c.nprob};
   if (c.lmax > kTinySvdL && class_reached(mlo, mhi, 1024, 3072))
-    hipLaunchKernelGGL((k_small_svd<256, 3072, 1024, 1>), g, dim3(256), 3072 * sizeof(zt), s, probs);
+    items[n++] = {[](hipStream_t t, Prob* p, int np) {
+                    hipLaunchKernelGGL((k_small_svd<256, 3072, 1024, 1>), dim3(np), dim3(256),
+                                       3072 * sizeof(zt), t, p);
+                  }, probs, c.nprob};
   if (c.lmax > kTinySvdL && class_reached(mlo, mhi, 3072, kLdsElems))
-    hipLaunchKernelGGL((k_small_svd<1024, kLdsElems, 3072, 2>), g, dim3(1024),
-                       size_t(kLdsElems) * sizeof(zt), s, probs);
+    items[n++] = {[](hipStream_t t, Prob* p, int np) {
+                    hipLaunchKernelGGL((k_small_svd<1024, kLdsElems, 3072, 2>), dim3(np), dim3(1024),
+                                       size_t(kLdsElems) * sizeof(zt), t, p);
+                  }, probs, c.nprob};
   if (c.lmax > kTinySvdL && class_reached(mlo, mhi, kLdsElems, 0))
-    hipLaunchKernelGGL((k_small_svd<1024, 0, kLdsElems, 4>), g, dim3(1024), 0, s, probs);
-  return hipGetLastError();
+    items[n++] = {[](hipStream_t t, Prob* p, int np) {
+                    hipLaunchKernelGGL((k_small_svd<1024, 0, kLdsElems, 4>), dim3(np), dim3(1024), 0, t,
+                                       p);
+                  }, probs, c.nprob};
+  return fork_join(s, items, n, c.nprob);
 }
 
 // --------------------------------------------------------------------------

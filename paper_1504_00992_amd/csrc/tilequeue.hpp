@@ -33,39 +33,58 @@ __device__ __forceinline__ int kind_tiles(int kind, const PT& P, int flag) {
 }
 
 // Exclusive prefix sums of tile counts for every kind (one workgroup):
-// thread t sums a contiguous chunk of problems, thread 0 scans the chunk
-// sums, then every thread writes its chunk's offsets.
+// thread t reads its contiguous chunk of problems once and sums the tiles
+// of every kind; a block-wide scan per kind (shuffle scan inside each
+// wavefront, then the four wavefront totals, one barrier for all kinds)
+// gives every chunk its starts; a second pass writes the chunk's offsets.
 template <class PT>
 __global__ __launch_bounds__(256) void k_schedule(const PT* probs, int nprob, int flag,
                                                   int32_t* offs) {
-  __shared__ int32_t part[256];
-  __shared__ int32_t total;
-  const int tid = threadIdx.x;
+  constexpr int NK = TileKinds<PT>::count;
+  __shared__ int32_t wsum[NK][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int chunk = (nprob + 255) / 256;
   const int p0 = min(nprob, tid * chunk), p1 = min(nprob, p0 + chunk);
-  for (int kind = 0; kind < TileKinds<PT>::count; ++kind) {
-    int32_t s = 0;
-    for (int p = p0; p < p1; ++p) s += kind_tiles(kind, probs[p], flag);
-    part[tid] = s;
-    __syncthreads();
-    if (tid == 0) {
-      int32_t run = 0;
-      for (int i = 0; i < 256; ++i) {
-        const int32_t v = part[i];
-        part[i] = run;
-        run += v;
-      }
-      total = run;
+  int32_t own[NK], incl[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) own[k] = 0;
+  for (int p = p0; p < p1; ++p) {
+    const PT& P = probs[p];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) own[k] += kind_tiles(k, P, flag);
+  }
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    int32_t v = own[k];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t t = __shfl_up(v, off, 64);
+      if (lane >= off) v += t;
     }
-    __syncthreads();
-    int32_t* o = offs + size_t(kind) * (nprob + 1);
-    int32_t run = part[tid];
-    for (int p = p0; p < p1; ++p) {
-      o[p] = run;
-      run += kind_tiles(kind, probs[p], flag);
+    incl[k] = v;
+    if (lane == 63) wsum[k][wave] = v;
+  }
+  __syncthreads();
+  int32_t run[NK];
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    int32_t base = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int32_t ws = wsum[k][w];
+      if (w < wave) base += ws;
+      total += ws;
     }
-    if (tid == 0) o[nprob] = total;
-    __syncthreads();
+    run[k] = base + incl[k] - own[k];
+    if (tid == 0) offs[size_t(k) * (nprob + 1) + nprob] = total;
+  }
+  for (int p = p0; p < p1; ++p) {
+    const PT& P = probs[p];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      offs[size_t(k) * (nprob + 1) + p] = run[k];
+      run[k] += kind_tiles(k, P, flag);
+    }
   }
 }
 
