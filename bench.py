@@ -134,7 +134,7 @@ def run_gpu_tebd(args, torch, api, models, adaptive, prof_on=True):
     dims, hb = models.spin_boson(N, d, 1.0, 0.5, 1.0, 0.5)
     mps = api.DeviceMPS.product_state(args.chains, dims, [0] * N, chi_max)
     drv = api.TEBD(mps, hb, 0.05, chi_max, p=p, q=q, trunc_eps=1e-10, seed=1504,
-                   adaptive=1 if adaptive else 0)
+                   adaptive=2 if adaptive else 0)
     for _ in range(args.warmup):
         drv.step()
     torch.cuda.synchronize()
@@ -326,7 +326,7 @@ def mixed_precision(args, torch, api, models):
     for prec in (0, 1):
         mps = api.DeviceMPS.product_state(args.chains, dims, [0] * N, chi_max)
         drv = api.TEBD(mps, hb, 0.05, chi_max, p=10, q=2, trunc_eps=1e-10, seed=1504,
-                       precision=prec, adaptive=1)
+                       precision=prec, adaptive=2)
         for _ in range(min(args.warmup, 2)):
             drv.step()
         torch.cuda.synchronize()
@@ -368,7 +368,7 @@ def adjoint_gradient(torch, api, models, wl, reps=3):
     for rep in range(reps + 1):
         mps = api.DeviceMPS.product_state(1, dims, wl.neel_levels(n), chi_max)
         drv = gradient.CheckpointedTEBD(mps, g_half, g_full, chi_max, 10, 2, 1e-10, 1504,
-                                        adaptive=1, checkpoint=10)
+                                        adaptive=2, checkpoint=10)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         drv.forward(steps)
@@ -453,7 +453,8 @@ def main():
                                "(spin + 99 oscillators, d=10), t_n=0.5, w_n=1, dt=0.05, chi_max=100, "
                                "RRSVD p=10 q=2, w<=1e-10 per bond",
                    "rank": ("two-stage adaptive: k1 = chi + max(4, chi/2), k = chi_max when the "
-                            "Frobenius residual needs it" if adaptive else "fixed k = chi_max"),
+                            "Frobenius residual needs it (second pass skipped on the host when no "
+                            "bond needs it)" if adaptive else "fixed k = chi_max"),
                    "chains": args.chains, "bond_updates_per_step": per_step,
                    "chi_final_max": int(res["chi_final"].max()),
                    "status_bits_seen": sorted(set(int(x) for x in np.unique(res["status"])))},

@@ -97,7 +97,12 @@ typedef struct {
                            c <= k1 has w(c) <= trunc_eps; otherwise stage 2
                            repeats with k = chi_max, reusing the first Omega
                            columns (the paper's adaptive TEBD, Sec. IV and
-                           Alg. 2, with the exact Frobenius residual)          */
+                           Alg. 2, with the exact Frobenius residual).
+                           2: as 1 (same results), but the host reads back
+                           how many bonds need stage 2 and skips that pass
+                           when none does: the call then waits for the
+                           stream once per sweep and cannot be captured in
+                           a graph                                            */
 } tebd_params;
 
 /* Fixed-capacity batch of MPS chains in Vidal form (Sec. II.A, Eq. defmps).

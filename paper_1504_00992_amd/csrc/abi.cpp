@@ -48,10 +48,10 @@ tebd_status check_params(const tebd_params* prm) {
     return fail(TEBD_ERR_ARG, "prm->trunc_eps must be finite");
   if (!(prm->lambda_floor >= 0.0) || !std::isfinite(prm->lambda_floor))
     return fail(TEBD_ERR_ARG, "prm->lambda_floor must be finite and >= 0");
-  if (prm->adaptive != 0 && prm->adaptive != 1)
-    return fail(TEBD_ERR_ARG, "prm->adaptive = %d must be 0 or 1", prm->adaptive);
+  if (prm->adaptive < 0 || prm->adaptive > 2)
+    return fail(TEBD_ERR_ARG, "prm->adaptive = %d must be 0, 1 or 2", prm->adaptive);
   if (prm->adaptive && !(prm->trunc_eps > 0.0))
-    return fail(TEBD_ERR_ARG, "prm->adaptive = 1 needs prm->trunc_eps > 0");
+    return fail(TEBD_ERR_ARG, "prm->adaptive = %d needs prm->trunc_eps > 0", prm->adaptive);
   return TEBD_OK;
 }
 
@@ -107,7 +107,8 @@ SweepPlan plan_sweep(const tebd_mps& mps, const tebd_params& prm) {
   s.mcap = int64_t(mps.d_max) * mps.chi_max;
   s.lcap = sketch_l(prm.chi_max, prm.p, s.mcap, s.mcap);
   s.npart = int64_t((mps.d_max * mps.d_max + 63) / 64) * ((int64_t(mps.chi_max) * mps.chi_max + 63) / 64);
-  s.desc_bytes = align256(size_t(s.pmax) * sizeof(Prob)) + align256(sched_bytes(s.pmax));
+  // descriptors, tile-queue offsets, then 256 bytes of counters
+  s.desc_bytes = align256(size_t(s.pmax) * sizeof(Prob)) + align256(sched_bytes(s.pmax)) + 256;
   s.slab_sz = slab_bytes(s.mcap, s.mcap, s.lcap, 1, prm.precision, s.npart);
   const int64_t cap = mps.chi_max, d2 = int64_t(mps.d_max) * mps.d_max;
   s.nchunk = (cap * cap + kGateChunk - 1) / kGateChunk;
@@ -161,6 +162,21 @@ hipError_t upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
   e = hipMemcpyAsync(dst, g_stage.buf[k], bytes, hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
   return hipEventRecord(g_stage.ev[k], s);
+}
+
+// Blocking read of one device counter through pinned host memory (one per
+// host thread), ordered after everything enqueued on s.
+hipError_t read_counter(const int32_t* dev, int32_t* out, hipStream_t s) {
+  static thread_local int32_t* pinned = nullptr;
+  static thread_local hipEvent_t done = nullptr;
+  hipError_t e = hipSuccess;
+  if (!pinned) e = hipHostMalloc(reinterpret_cast<void**>(&pinned), 256, hipHostMallocDefault);
+  if (e == hipSuccess && !done) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMemcpyAsync(pinned, dev, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipEventRecord(done, s);
+  if (e == hipSuccess) e = hipEventSynchronize(done);
+  if (e == hipSuccess) *out = *pinned;
+  return e;
 }
 
 // Optional per-kernel event timing (tebd_profile_enable / tebd_profile_read).
@@ -295,6 +311,9 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   c.mixed = prm->precision;
   c.record = tape != nullptr;
   c.nsites = mps->n_sites;
+  c.retry_count = prm->adaptive
+                      ? reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) + pl.desc_bytes - 256)
+                      : nullptr;
   c.dmax = mps->d_max;
   c.chimax = mps->chi_max;
   c.offs = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(ws) +
@@ -313,10 +332,17 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
     return launch_plan_sweep(probs, c, *mps, reinterpret_cast<const zt*>(gates), gate_chain_stride,
                              parity, single_chain, single_bond, prm->p, slabs, pl.slab_sz, disc,
                              status, prm->lambda_floor, prm->precision, prm->adaptive,
-                             reinterpret_cast<char*>(tape), pl.tape_slot, s);
+                             reinterpret_cast<char*>(tape), pl.tape_slot, c.retry_count, s);
   });
   if (e == hipSuccess) e = run_pipeline(probs, c, s);
-  if (e == hipSuccess && c.adaptive) {
+  bool second = c.adaptive != 0;
+  if (e == hipSuccess && c.adaptive == 2) {
+    // read the number of rejected first stages back and skip an empty pass
+    int32_t n_retry = 0;
+    e = read_counter(c.retry_count, &n_retry, s);
+    second = n_retry > 0;
+  }
+  if (e == hipSuccess && second) {
     // second pass: only problems whose first stage was rejected do any work
     e = timed(PK_STAGE2, s, [&]() { return launch_stage2(probs, c, s); });
     c.pass2 = 1;
@@ -467,6 +493,7 @@ tebd_status rrsvd_truncate(int64_t batch, const int64_t* m, const int64_t* n,
   c.mixed = prm->precision;
   c.record = 0;
   c.nsites = 0;
+  c.retry_count = nullptr;
   c.dmax = 0;
   c.chimax = 0;
   for (int64_t b = 0; b < batch; ++b) {

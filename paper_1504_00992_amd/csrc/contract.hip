@@ -275,11 +275,12 @@ hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s)
 
 // --------------------------------------------------------------------------
 // Kept singular vectors and lambda^-1 reabsorption
-struct LdQ {  // (r, k) -> Q[k*ld + r] (column-major Q, rows r)
+struct LdQP {  // (r, k) -> Q[piv[k]*ld + r]: the columns of Q in the order P of B^H P = Q_B R_B
   const zt* p;
   int64_t ld;
+  const int32_t* piv;
   static constexpr bool contig_k = false;
-  __device__ zt operator()(int r, int k) const { return p[size_t(k) * ld + r]; }
+  __device__ zt operator()(int r, int k) const { return p[size_t(piv[k]) * ld + r]; }
 };
 struct LdSmallColB {  // B[k][c] = X[c*l + k], zero for c >= l
   const zt* p;
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(256) void k_form_u(Prob* probs, const int32_t* offs
     if (P.retry) return;  // adaptive rank: stage 2 will write this problem
     const int chi = P.chi_new;
     const int Keff = (n0 >= chi) ? 0 : P.l;
-    LdQ la{P.Y, P.m};
+    LdQP la{P.Y, P.m, P.piv};
     LdSmallColB lb{P.X, P.l};
     if (TEBD_) {
       StGammaL st{P.gk, P.lam_l, P.lambda_floor, P.chi_l, P.chi_cap, chi};
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(256) void k_tape_uv(Prob* probs, const int32_t* off
   __shared__ zt smem[Cfg64::lds_elems];
   for_each_tile<TK_TAPEU>(probs, offs, nprob, 1, [&](Prob& P, int M, int N, int m0, int n0, int) {
     if (P.retry) return;
-    LdQ la{P.Y, P.m};
+    LdQP la{P.Y, P.m, P.piv};
     LdSmallColB lb{P.X, P.l};
     StRow st{P.tape_u, P.tape_ldu};
     zgemm_tile<Cfg64>(M, N, P.l, m0, n0, la, lb, st, smem);

@@ -23,8 +23,9 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
                              size_t slab_sz, int64_t mcap, int64_t ncap, int64_t lcap,
                              int64_t npart_cap, double* disc, int32_t* status,
                              double lambda_floor, int mixed, int adaptive, char* tape,
-                             size_t tape_stride) {
+                             size_t tape_stride, int32_t* retry_count) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0 && retry_count) *retry_count = 0;
   if (p >= nprob) return;
   const int N = mps.n_sites, cap = mps.chi_max, dmax = mps.d_max;
   const int nb = (N - 1 - parity + 1) / 2;
@@ -129,14 +130,14 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
                              int32_t single_bond, int32_t p_over, char* slab_base,
                              size_t slab_sz, double* disc, int32_t* status, double lambda_floor,
                              int32_t mixed, int32_t adaptive, char* tape, size_t tape_stride,
-                             hipStream_t s) {
+                             int32_t* retry_count, hipStream_t s) {
   const int64_t mcap = int64_t(c.dmax) * c.chimax;
   const int64_t lcap = c.lmax;
   const int64_t npart_cap = int64_t((c.dmax * c.dmax + 63) / 64) * ((c.chimax * c.chimax + 63) / 64);
   hipLaunchKernelGGL(k_plan_sweep, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob, mps,
                      gates, gate_chain_stride, parity, single_chain, single_bond, c.kcap, p_over,
                      slab_base, slab_sz, mcap, mcap, lcap, npart_cap, disc, status, lambda_floor,
-                     mixed, adaptive, tape, tape_stride);
+                     mixed, adaptive, tape, tape_stride, retry_count);
   return hipGetLastError();
 }
 
@@ -252,8 +253,9 @@ constexpr double kRankTol = 1e-13;
 
 template <int NT, int REG>
 __device__ __forceinline__ int qr_core(zt* Y, int rows, int l, zt* u_s /* 2 * rows */,
-                                       zt* rdiag, zt* Rb, bool piv, double* nrm /* 2 * kMaxL */,
-                                       int* sh_i) {
+                                       zt* rdiag, zt* Rb, bool piv, bool allow_stop,
+                                       int32_t* perm /* l, or nullptr */,
+                                       double* nrm /* 2 * kMaxL */, int* sh_i) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = NT / 64;
   int rank = l;
@@ -294,7 +296,7 @@ __device__ __forceinline__ int qr_core(zt* Y, int rows, int l, zt* u_s /* 2 * ro
         }
         const double pn = sqrt(fmax(best, 0.0));
         if (j == 0) r00 = pn;
-        if (j > 0 && !(pn > kRankTol * r00)) stop = 1;
+        if (allow_stop && j > 0 && !(pn > kRankTol * r00)) stop = 1;
         if (!stop && bi != j) {
           zt* ya = Y + size_t(j) * rows;
           zt* yb = Y + size_t(bi) * rows;
@@ -302,6 +304,11 @@ __device__ __forceinline__ int qr_core(zt* Y, int rows, int l, zt* u_s /* 2 * ro
             const zt t = ya[r];
             ya[r] = yb[r];
             yb[r] = t;
+          }
+          if (perm && lane == 0) {
+            const int32_t t = perm[j];
+            perm[j] = perm[bi];
+            perm[bi] = t;
           }
         }
       }
@@ -416,7 +423,10 @@ __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want
   const int G = 64 / lp2;                    // lanes per column
   const int col = lane / G, h = lane - col * G;
   zt* Yg = which ? P.Yt : P.Y;
-  const bool piv = !want_r;
+  // Both QRs pivot: the range finder to reveal the rank (and stop there),
+  // the QR of B^H to grade R_B for the Jacobi SVD (its order is recorded).
+  const bool piv = true, allow_stop = !want_r;
+  int32_t perm = lane;  // lane c: original index of column c (want_r)
   const zt zero = make_double2(0.0, 0.0);
   for (int e = lane; e < rows * l; e += 64) {
     const int c = e / rows, r = e - c * rows;
@@ -446,7 +456,7 @@ __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want
       }
       const double pn = sqrt(fmax(best, 0.0));
       if (j == 0) r00 = pn;
-      if (j > 0 && !(pn > kRankTol * r00)) {
+      if (allow_stop && j > 0 && !(pn > kRankTol * r00)) {
         rank = j;
         break;
       }
@@ -459,6 +469,9 @@ __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want
         const double nj = __shfl(nrm, j * G, 64), nb = __shfl(nrm, bi * G, 64);
         if (col == j) nrm = nb;
         if (col == bi) nrm = nj;
+        const int32_t pj = __shfl(perm, j, 64), pb = __shfl(perm, bi, 64);
+        if (lane == j) perm = pb;
+        if (lane == bi) perm = pj;
         __syncthreads();
       }
     }
@@ -510,9 +523,11 @@ __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want
     __syncthreads();
   }
   if (want_r) {
-    if (lane < rank)
+    if (lane < rank) {
       for (int i = 0; i < rank; ++i)
         P.Rb[lane * rank + i] = i == lane ? rdiag[lane] : zload_if(i < lane, Ys + lane * S + i);
+      P.piv[lane] = perm;
+    }
     __syncthreads();
   }
   // Q = H_0 ... H_{rank-1} [I; 0] from the last reflector backwards
@@ -560,8 +575,9 @@ __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want
 // work (swap, reflector, Q columns) is strided over all NT threads, and
 // each thread swaps and reads the same rows, so a step needs three barriers:
 // after the reflector-norm partials, after the reflector is written, and
-// after the trailing update.  The pivot is read by every thread from the
-// trailing norms in LDS, which the owners of the columns rewrite each step.
+// after the trailing update.  Every wavefront finds the pivot itself from
+// the trailing norms in LDS, which the owners of the columns rewrite each
+// step.
 template <int NT, int HI, int LO>
 __global__ __launch_bounds__(NT) void k_qr_lpc(Prob* probs, int which, int want_r) {
   extern __shared__ zt lds[];
@@ -583,7 +599,9 @@ __global__ __launch_bounds__(NT) void k_qr_lpc(Prob* probs, int which, int want_
   const int G = NT / lp2 < 64 ? NT / lp2 : 64;
   const int col = tid / G, h = tid - col * G;
   zt* Yg = which ? P.Yt : P.Y;
-  const bool piv = !want_r;
+  const bool piv = true, allow_stop = !want_r;  // see k_qr_tiny
+  __shared__ int32_t perm_s[kMaxL];
+  for (int c = tid; c < l; c += NT) perm_s[c] = c;
   const zt zero = make_double2(0.0, 0.0);
   for (int e = tid; e < rows * l; e += NT) {
     const int c = e / rows, r = e - c * rows;
@@ -602,27 +620,43 @@ __global__ __launch_bounds__(NT) void k_qr_lpc(Prob* probs, int which, int want_
   int rank = l;
   for (int j = 0; j < l; ++j) {
     if (piv) {
-      int bi = j;
-      double best = nrm_s[j];
-      for (int c = j + 1; c < l; ++c) {
+      // every wavefront finds the same pivot: lane-strided scan, butterfly
+      double best = -1.0;
+      int bi = l;
+      for (int c = j + lane; c < l; c += 64) {
         const double v = nrm_s[c];
         if (v > best) {
           best = v;
           bi = c;
         }
       }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
       const double pn = sqrt(fmax(best, 0.0));
       if (j == 0) r00 = pn;
-      if (j > 0 && !(pn > kRankTol * r00)) {
+      if (allow_stop && j > 0 && !(pn > kRankTol * r00)) {
         rank = j;
         break;
       }
-      if (bi != j)
+      if (bi != j) {
         for (int r = tid; r < rows; r += NT) {
           const zt t = Ys[j * S + r];
           Ys[j * S + r] = Ys[bi * S + r];
           Ys[bi * S + r] = t;
         }
+        if (tid == 0) {  // read again only after this step's barriers
+          const int32_t t = perm_s[j];
+          perm_s[j] = perm_s[bi];
+          perm_s[bi] = t;
+        }
+      }
     }
     // reflector from column j: every thread reads the rows it swapped
     double s2 = 0.0;
@@ -681,6 +715,7 @@ __global__ __launch_bounds__(NT) void k_qr_lpc(Prob* probs, int which, int want_
       const int c = e / rank, i = e - c * rank;
       P.Rb[e] = i == c ? rdiag[c] : zload_if(i < c, Ys + c * S + i);
     }
+    for (int c = tid; c < rank; c += NT) P.piv[c] = perm_s[c];
     __syncthreads();
   }
   for (int j = rank - 1; j >= 0; --j) {
@@ -722,6 +757,36 @@ __global__ __launch_bounds__(NT) void k_qr_lpc(Prob* probs, int which, int want_
   if (tid == 0) P.l = rank;
 }
 
+// The largest LDS class, (l + 2) * rows in (3072, 9600]: qr_core's column
+// ownership with 1024 threads (one wavefront per column at a time), the
+// matrix in 150 KiB of LDS.
+template <int NT, int HI, int LO>
+__global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_r) {
+  extern __shared__ zt lds[];  // rows * l matrix, then 2 * rows for u
+  __shared__ zt rdiag[kMaxL];
+  Prob& P = probs[blockIdx.x];
+  const int l = P.l;
+  const int rows = which ? P.n : P.m;
+  const int64_t meas = int64_t(P.l1 + 2) * rows;  // class of the pass's starting width
+  if (l == 0 || meas <= LO || meas > HI || qr_tiny(rows, P.l1)) return;
+  __shared__ double nrm[2 * kMaxL];
+  __shared__ int sh_i[2];
+  zt* Yg = which ? P.Yt : P.Y;
+  const int tot = rows * l;
+  for (int e = threadIdx.x; e < tot; e += NT) lds[e] = Yg[e];
+  __syncthreads();
+  __shared__ int32_t perm_s[kMaxL];
+  for (int c = threadIdx.x; c < l; c += NT) perm_s[c] = c;
+  __syncthreads();
+  const int rank = qr_core<NT, 0>(lds, rows, l, lds + tot, rdiag, want_r ? P.Rb : nullptr, true,
+                                  !want_r, want_r ? perm_s : nullptr, nrm, sh_i);
+  if (want_r)
+    for (int c = threadIdx.x; c < l; c += NT) P.piv[c] = perm_s[c];
+  const int keep = rows * rank;
+  for (int e = threadIdx.x; e < keep; e += NT) Yg[e] = lds[e];
+  if (threadIdx.x == 0) P.l = rank;
+}
+
 // Problems beyond the LDS classes run on global memory (L2-resident) with
 // 1024 threads, qr_core's column ownership, and each column held in
 // registers between its dot product and its update.
@@ -735,8 +800,14 @@ __global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_
   if (l == 0 || qr_in_lds(rows, P.l1) || qr_tiny(rows, P.l1)) return;
   __shared__ double nrm[2 * kMaxL];
   __shared__ int sh_i[2];
+  __shared__ int32_t perm_s[kMaxL];
+  for (int c = threadIdx.x; c < l; c += NT) perm_s[c] = c;
+  __syncthreads();
   const int rank = qr_core<NT, kRegRows>(which ? P.Yt : P.Y, rows, l, u_s, rdiag,
-                                         want_r ? P.Rb : nullptr, !want_r, nrm, sh_i);
+                                         want_r ? P.Rb : nullptr, true, !want_r,
+                                         want_r ? perm_s : nullptr, nrm, sh_i);
+  if (want_r)
+    for (int c = threadIdx.x; c < l; c += NT) P.piv[c] = perm_s[c];
   if (threadIdx.x == 0) P.l = rank;
 }
 
@@ -784,15 +855,17 @@ hipError_t side_streams(SideStreams*& out) {
 
 // Run launches[0..n) (each a callable taking a stream) concurrently after
 // everything already enqueued on s; s continues after all of them.  Small
-// batches run them in order on s: there the fork and join cost more than
-// the overlap gains.
+// batches, and the second pass of the adaptive rank (which re-runs only the
+// few rejected problems), run them in order on s: there the fork and join
+// cost more than the overlap gains.
 constexpr int kForkMinProblems = 64;
 
 template <class L>
-hipError_t fork_join(hipStream_t s, L* launches, int n, int nprob) {
+hipError_t fork_join(hipStream_t s, L* launches, int n, const Common& c) {
   if (n == 0) return hipSuccess;
   SideStreams* ss = nullptr;
-  hipError_t e = (n > 1 && nprob >= kForkMinProblems) ? side_streams(ss) : hipSuccess;
+  const bool fork = n > 1 && c.nprob >= kForkMinProblems && !c.pass2;
+  hipError_t e = fork ? side_streams(ss) : hipSuccess;
   if (e != hipSuccess) return e;
   if (n == 1 || !ss) {
     for (int i = 0; i < n; ++i) {
@@ -833,7 +906,7 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStr
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        int(2 * size_t(kMaxRows) * sizeof(zt)));
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_qr_lpc<1024, kLdsElems, 3072>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_qr_lds<1024, kLdsElems, 3072>),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                int(size_t(kLdsElems) * sizeof(zt)));
   }();
@@ -858,7 +931,7 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStr
                   }, probs, which, want_r, c.nprob, rows};
   if (class_reached(mlo, mhi, 3072, kLdsElems))
     items[n++] = {[](hipStream_t t, Prob* p, int w, int r, int np, int) {
-                    hipLaunchKernelGGL((k_qr_lpc<1024, kLdsElems, 3072>), dim3(np), dim3(1024),
+                    hipLaunchKernelGGL((k_qr_lds<1024, kLdsElems, 3072>), dim3(np), dim3(1024),
                                        size_t(kLdsElems) * sizeof(zt), t, p, w, r);
                   }, probs, which, want_r, c.nprob, rows};
   if (class_reached(mlo, mhi, kLdsElems, 0))
@@ -866,7 +939,7 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStr
                     hipLaunchKernelGGL(k_qr_glb<1024>, dim3(np), dim3(1024), 2 * size_t(rw) * sizeof(zt),
                                        t, p, w, r);
                   }, probs, which, want_r, c.nprob, rows};
-  return fork_join(s, items, n, c.nprob);
+  return fork_join(s, items, n, c);
 }
 
 // --------------------------------------------------------------------------
@@ -1188,7 +1261,7 @@ hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s) {
                     hipLaunchKernelGGL((k_small_svd<1024, 0, kLdsElems, 4>), dim3(np), dim3(1024), 0, t,
                                        p);
                   }, probs, c.nprob};
-  return fork_join(s, items, n, c.nprob);
+  return fork_join(s, items, n, c);
 }
 
 // --------------------------------------------------------------------------
@@ -1197,7 +1270,8 @@ hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s) {
 // min(chi_max, l).  TEBD: lambda' = s / ||s_{1..chi'}|| and chi' are written
 // into the MPS.  One wavefront per problem; the scans run on lane 0 so the
 // summation order is fixed.
-__global__ __launch_bounds__(64) void k_truncate(Prob* probs, double eps, int tebd) {
+__global__ __launch_bounds__(64) void k_truncate(Prob* probs, double eps, int tebd,
+                                                 int32_t* retry_count) {
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   if (l == 0) return;
@@ -1239,6 +1313,7 @@ __global__ __launch_bounds__(64) void k_truncate(Prob* probs, double eps, int te
     if (can_retry && !(eps > 0.0 && found)) {
       // stage 1 rejected: leave every output untouched, run stage 2
       P.retry = 1;
+      if (retry_count) atomicAdd(retry_count, 1);
       chi_s = -1;
     }
     if (eps > 0.0 && !found) flags |= TEBD_DEV_CHI_BOUND;
@@ -1279,7 +1354,8 @@ __global__ __launch_bounds__(64) void k_truncate(Prob* probs, double eps, int te
 }
 
 hipError_t launch_truncate(Prob* probs, const Common& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_truncate, dim3(c.nprob), dim3(64), 0, s, probs, c.eps, c.tebd);
+  hipLaunchKernelGGL(k_truncate, dim3(c.nprob), dim3(64), 0, s, probs, c.eps, c.tebd,
+                     c.pass2 ? nullptr : c.retry_count);
   return hipGetLastError();
 }
 

@@ -53,6 +53,7 @@ struct Prob {
   zt* X;         // l x l column-major: left vectors of the small SVD, sorted
   zt* W;         // l x l column-major: right rotation, sorted
   double* sig;   // l: singular values sorted descending
+  int32_t* piv;  // l: column order of the pivoted QR of B^H (B^H P = Q_B R_B)
   double* part;  // npart Frobenius partial sums
   float2* Af;    // mixed: complex64 copy of A (row-major, ld n)
   float2* Yf;    // mixed: complex64 copy of the current Q or Q~ (column-major)
@@ -102,6 +103,7 @@ struct Common {
   int32_t mixed;     // 1: complex FP32 sketch and power-iteration products
   int32_t record;    // 1: write the adjoint's tape
   int32_t nsites;    // TEBD: sites per chain
+  int32_t* retry_count;  // device: problems whose first stage was rejected (adaptive rank)
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
 };
@@ -130,7 +132,7 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
                              int32_t single_bond, int32_t p_over, char* slab_base,
                              size_t slab_bytes, double* disc, int32_t* status, double lambda_floor,
                              int32_t mixed, int32_t adaptive, char* tape, size_t tape_stride,
-                             hipStream_t s);
+                             int32_t* retry_count, hipStream_t s);
 hipError_t launch_stage2(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_schedule(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s);
@@ -168,6 +170,7 @@ __host__ __device__ inline size_t slab_bytes(int64_t m, int64_t n, int64_t l, in
   b += align256(n * l * z);          // Yt
   b += 5 * align256(l * l * z);      // Rb, C, J, X, W
   b += align256(l * sizeof(double)); // sig
+  b += align256(l * sizeof(int32_t));  // piv
   b += align256(npart * sizeof(double));
   (void)mixed;
   return b;
@@ -204,6 +207,8 @@ __host__ __device__ inline void carve_slab(Prob& p, char* base, int64_t m, int64
   c += align256(l * l * z);
   p.sig = reinterpret_cast<double*>(c);
   c += align256(l * sizeof(double));
+  p.piv = reinterpret_cast<int32_t*>(c);
+  c += align256(l * sizeof(int32_t));
   p.part = reinterpret_cast<double*>(c);
   c += align256(npart * sizeof(double));
   (void)mixed;

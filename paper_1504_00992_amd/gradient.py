@@ -49,7 +49,7 @@ class CheckpointedTEBD:
     SWEEPS = ((0, "half"), (1, "full"), (0, "half"))
 
     def __init__(self, mps, gates_half, gates_full, chi_max, p=10, q=2, trunc_eps=1e-10,
-                 seed=1504, lambda_floor=1e-14, precision=0, adaptive=1, checkpoint=10):
+                 seed=1504, lambda_floor=1e-14, precision=0, adaptive=2, checkpoint=10):
         if checkpoint < 1:
             raise ValueError("checkpoint must be >= 1")
         self.mps = mps

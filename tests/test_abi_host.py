@@ -58,7 +58,7 @@ def test_workspace_size_and_validation():
         _ws(prm, [0], [8])
     assert e.value.status == _lib.TEBD_ERR_SHAPE
     bad = _lib.params(8, 10, 2)
-    bad.adaptive = 2
+    bad.adaptive = 3
     with pytest.raises(_lib.TebdError):
         _ws(bad, [8], [8])
     with pytest.raises(_lib.TebdError) as e:

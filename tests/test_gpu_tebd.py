@@ -235,3 +235,20 @@ def test_tfim_n20_full_run_matches_oracle_and_golden():
         assert abs(zg - gold[i]) < 1e-4, (i, zg, gold[i])
         assert abs(abs(zg - gold[i]) - abs(zo - gold[i])) < 1e-10
     assert int(g.ws.status.max().item()) == 0
+
+
+def test_adaptive_host_skip_mode_matches_device_mode():
+    # adaptive = 2 only decides on the host whether the second pass runs;
+    # every result must be bitwise that of adaptive = 1
+    from paper_1504_00992_amd import api, models as pm
+    dims, hb = pm.spin_boson(10, 4)
+    runs = []
+    for mode in (1, 2):
+        dev = api.DeviceMPS.product_state(3, dims, [0] * 10, 12)
+        drv = api.TEBD(dev, hb, 0.1, 12, p=4, q=2, trunc_eps=1e-10, seed=SEED, adaptive=mode)
+        for _ in range(6):
+            drv.step()
+        torch.cuda.synchronize()
+        runs.append((dev.gamma.clone(), dev.lam.clone(), dev.chi.clone(), drv.ws.status.clone()))
+    for a, b in zip(runs[0], runs[1]):
+        assert torch.equal(a, b)
