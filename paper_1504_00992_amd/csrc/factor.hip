@@ -386,6 +386,73 @@ __device__ __forceinline__ int qr_core(zt* Y, int rows, int l, zt* u_s /* 2 * ro
   return rank;
 }
 
+// Column kernels over the strided rows r0, r0 + G, ... < rows, four rows per
+// iteration with independent partial sums, so that the LDS loads of four
+// rows are in flight together instead of one load latency per row.
+__device__ __forceinline__ zt col_dot(const zt* u, const zt* y, int r0, int rows, int G) {
+  double a0 = 0.0, b0 = 0.0, a1 = 0.0, b1 = 0.0, a2 = 0.0, b2 = 0.0, a3 = 0.0, b3 = 0.0;
+  int r = r0;
+  for (; r + 3 * G < rows; r += 4 * G) {
+    const zt u0 = u[r], u1 = u[r + G], u2 = u[r + 2 * G], u3 = u[r + 3 * G];
+    const zt y0 = y[r], y1 = y[r + G], y2 = y[r + 2 * G], y3 = y[r + 3 * G];
+    const zt t0 = zcmul(u0, y0), t1 = zcmul(u1, y1), t2 = zcmul(u2, y2), t3 = zcmul(u3, y3);
+    a0 += t0.x;
+    b0 += t0.y;
+    a1 += t1.x;
+    b1 += t1.y;
+    a2 += t2.x;
+    b2 += t2.y;
+    a3 += t3.x;
+    b3 += t3.y;
+  }
+  for (; r < rows; r += G) {
+    const zt t = zcmul(u[r], y[r]);
+    a0 += t.x;
+    b0 += t.y;
+  }
+  return make_double2((a0 + a1) + (a2 + a3), (b0 + b1) + (b2 + b3));
+}
+
+// y -= u d on those rows; returns sum |y_new|^2 over the rows > jn.
+__device__ __forceinline__ double col_axpy(const zt* u, zt* y, zt d, int r0, int rows, int G,
+                                           int jn) {
+  double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
+  int r = r0;
+  for (; r + 3 * G < rows; r += 4 * G) {
+    const zt u0 = u[r], u1 = u[r + G], u2 = u[r + 2 * G], u3 = u[r + 3 * G];
+    const zt y0 = y[r], y1 = y[r + G], y2 = y[r + 2 * G], y3 = y[r + 3 * G];
+    const zt v0 = zsub(y0, zmul(u0, d)), v1 = zsub(y1, zmul(u1, d));
+    const zt v2 = zsub(y2, zmul(u2, d)), v3 = zsub(y3, zmul(u3, d));
+    y[r] = v0;
+    y[r + G] = v1;
+    y[r + 2 * G] = v2;
+    y[r + 3 * G] = v3;
+    if (r > jn) n0 += zabs2(v0);
+    if (r + G > jn) n1 += zabs2(v1);
+    if (r + 2 * G > jn) n2 += zabs2(v2);
+    if (r + 3 * G > jn) n3 += zabs2(v3);
+  }
+  for (; r < rows; r += G) {
+    const zt v = zsub(y[r], zmul(u[r], d));
+    y[r] = v;
+    if (r > jn) n0 += zabs2(v);
+  }
+  return (n0 + n1) + (n2 + n3);
+}
+
+__device__ __forceinline__ double col_norm2(const zt* y, int r0, int rows, int G) {
+  double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
+  int r = r0;
+  for (; r + 3 * G < rows; r += 4 * G) {
+    n0 += zabs2(y[r]);
+    n1 += zabs2(y[r + G]);
+    n2 += zabs2(y[r + 2 * G]);
+    n3 += zabs2(y[r + 3 * G]);
+  }
+  for (; r < rows; r += G) n0 += zabs2(y[r]);
+  return (n0 + n1) + (n2 + n3);
+}
+
 // Tiny problems (rows <= 64, l <= 32), the bulk of a TEBD run's bonds: one
 // wavefront, the matrix in LDS with an odd column stride.  Column work
 // (dot products u^H y_c, updates y_c -= 2 u (u^H y_c), trailing norms) gives
@@ -399,11 +466,6 @@ constexpr int kTinyRows = 64, kTinyL = 32, kTinyStride = kTinyRows + 1;
 
 __host__ __device__ __forceinline__ bool qr_tiny(int rows, int l) {
   return rows <= kTinyRows && l <= kTinyL;
-}
-
-__device__ __forceinline__ double group_sum(double v, int g) {
-  for (int off = 1; off < g; off <<= 1) v += __shfl_xor(v, off, 64);
-  return v;
 }
 
 __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want_r) {
@@ -435,25 +497,19 @@ __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want
   __syncthreads();
   double nrm = 0.0;  // lanes of column c: squared norm of its trailing part
   if (piv) {
-    if (col < l)
-      for (int r = h; r < rows; r += G) nrm += zabs2(Ys[col * S + r]);
+    if (col < l) nrm = col_norm2(Ys + col * S, h, rows, G);
     nrm = group_sum(nrm, G);
   }
   double r00 = 0.0;
   int rank = l;
   for (int j = 0; j < l; ++j) {
     if (piv) {
-      double best = (h == 0 && col >= j && col < l) ? nrm : -1.0;
-      int bi = col;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
+      // largest trailing norm (ties: lowest column): DPP max, then the
+      // lowest lane holding it
+      const bool cand = h == 0 && col >= j && col < l;
+      const double best = wave_max_nonneg(cand ? nrm : 0.0);
+      const unsigned long long hit = __ballot(cand && nrm == best);
+      const int bi = (__ffsll(hit) - 1) / G;
       const double pn = sqrt(fmax(best, 0.0));
       if (j == 0) r00 = pn;
       if (allow_stop && j > 0 && !(pn > kRankTol * r00)) {
@@ -466,10 +522,11 @@ __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want
           Ys[j * S + lane] = Ys[bi * S + lane];
           Ys[bi * S + lane] = t;
         }
-        const double nj = __shfl(nrm, j * G, 64), nb = __shfl(nrm, bi * G, 64);
+        const double nj = read_lane(nrm, j * G), nb = read_lane(nrm, bi * G);
         if (col == j) nrm = nb;
         if (col == bi) nrm = nj;
-        const int32_t pj = __shfl(perm, j, 64), pb = __shfl(perm, bi, 64);
+        const int32_t pj = __builtin_amdgcn_readlane(perm, j);
+        const int32_t pb = __builtin_amdgcn_readlane(perm, bi);
         if (lane == j) perm = pb;
         if (lane == bi) perm = pj;
         __syncthreads();
@@ -500,24 +557,11 @@ __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want
     // trailing columns: G lanes per column
     const bool mine = col > j && col < l;
     zt* yc = Ys + col * S;
-    double dr = 0.0, di = 0.0;
-    if (mine)
-      for (int r = j + h; r < rows; r += G) {
-        const zt t = zcmul(us[r], yc[r]);
-        dr += t.x;
-        di += t.y;
-      }
-    dr = group_sum(dr, G);
-    di = group_sum(di, G);
+    zt dd = zero;
+    if (mine) dd = col_dot(us, yc, j + h, rows, G);
+    const double dr = group_sum(dd.x, G), di = group_sum(dd.y, G);
     double nn = 0.0;
-    if (mine) {
-      const zt d2 = make_double2(2.0 * dr, 2.0 * di);
-      for (int r = j + h; r < rows; r += G) {
-        const zt v = zsub(yc[r], zmul(us[r], d2));
-        yc[r] = v;
-        if (r > j) nn += zabs2(v);
-      }
-    }
+    if (mine) nn = col_axpy(us, yc, make_double2(2.0 * dr, 2.0 * di), j + h, rows, G, j);
     nn = group_sum(nn, G);
     if (mine) nrm = nn;
     __syncthreads();
@@ -546,19 +590,13 @@ __global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want
     __syncthreads();
     const bool mine = col > j && col < rank;
     zt* yc = Ys + col * S;
-    double dr = 0.0, di = 0.0;  // row j of these columns holds an R entry: taken as 0
-    if (mine)
-      for (int r = j + 1 + h; r < rows; r += G) {
-        const zt t = zcmul(us[r], yc[r]);
-        dr += t.x;
-        di += t.y;
-      }
-    dr = group_sum(dr, G);
-    di = group_sum(di, G);
+    zt dd = zero;  // row j of these columns holds an R entry: taken as 0
+    if (mine) dd = col_dot(us, yc, j + 1 + h, rows, G);
+    const double dr = group_sum(dd.x, G), di = group_sum(dd.y, G);
     if (mine) {
       const zt d2 = make_double2(2.0 * dr, 2.0 * di);
       if (h == 0) yc[j] = zsub(zero, zmul(us[j], d2));
-      for (int r = j + 1 + h; r < rows; r += G) yc[r] = zsub(yc[r], zmul(us[r], d2));
+      col_axpy(us, yc, d2, j + 1 + h, rows, G, rows);
     }
     __syncthreads();
   }
@@ -610,8 +648,7 @@ __global__ __launch_bounds__(NT) void k_qr_lpc(Prob* probs, int which, int want_
   __syncthreads();
   if (piv) {
     double nn = 0.0;
-    if (col < l)
-      for (int r = h; r < rows; r += G) nn += zabs2(Ys[col * S + r]);
+    if (col < l) nn = col_norm2(Ys + col * S, h, rows, G);
     nn = group_sum(nn, G);
     if (col < l && h == 0) nrm_s[col] = nn;
     __syncthreads();
@@ -620,25 +657,21 @@ __global__ __launch_bounds__(NT) void k_qr_lpc(Prob* probs, int which, int want_
   int rank = l;
   for (int j = 0; j < l; ++j) {
     if (piv) {
-      // every wavefront finds the same pivot: lane-strided scan, butterfly
-      double best = -1.0;
-      int bi = l;
+      // every wavefront finds the same pivot: per-lane scan of the columns
+      // j + lane, j + lane + 64, ... (first maximum kept), DPP max, then the
+      // lowest lane holding it
+      double mine = -1.0;
+      int mi = l;
       for (int c = j + lane; c < l; c += 64) {
         const double v = nrm_s[c];
-        if (v > best) {
-          best = v;
-          bi = c;
+        if (v > mine) {
+          mine = v;
+          mi = c;
         }
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
+      const double best = wave_max_nonneg(fmax(mine, 0.0));
+      const unsigned long long hit = __ballot(mi < l && mine == best);
+      const int bi = __builtin_amdgcn_readlane(mi, __ffsll(hit) - 1);
       const double pn = sqrt(fmax(best, 0.0));
       if (j == 0) r00 = pn;
       if (allow_stop && j > 0 && !(pn > kRankTol * r00)) {
@@ -688,24 +721,11 @@ __global__ __launch_bounds__(NT) void k_qr_lpc(Prob* probs, int which, int want_
     __syncthreads();
     const bool mine = col > j && col < l;
     zt* yc = Ys + col * S;
-    double dr = 0.0, di = 0.0;
-    if (mine)
-      for (int r = j + h; r < rows; r += G) {
-        const zt t = zcmul(us[r], yc[r]);
-        dr += t.x;
-        di += t.y;
-      }
-    dr = group_sum(dr, G);
-    di = group_sum(di, G);
+    zt dd = zero;
+    if (mine) dd = col_dot(us, yc, j + h, rows, G);
+    const double dr = group_sum(dd.x, G), di = group_sum(dd.y, G);
     double nn = 0.0;
-    if (mine) {
-      const zt d2 = make_double2(2.0 * dr, 2.0 * di);
-      for (int r = j + h; r < rows; r += G) {
-        const zt v = zsub(yc[r], zmul(us[r], d2));
-        yc[r] = v;
-        if (r > j) nn += zabs2(v);
-      }
-    }
+    if (mine) nn = col_axpy(us, yc, make_double2(2.0 * dr, 2.0 * di), j + h, rows, G, j);
     nn = group_sum(nn, G);
     if (mine && h == 0) nrm_s[col] = nn;
     __syncthreads();
@@ -734,19 +754,13 @@ __global__ __launch_bounds__(NT) void k_qr_lpc(Prob* probs, int which, int want_
     __syncthreads();
     const bool mine = col > j && col < rank;
     zt* yc = Ys + col * S;
-    double dr = 0.0, di = 0.0;  // row j of these columns holds an R entry: taken as 0
-    if (mine)
-      for (int r = j + 1 + h; r < rows; r += G) {
-        const zt t = zcmul(us[r], yc[r]);
-        dr += t.x;
-        di += t.y;
-      }
-    dr = group_sum(dr, G);
-    di = group_sum(di, G);
+    zt dd = zero;  // row j of these columns holds an R entry: taken as 0
+    if (mine) dd = col_dot(us, yc, j + 1 + h, rows, G);
+    const double dr = group_sum(dd.x, G), di = group_sum(dd.y, G);
     if (mine) {
       const zt d2 = make_double2(2.0 * dr, 2.0 * di);
       if (h == 0) yc[j] = zsub(zero, zmul(us[j], d2));
-      for (int r = j + 1 + h; r < rows; r += G) yc[r] = zsub(yc[r], zmul(us[r], d2));
+      col_axpy(us, yc, d2, j + 1 + h, rows, G, rows);
     }
     __syncthreads();
   }
@@ -1118,11 +1132,7 @@ __global__ __launch_bounds__(64) void k_small_svd_tiny(Prob* probs) {
   constexpr int kMaxSweeps = 40;
   bool converged = (l == 1);
   for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
-    if (lane < l) {
-      double sn2 = 0.0;
-      for (int r = 0; r < l; ++r) sn2 += zabs2(Cs[lane * S + r]);
-      nrm[lane] = sn2;
-    }
+    if (lane < l) nrm[lane] = col_norm2(Cs + lane * S, 0, l, 1);
     __syncthreads();
     bool any = false;
     for (int round = 0; round < lp - 1; ++round) {
@@ -1134,15 +1144,9 @@ __global__ __launch_bounds__(64) void k_small_svd_tiny(Prob* probs) {
         q = a < b ? b : a;
         act = q < l;
       }
-      double gr = 0.0, gi = 0.0;
-      if (act)
-        for (int r = h; r < l; r += G) {
-          const zt t = zcmul(Cs[p * S + r], Cs[q * S + r]);
-          gr += t.x;
-          gi += t.y;
-        }
-      gr = group_sum(gr, G);
-      gi = group_sum(gi, G);
+      zt gg = make_double2(0.0, 0.0);
+      if (act) gg = col_dot(Cs + p * S, Cs + q * S, h, l, G);
+      const double gr = group_sum(gg.x, G), gi = group_sum(gg.y, G);
       if (act) {
         const double app = nrm[p], aqq = nrm[q];
         const double ag = sqrt(gr * gr + gi * gi);
@@ -1151,13 +1155,30 @@ __global__ __launch_bounds__(64) void k_small_svd_tiny(Prob* probs) {
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
           const zt em = make_double2(gr / ag, -gi / ag);  // e^{-i phi}
-          for (int r = h; r < l; r += G) {
-            const zt x = Cs[p * S + r], y = zmul(em, Cs[q * S + r]);
-            Cs[p * S + r] = zsub(zscale(x, cs), zscale(y, sn));
-            Cs[q * S + r] = zadd(zscale(x, sn), zscale(y, cs));
-            const zt xj = Js[p * S + r], yj = zmul(em, Js[q * S + r]);
-            Js[p * S + r] = zsub(zscale(xj, cs), zscale(yj, sn));
-            Js[q * S + r] = zadd(zscale(xj, sn), zscale(yj, cs));
+          zt* cp = Cs + p * S;
+          zt* cq = Cs + q * S;
+          zt* jp = Js + p * S;
+          zt* jq = Js + q * S;
+          int r = h;
+          for (; r + G < l; r += 2 * G) {  // two rows at once: loads in flight together
+            const zt x0 = cp[r], y0 = zmul(em, cq[r]), x1 = cp[r + G], y1 = zmul(em, cq[r + G]);
+            const zt a0 = jp[r], b0 = zmul(em, jq[r]), a1 = jp[r + G], b1 = zmul(em, jq[r + G]);
+            cp[r] = zsub(zscale(x0, cs), zscale(y0, sn));
+            cq[r] = zadd(zscale(x0, sn), zscale(y0, cs));
+            cp[r + G] = zsub(zscale(x1, cs), zscale(y1, sn));
+            cq[r + G] = zadd(zscale(x1, sn), zscale(y1, cs));
+            jp[r] = zsub(zscale(a0, cs), zscale(b0, sn));
+            jq[r] = zadd(zscale(a0, sn), zscale(b0, cs));
+            jp[r + G] = zsub(zscale(a1, cs), zscale(b1, sn));
+            jq[r + G] = zadd(zscale(a1, sn), zscale(b1, cs));
+          }
+          for (; r < l; r += G) {
+            const zt x = cp[r], y = zmul(em, cq[r]);
+            cp[r] = zsub(zscale(x, cs), zscale(y, sn));
+            cq[r] = zadd(zscale(x, sn), zscale(y, cs));
+            const zt xj = jp[r], yj = zmul(em, jq[r]);
+            jp[r] = zsub(zscale(xj, cs), zscale(yj, sn));
+            jq[r] = zadd(zscale(xj, sn), zscale(yj, cs));
           }
           if (h == 0) {
             nrm[p] = fmax(app - t * ag, 0.0);
@@ -1172,11 +1193,7 @@ __global__ __launch_bounds__(64) void k_small_svd_tiny(Prob* probs) {
   }
   if (!converged && lane == 0) P.flags |= TEBD_DEV_JACOBI_NOCONV;
   // singular values, descending order, sorted outputs
-  if (lane < l) {
-    double sn2 = 0.0;
-    for (int r = 0; r < l; ++r) sn2 += zabs2(Cs[lane * S + r]);
-    sig_s[lane] = sqrt(sn2);
-  }
+  if (lane < l) sig_s[lane] = sqrt(col_norm2(Cs + lane * S, 0, l, 1));
   __syncthreads();
   if (lane < l) {
     const double sj = sig_s[lane];

@@ -57,6 +57,41 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __hiloint2double(hi, lo);
 #endif
 }
+// Sum over aligned groups of g lanes (g a power of two), result in every
+// lane of the group: DPP quad_perm [1,0,3,2] and [2,3,0,1], then
+// row_half_mirror and row_mirror pair the halves of 8- and 16-lane groups;
+// wider groups cross rows with shuffles.
+__device__ __forceinline__ double group_sum(double v, int g) {
+  if (g >= 2) v += dpp_move<0xb1>(v);
+  if (g >= 4) v += dpp_move<0x4e>(v);
+  if (g >= 8) v += dpp_move<0x141>(v);
+  if (g >= 16) v += dpp_move<0x140>(v);
+  for (int off = 16; off < g; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Wavefront maximum of non-negative values (uniform result): the row_bcast
+// steps of wave_sum with max in place of +; masked-off rows see 0, which
+// cannot exceed a non-negative maximum.
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+  v = fmax(v, dpp_move<0xb1>(v));
+  v = fmax(v, dpp_move<0x4e>(v));
+  v = fmax(v, dpp_move<0x141>(v));
+  v = fmax(v, dpp_move<0x140>(v));
+  v = fmax(v, dpp_move<0x142, 0xa>(v));
+  v = fmax(v, dpp_move<0x143, 0xc>(v));
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// Uniform read of lane `src` (src uniform across the wavefront).
+__device__ __forceinline__ double read_lane(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
