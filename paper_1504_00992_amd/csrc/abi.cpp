@@ -9,6 +9,7 @@
 // with lambda^-1 reabsorption (step iii and Sec. II.B).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -164,19 +165,41 @@ hipError_t upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
   return hipEventRecord(g_stage.ev[k], s);
 }
 
-// Blocking read of one device counter through pinned host memory (one per
-// host thread), ordered after everything enqueued on s.
-hipError_t read_counter(const int32_t* dev, int32_t* out, hipStream_t s) {
-  static thread_local int32_t* pinned = nullptr;
-  static thread_local hipEvent_t done = nullptr;
+// Reads of small device counters through pinned host memory (one buffer per
+// host thread): counters_async enqueues the copy of n <= 64 values on s,
+// counters_wait blocks until it has landed.  One read at a time per thread.
+struct PinnedCounters {
+  int32_t* buf = nullptr;
+  hipEvent_t done = nullptr;
+};
+
+PinnedCounters& pinned_counters() {
+  static thread_local PinnedCounters pc;
+  return pc;
+}
+
+hipError_t counters_async(const int32_t* dev, int n, hipStream_t s) {
+  PinnedCounters& pc = pinned_counters();
   hipError_t e = hipSuccess;
-  if (!pinned) e = hipHostMalloc(reinterpret_cast<void**>(&pinned), 256, hipHostMallocDefault);
-  if (e == hipSuccess && !done) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipMemcpyAsync(pinned, dev, sizeof(int32_t), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipEventRecord(done, s);
-  if (e == hipSuccess) e = hipEventSynchronize(done);
-  if (e == hipSuccess) *out = *pinned;
+  if (!pc.buf) e = hipHostMalloc(reinterpret_cast<void**>(&pc.buf), 256, hipHostMallocDefault);
+  if (e == hipSuccess && !pc.done) e = hipEventCreateWithFlags(&pc.done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMemcpyAsync(pc.buf, dev, size_t(n) * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipEventRecord(pc.done, s);
   return e;
+}
+
+hipError_t counters_wait(int32_t* out, int n) {
+  PinnedCounters& pc = pinned_counters();
+  hipError_t e = hipEventSynchronize(pc.done);
+  if (e == hipSuccess)
+    for (int i = 0; i < n; ++i) out[i] = pc.buf[i];
+  return e;
+}
+
+// Blocking read of one device counter, ordered after everything on s.
+hipError_t read_counter(const int32_t* dev, int32_t* out, hipStream_t s) {
+  hipError_t e = counters_async(dev, 1, s);
+  return e == hipSuccess ? counters_wait(out, 1) : e;
 }
 
 // Optional per-kernel event timing (tebd_profile_enable / tebd_profile_read).
@@ -244,7 +267,10 @@ int32_t persistent_grid(int64_t cap_tiles) {
   return int32_t(g < 8 ? 8 : g);
 }
 
-hipError_t run_pipeline(Prob* probs, const Common& c, hipStream_t s) {
+// With c.bounds_dev set, the size bounds that k_schedule writes are read back
+// while the contractions before the first QR run, and replace c's bounds, so
+// that only the QR size classes the batch reaches are launched.
+hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
   hipError_t e;
 #define TRY(x)                     \
   do {                             \
@@ -253,6 +279,7 @@ hipError_t run_pipeline(Prob* probs, const Common& c, hipStream_t s) {
   } while (0)
 #define TIMED(kind, call) TRY(timed(kind, s, [&]() { return (call); }))
   TIMED(PK_SCHEDULE, launch_schedule(probs, c, s));
+  if (c.bounds_dev) TRY(counters_async(c.bounds_dev, 6, s));
   if (c.tebd) {
     if (!c.pass2) TIMED(PK_THETA_GATE, launch_theta_gate(probs, c, s));
   } else {
@@ -265,6 +292,16 @@ hipError_t run_pipeline(Prob* probs, const Common& c, hipStream_t s) {
     return c.mixed ? launch_sketch_f32(probs, c, which, s) : launch_sketch(probs, c, which, s);
   };
   TIMED(PK_SKETCH_AOM, sketch(SK_Y_FROM_OMEGA));
+  if (c.bounds_dev) {
+    int32_t b[6];
+    TRY(counters_wait(b, 6));
+    c.mmin = b[0];
+    c.mmax = b[1];
+    c.nmin = b[2];
+    c.nmax = b[3];
+    c.lmin = b[4];
+    c.lmax = b[5];
+  }
   TIMED(PK_QR, launch_qr(probs, c, 0, 0, s));
   for (int j = 0; j < c.q; ++j) {
     TIMED(PK_SKETCH_AHQ, sketch(SK_YT_FROM_Y));
@@ -274,7 +311,11 @@ hipError_t run_pipeline(Prob* probs, const Common& c, hipStream_t s) {
   }
   TIMED(PK_SKETCH_AHQ, launch_sketch(probs, c, SK_YT_FROM_Y, s));  // B^H = A^H Q
   TIMED(PK_QR_R, launch_qr(probs, c, 1, 1, s));                    // B^H = Q_B R_B
-  TIMED(PK_SMALL_SVD, launch_small_svd(probs, c, s));
+  {
+    Common cs = c;  // the small SVD works on the revealed rank, anywhere in [1, l1]
+    cs.lmin = 1;
+    TIMED(PK_SMALL_SVD, launch_small_svd(probs, cs, s));
+  }
   TIMED(PK_TRUNCATE, launch_truncate(probs, c, s));
   TIMED(PK_FORM_UV, launch_form_uv(probs, c, s));
   if (c.record) TIMED(PK_TAPE, launch_tape(probs, c, s));
@@ -334,7 +375,16 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
                              status, prm->lambda_floor, prm->precision, prm->adaptive,
                              reinterpret_cast<char*>(tape), pl.tape_slot, c.retry_count, s);
   });
+  // the host-synchronising adaptive mode also reads the batch's size bounds
+  if (c.adaptive == 2) c.bounds_dev = c.retry_count + 4;
   if (e == hipSuccess) e = run_pipeline(probs, c, s);
+  if (c.bounds_dev) {
+    // the second pass runs the fixed-rank stage: width min(chi_max + p, m, n)
+    const int32_t l2 = prm->chi_max + prm->p;
+    c.lmin = std::min(l2, std::min(c.mmin, c.nmin));
+    c.lmax = std::min(l2, std::min(c.mmax, c.nmax));
+    c.bounds_dev = nullptr;
+  }
   bool second = c.adaptive != 0;
   if (e == hipSuccess && c.adaptive == 2) {
     // read the number of rejected first stages back and skip an empty pass

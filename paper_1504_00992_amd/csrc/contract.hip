@@ -76,10 +76,22 @@ struct TileKinds<Prob> {
         break;
     }
   }
+  // rows of the two sketches and the width of the pass (the QR size classes)
+  __device__ static __forceinline__ bool dims(const Prob& P, int d[3]) {
+    d[0] = P.m;
+    d[1] = P.n;
+    d[2] = P.l1;
+    return P.l > 0;
+  }
 };
 
 hipError_t launch_schedule(Prob* probs, const Common& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_schedule<Prob>, dim3(1), dim3(256), 0, s, probs, c.nprob, c.tebd, c.offs);
+  if (c.bounds_dev)
+    hipLaunchKernelGGL((k_schedule<Prob, true>), dim3(1), dim3(256), 0, s, probs, c.nprob, c.tebd,
+                       c.offs, c.bounds_dev);
+  else
+    hipLaunchKernelGGL((k_schedule<Prob, false>), dim3(1), dim3(256), 0, s, probs, c.nprob,
+                       c.tebd, c.offs, nullptr);
   return hipGetLastError();
 }
 

@@ -169,17 +169,14 @@ hipError_t launch_frob(Prob* probs, const Common& c, hipStream_t s) {
 // H_j x = beta e_j with beta = -phase(x_j) ||x||; a zero column gives H_j = I.
 // With want_r the l x l upper factor (column-major) is written to P.Rb first.
 //
-// Two variants share one body: problems with (l + 1) rows <= kLdsElems keep
-// the whole matrix in LDS (small bonds are latency-bound); larger ones work
+// qr_core serves the two larger size classes: problems with
+// (l + 2) rows <= kLdsElems keep the whole matrix in LDS; larger ones work
 // on the matrix in global memory (L2-resident) with one wavefront per
 // trailing column, the column held in registers between its dot product and
-// its update when it has at most 64 * kRegRows rows left.
+// its update when it has at most 64 * kRegRows rows left.  The small
+// problems that dominate a TEBD sweep run register-resident (k_qr_reg).
 constexpr int kLdsElems = 9600;  // complex elements of LDS a workgroup may claim (150 KiB)
 constexpr int kRegRows = 16;
-
-__device__ __forceinline__ bool qr_in_lds(int rows, int l) {
-  return int64_t(l + 2) * rows <= kLdsElems;
-}
 
 // y_c[j0..rows) -= 2 u (u^H y_c) for one column, by one wavefront.  Rows
 // below `skip` are treated as zero on input (they held R entries).
@@ -453,336 +450,330 @@ __device__ __forceinline__ double col_norm2(const zt* y, int r0, int rows, int G
   return (n0 + n1) + (n2 + n3);
 }
 
-// Tiny problems (rows <= 64, l <= 32), the bulk of a TEBD run's bonds: one
-// wavefront, the matrix in LDS with an odd column stride.  Column work
-// (dot products u^H y_c, updates y_c -= 2 u (u^H y_c), trailing norms) gives
-// each column G = 64 / (l rounded up to a power of two) lanes, lane h of a
-// column taking rows h, h + G, ...; the G partial sums meet in xor-shuffles,
-// so a step has no full-wavefront reduction except the reflector norm and
-// the pivot search.  Lane r owns row r when a reflector is built or a
-// column swapped.  Same arithmetic, pivoting rule and rank tolerance as
-// qr_core.
-constexpr int kTinyRows = 64, kTinyL = 32, kTinyStride = kTinyRows + 1;
+// Size classes of the batched QR, by (rows, l): 0 and 1 are register-
+// resident (512 threads with 8 rows per lane, 1024 threads with 12), 2 keeps
+// the matrix in LDS (1024 threads), 3 works on global memory.  The class
+// index never decreases when rows or l grow, so a box of sizes
+// [rmin, rmax] x [lmin, lmax] reaches exactly the classes between
+// qr_class(rmin, lmin) and qr_class(rmax, lmax).
+constexpr int kRegGroupMax = 32;  // lanes per column of the register classes
 
-__host__ __device__ __forceinline__ bool qr_tiny(int rows, int l) {
-  return rows <= kTinyRows && l <= kTinyL;
-}
-
-__global__ __launch_bounds__(64) void k_qr_tiny(Prob* probs, int which, int want_r) {
-  __shared__ zt Ys[kTinyL * kTinyStride];
-  __shared__ zt us[kTinyRows];
-  __shared__ zt rdiag[kTinyL];
-  Prob& P = probs[blockIdx.x];
-  const int l = P.l;
-  const int rows = which ? P.n : P.m;
-  // class membership from the width the pass started with: the size classes
-  // run concurrently and P.l shrinks under them
-  if (l == 0 || !qr_tiny(rows, P.l1)) return;
-  constexpr int S = kTinyStride;
-  const int lane = threadIdx.x;
+__host__ __device__ __forceinline__ int reg_group(int nt, int l) {
   int lp2 = 1;
   while (lp2 < l) lp2 <<= 1;
-  const int G = 64 / lp2;                    // lanes per column
-  const int col = lane / G, h = lane - col * G;
-  zt* Yg = which ? P.Yt : P.Y;
-  // Both QRs pivot: the range finder to reveal the rank (and stop there),
-  // the QR of B^H to grade R_B for the Jacobi SVD (its order is recorded).
-  const bool piv = true, allow_stop = !want_r;
-  int32_t perm = lane;  // lane c: original index of column c (want_r)
-  const zt zero = make_double2(0.0, 0.0);
-  for (int e = lane; e < rows * l; e += 64) {
-    const int c = e / rows, r = e - c * rows;
-    Ys[c * S + r] = Yg[e];
-  }
-  __syncthreads();
-  double nrm = 0.0;  // lanes of column c: squared norm of its trailing part
-  if (piv) {
-    if (col < l) nrm = col_norm2(Ys + col * S, h, rows, G);
-    nrm = group_sum(nrm, G);
-  }
-  double r00 = 0.0;
-  int rank = l;
-  for (int j = 0; j < l; ++j) {
-    if (piv) {
-      // largest trailing norm (ties: lowest column): DPP max, then the
-      // lowest lane holding it
-      const bool cand = h == 0 && col >= j && col < l;
-      const double best = wave_max_nonneg(cand ? nrm : 0.0);
-      const unsigned long long hit = __ballot(cand && nrm == best);
-      const int bi = (__ffsll(hit) - 1) / G;
-      const double pn = sqrt(fmax(best, 0.0));
-      if (j == 0) r00 = pn;
-      if (allow_stop && j > 0 && !(pn > kRankTol * r00)) {
-        rank = j;
-        break;
-      }
-      if (bi != j) {
-        if (lane < rows) {
-          const zt t = Ys[j * S + lane];
-          Ys[j * S + lane] = Ys[bi * S + lane];
-          Ys[bi * S + lane] = t;
-        }
-        const double nj = read_lane(nrm, j * G), nb = read_lane(nrm, bi * G);
-        if (col == j) nrm = nb;
-        if (col == bi) nrm = nj;
-        const int32_t pj = __builtin_amdgcn_readlane(perm, j);
-        const int32_t pb = __builtin_amdgcn_readlane(perm, bi);
-        if (lane == j) perm = pb;
-        if (lane == bi) perm = pj;
-        __syncthreads();
-      }
-    }
-    // reflector from column j (lane = row)
-    const zt x = zload_if(lane >= j && lane < rows, Ys + j * S + lane);
-    double s2 = (lane > j && lane < rows) ? zabs2(x) : 0.0;
-    s2 = wave_sum(s2);
-    const zt alpha = Ys[j * S + j];
-    const double aa = sqrt(zabs2(alpha));
-    const double xnorm = sqrt(aa * aa + s2);
-    zt beta = zero, v0 = zero;
-    double vinv = 0.0;
-    if (xnorm > 0.0) {
-      const zt ph = aa > 0.0 ? zscale(alpha, 1.0 / aa) : make_double2(1.0, 0.0);
-      beta = zscale(ph, -xnorm);
-      v0 = zsub(alpha, beta);
-      vinv = 1.0 / sqrt(2.0 * xnorm * (xnorm + aa));
-    }
-    if (lane >= j && lane < rows) {
-      const zt uu = zscale(lane == j ? v0 : x, vinv);
-      us[lane] = uu;
-      Ys[j * S + lane] = uu;
-    }
-    if (lane == 0) rdiag[j] = beta;
-    __syncthreads();
-    // trailing columns: G lanes per column
-    const bool mine = col > j && col < l;
-    zt* yc = Ys + col * S;
-    zt dd = zero;
-    if (mine) dd = col_dot(us, yc, j + h, rows, G);
-    const double dr = group_sum(dd.x, G), di = group_sum(dd.y, G);
-    double nn = 0.0;
-    if (mine) nn = col_axpy(us, yc, make_double2(2.0 * dr, 2.0 * di), j + h, rows, G, j);
-    nn = group_sum(nn, G);
-    if (mine) nrm = nn;
-    __syncthreads();
-  }
-  if (want_r) {
-    if (lane < rank) {
-      for (int i = 0; i < rank; ++i)
-        P.Rb[lane * rank + i] = i == lane ? rdiag[lane] : zload_if(i < lane, Ys + lane * S + i);
-      P.piv[lane] = perm;
-    }
-    __syncthreads();
-  }
-  // Q = H_0 ... H_{rank-1} [I; 0] from the last reflector backwards
-  for (int j = rank - 1; j >= 0; --j) {
-    const zt uj = Ys[j * S + j];
-    if (lane < rows) {
-      const zt ur = zload_if(lane >= j, Ys + j * S + lane);
-      us[lane] = ur;
-      zt v = zero;
-      if (lane >= j) {
-        v = zscale(zmul(ur, zconj(uj)), -2.0);
-        if (lane == j) v.x += 1.0;
-      }
-      Ys[j * S + lane] = v;
-    }
-    __syncthreads();
-    const bool mine = col > j && col < rank;
-    zt* yc = Ys + col * S;
-    zt dd = zero;  // row j of these columns holds an R entry: taken as 0
-    if (mine) dd = col_dot(us, yc, j + 1 + h, rows, G);
-    const double dr = group_sum(dd.x, G), di = group_sum(dd.y, G);
-    if (mine) {
-      const zt d2 = make_double2(2.0 * dr, 2.0 * di);
-      if (h == 0) yc[j] = zsub(zero, zmul(us[j], d2));
-      col_axpy(us, yc, d2, j + 1 + h, rows, G, rows);
-    }
-    __syncthreads();
-  }
-  for (int e = lane; e < rows * rank; e += 64) {
-    const int c = e / rows, r = e - c * rows;
-    Yg[e] = Ys[c * S + r];
-  }
-  if (lane == 0) P.l = rank;
+  const int g = nt / lp2;
+  return g > kRegGroupMax ? kRegGroupMax : g;
 }
 
-// Larger LDS-resident problems, (l + 2) * rows in (LO, HI], not tiny: the
-// same column ownership with NT threads.  Column c gets G lanes of one
-// wavefront (G = NT / (l rounded up to a power of two), at most 64); row
-// work (swap, reflector, Q columns) is strided over all NT threads, and
-// each thread swaps and reads the same rows, so a step needs three barriers:
-// after the reflector-norm partials, after the reflector is written, and
-// after the trailing update.  Every wavefront finds the pivot itself from
-// the trailing norms in LDS, which the owners of the columns rewrite each
-// step.
-template <int NT, int HI, int LO>
-__global__ __launch_bounds__(NT) void k_qr_lpc(Prob* probs, int which, int want_r) {
-  extern __shared__ zt lds[];
-  __shared__ zt rdiag[kMaxL];
-  __shared__ double nrm_s[kMaxL];
-  __shared__ double red[NT / 64];
-  constexpr int NW = NT / 64;
-  Prob& P = probs[blockIdx.x];
-  const int l = P.l;
-  const int rows = which ? P.n : P.m;
-  const int64_t meas = int64_t(P.l1 + 2) * rows;  // class of the pass's starting width
-  if (l == 0 || meas <= LO || meas > HI || qr_tiny(rows, P.l1)) return;
-  const int S = rows | 1;  // odd column stride; l * S + rows <= (l + 2) * rows
-  zt* Ys = lds;
-  zt* us = lds + size_t(l) * S;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int lp2 = 1;
-  while (lp2 < l) lp2 <<= 1;
-  const int G = NT / lp2 < 64 ? NT / lp2 : 64;
-  const int col = tid / G, h = tid - col * G;
-  zt* Yg = which ? P.Yt : P.Y;
-  const bool piv = true, allow_stop = !want_r;  // see k_qr_tiny
-  __shared__ int32_t perm_s[kMaxL];
-  for (int c = tid; c < l; c += NT) perm_s[c] = c;
+__host__ __device__ __forceinline__ bool qr_reg_fits(int nt, int rpl, int rows, int l) {
+  if (l < 1 || l > kMaxL) return false;
+  const int g = reg_group(nt, l);
+  return g >= 1 && rows <= g * rpl;
+}
+
+__host__ __device__ __forceinline__ int qr_class(int rows, int l) {
+  if (qr_reg_fits(512, 8, rows, l)) return 0;
+  if (qr_reg_fits(1024, 12, rows, l)) return 1;
+  if (int64_t(l + 2) * rows <= kLdsElems) return 2;
+  return 3;
+}
+
+// Register-resident QR.  Column c of the rows x l matrix belongs to a group
+// of G lanes (G = NT / l rounded up to a power of two, at most 32, so a
+// group never straddles wavefronts); lane h of the group keeps rows h,
+// h + G, ... of the column in registers.  Dot products, updates and
+// trailing norms of a column are register arithmetic plus a DPP sum over
+// the group; only the reflector is broadcast through LDS, where all groups
+// read the same G addresses at a time.  The reflector buffer holds zeros
+// outside the reflector's rows, so the row loops run without branches (their
+// LDS loads overlap) and rows outside [j, rows) are left exactly unchanged.
+//
+// Columns never move.  Pivoting picks the unfactored group with the largest
+// trailing norm (ties: the lowest position in the order the swaps of
+// qr_core would have produced, which is tracked) and records it as logical
+// column j; R, the pivot order and the thin Q are written out in logical
+// order.  Same reflectors, pivoting rule and rank tolerance as qr_core; two
+// barriers per factorisation step (trailing norms, reflector) and one per
+// step of the backward Q accumulation (its reflector buffer alternates).
+template <int RPL>
+struct RegQrShared {
+  zt us[2][kRegGroupMax * RPL];  // reflector (zero outside its rows), alternating
+  zt rdiag[kMaxL];
+  double nrm_s[kMaxL];  // trailing norm of each group; -1 once pivoted
+  int32_t pos_s[kMaxL], grp_at[kMaxL], piv_grp[kMaxL];
+};
+
+// The body for one group width G (a compile-time constant, so the row
+// offsets of the register loops are immediates).
+template <int NT, int RPL, int G>
+__device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, int want_r,
+                                            RegQrShared<RPL>& sh) {
+  constexpr int UCAP = kRegGroupMax * RPL;  // rows a group can hold
+  constexpr int KEEP = RPL <= 8 ? RPL : 1;  // reflector rows kept in registers
+  auto& us = sh.us;
+  auto& rdiag = sh.rdiag;
+  auto& nrm_s = sh.nrm_s;
+  auto& pos_s = sh.pos_s;
+  auto& grp_at = sh.grp_at;
+  auto& piv_grp = sh.piv_grp;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int g = tid / G, h = tid - g * G;
+  const bool have = g < l;
+  const bool allow_stop = !want_r;  // the QR of B^H keeps every column
   const zt zero = make_double2(0.0, 0.0);
-  for (int e = tid; e < rows * l; e += NT) {
-    const int c = e / rows, r = e - c * rows;
-    Ys[c * S + r] = Yg[e];
-  }
-  __syncthreads();
-  if (piv) {
-    double nn = 0.0;
-    if (col < l) nn = col_norm2(Ys + col * S, h, rows, G);
-    nn = group_sum(nn, G);
-    if (col < l && h == 0) nrm_s[col] = nn;
-    __syncthreads();
-  }
-  double r00 = 0.0;
-  int rank = l;
-  for (int j = 0; j < l; ++j) {
-    if (piv) {
-      // every wavefront finds the same pivot: per-lane scan of the columns
-      // j + lane, j + lane + 64, ... (first maximum kept), DPP max, then the
-      // lowest lane holding it
-      double mine = -1.0;
-      int mi = l;
-      for (int c = j + lane; c < l; c += 64) {
-        const double v = nrm_s[c];
-        if (v > mine) {
-          mine = v;
-          mi = c;
-        }
-      }
-      const double best = wave_max_nonneg(fmax(mine, 0.0));
-      const unsigned long long hit = __ballot(mi < l && mine == best);
-      const int bi = __builtin_amdgcn_readlane(mi, __ffsll(hit) - 1);
-      const double pn = sqrt(fmax(best, 0.0));
-      if (j == 0) r00 = pn;
-      if (allow_stop && j > 0 && !(pn > kRankTol * r00)) {
-        rank = j;
-        break;
-      }
-      if (bi != j) {
-        for (int r = tid; r < rows; r += NT) {
-          const zt t = Ys[j * S + r];
-          Ys[j * S + r] = Ys[bi * S + r];
-          Ys[bi * S + r] = t;
-        }
-        if (tid == 0) {  // read again only after this step's barriers
-          const int32_t t = perm_s[j];
-          perm_s[j] = perm_s[bi];
-          perm_s[bi] = t;
-        }
-      }
-    }
-    // reflector from column j: every thread reads the rows it swapped
-    double s2 = 0.0;
-    for (int r = tid; r < rows; r += NT)
-      if (r > j) s2 += zabs2(Ys[j * S + r]);
-    s2 = wave_sum(s2);
-    if (lane == 0) red[wave] = s2;
-    __syncthreads();
-    s2 = 0.0;
+  for (int e = tid; e < 2 * UCAP; e += NT) us[e / UCAP][e % UCAP] = zero;
+  zt y[RPL];
+  double nn = 0.0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) s2 += red[w];
-    const zt alpha = Ys[j * S + j];
-    const double aa = sqrt(zabs2(alpha));
-    const double xnorm = sqrt(aa * aa + s2);
-    zt beta = zero, v0 = zero;
-    double vinv = 0.0;
-    if (xnorm > 0.0) {
-      const zt ph = aa > 0.0 ? zscale(alpha, 1.0 / aa) : make_double2(1.0, 0.0);
-      beta = zscale(ph, -xnorm);
-      v0 = zsub(alpha, beta);
-      vinv = 1.0 / sqrt(2.0 * xnorm * (xnorm + aa));
+  for (int i = 0; i < RPL; ++i) {
+    const int r = h + G * i;
+    y[i] = zload_if(have && r < rows, Yg + size_t(g) * rows + r);
+    nn += zabs2(y[i]);
+  }
+  nn = group_sum(nn, G);
+  if (have && h == 0) nrm_s[g] = nn;
+  for (int c = tid; c < l; c += NT) {
+    pos_s[c] = c;
+    grp_at[c] = c;
+  }
+  int mine = kMaxL;  // logical column of this group once it has been the pivot
+  __syncthreads();
+  double r00 = 0.0;
+  int rank = l;
+  for (int j = 0; j < l; ++j) {
+    // pivot search, identical in every wavefront
+    double bv = -1.0;
+    int bg = -1, bp = kMaxL;
+    for (int c = lane; c < l; c += 64) {
+      const double v = nrm_s[c];
+      if (v < 0.0) continue;
+      const int pc = pos_s[c];
+      if (v > bv || (v == bv && pc < bp)) {
+        bv = v;
+        bg = c;
+        bp = pc;
+      }
     }
-    for (int r = j + tid; r < rows; r += NT) {
-      const zt uu = zscale(r == j ? v0 : Ys[j * S + r], vinv);
-      us[r] = uu;
-      Ys[j * S + r] = uu;
+    const double best = wave_max_nonneg(fmax(bv, 0.0));
+    const bool hit = bg >= 0 && bv == best;
+    unsigned long long hits = __ballot(hit);
+    if (hits == 0) {  // only NaN norms left: stop here
+      rank = j;
+      break;
     }
-    if (tid == 0) rdiag[j] = beta;
-    __syncthreads();
-    const bool mine = col > j && col < l;
-    zt* yc = Ys + col * S;
-    zt dd = zero;
-    if (mine) dd = col_dot(us, yc, j + h, rows, G);
-    const double dr = group_sum(dd.x, G), di = group_sum(dd.y, G);
-    double nn = 0.0;
-    if (mine) nn = col_axpy(us, yc, make_double2(2.0 * dr, 2.0 * di), j + h, rows, G, j);
-    nn = group_sum(nn, G);
-    if (mine && h == 0) nrm_s[col] = nn;
-    __syncthreads();
+    if (__popcll(hits) > 1) {  // equal norms: the lowest position wins
+      const double key = wave_max_nonneg(hit ? double(kMaxL - bp) : 0.0);
+      hits = __ballot(hit && double(kMaxL - bp) == key);
+    }
+    const int p = __builtin_amdgcn_readlane(bg, __ffsll(hits) - 1);
+    const double pn = sqrt(best);
+    if (j == 0) r00 = pn;
+    if (allow_stop && j > 0 && !(pn > kRankTol * r00)) {
+      rank = j;
+      break;
+    }
+    if (g == p) {  // reflector from the pivot column
+      double s2 = 0.0, ax = 0.0, ay = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = h + G * i;
+        const double a2 = zabs2(y[i]);
+        s2 += r > j ? a2 : 0.0;
+        ax = r == j ? y[i].x : ax;
+        ay = r == j ? y[i].y : ay;
+      }
+      s2 = group_sum(s2, G);
+      ax = group_sum(ax, G);  // one lane of the group holds row j
+      ay = group_sum(ay, G);
+      const zt alpha = make_double2(ax, ay);
+      const double aa = sqrt(zabs2(alpha));
+      const double xnorm = sqrt(aa * aa + s2);
+      zt beta = zero, v0 = zero;
+      double vinv = 0.0;
+      if (xnorm > 0.0) {
+        const zt ph = aa > 0.0 ? zscale(alpha, 1.0 / aa) : make_double2(1.0, 0.0);
+        beta = zscale(ph, -xnorm);
+        v0 = zsub(alpha, beta);
+        vinv = 1.0 / sqrt(2.0 * xnorm * (xnorm + aa));
+      }
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = h + G * i;
+        const double sx = r == j ? v0.x : y[i].x, sy = r == j ? v0.y : y[i].y;
+        const double mx = r >= j ? sx * vinv : 0.0, my = r >= j ? sy * vinv : 0.0;
+        us[0][r] = make_double2(mx, my);
+        // rows >= j now hold u (kept for the Q accumulation), rows < j R
+        y[i].x = r >= j ? mx : y[i].x;
+        y[i].y = r >= j ? my : y[i].y;
+      }
+      if (h == 0) rdiag[j] = beta;
+      mine = j;
+    }
+    __syncthreads();  // reflector j is published; every pivot search is done
+    if (tid == 0) {   // positions as the column swap of qr_core would leave them
+      const int q = grp_at[j], pp = pos_s[p];
+      grp_at[pp] = q;
+      pos_s[q] = pp;
+      grp_at[j] = p;
+      pos_s[p] = j;
+      piv_grp[j] = p;
+    }
+    if (have && mine == kMaxL) {  // trailing column: y -= 2 u (u^H y)
+      zt uu[KEEP];  // u kept in registers between the two loops when they fit
+      double dr0 = 0.0, di0 = 0.0, dr1 = 0.0, di1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const zt u = us[0][h + G * i];  // zero outside [j, rows)
+        if (i < KEEP) uu[i < KEEP ? i : 0] = u;
+        const zt t = zcmul(u, y[i]);
+        if (i & 1) {
+          dr1 += t.x;
+          di1 += t.y;
+        } else {
+          dr0 += t.x;
+          di0 += t.y;
+        }
+      }
+      const double dr = group_sum(dr0 + dr1, G), di = group_sum(di0 + di1, G);
+      const zt d2 = make_double2(2.0 * dr, 2.0 * di);
+      // without the kept copy, the second read of u must not be hoisted
+      // above this point (it would hold every row twice in registers)
+      if (KEEP < RPL) __builtin_amdgcn_sched_barrier(0);
+      double tn0 = 0.0, tn1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = h + G * i;
+        const zt u = i < KEEP ? uu[i < KEEP ? i : 0] : us[0][r];
+        y[i] = zsub(y[i], zmul(u, d2));
+        const double a2 = r > j ? zabs2(y[i]) : 0.0;
+        if (i & 1)
+          tn1 += a2;
+        else
+          tn0 += a2;
+      }
+      const double tn = group_sum(tn0 + tn1, G);
+      if (h == 0) nrm_s[g] = tn;
+    }
+    if (g == p && h == 0) nrm_s[g] = -1.0;
+    __syncthreads();  // trailing norms and positions of step j are complete
   }
   if (want_r) {
-    for (int e = tid; e < rank * rank; e += NT) {
-      const int c = e / rank, i = e - c * rank;
-      P.Rb[e] = i == c ? rdiag[c] : zload_if(i < c, Ys + c * S + i);
-    }
-    for (int c = tid; c < rank; c += NT) P.piv[c] = perm_s[c];
-    __syncthreads();
-  }
-  for (int j = rank - 1; j >= 0; --j) {
-    const zt uj = Ys[j * S + j];
-    __syncthreads();  // every thread has read u_j before column j is rewritten
-    for (int r = tid; r < rows; r += NT) {
-      const zt ur = zload_if(r >= j, Ys + j * S + r);
-      us[r] = ur;
-      zt v = zero;
-      if (r >= j) {
-        v = zscale(zmul(ur, zconj(uj)), -2.0);
-        if (r == j) v.x += 1.0;
+    if (have && mine < rank) {
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = h + G * i;
+        if (r < rank) {  // value selects only (no select between addresses)
+          const zt d = rdiag[r];
+          const bool up = r < mine, dg = r == mine;
+          zt v;
+          v.x = up ? y[i].x : (dg ? d.x : 0.0);
+          v.y = up ? y[i].y : (dg ? d.y : 0.0);
+          P.Rb[size_t(mine) * rank + r] = v;
+        }
       }
-      Ys[j * S + r] = v;
     }
-    __syncthreads();
-    const bool mine = col > j && col < rank;
-    zt* yc = Ys + col * S;
-    zt dd = zero;  // row j of these columns holds an R entry: taken as 0
-    if (mine) dd = col_dot(us, yc, j + 1 + h, rows, G);
-    const double dr = group_sum(dd.x, G), di = group_sum(dd.y, G);
-    if (mine) {
-      const zt d2 = make_double2(2.0 * dr, 2.0 * di);
-      if (h == 0) yc[j] = zsub(zero, zmul(us[j], d2));
-      col_axpy(us, yc, d2, j + 1 + h, rows, G, rows);
-    }
-    __syncthreads();
+    for (int c = tid; c < rank; c += NT) P.piv[c] = piv_grp[c];
   }
-  for (int e = tid; e < rows * rank; e += NT) {
-    const int c = e / rows, r = e - c * rows;
-    Yg[e] = Ys[c * S + r];
+  // Q = H_0 ... H_{r-1} [I; 0] from the last reflector backwards: the group
+  // of logical column j publishes u_j and becomes H_j e_j, the groups of
+  // later logical columns apply H_j
+  for (int j = rank - 1; j >= 0; --j) {
+    zt* ub = us[j & 1];
+    const int p = piv_grp[j];
+    if (g == p) {
+      double ux = 0.0, uy = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const bool at = h + G * i == j;
+        ux = at ? y[i].x : ux;
+        uy = at ? y[i].y : uy;
+      }
+      ux = group_sum(ux, G);
+      uy = group_sum(uy, G);
+      const zt cuj = make_double2(ux, -uy);
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = h + G * i;
+        const bool on = r >= j;  // rows >= rows hold zeros
+        const zt u = make_double2(on ? y[i].x : 0.0, on ? y[i].y : 0.0);
+        ub[r] = u;
+        zt v = zscale(zmul(u, cuj), -2.0);
+        if (r == j) v.x += 1.0;
+        y[i] = v;
+      }
+    }
+    __syncthreads();
+    if (have && mine > j && mine < rank) {
+      zt uu[KEEP];
+      double dr0 = 0.0, di0 = 0.0, dr1 = 0.0, di1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const zt u = ub[h + G * i];  // zero outside [j, rows)
+        if (i < KEEP) uu[i < KEEP ? i : 0] = u;
+        const zt t = zcmul(u, y[i]);
+        if (i & 1) {
+          dr1 += t.x;
+          di1 += t.y;
+        } else {
+          dr0 += t.x;
+          di0 += t.y;
+        }
+      }
+      const double dr = group_sum(dr0 + dr1, G), di = group_sum(di0 + di1, G);
+      const zt d2 = make_double2(2.0 * dr, 2.0 * di);
+      if (KEEP < RPL) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const zt u = i < KEEP ? uu[i < KEEP ? i : 0] : ub[h + G * i];
+        y[i] = zsub(y[i], zmul(u, d2));
+      }
+    }
+  }
+  if (have && mine < rank) {
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int r = h + G * i;
+      if (r < rows) Yg[size_t(mine) * rows + r] = y[i];
+    }
   }
   if (tid == 0) P.l = rank;
 }
 
-// The largest LDS class, (l + 2) * rows in (3072, 9600]: qr_core's column
-// ownership with 1024 threads (one wavefront per column at a time), the
-// matrix in 150 KiB of LDS.
-template <int NT, int HI, int LO>
+template <int NT, int RPL>
+__global__ __launch_bounds__(NT) void k_qr_reg(Prob* probs, int which, int want_r, int cls) {
+  __shared__ RegQrShared<RPL> sh;
+  Prob& P = probs[blockIdx.x];
+  const int l = P.l;
+  const int rows = which ? P.n : P.m;
+  // class from the width the pass started with: P.l shrinks as QRs run
+  if (l == 0 || qr_class(rows, P.l1) != cls) return;
+  zt* Yg = which ? P.Yt : P.Y;
+  // l <= kMaxL, so G >= NT / kMaxL
+  static_assert(NT / kMaxL >= 2, "group widths below 2 are not instantiated");
+  const int G = reg_group(NT, l);
+  if (G == 32)
+    qr_reg_body<NT, RPL, 32>(P, rows, l, Yg, want_r, sh);
+  else if (G == 16)
+    qr_reg_body<NT, RPL, 16>(P, rows, l, Yg, want_r, sh);
+  else if (G == 8)
+    qr_reg_body<NT, RPL, 8>(P, rows, l, Yg, want_r, sh);
+  else if (NT / kMaxL <= 4 && G == 4)
+    qr_reg_body<NT, RPL, (NT / kMaxL <= 4 ? 4 : 8)>(P, rows, l, Yg, want_r, sh);
+  else if (NT / kMaxL <= 2)
+    qr_reg_body<NT, RPL, (NT / kMaxL <= 2 ? 2 : 8)>(P, rows, l, Yg, want_r, sh);
+}
+
+// Class 2, (l + 2) * rows <= kLdsElems beyond the register classes:
+// qr_core's column ownership with 1024 threads (one wavefront per column at
+// a time), the matrix in up to 150 KiB of LDS.
+template <int NT>
 __global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_r) {
   extern __shared__ zt lds[];  // rows * l matrix, then 2 * rows for u
   __shared__ zt rdiag[kMaxL];
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
-  const int64_t meas = int64_t(P.l1 + 2) * rows;  // class of the pass's starting width
-  if (l == 0 || meas <= LO || meas > HI || qr_tiny(rows, P.l1)) return;
+  if (l == 0 || qr_class(rows, P.l1) != 2) return;
   __shared__ double nrm[2 * kMaxL];
   __shared__ int sh_i[2];
   zt* Yg = which ? P.Yt : P.Y;
@@ -801,7 +792,7 @@ __global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_
   if (threadIdx.x == 0) P.l = rank;
 }
 
-// Problems beyond the LDS classes run on global memory (L2-resident) with
+// Class 3, everything larger, runs on global memory (L2-resident) with
 // 1024 threads, qr_core's column ownership, and each column held in
 // registers between its dot product and its update.
 template <int NT>
@@ -811,7 +802,7 @@ __global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
-  if (l == 0 || qr_in_lds(rows, P.l1) || qr_tiny(rows, P.l1)) return;
+  if (l == 0 || qr_class(rows, P.l1) != 3) return;
   __shared__ double nrm[2 * kMaxL];
   __shared__ int sh_i[2];
   __shared__ int32_t perm_s[kMaxL];
@@ -912,15 +903,14 @@ hipError_t fork_join(hipStream_t s, L* launches, int n, const Common& c) {
 }  // namespace
 
 hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStream_t s) {
-  const int rows = which ? c.nmax : c.mmax;
+  const int rows_max = which ? c.nmax : c.mmax;
   const int rows_min = which ? c.nmin : c.mmin;
-  const int64_t mhi = int64_t(c.lmax + 2) * rows, mlo = int64_t(c.lmin + 2) * rows_min;
   static const hipError_t attr = []() {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_qr_glb<1024>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        int(2 * size_t(kMaxRows) * sizeof(zt)));
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_qr_lds<1024, kLdsElems, 3072>),
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_qr_lds<1024>),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                int(size_t(kLdsElems) * sizeof(zt)));
   }();
@@ -932,27 +922,26 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStr
     int which, want_r, nprob, rows;
     void operator()(hipStream_t t) const { fn(t, probs, which, want_r, nprob, rows); }
   };
+  const Launch fns[4] = {
+      [](hipStream_t t, Prob* p, int w, int r, int np, int) {
+        hipLaunchKernelGGL((k_qr_reg<512, 8>), dim3(np), dim3(512), 0, t, p, w, r, 0);
+      },
+      [](hipStream_t t, Prob* p, int w, int r, int np, int) {
+        hipLaunchKernelGGL((k_qr_reg<1024, 12>), dim3(np), dim3(1024), 0, t, p, w, r, 1);
+      },
+      [](hipStream_t t, Prob* p, int w, int r, int np, int) {
+        hipLaunchKernelGGL(k_qr_lds<1024>, dim3(np), dim3(1024), size_t(kLdsElems) * sizeof(zt),
+                           t, p, w, r);
+      },
+      [](hipStream_t t, Prob* p, int w, int r, int np, int rw) {
+        hipLaunchKernelGGL(k_qr_glb<1024>, dim3(np), dim3(1024), 2 * size_t(rw) * sizeof(zt), t,
+                           p, w, r);
+      }};
+  // the classes between those of the smallest and the largest possible size
+  const int lo = qr_class(rows_min, c.lmin), hi = qr_class(rows_max, c.lmax);
   Item items[4];
   int n = 0;
-  if (rows_min <= kTinyRows && c.lmin <= kTinyL)
-    items[n++] = {[](hipStream_t t, Prob* p, int w, int r, int np, int) {
-                    hipLaunchKernelGGL(k_qr_tiny, dim3(np), dim3(64), 0, t, p, w, r);
-                  }, probs, which, want_r, c.nprob, rows};
-  if (class_reached(mlo, mhi, 0, 3072))
-    items[n++] = {[](hipStream_t t, Prob* p, int w, int r, int np, int) {
-                    hipLaunchKernelGGL((k_qr_lpc<256, 3072, 0>), dim3(np), dim3(256),
-                                       3072 * sizeof(zt), t, p, w, r);
-                  }, probs, which, want_r, c.nprob, rows};
-  if (class_reached(mlo, mhi, 3072, kLdsElems))
-    items[n++] = {[](hipStream_t t, Prob* p, int w, int r, int np, int) {
-                    hipLaunchKernelGGL((k_qr_lds<1024, kLdsElems, 3072>), dim3(np), dim3(1024),
-                                       size_t(kLdsElems) * sizeof(zt), t, p, w, r);
-                  }, probs, which, want_r, c.nprob, rows};
-  if (class_reached(mlo, mhi, kLdsElems, 0))
-    items[n++] = {[](hipStream_t t, Prob* p, int w, int r, int np, int rw) {
-                    hipLaunchKernelGGL(k_qr_glb<1024>, dim3(np), dim3(1024), 2 * size_t(rw) * sizeof(zt),
-                                       t, p, w, r);
-                  }, probs, which, want_r, c.nprob, rows};
+  for (int k = lo; k <= hi; ++k) items[n++] = {fns[k], probs, which, want_r, c.nprob, rows_max};
   return fork_join(s, items, n, c);
 }
 

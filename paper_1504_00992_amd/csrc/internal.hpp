@@ -104,6 +104,7 @@ struct Common {
   int32_t record;    // 1: write the adjoint's tape
   int32_t nsites;    // TEBD: sites per chain
   int32_t* retry_count;  // device: problems whose first stage was rejected (adaptive rank)
+  int32_t* bounds_dev = nullptr;  // device: k_schedule writes {min, max} of m, n, l1 there
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
 };

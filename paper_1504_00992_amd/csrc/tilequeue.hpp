@@ -11,7 +11,9 @@
 // A descriptor type PT plugs in through TileKinds<PT>:
 //   static constexpr int count;   number of kinds
 //   static __device__ void shape(int kind, const PT&, int flag, int& M, int& N);
-// (M x N = 0 x 0 when the problem has no tiles of that kind).
+// (M x N = 0 x 0 when the problem has no tiles of that kind), and, for
+// k_schedule<PT, true>, static __device__ bool dims(const PT&, int d[3])
+// (false for an inactive problem).
 #pragma once
 
 #include "zdev.hpp"
@@ -37,21 +39,35 @@ __device__ __forceinline__ int kind_tiles(int kind, const PT& P, int flag) {
 // of every kind; a block-wide scan per kind (shuffle scan inside each
 // wavefront, then the four wavefront totals, one barrier for all kinds)
 // gives every chunk its starts; a second pass writes the chunk's offsets.
-template <class PT>
+// With BOUNDS, the same pass also writes the smallest and largest sizes
+// over the active problems, {min, max} of each of TileKinds<PT>::dims
+// (three values), to bounds[0..6); an empty batch gives {1, 1} each.
+template <class PT, bool BOUNDS = false>
 __global__ __launch_bounds__(256) void k_schedule(const PT* probs, int nprob, int flag,
-                                                  int32_t* offs) {
+                                                  int32_t* offs, int32_t* bounds = nullptr) {
   constexpr int NK = TileKinds<PT>::count;
   __shared__ int32_t wsum[NK][4];
+  __shared__ int32_t ext[6];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int chunk = (nprob + 255) / 256;
   const int p0 = min(nprob, tid * chunk), p1 = min(nprob, p0 + chunk);
   int32_t own[NK], incl[NK];
+  int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {0, 0, 0};
+  if (BOUNDS && tid < 6) ext[tid] = (tid & 1) ? 0 : INT32_MAX;
 #pragma unroll
   for (int k = 0; k < NK; ++k) own[k] = 0;
   for (int p = p0; p < p1; ++p) {
     const PT& P = probs[p];
 #pragma unroll
     for (int k = 0; k < NK; ++k) own[k] += kind_tiles(k, P, flag);
+    if constexpr (BOUNDS) {
+      int d[3];
+      if (TileKinds<PT>::dims(P, d))
+        for (int i = 0; i < 3; ++i) {
+          lo[i] = min(lo[i], d[i]);
+          hi[i] = max(hi[i], d[i]);
+        }
+    }
   }
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
@@ -64,7 +80,19 @@ __global__ __launch_bounds__(256) void k_schedule(const PT* probs, int nprob, in
     incl[k] = v;
     if (lane == 63) wsum[k][wave] = v;
   }
+  if constexpr (BOUNDS) {
+    __syncthreads();  // ext is initialised
+    for (int i = 0; i < 3; ++i) {
+      if (hi[i] > 0) {
+        atomicMin(&ext[2 * i], lo[i]);
+        atomicMax(&ext[2 * i + 1], hi[i]);
+      }
+    }
+  }
   __syncthreads();
+  if constexpr (BOUNDS) {
+    if (tid < 6) bounds[tid] = ext[tid | 1] > 0 ? ext[tid] : 1;
+  }
   int32_t run[NK];
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
