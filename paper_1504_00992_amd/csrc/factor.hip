@@ -816,11 +816,6 @@ __global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_
   if (threadIdx.x == 0) P.l = rank;
 }
 
-// Whether any problem with measure in [mlo, mhi] can fall in (lo, hi].
-inline bool class_reached(int64_t mlo, int64_t mhi, int64_t lo, int64_t hi) {
-  return mhi > lo && (hi == 0 || mlo <= hi);
-}
-
 // --------------------------------------------------------------------------
 // The size classes of one batched factorisation touch disjoint problems and
 // each fills only a few waves per CU, so they run side by side: the first
@@ -1086,44 +1081,64 @@ __device__ __forceinline__ void jacobi_finish(Prob& P, const zt* C, const zt* J,
   for (int c = tid; c < l; c += NT) P.sig[c] = sig_s[perm_s[c]];
 }
 
-// Tiny problems (l <= 32): one wavefront, C and J in LDS (odd column
-// stride), and all l/2 pairs of a round rotated at once: G lanes per pair
-// (64 / (l/2 rounded up to a power of two), at least 4) each sum every G-th
-// row of g = c_p^H c_q, xor-shuffles combine them, and the same lanes
-// rotate their rows of C and J.  Same rotation,
-// tolerance, carried norms and sweep limit as jacobi_core.
-constexpr int kTinySvdL = 32, kTinySvdStride = kTinySvdL + 1;
+// Size classes of the small SVD, by l: 0 (l <= 32, 256 threads) and 1
+// (l <= 64, 512 threads) rotate every pair of a round at once (k_svd_pairs);
+// 2 (C and J in LDS) and 3 (global memory) rotate one pair per wavefront at
+// a time (jacobi_core).
+__host__ __device__ __forceinline__ int svd_class(int l) {
+  if (l <= 32) return 0;
+  if (l <= 64) return 1;
+  if (2 * l * l <= kLdsElems) return 2;
+  return 3;
+}
 
-__global__ __launch_bounds__(64) void k_small_svd_tiny(Prob* probs) {
-  constexpr int S = kTinySvdStride;
-  __shared__ zt Cs[kTinySvdL * S];
-  __shared__ zt Js[kTinySvdL * S];
-  __shared__ double nrm[kTinySvdL];
-  __shared__ double sig_s[kTinySvdL];
-  __shared__ int perm_s[kTinySvdL];
+// C and J in LDS with an odd column stride, and all l/2 pairs of a round
+// rotated at once: G = NT / (l/2 rounded up to a power of two) lanes per
+// pair, at most 16 (DPP sums only).  Lane h of a pair sums every G-th row of
+// g = c_p^H c_q, the group sum combines them, and the same lanes rotate
+// their rows of C and J; one barrier per round.  Same rotation, tolerance,
+// carried norms and sweep limit as jacobi_core.
+constexpr int kPairGroupMax = 16;
+
+template <int NT, int CLS>
+__global__ __launch_bounds__(NT) void k_svd_pairs(Prob* probs) {
+  extern __shared__ zt lds[];  // C, then J: l columns of stride l | 1 each
+  __shared__ double nrm[64];
+  __shared__ double sig_s[64];
+  __shared__ int perm_s[64];
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
-  if (l == 0 || l > kTinySvdL) return;
-  const int lane = threadIdx.x;
+  if (l == 0 || svd_class(l) != CLS) return;
+  const int S = l | 1;
+  zt* Cs = lds;
+  zt* Js = lds + l * S;
+  const int tid = threadIdx.x;
   const zt zero = make_double2(0.0, 0.0);  // value, never addressed
-  for (int e = lane; e < l * l; e += 64) {
+  for (int e = tid; e < l * l; e += NT) {
     const int c = e / l, r = e - c * l;
     Cs[c * S + r] = zconj(P.Rb[size_t(r) * l + c]);
     Js[c * S + r] = make_double2(r == c ? 1.0 : 0.0, 0.0);
   }
-  __syncthreads();
   const int lp = l + (l & 1);
   int np2 = 1;
   while (np2 < lp / 2) np2 <<= 1;
-  const int G = 64 / np2;  // lanes per pair: 4 for l <= 32, more for smaller l
-  const int k = lane / G, h = lane - k * G;
+  const int G = NT / np2 < kPairGroupMax ? NT / np2 : kPairGroupMax;  // lanes per pair
+  const int k = tid / G, h = tid - k * G;
+  int lc2 = 1;
+  while (lc2 < l) lc2 <<= 1;
+  const int GN = NT / lc2 < kPairGroupMax ? NT / lc2 : kPairGroupMax;  // lanes per column
+  const int cn = tid / GN, hn = tid - cn * GN;
   const double tol = DBL_EPSILON * sqrt(double(l));
   constexpr int kMaxSweeps = 40;
   bool converged = (l == 1);
+  __syncthreads();
   for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
-    if (lane < l) nrm[lane] = col_norm2(Cs + lane * S, 0, l, 1);
+    double s = 0.0;
+    if (cn < l) s = col_norm2(Cs + cn * S, hn, l, GN);
+    s = group_sum(s, GN);
+    if (cn < l && hn == 0) nrm[cn] = s;
     __syncthreads();
-    bool any = false;
+    int any = 0;
     for (int round = 0; round < lp - 1; ++round) {
       int p = 0, q = 0;
       bool act = k < lp / 2;
@@ -1133,7 +1148,7 @@ __global__ __launch_bounds__(64) void k_small_svd_tiny(Prob* probs) {
         q = a < b ? b : a;
         act = q < l;
       }
-      zt gg = make_double2(0.0, 0.0);
+      zt gg = zero;
       if (act) gg = col_dot(Cs + p * S, Cs + q * S, h, l, G);
       const double gr = group_sum(gg.x, G), gi = group_sum(gg.y, G);
       if (act) {
@@ -1148,24 +1163,11 @@ __global__ __launch_bounds__(64) void k_small_svd_tiny(Prob* probs) {
           zt* cq = Cs + q * S;
           zt* jp = Js + p * S;
           zt* jq = Js + q * S;
-          int r = h;
-          for (; r + G < l; r += 2 * G) {  // two rows at once: loads in flight together
-            const zt x0 = cp[r], y0 = zmul(em, cq[r]), x1 = cp[r + G], y1 = zmul(em, cq[r + G]);
-            const zt a0 = jp[r], b0 = zmul(em, jq[r]), a1 = jp[r + G], b1 = zmul(em, jq[r + G]);
-            cp[r] = zsub(zscale(x0, cs), zscale(y0, sn));
-            cq[r] = zadd(zscale(x0, sn), zscale(y0, cs));
-            cp[r + G] = zsub(zscale(x1, cs), zscale(y1, sn));
-            cq[r + G] = zadd(zscale(x1, sn), zscale(y1, cs));
-            jp[r] = zsub(zscale(a0, cs), zscale(b0, sn));
-            jq[r] = zadd(zscale(a0, sn), zscale(b0, cs));
-            jp[r + G] = zsub(zscale(a1, cs), zscale(b1, sn));
-            jq[r + G] = zadd(zscale(a1, sn), zscale(b1, cs));
-          }
-          for (; r < l; r += G) {
+          for (int r = h; r < l; r += G) {
             const zt x = cp[r], y = zmul(em, cq[r]);
+            const zt xj = jp[r], yj = zmul(em, jq[r]);
             cp[r] = zsub(zscale(x, cs), zscale(y, sn));
             cq[r] = zadd(zscale(x, sn), zscale(y, cs));
-            const zt xj = jp[r], yj = zmul(em, jq[r]);
             jp[r] = zsub(zscale(xj, cs), zscale(yj, sn));
             jq[r] = zadd(zscale(xj, sn), zscale(yj, cs));
           }
@@ -1173,28 +1175,33 @@ __global__ __launch_bounds__(64) void k_small_svd_tiny(Prob* probs) {
             nrm[p] = fmax(app - t * ag, 0.0);
             nrm[q] = aqq + t * ag;
           }
-          any = true;
+          any = 1;
         }
       }
       __syncthreads();
     }
-    converged = __ballot(any) == 0;
+    converged = __syncthreads_or(any) == 0;
   }
-  if (!converged && lane == 0) P.flags |= TEBD_DEV_JACOBI_NOCONV;
+  if (!converged && tid == 0) P.flags |= TEBD_DEV_JACOBI_NOCONV;
   // singular values, descending order, sorted outputs
-  if (lane < l) sig_s[lane] = sqrt(col_norm2(Cs + lane * S, 0, l, 1));
+  {
+    double s = 0.0;
+    if (cn < l) s = col_norm2(Cs + cn * S, hn, l, GN);
+    s = group_sum(s, GN);
+    if (cn < l && hn == 0) sig_s[cn] = sqrt(s);
+  }
   __syncthreads();
-  if (lane < l) {
-    const double sj = sig_s[lane];
+  if (tid < l) {
+    const double sj = sig_s[tid];
     int rank = 0;
     for (int i = 0; i < l; ++i) {
       const double si = sig_s[i];
-      rank += (si > sj) || (si == sj && i < lane);
+      rank += (si > sj) || (si == sj && i < tid);
     }
-    perm_s[rank] = lane;
+    perm_s[rank] = tid;
   }
   __syncthreads();
-  for (int e = lane; e < l * l; e += 64) {
+  for (int e = tid; e < l * l; e += NT) {
     const int c = e / l, r = e - c * l;
     const int src = perm_s[c];
     const double sv = sig_s[src];
@@ -1202,11 +1209,12 @@ __global__ __launch_bounds__(64) void k_small_svd_tiny(Prob* probs) {
     P.X[e] = sv > 0.0 ? zscale(x, 1.0 / sv) : zero;
     P.W[e] = Js[src * S + r];
   }
-  if (lane < l) P.sig[lane] = sig_s[perm_s[lane]];
+  if (tid < l) P.sig[tid] = sig_s[perm_s[tid]];
 }
 
-// Size classes on 2 l^2 (C and J together), as for the QR.
-template <int NT, int HI, int LO, int REGS>
+// Classes 2 and 3: one pair per wavefront at a time (jacobi_core), C and J
+// in LDS (LDS_CJ) or in the problem's global scratch.
+template <int NT, int REGS, bool LDS_CJ>
 __global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
   extern __shared__ zt lds[];
   __shared__ double sig_s[kMaxL];
@@ -1215,10 +1223,9 @@ __global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
   __shared__ double nrm[kMaxL];
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
-  const int meas = 2 * l * l;
-  if (l == 0 || l <= kTinySvdL || meas <= LO || (HI > 0 && meas > HI)) return;
-  zt* C = HI > 0 ? lds : P.C;
-  zt* J = HI > 0 ? lds + l * l : P.J;
+  if (l == 0 || svd_class(l) != (LDS_CJ ? 2 : 3)) return;
+  zt* C = LDS_CJ ? lds : P.C;
+  zt* J = LDS_CJ ? lds + l * l : P.J;
   for (int e = threadIdx.x; e < l * l; e += NT) {
     const int c = e / l, r = e - c * l;
     C[e] = zconj(P.Rb[size_t(r) * l + c]);
@@ -1232,13 +1239,16 @@ __global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
 }
 
 hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s) {
-  static const hipError_t attr = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(&k_small_svd<1024, kLdsElems, 3072, 2>),
-      hipFuncAttributeMaxDynamicSharedMemorySize, int(size_t(kLdsElems) * sizeof(zt)));
+  static const hipError_t attr = []() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_small_svd<1024, 2, true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       int(size_t(kLdsElems) * sizeof(zt)));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_svd_pairs<512, 1>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               int(2 * 64 * 65 * sizeof(zt)));
+  }();
   if (attr != hipSuccess) return attr;
-  // l <= kTinySvdL runs in k_small_svd_tiny; the classes below see larger l
-  const int64_t lo_l = c.lmin > kTinySvdL ? c.lmin : kTinySvdL + 1;
-  const int64_t mhi = 2 * int64_t(c.lmax) * c.lmax, mlo = 2 * lo_l * lo_l;
   typedef void (*Launch)(hipStream_t, Prob*, int);
   struct Item {
     Launch fn;
@@ -1246,27 +1256,27 @@ hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s) {
     int nprob;
     void operator()(hipStream_t t) const { fn(t, probs, nprob); }
   };
+  const Launch fns[4] = {
+      [](hipStream_t t, Prob* p, int np) {
+        hipLaunchKernelGGL((k_svd_pairs<256, 0>), dim3(np), dim3(256), 2 * 32 * 33 * sizeof(zt), t,
+                           p);
+      },
+      [](hipStream_t t, Prob* p, int np) {
+        hipLaunchKernelGGL((k_svd_pairs<512, 1>), dim3(np), dim3(512), 2 * 64 * 65 * sizeof(zt), t,
+                           p);
+      },
+      [](hipStream_t t, Prob* p, int np) {
+        hipLaunchKernelGGL((k_small_svd<1024, 2, true>), dim3(np), dim3(1024),
+                           size_t(kLdsElems) * sizeof(zt), t, p);
+      },
+      [](hipStream_t t, Prob* p, int np) {
+        hipLaunchKernelGGL((k_small_svd<1024, 4, false>), dim3(np), dim3(1024), 0, t, p);
+      }};
+  // the problem's l here is the rank the range finder revealed
+  const int lo = svd_class(c.lmin < 1 ? 1 : c.lmin), hi = svd_class(c.lmax);
   Item items[4];
   int n = 0;
-  if (c.lmin <= kTinySvdL)
-    items[n++] = {[](hipStream_t t, Prob* p, int np) {
-                    hipLaunchKernelGGL(k_small_svd_tiny, dim3(np), dim3(64), 0, t, p);
-                  }, probs, c.nprob};
-  if (c.lmax > kTinySvdL && class_reached(mlo, mhi, 1024, 3072))
-    items[n++] = {[](hipStream_t t, Prob* p, int np) {
-                    hipLaunchKernelGGL((k_small_svd<256, 3072, 1024, 1>), dim3(np), dim3(256),
-                                       3072 * sizeof(zt), t, p);
-                  }, probs, c.nprob};
-  if (c.lmax > kTinySvdL && class_reached(mlo, mhi, 3072, kLdsElems))
-    items[n++] = {[](hipStream_t t, Prob* p, int np) {
-                    hipLaunchKernelGGL((k_small_svd<1024, kLdsElems, 3072, 2>), dim3(np), dim3(1024),
-                                       size_t(kLdsElems) * sizeof(zt), t, p);
-                  }, probs, c.nprob};
-  if (c.lmax > kTinySvdL && class_reached(mlo, mhi, kLdsElems, 0))
-    items[n++] = {[](hipStream_t t, Prob* p, int np) {
-                    hipLaunchKernelGGL((k_small_svd<1024, 0, kLdsElems, 4>), dim3(np), dim3(1024), 0, t,
-                                       p);
-                  }, probs, c.nprob};
+  for (int k = lo; k <= hi; ++k) items[n++] = {fns[k], probs, c.nprob};
   return fork_join(s, items, n, c);
 }
 
