@@ -107,7 +107,7 @@ SweepPlan plan_sweep(const tebd_mps& mps, const tebd_params& prm) {
   s.pmax = int64_t(mps.n_chains) * nb;
   s.mcap = int64_t(mps.d_max) * mps.chi_max;
   s.lcap = sketch_l(prm.chi_max, prm.p, s.mcap, s.mcap);
-  s.npart = int64_t((mps.d_max * mps.d_max + 63) / 64) * ((int64_t(mps.chi_max) * mps.chi_max + 63) / 64);
+  s.npart = gate_tiles(mps.d_max * mps.d_max, mps.chi_max * mps.chi_max);
   // descriptors, tile-queue offsets, then 256 bytes of counters
   s.desc_bytes = align256(size_t(s.pmax) * sizeof(Prob)) + align256(sched_bytes(s.pmax)) + 256;
   s.slab_sz = slab_bytes(s.mcap, s.mcap, s.lcap, 1, prm.precision, s.npart);
@@ -260,7 +260,9 @@ hipError_t timed(int kind, hipStream_t s, F&& launch) {
 }
 
 // Workgroups of the persistent contraction launches: enough to fill the 256
-// CUs several times over, never more than the largest possible tile count.
+// CUs a few times over, never more than the largest possible tile count.
+// Workgroups beyond the tiles still cost dispatch time, so launches whose
+// tile totals the host knows use those instead (grid_for).
 int32_t persistent_grid(int64_t cap_tiles) {
   int64_t g = cap_tiles < 2048 ? cap_tiles : 2048;
   g = (g + 7) / 8 * 8;
@@ -279,7 +281,7 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
   } while (0)
 #define TIMED(kind, call) TRY(timed(kind, s, [&]() { return (call); }))
   TIMED(PK_SCHEDULE, launch_schedule(probs, c, s));
-  if (c.bounds_dev) TRY(counters_async(c.bounds_dev, 6, s));
+  if (c.bounds_dev) TRY(counters_async(c.bounds_dev, 6 + TK_COUNT, s));
   if (c.tebd) {
     if (!c.pass2) TIMED(PK_THETA_GATE, launch_theta_gate(probs, c, s));
   } else {
@@ -293,14 +295,15 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
   };
   TIMED(PK_SKETCH_AOM, sketch(SK_Y_FROM_OMEGA));
   if (c.bounds_dev) {
-    int32_t b[6];
-    TRY(counters_wait(b, 6));
+    int32_t b[6 + TK_COUNT];
+    TRY(counters_wait(b, 6 + TK_COUNT));
     c.mmin = b[0];
     c.mmax = b[1];
     c.nmin = b[2];
     c.nmax = b[3];
     c.lmin = b[4];
     c.lmax = b[5];
+    for (int k = 0; k < TK_COUNT; ++k) c.ktiles[k] = b[6 + k];
   }
   TIMED(PK_QR, launch_qr(probs, c, 0, 0, s));
   for (int j = 0; j < c.q; ++j) {
@@ -361,8 +364,7 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
                                       align256(size_t(pl.pmax) * sizeof(Prob)));
   {
     const int64_t t = (pl.mcap + 63) / 64;
-    const int64_t tq = int64_t((mps->d_max * mps->d_max + 63) / 64) *
-                       ((int64_t(mps->chi_max) * mps->chi_max + 63) / 64);
+    const int64_t tq = gate_tiles(mps->d_max * mps->d_max, mps->chi_max * mps->chi_max);
     c.grid = persistent_grid(int64_t(c.nprob) * (t * t > tq ? t * t : tq));
   }
   if (c.nprob == 0) return ok();
@@ -375,15 +377,29 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
                              status, prm->lambda_floor, prm->precision, prm->adaptive,
                              reinterpret_cast<char*>(tape), pl.tape_slot, c.retry_count, s);
   });
-  // the host-synchronising adaptive mode also reads the batch's size bounds
-  if (c.adaptive == 2) c.bounds_dev = c.retry_count + 4;
+  // The host-synchronising adaptive mode also reads the batch's size bounds
+  // and tile totals.  Until they arrive, the grids of the first contractions
+  // follow the totals of the previous sweep of this parity on this host
+  // thread, with a quarter of headroom: any grid covers every tile (the
+  // launches are persistent), so the estimate only affects speed.
+  static thread_local int32_t last_tiles[2][TK_COUNT] = {{-1, -1, -1, -1, -1, -1, -1, -1},
+                                                         {-1, -1, -1, -1, -1, -1, -1, -1}};
+  if (c.adaptive == 2) {
+    c.bounds_dev = c.retry_count + 4;
+    for (int k = 0; k < TK_COUNT; ++k) {
+      const int32_t t = last_tiles[parity & 1][k];
+      c.ktiles[k] = t < 0 ? -1 : t + t / 4;
+    }
+  }
   if (e == hipSuccess) e = run_pipeline(probs, c, s);
   if (c.bounds_dev) {
+    for (int k = 0; k < TK_COUNT; ++k) last_tiles[parity & 1][k] = c.ktiles[k];
     // the second pass runs the fixed-rank stage: width min(chi_max + p, m, n)
     const int32_t l2 = prm->chi_max + prm->p;
     c.lmin = std::min(l2, std::min(c.mmin, c.nmin));
     c.lmax = std::min(l2, std::min(c.mmax, c.nmax));
     c.bounds_dev = nullptr;
+    for (int k = 0; k < TK_COUNT; ++k) c.ktiles[k] = -1;  // the second pass schedules anew
   }
   bool second = c.adaptive != 0;
   if (e == hipSuccess && c.adaptive == 2) {

@@ -41,6 +41,8 @@ __device__ __forceinline__ double lam_or_one(const double* lam, int i) {
 template <>
 struct TileKinds<AdjProb> {
   static constexpr int count = TA_COUNT;
+  static constexpr int tile_m(int) { return 64; }
+  static constexpr int tile_n(int) { return 64; }
   __device__ static __forceinline__ void shape(int kind, const AdjProb& P, int, int& M, int& N) {
     M = N = 0;
     if (P.L == 0) return;

@@ -17,17 +17,22 @@
 // (prefix sums over problems built by k_schedule).  Workgroup i takes the
 // virtual index (i mod 8) * G/8 + i / 8, so the consecutive tiles of one
 // problem, which share operand rows, land on the same XCD and its L2.
+#include <algorithm>
+
 #include "loaders.hpp"
 #include "tilequeue.hpp"
 
 namespace tebd {
 
 using Cfg64 = ZCfg<64, 64, 16, 2, 2>;
+using CfgGate = ZCfg<kGateTileM, kGateTileN, 16, 4, 1>;
 
 // Output shape of each contraction kind for problem P (0 x 0 when skipped).
 template <>
 struct TileKinds<Prob> {
   static constexpr int count = TK_COUNT;
+  static constexpr int tile_m(int kind) { return kind == TK_GATE ? kGateTileM : 64; }
+  static constexpr int tile_n(int kind) { return kind == TK_GATE ? kGateTileN : 64; }
   __device__ static __forceinline__ void shape(int kind, const Prob& P, int tebd, int& M, int& N) {
     M = N = 0;
     if (P.l == 0) return;
@@ -142,7 +147,7 @@ __global__ __launch_bounds__(256) void k_omega(Prob* probs, const int32_t* offs,
 }
 
 hipError_t launch_omega(Prob* probs, const Common& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_omega, dim3(c.grid), dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd,
+  hipLaunchKernelGGL(k_omega, dim3(grid_for(c, TK_SKN)), dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd,
                      c.seed, c.stream_id);
   return hipGetLastError();
 }
@@ -181,24 +186,24 @@ struct StGate {
 };
 
 __global__ __launch_bounds__(256) void k_gate(Prob* probs, const int32_t* offs, int nprob) {
-  __shared__ zt smem[Cfg64::lds_elems];
+  __shared__ zt smem[CfgGate::lds_elems];
   __shared__ double red[4];
   for_each_tile<TK_GATE>(probs, offs, nprob, 1,
                          [&](Prob& P, int M, int N, int m0, int n0, int local) {
                            LdGate la{P.gate, P.gate_ld};
                            LdRowB lb{P.T, N};
                            StGate st{P.A, P.chi_l, P.chi_r, P.dr, P.n, 0.0};
-                           zgemm_tile<Cfg64>(M, N, P.dl * P.dr, m0, n0, la, lb, st, smem);
+                           zgemm_tile<CfgGate>(M, N, P.dl * P.dr, m0, n0, la, lb, st, smem);
                            const double s = block_sum<256>(st.acc, red);
                            if (threadIdx.x == 0) P.part[local] = s;
                          });
 }
 
 hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_theta, dim3(c.grid), dim3(256), 0, s, probs, c.offs, c.nprob);
+  hipLaunchKernelGGL(k_theta, dim3(grid_for(c, TK_THETA)), dim3(256), 0, s, probs, c.offs, c.nprob);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gate, dim3(c.grid), dim3(256), 0, s, probs, c.offs, c.nprob);
+  hipLaunchKernelGGL(k_gate, dim3(grid_for(c, TK_GATE)), dim3(256), 0, s, probs, c.offs, c.nprob);
   return hipGetLastError();
 }
 
@@ -264,7 +269,7 @@ __global__ __launch_bounds__(256) void k_sketch_f32(Prob* probs, const int32_t* 
 }
 
 hipError_t launch_sketch_f32(Prob* probs, const Common& c, int which, hipStream_t s) {
-  dim3 g(c.grid);
+  const dim3 g(grid_for(c, which == SK_YT_FROM_Y ? TK_SKN : TK_SKM));
   if (which == SK_Y_FROM_OMEGA)
     hipLaunchKernelGGL(k_sketch_f32<SK_Y_FROM_OMEGA>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
   else if (which == SK_YT_FROM_Y)
@@ -275,7 +280,7 @@ hipError_t launch_sketch_f32(Prob* probs, const Common& c, int which, hipStream_
 }
 
 hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s) {
-  dim3 g(c.grid);
+  const dim3 g(grid_for(c, which == SK_YT_FROM_Y ? TK_SKN : TK_SKM));
   if (which == SK_Y_FROM_OMEGA)
     hipLaunchKernelGGL(k_sketch<SK_Y_FROM_OMEGA>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
   else if (which == SK_YT_FROM_Y)
@@ -397,13 +402,13 @@ __global__ __launch_bounds__(256) void k_form_vh(Prob* probs, const int32_t* off
 }
 
 hipError_t launch_form_uv(Prob* probs, const Common& c, hipStream_t s) {
-  dim3 g(c.grid);
+  const dim3 gu(grid_for(c, TK_FORMU)), gv(grid_for(c, TK_FORMV));
   if (c.tebd) {
-    hipLaunchKernelGGL(k_form_u<1>, g, dim3(256), 0, s, probs, c.offs, c.nprob);
-    hipLaunchKernelGGL(k_form_vh<1>, g, dim3(256), 0, s, probs, c.offs, c.nprob);
+    hipLaunchKernelGGL(k_form_u<1>, gu, dim3(256), 0, s, probs, c.offs, c.nprob);
+    hipLaunchKernelGGL(k_form_vh<1>, gv, dim3(256), 0, s, probs, c.offs, c.nprob);
   } else {
-    hipLaunchKernelGGL(k_form_u<0>, g, dim3(256), 0, s, probs, c.offs, c.nprob);
-    hipLaunchKernelGGL(k_form_vh<0>, g, dim3(256), 0, s, probs, c.offs, c.nprob);
+    hipLaunchKernelGGL(k_form_u<0>, gu, dim3(256), 0, s, probs, c.offs, c.nprob);
+    hipLaunchKernelGGL(k_form_vh<0>, gv, dim3(256), 0, s, probs, c.offs, c.nprob);
   }
   return hipGetLastError();
 }
@@ -460,7 +465,8 @@ __global__ __launch_bounds__(64) void k_tape_meta(Prob* probs, int pass2, int n_
 }
 
 hipError_t launch_tape(Prob* probs, const Common& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_tape_uv, dim3(c.grid), dim3(256), 0, s, probs, c.offs, c.nprob);
+  hipLaunchKernelGGL(k_tape_uv, dim3(std::max(grid_for(c, TK_TAPEU), grid_for(c, TK_TAPEV))),
+                     dim3(256), 0, s, probs, c.offs, c.nprob);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tape_meta, dim3(c.nprob), dim3(64), 0, s, probs, c.pass2, c.nsites);

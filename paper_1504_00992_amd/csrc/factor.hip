@@ -133,7 +133,7 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
                              int32_t* retry_count, hipStream_t s) {
   const int64_t mcap = int64_t(c.dmax) * c.chimax;
   const int64_t lcap = c.lmax;
-  const int64_t npart_cap = int64_t((c.dmax * c.dmax + 63) / 64) * ((c.chimax * c.chimax + 63) / 64);
+  const int64_t npart_cap = gate_tiles(c.dmax * c.dmax, c.chimax * c.chimax);
   hipLaunchKernelGGL(k_plan_sweep, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob, mps,
                      gates, gate_chain_stride, parity, single_chain, single_bond, c.kcap, p_over,
                      slab_base, slab_sz, mcap, mcap, lcap, npart_cap, disc, status, lambda_floor,
@@ -1300,7 +1300,7 @@ __global__ __launch_bounds__(64) void k_truncate(Prob* probs, double eps, int te
     double frob2 = P.frob2;
     if (tebd) {
       const int N = P.chi_l * P.chi_r, M = P.dl * P.dr;
-      const int npart = ((M + 63) / 64) * ((N + 63) / 64);
+      const int npart = gate_tiles(M, N);
       frob2 = 0.0;
       for (int i = 0; i < npart; ++i) frob2 += P.part[i];
       P.frob2 = frob2;

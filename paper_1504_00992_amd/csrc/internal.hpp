@@ -104,7 +104,9 @@ struct Common {
   int32_t record;    // 1: write the adjoint's tape
   int32_t nsites;    // TEBD: sites per chain
   int32_t* retry_count;  // device: problems whose first stage was rejected (adaptive rank)
-  int32_t* bounds_dev = nullptr;  // device: k_schedule writes {min, max} of m, n, l1 there
+  int32_t* bounds_dev = nullptr;  // device: k_schedule writes {min, max} of m, n, l1 there,
+                                  // then the tile total of every kind
+  int32_t ktiles[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
 };
@@ -123,7 +125,29 @@ enum {
   TK_COUNT = 8
 };
 
+static_assert(TK_COUNT == 8, "Common::ktiles holds one total per kind");
+
+// Output tile of the gate product, (dl dr) x (chi_l chi_r): tall and narrow,
+// because the gate side has a few dozen to a few hundred rows while the bond
+// side is often a single column (a 64 x 64 tile would spend almost all of
+// its FP64 matrix-core work on padding).  One Frobenius partial sum per tile.
+constexpr int kGateTileM = 128, kGateTileN = 16;
+__host__ __device__ inline int gate_tiles(int M, int N) {
+  return (M <= 0 || N <= 0) ? 0 : ((M + kGateTileM - 1) / kGateTileM) * ((N + kGateTileN - 1) / kGateTileN);
+}
+
 inline size_t sched_bytes(int64_t nprob) { return size_t(TK_COUNT) * size_t(nprob + 1) * sizeof(int32_t); }
+
+// Workgroups of a persistent launch over the tiles of `kind`: the kind's
+// tile total when the host knows it, else the capacity-based c.grid; a
+// multiple of 8 (the XCD-aware tile mapping), at least 8, at most c.grid.
+inline int32_t grid_for(const Common& c, int kind) {
+  const int32_t t = c.ktiles[kind];
+  if (t < 0) return c.grid;
+  int32_t g = (t + 7) / 8 * 8;
+  if (g < 8) g = 8;
+  return g < c.grid ? g : c.grid;
+}
 
 
 // Launchers (defined in the .hip files).  All enqueue on `s` and return the

@@ -2,7 +2,7 @@
 // device.
 //
 // Every contraction kind k has, per batch, an exclusive prefix sum over
-// problems of its 64 x 64 output-tile counts (offs[k][p], offs[k][nprob] =
+// problems of its output-tile counts (offs[k][p], offs[k][nprob] =
 // total), built on the device by k_schedule.  A persistent launch then walks
 // the global tile index t = vb, vb + G, ... where vb = (i mod 8) * G/8 + i / 8
 // for workgroup i of G: consecutive tiles of one problem, which share
@@ -11,7 +11,9 @@
 // A descriptor type PT plugs in through TileKinds<PT>:
 //   static constexpr int count;   number of kinds
 //   static __device__ void shape(int kind, const PT&, int flag, int& M, int& N);
-// (M x N = 0 x 0 when the problem has no tiles of that kind), and, for
+// (M x N = 0 x 0 when the problem has no tiles of that kind),
+//   static constexpr int tile_m(int kind), tile_n(int kind);   the kind's tile
+// (64 x 64 unless a kind's shapes call for another), and, for
 // k_schedule<PT, true>, static __device__ bool dims(const PT&, int d[3])
 // (false for an inactive problem).
 #pragma once
@@ -23,15 +25,15 @@ namespace tebd {
 template <class PT>
 struct TileKinds;
 
-__device__ __forceinline__ int tiles_of(int M, int N) {
-  return (M <= 0 || N <= 0) ? 0 : ((M + 63) / 64) * ((N + 63) / 64);
+__host__ __device__ __forceinline__ int tiles_of(int M, int N, int tm = 64, int tn = 64) {
+  return (M <= 0 || N <= 0) ? 0 : ((M + tm - 1) / tm) * ((N + tn - 1) / tn);
 }
 
 template <class PT>
 __device__ __forceinline__ int kind_tiles(int kind, const PT& P, int flag) {
   int M, N;
   TileKinds<PT>::shape(kind, P, flag, M, N);
-  return tiles_of(M, N);
+  return tiles_of(M, N, TileKinds<PT>::tile_m(kind), TileKinds<PT>::tile_n(kind));
 }
 
 // Exclusive prefix sums of tile counts for every kind (one workgroup):
@@ -41,7 +43,8 @@ __device__ __forceinline__ int kind_tiles(int kind, const PT& P, int flag) {
 // gives every chunk its starts; a second pass writes the chunk's offsets.
 // With BOUNDS, the same pass also writes the smallest and largest sizes
 // over the active problems, {min, max} of each of TileKinds<PT>::dims
-// (three values), to bounds[0..6); an empty batch gives {1, 1} each.
+// (three values), to bounds[0..6) (an empty batch gives {1, 1} each), and
+// the tile total of every kind to bounds[6..6 + count).
 template <class PT, bool BOUNDS = false>
 __global__ __launch_bounds__(256) void k_schedule(const PT* probs, int nprob, int flag,
                                                   int32_t* offs, int32_t* bounds = nullptr) {
@@ -105,6 +108,7 @@ __global__ __launch_bounds__(256) void k_schedule(const PT* probs, int nprob, in
     }
     run[k] = base + incl[k] - own[k];
     if (tid == 0) offs[size_t(k) * (nprob + 1) + nprob] = total;
+    if (BOUNDS && tid == 0) bounds[6 + k] = total;
   }
   for (int p = p0; p < p1; ++p) {
     const PT& P = probs[p];
@@ -149,11 +153,12 @@ __device__ __forceinline__ void for_each_tile(PT* probs, const int32_t* offs, in
     const int local = t - off[p];
     // a size may have shrunk since the queue was built (the range finder
     // lowers l): tiles of the old shape that now lie outside are skipped
-    const int tiles_n = (N + 63) / 64;
+    constexpr int TM = TileKinds<PT>::tile_m(KIND), TN = TileKinds<PT>::tile_n(KIND);
+    const int tiles_n = (N + TN - 1) / TN;
     if (tiles_n == 0) continue;
     const int tm = local / tiles_n, tn = local - tm * tiles_n;
-    if (tm * 64 >= M) continue;
-    body(P, M, N, tm * 64, tn * 64, local);
+    if (tm * TM >= M) continue;
+    body(P, M, N, tm * TM, tn * TN, local);
   }
 }
 
