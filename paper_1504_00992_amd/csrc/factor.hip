@@ -572,22 +572,19 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
       rank = j;
       break;
     }
-    if (g == p) {  // reflector from the pivot column
-      double s2 = 0.0, ax = 0.0, ay = 0.0;
+    if (g == p) {  // reflector from the pivot column, whose trailing norm is `best`
+      // row j sits in register j / G of the group's lane j % G (uniform)
+      const int i0 = j / G, hj = j - i0 * G, lj = (p * G + hj) & 63;
+      double ax = 0.0, ay = 0.0;
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int r = h + G * i;
-        const double a2 = zabs2(y[i]);
-        s2 += r > j ? a2 : 0.0;
-        ax = r == j ? y[i].x : ax;
-        ay = r == j ? y[i].y : ay;
-      }
-      s2 = group_sum(s2, G);
-      ax = group_sum(ax, G);  // one lane of the group holds row j
-      ay = group_sum(ay, G);
+      for (int i = 0; i < RPL; ++i)
+        if (i == i0) {
+          ax = read_lane(y[i].x, lj);
+          ay = read_lane(y[i].y, lj);
+        }
       const zt alpha = make_double2(ax, ay);
       const double aa = sqrt(zabs2(alpha));
-      const double xnorm = sqrt(aa * aa + s2);
+      const double xnorm = pn;  // ||column p, rows >= j||
       zt beta = zero, v0 = zero;
       double vinv = 0.0;
       if (xnorm > 0.0) {
@@ -596,16 +593,26 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
         v0 = zsub(alpha, beta);
         vinv = 1.0 / sqrt(2.0 * xnorm * (xnorm + aa));
       }
+      // u = (x - beta e_j) / ||x - beta e_j|| on rows >= j, kept in the
+      // registers for the Q accumulation (rows < j keep R) and published;
+      // the previous pivot row of the buffer is cleared, so rows < j read 0
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
         const int r = h + G * i;
-        const double sx = r == j ? v0.x : y[i].x, sy = r == j ? v0.y : y[i].y;
-        const double mx = r >= j ? sx * vinv : 0.0, my = r >= j ? sy * vinv : 0.0;
-        us[0][r] = make_double2(mx, my);
-        // rows >= j now hold u (kept for the Q accumulation), rows < j R
-        y[i].x = r >= j ? mx : y[i].x;
-        y[i].y = r >= j ? my : y[i].y;
+        if (r >= j && r < rows) {
+          const zt uu = zscale(y[i], vinv);
+          y[i] = uu;
+          us[0][r] = uu;
+        }
       }
+      const zt u0 = zscale(v0, vinv);
+#pragma unroll
+      for (int i = 0; i < RPL; ++i)
+        if (i == i0 && h == hj) {
+          y[i] = u0;
+          us[0][j] = u0;
+        }
+      if (j > 0 && h == (j - 1) % G) us[0][j - 1] = zero;
       if (h == 0) rdiag[j] = beta;
       mine = j;
     }
@@ -681,26 +688,29 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
     zt* ub = us[j & 1];
     const int p = piv_grp[j];
     if (g == p) {
+      const int i0 = j / G, hj = j - i0 * G, lj = (p * G + hj) & 63;
       double ux = 0.0, uy = 0.0;
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const bool at = h + G * i == j;
-        ux = at ? y[i].x : ux;
-        uy = at ? y[i].y : uy;
-      }
-      ux = group_sum(ux, G);
-      uy = group_sum(uy, G);
-      const zt cuj = make_double2(ux, -uy);
+      for (int i = 0; i < RPL; ++i)
+        if (i == i0) {
+          ux = read_lane(y[i].x, lj);
+          uy = read_lane(y[i].y, lj);
+        }
+      const zt cuj = make_double2(ux, -uy);  // conj(u_j[j])
+      // publish u_j (rows < j of this buffer are zero) and become H_j e_j
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
         const int r = h + G * i;
-        const bool on = r >= j;  // rows >= rows hold zeros
-        const zt u = make_double2(on ? y[i].x : 0.0, on ? y[i].y : 0.0);
-        ub[r] = u;
-        zt v = zscale(zmul(u, cuj), -2.0);
-        if (r == j) v.x += 1.0;
-        y[i] = v;
+        if (r >= j && r < rows) {
+          ub[r] = y[i];
+          y[i] = zscale(zmul(y[i], cuj), -2.0);
+        } else {
+          y[i] = zero;
+        }
       }
+#pragma unroll
+      for (int i = 0; i < RPL; ++i)
+        if (i == i0 && h == hj) y[i].x += 1.0;
     }
     __syncthreads();
     if (have && mine > j && mine < rank) {
