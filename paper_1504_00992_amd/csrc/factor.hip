@@ -683,37 +683,42 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
   }
   // Q = H_0 ... H_{r-1} [I; 0] from the last reflector backwards: the group
   // of logical column j publishes u_j and becomes H_j e_j, the groups of
-  // later logical columns apply H_j
-  for (int j = rank - 1; j >= 0; --j) {
+  // later logical columns apply H_j.  Column j is not touched by H_j or
+  // later reflectors, so its group publishes u_j while H_{j+1} is being
+  // applied (the buffers alternate): one barrier per step, and the
+  // publication is off the chain of dependent steps.
+  auto publish = [&](int j) {
     zt* ub = us[j & 1];
-    const int p = piv_grp[j];
-    if (g == p) {
-      const int i0 = j / G, hj = j - i0 * G, lj = (p * G + hj) & 63;
-      double ux = 0.0, uy = 0.0;
+    const int i0 = j / G, hj = j - i0 * G, lj = (g * G + hj) & 63;  // g = piv_grp[j]
+    double ux = 0.0, uy = 0.0;
 #pragma unroll
-      for (int i = 0; i < RPL; ++i)
-        if (i == i0) {
-          ux = read_lane(y[i].x, lj);
-          uy = read_lane(y[i].y, lj);
-        }
-      const zt cuj = make_double2(ux, -uy);  // conj(u_j[j])
-      // publish u_j (rows < j of this buffer are zero) and become H_j e_j
-#pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int r = h + G * i;
-        if (r >= j && r < rows) {
-          ub[r] = y[i];
-          y[i] = zscale(zmul(y[i], cuj), -2.0);
-        } else {
-          y[i] = zero;
-        }
+    for (int i = 0; i < RPL; ++i)
+      if (i == i0) {
+        ux = read_lane(y[i].x, lj);
+        uy = read_lane(y[i].y, lj);
       }
+    const zt cuj = make_double2(ux, -uy);  // conj(u_j[j])
+    // rows < j of this buffer are zero
 #pragma unroll
-      for (int i = 0; i < RPL; ++i)
-        if (i == i0 && h == hj) y[i].x += 1.0;
+    for (int i = 0; i < RPL; ++i) {
+      const int r = h + G * i;
+      if (r >= j && r < rows) {
+        ub[r] = y[i];
+        y[i] = zscale(zmul(y[i], cuj), -2.0);
+      } else {
+        y[i] = zero;
+      }
     }
-    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+      if (i == i0 && h == hj) y[i].x += 1.0;
+  };
+  if (rank > 0 && mine == rank - 1) publish(rank - 1);
+  for (int j = rank - 1; j >= 0; --j) {
+    __syncthreads();  // u_j is published; the reads of the other buffer are done
+    if (j > 0 && mine == j - 1) publish(j - 1);
     if (have && mine > j && mine < rank) {
+      const zt* ub = us[j & 1];
       zt uu[KEEP];
       double dr0 = 0.0, di0 = 0.0, dr1 = 0.0, di1 = 0.0;
 #pragma unroll
