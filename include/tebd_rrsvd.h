@@ -111,7 +111,9 @@ typedef struct {
  * + alpha * chi_max + beta].  Bond b (sites b, b+1) holds lambda^[b] at
  * lambda[(c * (n_sites - 1) + b) * chi_max + j], zero beyond chi_{b+1}.
  * chi[c * (n_sites + 1) + k] = chi_k with chi_0 = chi_N = 1.  Entries outside
- * the current chi are kept at zero by the library. */
+ * the current chi must be zero on input; the library keeps them zero (an
+ * update rewrites the updated bond's index only up to the larger of its old
+ * and new dimension). */
 typedef struct {
   int32_t n_chains, n_sites, d_max, chi_max;
   const int32_t* d; /* device [n_sites], 1 <= d[k] <= d_max                    */

@@ -17,8 +17,6 @@
 // (prefix sums over problems built by k_schedule).  Workgroup i takes the
 // virtual index (i mod 8) * G/8 + i / 8, so the consecutive tiles of one
 // problem, which share operand rows, land on the same XCD and its L2.
-#include <algorithm>
-
 #include "loaders.hpp"
 #include "tilequeue.hpp"
 
@@ -26,6 +24,16 @@ namespace tebd {
 
 using Cfg64 = ZCfg<64, 64, 16, 2, 2>;
 using CfgGate = ZCfg<kGateTileM, kGateTileN, 16, 4, 1>;
+
+// Extent of the updated bond index that a TEBD update writes in Gamma^[k]
+// (columns) and Gamma^[k+1] (rows): the new dimension chi' <= min(l, chi_max)
+// and, cleared to zero, the old one chi_m; beyond both the arrays are
+// already zero, so the padding up to the capacity is not rewritten.
+__device__ __forceinline__ int updated_bond_extent(const Prob& P) {
+  const int kept = P.l < P.kcap ? P.l : P.kcap;
+  const int e = kept > P.chi_m ? kept : P.chi_m;
+  return e < P.chi_cap ? e : P.chi_cap;
+}
 
 // Output shape of each contraction kind for problem P (0 x 0 when skipped).
 template <>
@@ -57,12 +65,12 @@ struct TileKinds<Prob> {
         M = P.n;
         N = P.l;
         break;
-      case TK_FORMU:
+      case TK_FORMU:  // TEBD: the new bond's columns, and the old ones beyond it (cleared)
         M = P.m;
-        N = tebd ? P.chi_cap : P.kcap;
+        N = tebd ? updated_bond_extent(P) : P.kcap;
         break;
       case TK_FORMV:
-        M = tebd ? P.chi_cap : P.kcap;
+        M = tebd ? updated_bond_extent(P) : P.kcap;
         N = P.n;
         break;
       case TK_TAPEU:
@@ -92,11 +100,11 @@ struct TileKinds<Prob> {
 
 hipError_t launch_schedule(Prob* probs, const Common& c, hipStream_t s) {
   if (c.bounds_dev)
-    hipLaunchKernelGGL((k_schedule<Prob, true>), dim3(1), dim3(256), 0, s, probs, c.nprob, c.tebd,
-                       c.offs, c.bounds_dev);
+    hipLaunchKernelGGL((k_schedule<Prob, true>), dim3(1), dim3(kScheduleThreads), 0, s, probs,
+                       c.nprob, c.tebd, c.offs, c.bounds_dev);
   else
-    hipLaunchKernelGGL((k_schedule<Prob, false>), dim3(1), dim3(256), 0, s, probs, c.nprob,
-                       c.tebd, c.offs, nullptr);
+    hipLaunchKernelGGL((k_schedule<Prob, false>), dim3(1), dim3(kScheduleThreads), 0, s, probs,
+                       c.nprob, c.tebd, c.offs, nullptr);
   return hipGetLastError();
 }
 
@@ -419,20 +427,21 @@ hipError_t launch_form_uv(Prob* probs, const Common& c, hipStream_t s) {
 // the geometry, written once per bond in the pass that finishes it.
 __global__ __launch_bounds__(256) void k_tape_uv(Prob* probs, const int32_t* offs, int nprob) {
   __shared__ zt smem[Cfg64::lds_elems];
-  for_each_tile<TK_TAPEU>(probs, offs, nprob, 1, [&](Prob& P, int M, int N, int m0, int n0, int) {
+  auto tape_u = [&](Prob& P, int M, int N, int m0, int n0, int) {
     if (P.retry) return;
     LdQP la{P.Y, P.m, P.piv};
     LdSmallColB lb{P.X, P.l};
     StRow st{P.tape_u, P.tape_ldu};
     zgemm_tile<Cfg64>(M, N, P.l, m0, n0, la, lb, st, smem);
-  });
-  for_each_tile<TK_TAPEV>(probs, offs, nprob, 1, [&](Prob& P, int M, int N, int m0, int n0, int) {
+  };
+  auto tape_vh = [&](Prob& P, int M, int N, int m0, int n0, int) {
     if (P.retry) return;
     LdSmallAdjA la{P.W, P.l};
     LdQbAdjB lb{P.Yt, P.n};
     StRow st{P.tape_vh, P.tape_ldvh};
     zgemm_tile<Cfg64>(M, N, P.l, m0, n0, la, lb, st, smem);
-  });
+  };
+  for_each_tile2<TK_TAPEU, TK_TAPEV>(probs, offs, nprob, 1, tape_u, tape_vh);
 }
 
 // One wavefront per problem: header and singular values.  A problem the
@@ -465,8 +474,8 @@ __global__ __launch_bounds__(64) void k_tape_meta(Prob* probs, int pass2, int n_
 }
 
 hipError_t launch_tape(Prob* probs, const Common& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_tape_uv, dim3(std::max(grid_for(c, TK_TAPEU), grid_for(c, TK_TAPEV))),
-                     dim3(256), 0, s, probs, c.offs, c.nprob);
+  hipLaunchKernelGGL(k_tape_uv, dim3(grid_for(c, TK_TAPEU, TK_TAPEV)), dim3(256), 0, s, probs,
+                     c.offs, c.nprob);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_tape_meta, dim3(c.nprob), dim3(64), 0, s, probs, c.pass2, c.nsites);

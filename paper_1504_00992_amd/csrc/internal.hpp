@@ -138,11 +138,13 @@ __host__ __device__ inline int gate_tiles(int M, int N) {
 
 inline size_t sched_bytes(int64_t nprob) { return size_t(TK_COUNT) * size_t(nprob + 1) * sizeof(int32_t); }
 
-// Workgroups of a persistent launch over the tiles of `kind`: the kind's
-// tile total when the host knows it, else the capacity-based c.grid; a
-// multiple of 8 (the XCD-aware tile mapping), at least 8, at most c.grid.
-inline int32_t grid_for(const Common& c, int kind) {
-  const int32_t t = c.ktiles[kind];
+// Workgroups of a persistent launch over the tiles of `kind` (and of
+// `kind2`, when two queues share the launch): their tile total when the host
+// knows it, else the capacity-based c.grid; a multiple of 8 (the XCD-aware
+// tile mapping), at least 8, at most c.grid.
+inline int32_t grid_for(const Common& c, int kind, int kind2 = -1) {
+  int32_t t = c.ktiles[kind];
+  if (kind2 >= 0) t = (t < 0 || c.ktiles[kind2] < 0) ? -1 : t + c.ktiles[kind2];
   if (t < 0) return c.grid;
   int32_t g = (t + 7) / 8 * 8;
   if (g < 8) g = 8;

@@ -36,23 +36,27 @@ __device__ __forceinline__ int kind_tiles(int kind, const PT& P, int flag) {
   return tiles_of(M, N, TileKinds<PT>::tile_m(kind), TileKinds<PT>::tile_n(kind));
 }
 
-// Exclusive prefix sums of tile counts for every kind (one workgroup):
-// thread t reads its contiguous chunk of problems once and sums the tiles
-// of every kind; a block-wide scan per kind (shuffle scan inside each
-// wavefront, then the four wavefront totals, one barrier for all kinds)
-// gives every chunk its starts; a second pass writes the chunk's offsets.
+// Exclusive prefix sums of tile counts for every kind (one workgroup of
+// kScheduleThreads): thread t reads its contiguous chunk of problems once
+// and sums the tiles of every kind; a block-wide scan per kind (shuffle scan
+// inside each wavefront, then one thread per kind scans the wavefront
+// totals) gives every chunk its starts; a second pass writes the chunk's
+// offsets (from the counts kept in registers when the chunk is one problem).
 // With BOUNDS, the same pass also writes the smallest and largest sizes
 // over the active problems, {min, max} of each of TileKinds<PT>::dims
 // (three values), to bounds[0..6) (an empty batch gives {1, 1} each), and
 // the tile total of every kind to bounds[6..6 + count).
+constexpr int kScheduleThreads = 1024;
+
 template <class PT, bool BOUNDS = false>
-__global__ __launch_bounds__(256) void k_schedule(const PT* probs, int nprob, int flag,
-                                                  int32_t* offs, int32_t* bounds = nullptr) {
-  constexpr int NK = TileKinds<PT>::count;
-  __shared__ int32_t wsum[NK][4];
+__global__ __launch_bounds__(kScheduleThreads) void k_schedule(const PT* probs, int nprob,
+                                                               int flag, int32_t* offs,
+                                                               int32_t* bounds = nullptr) {
+  constexpr int NK = TileKinds<PT>::count, NT = kScheduleThreads, NW = NT / 64;
+  __shared__ int32_t wsum[NK][NW];
   __shared__ int32_t ext[6];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int chunk = (nprob + 255) / 256;
+  const int chunk = (nprob + NT - 1) / NT;
   const int p0 = min(nprob, tid * chunk), p1 = min(nprob, p0 + chunk);
   int32_t own[NK], incl[NK];
   int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {0, 0, 0};
@@ -66,6 +70,7 @@ __global__ __launch_bounds__(256) void k_schedule(const PT* probs, int nprob, in
     if constexpr (BOUNDS) {
       int d[3];
       if (TileKinds<PT>::dims(P, d))
+#pragma unroll
         for (int i = 0; i < 3; ++i) {
           lo[i] = min(lo[i], d[i]);
           hi[i] = max(hi[i], d[i]);
@@ -85,6 +90,7 @@ __global__ __launch_bounds__(256) void k_schedule(const PT* probs, int nprob, in
   }
   if constexpr (BOUNDS) {
     __syncthreads();  // ext is initialised
+#pragma unroll
     for (int i = 0; i < 3; ++i) {
       if (hi[i] > 0) {
         atomicMin(&ext[2 * i], lo[i]);
@@ -96,19 +102,25 @@ __global__ __launch_bounds__(256) void k_schedule(const PT* probs, int nprob, in
   if constexpr (BOUNDS) {
     if (tid < 6) bounds[tid] = ext[tid | 1] > 0 ? ext[tid] : 1;
   }
+  if (tid < NK) {  // exclusive scan of the wavefront totals, one thread per kind
+    int32_t acc = 0;
+    for (int w = 0; w < NW; ++w) {
+      const int32_t ws = wsum[tid][w];
+      wsum[tid][w] = acc;
+      acc += ws;
+    }
+    offs[size_t(tid) * (nprob + 1) + nprob] = acc;
+    if (BOUNDS) bounds[6 + tid] = acc;
+  }
+  __syncthreads();
   int32_t run[NK];
 #pragma unroll
-  for (int k = 0; k < NK; ++k) {
-    int32_t base = 0, total = 0;
+  for (int k = 0; k < NK; ++k) run[k] = wsum[k][wave] + incl[k] - own[k];
+  if (chunk == 1) {
+    if (p0 < p1)
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      const int32_t ws = wsum[k][w];
-      if (w < wave) base += ws;
-      total += ws;
-    }
-    run[k] = base + incl[k] - own[k];
-    if (tid == 0) offs[size_t(k) * (nprob + 1) + nprob] = total;
-    if (BOUNDS && tid == 0) bounds[6 + k] = total;
+      for (int k = 0; k < NK; ++k) offs[size_t(k) * (nprob + 1) + p0] = run[k];
+    return;
   }
   for (int p = p0; p < p1; ++p) {
     const PT& P = probs[p];
@@ -138,27 +150,47 @@ __device__ __forceinline__ int virtual_block() {
   return (i & 7) * (g >> 3) + (i >> 3);
 }
 
-// Iterate over this workgroup's tiles of one kind:
-// body(P, M, N, m0, n0, tile_index_within_problem).
+// Run global tile t of one kind: body(P, M, N, m0, n0, tile_index_within_problem).
+template <int KIND, class PT, class Body>
+__device__ __forceinline__ void run_tile(PT* probs, const int32_t* off, int nprob, int flag, int t,
+                                         Body& body) {
+  const int p = find_problem(off, nprob, t);
+  PT& P = probs[p];
+  int M, N;
+  TileKinds<PT>::shape(KIND, P, flag, M, N);
+  const int local = t - off[p];
+  // a size may have shrunk since the queue was built (the range finder
+  // lowers l): tiles of the old shape that now lie outside are skipped
+  constexpr int TM = TileKinds<PT>::tile_m(KIND), TN = TileKinds<PT>::tile_n(KIND);
+  const int tiles_n = (N + TN - 1) / TN;
+  if (tiles_n == 0) return;
+  const int tm = local / tiles_n, tn = local - tm * tiles_n;
+  if (tm * TM >= M) return;
+  body(P, M, N, tm * TM, tn * TN, local);
+}
+
+// Iterate over this workgroup's tiles of one kind.
 template <int KIND, class PT, class Body>
 __device__ __forceinline__ void for_each_tile(PT* probs, const int32_t* offs, int nprob, int flag,
                                               Body body) {
   const int32_t* off = offs + size_t(KIND) * (nprob + 1);
   const int total = off[nprob];
+  for (int t = virtual_block(); t < total; t += gridDim.x)
+    run_tile<KIND>(probs, off, nprob, flag, t, body);
+}
+
+// Two independent kinds as one queue: the tiles of K1, then those of K2.
+template <int K1, int K2, class PT, class B1, class B2>
+__device__ __forceinline__ void for_each_tile2(PT* probs, const int32_t* offs, int nprob, int flag,
+                                               B1 body1, B2 body2) {
+  const int32_t* off1 = offs + size_t(K1) * (nprob + 1);
+  const int32_t* off2 = offs + size_t(K2) * (nprob + 1);
+  const int total1 = off1[nprob], total = total1 + off2[nprob];
   for (int t = virtual_block(); t < total; t += gridDim.x) {
-    const int p = find_problem(off, nprob, t);
-    PT& P = probs[p];
-    int M, N;
-    TileKinds<PT>::shape(KIND, P, flag, M, N);
-    const int local = t - off[p];
-    // a size may have shrunk since the queue was built (the range finder
-    // lowers l): tiles of the old shape that now lie outside are skipped
-    constexpr int TM = TileKinds<PT>::tile_m(KIND), TN = TileKinds<PT>::tile_n(KIND);
-    const int tiles_n = (N + TN - 1) / TN;
-    if (tiles_n == 0) continue;
-    const int tm = local / tiles_n, tn = local - tm * tiles_n;
-    if (tm * TM >= M) continue;
-    body(P, M, N, tm * TM, tn * TN, local);
+    if (t < total1)
+      run_tile<K1>(probs, off1, nprob, flag, t, body1);
+    else
+      run_tile<K2>(probs, off2, nprob, flag, t - total1, body2);
   }
 }
 
