@@ -583,15 +583,17 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
           ay = read_lane(y[i].y, lj);
         }
       const zt alpha = make_double2(ax, ay);
-      const double aa = sqrt(zabs2(alpha));
+      const double a2 = zabs2(alpha);
+      const double ia = a2 > 0.0 ? rsqrt(a2) : 0.0;  // 1 / |alpha|
+      const double aa = a2 * ia;
       const double xnorm = pn;  // ||column p, rows >= j||
       zt beta = zero, v0 = zero;
       double vinv = 0.0;
       if (xnorm > 0.0) {
-        const zt ph = aa > 0.0 ? zscale(alpha, 1.0 / aa) : make_double2(1.0, 0.0);
+        const zt ph = aa > 0.0 ? zscale(alpha, ia) : make_double2(1.0, 0.0);
         beta = zscale(ph, -xnorm);
         v0 = zsub(alpha, beta);
-        vinv = 1.0 / sqrt(2.0 * xnorm * (xnorm + aa));
+        vinv = rsqrt(2.0 * xnorm * (xnorm + aa));
       }
       // u = (x - beta e_j) / ||x - beta e_j|| on rows >= j, kept in the
       // registers for the Q accumulation (rows < j keep R) and published;
@@ -970,6 +972,27 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStr
 // C and J live in LDS when 2 l^2 fits, else in global memory; a pair's
 // columns are held in registers (l <= 64 * REGS) for the whole rotation.
 
+// Rotation of a column pair with Gram entries a = |c_p|^2, b = |c_q|^2 and
+// g = c_p^H c_q (given as gr + i gi): false when |g| <= tol sqrt(a b).
+// Otherwise zeta = (b - a) / (2|g|), t = sign(zeta) / (|zeta| + sqrt(1 +
+// zeta^2)), cs = 1 / sqrt(1 + t^2), sn = t cs, em = e^{-i arg g}, and
+// ag = |g| (the carried norms move by t |g|).  Reciprocal square roots keep
+// the chain of dependent operations short.
+__device__ __forceinline__ bool jacobi_rotation(double gr, double gi, double a, double b,
+                                                double tol, double& ag, double& t, double& cs,
+                                                double& sn, zt& em) {
+  const double g2 = gr * gr + gi * gi;
+  if (!(g2 > tol * tol * (a * b)) || g2 == 0.0) return false;
+  const double ig = rsqrt(g2);  // 1 / |g|
+  ag = g2 * ig;
+  const double zeta = 0.5 * (b - a) * ig;
+  t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  cs = rsqrt(1.0 + t * t);
+  sn = t * cs;
+  em = make_double2(gr * ig, -gi * ig);
+  return true;
+}
+
 __device__ __forceinline__ int circle_player(int pos, int round, int lp) {
   if (pos == 0) return 0;
   return 1 + (pos - 1 + round) % (lp - 1);
@@ -1022,12 +1045,9 @@ __device__ __forceinline__ void jacobi_core(zt* C, zt* J, int l, int& converged_
         gr = wave_sum(gr);
         gi = wave_sum(gi);
         const double app = nrm[p], aqq = nrm[q];
-        const double ag = sqrt(gr * gr + gi * gi);
-        if (!(ag > tol * sqrt(app * aqq)) || ag == 0.0) continue;
-        const double zeta = (aqq - app) / (2.0 * ag);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
-        const zt em = make_double2(gr / ag, -gi / ag);  // e^{-i phi}
+        double ag, t, cs, sn;
+        zt em;  // e^{-i phi}
+        if (!jacobi_rotation(gr, gi, app, aqq, tol, ag, t, cs, sn, em)) continue;
 #pragma unroll
         for (int i = 0; i < REGS; ++i) {
           const int r = lane + 64 * i;
@@ -1168,12 +1188,9 @@ __global__ __launch_bounds__(NT) void k_svd_pairs(Prob* probs) {
       const double gr = group_sum(gg.x, G), gi = group_sum(gg.y, G);
       if (act) {
         const double app = nrm[p], aqq = nrm[q];
-        const double ag = sqrt(gr * gr + gi * gi);
-        if (ag > tol * sqrt(app * aqq) && ag != 0.0) {
-          const double zeta = (aqq - app) / (2.0 * ag);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
-          const zt em = make_double2(gr / ag, -gi / ag);  // e^{-i phi}
+        double ag, t, cs, sn;
+        zt em;  // e^{-i phi}
+        if (jacobi_rotation(gr, gi, app, aqq, tol, ag, t, cs, sn, em)) {
           zt* cp = Cs + p * S;
           zt* cq = Cs + q * S;
           zt* jp = Js + p * S;
