@@ -115,7 +115,11 @@ def roofline(prof, flops):
     """Roofline entry for the kind with the largest event time."""
     kind = max(prof, key=lambda k: prof[k][0])
     ms, launches = prof[kind]
-    entry = {"kernel": kind, "launches": launches, "event_ms_total": round(ms, 3)}
+    entry = {"kernel": kind, "launches": launches, "event_ms_total": round(ms, 3),
+             "avg_launch_us": round(1e3 * ms / launches, 2) if launches else None}
+    if kind in ("qr", "qr_with_r", "small_svd"):
+        entry["note"] = ("one launch = every size class the batch reaches, run side by side; "
+                         "rocprofv3 lists the class kernels (k_qr_reg<512, 8>, ...) separately")
     if kind in flops and ms > 0:
         ach = flops[kind] / (ms * 1e-3) / 1e12
         entry.update({"bound": KIND_BOUND[kind], "achieved": round(ach, 4),
