@@ -13,8 +13,9 @@
 //   folded into the store.
 //
 // Scheduling: problem sizes live on the device, so every contraction kind
-// runs as one persistent launch over a global queue of 64 x 64 output tiles
-// (prefix sums over problems built by k_schedule).  Workgroup i takes the
+// runs as one persistent launch over a global queue of output tiles (64 x 64;
+// 64 x 32 for the sketches, 128 x 16 for the gate; prefix sums over problems
+// built by k_schedule).  Workgroup i takes the
 // virtual index (i mod 8) * G/8 + i / 8, so the consecutive tiles of one
 // problem, which share operand rows, land on the same XCD and its L2.
 #include "loaders.hpp"
@@ -24,6 +25,11 @@ namespace tebd {
 
 using Cfg64 = ZCfg<64, 64, 16, 2, 2>;
 using CfgGate = ZCfg<kGateTileM, kGateTileN, 16, 4, 1>;
+// Sketch and power-iteration products (m x l, n x l): the sketch width l is
+// a few dozen in a TEBD sweep, so 32-wide tiles halve the FP64 matrix-core
+// work spent on padding (FP64 MFMA runs at the vector rate on this chip).
+constexpr int kSketchTileN = 32;
+using CfgSk = ZCfg<64, kSketchTileN, 16, 2, 2>;
 
 // Extent of the updated bond index that a TEBD update writes in Gamma^[k]
 // (columns) and Gamma^[k+1] (rows): the new dimension chi' <= min(l, chi_max)
@@ -40,7 +46,9 @@ template <>
 struct TileKinds<Prob> {
   static constexpr int count = TK_COUNT;
   static constexpr int tile_m(int kind) { return kind == TK_GATE ? kGateTileM : 64; }
-  static constexpr int tile_n(int kind) { return kind == TK_GATE ? kGateTileN : 64; }
+  static constexpr int tile_n(int kind) {
+    return kind == TK_GATE ? kGateTileN : (kind == TK_SKM || kind == TK_SKN) ? kSketchTileN : 64;
+  }
   __device__ static __forceinline__ void shape(int kind, const Prob& P, int tebd, int& M, int& N) {
     M = N = 0;
     if (P.l == 0) return;
@@ -139,8 +147,9 @@ __global__ __launch_bounds__(256) void k_omega(Prob* probs, const int32_t* offs,
   for_each_tile<TK_SKN>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
     if (P.om_ext) return;
     zt* om = const_cast<zt*>(P.om);
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-      const int r = m0 + e / 64, c = n0 + (e & 63);
+    constexpr int TN = kSketchTileN;  // the n x l queue's tiles are 64 x TN
+    for (int e = threadIdx.x; e < 64 * TN; e += 256) {
+      const int r = m0 + e / TN, c = n0 + e % TN;
       if (r >= M || c >= N) continue;
       uint32_t x[4] = {uint32_t(r), uint32_t(c), uint32_t(P.pid), sid};
       philox10(x, uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32));
@@ -221,27 +230,27 @@ hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s) {
 template <int WHICH>
 __global__ __launch_bounds__(256) void k_sketch(Prob* probs, const int32_t* offs, int nprob,
                                                 int tebd) {
-  __shared__ zt smem[Cfg64::lds_elems];
+  __shared__ zt smem[CfgSk::lds_elems];
   if (WHICH == SK_Y_FROM_OMEGA) {
     for_each_tile<TK_SKM>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
       LdRowA la{P.A, P.lda};
       LdRowB lb{P.om, P.ldom};
       StCol st{P.Y, P.m};
-      zgemm_tile<Cfg64>(M, N, P.n, m0, n0, la, lb, st, smem);
+      zgemm_tile<CfgSk>(M, N, P.n, m0, n0, la, lb, st, smem);
     });
   } else if (WHICH == SK_YT_FROM_Y) {
     for_each_tile<TK_SKN>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
       LdAdjA la{P.A, P.lda};
       LdColB lb{P.Y, P.m};
       StCol st{P.Yt, P.n};
-      zgemm_tile<Cfg64>(M, N, P.m, m0, n0, la, lb, st, smem);
+      zgemm_tile<CfgSk>(M, N, P.m, m0, n0, la, lb, st, smem);
     });
   } else {
     for_each_tile<TK_SKM>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
       LdRowA la{P.A, P.lda};
       LdColB lb{P.Yt, P.n};
       StCol st{P.Y, P.m};
-      zgemm_tile<Cfg64>(M, N, P.n, m0, n0, la, lb, st, smem);
+      zgemm_tile<CfgSk>(M, N, P.n, m0, n0, la, lb, st, smem);
     });
   }
 }
@@ -251,27 +260,27 @@ __global__ __launch_bounds__(256) void k_sketch(Prob* probs, const int32_t* offs
 template <int WHICH>
 __global__ __launch_bounds__(256) void k_sketch_f32(Prob* probs, const int32_t* offs, int nprob,
                                                     int tebd) {
-  __shared__ float2 smem[Cfg64::lds_elems];
+  __shared__ float2 smem[CfgSk::lds_elems];
   if (WHICH == SK_Y_FROM_OMEGA) {
     for_each_tile<TK_SKM>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
       LdRowA la{P.A, P.lda};
       LdRowB lb{P.om, P.ldom};
       StCol st{P.Y, P.m};
-      cgemm_tile<Cfg64>(M, N, P.n, m0, n0, la, lb, st, smem);
+      cgemm_tile<CfgSk>(M, N, P.n, m0, n0, la, lb, st, smem);
     });
   } else if (WHICH == SK_YT_FROM_Y) {
     for_each_tile<TK_SKN>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
       LdAdjA la{P.A, P.lda};
       LdColB lb{P.Y, P.m};
       StCol st{P.Yt, P.n};
-      cgemm_tile<Cfg64>(M, N, P.m, m0, n0, la, lb, st, smem);
+      cgemm_tile<CfgSk>(M, N, P.m, m0, n0, la, lb, st, smem);
     });
   } else {
     for_each_tile<TK_SKM>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
       LdRowA la{P.A, P.lda};
       LdColB lb{P.Yt, P.n};
       StCol st{P.Y, P.m};
-      cgemm_tile<Cfg64>(M, N, P.n, m0, n0, la, lb, st, smem);
+      cgemm_tile<CfgSk>(M, N, P.n, m0, n0, la, lb, st, smem);
     });
   }
 }
