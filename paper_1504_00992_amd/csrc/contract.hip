@@ -30,6 +30,9 @@ using CfgGate = ZCfg<kGateTileM, kGateTileN, 16, 4, 1>;
 // work spent on padding (FP64 MFMA runs at the vector rate on this chip).
 constexpr int kSketchTileN = 32;
 using CfgSk = ZCfg<64, kSketchTileN, 16, 2, 2>;
+// Theta's contraction depth is the old bond dimension chi_m, often 1 to a
+// few dozen: K slabs of 4 (the MFMA depth) instead of 16.
+using CfgTheta = ZCfg<64, 64, 4, 2, 2>;
 
 // Extent of the updated bond index that a TEBD update writes in Gamma^[k]
 // (columns) and Gamma^[k+1] (rows): the new dimension chi' <= min(l, chi_max)
@@ -173,12 +176,12 @@ hipError_t launch_omega(Prob* probs, const Common& c, hipStream_t s) {
 // Theta build
 
 __global__ __launch_bounds__(256) void k_theta(Prob* probs, const int32_t* offs, int nprob) {
-  __shared__ zt smem[Cfg64::lds_elems];
+  __shared__ zt smem[CfgTheta::lds_elems];
   for_each_tile<TK_THETA>(probs, offs, nprob, 1, [&](Prob& P, int M, int N, int m0, int n0, int) {
     LdThetaA la{P.gk, P.lam_l, P.lam_mid, P.chi_l, P.chi_cap};
     LdThetaB lb{P.gk1, P.lam_r, P.chi_r, P.chi_cap};
     StTheta st{P.T, P.chi_l, P.chi_r, P.dr};
-    zgemm_tile<Cfg64>(M, N, P.chi_m, m0, n0, la, lb, st, smem);
+    zgemm_tile<CfgTheta>(M, N, P.chi_m, m0, n0, la, lb, st, smem);
   });
 }
 
