@@ -108,21 +108,32 @@ def range_basis(y, tol=RANK_TOL):
     return q[:, :keep]
 
 
+def orthonormal_basis(y):
+    """Q of the plain Householder QR Y = Q R (LAPACK geqrf/ungqr), every column.
+
+    Used for the QRs of the power iterations, whose inputs A^H Q and A Qt
+    have the rank r that the first QR kept (in exact arithmetic).
+    """
+    q, _ = scipy.linalg.qr(np.asarray(y, dtype=np.complex128), mode="economic")
+    return q
+
+
 def rrsvd_range(a, omega, q):
     """Alg. 1 (randomized range finder with q power iterations).
 
     Y0 = A Omega, Y0 = Q0 R0; for j = 1..q: Yt_j = A^H Q_{j-1} = Qt_j Rt_j,
-    Y_j = A Qt_j = Q_j R_j.  Returns Q_q (m x r, orthonormal columns, r <= l
-    the numerical rank kept by range_basis).
+    Y_j = A Qt_j = Q_j R_j.  The first QR reveals the numerical rank r <= l
+    (range_basis); the power iterations orthonormalise their r columns
+    (orthonormal_basis).  Returns Q_q (m x r, orthonormal columns).
     """
     a = np.asarray(a, dtype=np.complex128)
     y = a @ omega
     qmat = range_basis(y)
     for _ in range(q):
         yt = a.conj().T @ qmat
-        qt = range_basis(yt)
+        qt = orthonormal_basis(yt)
         y = a @ qt
-        qmat = range_basis(y)
+        qmat = orthonormal_basis(y)
     return qmat
 
 

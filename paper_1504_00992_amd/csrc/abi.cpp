@@ -305,15 +305,17 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
     c.lmax = b[5];
     for (int k = 0; k < TK_COUNT; ++k) c.ktiles[k] = b[6 + k];
   }
-  TIMED(PK_QR, launch_qr(probs, c, 0, 0, s));
+  // the first QR reveals the sketch's rank (column pivoting); the power
+  // iterations keep that rank and orthonormalise without pivoting
+  TIMED(PK_QR, launch_qr(probs, c, 0, 0, 1, s));
   for (int j = 0; j < c.q; ++j) {
     TIMED(PK_SKETCH_AHQ, sketch(SK_YT_FROM_Y));
-    TIMED(PK_QR, launch_qr(probs, c, 1, 0, s));
+    TIMED(PK_QR, launch_qr(probs, c, 1, 0, 0, s));
     TIMED(PK_SKETCH_AQT, sketch(SK_Y_FROM_YT));
-    TIMED(PK_QR, launch_qr(probs, c, 0, 0, s));
+    TIMED(PK_QR, launch_qr(probs, c, 0, 0, 0, s));
   }
   TIMED(PK_SKETCH_AHQ, launch_sketch(probs, c, SK_YT_FROM_Y, s));  // B^H = A^H Q
-  TIMED(PK_QR_R, launch_qr(probs, c, 1, 1, s));                    // B^H = Q_B R_B
+  TIMED(PK_QR_R, launch_qr(probs, c, 1, 1, 1, s));                 // B^H P = Q_B R_B
   {
     Common cs = c;  // the small SVD works on the revealed rank, anywhere in [1, l1]
     cs.lmin = 1;

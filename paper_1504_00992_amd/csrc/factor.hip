@@ -506,7 +506,7 @@ struct RegQrShared {
 // The body for one group width G (a compile-time constant, so the row
 // offsets of the register loops are immediates).
 template <int NT, int RPL, int G>
-__device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, int want_r,
+__device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, int want_r, bool piv,
                                             RegQrShared<RPL>& sh) {
   constexpr int UCAP = kRegGroupMax * RPL;  // rows a group can hold
   constexpr int KEEP = RPL <= 8 ? RPL : 1;  // reflector rows kept in registers
@@ -519,7 +519,8 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
   const int tid = threadIdx.x, lane = tid & 63;
   const int g = tid / G, h = tid - g * G;
   const bool have = g < l;
-  const bool allow_stop = !want_r;  // the QR of B^H keeps every column
+  // the QR of B^H keeps every column; without pivoting no rank is revealed
+  const bool allow_stop = piv && !want_r;
   const zt zero = make_double2(0.0, 0.0);
   for (int e = tid; e < 2 * UCAP; e += NT) us[e / UCAP][e % UCAP] = zero;
   zt y[RPL];
@@ -541,38 +542,42 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
   double r00 = 0.0;
   int rank = l;
   for (int j = 0; j < l; ++j) {
-    // pivot search, identical in every wavefront
-    double bv = -1.0;
-    int bg = -1, bp = kMaxL;
-    for (int c = lane; c < l; c += 64) {
-      const double v = nrm_s[c];
-      if (v < 0.0) continue;
-      const int pc = pos_s[c];
-      if (v > bv || (v == bv && pc < bp)) {
-        bv = v;
-        bg = c;
-        bp = pc;
+    int p = j;
+    double pn = 0.0;
+    if (piv) {
+      // pivot search, identical in every wavefront
+      double bv = -1.0;
+      int bg = -1, bp = kMaxL;
+      for (int c = lane; c < l; c += 64) {
+        const double v = nrm_s[c];
+        if (v < 0.0) continue;
+        const int pc = pos_s[c];
+        if (v > bv || (v == bv && pc < bp)) {
+          bv = v;
+          bg = c;
+          bp = pc;
+        }
+      }
+      const double best = wave_max_nonneg(fmax(bv, 0.0));
+      const bool hit = bg >= 0 && bv == best;
+      unsigned long long hits = __ballot(hit);
+      if (hits == 0) {  // only NaN norms left: stop here
+        rank = j;
+        break;
+      }
+      if (__popcll(hits) > 1) {  // equal norms: the lowest position wins
+        const double key = wave_max_nonneg(hit ? double(kMaxL - bp) : 0.0);
+        hits = __ballot(hit && double(kMaxL - bp) == key);
+      }
+      p = __builtin_amdgcn_readlane(bg, __ffsll(hits) - 1);
+      pn = sqrt(best);
+      if (j == 0) r00 = pn;
+      if (allow_stop && j > 0 && !(pn > kRankTol * r00)) {
+        rank = j;
+        break;
       }
     }
-    const double best = wave_max_nonneg(fmax(bv, 0.0));
-    const bool hit = bg >= 0 && bv == best;
-    unsigned long long hits = __ballot(hit);
-    if (hits == 0) {  // only NaN norms left: stop here
-      rank = j;
-      break;
-    }
-    if (__popcll(hits) > 1) {  // equal norms: the lowest position wins
-      const double key = wave_max_nonneg(hit ? double(kMaxL - bp) : 0.0);
-      hits = __ballot(hit && double(kMaxL - bp) == key);
-    }
-    const int p = __builtin_amdgcn_readlane(bg, __ffsll(hits) - 1);
-    const double pn = sqrt(best);
-    if (j == 0) r00 = pn;
-    if (allow_stop && j > 0 && !(pn > kRankTol * r00)) {
-      rank = j;
-      break;
-    }
-    if (g == p) {  // reflector from the pivot column, whose trailing norm is `best`
+    if (g == p) {  // reflector from the pivot column (pivoting: its trailing norm is pn)
       // row j sits in register j / G of the group's lane j % G (uniform)
       const int i0 = j / G, hj = j - i0 * G, lj = (p * G + hj) & 63;
       double ax = 0.0, ay = 0.0;
@@ -582,6 +587,12 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
           ax = read_lane(y[i].x, lj);
           ay = read_lane(y[i].y, lj);
         }
+      if (!piv) {  // no trailing norms are kept: ||column, rows >= j|| here
+        double s2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) s2 += h + G * i >= j ? zabs2(y[i]) : 0.0;
+        pn = sqrt(group_sum(s2, G));
+      }
       const zt alpha = make_double2(ax, ay);
       const double a2 = zabs2(alpha);
       const double ia = a2 > 0.0 ? rsqrt(a2) : 0.0;  // 1 / |alpha|
@@ -620,11 +631,13 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
     }
     __syncthreads();  // reflector j is published; every pivot search is done
     if (tid == 0) {   // positions as the column swap of qr_core would leave them
-      const int q = grp_at[j], pp = pos_s[p];
-      grp_at[pp] = q;
-      pos_s[q] = pp;
-      grp_at[j] = p;
-      pos_s[p] = j;
+      if (piv) {
+        const int q = grp_at[j], pp = pos_s[p];
+        grp_at[pp] = q;
+        pos_s[q] = pp;
+        grp_at[j] = p;
+        pos_s[p] = j;
+      }
       piv_grp[j] = p;
     }
     if (have && mine == kMaxL) {  // trailing column: y -= 2 u (u^H y)
@@ -654,14 +667,18 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
         const int r = h + G * i;
         const zt u = i < KEEP ? uu[i < KEEP ? i : 0] : us[0][r];
         y[i] = zsub(y[i], zmul(u, d2));
-        const double a2 = r > j ? zabs2(y[i]) : 0.0;
-        if (i & 1)
-          tn1 += a2;
-        else
-          tn0 += a2;
+        if (piv) {
+          const double a2 = r > j ? zabs2(y[i]) : 0.0;
+          if (i & 1)
+            tn1 += a2;
+          else
+            tn0 += a2;
+        }
       }
-      const double tn = group_sum(tn0 + tn1, G);
-      if (h == 0) nrm_s[g] = tn;
+      if (piv) {
+        const double tn = group_sum(tn0 + tn1, G);
+        if (h == 0) nrm_s[g] = tn;
+      }
     }
     if (g == p && h == 0) nrm_s[g] = -1.0;
     __syncthreads();  // trailing norms and positions of step j are complete
@@ -757,7 +774,8 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
 }
 
 template <int NT, int RPL>
-__global__ __launch_bounds__(NT) void k_qr_reg(Prob* probs, int which, int want_r, int cls) {
+__global__ __launch_bounds__(NT) void k_qr_reg(Prob* probs, int which, int want_r, int cls,
+                                               int pivot) {
   __shared__ RegQrShared<RPL> sh;
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
@@ -769,22 +787,22 @@ __global__ __launch_bounds__(NT) void k_qr_reg(Prob* probs, int which, int want_
   static_assert(NT / kMaxL >= 2, "group widths below 2 are not instantiated");
   const int G = reg_group(NT, l);
   if (G == 32)
-    qr_reg_body<NT, RPL, 32>(P, rows, l, Yg, want_r, sh);
+    qr_reg_body<NT, RPL, 32>(P, rows, l, Yg, want_r, pivot != 0, sh);
   else if (G == 16)
-    qr_reg_body<NT, RPL, 16>(P, rows, l, Yg, want_r, sh);
+    qr_reg_body<NT, RPL, 16>(P, rows, l, Yg, want_r, pivot != 0, sh);
   else if (G == 8)
-    qr_reg_body<NT, RPL, 8>(P, rows, l, Yg, want_r, sh);
+    qr_reg_body<NT, RPL, 8>(P, rows, l, Yg, want_r, pivot != 0, sh);
   else if (NT / kMaxL <= 4 && G == 4)
-    qr_reg_body<NT, RPL, (NT / kMaxL <= 4 ? 4 : 8)>(P, rows, l, Yg, want_r, sh);
+    qr_reg_body<NT, RPL, (NT / kMaxL <= 4 ? 4 : 8)>(P, rows, l, Yg, want_r, pivot != 0, sh);
   else if (NT / kMaxL <= 2)
-    qr_reg_body<NT, RPL, (NT / kMaxL <= 2 ? 2 : 8)>(P, rows, l, Yg, want_r, sh);
+    qr_reg_body<NT, RPL, (NT / kMaxL <= 2 ? 2 : 8)>(P, rows, l, Yg, want_r, pivot != 0, sh);
 }
 
 // Class 2, (l + 2) * rows <= kLdsElems beyond the register classes:
 // qr_core's column ownership with 1024 threads (one wavefront per column at
 // a time), the matrix in up to 150 KiB of LDS.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_r) {
+__global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_r, int pivot) {
   extern __shared__ zt lds[];  // rows * l matrix, then 2 * rows for u
   __shared__ zt rdiag[kMaxL];
   Prob& P = probs[blockIdx.x];
@@ -800,8 +818,9 @@ __global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_
   __shared__ int32_t perm_s[kMaxL];
   for (int c = threadIdx.x; c < l; c += NT) perm_s[c] = c;
   __syncthreads();
-  const int rank = qr_core<NT, 0>(lds, rows, l, lds + tot, rdiag, want_r ? P.Rb : nullptr, true,
-                                  !want_r, want_r ? perm_s : nullptr, nrm, sh_i);
+  const int rank = qr_core<NT, 0>(lds, rows, l, lds + tot, rdiag, want_r ? P.Rb : nullptr,
+                                  pivot != 0, pivot != 0 && !want_r, want_r ? perm_s : nullptr, nrm,
+                                  sh_i);
   if (want_r)
     for (int c = threadIdx.x; c < l; c += NT) P.piv[c] = perm_s[c];
   const int keep = rows * rank;
@@ -813,7 +832,7 @@ __global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_
 // 1024 threads, qr_core's column ownership, and each column held in
 // registers between its dot product and its update.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_r) {
+__global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_r, int pivot) {
   extern __shared__ zt u_s[];  // 2 * rows
   __shared__ zt rdiag[kMaxL];
   Prob& P = probs[blockIdx.x];
@@ -826,8 +845,9 @@ __global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_
   for (int c = threadIdx.x; c < l; c += NT) perm_s[c] = c;
   __syncthreads();
   const int rank = qr_core<NT, kRegRows>(which ? P.Yt : P.Y, rows, l, u_s, rdiag,
-                                         want_r ? P.Rb : nullptr, true, !want_r,
-                                         want_r ? perm_s : nullptr, nrm, sh_i);
+                                         want_r ? P.Rb : nullptr, pivot != 0,
+                                         pivot != 0 && !want_r, want_r ? perm_s : nullptr, nrm,
+                                         sh_i);
   if (want_r)
     for (int c = threadIdx.x; c < l; c += NT) P.piv[c] = perm_s[c];
   if (threadIdx.x == 0) P.l = rank;
@@ -914,7 +934,8 @@ hipError_t fork_join(hipStream_t s, L* launches, int n, const Common& c) {
 }
 }  // namespace
 
-hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStream_t s) {
+hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pivot,
+                     hipStream_t s) {
   const int rows_max = which ? c.nmax : c.mmax;
   const int rows_min = which ? c.nmin : c.mmin;
   static const hipError_t attr = []() {
@@ -927,33 +948,33 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStr
                                int(size_t(kLdsElems) * sizeof(zt)));
   }();
   if (attr != hipSuccess) return attr;
-  typedef void (*Launch)(hipStream_t, Prob*, int, int, int, int);
+  typedef void (*Launch)(hipStream_t, Prob*, int, int, int, int, int);
   struct Item {
     Launch fn;
     Prob* probs;
-    int which, want_r, nprob, rows;
-    void operator()(hipStream_t t) const { fn(t, probs, which, want_r, nprob, rows); }
+    int which, want_r, pivot, nprob, rows;
+    void operator()(hipStream_t t) const { fn(t, probs, which, want_r, pivot, nprob, rows); }
   };
   const Launch fns[4] = {
-      [](hipStream_t t, Prob* p, int w, int r, int np, int) {
-        hipLaunchKernelGGL((k_qr_reg<512, 8>), dim3(np), dim3(512), 0, t, p, w, r, 0);
+      [](hipStream_t t, Prob* p, int w, int r, int v, int np, int) {
+        hipLaunchKernelGGL((k_qr_reg<512, 8>), dim3(np), dim3(512), 0, t, p, w, r, 0, v);
       },
-      [](hipStream_t t, Prob* p, int w, int r, int np, int) {
-        hipLaunchKernelGGL((k_qr_reg<1024, 12>), dim3(np), dim3(1024), 0, t, p, w, r, 1);
+      [](hipStream_t t, Prob* p, int w, int r, int v, int np, int) {
+        hipLaunchKernelGGL((k_qr_reg<1024, 12>), dim3(np), dim3(1024), 0, t, p, w, r, 1, v);
       },
-      [](hipStream_t t, Prob* p, int w, int r, int np, int) {
+      [](hipStream_t t, Prob* p, int w, int r, int v, int np, int) {
         hipLaunchKernelGGL(k_qr_lds<1024>, dim3(np), dim3(1024), size_t(kLdsElems) * sizeof(zt),
-                           t, p, w, r);
+                           t, p, w, r, v);
       },
-      [](hipStream_t t, Prob* p, int w, int r, int np, int rw) {
+      [](hipStream_t t, Prob* p, int w, int r, int v, int np, int rw) {
         hipLaunchKernelGGL(k_qr_glb<1024>, dim3(np), dim3(1024), 2 * size_t(rw) * sizeof(zt), t,
-                           p, w, r);
+                           p, w, r, v);
       }};
   // the classes between those of the smallest and the largest possible size
   const int lo = qr_class(rows_min, c.lmin), hi = qr_class(rows_max, c.lmax);
   Item items[4];
   int n = 0;
-  for (int k = lo; k <= hi; ++k) items[n++] = {fns[k], probs, which, want_r, c.nprob, rows_max};
+  for (int k = lo; k <= hi; ++k) items[n++] = {fns[k], probs, which, want_r, pivot, c.nprob, rows_max};
   return fork_join(s, items, n, c);
 }
 

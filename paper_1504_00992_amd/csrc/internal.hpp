@@ -167,7 +167,9 @@ hipError_t launch_frob(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_omega(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s);
 hipError_t launch_sketch_f32(Prob* probs, const Common& c, int which, hipStream_t s);
-hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, hipStream_t s);
+// pivot: column pivoting with the rank tolerance (the QR of B^H pivots and
+// keeps every column); 0: plain Householder in column order, every column kept
+hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pivot, hipStream_t s);
 hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_truncate(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_form_uv(Prob* probs, const Common& c, hipStream_t s);
