@@ -647,37 +647,37 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
       for (int i = 0; i < RPL; ++i) {
         const zt u = us[0][h + G * i];  // zero outside [j, rows)
         if (i < KEEP) uu[i < KEEP ? i : 0] = u;
-        const zt t = zcmul(u, y[i]);
-        if (i & 1) {
-          dr1 += t.x;
-          di1 += t.y;
-        } else {
-          dr0 += t.x;
-          di0 += t.y;
-        }
+        if (i & 1)
+          zdot_acc(u, y[i], dr1, di1);
+        else
+          zdot_acc(u, y[i], dr0, di0);
       }
       const double dr = group_sum(dr0 + dr1, G), di = group_sum(di0 + di1, G);
       const zt d2 = make_double2(2.0 * dr, 2.0 * di);
       // without the kept copy, the second read of u must not be hoisted
       // above this point (it would hold every row twice in registers)
       if (KEEP < RPL) __builtin_amdgcn_sched_barrier(0);
-      double tn0 = 0.0, tn1 = 0.0;
-#pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int r = h + G * i;
-        const zt u = i < KEEP ? uu[i < KEEP ? i : 0] : us[0][r];
-        y[i] = zsub(y[i], zmul(u, d2));
-        if (piv) {
-          const double a2 = r > j ? zabs2(y[i]) : 0.0;
-          if (i & 1)
-            tn1 += a2;
-          else
-            tn0 += a2;
-        }
-      }
       if (piv) {
+        double tn0 = 0.0, tn1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int r = h + G * i;
+          const zt u = i < KEEP ? uu[i < KEEP ? i : 0] : us[0][r];
+          y[i] = zsub_mul(y[i], u, d2);
+          const double yx = r > j ? y[i].x : 0.0, yy = r > j ? y[i].y : 0.0;
+          if (i & 1)
+            tn1 = fma(yx, yx, fma(yy, yy, tn1));
+          else
+            tn0 = fma(yx, yx, fma(yy, yy, tn0));
+        }
         const double tn = group_sum(tn0 + tn1, G);
         if (h == 0) nrm_s[g] = tn;
+      } else {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const zt u = i < KEEP ? uu[i < KEEP ? i : 0] : us[0][h + G * i];
+          y[i] = zsub_mul(y[i], u, d2);
+        }
       }
     }
     if (g == p && h == 0) nrm_s[g] = -1.0;
@@ -744,14 +744,10 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
       for (int i = 0; i < RPL; ++i) {
         const zt u = ub[h + G * i];  // zero outside [j, rows)
         if (i < KEEP) uu[i < KEEP ? i : 0] = u;
-        const zt t = zcmul(u, y[i]);
-        if (i & 1) {
-          dr1 += t.x;
-          di1 += t.y;
-        } else {
-          dr0 += t.x;
-          di0 += t.y;
-        }
+        if (i & 1)
+          zdot_acc(u, y[i], dr1, di1);
+        else
+          zdot_acc(u, y[i], dr0, di0);
       }
       const double dr = group_sum(dr0 + dr1, G), di = group_sum(di0 + di1, G);
       const zt d2 = make_double2(2.0 * dr, 2.0 * di);
@@ -759,7 +755,7 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
         const zt u = i < KEEP ? uu[i < KEEP ? i : 0] : ub[h + G * i];
-        y[i] = zsub(y[i], zmul(u, d2));
+        y[i] = zsub_mul(y[i], u, d2);
       }
     }
   }

@@ -19,6 +19,15 @@ __device__ __forceinline__ zt zcmul(zt a, zt b) {
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 __device__ __forceinline__ double zabs2(zt a) { return a.x * a.x + a.y * a.y; }
+// re + i im += conj(u) y, as four fused multiply-adds
+__device__ __forceinline__ void zdot_acc(zt u, zt y, double& re, double& im) {
+  re = fma(u.x, y.x, fma(u.y, y.y, re));
+  im = fma(u.x, y.y, fma(-u.y, y.x, im));
+}
+// y - u d, as four fused multiply-adds
+__device__ __forceinline__ zt zsub_mul(zt y, zt u, zt d) {
+  return make_double2(fma(-u.x, d.x, fma(u.y, d.y, y.x)), fma(-u.x, d.y, fma(-u.y, d.x, y.y)));
+}
 // *p when c holds, else 0, without selecting between addresses (a select of
 // an LDS or global address with a local's address would put the local in
 // scratch memory).
