@@ -42,11 +42,20 @@ __device__ __forceinline__ zt zload_if(bool c, const zt* p) {
 // row_mirror give every lane its 16-lane row sum; row_bcast15 into rows 1, 3
 // and row_bcast31 into rows 2, 3 leave the total in lane 63, which is read
 // back as a uniform value.  (GFX9 DPP controls; no LDS traffic.)
+// With every row enabled each lane receives a valid source lane for the
+// row-local patterns used here, so the destination's old value is never kept
+// and needs no initialisation; masked rows (the row broadcasts) keep 0.
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
-  return __hiloint2double(hi, lo);
+  if constexpr (ROW_MASK == 0xf) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+  } else {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+  }
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
