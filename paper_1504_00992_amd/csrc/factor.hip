@@ -392,49 +392,13 @@ __device__ __forceinline__ zt col_dot(const zt* u, const zt* y, int r0, int rows
   for (; r + 3 * G < rows; r += 4 * G) {
     const zt u0 = u[r], u1 = u[r + G], u2 = u[r + 2 * G], u3 = u[r + 3 * G];
     const zt y0 = y[r], y1 = y[r + G], y2 = y[r + 2 * G], y3 = y[r + 3 * G];
-    const zt t0 = zcmul(u0, y0), t1 = zcmul(u1, y1), t2 = zcmul(u2, y2), t3 = zcmul(u3, y3);
-    a0 += t0.x;
-    b0 += t0.y;
-    a1 += t1.x;
-    b1 += t1.y;
-    a2 += t2.x;
-    b2 += t2.y;
-    a3 += t3.x;
-    b3 += t3.y;
+    zdot_acc(u0, y0, a0, b0);
+    zdot_acc(u1, y1, a1, b1);
+    zdot_acc(u2, y2, a2, b2);
+    zdot_acc(u3, y3, a3, b3);
   }
-  for (; r < rows; r += G) {
-    const zt t = zcmul(u[r], y[r]);
-    a0 += t.x;
-    b0 += t.y;
-  }
+  for (; r < rows; r += G) zdot_acc(u[r], y[r], a0, b0);
   return make_double2((a0 + a1) + (a2 + a3), (b0 + b1) + (b2 + b3));
-}
-
-// y -= u d on those rows; returns sum |y_new|^2 over the rows > jn.
-__device__ __forceinline__ double col_axpy(const zt* u, zt* y, zt d, int r0, int rows, int G,
-                                           int jn) {
-  double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
-  int r = r0;
-  for (; r + 3 * G < rows; r += 4 * G) {
-    const zt u0 = u[r], u1 = u[r + G], u2 = u[r + 2 * G], u3 = u[r + 3 * G];
-    const zt y0 = y[r], y1 = y[r + G], y2 = y[r + 2 * G], y3 = y[r + 3 * G];
-    const zt v0 = zsub(y0, zmul(u0, d)), v1 = zsub(y1, zmul(u1, d));
-    const zt v2 = zsub(y2, zmul(u2, d)), v3 = zsub(y3, zmul(u3, d));
-    y[r] = v0;
-    y[r + G] = v1;
-    y[r + 2 * G] = v2;
-    y[r + 3 * G] = v3;
-    if (r > jn) n0 += zabs2(v0);
-    if (r + G > jn) n1 += zabs2(v1);
-    if (r + 2 * G > jn) n2 += zabs2(v2);
-    if (r + 3 * G > jn) n3 += zabs2(v3);
-  }
-  for (; r < rows; r += G) {
-    const zt v = zsub(y[r], zmul(u[r], d));
-    y[r] = v;
-    if (r > jn) n0 += zabs2(v);
-  }
-  return (n0 + n1) + (n2 + n3);
 }
 
 __device__ __forceinline__ double col_norm2(const zt* y, int r0, int rows, int G) {
@@ -1070,8 +1034,8 @@ __device__ __forceinline__ void jacobi_core(zt* C, zt* J, int l, int& converged_
           const int r = lane + 64 * i;
           if (r < l) {
             const zt x = xp[i], y = zmul(em, xq[i]);
-            cp[r] = zsub(zscale(x, cs), zscale(y, sn));
-            cq[r] = zadd(zscale(x, sn), zscale(y, cs));
+            cp[r] = zrot_lo(x, y, cs, sn);
+            cq[r] = zrot_hi(x, y, cs, sn);
           }
         }
         zt* jp = J + size_t(p) * l;
@@ -1081,8 +1045,8 @@ __device__ __forceinline__ void jacobi_core(zt* C, zt* J, int l, int& converged_
           const int r = lane + 64 * i;
           if (r < l) {
             const zt x = jp[r], y = zmul(em, jq[r]);
-            jp[r] = zsub(zscale(x, cs), zscale(y, sn));
-            jq[r] = zadd(zscale(x, sn), zscale(y, cs));
+            jp[r] = zrot_lo(x, y, cs, sn);
+            jq[r] = zrot_hi(x, y, cs, sn);
           }
         }
         if (lane == 0) {
@@ -1215,10 +1179,10 @@ __global__ __launch_bounds__(NT) void k_svd_pairs(Prob* probs) {
           for (int r = h; r < l; r += G) {
             const zt x = cp[r], y = zmul(em, cq[r]);
             const zt xj = jp[r], yj = zmul(em, jq[r]);
-            cp[r] = zsub(zscale(x, cs), zscale(y, sn));
-            cq[r] = zadd(zscale(x, sn), zscale(y, cs));
-            jp[r] = zsub(zscale(xj, cs), zscale(yj, sn));
-            jq[r] = zadd(zscale(xj, sn), zscale(yj, cs));
+            cp[r] = zrot_lo(x, y, cs, sn);
+            cq[r] = zrot_hi(x, y, cs, sn);
+            jp[r] = zrot_lo(xj, yj, cs, sn);
+            jq[r] = zrot_hi(xj, yj, cs, sn);
           }
           if (h == 0) {
             nrm[p] = fmax(app - t * ag, 0.0);

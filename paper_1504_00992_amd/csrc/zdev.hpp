@@ -24,6 +24,14 @@ __device__ __forceinline__ void zdot_acc(zt u, zt y, double& re, double& im) {
   re = fma(u.x, y.x, fma(u.y, y.y, re));
   im = fma(u.x, y.y, fma(-u.y, y.x, im));
 }
+// The two outputs of a real plane rotation of complex x, y:
+// cs x - sn y and sn x + cs y, with fused multiply-adds.
+__device__ __forceinline__ zt zrot_lo(zt x, zt y, double cs, double sn) {
+  return make_double2(fma(cs, x.x, -sn * y.x), fma(cs, x.y, -sn * y.y));
+}
+__device__ __forceinline__ zt zrot_hi(zt x, zt y, double cs, double sn) {
+  return make_double2(fma(sn, x.x, cs * y.x), fma(sn, x.y, cs * y.y));
+}
 // y - u d, as four fused multiply-adds
 __device__ __forceinline__ zt zsub_mul(zt y, zt u, zt d) {
   return make_double2(fma(-u.x, d.x, fma(u.y, d.y, y.x)), fma(-u.x, d.y, fma(-u.y, d.x, y.y)));
