@@ -10,6 +10,7 @@
 // accuracy), and the discarded weight of Sec. II.C, Eq. (defdiscweigt),
 // evaluated with the Frobenius identity of Sec. IV.
 #include <cfloat>
+#include <type_traits>
 
 #include "zdev.hpp"
 
@@ -456,25 +457,31 @@ __host__ __device__ __forceinline__ int qr_class(int rows, int l) {
 // trailing norm (ties: the lowest position in the order the swaps of
 // qr_core would have produced, which is tracked) and records it as logical
 // column j; R, the pivot order and the thin Q are written out in logical
-// order.  Same reflectors, pivoting rule and rank tolerance as qr_core; two
-// barriers per factorisation step (trailing norms, reflector) and one per
-// step of the backward Q accumulation (its reflector buffer alternates).
+// order.  Same reflectors, pivoting rule and rank tolerance as qr_core.
+// With pivoting, two barriers per factorisation step (trailing norms,
+// reflector); without, one.  Every reflector keeps an LDS slot of its own
+// when they all fit (always for 512 threads x 8 rows), and then each group
+// accumulates its column of Q with no barrier at all; otherwise two
+// alternating buffers serve, and the backward accumulation takes one
+// barrier per step.
 template <int RPL>
 struct RegQrShared {
-  zt us[2][kRegGroupMax * RPL];  // reflector (zero outside its rows), alternating
+  // rows x l elements always fit for 512 x 8; 144 KiB for 1024 x 12
+  static constexpr int kBuf = RPL <= 8 ? 4096 : 9216;
+  zt buf[kBuf];  // reflector slots (zero outside the reflector's rows)
   zt rdiag[kMaxL];
   double nrm_s[kMaxL];  // trailing norm of each group; -1 once pivoted
   int32_t pos_s[kMaxL], grp_at[kMaxL], piv_grp[kMaxL];
 };
 
 // The body for one group width G (a compile-time constant, so the row
-// offsets of the register loops are immediates).
-template <int NT, int RPL, int G>
+// offsets of the register loops are immediates); SLOTS: every reflector
+// keeps its own slot (G * RPL * l <= RegQrShared<RPL>::kBuf).
+template <int NT, int RPL, int G, bool SLOTS>
 __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, int want_r, bool piv,
                                             RegQrShared<RPL>& sh) {
-  constexpr int UCAP = kRegGroupMax * RPL;  // rows a group can hold
+  constexpr int UST = G * RPL;               // rows a group can hold
   constexpr int KEEP = RPL <= 8 ? RPL : 1;  // reflector rows kept in registers
-  auto& us = sh.us;
   auto& rdiag = sh.rdiag;
   auto& nrm_s = sh.nrm_s;
   auto& pos_s = sh.pos_s;
@@ -486,7 +493,9 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
   // the QR of B^H keeps every column; without pivoting no rank is revealed
   const bool allow_stop = piv && !want_r;
   const zt zero = make_double2(0.0, 0.0);
-  for (int e = tid; e < 2 * UCAP; e += NT) us[e / UCAP][e % UCAP] = zero;
+  // reflector j: slot j, or the alternating buffers
+  constexpr bool slots = SLOTS;
+  auto slot = [&](int j) { return sh.buf + (slots ? j : (j & 1)) * UST; };
   zt y[RPL];
   double nn = 0.0;
 #pragma unroll
@@ -500,149 +509,166 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
   for (int c = tid; c < l; c += NT) {
     pos_s[c] = c;
     grp_at[c] = c;
+    piv_grp[c] = c;
   }
-  int mine = kMaxL;  // logical column of this group once it has been the pivot
   __syncthreads();
-  double r00 = 0.0;
-  int rank = l;
-  for (int j = 0; j < l; ++j) {
-    int p = j;
-    double pn = 0.0;
-    if (piv) {
-      // pivot search, identical in every wavefront
-      double bv = -1.0;
-      int bg = -1, bp = kMaxL;
-      for (int c = lane; c < l; c += 64) {
-        const double v = nrm_s[c];
-        if (v < 0.0) continue;
-        const int pc = pos_s[c];
-        if (v > bv || (v == bv && pc < bp)) {
-          bv = v;
-          bg = c;
-          bp = pc;
-        }
+  int mine = kMaxL;  // logical column of this group once it has been the pivot
+  // The group of logical column j keeps its column x unscaled: the reflector
+  // is u = x * my_vinv on rows > j and my_u0 on row j.
+  double my_vinv = 0.0;
+  zt my_u0 = zero;
+  // Reflector j from the column of group p (pn = ||column p, rows >= j||)
+  // into buffer ub, called by the whole group p.  Every row of the group's
+  // range is written, zeros outside [j, rows), so no earlier reflector
+  // survives in the buffer.
+  auto reflector = [&](int j, int p, double pn, zt* ub) {
+    // row j sits in register j / G of the group's lane j % G (uniform)
+    const int i0 = j / G, hj = j - i0 * G, lj = (p * G + hj) & 63;
+    double ax = 0.0, ay = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+      if (i == i0) {
+        ax = read_lane(y[i].x, lj);
+        ay = read_lane(y[i].y, lj);
       }
-      const double best = wave_max_nonneg(fmax(bv, 0.0));
-      const bool hit = bg >= 0 && bv == best;
-      unsigned long long hits = __ballot(hit);
-      if (hits == 0) {  // only NaN norms left: stop here
-        rank = j;
-        break;
-      }
-      if (__popcll(hits) > 1) {  // equal norms: the lowest position wins
-        const double key = wave_max_nonneg(hit ? double(kMaxL - bp) : 0.0);
-        hits = __ballot(hit && double(kMaxL - bp) == key);
-      }
-      p = __builtin_amdgcn_readlane(bg, __ffsll(hits) - 1);
-      pn = sqrt(best);
-      if (j == 0) r00 = pn;
-      if (allow_stop && j > 0 && !(pn > kRankTol * r00)) {
-        rank = j;
-        break;
-      }
+    const zt alpha = make_double2(ax, ay);
+    const double a2 = zabs2(alpha);
+    const double ia = a2 > 0.0 ? rsqrt(a2) : 0.0;  // 1 / |alpha|
+    const double aa = a2 * ia;
+    const double xnorm = pn;
+    zt beta = zero, v0 = zero;
+    double vinv = 0.0;
+    if (xnorm > 0.0) {
+      const zt ph = aa > 0.0 ? zscale(alpha, ia) : make_double2(1.0, 0.0);
+      beta = zscale(ph, -xnorm);
+      v0 = zsub(alpha, beta);
+      vinv = rsqrt(2.0 * xnorm * (xnorm + aa));
     }
-    if (g == p) {  // reflector from the pivot column (pivoting: its trailing norm is pn)
-      // row j sits in register j / G of the group's lane j % G (uniform)
-      const int i0 = j / G, hj = j - i0 * G, lj = (p * G + hj) & 63;
-      double ax = 0.0, ay = 0.0;
+    // u = (x - beta e_j) / ||x - beta e_j||: rows > j are x * vinv
 #pragma unroll
-      for (int i = 0; i < RPL; ++i)
-        if (i == i0) {
-          ax = read_lane(y[i].x, lj);
-          ay = read_lane(y[i].y, lj);
-        }
-      if (!piv) {  // no trailing norms are kept: ||column, rows >= j|| here
-        double s2 = 0.0;
+    for (int i = 0; i < RPL; ++i) {
+      const bool on = h + G * i > j && h + G * i < rows;
+      const zt uu = zscale(y[i], vinv);
+      zt w;
+      w.x = on ? uu.x : 0.0;
+      w.y = on ? uu.y : 0.0;
+      ub[h + G * i] = w;
+    }
+    const zt u0 = zscale(v0, vinv);
+    if (h == hj) ub[j] = u0;
+    if (h == 0) rdiag[j] = beta;
+    my_vinv = vinv;
+    my_u0 = u0;
+    mine = j;
+  };
+  // trailing column: y -= 2 u (u^H y) with u in ub, zero outside its rows;
+  // with want_norm (uniform over the wavefront) the norm of rows > j is
+  // returned (else 0)
+  auto apply = [&](const zt* ub, int j, bool want_norm) {
+    zt uu[KEEP];  // u kept in registers between the two loops when they fit
+    double dr0 = 0.0, di0 = 0.0, dr1 = 0.0, di1 = 0.0;
 #pragma unroll
-        for (int i = 0; i < RPL; ++i) s2 += h + G * i >= j ? zabs2(y[i]) : 0.0;
-        pn = sqrt(group_sum(s2, G));
-      }
-      const zt alpha = make_double2(ax, ay);
-      const double a2 = zabs2(alpha);
-      const double ia = a2 > 0.0 ? rsqrt(a2) : 0.0;  // 1 / |alpha|
-      const double aa = a2 * ia;
-      const double xnorm = pn;  // ||column p, rows >= j||
-      zt beta = zero, v0 = zero;
-      double vinv = 0.0;
-      if (xnorm > 0.0) {
-        const zt ph = aa > 0.0 ? zscale(alpha, ia) : make_double2(1.0, 0.0);
-        beta = zscale(ph, -xnorm);
-        v0 = zsub(alpha, beta);
-        vinv = rsqrt(2.0 * xnorm * (xnorm + aa));
-      }
-      // u = (x - beta e_j) / ||x - beta e_j|| on rows >= j, kept in the
-      // registers for the Q accumulation (rows < j keep R) and published;
-      // the previous pivot row of the buffer is cleared, so rows < j read 0
+    for (int i = 0; i < RPL; ++i) {
+      const zt u = ub[h + G * i];
+      if (i < KEEP) uu[i < KEEP ? i : 0] = u;
+      if (i & 1)
+        zdot_acc(u, y[i], dr1, di1);
+      else
+        zdot_acc(u, y[i], dr0, di0);
+    }
+    const double dr = group_sum(dr0 + dr1, G), di = group_sum(di0 + di1, G);
+    const zt d2 = make_double2(2.0 * dr, 2.0 * di);
+    // without the kept copy, the second read of u must not be hoisted
+    // above this point (it would hold every row twice in registers)
+    if (KEEP < RPL) __builtin_amdgcn_sched_barrier(0);
+    double tn = 0.0;
+    if (want_norm) {
+      double tn0 = 0.0, tn1 = 0.0;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
         const int r = h + G * i;
-        if (r >= j && r < rows) {
-          const zt uu = zscale(y[i], vinv);
-          y[i] = uu;
-          us[0][r] = uu;
-        }
+        const zt u = i < KEEP ? uu[i < KEEP ? i : 0] : ub[r];
+        y[i] = zsub_mul(y[i], u, d2);
+        const double yx = r > j ? y[i].x : 0.0, yy = r > j ? y[i].y : 0.0;
+        if (i & 1)
+          tn1 = fma(yx, yx, fma(yy, yy, tn1));
+        else
+          tn0 = fma(yx, yx, fma(yy, yy, tn0));
       }
-      const zt u0 = zscale(v0, vinv);
-#pragma unroll
-      for (int i = 0; i < RPL; ++i)
-        if (i == i0 && h == hj) {
-          y[i] = u0;
-          us[0][j] = u0;
-        }
-      if (j > 0 && h == (j - 1) % G) us[0][j - 1] = zero;
-      if (h == 0) rdiag[j] = beta;
-      mine = j;
-    }
-    __syncthreads();  // reflector j is published; every pivot search is done
-    if (tid == 0) {   // positions as the column swap of qr_core would leave them
-      if (piv) {
-        const int q = grp_at[j], pp = pos_s[p];
-        grp_at[pp] = q;
-        pos_s[q] = pp;
-        grp_at[j] = p;
-        pos_s[p] = j;
-      }
-      piv_grp[j] = p;
-    }
-    if (have && mine == kMaxL) {  // trailing column: y -= 2 u (u^H y)
-      zt uu[KEEP];  // u kept in registers between the two loops when they fit
-      double dr0 = 0.0, di0 = 0.0, dr1 = 0.0, di1 = 0.0;
+      tn = group_sum(tn0 + tn1, G);
+    } else {
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
-        const zt u = us[0][h + G * i];  // zero outside [j, rows)
-        if (i < KEEP) uu[i < KEEP ? i : 0] = u;
-        if (i & 1)
-          zdot_acc(u, y[i], dr1, di1);
-        else
-          zdot_acc(u, y[i], dr0, di0);
+        const zt u = i < KEEP ? uu[i < KEEP ? i : 0] : ub[h + G * i];
+        y[i] = zsub_mul(y[i], u, d2);
       }
-      const double dr = group_sum(dr0 + dr1, G), di = group_sum(di0 + di1, G);
-      const zt d2 = make_double2(2.0 * dr, 2.0 * di);
-      // without the kept copy, the second read of u must not be hoisted
-      // above this point (it would hold every row twice in registers)
-      if (KEEP < RPL) __builtin_amdgcn_sched_barrier(0);
-      if (piv) {
-        double tn0 = 0.0, tn1 = 0.0;
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-          const int r = h + G * i;
-          const zt u = i < KEEP ? uu[i < KEEP ? i : 0] : us[0][r];
-          y[i] = zsub_mul(y[i], u, d2);
-          const double yx = r > j ? y[i].x : 0.0, yy = r > j ? y[i].y : 0.0;
-          if (i & 1)
-            tn1 = fma(yx, yx, fma(yy, yy, tn1));
-          else
-            tn0 = fma(yx, yx, fma(yy, yy, tn0));
-        }
-        const double tn = group_sum(tn0 + tn1, G);
-        if (h == 0) nrm_s[g] = tn;
-      } else {
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-          const zt u = i < KEEP ? uu[i < KEEP ? i : 0] : us[0][h + G * i];
-          y[i] = zsub_mul(y[i], u, d2);
-        }
+    }
+    return tn;
+  };
+  double r00 = 0.0;
+  int rank = l;
+  if (!piv) {
+    // Logical column j is group j, which builds reflector j as soon as its
+    // own update by reflector j - 1 is done (with its trailing norm summed
+    // in the same pass), while the other groups are still applying j - 1;
+    // the reflector buffers alternate, so one barrier per step suffices.
+    if (g == 0) reflector(0, 0, sqrt(nn), slot(0));
+    __syncthreads();
+    for (int j = 0; j + 1 < l; ++j) {
+      if (have && g > j) {
+        // the wavefront that holds group j + 1 sums trailing norms
+        const bool lead = (tid >> 6) == (((j + 1) * G) >> 6);
+        const double tn = apply(slot(j), j, lead);
+        if (g == j + 1) reflector(j + 1, g, sqrt(tn), slot(j + 1));
       }
+      __syncthreads();  // reflector j + 1 is published; reflector j is read
+    }
+  }
+  for (int j = 0; piv && j < l; ++j) {
+    // pivot search, identical in every wavefront
+    double bv = -1.0;
+    int bg = -1, bp = kMaxL;
+    for (int c = lane; c < l; c += 64) {
+      const double v = nrm_s[c];
+      if (v < 0.0) continue;
+      const int pc = pos_s[c];
+      if (v > bv || (v == bv && pc < bp)) {
+        bv = v;
+        bg = c;
+        bp = pc;
+      }
+    }
+    const double best = wave_max_nonneg(fmax(bv, 0.0));
+    const bool hit = bg >= 0 && bv == best;
+    unsigned long long hits = __ballot(hit);
+    if (hits == 0) {  // only NaN norms left: stop here
+      rank = j;
+      break;
+    }
+    if (__popcll(hits) > 1) {  // equal norms: the lowest position wins
+      const double key = wave_max_nonneg(hit ? double(kMaxL - bp) : 0.0);
+      hits = __ballot(hit && double(kMaxL - bp) == key);
+    }
+    const int p = __builtin_amdgcn_readlane(bg, __ffsll(hits) - 1);
+    const double pn = sqrt(best);
+    if (j == 0) r00 = pn;
+    if (allow_stop && j > 0 && !(pn > kRankTol * r00)) {
+      rank = j;
+      break;
+    }
+    if (g == p) reflector(j, p, pn, slot(j));
+    __syncthreads();  // reflector j is published; every pivot search is done
+    if (tid == 0) {   // positions as the column swap of qr_core would leave them
+      const int q = grp_at[j], pp = pos_s[p];
+      grp_at[pp] = q;
+      pos_s[q] = pp;
+      grp_at[j] = p;
+      pos_s[p] = j;
+      piv_grp[j] = p;
+    }
+    if (have && mine == kMaxL) {
+      const double tn = apply(slot(j), j, true);
+      if (h == 0) nrm_s[g] = tn;
     }
     if (g == p && h == 0) nrm_s[g] = -1.0;
     __syncthreads();  // trailing norms and positions of step j are complete
@@ -664,63 +690,43 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
     }
     for (int c = tid; c < rank; c += NT) P.piv[c] = piv_grp[c];
   }
-  // Q = H_0 ... H_{r-1} [I; 0] from the last reflector backwards: the group
-  // of logical column j publishes u_j and becomes H_j e_j, the groups of
-  // later logical columns apply H_j.  Column j is not touched by H_j or
-  // later reflectors, so its group publishes u_j while H_{j+1} is being
-  // applied (the buffers alternate): one barrier per step, and the
-  // publication is off the chain of dependent steps.
-  auto publish = [&](int j) {
-    zt* ub = us[j & 1];
-    const int i0 = j / G, hj = j - i0 * G, lj = (g * G + hj) & 63;  // g = piv_grp[j]
-    double ux = 0.0, uy = 0.0;
-#pragma unroll
-    for (int i = 0; i < RPL; ++i)
-      if (i == i0) {
-        ux = read_lane(y[i].x, lj);
-        uy = read_lane(y[i].y, lj);
-      }
-    const zt cuj = make_double2(ux, -uy);  // conj(u_j[j])
-    // rows < j of this buffer are zero
+  // Q = H_0 ... H_{r-1} [I; 0]: the group of logical column c < rank starts
+  // from H_c e_c = e_c - 2 u_c conj(u_c[c]) and applies H_{c-1}, ..., H_0.
+  // With a slot per reflector the groups need no barrier.  With the
+  // alternating buffers, the group of column j publishes u_j one step
+  // ahead, while H_{j+1} is being applied (column j is not touched by H_j or
+  // later reflectors): one barrier per step.
+  auto start_q = [&](zt* ub) {  // by the group with mine < rank; ub: publish u_c there
+    const int c = mine, i0 = c / G, hc = c - i0 * G;
+    const zt m = make_double2(-2.0 * my_u0.x, 2.0 * my_u0.y);  // -2 conj(u_c[c])
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
-      const int r = h + G * i;
-      if (r >= j && r < rows) {
-        ub[r] = y[i];
-        y[i] = zscale(zmul(y[i], cuj), -2.0);
-      } else {
-        y[i] = zero;
-      }
+      const bool on = h + G * i > c && h + G * i < rows;
+      const zt uu = zscale(y[i], my_vinv);
+      zt w;
+      w.x = on ? uu.x : 0.0;
+      w.y = on ? uu.y : 0.0;
+      if (ub) ub[h + G * i] = w;  // zeros outside [c, rows)
+      y[i] = zmul(w, m);
     }
+    if (ub && h == hc) ub[c] = my_u0;
 #pragma unroll
     for (int i = 0; i < RPL; ++i)
-      if (i == i0 && h == hj) y[i].x += 1.0;
+      if (i == i0 && h == hc) {
+        y[i] = zmul(my_u0, m);
+        y[i].x += 1.0;
+      }
   };
-  if (rank > 0 && mine == rank - 1) publish(rank - 1);
-  for (int j = rank - 1; j >= 0; --j) {
-    __syncthreads();  // u_j is published; the reads of the other buffer are done
-    if (j > 0 && mine == j - 1) publish(j - 1);
-    if (have && mine > j && mine < rank) {
-      const zt* ub = us[j & 1];
-      zt uu[KEEP];
-      double dr0 = 0.0, di0 = 0.0, dr1 = 0.0, di1 = 0.0;
-#pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const zt u = ub[h + G * i];  // zero outside [j, rows)
-        if (i < KEEP) uu[i < KEEP ? i : 0] = u;
-        if (i & 1)
-          zdot_acc(u, y[i], dr1, di1);
-        else
-          zdot_acc(u, y[i], dr0, di0);
-      }
-      const double dr = group_sum(dr0 + dr1, G), di = group_sum(di0 + di1, G);
-      const zt d2 = make_double2(2.0 * dr, 2.0 * di);
-      if (KEEP < RPL) __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const zt u = i < KEEP ? uu[i < KEEP ? i : 0] : ub[h + G * i];
-        y[i] = zsub_mul(y[i], u, d2);
-      }
+  if constexpr (slots) {
+    if (have && mine < rank) start_q(nullptr);
+    for (int j = rank - 2; j >= 0; --j)
+      if (have && mine > j && mine < rank) apply(slot(j), j, false);
+  } else {
+    if (rank > 0 && mine == rank - 1) start_q(slot(rank - 1));
+    for (int j = rank - 1; j >= 0; --j) {
+      __syncthreads();  // u_j is published; the reads of the other buffer are done
+      if (j > 0 && mine == j - 1) start_q(slot(j - 1));
+      if (have && mine > j && mine < rank) apply(slot(j), j, false);
     }
   }
   if (have && mine < rank) {
@@ -746,16 +752,24 @@ __global__ __launch_bounds__(NT) void k_qr_reg(Prob* probs, int which, int want_
   // l <= kMaxL, so G >= NT / kMaxL
   static_assert(NT / kMaxL >= 2, "group widths below 2 are not instantiated");
   const int G = reg_group(NT, l);
+  auto run = [&](auto gc) {
+    constexpr int GC = decltype(gc)::value;
+    // 512 x 8: G * 8 * l <= 4096 for every l (G * l <= 512, or G = 32 and l <= 16)
+    if (RPL <= 8 || GC * RPL * l <= RegQrShared<RPL>::kBuf)
+      qr_reg_body<NT, RPL, GC, true>(P, rows, l, Yg, want_r, pivot != 0, sh);
+    else
+      qr_reg_body<NT, RPL, GC, (RPL <= 8)>(P, rows, l, Yg, want_r, pivot != 0, sh);
+  };
   if (G == 32)
-    qr_reg_body<NT, RPL, 32>(P, rows, l, Yg, want_r, pivot != 0, sh);
+    run(std::integral_constant<int, 32>());
   else if (G == 16)
-    qr_reg_body<NT, RPL, 16>(P, rows, l, Yg, want_r, pivot != 0, sh);
+    run(std::integral_constant<int, 16>());
   else if (G == 8)
-    qr_reg_body<NT, RPL, 8>(P, rows, l, Yg, want_r, pivot != 0, sh);
+    run(std::integral_constant<int, 8>());
   else if (NT / kMaxL <= 4 && G == 4)
-    qr_reg_body<NT, RPL, (NT / kMaxL <= 4 ? 4 : 8)>(P, rows, l, Yg, want_r, pivot != 0, sh);
+    run(std::integral_constant<int, (NT / kMaxL <= 4 ? 4 : 8)>());
   else if (NT / kMaxL <= 2)
-    qr_reg_body<NT, RPL, (NT / kMaxL <= 2 ? 2 : 8)>(P, rows, l, Yg, want_r, pivot != 0, sh);
+    run(std::integral_constant<int, (NT / kMaxL <= 2 ? 2 : 8)>());
 }
 
 // Class 2, (l + 2) * rows <= kLdsElems beyond the register classes:
