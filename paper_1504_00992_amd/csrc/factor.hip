@@ -234,9 +234,53 @@ __device__ __forceinline__ void reflect_column(const zt* __restrict__ u, zt* yc,
   }
 }
 
+// Pivot order key of a remaining column: larger for a larger trailing norm
+// v; norms that agree to 2^-36 relative count as equal, and then the lower
+// position wins.  0 (no candidate) for a NaN norm.  The low byte carries a
+// payload (the group of the register QR).  One 64-bit maximum picks the
+// pivot, and the norm it returns is v to 2^-36 relative.
+__device__ __forceinline__ unsigned long long pivot_key(double v, int pos, int payload) {
+  if (!(v >= 0.0)) return 0ull;
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  return (1ull << 63) | (b & 0x7FFFFFFFFFFF0000ull) |
+         (static_cast<unsigned long long>(255 - pos) << 8) | static_cast<unsigned>(payload);
+}
+__device__ __forceinline__ double pivot_key_norm(unsigned long long k) {
+  return __longlong_as_double(static_cast<long long>(k & 0x7FFFFFFFFFFF0000ull));
+}
+__device__ __forceinline__ int pivot_key_pos(unsigned long long k) {
+  return 255 - static_cast<int>((k >> 8) & 0xff);
+}
+__device__ __forceinline__ unsigned long long key_max(unsigned long long a, unsigned long long b) {
+  return a > b ? a : b;
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ unsigned long long key_dpp(unsigned long long k) {
+  return static_cast<unsigned long long>(
+      __double_as_longlong(dpp_move<CTRL, ROW_MASK>(__longlong_as_double(static_cast<long long>(k)))));
+}
+// Wavefront maximum of keys (uniform result): the row steps of
+// wave_max_nonneg, masked-off rows reading 0 (no candidate).
+__device__ __forceinline__ unsigned long long key_wave_max(unsigned long long k) {
+  k = key_max(k, key_dpp<0xb1>(k));
+  k = key_max(k, key_dpp<0x4e>(k));
+  k = key_max(k, key_dpp<0x141>(k));
+  k = key_max(k, key_dpp<0x140>(k));
+  k = key_max(k, key_dpp<0x142, 0xa>(k));
+  k = key_max(k, key_dpp<0x143, 0xc>(k));
+  const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(k & 0xffffffffu), 63));
+  const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(k >> 32), 63));
+  return (static_cast<unsigned long long>(hi) << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long key_max_xor(unsigned long long k, int off) {
+  const double o = __shfl_xor(__longlong_as_double(static_cast<long long>(k)), off, 64);
+  const unsigned long long ok = static_cast<unsigned long long>(__double_as_longlong(o));
+  return ok > k ? ok : k;
+}
+
 // Column pivoting for the range-finder QRs of Alg. 1: before step j the
-// remaining column with the largest trailing norm is swapped into place
-// (ties: lowest index), and the factorisation stops at the first j >= 1 whose
+// remaining column with the largest trailing norm (pivot_key order) is
+// swapped into place, and the factorisation stops at the first j >= 1 whose
 // pivot norm |R_jj| is <= kRankTol |R_00|.  The kept rank r replaces the
 // sketch width l of the problem, so later products and the small SVD work on
 // the numerical range only.
@@ -257,7 +301,7 @@ __device__ __forceinline__ int qr_core(zt* Y, int rows, int l, zt* u_s /* 2 * ro
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int NW = NT / 64;
   int rank = l;
-  double r00 = 0.0;
+  double best00 = 0.0;  // squared pivot norm of step 0
   if (piv) {
     for (int c = wave; c < l; c += NW) {
       double s = 0.0;
@@ -274,27 +318,17 @@ __device__ __forceinline__ int qr_core(zt* Y, int rows, int l, zt* u_s /* 2 * ro
     if (wave == (j % NW)) {
       int stop = 0;
       if (piv) {
-        double best = -1.0;
-        int bi = j;
+        unsigned long long bk = 0ull;
         for (int c = j + lane; c < l; c += 64) {
-          const double v = ncur[c];
-          if (v > best) {
-            best = v;
-            bi = c;
-          }
+          const unsigned long long k = pivot_key(ncur[c], c, 0);
+          bk = k > bk ? k : bk;
         }
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          const double ob = __shfl_xor(best, off, 64);
-          const int oi = __shfl_xor(bi, off, 64);
-          if (ob > best || (ob == best && oi < bi)) {
-            best = ob;
-            bi = oi;
-          }
-        }
-        const double pn = sqrt(fmax(best, 0.0));
-        if (j == 0) r00 = pn;
-        if (allow_stop && j > 0 && !(pn > kRankTol * r00)) stop = 1;
+        for (int off = 32; off > 0; off >>= 1) bk = key_max_xor(bk, off);
+        const int bi = bk ? pivot_key_pos(bk) : j;
+        const double best = pivot_key_norm(bk);  // |R_jj|^2 to 2^-36
+        if (j == 0) best00 = best;
+        if (allow_stop && j > 0 && !(best > kRankTol * kRankTol * best00)) stop = 1;
         if (!stop && bi != j) {
           zt* ya = Y + size_t(j) * rows;
           zt* yb = Y + size_t(bi) * rows;
@@ -453,10 +487,11 @@ __host__ __device__ __forceinline__ int qr_class(int rows, int l) {
 // outside the reflector's rows, so the row loops run without branches (their
 // LDS loads overlap) and rows outside [j, rows) are left exactly unchanged.
 //
-// Columns never move.  Pivoting picks the unfactored group with the largest
-// trailing norm (ties: the lowest position in the order the swaps of
-// qr_core would have produced, which is tracked) and records it as logical
-// column j; R, the pivot order and the thin Q are written out in logical
+// Columns never move.  Pivoting picks the unfactored group first in
+// pivot_key order, over the positions the swaps of qr_core would have
+// produced (each group tracks its own): every trailing group posts its key
+// in LDS, and after the barrier each wavefront takes their maximum.  The
+// pivot group is recorded as logical column j; R, the pivot order and the thin Q are written out in logical
 // order.  Same reflectors, pivoting rule and rank tolerance as qr_core.
 // With pivoting, two barriers per factorisation step (trailing norms,
 // reflector); without, one.  Every reflector keeps an LDS slot of its own
@@ -470,22 +505,22 @@ struct RegQrShared {
   static constexpr int kBuf = RPL <= 8 ? 4096 : 9216;
   zt buf[kBuf];  // reflector slots (zero outside the reflector's rows)
   zt rdiag[kMaxL];
-  double nrm_s[kMaxL];  // trailing norm of each group; -1 once pivoted
-  int32_t pos_s[kMaxL], grp_at[kMaxL], piv_grp[kMaxL];
+  unsigned long long key_s[kMaxL];  // pivot key of each group; 0 once pivoted
+  int32_t piv_grp[kMaxL];
 };
 
 // The body for one group width G (a compile-time constant, so the row
 // offsets of the register loops are immediates); SLOTS: every reflector
-// keeps its own slot (G * RPL * l <= RegQrShared<RPL>::kBuf).
-template <int NT, int RPL, int G, bool SLOTS>
-__device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, int want_r, bool piv,
+// keeps its own slot (G * RPL * l <= RegQrShared<RPL>::kBuf); PIV: column
+// pivoting.
+template <int NT, int RPL, int G, bool SLOTS, bool PIV>
+__device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, int want_r,
                                             RegQrShared<RPL>& sh) {
+  constexpr bool piv = PIV;
   constexpr int UST = G * RPL;               // rows a group can hold
   constexpr int KEEP = RPL <= 8 ? RPL : 1;  // reflector rows kept in registers
   auto& rdiag = sh.rdiag;
-  auto& nrm_s = sh.nrm_s;
-  auto& pos_s = sh.pos_s;
-  auto& grp_at = sh.grp_at;
+  auto& key_s = sh.key_s;
   auto& piv_grp = sh.piv_grp;
   const int tid = threadIdx.x, lane = tid & 63;
   const int g = tid / G, h = tid - g * G;
@@ -505,13 +540,12 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
     nn += zabs2(y[i]);
   }
   nn = group_sum(nn, G);
-  if (have && h == 0) nrm_s[g] = nn;
-  for (int c = tid; c < l; c += NT) {
-    pos_s[c] = c;
-    grp_at[c] = c;
-    piv_grp[c] = c;
-  }
+  for (int c = tid; c < l; c += NT) piv_grp[c] = c;
+  if (piv && have && h == 0) key_s[g] = pivot_key(nn, g, g);
   __syncthreads();
+  // trailing norm (rows >= the next step) and position of this group
+  double my_tn = nn;
+  int my_pos = g;
   int mine = kMaxL;  // logical column of this group once it has been the pivot
   // The group of logical column j keeps its column x unscaled: the reflector
   // is u = x * my_vinv on rows > j and my_u0 on row j.
@@ -605,9 +639,8 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
     }
     return tn;
   };
-  double r00 = 0.0;
   int rank = l;
-  if (!piv) {
+  if constexpr (!piv) {
     // Logical column j is group j, which builds reflector j as soon as its
     // own update by reflector j - 1 is done (with its trailing norm summed
     // in the same pass), while the other groups are still applying j - 1;
@@ -624,54 +657,32 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
       __syncthreads();  // reflector j + 1 is published; reflector j is read
     }
   }
+  double best00 = 0.0;  // squared pivot norm of step 0
   for (int j = 0; piv && j < l; ++j) {
-    // pivot search, identical in every wavefront
-    double bv = -1.0;
-    int bg = -1, bp = kMaxL;
-    for (int c = lane; c < l; c += 64) {
-      const double v = nrm_s[c];
-      if (v < 0.0) continue;
-      const int pc = pos_s[c];
-      if (v > bv || (v == bv && pc < bp)) {
-        bv = v;
-        bg = c;
-        bp = pc;
-      }
-    }
-    const double best = wave_max_nonneg(fmax(bv, 0.0));
-    const bool hit = bg >= 0 && bv == best;
-    unsigned long long hits = __ballot(hit);
-    if (hits == 0) {  // only NaN norms left: stop here
+    unsigned long long key = 0ull;
+    for (int c = lane; c < l; c += 64) key = key_max(key, key_s[c]);
+    key = key_wave_max(key);
+    if (key == 0ull) {  // only NaN norms left: stop here
       rank = j;
       break;
     }
-    if (__popcll(hits) > 1) {  // equal norms: the lowest position wins
-      const double key = wave_max_nonneg(hit ? double(kMaxL - bp) : 0.0);
-      hits = __ballot(hit && double(kMaxL - bp) == key);
-    }
-    const int p = __builtin_amdgcn_readlane(bg, __ffsll(hits) - 1);
-    const double pn = sqrt(best);
-    if (j == 0) r00 = pn;
-    if (allow_stop && j > 0 && !(pn > kRankTol * r00)) {
+    const int p = static_cast<int>(key & 0xff), pp = pivot_key_pos(key);
+    const double best = pivot_key_norm(key);  // |R_jj|^2 to 2^-36
+    if (j == 0) best00 = best;
+    if (allow_stop && j > 0 && !(best > kRankTol * kRankTol * best00)) {
       rank = j;
       break;
     }
-    if (g == p) reflector(j, p, pn, slot(j));
-    __syncthreads();  // reflector j is published; every pivot search is done
-    if (tid == 0) {   // positions as the column swap of qr_core would leave them
-      const int q = grp_at[j], pp = pos_s[p];
-      grp_at[pp] = q;
-      pos_s[q] = pp;
-      grp_at[j] = p;
-      pos_s[p] = j;
-      piv_grp[j] = p;
-    }
+    if (g == p) reflector(j, p, sqrt(my_tn), slot(j));
+    __syncthreads();  // reflector j is published; every key read is done
+    if (tid == 0) piv_grp[j] = p;
     if (have && mine == kMaxL) {
-      const double tn = apply(slot(j), j, true);
-      if (h == 0) nrm_s[g] = tn;
+      if (my_pos == j) my_pos = pp;  // the swap of qr_core moves it to the pivot's place
+      my_tn = apply(slot(j), j, true);
+      if (h == 0) key_s[g] = pivot_key(my_tn, my_pos, g);
     }
-    if (g == p && h == 0) nrm_s[g] = -1.0;
-    __syncthreads();  // trailing norms and positions of step j are complete
+    if (g == p && h == 0) key_s[g] = 0ull;
+    __syncthreads();  // the keys of step j + 1 are in
   }
   if (want_r) {
     if (have && mine < rank) {
@@ -739,9 +750,8 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
   if (tid == 0) P.l = rank;
 }
 
-template <int NT, int RPL>
-__global__ __launch_bounds__(NT) void k_qr_reg(Prob* probs, int which, int want_r, int cls,
-                                               int pivot) {
+template <int NT, int RPL, bool PIV>
+__global__ __launch_bounds__(NT) void k_qr_reg(Prob* probs, int which, int want_r, int cls) {
   __shared__ RegQrShared<RPL> sh;
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
@@ -756,9 +766,9 @@ __global__ __launch_bounds__(NT) void k_qr_reg(Prob* probs, int which, int want_
     constexpr int GC = decltype(gc)::value;
     // 512 x 8: G * 8 * l <= 4096 for every l (G * l <= 512, or G = 32 and l <= 16)
     if (RPL <= 8 || GC * RPL * l <= RegQrShared<RPL>::kBuf)
-      qr_reg_body<NT, RPL, GC, true>(P, rows, l, Yg, want_r, pivot != 0, sh);
+      qr_reg_body<NT, RPL, GC, true, PIV>(P, rows, l, Yg, want_r, sh);
     else
-      qr_reg_body<NT, RPL, GC, (RPL <= 8)>(P, rows, l, Yg, want_r, pivot != 0, sh);
+      qr_reg_body<NT, RPL, GC, (RPL <= 8), PIV>(P, rows, l, Yg, want_r, sh);
   };
   if (G == 32)
     run(std::integral_constant<int, 32>());
@@ -931,10 +941,16 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pi
   };
   const Launch fns[4] = {
       [](hipStream_t t, Prob* p, int w, int r, int v, int np, int) {
-        hipLaunchKernelGGL((k_qr_reg<512, 8>), dim3(np), dim3(512), 0, t, p, w, r, 0, v);
+        if (v)
+          hipLaunchKernelGGL((k_qr_reg<512, 8, true>), dim3(np), dim3(512), 0, t, p, w, r, 0);
+        else
+          hipLaunchKernelGGL((k_qr_reg<512, 8, false>), dim3(np), dim3(512), 0, t, p, w, r, 0);
       },
       [](hipStream_t t, Prob* p, int w, int r, int v, int np, int) {
-        hipLaunchKernelGGL((k_qr_reg<1024, 12>), dim3(np), dim3(1024), 0, t, p, w, r, 1, v);
+        if (v)
+          hipLaunchKernelGGL((k_qr_reg<1024, 12, true>), dim3(np), dim3(1024), 0, t, p, w, r, 1);
+        else
+          hipLaunchKernelGGL((k_qr_reg<1024, 12, false>), dim3(np), dim3(1024), 0, t, p, w, r, 1);
       },
       [](hipStream_t t, Prob* p, int w, int r, int v, int np, int) {
         hipLaunchKernelGGL(k_qr_lds<1024>, dim3(np), dim3(1024), size_t(kLdsElems) * sizeof(zt),
