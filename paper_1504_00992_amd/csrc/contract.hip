@@ -14,7 +14,7 @@
 //
 // Scheduling: problem sizes live on the device, so every contraction kind
 // runs as one persistent launch over a global queue of output tiles (64 x 64;
-// 64 x 32 for the sketches, 128 x 16 for the gate; prefix sums over problems
+// 32 x 32 for the sketches, 128 x 16 for the gate; prefix sums over problems
 // built by k_schedule).  Workgroup i takes the
 // virtual index (i mod 8) * G/8 + i / 8, so the consecutive tiles of one
 // problem, which share operand rows, land on the same XCD and its L2.
@@ -28,8 +28,12 @@ using CfgGate = ZCfg<kGateTileM, kGateTileN, 16, 4, 1>;
 // Sketch and power-iteration products (m x l, n x l): the sketch width l is
 // a few dozen in a TEBD sweep, so 32-wide tiles halve the FP64 matrix-core
 // work spent on padding (FP64 MFMA runs at the vector rate on this chip).
-constexpr int kSketchTileN = 32;
-using CfgSk = ZCfg<64, kSketchTileN, 16, 2, 2>;
+// 32 x 32 tiles (one 16 x 16 block per wavefront): the largest problems of a
+// batch set the duration of the launch, and their K loop over the full
+// contraction depth is the critical path, so smaller tiles spread it over
+// more compute units.
+constexpr int kSketchTileM = 32, kSketchTileN = 32;
+using CfgSk = ZCfg<kSketchTileM, kSketchTileN, 16, 2, 2>;
 // Theta's contraction depth is the old bond dimension chi_m, often 1 to a
 // few dozen: K slabs of 4 (the MFMA depth) instead of 16.
 using CfgTheta = ZCfg<64, 64, 4, 2, 2>;
@@ -48,7 +52,9 @@ __device__ __forceinline__ int updated_bond_extent(const Prob& P) {
 template <>
 struct TileKinds<Prob> {
   static constexpr int count = TK_COUNT;
-  static constexpr int tile_m(int kind) { return kind == TK_GATE ? kGateTileM : 64; }
+  static constexpr int tile_m(int kind) {
+    return kind == TK_GATE ? kGateTileM : (kind == TK_SKM || kind == TK_SKN) ? kSketchTileM : 64;
+  }
   static constexpr int tile_n(int kind) {
     return kind == TK_GATE ? kGateTileN : (kind == TK_SKM || kind == TK_SKN) ? kSketchTileN : 64;
   }
@@ -150,8 +156,8 @@ __global__ __launch_bounds__(256) void k_omega(Prob* probs, const int32_t* offs,
   for_each_tile<TK_SKN>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
     if (P.om_ext) return;
     zt* om = const_cast<zt*>(P.om);
-    constexpr int TN = kSketchTileN;  // the n x l queue's tiles are 64 x TN
-    for (int e = threadIdx.x; e < 64 * TN; e += 256) {
+    constexpr int TM = kSketchTileM, TN = kSketchTileN;  // the n x l queue's tiles
+    for (int e = threadIdx.x; e < TM * TN; e += 256) {
       const int r = m0 + e / TN, c = n0 + e % TN;
       if (r >= M || c >= N) continue;
       uint32_t x[4] = {uint32_t(r), uint32_t(c), uint32_t(P.pid), sid};

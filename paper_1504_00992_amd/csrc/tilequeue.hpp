@@ -132,15 +132,25 @@ __global__ __launch_bounds__(kScheduleThreads) void k_schedule(const PT* probs, 
   }
 }
 
-// Problem owning global tile t: the largest p with off[p] <= t.
+// Problem owning global tile t: the largest p with off[p] <= t (off is
+// non-decreasing, off[0] = 0).  A 64-way search per wavefront: every lane
+// probes one point of the current range and a ballot narrows it, so a
+// batch of up to 4096 problems takes two rounds of independent loads
+// instead of a dozen dependent ones (each a cache miss on the first tiles of
+// a launch, whose XCD has not seen the offsets yet).  Called by whole
+// wavefronts with a uniform t.
 __device__ __forceinline__ int find_problem(const int32_t* off, int nprob, int t) {
-  int lo = 0, hi = nprob;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (off[mid] <= t)
-      lo = mid;
-    else
-      hi = mid;
+  const int lane = threadIdx.x & 63;
+  int lo = 0, n = nprob;  // the answer lies in [lo, lo + n)
+  while (n > 1) {
+    const int step = (n + 63) >> 6;
+    const int q = lo + lane * step;
+    const bool ok = q < lo + n && off[q] <= t;  // a prefix of the lanes (off[lo] <= t)
+    const int cnt = __popcll(__ballot(ok));
+    const int nlo = lo + (cnt - 1) * step;
+    const int end = lo + n;
+    lo = nlo;
+    n = end - nlo < step ? end - nlo : step;
   }
   return lo;
 }
