@@ -54,13 +54,12 @@ __global__ __launch_bounds__(kScheduleThreads) void k_schedule(const PT* probs, 
                                                                int32_t* bounds = nullptr) {
   constexpr int NK = TileKinds<PT>::count, NT = kScheduleThreads, NW = NT / 64;
   __shared__ int32_t wsum[NK][NW];
-  __shared__ int32_t ext[6];
+  __shared__ int32_t wext[6][NW];  // per-wavefront {min, max} of the three sizes
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int chunk = (nprob + NT - 1) / NT;
   const int p0 = min(nprob, tid * chunk), p1 = min(nprob, p0 + chunk);
   int32_t own[NK], incl[NK];
   int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {0, 0, 0};
-  if (BOUNDS && tid < 6) ext[tid] = (tid & 1) ? 0 : INT32_MAX;
 #pragma unroll
   for (int k = 0; k < NK; ++k) own[k] = 0;
   for (int p = p0; p < p1; ++p) {
@@ -88,19 +87,32 @@ __global__ __launch_bounds__(kScheduleThreads) void k_schedule(const PT* probs, 
     incl[k] = v;
     if (lane == 63) wsum[k][wave] = v;
   }
-  if constexpr (BOUNDS) {
-    __syncthreads();  // ext is initialised
+  if constexpr (BOUNDS) {  // wavefront minima and maxima (empty lanes: INT32_MAX, 0)
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      if (hi[i] > 0) {
-        atomicMin(&ext[2 * i], lo[i]);
-        atomicMax(&ext[2 * i + 1], hi[i]);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        lo[i] = min(lo[i], __shfl_xor(lo[i], off, 64));
+        hi[i] = max(hi[i], __shfl_xor(hi[i], off, 64));
+      }
+      if (lane == 0) {
+        wext[2 * i][wave] = lo[i];
+        wext[2 * i + 1][wave] = hi[i];
       }
     }
   }
   __syncthreads();
   if constexpr (BOUNDS) {
-    if (tid < 6) bounds[tid] = ext[tid | 1] > 0 ? ext[tid] : 1;
+    if (tid >= 64 && tid < 67) {  // one thread per size, beside the scan of wavefront 0
+      const int i = tid - 64;
+      int32_t mn = INT32_MAX, mx = 0;
+      for (int w = 0; w < NW; ++w) {
+        mn = min(mn, wext[2 * i][w]);
+        mx = max(mx, wext[2 * i + 1][w]);
+      }
+      bounds[2 * i] = mx > 0 ? mn : 1;
+      bounds[2 * i + 1] = mx > 0 ? mx : 1;
+    }
   }
   if (tid < NK) {  // exclusive scan of the wavefront totals, one thread per kind
     int32_t acc = 0;
