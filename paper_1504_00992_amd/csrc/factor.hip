@@ -1004,9 +1004,13 @@ __device__ __forceinline__ bool jacobi_rotation(double gr, double gi, double a, 
   return true;
 }
 
+// Round-robin (circle method) pairing of lp players: position 0 stays, the
+// others rotate by one place per round.  pos < lp and round < lp - 1, so
+// one conditional subtraction reduces modulo lp - 1 (no integer division).
 __device__ __forceinline__ int circle_player(int pos, int round, int lp) {
   if (pos == 0) return 0;
-  return 1 + (pos - 1 + round) % (lp - 1);
+  const int x = pos - 1 + round;
+  return 1 + (x >= lp - 1 ? x - (lp - 1) : x);
 }
 
 
@@ -1140,10 +1144,12 @@ __host__ __device__ __forceinline__ int svd_class(int l) {
 
 // C and J in LDS with an odd column stride, and all l/2 pairs of a round
 // rotated at once: G = NT / (l/2 rounded up to a power of two) lanes per
-// pair, at most 16 (DPP sums only).  Lane h of a pair sums every G-th row of
-// g = c_p^H c_q, the group sum combines them, and the same lanes rotate
-// their rows of C and J; one barrier per round.  Same rotation, tolerance,
-// carried norms and sweep limit as jacobi_core.
+// pair, at most 16 (DPP sums only; for these two classes always 16).  Lane h
+// of a pair loads every G-th row of both columns of C and J into
+// registers, sums its part of g = c_p^H c_q, the group sum
+// combines them, and the same lanes rotate the rows they hold and store
+// them; one barrier per round.  Same rotation, tolerance, carried norms and
+// sweep limit as jacobi_core.
 constexpr int kPairGroupMax = 16;
 
 template <int NT, int CLS>
@@ -1166,9 +1172,9 @@ __global__ __launch_bounds__(NT) void k_svd_pairs(Prob* probs) {
     Js[c * S + r] = make_double2(r == c ? 1.0 : 0.0, 0.0);
   }
   const int lp = l + (l & 1);
-  int np2 = 1;
-  while (np2 < lp / 2) np2 <<= 1;
-  const int G = NT / np2 < kPairGroupMax ? NT / np2 : kPairGroupMax;  // lanes per pair
+  // lanes per pair: l/2 <= NT / 16 pairs in these classes, so 16 each
+  constexpr int G = kPairGroupMax;
+  static_assert(NT / (CLS == 0 ? 16 : 32) >= kPairGroupMax, "pairs of a round fit at 16 lanes");
   const int k = tid / G, h = tid - k * G;
   int lc2 = 1;
   while (lc2 < l) lc2 <<= 1;
@@ -1194,25 +1200,41 @@ __global__ __launch_bounds__(NT) void k_svd_pairs(Prob* probs) {
         q = a < b ? b : a;
         act = q < l;
       }
-      zt gg = zero;
-      if (act) gg = col_dot(Cs + p * S, Cs + q * S, h, l, G);
-      const double gr = group_sum(gg.x, G), gi = group_sum(gg.y, G);
+      // rows h, h + G, ... < l: G = 16 here (l/2 <= NT / 16), so at most
+      // 32 / 16 or 64 / 16 of them
+      constexpr int RPR = (CLS == 0 ? 32 : 64) / kPairGroupMax;
+      zt x[RPR], y[RPR], xj[RPR], yj[RPR];
+      zt* cp = Cs + p * S;
+      zt* cq = Cs + q * S;
+      zt* jp = Js + p * S;
+      zt* jq = Js + q * S;
+      double g0 = 0.0, g1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPR; ++i) {
+        const int r = h + G * i;
+        const bool in = act && r < l;
+        x[i] = zload_if(in, cp + r);
+        y[i] = zload_if(in, cq + r);
+        xj[i] = zload_if(in, jp + r);
+        yj[i] = zload_if(in, jq + r);
+        zdot_acc(x[i], y[i], g0, g1);
+      }
+      const double gr = group_sum(g0, G), gi = group_sum(g1, G);
       if (act) {
         const double app = nrm[p], aqq = nrm[q];
         double ag, t, cs, sn;
         zt em;  // e^{-i phi}
         if (jacobi_rotation(gr, gi, app, aqq, tol, ag, t, cs, sn, em)) {
-          zt* cp = Cs + p * S;
-          zt* cq = Cs + q * S;
-          zt* jp = Js + p * S;
-          zt* jq = Js + q * S;
-          for (int r = h; r < l; r += G) {
-            const zt x = cp[r], y = zmul(em, cq[r]);
-            const zt xj = jp[r], yj = zmul(em, jq[r]);
-            cp[r] = zrot_lo(x, y, cs, sn);
-            cq[r] = zrot_hi(x, y, cs, sn);
-            jp[r] = zrot_lo(xj, yj, cs, sn);
-            jq[r] = zrot_hi(xj, yj, cs, sn);
+#pragma unroll
+          for (int i = 0; i < RPR; ++i) {
+            const int r = h + G * i;
+            if (r < l) {
+              const zt ey = zmul(em, y[i]), eyj = zmul(em, yj[i]);
+              cp[r] = zrot_lo(x[i], ey, cs, sn);
+              cq[r] = zrot_hi(x[i], ey, cs, sn);
+              jp[r] = zrot_lo(xj[i], eyj, cs, sn);
+              jq[r] = zrot_hi(xj[i], eyj, cs, sn);
+            }
           }
           if (h == 0) {
             nrm[p] = fmax(app - t * ag, 0.0);
