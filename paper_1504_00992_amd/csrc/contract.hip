@@ -211,7 +211,9 @@ struct StGate {
   }
 };
 
-__global__ __launch_bounds__(256) void k_gate(Prob* probs, const int32_t* offs, int nprob) {
+constexpr int kGateNarrow = 4;  // gate tiles with at most this many columns use the ALU
+
+__global__ __launch_bounds__(256, 3) void k_gate(Prob* probs, const int32_t* offs, int nprob) {
   __shared__ zt smem[CfgGate::lds_elems];
   __shared__ double red[4];
   for_each_tile<TK_GATE>(probs, offs, nprob, 1,
@@ -219,7 +221,15 @@ __global__ __launch_bounds__(256) void k_gate(Prob* probs, const int32_t* offs, 
                            LdGate la{P.gate, P.gate_ld};
                            LdRowB lb{P.T, N};
                            StGate st{P.A, P.chi_l, P.chi_r, P.dr, P.n, 0.0};
-                           zgemm_tile<CfgGate>(M, N, P.dl * P.dr, m0, n0, la, lb, st, smem);
+                           // over most of a spin-boson chain chi_l chi_r = 1: the gate
+                           // acts on a vector, and a 16-wide MFMA tile would do 16
+                           // times the useful work
+                           const int ncol = N - n0 < kGateTileN ? N - n0 : kGateTileN;
+                           if (ncol <= kGateNarrow)
+                             zgemm_narrow_tile<CfgGate, kGateNarrow>(M, N, P.dl * P.dr, m0, n0, ncol,
+                                                                     la, lb, st, smem);
+                           else
+                             zgemm_tile<CfgGate>(M, N, P.dl * P.dr, m0, n0, la, lb, st, smem);
                            const double s = block_sum<256>(st.acc, red);
                            if (threadIdx.x == 0) P.part[local] = s;
                          });
