@@ -52,11 +52,14 @@ __device__ __forceinline__ int updated_bond_extent(const Prob& P) {
 template <>
 struct TileKinds<Prob> {
   static constexpr int count = TK_COUNT;
+  static constexpr bool small_tiles(int kind) {
+    return kind == TK_SKM || kind == TK_SKN || kind == TK_FORMU || kind == TK_FORMV;
+  }
   static constexpr int tile_m(int kind) {
-    return kind == TK_GATE ? kGateTileM : (kind == TK_SKM || kind == TK_SKN) ? kSketchTileM : 64;
+    return kind == TK_GATE ? kGateTileM : small_tiles(kind) ? kSketchTileM : 64;
   }
   static constexpr int tile_n(int kind) {
-    return kind == TK_GATE ? kGateTileN : (kind == TK_SKM || kind == TK_SKN) ? kSketchTileN : 64;
+    return kind == TK_GATE ? kGateTileN : small_tiles(kind) ? kSketchTileN : 64;
   }
   __device__ static __forceinline__ void shape(int kind, const Prob& P, int tebd, int& M, int& N) {
     M = N = 0;
@@ -401,7 +404,7 @@ struct StGammaR {  // Gamma'_k+1[j][g][b] = V^H[g, (j,b)] / lam_r[b]
 // column range is the padded MPS capacity, so stale entries are cleared.
 template <int TEBD_>
 __global__ __launch_bounds__(256) void k_form_u(Prob* probs, const int32_t* offs, int nprob) {
-  __shared__ zt smem[Cfg64::lds_elems];
+  __shared__ zt smem[CfgSk::lds_elems];
   for_each_tile<TK_FORMU>(probs, offs, nprob, TEBD_, [&](Prob& P, int M, int N, int m0, int n0, int) {
     if (P.retry) return;  // adaptive rank: stage 2 will write this problem
     const int chi = P.chi_new;
@@ -410,17 +413,17 @@ __global__ __launch_bounds__(256) void k_form_u(Prob* probs, const int32_t* offs
     LdSmallColB lb{P.X, P.l};
     if (TEBD_) {
       StGammaL st{P.gk, P.lam_l, P.lambda_floor, P.chi_l, P.chi_cap, chi};
-      zgemm_tile<Cfg64>(M, N, Keff, m0, n0, la, lb, st, smem);
+      zgemm_tile<CfgSk>(M, N, Keff, m0, n0, la, lb, st, smem);
     } else {
       StU st{P.U, P.ldu, chi};
-      zgemm_tile<Cfg64>(M, N, Keff, m0, n0, la, lb, st, smem);
+      zgemm_tile<CfgSk>(M, N, Keff, m0, n0, la, lb, st, smem);
     }
   });
 }
 
 template <int TEBD_>
 __global__ __launch_bounds__(256) void k_form_vh(Prob* probs, const int32_t* offs, int nprob) {
-  __shared__ zt smem[Cfg64::lds_elems];
+  __shared__ zt smem[CfgSk::lds_elems];
   for_each_tile<TK_FORMV>(probs, offs, nprob, TEBD_, [&](Prob& P, int M, int N, int m0, int n0, int) {
     if (P.retry) return;  // adaptive rank: stage 2 will write this problem
     const int chi = P.chi_new;
@@ -429,10 +432,10 @@ __global__ __launch_bounds__(256) void k_form_vh(Prob* probs, const int32_t* off
     LdQbAdjB lb{P.Yt, P.n};
     if (TEBD_) {
       StGammaR st{P.gk1, P.lam_r, P.lambda_floor, P.chi_r, P.chi_cap, chi};
-      zgemm_tile<Cfg64>(M, N, Keff, m0, n0, la, lb, st, smem);
+      zgemm_tile<CfgSk>(M, N, Keff, m0, n0, la, lb, st, smem);
     } else {
       StVH st{P.VH, P.ldvh, chi};
-      zgemm_tile<Cfg64>(M, N, Keff, m0, n0, la, lb, st, smem);
+      zgemm_tile<CfgSk>(M, N, Keff, m0, n0, la, lb, st, smem);
     }
   });
 }
