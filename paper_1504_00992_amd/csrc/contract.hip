@@ -13,8 +13,9 @@
 //   folded into the store.
 //
 // Scheduling: problem sizes live on the device, so every contraction kind
-// runs as one persistent launch over a global queue of output tiles (64 x 64;
-// 32 x 32 for the sketches, 128 x 16 for the gate; prefix sums over problems
+// runs as one persistent launch over a global queue of output tiles (32 x 32
+// for Theta, the sketches and U, V^H; 64 x 16 for the gate; 64 x 64 for the
+// others; prefix sums over problems
 // built by k_schedule).  Workgroup i takes the
 // virtual index (i mod 8) * G/8 + i / 8, so the consecutive tiles of one
 // problem, which share operand rows, land on the same XCD and its L2.
@@ -35,8 +36,9 @@ using CfgGate = ZCfg<kGateTileM, kGateTileN, 16, 4, 1>;
 constexpr int kSketchTileM = 32, kSketchTileN = 32;
 using CfgSk = ZCfg<kSketchTileM, kSketchTileN, 16, 2, 2>;
 // Theta's contraction depth is the old bond dimension chi_m, often 1 to a
-// few dozen: K slabs of 4 (the MFMA depth) instead of 16.
-using CfgTheta = ZCfg<64, 64, 4, 2, 2>;
+// few dozen: K slabs of 8 instead of 16 (the least that 32 x 32 tiles of
+// 256 threads stage evenly), and 32 x 32 tiles like the sketches.
+using CfgTheta = ZCfg<32, 32, 8, 2, 2>;
 
 // Extent of the updated bond index that a TEBD update writes in Gamma^[k]
 // (columns) and Gamma^[k+1] (rows): the new dimension chi' <= min(l, chi_max)
@@ -53,7 +55,8 @@ template <>
 struct TileKinds<Prob> {
   static constexpr int count = TK_COUNT;
   static constexpr bool small_tiles(int kind) {
-    return kind == TK_SKM || kind == TK_SKN || kind == TK_FORMU || kind == TK_FORMV;
+    return kind == TK_SKM || kind == TK_SKN || kind == TK_FORMU || kind == TK_FORMV ||
+           kind == TK_THETA;
   }
   static constexpr int tile_m(int kind) {
     return kind == TK_GATE ? kGateTileM : small_tiles(kind) ? kSketchTileM : 64;

@@ -131,7 +131,7 @@ static_assert(TK_COUNT == 8, "Common::ktiles holds one total per kind");
 // because the gate side has a few dozen to a few hundred rows while the bond
 // side is often a single column (a 64 x 64 tile would spend almost all of
 // its FP64 matrix-core work on padding).  One Frobenius partial sum per tile.
-constexpr int kGateTileM = 128, kGateTileN = 16;
+constexpr int kGateTileM = 64, kGateTileN = 16;
 __host__ __device__ inline int gate_tiles(int M, int N) {
   return (M <= 0 || N <= 0) ? 0 : ((M + kGateTileM - 1) / kGateTileM) * ((N + kGateTileN - 1) / kGateTileN);
 }
