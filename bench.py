@@ -44,6 +44,9 @@ PEAK_HBM_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy a 256 MiB device buffer three times (the known-size kernel "
+                         "that scales the HBM byte counters) and exit")
     ap.add_argument("--steps", type=int, default=190)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--chains", type=int, default=16)
@@ -80,31 +83,76 @@ def theta_gate_flops(dl, dr, cl, cm, cr):
     return 8.0 * (dl * cl * cm * dr * cr + (dl * dr) ** 2 * cl * cr)
 
 
-def sweep_problems(chi_row, dims, parity, chi_max, p):
-    """(dl, dr, cl, cm, cr, m, n, l) of every bond of one chain in a sweep."""
+def sweep_problems(chi_row, dims, parity, chi_max, p, adaptive):
+    """(dl, dr, cl, cm, cr, m, n, l) of every bond of one chain in a sweep.
+
+    l is the sketch width of the pass that every bond runs: with the
+    adaptive rank the first stage's k1 + p, k1 = chi_m + max(4, ceil(chi_m / 2))
+    capped by chi_max (the few bonds that need the fixed-rank second stage
+    add work that is not counted); otherwise chi_max + p.  Both capped by
+    m and n."""
     out = []
     for b in range(parity, len(dims) - 1, 2):
         cl, cm, cr = int(chi_row[b]), int(chi_row[b + 1]), int(chi_row[b + 2])
         dl, dr = dims[b], dims[b + 1]
         m, n = dl * cl, dr * cr
-        out.append((dl, dr, cl, cm, cr, m, n, min(chi_max + p, m, n)))
+        k = min(chi_max, cm + max(4, (cm + 1) // 2)) if adaptive else chi_max
+        out.append((dl, dr, cl, cm, cr, m, n, min(k + p, m, n)))
     return out
 
 
-def kind_flops(chi_hist, parities, dims, chi_max, p, q):
-    """Algorithmic flops per profiled kernel kind over the recorded sweeps."""
+def qr_bytes(rows, l, with_r=False):
+    """HBM bytes a QR must move: read the rows x l sketch, write the thin Q
+    (and the l x l R factor)."""
+    return 16.0 * (2 * rows * l + (l * l if with_r else 0))
+
+
+def kind_flops(chi_hist, parities, dims, chi_max, p, q, adaptive):
+    """Algorithmic flops per profiled kernel kind over the recorded sweeps,
+    and the QR launches' algorithmic bytes (key "qr_bytes", both QR kinds)."""
     tot = {"theta_gate": 0.0, "sketch_A_Omega": 0.0, "sketch_AH_Q": 0.0, "sketch_A_Qt": 0.0,
-           "qr": 0.0, "qr_with_r": 0.0}
+           "qr": 0.0, "qr_with_r": 0.0, "qr_bytes": 0.0}
     for chi, parity in zip(chi_hist, parities):
         for c in range(chi.shape[0]):
-            for (dl, dr, cl, cm, cr, m, n, l) in sweep_problems(chi[c], dims, parity, chi_max, p):
+            for (dl, dr, cl, cm, cr, m, n, l) in sweep_problems(chi[c], dims, parity, chi_max, p,
+                                                                adaptive):
                 tot["theta_gate"] += theta_gate_flops(dl, dr, cl, cm, cr)
                 tot["sketch_A_Omega"] += sketch_flops(m, n, l)
                 tot["sketch_AH_Q"] += (q + 1) * sketch_flops(m, n, l)
                 tot["sketch_A_Qt"] += q * sketch_flops(m, n, l)
                 tot["qr"] += (q + 1) * qr_flops(m, l) + q * qr_flops(n, l)
                 tot["qr_with_r"] += qr_flops(n, l)
+                tot["qr_bytes"] += ((q + 1) * qr_bytes(m, l) + q * qr_bytes(n, l)
+                                    + qr_bytes(n, l, with_r=True))
     return tot
+
+
+COPY_PROBE_BYTES = 256 << 20
+# HBM bytes of the QR kernels from rocprofv3 counters (FETCH_SIZE and
+# WRITE_SIZE runs, scaled by the same counters on a copy of known size);
+# used only while the QR source still matches the one the counters saw
+QR_TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "qr_hbm_traffic_counters.txt")
+QR_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1504_00992_amd",
+                         "csrc", "factor.hip")
+
+
+def qr_traffic():
+    """Bytes per QR launch from the committed counter summary, or None when
+    it is absent or was taken on another version of the QR source."""
+    import hashlib
+    try:
+        lines = open(QR_TRAFFIC_FILE).read().splitlines()
+        digest = hashlib.sha256(open(QR_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = dict(l[2:].split(": ", 1) for l in lines if l.startswith("# ") and ": " in l)
+    if fields.get("factor.hip sha256") != digest:
+        return None
+    try:
+        return float(fields["bytes per qr launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 KIND_BOUND = {"theta_gate": "mfma", "sketch_A_Omega": "mfma", "sketch_AH_Q": "mfma",
@@ -125,6 +173,16 @@ def roofline(prof, flops):
         entry.update({"bound": KIND_BOUND[kind], "achieved": round(ach, 4),
                       "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                       "frac": round(ach / PEAK_FP64_TFLOPS, 5), "traffic": None})
+        if kind == "qr":
+            nl = launches + (prof["qr_with_r"][1] if "qr_with_r" in prof else 0)
+            if nl and "qr_bytes" in flops:
+                # per launch of either QR kind, as the counters are taken
+                entry["algorithmic_bytes"] = round(flops["qr_bytes"] / nl)
+            t = qr_traffic()
+            if t is not None:
+                entry["traffic"] = round(t)
+                entry["traffic_note"] = ("HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by "
+                                         "a copy of known size): " + os.path.basename(QR_TRAFFIC_FILE))
     else:
         entry.update({"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS,
                       "unit": "TFLOP/s", "frac": None, "traffic": None,
@@ -429,6 +487,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe:
+        src = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES, "copies": 3}))
+        return
     from paper_1504_00992_amd import api, models, _lib
     import workloads as wl
     _lib.load()
@@ -446,7 +513,7 @@ def main():
     total_updates = per_step * args.steps
     sec = res["seconds"]
     value = total_updates / sec
-    flops = kind_flops(profd["chi_hist"], profd["parities"], profd["dims"], 100, 10, 2)
+    flops = kind_flops(profd["chi_hist"], profd["parities"], profd["dims"], 100, 10, 2, adaptive)
     prof = profd["prof"]
     line = {
         "metric": "TEBD bond updates/s, RRSVD vs full SVD on 1 GPU at <=1e-10 trunc err",
@@ -471,6 +538,7 @@ def main():
                    "chi_final_max": int(res["chi_final"].max()),
                    "status_bits_seen": sorted(set(int(x) for x in np.unique(res["status"])))},
         "phase_ms": {k: round(v[0], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
+        "phase_launches": {k: int(v[1]) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
         "profiled_ms_per_step": round(1e3 * profd["seconds"] / args.steps, 4),
         "roofline": roofline(prof, flops),
     }
