@@ -505,6 +505,7 @@ struct RegQrShared {
   static constexpr int kBuf = RPL <= 8 ? 4096 : 9216;
   zt buf[kBuf];  // reflector slots (zero outside the reflector's rows)
   zt rdiag[kMaxL];
+  double tau_s[kMaxL];              // tau of each reflector (H = I - tau v v^H)
   unsigned long long key_s[kMaxL];  // pivot key of each group; 0 once pivoted
   int32_t piv_grp[kMaxL];
 };
@@ -547,15 +548,30 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
   double my_tn = nn;
   int my_pos = g;
   int mine = kMaxL;  // logical column of this group once it has been the pivot
-  // The group of logical column j keeps its column x unscaled: the reflector
-  // is u = x * my_vinv on rows > j and my_u0 on row j.
-  double my_vinv = 0.0;
-  zt my_u0 = zero;
-  // Reflector j from the column of group p (pn = ||column p, rows >= j||)
-  // into buffer ub, called by the whole group p.  Every row of the group's
-  // range is written, zeros outside [j, rows), so no earlier reflector
-  // survives in the buffer.
-  auto reflector = [&](int j, int p, double pn, zt* ub) {
+  // Reflectors are kept unnormalised, H_j = I - tau_j v v^H with
+  // v = x - beta e_j (x: the column at step j, zero above row j) and
+  // tau_j = 2 / ||v||^2 = 1 / (||x|| (||x|| + |x_j|)): rows > j of v are the
+  // column itself, so they are written before beta and tau are known.  The
+  // group of logical column j keeps x unscaled in its registers and v_j, tau_j
+  // in my_v0, my_tau.
+  double my_tau = 0.0;
+  zt my_v0 = zero;
+  // rows > j of v into buffer ub, zeros elsewhere in the group's range (so no
+  // earlier reflector survives in the buffer)
+  auto write_v = [&](zt* ub, int j) {
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const bool on = h + G * i > j && h + G * i < rows;
+      zt w;
+      w.x = on ? y[i].x : 0.0;
+      w.y = on ? y[i].y : 0.0;
+      ub[h + G * i] = w;
+    }
+  };
+  // The rest of reflector j from the column of group p (pn = ||column p,
+  // rows >= j||), called by the whole group p after write_v: row j of v,
+  // tau_j and R_jj = beta.
+  auto finish_reflector = [&](int j, int p, double pn, zt* ub) {
     // row j sits in register j / G of the group's lane j % G (uniform)
     const int i0 = j / G, hj = j - i0 * G, lj = (p * G + hj) & 63;
     double ax = 0.0, ay = 0.0;
@@ -571,35 +587,34 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
     const double aa = a2 * ia;
     const double xnorm = pn;
     zt beta = zero, v0 = zero;
-    double vinv = 0.0;
+    double tau = 0.0;
     if (xnorm > 0.0) {
       const zt ph = aa > 0.0 ? zscale(alpha, ia) : make_double2(1.0, 0.0);
       beta = zscale(ph, -xnorm);
       v0 = zsub(alpha, beta);
-      vinv = rsqrt(2.0 * xnorm * (xnorm + aa));
+      tau = 1.0 / (xnorm * (xnorm + aa));
     }
-    // u = (x - beta e_j) / ||x - beta e_j||: rows > j are x * vinv
-#pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-      const bool on = h + G * i > j && h + G * i < rows;
-      const zt uu = zscale(y[i], vinv);
-      zt w;
-      w.x = on ? uu.x : 0.0;
-      w.y = on ? uu.y : 0.0;
-      ub[h + G * i] = w;
+    if (h == hj) ub[j] = v0;
+    if (h == 0) {
+      rdiag[j] = beta;
+      sh.tau_s[j] = tau;
     }
-    const zt u0 = zscale(v0, vinv);
-    if (h == hj) ub[j] = u0;
-    if (h == 0) rdiag[j] = beta;
-    my_vinv = vinv;
-    my_u0 = u0;
+    my_tau = tau;
+    my_v0 = v0;
     mine = j;
   };
-  // trailing column: y -= 2 u (u^H y) with u in ub, zero outside its rows;
-  // with want_norm (uniform over the wavefront) the norm of rows > j is
-  // returned (else 0)
-  auto apply = [&](const zt* ub, int j, bool want_norm) {
-    zt uu[KEEP];  // u kept in registers between the two loops when they fit
+  auto reflector = [&](int j, int p, double pn, zt* ub) {
+    write_v(ub, j);
+    finish_reflector(j, p, pn, ub);
+  };
+  // trailing column: y -= tau_j v (v^H y) with v in ub, zero outside its
+  // rows; with want_norm (uniform over the wavefront) the norm of rows > j is
+  // returned (else 0); with vout (the next reflector's group) rows > j + 1 of
+  // the updated column are written there as the next v, before the norm is
+  // reduced
+  auto apply = [&](const zt* ub, int j, bool want_norm, zt* vout) {
+    const double tau = sh.tau_s[j];
+    zt uu[KEEP];  // v kept in registers between the two loops when they fit
     double dr0 = 0.0, di0 = 0.0, dr1 = 0.0, di1 = 0.0;
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
@@ -611,7 +626,7 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
         zdot_acc(u, y[i], dr0, di0);
     }
     const double dr = group_sum(dr0 + dr1, G), di = group_sum(di0 + di1, G);
-    const zt d2 = make_double2(2.0 * dr, 2.0 * di);
+    const zt d2 = make_double2(tau * dr, tau * di);
     // without the kept copy, the second read of u must not be hoisted
     // above this point (it would hold every row twice in registers)
     if (KEEP < RPL) __builtin_amdgcn_sched_barrier(0);
@@ -629,6 +644,7 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
         else
           tn0 = fma(yx, yx, fma(yy, yy, tn0));
       }
+      if (vout) write_v(vout, j + 1);
       tn = group_sum(tn0 + tn1, G);
     } else {
 #pragma unroll
@@ -651,8 +667,8 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
       if (have && g > j) {
         // the wavefront that holds group j + 1 sums trailing norms
         const bool lead = (tid >> 6) == (((j + 1) * G) >> 6);
-        const double tn = apply(slot(j), j, lead);
-        if (g == j + 1) reflector(j + 1, g, sqrt(tn), slot(j + 1));
+        const double tn = apply(slot(j), j, lead, g == j + 1 ? slot(j + 1) : nullptr);
+        if (g == j + 1) finish_reflector(j + 1, g, sqrt(tn), slot(j + 1));
       }
       __syncthreads();  // reflector j + 1 is published; reflector j is read
     }
@@ -678,7 +694,7 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
     if (tid == 0) piv_grp[j] = p;
     if (have && mine == kMaxL) {
       if (my_pos == j) my_pos = pp;  // the swap of qr_core moves it to the pivot's place
-      my_tn = apply(slot(j), j, true);
+      my_tn = apply(slot(j), j, true, nullptr);
       if (h == 0) key_s[g] = pivot_key(my_tn, my_pos, g);
     }
     if (g == p && h == 0) key_s[g] = 0ull;
@@ -702,42 +718,42 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
     for (int c = tid; c < rank; c += NT) P.piv[c] = piv_grp[c];
   }
   // Q = H_0 ... H_{r-1} [I; 0]: the group of logical column c < rank starts
-  // from H_c e_c = e_c - 2 u_c conj(u_c[c]) and applies H_{c-1}, ..., H_0.
+  // from H_c e_c = e_c - tau_c v_c conj(v_c[c]) and applies H_{c-1}, ..., H_0.
   // With a slot per reflector the groups need no barrier.  With the
-  // alternating buffers, the group of column j publishes u_j one step
+  // alternating buffers, the group of column j publishes v_j one step
   // ahead, while H_{j+1} is being applied (column j is not touched by H_j or
   // later reflectors): one barrier per step.
-  auto start_q = [&](zt* ub) {  // by the group with mine < rank; ub: publish u_c there
+  auto start_q = [&](zt* ub) {  // by the group with mine < rank; ub: publish v_c there
     const int c = mine, i0 = c / G, hc = c - i0 * G;
-    const zt m = make_double2(-2.0 * my_u0.x, 2.0 * my_u0.y);  // -2 conj(u_c[c])
+    // -tau_c conj(v_c[c])
+    const zt m = make_double2(-my_tau * my_v0.x, my_tau * my_v0.y);
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
       const bool on = h + G * i > c && h + G * i < rows;
-      const zt uu = zscale(y[i], my_vinv);
       zt w;
-      w.x = on ? uu.x : 0.0;
-      w.y = on ? uu.y : 0.0;
+      w.x = on ? y[i].x : 0.0;
+      w.y = on ? y[i].y : 0.0;
       if (ub) ub[h + G * i] = w;  // zeros outside [c, rows)
       y[i] = zmul(w, m);
     }
-    if (ub && h == hc) ub[c] = my_u0;
+    if (ub && h == hc) ub[c] = my_v0;
 #pragma unroll
     for (int i = 0; i < RPL; ++i)
       if (i == i0 && h == hc) {
-        y[i] = zmul(my_u0, m);
+        y[i] = zmul(my_v0, m);
         y[i].x += 1.0;
       }
   };
   if constexpr (slots) {
     if (have && mine < rank) start_q(nullptr);
     for (int j = rank - 2; j >= 0; --j)
-      if (have && mine > j && mine < rank) apply(slot(j), j, false);
+      if (have && mine > j && mine < rank) apply(slot(j), j, false, nullptr);
   } else {
     if (rank > 0 && mine == rank - 1) start_q(slot(rank - 1));
     for (int j = rank - 1; j >= 0; --j) {
       __syncthreads();  // u_j is published; the reads of the other buffer are done
       if (j > 0 && mine == j - 1) start_q(slot(j - 1));
-      if (have && mine > j && mine < rank) apply(slot(j), j, false);
+      if (have && mine > j && mine < rank) apply(slot(j), j, false, nullptr);
     }
   }
   if (have && mine < rank) {
