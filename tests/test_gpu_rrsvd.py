@@ -66,7 +66,12 @@ def _compare(mats, res, chi_max, p, q, eps, omegas=None):
         assert np.allclose(VH[b][:c] @ VH[b][:c].conj().T, np.eye(c), atol=1e-12)
 
 
-@pytest.mark.parametrize("m,n,chi_max,p", [(37, 53, 8, 10), (200, 130, 40, 10), (130, 200, 40, 10),
+# the QR size classes: (37, 53) register class 0; (190, 140, l = 33) and
+# (300, 200, l = 20) register class 1 with a slot per reflector (16 and 32
+# lanes per column); the 130-row side of (200, 130) register class 1 with
+# alternating reflector buffers; the larger ones the global class
+@pytest.mark.parametrize("m,n,chi_max,p", [(37, 53, 8, 10), (190, 140, 23, 10), (300, 200, 10, 10),
+                                           (200, 130, 40, 10), (130, 200, 40, 10),
                                            (300, 300, 50, 10), (700, 650, 64, 10)])
 def test_parity_with_oracle_same_omega(m, n, chi_max, p):
     gen = wl.rng(m * 1000 + n)
