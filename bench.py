@@ -137,17 +137,27 @@ QR_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1504
                          "csrc", "factor.hip")
 
 
+def code_digest(path):
+    """sha256 of a C++ source with comments and white space removed, so that
+    a change to the comments alone keeps the digest (and the counters)."""
+    import hashlib
+    import re
+    text = open(path, encoding="utf-8").read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return hashlib.sha256(re.sub(r"\s+", "", text).encode()).hexdigest()
+
+
 def qr_traffic():
     """Bytes per QR launch from the committed counter summary, or None when
-    it is absent or was taken on another version of the QR source."""
-    import hashlib
+    it is absent or was taken on another version of the QR code."""
     try:
         lines = open(QR_TRAFFIC_FILE).read().splitlines()
-        digest = hashlib.sha256(open(QR_SOURCE, "rb").read()).hexdigest()
+        digest = code_digest(QR_SOURCE)
     except OSError:
         return None
     fields = dict(l[2:].split(": ", 1) for l in lines if l.startswith("# ") and ": " in l)
-    if fields.get("factor.hip sha256") != digest:
+    if fields.get("factor.hip code sha256") != digest:
         return None
     try:
         return float(fields["bytes per qr launch"])

@@ -491,8 +491,9 @@ __host__ __device__ __forceinline__ int qr_class(int rows, int l) {
 // pivot_key order, over the positions the swaps of qr_core would have
 // produced (each group tracks its own): every trailing group posts its key
 // in LDS, and after the barrier each wavefront takes their maximum.  The
-// pivot group is recorded as logical column j; R, the pivot order and the thin Q are written out in logical
-// order.  Same reflectors, pivoting rule and rank tolerance as qr_core.
+// pivot group is recorded as logical column j; R, the pivot order and the
+// thin Q are written out in logical order.  Same reflectors (stored
+// unnormalised), pivoting rule and rank tolerance as qr_core.
 // With pivoting, two barriers per factorisation step (trailing norms,
 // reflector); without, one.  Every reflector keeps an LDS slot of its own
 // when they all fit (always for 512 threads x 8 rows), and then each group
@@ -660,7 +661,8 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
     // Logical column j is group j, which builds reflector j as soon as its
     // own update by reflector j - 1 is done (with its trailing norm summed
     // in the same pass), while the other groups are still applying j - 1;
-    // the reflector buffers alternate, so one barrier per step suffices.
+    // reflector j + 1 goes to another slot or buffer than reflector j, so
+    // one barrier per step suffices.
     if (g == 0) reflector(0, 0, sqrt(nn), slot(0));
     __syncthreads();
     for (int j = 0; j + 1 < l; ++j) {
@@ -751,7 +753,7 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
   } else {
     if (rank > 0 && mine == rank - 1) start_q(slot(rank - 1));
     for (int j = rank - 1; j >= 0; --j) {
-      __syncthreads();  // u_j is published; the reads of the other buffer are done
+      __syncthreads();  // v_j is published; the reads of the other buffer are done
       if (j > 0 && mine == j - 1) start_q(slot(j - 1));
       if (have && mine > j && mine < rank) apply(slot(j), j, false, nullptr);
     }

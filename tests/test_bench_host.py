@@ -41,14 +41,15 @@ def test_qr_bytes():
 def test_traffic_only_for_the_measured_source(tmp_path):
     b = _bench()
     src = tmp_path / "factor.hip"
-    src.write_text("// some QR source\n")
-    import hashlib
-    digest = hashlib.sha256(src.read_bytes()).hexdigest()
+    src.write_text("// some QR source\nint f() { return 1; }\n")
+    digest = b.code_digest(str(src))
     summary = tmp_path / "qr_hbm_traffic_counters.txt"
-    summary.write_text(f"# factor.hip sha256: {digest}\n# bytes per qr launch: 1234\n")
+    summary.write_text(f"# factor.hip code sha256: {digest}\n# bytes per qr launch: 1234\n")
     b.QR_SOURCE, b.QR_TRAFFIC_FILE = str(src), str(summary)
     assert b.qr_traffic() == 1234.0
-    src.write_text("// the QR source, changed since the counters\n")
+    src.write_text("/* reworded */ int f()  {\n  return 1;  // comment\n}\n")  # comments only
+    assert b.qr_traffic() == 1234.0
+    src.write_text("int f() { return 2; }\n")  # the code changed since the counters
     assert b.qr_traffic() is None
     b.QR_TRAFFIC_FILE = str(tmp_path / "absent.txt")
     assert b.qr_traffic() is None
