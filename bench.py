@@ -177,7 +177,7 @@ def roofline(prof, flops):
              "avg_launch_us": round(1e3 * ms / launches, 2) if launches else None}
     if kind in ("qr", "qr_with_r", "small_svd"):
         entry["note"] = ("one launch = every size class the batch reaches, run side by side; "
-                         "rocprofv3 lists the class kernels (k_qr_reg<512, 8>, ...) separately")
+                         "rocprofv3 lists the class kernels (k_qr_reg<512, 8, piv>, ...) separately")
     if kind in flops and ms > 0:
         ach = flops[kind] / (ms * 1e-3) / 1e12
         entry.update({"bound": KIND_BOUND[kind], "achieved": round(ach, 4),
