@@ -1,433 +1,650 @@
 """Throughput of the batched TEBD bond update with RRSVD on one MI355X.
 
-Workload (default): 16 independent chain-mapped spin-boson chains (Eq. H_1D:
+Headline workload: 16 independent chain-mapped spin-boson chains (Eq. H_1D:
 spin-1/2 plus 99 oscillators truncated to d = 10, t_n = 0.5, omega_n = 1),
 chi_max = 100, RRSVD with p = 10, q = 2, per-bond discarded weight
-<= 1e-10, dt = 0.05, symmetric Trotter steps from |up>|0...0>.  One step is
-three sweeps (even, odd, even bonds) over all 16 chains = 2384 bond updates.
-W warm-up steps, then K timed steps, continue one run of W + K = 200 steps
-by default, so the timed region covers the whole evolution.
+<= 1e-10, dt = 0.05, 200 symmetric Trotter steps from |up>|0...0>.  One
+"step" of this benchmark is the whole 200-step evolution of all 16 chains
+from the product state (600 sweeps, 476,800 bond updates): --warmup W such
+evolutions run untimed, then --steps K are timed one by one (the state is
+reset to the product state outside the timed region; every repetition
+computes the same numbers, its Gaussian test matrices included).
 
 The JSON line also carries:
-* roofline   -- the kernel kind with the largest event time in the timed
-                region; algorithmic flops from the recorded bond dimensions
-                of every problem, divided by its event-timed duration;
-* cpu_baseline -- the FP64 CPU oracle (full-SVD TEBD of chain 0 of the same
-                workload) timed on the host for a bounded sample;
-* full_svd   -- the same TEBD steps with the vendor full SVD
-                (torch.linalg.svd) in a torch-only comparator on this GPU;
-* batched_rrsvd -- the 256-matrix standalone RRSVD workload (sizes
-                256..2048, s_i = exp(-i/25), k = 64, p = 10, q = 2);
-* mixed_precision -- the spin-boson workload at chi_max = 128 with the
-                sketch and power-iteration GEMMs in complex FP32, beside the
-                FP64 path on the same inputs (errors of lambda and <sigma_z>);
-* adjoint    -- d<Z_0(T)>/dJ_b of the XX chain with random fields (N = 40,
-                chi_max = 64, 50 steps of dt = 0.02, checkpoints every 10
-                steps): time per gradient and its error against the stored
-                references (exact-SVD reverse mode, central differences,
-                free fermions).
+* roofline   -- the kernel with the largest event time in a profiled
+                repetition of the same evolution (HIP events around every
+                launch, on the launch's stream); algorithmic flops and bytes
+                from the recorded bond dimensions of every problem of every
+                sweep, divided by that kernel's summed event time; measured
+                HBM bytes per launch from committed rocprofv3 counters while
+                the kernel sources match them;
+* cpu_baseline -- the FP64 CPU oracle (full-SVD TEBD) on chain 0 of the same
+                workload, all 200 steps;
+* full_svd   -- the same evolution with the vendor full SVD
+                (torch.linalg.svd), batched over every same-shape bond of a
+                sweep, truncated on the device, on this GPU;
+* tfim, batched_rrsvd, mixed_precision, adjoint -- the other workloads
+                (plain TEBD N = 20; 256 standalone RRSVDs; chi_max = 128 with
+                complex FP32 sketches; the reverse-mode gradient of the XX
+                chain), each with its own roofline and CPU-oracle figure.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
+PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix and vector)
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+METRIC = "TEBD bond updates/s, RRSVD vs full SVD on 1 GPU at <=1e-10 trunc err"
+
+SB = dict(N=100, d=10, chi_max=100, p=10, q=2, dt=0.05, steps=200, eps=1e-10, seed=1504)
+TFIM = dict(N=20, chi_max=32, p=10, q=2, dt=0.01, steps=100, eps=1e-10, seed=1504)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5,
+                    help="timed repetitions of the whole 200-step evolution")
+    ap.add_argument("--warmup", type=int, default=1,
+                    help="untimed repetitions before the timed ones")
+    ap.add_argument("--chains", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 256 MiB device buffer three times (the known-size kernel "
                          "that scales the HBM byte counters) and exit")
-    ap.add_argument("--steps", type=int, default=190)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--chains", type=int, default=16)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--full-svd-steps", type=int, default=-1,
-                    help="steps of the torch full-SVD comparator (-1: same as --steps)")
-    ap.add_argument("--full-svd-seconds", type=float, default=90.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-full-svd", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--mixed-steps", type=int, default=100)
-    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="the headline evolution only (timed, then one profiled repetition)")
+    ap.add_argument("--no-profile", action="store_true", help="skip the profiled repetition")
+    for x in ("cpu-baseline", "full-svd", "other-rank", "tfim", "batched", "mixed", "adjoint"):
+        ap.add_argument(f"--no-{x}", action="store_true")
     ap.add_argument("--rank", choices=("adaptive", "fixed"), default="adaptive",
                     help="rank of the timed run: two-stage adaptive (k1 from the bond dimension, "
                          "k = chi_max when needed) or fixed k = chi_max")
-    ap.add_argument("--no-other-rank", action="store_true",
-                    help="skip the run with the other rank mode")
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.headline_only:
+        for x in ("cpu_baseline", "full_svd", "other_rank", "tfim", "batched", "mixed", "adjoint"):
+            setattr(a, "no_" + x, True)
+    return a
+
+
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 # ---------------------------------------------------------------------------
-# algorithmic flop counts (complex arithmetic: one multiply-add = 8 flops)
-def sketch_flops(m, n, l):
-    return 8.0 * m * n * l
-
-
+# Algorithmic work per kernel (complex arithmetic: one multiply-add = 8 real
+# flops; bytes are those the operation must move between HBM and the chip).
 def qr_flops(rows, l):
-    # Householder factorisation plus explicit thin Q, complex: 2 x 4 (2 r l^2 - 2 l^3 / 3)
+    """Householder factorisation plus explicit thin Q, complex."""
     return 16.0 * rows * l * l - 16.0 / 3.0 * l ** 3
 
 
-def theta_gate_flops(dl, dr, cl, cm, cr):
-    return 8.0 * (dl * cl * cm * dr * cr + (dl * dr) ** 2 * cl * cr)
-
-
-def sweep_problems(chi_row, dims, parity, chi_max, p, adaptive):
-    """(dl, dr, cl, cm, cr, m, n, l) of every bond of one chain in a sweep.
-
-    l is the sketch width of the pass that every bond runs: with the
-    adaptive rank the first stage's k1 + p, k1 = chi_m + max(4, ceil(chi_m / 2))
-    capped by chi_max (the few bonds that need the fixed-rank second stage
-    add work that is not counted); otherwise chi_max + p.  Both capped by
-    m and n."""
-    out = []
-    for b in range(parity, len(dims) - 1, 2):
-        cl, cm, cr = int(chi_row[b]), int(chi_row[b + 1]), int(chi_row[b + 2])
-        dl, dr = dims[b], dims[b + 1]
-        m, n = dl * cl, dr * cr
-        k = min(chi_max, cm + max(4, (cm + 1) // 2)) if adaptive else chi_max
-        out.append((dl, dr, cl, cm, cr, m, n, min(k + p, m, n)))
-    return out
-
-
 def qr_bytes(rows, l, with_r=False):
-    """HBM bytes a QR must move: read the rows x l sketch, write the thin Q
-    (and the l x l R factor)."""
+    """Read the rows x l sketch, write Q (and the l x l R)."""
     return 16.0 * (2 * rows * l + (l * l if with_r else 0))
 
 
-def kind_flops(chi_hist, parities, dims, chi_max, p, q, adaptive):
-    """Algorithmic flops per profiled kernel kind over the recorded sweeps,
-    and the QR launches' algorithmic bytes (key "qr_bytes", both QR kinds)."""
-    tot = {"theta_gate": 0.0, "sketch_A_Omega": 0.0, "sketch_AH_Q": 0.0, "sketch_A_Qt": 0.0,
-           "qr": 0.0, "qr_with_r": 0.0, "qr_bytes": 0.0}
-    for chi, parity in zip(chi_hist, parities):
-        for c in range(chi.shape[0]):
-            for (dl, dr, cl, cm, cr, m, n, l) in sweep_problems(chi[c], dims, parity, chi_max, p,
-                                                                adaptive):
-                tot["theta_gate"] += theta_gate_flops(dl, dr, cl, cm, cr)
-                tot["sketch_A_Omega"] += sketch_flops(m, n, l)
-                tot["sketch_AH_Q"] += (q + 1) * sketch_flops(m, n, l)
-                tot["sketch_A_Qt"] += q * sketch_flops(m, n, l)
-                tot["qr"] += (q + 1) * qr_flops(m, l) + q * qr_flops(n, l)
-                tot["qr_with_r"] += qr_flops(n, l)
-                tot["qr_bytes"] += ((q + 1) * qr_bytes(m, l) + q * qr_bytes(n, l)
-                                    + qr_bytes(n, l, with_r=True))
-    return tot
+QR_KERNELS = ("k_qr_reg<512, 8, {}>", "k_qr_reg<1024, 12, {}>", "k_qr_lds<1024>", "k_qr_glb<1024>")
 
 
-COPY_PROBE_BYTES = 256 << 20
-# HBM bytes of the QR kernels from rocprofv3 counters (FETCH_SIZE and
-# WRITE_SIZE runs, scaled by the same counters on a copy of known size);
-# used only while the QR source still matches the one the counters saw
-QR_TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                               "qr_hbm_traffic_counters.txt")
-QR_SOURCE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1504_00992_amd",
-                         "csrc", "factor.hip")
+class Work:
+    """{kernel name: [flops, bytes]} accumulated problem by problem."""
+
+    def __init__(self, lib):
+        self.lib = lib
+        self.k = {}
+        self._cls = {}
+
+    def add(self, name, flops, nbytes):
+        e = self.k.setdefault(name, [0.0, 0.0])
+        e[0] += flops
+        e[1] += nbytes
+
+    def qr_class(self, rows, l):
+        key = (rows, l)
+        if key not in self._cls:
+            self._cls[key] = self.lib.tebd_size_class(0, rows, l)
+        return self._cls[key]
+
+    def qr(self, rows, l_class, l, pivot, with_r=False):
+        name = QR_KERNELS[self.qr_class(rows, l_class)].format("true" if pivot else "false")
+        self.add(name, qr_flops(rows, l), qr_bytes(rows, l, with_r))
+
+    def rrsvd_pass(self, m, n, l, q, mixed, chi_new, form=True):
+        """Kernels of Alg. 1 and steps i-iii for one problem at width l
+        (form=False: a first pass whose result the second pass replaces)."""
+        lc = l
+        sk = "k_sketch_f32<{}>" if mixed else "k_sketch<{}>"
+        mn, f = 16.0 * m * n, 8.0 * m * n * l
+        self.add("k_omega", 0.0, 16.0 * n * l)
+        self.add(sk.format(0), f, mn + 16.0 * (n * l + m * l))
+        self.qr(m, lc, l, True)
+        for _ in range(q):
+            self.add(sk.format(1), f, mn + 16.0 * (m * l + n * l))
+            self.qr(n, lc, l, False)
+            self.add(sk.format(2), f, mn + 16.0 * (n * l + m * l))
+            self.qr(m, lc, l, False)
+        self.add("k_sketch<1>", f, mn + 16.0 * (m * l + n * l))   # B^H = A^H Q (FP64)
+        self.qr(n, lc, l, True, with_r=True)
+        c = chi_new
+        if not form:
+            return
+        self.add("k_form_u<1>", 8.0 * m * l * c, 16.0 * (m * l + l * c + m * c))
+        self.add("k_form_vh<1>", 8.0 * n * l * c, 16.0 * (n * l + l * c + n * c))
 
 
-def code_digest(path):
-    """sha256 of a C++ source with comments and white space removed, so that
-    a change to the comments alone keeps the digest (and the counters)."""
-    import hashlib
-    import re
-    text = open(path, encoding="utf-8").read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    text = re.sub(r"//[^\n]*", "", text)
-    return hashlib.sha256(re.sub(r"\s+", "", text).encode()).hexdigest()
+def first_stage_rank(chi_mid, chi_max):
+    return min(chi_max, chi_mid + max(4, (chi_mid + 1) // 2))
 
 
-def qr_traffic():
-    """Bytes per QR launch from the committed counter summary, or None when
-    it is absent or was taken on another version of the QR code."""
-    try:
-        lines = open(QR_TRAFFIC_FILE).read().splitlines()
-        digest = code_digest(QR_SOURCE)
-    except OSError:
-        return None
-    fields = dict(l[2:].split(": ", 1) for l in lines if l.startswith("# ") and ": " in l)
-    if fields.get("factor.hip code sha256") != digest:
-        return None
-    try:
-        return float(fields["bytes per qr launch"])
-    except (KeyError, ValueError):
-        return None
+def sweep_work(work, chi_before, chi_after, status, parity, dims, chi_max, p, q, adaptive,
+               mixed=False):
+    """Add every problem of one recorded sweep (all chains) to `work`.
 
-
-KIND_BOUND = {"theta_gate": "mfma", "sketch_A_Omega": "mfma", "sketch_AH_Q": "mfma",
-              "sketch_A_Qt": "mfma", "qr": "alu", "qr_with_r": "alu"}
-
-
-def roofline(prof, flops):
-    """Roofline entry for the kind with the largest event time."""
-    kind = max(prof, key=lambda k: prof[k][0])
-    ms, launches = prof[kind]
-    entry = {"kernel": kind, "launches": launches, "event_ms_total": round(ms, 3),
-             "avg_launch_us": round(1e3 * ms / launches, 2) if launches else None}
-    if kind in ("qr", "qr_with_r", "small_svd"):
-        entry["note"] = ("one launch = every size class the batch reaches, run side by side; "
-                         "rocprofv3 lists the class kernels (k_qr_reg<512, 8, piv>, ...) separately")
-    if kind in flops and ms > 0:
-        ach = flops[kind] / (ms * 1e-3) / 1e12
-        entry.update({"bound": KIND_BOUND[kind], "achieved": round(ach, 4),
-                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                      "frac": round(ach / PEAK_FP64_TFLOPS, 5), "traffic": None})
-        if kind == "qr":
-            nl = launches + (prof["qr_with_r"][1] if "qr_with_r" in prof else 0)
-            if nl and "qr_bytes" in flops:
-                # per launch of either QR kind, as the counters are taken
-                entry["algorithmic_bytes"] = round(flops["qr_bytes"] / nl)
-            t = qr_traffic()
-            if t is not None:
-                entry["traffic"] = round(t)
-                entry["traffic_note"] = ("HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by "
-                                         "a copy of known size): " + os.path.basename(QR_TRAFFIC_FILE))
-    else:
-        entry.update({"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS,
-                      "unit": "TFLOP/s", "frac": None, "traffic": None,
-                      "note": "iterative kernel: no fixed algorithmic flop count"})
-    return entry
+    chi_before / chi_after: [chains, N + 1]; status: [chains, N - 1] after the
+    sweep (bit 64: the problem ran the second, fixed-rank pass).  The first
+    pass runs at l1 = min(k1 + p, m, n) (k1 = chi_max without the adaptive
+    rank); the QRs after the first work on the rank it reveals, at most l1,
+    so the counts are upper bounds there."""
+    n_ch = chi_before.shape[0]
+    for c in range(n_ch):
+        for b in range(parity, len(dims) - 1, 2):
+            cl, cm, cr = int(chi_before[c, b]), int(chi_before[c, b + 1]), int(chi_before[c, b + 2])
+            dl, dr = dims[b], dims[b + 1]
+            m, n = dl * cl, dr * cr
+            cnew = int(chi_after[c, b + 1])
+            work.add("k_theta", 8.0 * dl * cl * cm * dr * cr,
+                     16.0 * (dl * cl * cm + dr * cm * cr + dl * dr * cl * cr))
+            gbytes = 16.0 * (dl * dr) ** 2 if c == 0 else 0.0   # gates shared by the chains
+            work.add("k_gate", 8.0 * (dl * dr) ** 2 * cl * cr,
+                     gbytes + 16.0 * 2 * dl * dr * cl * cr)
+            k1 = first_stage_rank(cm, chi_max) if adaptive else chi_max
+            l1 = min(k1 + p, m, n)
+            retried = adaptive and int(status[c, b]) & 64
+            work.rrsvd_pass(m, n, l1, q, mixed, cnew, form=not retried)
+            if retried:
+                l2 = min(chi_max + p, m, n)
+                work.rrsvd_pass(m, n, l2, q, mixed, cnew)
 
 
 # ---------------------------------------------------------------------------
-def run_gpu_tebd(args, torch, api, models, adaptive, prof_on=True):
-    N, d, chi_max, p, q = 100, 10, 100, 10, 2
-    dims, hb = models.spin_boson(N, d, 1.0, 0.5, 1.0, 0.5)
-    mps = api.DeviceMPS.product_state(args.chains, dims, [0] * N, chi_max)
-    drv = api.TEBD(mps, hb, 0.05, chi_max, p=p, q=q, trunc_eps=1e-10, seed=1504,
-                   adaptive=2 if adaptive else 0)
-    for _ in range(args.warmup):
-        drv.step()
-    torch.cuda.synchronize()
-    # the profiled pass also records every sweep's bond dimensions (for the
-    # algorithmic flop counts of the roofline)
-    chi_hist = torch.empty((3 * args.steps, args.chains, N + 1), dtype=torch.int32, device="cuda")
-    parities = []
-    api._lib.tebd_profile_enable(prof_on)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    k = 0
-    for _ in range(args.steps):
-        for parity, gates in ((0, drv.g_half), (1, drv.g_full), (0, drv.g_half)):
-            if prof_on:
-                chi_hist[k].copy_(mps.chi)
-            parities.append(parity)
-            drv.sweep(parity, gates)
-            k += 1
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = api._lib.tebd_profile_read() if prof_on else {}
-    api._lib.tebd_profile_enable(False)
-    status = drv.ws.status.cpu().numpy()
-    return dict(seconds=t1 - t0, prof=prof, chi_hist=chi_hist.cpu().numpy(), parities=parities,
-                dims=dims, hb=hb, chi_final=mps.chi.cpu().numpy(), status=status)
+# Measured HBM bytes (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a copy of
+# known size), keyed by kernel, valid while the kernel sources are unchanged.
+CSRC = os.path.join(ROOT, "paper_1504_00992_amd", "csrc")
 
 
+def code_digest():
+    """sha256 over the library's kernel sources with comments and white
+    space removed (a comment-only change keeps the digest)."""
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if not f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            continue
+        text = open(os.path.join(CSRC, f), encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update(f.encode())
+        h.update(re.sub(r"\s+", "", text).encode())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from profiles/<workload>_hbm_traffic.txt,
+    or None when absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.txt")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None, None
+    fields = dict(l[2:].split(": ", 1) for l in lines if l.startswith("# ") and ": " in l)
+    if fields.get("kernel sources sha256") != code_digest():
+        return None, os.path.basename(path)
+    for l in lines:
+        if l.startswith("#") or not l.strip():
+            continue
+        parts = l.rsplit(None, 4)
+        if len(parts) == 5 and parts[0].strip() == kernel:
+            return float(parts[4]), os.path.basename(path)
+    return None, os.path.basename(path)
+
+
+ALU_KERNELS = ("k_qr_", "k_svd_pairs", "k_small_svd", "k_truncate", "k_omega", "k_schedule",
+               "k_plan", "k_stage2", "k_frob")
+
+
+def kernel_roofline(prof, work, workload):
+    """Roofline entry of the kernel with the largest event time."""
+    kern = {k: v for k, v in prof.items() if k.startswith("k_")}
+    if not kern:
+        return None
+    name = max(kern, key=lambda k: kern[k][0])
+    ms, launches = kern[name]
+    e = {"kernel": name, "launches": launches, "event_ms_total": round(ms, 3),
+         "avg_launch_us": round(1e3 * ms / launches, 3) if launches else None}
+    fl, by = work.k.get(name, (0.0, 0.0))
+    f32 = name.startswith("k_sketch_f32")
+    if fl > 0 and ms > 0:
+        ach = fl / (ms * 1e-3) / 1e12
+        alu = name.startswith(ALU_KERNELS)
+        peak = PEAK_FP32_MFMA_TFLOPS if f32 else PEAK_FP64_TFLOPS
+        e.update({"bound": "alu" if alu else "mfma", "achieved": round(ach, 4), "peak": peak,
+                  "unit": "TFLOP/s", "frac": round(ach / peak, 5)})
+        e["flops_per_launch"] = round(fl / launches)
+        e["algorithmic_bytes_per_launch"] = round(by / launches)
+        e["hbm_GBps_algorithmic"] = round(by / (ms * 1e-3) / 1e9, 2)
+    else:
+        # no fixed flop count (iterative or data movement): rate in bytes
+        gbs = by / (ms * 1e-3) / 1e9 if ms > 0 else None
+        e.update({"bound": "hbm", "achieved": round(gbs, 3) if gbs else None,
+                  "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                  "frac": round(gbs / PEAK_HBM_GBS, 5) if gbs else None,
+                  "note": "no fixed algorithmic flop count: bytes per event time"})
+        e["algorithmic_bytes_per_launch"] = round(by / launches) if launches else None
+    t, src = measured_traffic(name, workload)
+    e["traffic"] = round(t) if t is not None else None
+    if src:
+        e["traffic_source"] = f"profiles/{src}" + ("" if t is not None else
+                                                   " (taken on other kernel sources: not used)")
+    e["measured"] = "HIP events around every launch of a profiled repetition, on its stream"
+    return e
+
+
+def kernel_table(prof):
+    k = {n: v for n, v in prof.items() if n.startswith("k_")}
+    return {n: [round(v[0], 3), int(v[1])] for n, v in sorted(k.items(), key=lambda kv: -kv[1][0])}
+
+
+def phase_table(prof):
+    k = {n: v for n, v in prof.items() if not n.startswith("k_")}
+    return {n: [round(v[0], 3), int(v[1])] for n, v in sorted(k.items(), key=lambda kv: -kv[1][0])}
+
+
+# ---------------------------------------------------------------------------
 def updates_per_step(n_sites):
-    even = (n_sites - 1 + 1) // 2
+    even = n_sites // 2
     odd = (n_sites - 1) // 2
     return 2 * even + odd
 
 
-def full_svd_tebd(args, torch, models, dims, hb, warmup, steps):
-    """torch-only TEBD with torch.linalg.svd (full SVD) on the same workload.
+class Evolution:
+    """A batch of chains evolved by api.TEBD, restartable from its initial
+    state (the reset runs outside any timed region)."""
 
-    Runs `warmup` untimed steps, then times up to `steps` steps (stopping
-    early after --full-svd-seconds, which only flatters the comparator since
-    later steps carry larger bonds)."""
-    N, chi_max, eps, floor_ = len(dims), 100, 1e-10, 1e-14
+    def __init__(self, torch, api, dims, hb, levels, chains, chi_max, p, q, dt, eps, seed,
+                 adaptive=2, precision=0):
+        self.torch = torch
+        self.mps = api.DeviceMPS.product_state(chains, dims, levels, chi_max)
+        self.init = (self.mps.gamma.clone(), self.mps.lam.clone(), self.mps.chi.clone())
+        self.drv = api.TEBD(self.mps, hb, dt, chi_max, p=p, q=q, trunc_eps=eps, seed=seed,
+                            adaptive=adaptive, precision=precision)
+        self.dims = dims
+
+    def reset(self):
+        self.mps.gamma.copy_(self.init[0])
+        self.mps.lam.copy_(self.init[1])
+        self.mps.chi.copy_(self.init[2])
+        self.drv.sweeps_done = 0
+        self.drv.ws.status.zero_()
+
+    def run(self, steps, record=None):
+        """Evolve `steps` steps; with record=list, append (parity, chi before,
+        chi after, status) of every sweep (device tensors)."""
+        d = self.drv
+        for _ in range(steps):
+            for parity, gates in ((0, d.g_half), (1, d.g_full), (0, d.g_half)):
+                before = self.mps.chi.clone() if record is not None else None
+                d.sweep(parity, gates)
+                if record is not None:
+                    record.append((parity, before, self.mps.chi.clone(), d.ws.status.clone()))
+
+    def timed(self, steps, reps, warmup):
+        torch = self.torch
+        for _ in range(warmup):
+            self.reset()
+            self.run(steps)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            self.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            self.run(steps)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        return times
+
+    def profiled(self, steps, lib):
+        """One repetition with per-launch events; returns (prof, history)."""
+        torch = self.torch
+        self.reset()
+        torch.cuda.synchronize()
+        hist = []
+        lib.tebd_profile_enable(True)
+        self.run(steps, record=hist)
+        torch.cuda.synchronize()
+        prof = lib.tebd_profile_read()
+        lib.tebd_profile_enable(False)
+        hist = [(p, b.cpu().numpy(), a.cpu().numpy(), s.cpu().numpy()) for p, b, a, s in hist]
+        return prof, hist
+
+
+def history_work(lib, hist, dims, chi_max, p, q, adaptive, mixed=False, times=1):
+    w = Work(lib)
+    for _ in range(times):
+        for parity, before, after, status in hist:
+            sweep_work(w, before, after, status, parity, dims, chi_max, p, q, adaptive, mixed)
+    return w
+
+
+# ---------------------------------------------------------------------------
+def full_svd_tebd(torch, models, dims, hb, chains, chi_max, dt, steps, eps=1e-10, floor_=1e-14):
+    """Torch-only TEBD with the vendor full SVD (torch.linalg.svd) on the GPU.
+
+    Every sweep groups its (chain, bond) problems by shape; each group is one
+    batched Theta contraction, gate product and SVD; the truncation rule,
+    renormalisation and lambda^-1 reabsorption run on the device with masks.
+    The new bond dimensions come back to the host once per sweep (to form the
+    next sweep's groups).  Returns the seconds of the timed evolution."""
+    import numpy as np
     dev = "cuda"
-    nch = args.chains
+    N = len(dims)
     dmax = max(dims)
-    gam = torch.zeros((nch, N, dmax, chi_max, chi_max), dtype=torch.complex128, device=dev)
-    lam = torch.zeros((nch, N - 1, chi_max), dtype=torch.float64, device=dev)
+    gam = torch.zeros((chains, N, dmax, chi_max, chi_max), dtype=torch.complex128, device=dev)
+    lam = torch.zeros((chains, N + 1, chi_max), dtype=torch.float64, device=dev)
     gam[:, :, 0, 0, 0] = 1.0
-    lam[:, :, 0] = 1.0
-    chi = [[1] * (N + 1) for _ in range(nch)]
-    gh = [torch.from_numpy(models.propagator(h, 0.025)).to(dev) for h in hb]
-    gf = [torch.from_numpy(models.propagator(h, 0.05)).to(dev) for h in hb]
+    lam[:, :, 0] = 1.0      # lam[:, b + 1] is the bond b; lam[:, 0] and lam[:, N] are edges (1)
+    chi = np.ones((chains, N + 1), dtype=np.int64)
+    gh = torch.from_numpy(models.gate_stack(dims, hb, 0.5 * dt)).to(dev)
+    gf = torch.from_numpy(models.gate_stack(dims, hb, dt)).to(dev)
 
-    def bond(b, g):
+    def sweep(parity, gates):
         groups = {}
-        for c in range(nch):
-            groups.setdefault((chi[c][b], chi[c][b + 1], chi[c][b + 2]), []).append(c)
-        dl, dr = dims[b], dims[b + 1]
-        for (cl, cm, cr), chains in groups.items():
-            idx = torch.tensor(chains, device=dev)
-            gk = gam[idx, b, :dl, :cl, :cm]
-            gk1 = gam[idx, b + 1, :dr, :cm, :cr]
-            ll = lam[idx, b - 1, :cl] if b >= 1 else torch.ones((len(chains), cl), dtype=torch.float64, device=dev)
-            lm = lam[idx, b, :cm]
-            lr = lam[idx, b + 1, :cr] if b + 1 <= N - 2 else torch.ones((len(chains), cr), dtype=torch.float64, device=dev)
-            left = (gk * ll[:, None, :, None] * lm[:, None, None, :]).contiguous()
-            right = (gk1 * lr[:, None, None, :]).contiguous()
-            th = torch.einsum("biag,bjgc->bijac", left, right).reshape(len(chains), dl * dr, cl * cr)
-            tt = torch.matmul(g, th)
-            a = tt.reshape(len(chains), dl, dr, cl, cr).permute(0, 1, 3, 2, 4).reshape(len(chains), dl * cl, dr * cr)
-            u, s, vh = torch.linalg.svd(a, full_matrices=False)
-            s2 = (s * s).cpu().numpy()
-            for j, c in enumerate(chains):
-                tot = s2[j].sum()
-                tails = (tot - s2[j].cumsum()) / tot
-                ok = [i for i in range(len(tails)) if tails[i] <= eps]
-                cp = min(chi_max, (ok[0] + 1) if ok else len(tails))
-                nrm = float(s2[j][:cp].sum()) ** 0.5
-                inv_l = torch.where(ll[j] > floor_, 1.0 / ll[j], torch.zeros_like(ll[j]))
-                inv_r = torch.where(lr[j] > floor_, 1.0 / lr[j], torch.zeros_like(lr[j]))
-                gam[c, b, :, :, :] = 0
-                gam[c, b + 1, :, :, :] = 0
-                gam[c, b, :dl, :cl, :cp] = u[j, :, :cp].reshape(dl, cl, cp) * inv_l[None, :, None]
-                gam[c, b + 1, :dr, :cp, :cr] = vh[j, :cp, :].reshape(cp, dr, cr).permute(1, 0, 2) * inv_r[None, None, :]
-                lam[c, b, :] = 0
-                lam[c, b, :cp] = s[j, :cp] / nrm
-                chi[c][b + 1] = cp
-
-    def step():
-        for parity, gs in ((0, gh), (1, gf), (0, gh)):
+        for c in range(chains):
             for b in range(parity, N - 1, 2):
-                bond(b, gs[b])
+                key = (dims[b], dims[b + 1], chi[c, b], chi[c, b + 1], chi[c, b + 2])
+                groups.setdefault(key, []).append((c, b))
+        new_chi = []
+        for (dl, dr, cl, cm, cr), items in groups.items():
+            ic = torch.tensor([x[0] for x in items], device=dev)
+            ib = torch.tensor([x[1] for x in items], device=dev)
+            G = len(items)
+            gk = gam[ic, ib, :dl, :cl, :cm]
+            gk1 = gam[ic, ib + 1, :dr, :cm, :cr]
+            ll = lam[ic, ib, :cl]
+            lm = lam[ic, ib + 1, :cm]
+            lr = lam[ic, ib + 2, :cr]
+            left = gk * (ll[:, None, :, None] * lm[:, None, None, :])
+            right = gk1 * lr[:, None, None, :]
+            th = torch.matmul(left.reshape(G, dl * cl, cm), right.permute(0, 2, 1, 3).reshape(
+                G, cm, dr * cr).contiguous())                       # [(i a), (j c)]
+            th = th.reshape(G, dl, cl, dr, cr).permute(0, 1, 3, 2, 4).reshape(G, dl * dr, cl * cr)
+            g = gates[ib][:, :dl * dr, :dl * dr].contiguous()
+            a = torch.matmul(g, th.contiguous()).reshape(G, dl, dr, cl, cr)
+            a = a.permute(0, 1, 3, 2, 4).reshape(G, dl * cl, dr * cr)
+            u, s, vh = torch.linalg.svd(a, full_matrices=False)
+            K = min(s.shape[1], chi_max)
+            s2 = s * s
+            tot = s2.sum(-1, keepdim=True)
+            tail = (tot - torch.cumsum(s2, -1)) / tot
+            cp = torch.clamp((tail > eps).sum(-1) + 1, max=K)       # smallest c with w(c) <= eps
+            keep = torch.arange(K, device=dev)[None, :] < cp[:, None]
+            sk = torch.where(keep, s[:, :K], torch.zeros_like(s[:, :K]))
+            nrm = torch.sqrt((sk * sk).sum(-1, keepdim=True))
+            inv_l = torch.where(ll > floor_, 1.0 / ll, torch.zeros_like(ll))
+            inv_r = torch.where(lr > floor_, 1.0 / lr, torch.zeros_like(lr))
+            uk = u[:, :, :K] * keep[:, None, :]
+            vk = vh[:, :K, :] * keep[:, :, None]
+            gam[ic, ib] = 0
+            gam[ic, ib + 1] = 0
+            gam[ic, ib, :dl, :cl, :K] = uk.reshape(G, dl, cl, K) * inv_l[:, None, :, None]
+            gam[ic, ib + 1, :dr, :K, :cr] = (vk.reshape(G, K, dr, cr).permute(0, 2, 1, 3)
+                                              * inv_r[:, None, None, :])
+            lam[ic, ib + 1] = 0
+            lam[ic, ib + 1, :K] = sk / nrm
+            new_chi.append((items, cp))
+        got = torch.cat([cp for _, cp in new_chi]).cpu().numpy()
+        i = 0
+        for items, _ in new_chi:
+            for (c, b) in items:
+                chi[c, b + 1] = got[i]
+                i += 1
 
-    for _ in range(warmup):
-        step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    done = 0
-    last = t0
     for _ in range(steps):
-        step()
-        done += 1
-        torch.cuda.synchronize()
-        now = time.perf_counter()
-        if now - last > 20.0:
-            _progress(f"full-SVD comparator: {done} steps, {now - t0:.0f} s")
-            last = now
-        if now - t0 > args.full_svd_seconds:
-            break
+        sweep(0, gh)
+        sweep(1, gf)
+        sweep(0, gh)
     torch.cuda.synchronize()
-    return done, time.perf_counter() - t0
+    return time.perf_counter() - t0, int(chi.max())
 
 
-def cpu_oracle_baseline(args, dims, budget_s):
-    """FP64 oracle TEBD (full LAPACK SVD) of chain 0, bounded by wall time."""
-    import numpy as np
-    from oracle import models as om, mps as omps
+# ---------------------------------------------------------------------------
+def _threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+        return max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
     except Exception:
-        threads = 1
-    N = len(dims)
-    _, hb = om.spin_boson_chain(N, dims[1], 1.0, 0.5, 1.0, 0.5)
+        return 1
+
+
+def oracle_tebd_seconds(dims, hb_oracle, dt, chi_max, steps, levels, eps=1e-10):
+    """FP64 oracle TEBD (full LAPACK SVD per bond) of one chain."""
+    from oracle import models as om, mps as omps
     cache = {}
 
     def gfn(b, tau):
-        key = (b, tau)
-        if key not in cache:
-            cache[key] = om.gate(hb[b], tau)
-        return cache[key]
-    m = omps.basis_product_state(dims, [0] * N)
-    drv = omps.TEBD(m, gfn, 0.05, 100, 1e-10, method="full")
-    for b in range(N - 1):  # gates outside the timed sample
-        gfn(b, 0.025), gfn(b, 0.05)
+        if (b, tau) not in cache:
+            cache[(b, tau)] = om.gate(hb_oracle[b], tau)
+        return cache[(b, tau)]
+    for b in range(len(dims) - 1):  # gates outside the timed sample
+        gfn(b, 0.5 * dt), gfn(b, dt)
+    drv = omps.TEBD(omps.basis_product_state(dims, levels), gfn, dt, chi_max, eps, method="full")
     t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < budget_s:
+    for _ in range(steps):
         drv.step()
-        steps += 1
-    dt = time.perf_counter() - t0
-    upd = steps * updates_per_step(N)
-    return {"value": round(upd / dt, 2), "unit": "bond updates/s", "cores": int(threads),
+    return time.perf_counter() - t0, max(drv.mps.chis())
+
+
+def cpu_baseline_spin_boson():
+    from oracle import models as om
+    N = SB["N"]
+    dims, hb = om.spin_boson_chain(N, SB["d"], 1.0, 0.5, 1.0, 0.5)
+    sec, chimax = oracle_tebd_seconds(dims, hb, SB["dt"], SB["chi_max"], SB["steps"], [0] * N)
+    upd = SB["steps"] * updates_per_step(N)
+    return {"value": round(upd / sec, 2), "unit": "bond updates/s", "cores": int(_threads()),
             "kind": "oracle",
-            "sample": f"chain 0 of the same workload, steps 1..{steps} of the run "
-                      f"({upd} bond updates, {dt:.1f} s), FP64 full LAPACK SVD per bond"}
+            "sample": f"chain 0 of the same workload, all {SB['steps']} steps from the product state "
+                      f"({upd} bond updates, {sec:.1f} s, max chi {chimax}); FP64, full LAPACK "
+                      f"SVD per bond, one chain (the 16 chains of the GPU run differ only in "
+                      f"their random test matrices)"}
 
 
-def batched_rrsvd(torch, api, wl):
+# ---------------------------------------------------------------------------
+def tfim_line(args, torch, api, models, lib):
+    """Plain TEBD: open TFIM N = 20, chi_max = 32, dt = 0.01, 100 steps."""
+    N = TFIM["N"]
+    dims, hb = models.transverse_ising(N, 1.0, 1.0)
+    ev = Evolution(torch, api, dims, hb, [0] * N, 1, TFIM["chi_max"], TFIM["p"], TFIM["q"],
+                   TFIM["dt"], TFIM["eps"], TFIM["seed"])
+    reps = max(3, args.steps)
+    times = ev.timed(TFIM["steps"], reps, 1)
+    upd = TFIM["steps"] * updates_per_step(N)
+    out = {"metric": "TEBD bond updates/s", "value": round(upd * reps / sum(times), 2),
+           "unit": "bond updates/s", "ms_per_evolution": round(1e3 * sum(times) / reps, 3),
+           "repetitions": reps,
+           "config": {"workload": "open transverse-field Ising chain N=20, J=h=1, |0...0>, "
+                                  "dt=0.01, 100 symmetric Trotter steps (2900 bond updates), "
+                                  "chi_max=32, RRSVD p=10 q=2, w<=1e-10, adaptive rank"}}
+    prof, hist = ev.profiled(TFIM["steps"], lib)
+    w = history_work(lib, hist, dims, TFIM["chi_max"], TFIM["p"], TFIM["q"], True)
+    out["roofline"] = kernel_roofline(prof, w, "tfim_n20")
+    out["chi_final_max"] = int(hist[-1][2].max())
+    if not args.no_cpu_baseline:
+        from oracle import models as om
+        odims, ohb = om.tfim(N, 1.0, 1.0)
+        sec, _ = oracle_tebd_seconds(odims, ohb, TFIM["dt"], TFIM["chi_max"], TFIM["steps"],
+                                     [0] * N)
+        out["cpu_baseline"] = {"value": round(upd / sec, 2), "unit": "bond updates/s",
+                               "cores": int(_threads()), "kind": "oracle",
+                               "sample": f"the whole evolution ({upd} bond updates, {sec:.2f} s), "
+                                         f"FP64 full LAPACK SVD per bond"}
+    return out
+
+
+def batched_rrsvd_line(args, torch, api, wl, lib):
+    """256 complex128 square matrices, n in {256, 512, 1024, 2048}, one call."""
+    import numpy as np
     sizes = wl.batched_rrsvd_sizes()
     mats = wl.batched_rrsvd_matrices_device(sizes)
-    from paper_1504_00992_amd import _lib
     api.rrsvd_truncate(mats, 64, 10, 2, 1e-10, 1504, 0)  # warm-up (workspace, code)
     torch.cuda.synchronize()
-    reps = 3
-    _lib.tebd_profile_enable(True)
-    t0 = time.perf_counter()
+    reps = max(3, args.steps)
+    times = []
+    out = None
     for r in range(reps):
-        out = api.rrsvd_truncate(mats, 64, 10, 2, 1e-10, 1504, r + 1)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = _lib.tebd_profile_read()
-    _lib.tebd_profile_enable(False)
-    l = 74
-    f_sk = sum(sketch_flops(n, n, l) for n in sizes)
-    sk_ms = sum(prof.get(k, (0.0, 0))[0] for k in ("sketch_A_Omega", "sketch_AH_Q", "sketch_A_Qt")) / reps
-    sk_fl = 6 * f_sk
-    ach = sk_fl / (sk_ms * 1e-3) / 1e12 if sk_ms > 0 else None
-    return {"metric": "RRSVD truncations/s", "value": round(len(sizes) * reps / (t1 - t0), 2),
-            "ms_per_batch": round(1e3 * (t1 - t0) / reps, 3),
-            "config": {"workload": "256 complex128 square matrices, n in {256,512,1024,2048}, "
-                                   "s_i=exp(-i/25), k=64, p=10, q=2, one call"},
-            "sketch_gemms": {"bound": "mfma", "achieved": round(ach, 3) if ach else None,
-                             "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                             "frac": round(ach / PEAK_FP64_TFLOPS, 4) if ach else None,
-                             "ms_per_batch": round(sk_ms, 3)},
-            "phase_ms_per_batch": {k: round(v[0] / reps, 3) for k, v in prof.items()}}
-
-
-def _spin_z(torch, gamma, lam, chains):
-    from paper_1504_00992_amd import gradient
-    z = torch.zeros((gamma.shape[2], gamma.shape[2]), dtype=torch.complex128, device="cuda")
-    z[0, 0], z[1, 1] = 1.0, -1.0
-    return [float(gradient.expectation(gamma[c], lam[c], z, 0).item()) for c in range(chains)]
-
-
-def mixed_precision(args, torch, api, models):
-    """Spin-boson chains at chi_max = 128: complex FP32 sketch / power GEMMs
-    (precision = 1) against the FP64 path on the same inputs and seeds."""
-    import numpy as np
-    N, d, chi_max, steps = 100, 10, 128, args.mixed_steps
-    dims, hb = models.spin_boson(N, d, 1.0, 0.5, 1.0, 0.5)
-    out = {}
-    for prec in (0, 1):
-        mps = api.DeviceMPS.product_state(args.chains, dims, [0] * N, chi_max)
-        drv = api.TEBD(mps, hb, 0.05, chi_max, p=10, q=2, trunc_eps=1e-10, seed=1504,
-                       precision=prec, adaptive=2)
-        for _ in range(min(args.warmup, 2)):
-            drv.step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            drv.step()
+        out = api.rrsvd_truncate(mats, 64, 10, 2, 1e-10, 1504, r + 1)
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        out[prec] = dict(sec=t1 - t0, chi=mps.chi.cpu().numpy(), lam=mps.lam.cpu().numpy(),
-                         z=_spin_z(torch, mps.gamma, mps.lam, args.chains))
-    same = bool(np.array_equal(out[0]["chi"], out[1]["chi"]))
-    lam_err = float(np.max(np.abs(out[0]["lam"] - out[1]["lam"]))) if same else None
-    z_err = float(np.max(np.abs(np.array(out[0]["z"]) - np.array(out[1]["z"]))))
-    per = updates_per_step(N) * args.chains * steps
-    return {"config": {"workload": f"{args.chains} spin-boson chains N=100 d=10, chi_max=128, "
-                                   f"dt=0.05, {steps} steps after warm-up, adaptive rank"},
-            "mixed_value": round(per / out[1]["sec"], 2), "fp64_value": round(per / out[0]["sec"], 2),
-            "unit": "bond updates/s",
-            "bond_dims_identical": same,
-            "max_abs_lambda_diff": lam_err,
-            "max_abs_sigma_z_diff": z_err,
-            "reference": "the FP64 path on the same inputs (its own parity with the CPU oracle "
-                         "is checked in the GPU tests)"}
+        times.append(time.perf_counter() - t0)
+    chi = out[3].cpu().numpy()
+    lib.tebd_profile_enable(True)
+    api.rrsvd_truncate(mats, 64, 10, 2, 1e-10, 1504, reps + 1)
+    torch.cuda.synchronize()
+    prof = lib.tebd_profile_read()
+    lib.tebd_profile_enable(False)
+    w = Work(lib)
+    l = 74
+    for n, c in zip(sizes, chi):
+        w.add("k_frob", 0.0, 16.0 * n * n)
+        w.rrsvd_pass(n, n, l, 2, False, int(c))
+    for k in ("k_form_u<1>", "k_form_vh<1>"):   # the standalone call writes plain U, V^H
+        if k in w.k:
+            w.k[k.replace("<1>", "<0>")] = w.k.pop(k)
+    sk_ms = sum(v[0] for k, v in prof.items() if k.startswith("k_sketch<"))
+    sk_fl = sum(v[0] for k, v in w.k.items() if k.startswith("k_sketch<"))
+    ach = sk_fl / (sk_ms * 1e-3) / 1e12 if sk_ms > 0 else None
+    res = {"metric": "RRSVD truncations/s", "value": round(len(sizes) * reps / sum(times), 2),
+           "unit": "truncations/s", "ms_per_batch": round(1e3 * sum(times) / reps, 3),
+           "config": {"workload": "256 complex128 square matrices, n in {256,512,1024,2048} "
+                                  "(seeded), A = U diag(exp(-i/25)) V^H with Haar U, V, k=64, "
+                                  "p=10, q=2, one call"},
+           "roofline": kernel_roofline(prof, w, "batched_rrsvd_256"),
+           "sketch_gemms": {"bound": "mfma", "achieved": round(ach, 3) if ach else None,
+                            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                            "frac": round(ach / PEAK_FP64_TFLOPS, 4) if ach else None,
+                            "event_ms": round(sk_ms, 3)},
+           "kernel_ms": kernel_table(prof)}
+    if not args.no_cpu_baseline:
+        from oracle import philox, rrsvd as orr
+        per = {}
+        t_all = 0.0
+        for n in sorted(set(sizes)):
+            ts = []
+            idx = [i for i, x in enumerate(sizes) if x == n][:8 if n < 2048 else 4]
+            for i in idx:
+                a = mats[i].cpu().numpy()
+                om_ = philox.gaussian_omega(n, l, 1504, i, 0)
+                t0 = time.perf_counter()
+                orr.truncate_rrsvd(a, om_, 2, 64, 1e-10)
+                ts.append(time.perf_counter() - t0)
+            per[n] = float(np.mean(ts))
+            t_all += per[n] * sizes.count(n)
+        res["cpu_baseline"] = {"value": round(len(sizes) / t_all, 3), "unit": "truncations/s",
+                               "cores": int(_threads()), "kind": "oracle",
+                               "sample": "extrapolated: the oracle's step-by-step RRSVD (same "
+                                         "algorithm, FP64, LAPACK QR and SVD) timed on the first 8 "
+                                         "matrices of each size in the batch (4 at n=2048), mean "
+                                         "seconds per size "
+                                         + json.dumps({str(k): round(v, 4) for k, v in per.items()})
+                                         + " times the count of each size in the batch"}
+    return res
 
 
-def adjoint_gradient(torch, api, models, wl, reps=3):
+def _golden_mixed():
+    path = os.path.join(ROOT, "tests", "golden", "spin_boson_n100_chi128.txt")
+    z, lam = {}, {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "obs":
+            z[int(f[1])] = float(f[2])
+        elif f[0] == "lam":
+            lam[int(f[1])] = [float(x) for x in f[2:]]
+    return z, lam
+
+
+def mixed_line(args, torch, api, models, lib):
+    """chi_max = 128 with complex FP32 sketch and power-iteration products."""
+    import numpy as np
+    from paper_1504_00992_amd import gradient
+    N, d, chi_max, steps = SB["N"], SB["d"], 128, SB["steps"]
+    dims, hb = models.spin_boson(N, d, 1.0, 0.5, 1.0, 0.5)
+    zop = torch.zeros((d, d), dtype=torch.complex128, device="cuda")
+    zop[0, 0], zop[1, 1] = 1.0, -1.0
+    res = {}
+    for prec in (1, 0):
+        ev = Evolution(torch, api, dims, hb, [0] * N, args.chains, chi_max, SB["p"], SB["q"],
+                       SB["dt"], SB["eps"], SB["seed"], precision=prec)
+        times = ev.timed(steps, 1, 1)
+        upd = steps * updates_per_step(N) * args.chains
+        r = {"value": round(upd / times[0], 2), "lam": ev.mps.lam[0].cpu().numpy(),
+             "chi": ev.mps.chi[0].cpu().numpy()}
+        # <sigma_z> of chain 0 at every 50th step, from a replay
+        ev.reset()
+        zs = {}
+        for s in range(1, steps + 1):
+            ev.run(1)
+            if s % 50 == 0:
+                zs[s] = float(gradient.expectation(ev.mps.gamma[0], ev.mps.lam[0], zop, 0).item())
+        r["z"] = zs
+        if prec == 1:
+            prof, hist = ev.profiled(steps, lib)
+            w = history_work(lib, hist, dims, chi_max, SB["p"], SB["q"], True, mixed=True)
+            r["roofline"] = kernel_roofline(prof, w, "spin_boson_16x100_chi128_mixed")
+            f32 = {k: v for k, v in prof.items() if k.startswith("k_sketch_f32")}
+            ms = sum(v[0] for v in f32.values())
+            fl = sum(w.k.get(k, (0, 0))[0] for k in f32)
+            r["f32_sketches"] = {"bound": "mfma", "achieved": round(fl / (ms * 1e-3) / 1e12, 4),
+                                 "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": round(fl / (ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 5),
+                                 "event_ms": round(ms, 3)} if ms > 0 else None
+        res[prec] = r
+    out = {"config": {"workload": f"{args.chains} spin-boson chains N=100 d=10, chi_max=128, "
+                                  "dt=0.05, 200 steps from the product state, adaptive rank, "
+                                  "sketch and power-iteration products in complex FP32 (FP32 "
+                                  "MFMA, FP32 accumulation), QRs, B = Q^H A, small SVD in FP64"},
+           "value": res[1]["value"], "fp64_value": res[0]["value"], "unit": "bond updates/s",
+           "roofline": res[1]["roofline"], "f32_sketches": res[1]["f32_sketches"]}
+    try:
+        gz, glam = _golden_mixed()
+        chi = res[1]["chi"]
+        errs = [float(np.max(np.abs(res[1]["lam"][b, :len(v)] - np.array(v))))
+                for b, v in glam.items() if chi[b + 1] == len(v)]
+        out["vs_fp64_oracle"] = {
+            "bond_dims_identical": bool(all(chi[b + 1] == len(v) for b, v in glam.items())),
+            "max_abs_lambda_err": max(errs) if errs else None,
+            "max_abs_sigma_z_err": max(abs(res[1]["z"][s] - gz[s]) for s in gz),
+            "reference": "tests/golden/spin_boson_n100_chi128.txt (chain 0, FP64 oracle with "
+                         "the same Omega, written by tests/golden/make_golden.py)"}
+        out["vs_gpu_fp64"] = {
+            "max_abs_lambda_diff": float(np.max(np.abs(res[1]["lam"] - res[0]["lam"]))),
+            "max_abs_sigma_z_diff": max(abs(res[1]["z"][s] - res[0]["z"][s]) for s in gz)}
+    except OSError:
+        out["vs_fp64_oracle"] = None
+    return out
+
+
+def adjoint_line(args, torch, api, models, wl, lib, reps=3):
     """Time per gradient of <Z_0(T)> w.r.t. the 39 couplings (XX + fields, N=40)."""
     import numpy as np
     from paper_1504_00992_amd import gradient
@@ -438,9 +655,8 @@ def adjoint_gradient(torch, api, models, wl, reps=3):
     g_half = torch.from_numpy(models.gate_stack(dims, hb, 0.5 * dt)).cuda()
     g_full = torch.from_numpy(models.gate_stack(dims, hb, dt)).cuda()
     z = torch.tensor([[1.0, 0.0], [0.0, -1.0]], dtype=torch.complex128, device="cuda")
-    timings = []
-    grad = None
-    for rep in range(reps + 1):
+
+    def gradient_once():
         mps = api.DeviceMPS.product_state(1, dims, wl.neel_levels(n), chi_max)
         drv = gradient.CheckpointedTEBD(mps, g_half, g_full, chi_max, 10, 2, 1e-10, 1504,
                                         adaptive=2, checkpoint=10)
@@ -449,8 +665,7 @@ def adjoint_gradient(torch, api, models, wl, reps=3):
         drv.forward(steps)
         gam = mps.gamma[0].clone().requires_grad_(True)
         lam = mps.lam[0].clone().requires_grad_(True)
-        val = gradient.expectation(gam, lam, z, 0)
-        val.backward()
+        gradient.expectation(gam, lam, z, 0).backward()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         gb = torch.zeros_like(mps.gamma)
@@ -463,34 +678,74 @@ def adjoint_gradient(torch, api, models, wl, reps=3):
         gh, gf = gh.cpu().numpy(), gf.cpu().numpy()
         grad = np.array([gradient.coupling_gradient(gh[b], hb[b], 0.5 * dt, hop)
                          + gradient.coupling_gradient(gf[b], hb[b], dt, hop) for b in range(n - 1)])
-        t3 = time.perf_counter()
-        if rep > 0:  # the first is a warm-up
-            timings.append((t1 - t0, t2 - t1, t3 - t2))
+        return grad, (t1 - t0, t2 - t1, time.perf_counter() - t2)
+
+    gradient_once()
+    timings = []
+    grad = None
+    for _ in range(reps):
+        grad, t = gradient_once()
+        timings.append(t)
+    lib.tebd_profile_enable(True)
+    gradient_once()
+    torch.cuda.synchronize()
+    prof = lib.tebd_profile_read()
+    lib.tebd_profile_enable(False)
+    # forward kernels: every sweep runs twice (forward, then its segment's
+    # recorded replay); the bond dimensions of the plain run are the same
+    ev = Evolution(torch, api, dims, hb, wl.neel_levels(n), 1, chi_max, 10, 2, dt, 1e-10, 1504)
+    hist = []
+    ev.reset()
+    ev.run(steps, record=hist)
+    hist = [(p, b.cpu().numpy(), a.cpu().numpy(), s.cpu().numpy()) for p, b, a, s in hist]
+    w = history_work(lib, hist, dims, chi_max, 10, 2, True, times=2)
     ref = np.loadtxt(os.path.join(ROOT, "tests", "golden", "xx_n40_gradient.txt"))
     scale = float(np.max(np.abs(ref[:, 3])))
     fw, bw, host = (float(np.median([t[i] for t in timings])) for i in range(3))
-    return {"config": {"workload": "XX chain + random fields, N=40, J_b~U[0.8,1.2], h_i~U[-1,1], "
-                                   "Neel start, 50 steps dt=0.02, chi_max=64, w<=1e-10, "
-                                   "checkpoint every 10 steps; gradient of <Z_0(T=1)> w.r.t. "
-                                   "all 39 J_b"},
-            "ms_per_gradient": round(1e3 * (fw + bw + host), 2),
-            "forward_ms": round(1e3 * fw, 2), "reverse_ms": round(1e3 * bw, 2),
-            "host_frechet_ms": round(1e3 * host, 2),
-            "rel_err_vs_exact_svd_reverse": float(np.max(np.abs(grad - ref[:, 2])) / scale),
-            "rel_err_vs_finite_differences": float(np.max(np.abs(grad - ref[:, 3])) / scale),
-            "rel_err_vs_free_fermions": float(np.max(np.abs(grad - ref[:, 4])) / scale),
-            "note": "errors relative to max|dL/dJ_b|; references in tests/golden/xx_n40_gradient.txt"}
+    out = {"config": {"workload": "XX chain + random fields, N=40, J_b~U[0.8,1.2], h_i~U[-1,1], "
+                                  "Neel start, 50 steps dt=0.02, chi_max=64, w<=1e-10, "
+                                  "checkpoint every 10 steps; gradient of <Z_0(T=1)> w.r.t. "
+                                  "all 39 J_b"},
+           "metric": "gradients/s", "value": round(1.0 / (fw + bw + host), 3),
+           "ms_per_gradient": round(1e3 * (fw + bw + host), 2),
+           "forward_ms": round(1e3 * fw, 2), "reverse_ms": round(1e3 * bw, 2),
+           "host_frechet_ms": round(1e3 * host, 2),
+           "rel_err_vs_exact_svd_reverse": float(np.max(np.abs(grad - ref[:, 2])) / scale),
+           "rel_err_vs_finite_differences": float(np.max(np.abs(grad - ref[:, 3])) / scale),
+           "rel_err_vs_free_fermions": float(np.max(np.abs(grad - ref[:, 4])) / scale),
+           "note": "errors relative to max|dL/dJ_b|; references in tests/golden/xx_n40_gradient.txt",
+           "roofline": kernel_roofline(prof, w, "adjoint_xx_n40"),
+           "kernel_ms": kernel_table(prof)}
+    if not args.no_cpu_baseline:
+        from oracle import adjoint as oadj, models as om, mps as omps
+        dims_o, hb_o = om.xx_field(J, h)
+        hop_o = 0.5 * (np.kron(om.X, om.X) + np.kron(om.Y, om.Y))
+        cache = {}
+
+        def gfn(b, tau):
+            if (b, tau) not in cache:
+                cache[(b, tau)] = om.gate(hb_o[b], tau)
+            return cache[(b, tau)]
+        m0 = omps.basis_product_state(dims_o, wl.neel_levels(n))
+        t0 = time.perf_counter()
+        oadj.tebd_gradient(m0, gfn, lambda b: hb_o[b], lambda b, k: hop_o if b == k else None,
+                           n - 1, dt, steps, chi_max, 1e-10, om.Z, 0)
+        sec = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(1.0 / sec, 4), "unit": "gradients/s",
+                               "cores": int(_threads()), "kind": "oracle",
+                               "sample": f"one whole gradient ({sec:.1f} s): the oracle's FP64 "
+                                         f"full-SVD TEBD and its reverse mode (every triplet "
+                                         f"coupled), no checkpointing"}
+    return out
 
 
-def _progress(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
+# ---------------------------------------------------------------------------
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is "
-              f"described in DESIGN.md and not launched here.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build measures one "
+              f"GPU's share of the workload; the multi-GPU layout is described, not launched.",
+              file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -498,93 +753,101 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     if args.copy_probe:
-        src = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda")
+        src = torch.ones((256 << 20) // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES, "copies": 3}))
+        print(json.dumps({"copy_probe_bytes": 256 << 20, "copies": 3}))
         return
     from paper_1504_00992_amd import api, models, _lib
     import workloads as wl
     _lib.load()
 
     adaptive = args.rank == "adaptive"
-    # value: the run without per-phase events (each event record adds a gap
-    # between launches); phase times and the roofline: the same run again
-    # with HIP events around every phase
-    res = run_gpu_tebd(args, torch, api, models, adaptive, prof_on=False)
-    _progress(f"timed TEBD run: {res['seconds']:.2f} s")
-    profd = run_gpu_tebd(args, torch, api, models, adaptive, prof_on=True)
-    _progress(f"profiled TEBD run: {profd['seconds']:.2f} s")
-    N = 100
-    per_step = updates_per_step(N) * args.chains
-    total_updates = per_step * args.steps
-    sec = res["seconds"]
-    value = total_updates / sec
-    flops = kind_flops(profd["chi_hist"], profd["parities"], profd["dims"], 100, 10, 2, adaptive)
-    prof = profd["prof"]
+    N, steps = SB["N"], SB["steps"]
+    dims, hb = models.spin_boson(N, SB["d"], 1.0, 0.5, 1.0, 0.5)
+    ev = Evolution(torch, api, dims, hb, [0] * N, args.chains, SB["chi_max"], SB["p"], SB["q"],
+                   SB["dt"], SB["eps"], SB["seed"], adaptive=2 if adaptive else 0)
+    times = ev.timed(steps, args.steps, args.warmup)
+    sec = sum(times)
+    per_rep = steps * updates_per_step(N) * args.chains
+    _progress(f"timed evolutions: {', '.join(f'{t:.3f}' for t in times)} s")
     line = {
-        "metric": "TEBD bond updates/s, RRSVD vs full SVD on 1 GPU at <=1e-10 trunc err",
-        "value": round(value, 2),
+        "metric": METRIC,
+        "value": round(per_rep * args.steps / sec, 2),
         "unit": "bond updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * sec / args.steps, 4),
+        "ms_per_step": round(1e3 * sec / args.steps, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c128 (f64)",
         "data": "synthetic",
-        "config": {"workload": "batched TEBD sweep: 16 chain-mapped spin-boson chains, N=100 "
-                               "(spin + 99 oscillators, d=10), t_n=0.5, w_n=1, dt=0.05, chi_max=100, "
-                               "RRSVD p=10 q=2, w<=1e-10 per bond",
+        "config": {"workload": f"batched TEBD: {args.chains} chain-mapped spin-boson chains, "
+                               "N=100 (spin + 99 oscillators, d=10), t_n=0.5, w_n=1, dt=0.05, "
+                               "chi_max=100, RRSVD p=10 q=2, w<=1e-10 per bond; one step = the "
+                               "whole evolution, Trotter steps 1..200 from the product state "
+                               f"({per_rep} bond updates)",
                    "rank": ("two-stage adaptive: k1 = chi + max(4, chi/2), k = chi_max when the "
                             "Frobenius residual needs it (second pass skipped on the host when no "
                             "bond needs it)" if adaptive else "fixed k = chi_max"),
-                   "chains": args.chains, "bond_updates_per_step": per_step,
-                   "chi_final_max": int(res["chi_final"].max()),
-                   "status_bits_seen": sorted(set(int(x) for x in np.unique(res["status"])))},
-        "phase_ms": {k: round(v[0], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
-        "phase_launches": {k: int(v[1]) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])},
-        "profiled_ms_per_step": round(1e3 * profd["seconds"] / args.steps, 4),
-        "roofline": roofline(prof, flops),
+                   "chains": args.chains, "trotter_steps": steps,
+                   "chi_final_max": int(ev.mps.chi.max().item()),
+                   "status_bits_seen": sorted(set(int(x) for x in
+                                                  np.unique(ev.drv.ws.status.cpu().numpy())))},
+        "rep_ms": [round(1e3 * t, 3) for t in times],
     }
-    line["roofline"]["measured"] = ("HIP events around every phase in a second pass of the same "
-                                    "timed steps (same inputs, same kernels); value is timed "
-                                    "without events")
+    if not args.no_profile:
+        prof, hist = ev.profiled(steps, _lib)
+        w = history_work(_lib, hist, dims, SB["chi_max"], SB["p"], SB["q"], adaptive)
+        line["roofline"] = kernel_roofline(prof, w, "spin_boson_16x100")
+        line["phase_ms"] = phase_table(prof)
+        line["kernel_ms"] = kernel_table(prof)
+        line["profiled_phase_ms_total"] = round(sum(v[0] for k, v in prof.items()
+                                                    if not k.startswith("k_")), 3)
+        _progress("profiled evolution done")
     if not args.no_other_rank:
-        other = run_gpu_tebd(args, torch, api, models, not adaptive, prof_on=False)
-        oval = total_updates / other["seconds"]
-        _progress(f"other rank mode: {other['seconds']:.2f} s")
+        other = Evolution(torch, api, dims, hb, [0] * N, args.chains, SB["chi_max"], SB["p"],
+                          SB["q"], SB["dt"], SB["eps"], SB["seed"], adaptive=0 if adaptive else 2)
+        ot = other.timed(steps, 1, 0)
         line["other_rank_mode"] = {
             "rank": "fixed k = chi_max" if adaptive else "two-stage adaptive",
-            "value": round(oval, 2), "unit": "bond updates/s",
-            "ms_per_step": round(1e3 * other["seconds"] / args.steps, 4),
-            "chi_final_max": int(other["chi_final"].max())}
+            "value": round(per_rep / ot[0], 2), "unit": "bond updates/s",
+            "ms_per_step": round(1e3 * ot[0], 3),
+            "chi_final_max": int(other.mps.chi.max().item())}
+        del other
+        torch.cuda.empty_cache()
+        _progress(f"other rank mode: {ot[0]:.2f} s")
     if not args.no_full_svd:
-        nsteps = args.steps if args.full_svd_steps < 0 else args.full_svd_steps
-        done, fsec = full_svd_tebd(args, torch, models, res["dims"], res["hb"], args.warmup, nsteps)
-        fval = done * per_step / fsec if fsec > 0 else None
-        _progress(f"full-SVD comparator: {done} steps in {fsec:.1f} s")
-        line["full_svd"] = {"value": round(fval, 2), "unit": "bond updates/s",
-                            "steps": done, "seconds": round(fsec, 2),
-                            "note": "torch.linalg.svd (vendor full SVD) in a torch-only TEBD step on "
-                                    "the same GPU, same warm-up, timed steps after it"}
-        line["speedup_vs_full_svd"] = round(value / fval, 3) if fval else None
+        fsec, fchi = full_svd_tebd(torch, models, dims, hb, args.chains, SB["chi_max"], SB["dt"],
+                                   steps)
+        line["full_svd"] = {"value": round(per_rep / fsec, 2), "unit": "bond updates/s",
+                            "seconds": round(fsec, 2), "chi_final_max": fchi,
+                            "note": "vendor full SVD (torch.linalg.svd) in a torch-only TEBD on "
+                                    "the same GPU: every same-shape bond of a sweep in one batched "
+                                    "call, truncation and reabsorption on the device, the same "
+                                    "200-step evolution of all chains"}
+        line["speedup_vs_full_svd"] = round(line["value"] / line["full_svd"]["value"], 3)
+        _progress(f"full-SVD comparator: {fsec:.1f} s")
+    if not args.no_tfim:
+        line["tfim"] = tfim_line(args, torch, api, models, _lib)
+        _progress("tfim done")
     if not args.no_batched:
-        line["batched_rrsvd"] = batched_rrsvd(torch, api, wl)
+        line["batched_rrsvd"] = batched_rrsvd_line(args, torch, api, wl, _lib)
         _progress("batched RRSVD done")
     if not args.no_mixed:
-        line["mixed_precision"] = mixed_precision(args, torch, api, models)
+        line["mixed_precision"] = mixed_line(args, torch, api, models, _lib)
         _progress("mixed precision done")
     if not args.no_adjoint:
-        line["adjoint"] = adjoint_gradient(torch, api, models, wl)
+        line["adjoint"] = adjoint_line(args, torch, api, models, wl, _lib)
         _progress("adjoint done")
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_oracle_baseline(args, res["dims"], args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline_spin_boson()
+        _progress("cpu baseline done")
     print(json.dumps(line), flush=True)
 
 

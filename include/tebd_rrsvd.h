@@ -96,8 +96,10 @@ typedef struct {
                            dimension before the update, and is kept when some
                            c <= k1 has w(c) <= trunc_eps; otherwise stage 2
                            repeats with k = chi_max, reusing the first Omega
-                           columns (the paper's adaptive TEBD, Sec. IV and
-                           Alg. 2, with the exact Frobenius residual).
+                           columns.  This two-stage rule is this library's
+                           own design: it stands in for the paper's Accuracy
+                           Check (Sec. IV, Alg. 2, which grows the basis by
+                           probe columns) with the exact Frobenius residual.
                            2: as 1 (same results), but the host reads back
                            how many bonds need stage 2 and skips that pass
                            when none does: the call then waits for the
@@ -273,16 +275,31 @@ tebd_status tebd_sweep_adjoint(const tebd_mps* mps_in, const tebd_z* gates,
 
 /* Per-kernel timing with HIP events, for the per-phase split of the update
  * (the paper's profile of the two-site update, Sec. V.B).  Off by default.
- * While on, each kernel launch of the library is bracketed by two events
- * recorded on the launch stream.  tebd_profile_enable(0 or 1) also discards
- * what was recorded so far.
+ * While on, each phase of the bond update (Theta and gate, Omega, each
+ * sketch product, each QR, the small SVD, ...) and, inside it, each kernel
+ * launch of the library is bracketed by two events recorded on the launch
+ * stream.  tebd_profile_enable(0 or 1) also discards what was recorded so
+ * far; call it and the profiled entry points from one host thread.
  * tebd_profile_read waits for the recorded events and writes, for up to
- * `capacity` kernel kinds, the kind's name (static string), the summed
- * elapsed milliseconds and the number of launches; *count receives the
- * number of kinds written.  The records are then discarded. */
+ * `capacity` kinds, the kind's name (static string), the summed elapsed
+ * milliseconds and the number of launches; *count receives the number of
+ * kinds written.  Phase kinds come first ("qr", "sketch_AH_Q", ...), then
+ * kernel kinds, named by the kernel instantiation as profiler tools print
+ * it without the namespace ("k_qr_reg<512, 8, false>", "k_gate", ...).  The
+ * records are then discarded. */
 tebd_status tebd_profile_enable(int32_t on);
 tebd_status tebd_profile_read(int32_t capacity, const char** names, double* ms, int64_t* launches,
                               int32_t* count);
+
+/* Size class, hence kernel, that a factorisation of the given shape runs
+ * in (a planning query; no device work).  factorization 0: the Householder
+ * QR of a rows x l sketch (the class follows the sketch width l the problem
+ * started with); 1: the small SVD of an l x l factor (rows is ignored).
+ * QR classes: 0 k_qr_reg<512, 8, *>, 1 k_qr_reg<1024, 12, *>, 2 k_qr_lds,
+ * 3 k_qr_glb; small-SVD classes: 0 k_svd_pairs<256, 0>, 1 k_svd_pairs<512, 1>,
+ * 2 k_small_svd<1024, 2, true>, 3 k_small_svd<1024, 4, false>.  Returns -1
+ * for sizes outside [1, 4096] x [1, 256] or an unknown factorization. */
+int32_t tebd_size_class(int32_t factorization, int32_t rows, int32_t l);
 
 #ifdef __cplusplus
 }

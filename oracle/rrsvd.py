@@ -163,9 +163,11 @@ def first_stage_rank(chi_mid, chi_max):
 def adaptive_factors(a, omega_of, q, chi_max, eps, k1, p):
     """Two-stage adaptive-rank RRSVD (TEBD with a tolerance), all factors.
 
-    The paper grows the sketch until the range error meets the tolerance
-    (Sec. IV, Alg. 2) and notes that ||(I - QQ^H)A||_F is available exactly
-    from Q.  Here: stage 1 runs the RRSVD with l1 = min(k1 + p, m, n) and is
+    This two-stage rule is this project's own design, not the paper's
+    Accuracy Check (Sec. IV, Alg. 2 grows Q by r probe columns until its
+    estimated range error meets the tolerance; see ``accuracy_check``).  It
+    uses the exact residual ||(I - QQ^H)A||_F that the Frobenius identity of
+    Sec. IV gives from the factors.  Stage 1 runs the RRSVD with l1 = min(k1 + p, m, n) and is
     accepted when some c <= k1 has relative discarded weight w(c) <= eps
     (w from the Frobenius identity, so the bound is exact for the factors
     returned).  Otherwise stage 2 repeats with the fixed-rank width

@@ -28,7 +28,7 @@ DEV_RANK_RETRY = 64
 
 EXPORTED = ("tebd_last_error", "tebd_version", "tebd_workspace_size", "rrsvd_truncate",
             "tebd_bond_update", "tebd_sweep", "tebd_adjoint_workspace_size", "tebd_tape_size", "tebd_sweep_record",
-            "tebd_sweep_adjoint", "tebd_profile_enable", "tebd_profile_read")
+            "tebd_sweep_adjoint", "tebd_profile_enable", "tebd_profile_read", "tebd_size_class")
 
 
 class TebdParams(ctypes.Structure):
@@ -100,6 +100,8 @@ def load():
     lib.tebd_profile_read.argtypes = [i32, ctypes.POINTER(ctypes.c_char_p),
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(ctypes.c_int32)]
+    lib.tebd_size_class.restype = ctypes.c_int32
+    lib.tebd_size_class.argtypes = [i32, i32, i32]
     _lib = lib
     return lib
 
@@ -206,7 +208,12 @@ def tebd_profile_enable(on):
     check(load().tebd_profile_enable(1 if on else 0))
 
 
-def tebd_profile_read(capacity=32):
+def tebd_size_class(factorization, rows, l):
+    """Size class (kernel) of a QR (factorization 0) or small SVD (1)."""
+    return int(load().tebd_size_class(int(factorization), int(rows), int(l)))
+
+
+def tebd_profile_read(capacity=96):
     """{kind: (milliseconds, launches)} recorded since profiling was enabled."""
     lib = load()
     names = (ctypes.c_char_p * capacity)()

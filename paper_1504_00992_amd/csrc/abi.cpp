@@ -222,6 +222,14 @@ struct Profiler {
     hipEvent_t a, b;
   };
   std::vector<Rec> recs;
+  // kernel-level brackets (prof_kernel_begin / prof_kernel_end)
+  struct KRec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<KRec> krecs;
+  const char* open_name = nullptr;
+  hipEvent_t open_a = nullptr;
   hipEvent_t get() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -238,6 +246,14 @@ struct Profiler {
       pool.push_back(r.b);
     }
     recs.clear();
+    for (auto& r : krecs) {
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    krecs.clear();
+    if (open_a) pool.push_back(open_a);
+    open_a = nullptr;
+    open_name = nullptr;
   }
 };
 Profiler g_prof;
@@ -258,6 +274,43 @@ hipError_t timed(int kind, hipStream_t s, F&& launch) {
   g_prof.recs.push_back({kind, a, b});
   return hipSuccess;
 }
+
+}  // namespace
+
+namespace tebd {
+
+void prof_kernel_begin(const char* name, hipStream_t s) {
+  if (!g_prof.on) return;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  hipEvent_t a = g_prof.get();
+  if (!a) return;
+  if (hipEventRecord(a, s) != hipSuccess) {
+    g_prof.pool.push_back(a);
+    return;
+  }
+  if (g_prof.open_a) g_prof.pool.push_back(g_prof.open_a);
+  g_prof.open_a = a;
+  g_prof.open_name = name;
+}
+
+void prof_kernel_end(hipStream_t s) {
+  if (!g_prof.on) return;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  if (!g_prof.open_a) return;
+  hipEvent_t b = g_prof.get();
+  if (!b) return;
+  if (hipEventRecord(b, s) != hipSuccess) {
+    g_prof.pool.push_back(b);
+    return;
+  }
+  g_prof.krecs.push_back({g_prof.open_name, g_prof.open_a, b});
+  g_prof.open_a = nullptr;
+  g_prof.open_name = nullptr;
+}
+
+}  // namespace tebd
+
+namespace {
 
 // Workgroups of the persistent contraction launches: enough to fill the 256
 // CUs a few times over, never more than the largest possible tile count.
@@ -454,6 +507,26 @@ tebd_status tebd_profile_read(int32_t capacity, const char** names, double* ms, 
     tot[r.kind] += t;
     cnt[r.kind] += 1;
   }
+  // kernel-level records, summed per kernel name in first-seen order
+  std::vector<const char*> kname;
+  std::vector<double> ktot;
+  std::vector<int64_t> kcnt;
+  for (auto& r : g_prof.krecs) {
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e != hipSuccess) return fail(TEBD_ERR_DEVICE, "event wait failed: %s", hipGetErrorString(e));
+    float t = 0.0f;
+    e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess) return fail(TEBD_ERR_DEVICE, "event timing failed: %s", hipGetErrorString(e));
+    size_t i = 0;
+    while (i < kname.size() && std::strcmp(kname[i], r.name) != 0) ++i;
+    if (i == kname.size()) {
+      kname.push_back(r.name);
+      ktot.push_back(0.0);
+      kcnt.push_back(0);
+    }
+    ktot[i] += t;
+    kcnt[i] += 1;
+  }
   g_prof.recycle();
   int32_t k = 0;
   for (int i = 0; i < PK_COUNT && k < capacity; ++i) {
@@ -461,6 +534,12 @@ tebd_status tebd_profile_read(int32_t capacity, const char** names, double* ms, 
     names[k] = kProfNames[i];
     ms[k] = tot[i];
     launches[k] = cnt[i];
+    ++k;
+  }
+  for (size_t i = 0; i < kname.size() && k < capacity; ++i) {
+    names[k] = kname[i];
+    ms[k] = ktot[i];
+    launches[k] = kcnt[i];
     ++k;
   }
   *count = k;

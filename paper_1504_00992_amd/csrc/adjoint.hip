@@ -586,27 +586,27 @@ hipError_t launch_adjoint(AdjProb* probs, const AdjCommon& c, const tebd_mps& mp
                           int32_t* status, double lambda_floor, char* slab_base, size_t slab_sz,
                           int64_t nchunk_cap, hipStream_t s) {
   hipError_t e;
-#define TRY(...)                    \
-  do {                              \
-    hipLaunchKernelGGL(__VA_ARGS__); \
-    e = hipGetLastError();          \
-    if (e != hipSuccess) return e;  \
+#define TRY(name, ...)               \
+  do {                               \
+    TEBD_LAUNCH(name, __VA_ARGS__);  \
+    e = hipGetLastError();           \
+    if (e != hipSuccess) return e;   \
   } while (0)
   const dim3 g(c.grid), pb(c.nprob);
-  TRY(k_adj_plan, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob, c.nb, c.parity,
+  TRY("k_adj_plan", k_adj_plan, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob, c.nb, c.parity,
       mps_in, gates, c.gate_chain_stride, tape, slot_bytes, mcap, lcap, gamma_bar, lambda_bar,
       gate_bar, status, lambda_floor, slab_base, slab_sz, nchunk_cap);
-  TRY(k_schedule<AdjProb>, dim3(1), dim3(kScheduleThreads), 0, s, probs, c.nprob, 0, c.offs);
-  TRY(k_adj_prep, pb, dim3(256), 0, s, probs);
-  TRY(k_adj_m12_theta, g, dim3(256), 0, s, probs, c.offs, c.nprob);
-  TRY(k_adj_core, pb, dim3(256), 0, s, probs);
-  TRY(k_adj_x, g, dim3(256), 0, s, probs, c.offs, c.nprob);
-  TRY(k_adj_abar, g, dim3(256), 0, s, probs, c.offs, c.nprob);
-  TRY(k_adj_gate, g, dim3(256), 0, s, probs, c.offs, c.nprob);
-  TRY(k_adj_r, g, dim3(256), 0, s, probs, c.offs, c.nprob);
-  TRY(k_adj_finish, pb, dim3(256), 0, s, probs);
-  TRY(k_adj_gsum, dim3(c.nb), dim3(256), 0, s, probs, c.n_chains, c.nb, c.gate_chain_stride);
-  TRY(k_adj_lambda, dim3(c.n_chains * (c.n_sites - 1)), dim3(64), 0, s, probs, mps_in,
+  TRY("k_schedule<tebd::AdjProb, false>", k_schedule<AdjProb>, dim3(1), dim3(kScheduleThreads), 0, s, probs, c.nprob, 0, c.offs);
+  TRY("k_adj_prep", k_adj_prep, pb, dim3(256), 0, s, probs);
+  TRY("k_adj_m12_theta", k_adj_m12_theta, g, dim3(256), 0, s, probs, c.offs, c.nprob);
+  TRY("k_adj_core", k_adj_core, pb, dim3(256), 0, s, probs);
+  TRY("k_adj_x", k_adj_x, g, dim3(256), 0, s, probs, c.offs, c.nprob);
+  TRY("k_adj_abar", k_adj_abar, g, dim3(256), 0, s, probs, c.offs, c.nprob);
+  TRY("k_adj_gate", k_adj_gate, g, dim3(256), 0, s, probs, c.offs, c.nprob);
+  TRY("k_adj_r", k_adj_r, g, dim3(256), 0, s, probs, c.offs, c.nprob);
+  TRY("k_adj_finish", k_adj_finish, pb, dim3(256), 0, s, probs);
+  TRY("k_adj_gsum", k_adj_gsum, dim3(c.nb), dim3(256), 0, s, probs, c.n_chains, c.nb, c.gate_chain_stride);
+  TRY("k_adj_lambda", k_adj_lambda, dim3(c.n_chains * (c.n_sites - 1)), dim3(64), 0, s, probs, mps_in,
       c.parity, c.nb, lambda_bar);
 #undef TRY
   return hipSuccess;

@@ -123,10 +123,10 @@ struct TileKinds<Prob> {
 
 hipError_t launch_schedule(Prob* probs, const Common& c, hipStream_t s) {
   if (c.bounds_dev)
-    hipLaunchKernelGGL((k_schedule<Prob, true>), dim3(1), dim3(kScheduleThreads), 0, s, probs,
+    TEBD_LAUNCH("k_schedule<tebd::Prob, true>", (k_schedule<Prob, true>), dim3(1), dim3(kScheduleThreads), 0, s, probs,
                        c.nprob, c.tebd, c.offs, c.bounds_dev);
   else
-    hipLaunchKernelGGL((k_schedule<Prob, false>), dim3(1), dim3(kScheduleThreads), 0, s, probs,
+    TEBD_LAUNCH("k_schedule<tebd::Prob, false>", (k_schedule<Prob, false>), dim3(1), dim3(kScheduleThreads), 0, s, probs,
                        c.nprob, c.tebd, c.offs, nullptr);
   return hipGetLastError();
 }
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_omega(Prob* probs, const int32_t* offs,
 }
 
 hipError_t launch_omega(Prob* probs, const Common& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_omega, dim3(grid_for(c, TK_SKN)), dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd,
+  TEBD_LAUNCH("k_omega", k_omega, dim3(grid_for(c, TK_SKN)), dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd,
                      c.seed, c.stream_id);
   return hipGetLastError();
 }
@@ -242,10 +242,10 @@ __global__ __launch_bounds__(256, 3) void k_gate(Prob* probs, const int32_t* off
 }
 
 hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_theta, dim3(grid_for(c, TK_THETA)), dim3(256), 0, s, probs, c.offs, c.nprob);
+  TEBD_LAUNCH("k_theta", k_theta, dim3(grid_for(c, TK_THETA)), dim3(256), 0, s, probs, c.offs, c.nprob);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_gate, dim3(grid_for(c, TK_GATE)), dim3(256), 0, s, probs, c.offs, c.nprob);
+  TEBD_LAUNCH("k_gate", k_gate, dim3(grid_for(c, TK_GATE)), dim3(256), 0, s, probs, c.offs, c.nprob);
   return hipGetLastError();
 }
 
@@ -313,22 +313,22 @@ __global__ __launch_bounds__(256) void k_sketch_f32(Prob* probs, const int32_t* 
 hipError_t launch_sketch_f32(Prob* probs, const Common& c, int which, hipStream_t s) {
   const dim3 g(grid_for(c, which == SK_YT_FROM_Y ? TK_SKN : TK_SKM));
   if (which == SK_Y_FROM_OMEGA)
-    hipLaunchKernelGGL(k_sketch_f32<SK_Y_FROM_OMEGA>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+    TEBD_LAUNCH("k_sketch_f32<0>", k_sketch_f32<SK_Y_FROM_OMEGA>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
   else if (which == SK_YT_FROM_Y)
-    hipLaunchKernelGGL(k_sketch_f32<SK_YT_FROM_Y>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+    TEBD_LAUNCH("k_sketch_f32<1>", k_sketch_f32<SK_YT_FROM_Y>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
   else
-    hipLaunchKernelGGL(k_sketch_f32<SK_Y_FROM_YT>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+    TEBD_LAUNCH("k_sketch_f32<2>", k_sketch_f32<SK_Y_FROM_YT>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
   return hipGetLastError();
 }
 
 hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s) {
   const dim3 g(grid_for(c, which == SK_YT_FROM_Y ? TK_SKN : TK_SKM));
   if (which == SK_Y_FROM_OMEGA)
-    hipLaunchKernelGGL(k_sketch<SK_Y_FROM_OMEGA>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+    TEBD_LAUNCH("k_sketch<0>", k_sketch<SK_Y_FROM_OMEGA>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
   else if (which == SK_YT_FROM_Y)
-    hipLaunchKernelGGL(k_sketch<SK_YT_FROM_Y>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+    TEBD_LAUNCH("k_sketch<1>", k_sketch<SK_YT_FROM_Y>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
   else
-    hipLaunchKernelGGL(k_sketch<SK_Y_FROM_YT>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+    TEBD_LAUNCH("k_sketch<2>", k_sketch<SK_Y_FROM_YT>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
   return hipGetLastError();
 }
 
@@ -446,11 +446,11 @@ __global__ __launch_bounds__(256) void k_form_vh(Prob* probs, const int32_t* off
 hipError_t launch_form_uv(Prob* probs, const Common& c, hipStream_t s) {
   const dim3 gu(grid_for(c, TK_FORMU)), gv(grid_for(c, TK_FORMV));
   if (c.tebd) {
-    hipLaunchKernelGGL(k_form_u<1>, gu, dim3(256), 0, s, probs, c.offs, c.nprob);
-    hipLaunchKernelGGL(k_form_vh<1>, gv, dim3(256), 0, s, probs, c.offs, c.nprob);
+    TEBD_LAUNCH("k_form_u<1>", k_form_u<1>, gu, dim3(256), 0, s, probs, c.offs, c.nprob);
+    TEBD_LAUNCH("k_form_vh<1>", k_form_vh<1>, gv, dim3(256), 0, s, probs, c.offs, c.nprob);
   } else {
-    hipLaunchKernelGGL(k_form_u<0>, gu, dim3(256), 0, s, probs, c.offs, c.nprob);
-    hipLaunchKernelGGL(k_form_vh<0>, gv, dim3(256), 0, s, probs, c.offs, c.nprob);
+    TEBD_LAUNCH("k_form_u<0>", k_form_u<0>, gu, dim3(256), 0, s, probs, c.offs, c.nprob);
+    TEBD_LAUNCH("k_form_vh<0>", k_form_vh<0>, gv, dim3(256), 0, s, probs, c.offs, c.nprob);
   }
   return hipGetLastError();
 }
@@ -508,11 +508,11 @@ __global__ __launch_bounds__(64) void k_tape_meta(Prob* probs, int pass2, int n_
 }
 
 hipError_t launch_tape(Prob* probs, const Common& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_tape_uv, dim3(grid_for(c, TK_TAPEU, TK_TAPEV)), dim3(256), 0, s, probs,
+  TEBD_LAUNCH("k_tape_uv", k_tape_uv, dim3(grid_for(c, TK_TAPEU, TK_TAPEV)), dim3(256), 0, s, probs,
                      c.offs, c.nprob);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_tape_meta, dim3(c.nprob), dim3(64), 0, s, probs, c.pass2, c.nsites);
+  TEBD_LAUNCH("k_tape_meta", k_tape_meta, dim3(c.nprob), dim3(64), 0, s, probs, c.pass2, c.nsites);
   return hipGetLastError();
 }
 

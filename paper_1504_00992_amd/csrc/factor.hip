@@ -135,7 +135,7 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
   const int64_t mcap = int64_t(c.dmax) * c.chimax;
   const int64_t lcap = c.lmax;
   const int64_t npart_cap = gate_tiles(c.dmax * c.dmax, c.chimax * c.chimax);
-  hipLaunchKernelGGL(k_plan_sweep, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob, mps,
+  TEBD_LAUNCH("k_plan_sweep", k_plan_sweep, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob, mps,
                      gates, gate_chain_stride, parity, single_chain, single_bond, c.kcap, p_over,
                      slab_base, slab_sz, mcap, mcap, lcap, npart_cap, disc, status, lambda_floor,
                      mixed, adaptive, tape, tape_stride, retry_count);
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_frob(Prob* probs) {
 }
 
 hipError_t launch_frob(Prob* probs, const Common& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_frob, dim3(c.nprob), dim3(256), 0, s, probs);
+  TEBD_LAUNCH("k_frob", k_frob, dim3(c.nprob), dim3(256), 0, s, probs);
   return hipGetLastError();
 }
 
@@ -960,22 +960,22 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pi
   const Launch fns[4] = {
       [](hipStream_t t, Prob* p, int w, int r, int v, int np, int) {
         if (v)
-          hipLaunchKernelGGL((k_qr_reg<512, 8, true>), dim3(np), dim3(512), 0, t, p, w, r, 0);
+          TEBD_LAUNCH("k_qr_reg<512, 8, true>", (k_qr_reg<512, 8, true>), dim3(np), dim3(512), 0, t, p, w, r, 0);
         else
-          hipLaunchKernelGGL((k_qr_reg<512, 8, false>), dim3(np), dim3(512), 0, t, p, w, r, 0);
+          TEBD_LAUNCH("k_qr_reg<512, 8, false>", (k_qr_reg<512, 8, false>), dim3(np), dim3(512), 0, t, p, w, r, 0);
       },
       [](hipStream_t t, Prob* p, int w, int r, int v, int np, int) {
         if (v)
-          hipLaunchKernelGGL((k_qr_reg<1024, 12, true>), dim3(np), dim3(1024), 0, t, p, w, r, 1);
+          TEBD_LAUNCH("k_qr_reg<1024, 12, true>", (k_qr_reg<1024, 12, true>), dim3(np), dim3(1024), 0, t, p, w, r, 1);
         else
-          hipLaunchKernelGGL((k_qr_reg<1024, 12, false>), dim3(np), dim3(1024), 0, t, p, w, r, 1);
+          TEBD_LAUNCH("k_qr_reg<1024, 12, false>", (k_qr_reg<1024, 12, false>), dim3(np), dim3(1024), 0, t, p, w, r, 1);
       },
       [](hipStream_t t, Prob* p, int w, int r, int v, int np, int) {
-        hipLaunchKernelGGL(k_qr_lds<1024>, dim3(np), dim3(1024), size_t(kLdsElems) * sizeof(zt),
+        TEBD_LAUNCH("k_qr_lds<1024>", k_qr_lds<1024>, dim3(np), dim3(1024), size_t(kLdsElems) * sizeof(zt),
                            t, p, w, r, v);
       },
       [](hipStream_t t, Prob* p, int w, int r, int v, int np, int rw) {
-        hipLaunchKernelGGL(k_qr_glb<1024>, dim3(np), dim3(1024), 2 * size_t(rw) * sizeof(zt), t,
+        TEBD_LAUNCH("k_qr_glb<1024>", k_qr_glb<1024>, dim3(np), dim3(1024), 2 * size_t(rw) * sizeof(zt), t,
                            p, w, r, v);
       }};
   // the classes between those of the smallest and the largest possible size
@@ -1341,19 +1341,19 @@ hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s) {
   };
   const Launch fns[4] = {
       [](hipStream_t t, Prob* p, int np) {
-        hipLaunchKernelGGL((k_svd_pairs<256, 0>), dim3(np), dim3(256), 2 * 32 * 33 * sizeof(zt), t,
+        TEBD_LAUNCH("k_svd_pairs<256, 0>", (k_svd_pairs<256, 0>), dim3(np), dim3(256), 2 * 32 * 33 * sizeof(zt), t,
                            p);
       },
       [](hipStream_t t, Prob* p, int np) {
-        hipLaunchKernelGGL((k_svd_pairs<512, 1>), dim3(np), dim3(512), 2 * 64 * 65 * sizeof(zt), t,
+        TEBD_LAUNCH("k_svd_pairs<512, 1>", (k_svd_pairs<512, 1>), dim3(np), dim3(512), 2 * 64 * 65 * sizeof(zt), t,
                            p);
       },
       [](hipStream_t t, Prob* p, int np) {
-        hipLaunchKernelGGL((k_small_svd<1024, 2, true>), dim3(np), dim3(1024),
+        TEBD_LAUNCH("k_small_svd<1024, 2, true>", (k_small_svd<1024, 2, true>), dim3(np), dim3(1024),
                            size_t(kLdsElems) * sizeof(zt), t, p);
       },
       [](hipStream_t t, Prob* p, int np) {
-        hipLaunchKernelGGL((k_small_svd<1024, 4, false>), dim3(np), dim3(1024), 0, t, p);
+        TEBD_LAUNCH("k_small_svd<1024, 4, false>", (k_small_svd<1024, 4, false>), dim3(np), dim3(1024), 0, t, p);
       }};
   // the problem's l here is the rank the range finder revealed
   const int lo = svd_class(c.lmin < 1 ? 1 : c.lmin), hi = svd_class(c.lmax);
@@ -1453,7 +1453,7 @@ __global__ __launch_bounds__(64) void k_truncate(Prob* probs, double eps, int te
 }
 
 hipError_t launch_truncate(Prob* probs, const Common& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_truncate, dim3(c.nprob), dim3(64), 0, s, probs, c.eps, c.tebd,
+  TEBD_LAUNCH("k_truncate", k_truncate, dim3(c.nprob), dim3(64), 0, s, probs, c.eps, c.tebd,
                      c.pass2 ? nullptr : c.retry_count);
   return hipGetLastError();
 }
@@ -1478,8 +1478,16 @@ __global__ void k_stage2(Prob* probs, int nprob) {
 }
 
 hipError_t launch_stage2(Prob* probs, const Common& c, hipStream_t s) {
-  hipLaunchKernelGGL(k_stage2, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob);
+  TEBD_LAUNCH("k_stage2", k_stage2, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob);
   return hipGetLastError();
 }
 
 }  // namespace tebd
+
+extern "C" int32_t tebd_size_class(int32_t factorization, int32_t rows, int32_t l) {
+  using namespace tebd;
+  if (l < 1 || l > kMaxL) return -1;
+  if (factorization == 0) return rows < 1 || rows > kMaxRows ? -1 : qr_class(rows, l);
+  if (factorization == 1) return svd_class(l);
+  return -1;
+}

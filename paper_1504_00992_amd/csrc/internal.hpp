@@ -111,6 +111,22 @@ struct Common {
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
 };
 
+// Kernel-level event timing for tebd_profile_enable / tebd_profile_read:
+// while profiling is on, every launch is bracketed by two events recorded on
+// its stream and keyed by the kernel's name (a string literal naming the
+// instantiation as the profiler tools print it); otherwise both calls return
+// at once.  Launches are made from one host thread at a time.
+void prof_kernel_begin(const char* name, hipStream_t s);
+void prof_kernel_end(hipStream_t s);
+
+#define TEBD_LAUNCH(name, kern, grid, block, shmem, strm, ...)          \
+  do {                                                                  \
+    const hipStream_t tebd_launch_s_ = (strm);                          \
+    ::tebd::prof_kernel_begin(name, tebd_launch_s_);                    \
+    hipLaunchKernelGGL(kern, grid, block, shmem, tebd_launch_s_, __VA_ARGS__); \
+    ::tebd::prof_kernel_end(tebd_launch_s_);                            \
+  } while (0)
+
 // Contraction kinds scheduled through a global tile queue: every kind has
 // its own prefix sum over problems of the number of 64 x 64 output tiles.
 enum {

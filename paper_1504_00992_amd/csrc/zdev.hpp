@@ -67,11 +67,6 @@ __device__ __forceinline__ double dpp_move(double v) {
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
-#ifdef TEBD_SHFL_REDUCE
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-#else
   v += dpp_move<0xb1>(v);
   v += dpp_move<0x4e>(v);
   v += dpp_move<0x141>(v);
@@ -81,7 +76,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
   return __hiloint2double(hi, lo);
-#endif
 }
 // Sum over aligned groups of g lanes (g a power of two), result in every
 // lane of the group: DPP quad_perm [1,0,3,2] and [2,3,0,1], then

@@ -12,7 +12,21 @@ mode over the O-def run (full LAPACK SVD, every triplet coupled), central
 finite differences (h = 1e-6) of the same run with its bond dimensions
 replayed, and the truncation-free free-fermion closed form.
 
-Usage: python tests/golden/make_golden.py [tfim|xx]
+spin_boson_n100_adaptive.txt: the 16-chain spin-boson workload (N = 100,
+spin-1/2 then 99 oscillators truncated at d = 10, t_n = 0.5, omega_n = 1,
+dt = 0.05, chi_max = 100, p = 10, q = 2, relative discarded weight <= 1e-10
+per bond, two-stage adaptive rank, Philox seed 1504), chains 0 and 15, by the
+oracle's step-by-step RRSVD TEBD: bond dimensions, <sigma_z> of the spin and
+<n_i> of oscillators 1, 2, 5, 10, 20 after 50, 100, 150 and 200 steps, and
+every lambda after 200 steps.  Also the smallest relative distance of a
+truncation decision from the threshold over the run (near-ties, where two
+correct runs may cut differently).
+
+spin_boson_n100_chi128.txt: chain 0 of the same workload at chi_max = 128
+(the mixed-precision comparison): <sigma_z> of the spin after 50, 100, 150
+and 200 steps and every lambda after 200 steps, FP64 oracle.
+
+Usage: python tests/golden/make_golden.py [tfim|xx|spinboson|chi128]
 """
 import os
 import sys
@@ -77,9 +91,91 @@ def xx_n40_gradient():
             f.write(f"{b} {couplings[b]:.16e} {grad[b]:.16e} {fd[b]:.16e} {ffg[b]:.16e}\n")
 
 
+SB_CHAINS = (0, 15)
+SB_CHECK_STEPS = (50, 100, 150, 200)
+SB_SITES = (1, 2, 5, 10, 20)
+
+
+def spin_boson_n100():
+    n, d, dt, steps, chi_max, eps = 100, 10, 0.05, 200, 100, 1e-10
+    dims, hb = models.spin_boson_chain(n, d, 1.0, 0.5, 1.0, 0.5)
+    cache = {}
+
+    def gfn(b, tau):
+        if (b, tau) not in cache:
+            cache[(b, tau)] = models.gate(hb[b], tau)
+        return cache[(b, tau)]
+    num = np.diag(np.arange(d)).astype(np.complex128)
+    out = []
+    for chain in SB_CHAINS:
+        drv = mps.TEBD(mps.basis_product_state(dims, [0] * n), gfn, dt, chi_max, eps,
+                       method="rrsvd_adaptive", p=10, q=2, seed=1504, chain=chain)
+        rows = []
+        for s in range(1, steps + 1):
+            drv.step()
+            if s in SB_CHECK_STEPS:
+                obs = [mps.expectation(drv.mps, models.Z, 0).real]
+                obs += [mps.expectation(drv.mps, num, i).real for i in SB_SITES]
+                rows.append((s, drv.mps.chis(), obs))
+        margin = np.inf
+        for info in drv.log:
+            sv, f2, c = info["s"], info["frob2"], info["chi"]
+            if f2 <= 0:
+                continue
+            w = 1.0 - np.cumsum(sv ** 2) / f2
+            for k in (c - 2, c - 1):  # w(c - 1) and w(c), 0-based
+                if 0 <= k < len(w):
+                    margin = min(margin, abs(w[k] - eps) / eps)
+        out.append((chain, rows, [l.copy() for l in drv.mps.lambdas], margin))
+    with open(os.path.join(HERE, "spin_boson_n100_adaptive.txt"), "w") as f:
+        f.write("# spin-boson chain N=100 (spin + 99 oscillators, d=10), t_n=0.5, w_n=1, dt=0.05,\n")
+        f.write("# chi_max=100, RRSVD p=10 q=2, w<=1e-10 per bond, two-stage adaptive rank, seed 1504\n")
+        f.write("# written by tests/golden/make_golden.py (oracle/mps.py, method rrsvd_adaptive)\n")
+        f.write("# obs lines: chain step <sigma_z_0> <n_1> <n_2> <n_5> <n_10> <n_20>\n")
+        f.write("# chi lines: chain step chi_0 .. chi_N;  lam lines: chain bond lambda_1 ..\n")
+        for chain, rows, lams, margin in out:
+            f.write(f"margin {chain} {margin:.6e}\n")
+            for s, chis, obs in rows:
+                f.write(f"obs {chain} {s} " + " ".join(f"{v:.16e}" for v in obs) + "\n")
+                f.write(f"chi {chain} {s} " + " ".join(str(c) for c in chis) + "\n")
+            for b, lam in enumerate(lams):
+                f.write(f"lam {chain} {b} " + " ".join(f"{v:.16e}" for v in lam) + "\n")
+
+
+def spin_boson_n100_chi128():
+    n, d, dt, steps, chi_max, eps = 100, 10, 0.05, 200, 128, 1e-10
+    dims, hb = models.spin_boson_chain(n, d, 1.0, 0.5, 1.0, 0.5)
+    cache = {}
+
+    def gfn(b, tau):
+        if (b, tau) not in cache:
+            cache[(b, tau)] = models.gate(hb[b], tau)
+        return cache[(b, tau)]
+    drv = mps.TEBD(mps.basis_product_state(dims, [0] * n), gfn, dt, chi_max, eps,
+                   method="rrsvd_adaptive", p=10, q=2, seed=1504, chain=0)
+    z = []
+    for s in range(1, steps + 1):
+        drv.step()
+        if s % 50 == 0:
+            z.append((s, mps.expectation(drv.mps, models.Z, 0).real))
+    with open(os.path.join(HERE, "spin_boson_n100_chi128.txt"), "w") as f:
+        f.write("# spin-boson chain N=100 (spin + 99 oscillators, d=10), t_n=0.5, w_n=1, dt=0.05,\n")
+        f.write("# chi_max=128, RRSVD p=10 q=2, w<=1e-10 per bond, two-stage adaptive rank, seed 1504,\n")
+        f.write("# chain 0; written by tests/golden/make_golden.py (oracle/mps.py, FP64)\n")
+        f.write("# obs lines: step <sigma_z_0>;  lam lines: bond lambda_1 .. (after 200 steps)\n")
+        for s, v in z:
+            f.write(f"obs {s} {v:.16e}\n")
+        for b, lam in enumerate(drv.mps.lambdas):
+            f.write(f"lam {b} " + " ".join(f"{v:.16e}" for v in lam) + "\n")
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "all"
     if which in ("tfim", "all"):
         tfim_n20()
     if which in ("xx", "all"):
         xx_n40_gradient()
+    if which in ("spinboson", "all"):
+        spin_boson_n100()
+    if which in ("chi128", "all"):
+        spin_boson_n100_chi128()

@@ -19,7 +19,7 @@ HEADER = os.path.join(ROOT, "include", "tebd_rrsvd.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(?:tebd_status|const char\*)\s+(\w+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(?:tebd_status|const char\*|int32_t)\s+(\w+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_function():

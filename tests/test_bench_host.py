@@ -1,6 +1,7 @@
-"""Host-side accounting of bench.py (no GPU): the sketch width the
-algorithmic counts use, the QR byte count, and the rule that measured HBM
-traffic is only reported for the QR source the counters were taken on."""
+"""Host-side accounting of bench.py (no GPU): the per-kernel algorithmic
+flop and byte counts of a recorded sweep (sketch widths of the adaptive
+rank, second passes, QR size classes), and the rule that measured HBM
+traffic is only reported for the kernel sources the counters were taken on."""
 import importlib.util
 import os
 
@@ -16,40 +17,104 @@ def _bench():
     return mod
 
 
-def test_sketch_width_adaptive_and_fixed():
+class _Classes:
+    """Stand-in for the library's size-class query: class 0 below 100 rows,
+    class 1 up to 200, else 3."""
+
+    @staticmethod
+    def tebd_size_class(kind, rows, l):
+        return 0 if rows < 100 else (1 if rows <= 200 else 3)
+
+
+def _sweep(b, chi_before, chi_after, status, parity, adaptive=True):
+    w = b.Work(_Classes())
+    b.sweep_work(w, chi_before[None, :], chi_after[None, :], status[None, :], parity,
+                 [10, 10, 10, 10], 100, 10, 2, adaptive)
+    return w.k
+
+
+def test_first_stage_width_and_kernel_counts():
     b = _bench()
-    dims = [2, 10, 10, 10]
-    chi = np.array([1, 2, 19, 14, 1])
-    # bond 1: chi_m = 19 -> k1 = 19 + 10 = 29, l = k1 + p = 39 (m = 20 caps it)
-    (dl, dr, cl, cm, cr, m, n, l), = b.sweep_problems(chi, dims, 1, 100, 10, True)[:1]
-    assert (cl, cm, cr, m, n) == (2, 19, 14, 20, 140) and l == 20
-    dims2 = [10, 10, 10, 10]
-    chi2 = np.array([1, 19, 19, 14, 1])
-    out = b.sweep_problems(chi2, dims2, 1, 100, 10, True)
-    assert out[0][-1] == 29 + 10                  # adaptive: chi_m + ceil(chi_m / 2) + p
-    assert b.sweep_problems(chi2, dims2, 1, 100, 10, False)[0][-1] == 110   # fixed: chi_max + p
-    # small bonds use the margin 4: chi_m = 1 -> k1 = 5
-    assert b.sweep_problems(np.array([1, 1, 1, 1, 1]), dims2, 0, 100, 10, True)[0][-1] == 10
+    before = np.array([1, 19, 19, 14, 1])
+    after = np.array([1, 19, 21, 14, 1])
+    k = _sweep(b, before, after, np.zeros(3, dtype=np.int32), 1)
+    m, n, l = 190, 140, 19 + 10 + 10            # k1 = chi + ceil(chi / 2), l1 = k1 + p
+    f = 8.0 * m * n * l
+    assert k["k_sketch<0>"][0] == f
+    assert k["k_sketch<2>"][0] == 2 * f          # q = 2
+    assert k["k_sketch<1>"][0] == 3 * f          # q = 2 plus B^H = A^H Q
+    assert k["k_theta"][0] == 8.0 * 10 * 19 * 19 * 10 * 14
+    assert k["k_gate"][0] == 8.0 * 100 ** 2 * 19 * 14
+    # rows 190 and 140 both fall in class 1 of the stand-in: pivoted first QR
+    # (of Y, m rows) and QR of B^H (n rows, with R); unpivoted power iterations
+    piv, unp = k["k_qr_reg<1024, 12, true>"], k["k_qr_reg<1024, 12, false>"]
+    assert piv[0] == b.qr_flops(m, l) + b.qr_flops(n, l)
+    assert unp[0] == 2 * (b.qr_flops(m, l) + b.qr_flops(n, l))
+    assert piv[1] == b.qr_bytes(m, l) + b.qr_bytes(n, l, with_r=True)
+    assert k["k_form_u<1>"][0] == 8.0 * m * l * 21
+    assert k["k_form_vh<1>"][0] == 8.0 * n * l * 21
 
 
-def test_qr_bytes():
+def test_second_pass_and_fixed_rank_widths():
+    b = _bench()
+    before = np.array([1, 19, 19, 14, 1])
+    after = before.copy()
+    st = np.zeros(3, dtype=np.int32)
+    st[1] = 64                                   # the bond ran the fixed-rank second pass
+    k = _sweep(b, before, after, st, 1)
+    m, n = 190, 140
+    l1, l2 = 39, 110
+    assert k["k_sketch<0>"][0] == 8.0 * m * n * (l1 + l2)
+    assert k["k_omega"][1] == 16.0 * n * (l1 + l2)
+    # U and V^H are formed once, by the pass whose result is kept
+    assert k["k_form_u<1>"][0] == 8.0 * m * l2 * 19
+    fixed = _sweep(b, before, after, np.zeros(3, dtype=np.int32), 1, adaptive=False)
+    assert fixed["k_sketch<0>"][0] == 8.0 * m * n * l2
+    # small bonds: chi = 1 -> k1 = 5 -> l1 = 10 (capped by m = n = 10 here)
+    one = _sweep(b, np.ones(5, dtype=np.int64), np.ones(5, dtype=np.int64),
+                 np.zeros(3, dtype=np.int32), 0)
+    assert one["k_sketch<0>"][0] == 2 * 8.0 * 10 * 10 * 10   # bonds 0 and 2
+
+
+def test_qr_bytes_and_first_stage_rank():
     b = _bench()
     assert b.qr_bytes(10, 3) == 16 * 2 * 10 * 3
     assert b.qr_bytes(10, 3, with_r=True) == 16 * (2 * 10 * 3 + 9)
+    assert b.first_stage_rank(1, 100) == 5
+    assert b.first_stage_rank(19, 100) == 29
+    assert b.first_stage_rank(90, 100) == 100
 
 
-def test_traffic_only_for_the_measured_source(tmp_path):
+def test_traffic_only_for_the_measured_sources(tmp_path):
     b = _bench()
-    src = tmp_path / "factor.hip"
-    src.write_text("// some QR source\nint f() { return 1; }\n")
-    digest = b.code_digest(str(src))
-    summary = tmp_path / "qr_hbm_traffic_counters.txt"
-    summary.write_text(f"# factor.hip code sha256: {digest}\n# bytes per qr launch: 1234\n")
-    b.QR_SOURCE, b.QR_TRAFFIC_FILE = str(src), str(summary)
-    assert b.qr_traffic() == 1234.0
-    src.write_text("/* reworded */ int f()  {\n  return 1;  // comment\n}\n")  # comments only
-    assert b.qr_traffic() == 1234.0
-    src.write_text("int f() { return 2; }\n")  # the code changed since the counters
-    assert b.qr_traffic() is None
-    b.QR_TRAFFIC_FILE = str(tmp_path / "absent.txt")
-    assert b.qr_traffic() is None
+    csrc = tmp_path / "csrc"
+    csrc.mkdir()
+    (tmp_path / "profiles").mkdir()
+    src = csrc / "k.hip"
+    src.write_text("// a kernel\n__global__ void k_gate() { }\n")
+    b.CSRC, b.ROOT = str(csrc), str(tmp_path)
+    summary = tmp_path / "profiles" / "wl_hbm_traffic.txt"
+    summary.write_text(f"# kernel sources sha256: {b.code_digest()}\n"
+                       "# kernel  dispatches  FETCH_KiB  WRITE_KiB  bytes_per_launch\n"
+                       "k_qr_reg<512, 8, false>  10  1.0  2.0  3000\n"
+                       "k_gate  10  1.0  2.0  1234\n")
+    assert b.measured_traffic("k_gate", "wl")[0] == 1234.0
+    assert b.measured_traffic("k_qr_reg<512, 8, false>", "wl")[0] == 3000.0
+    assert b.measured_traffic("k_theta", "wl")[0] is None
+    src.write_text("/* reworded */ __global__ void k_gate()  {\n }  // comment\n")  # comments only
+    assert b.measured_traffic("k_gate", "wl")[0] == 1234.0
+    src.write_text("__global__ void k_gate() { int x; }\n")  # the code changed since
+    assert b.measured_traffic("k_gate", "wl")[0] is None
+    assert b.measured_traffic("k_gate", "absent")[0] is None
+
+
+def test_size_class_query_of_the_library():
+    # the bench attributes QR work to kernels through the library's own query
+    from paper_1504_00992_amd import _lib
+    _lib.load()
+    assert _lib.tebd_size_class(0, 100, 24) == 0
+    assert _lib.tebd_size_class(0, 190, 33) == 1
+    assert _lib.tebd_size_class(0, 200, 40) == 2
+    assert _lib.tebd_size_class(0, 2048, 74) == 3
+    assert _lib.tebd_size_class(1, 0, 66) == 2
+    assert _lib.tebd_size_class(0, 0, 5) == -1 and _lib.tebd_size_class(2, 5, 5) == -1

@@ -75,3 +75,41 @@ def test_mixed_tebd_spin_boson_against_fp64_oracle():
     print(f"mixed TEBD: max observable error {max(errs):.2e}")
     assert max(errs) < 1e-5
     assert abs(omps.norm2(gm) - 1.0) < 1e-8
+
+
+def test_mixed_spin_boson_chi128_full_run_against_fp64_oracle():
+    # The mixed-precision workload at full size: 16 spin-boson chains, N = 100,
+    # d = 10, chi_max = 128, 200 steps, adaptive rank, FP32 sketch and
+    # power-iteration products.  Chain 0 against the FP64 oracle run with the
+    # same test matrices (tests/golden/spin_boson_n100_chi128.txt): bond
+    # dimensions exactly, lambda and <sigma_z> within the 1e-5 bound of this
+    # path.
+    import os
+    from paper_1504_00992_amd import api, models as pm
+    path = os.path.join(os.path.dirname(__file__), "golden", "spin_boson_n100_chi128.txt")
+    z, lams = {}, {}
+    for line in open(path):
+        t = line.split()
+        if not t or t[0].startswith("#"):
+            continue
+        if t[0] == "obs":
+            z[int(t[1])] = float(t[2])
+        elif t[0] == "lam":
+            lams[int(t[1])] = np.array([float(x) for x in t[2:]])
+    n, d = 100, 10
+    dims, hb = pm.spin_boson(n, d, 1.0, 0.5, 1.0, 0.5)
+    dev = api.DeviceMPS.product_state(16, dims, [0] * n, 128)
+    drv = api.TEBD(dev, hb, 0.05, 128, p=10, q=2, trunc_eps=1e-10, seed=SEED, adaptive=2,
+                   precision=1)
+    zerr = 0.0
+    for s in range(1, 201):
+        drv.step()
+        if s in z:
+            torch.cuda.synchronize()
+            gam, lam = dev.to_host(0)
+            zerr = max(zerr, abs(omps.expectation(omps.MPS(gam, lam), om.Z, 0).real - z[s]))
+    gam, lam = dev.to_host(0)
+    assert [len(x) for x in lam] == [len(lams[b]) for b in range(n - 1)]
+    lerr = max(float(np.max(np.abs(lam[b] - lams[b]))) for b in range(n - 1))
+    print(f"mixed chi_max=128 spin-boson: max |d lambda| {lerr:.2e}, max |d <sigma_z>| {zerr:.2e}")
+    assert lerr < 1e-5 and zerr < 1e-5

@@ -69,16 +69,32 @@ def _compare(mats, res, chi_max, p, q, eps, omegas=None):
 # the QR size classes: (37, 53) register class 0; (190, 140, l = 33) and
 # (300, 200, l = 20) register class 1 with a slot per reflector (16 and 32
 # lanes per column); the 130-row side of (200, 130) register class 1 with
-# alternating reflector buffers; the larger ones the global class
+# alternating reflector buffers; (200, 200, l = 40) the LDS class on both
+# sides; the larger ones the global class.  (300, 300, l = 66) also runs the
+# small SVD's third class (C and J in LDS, 65 <= l <= 69).
 @pytest.mark.parametrize("m,n,chi_max,p", [(37, 53, 8, 10), (190, 140, 23, 10), (300, 200, 10, 10),
                                            (200, 130, 40, 10), (130, 200, 40, 10),
-                                           (300, 300, 50, 10), (700, 650, 64, 10)])
+                                           (300, 300, 50, 10), (700, 650, 64, 10),
+                                           (200, 200, 30, 10), (300, 300, 56, 10)])
 def test_parity_with_oracle_same_omega(m, n, chi_max, p):
     gen = wl.rng(m * 1000 + n)
     s = np.exp(-np.arange(min(m, n)) / (chi_max / 6.0))
     a = wl.known_spectrum(m, n, s, gen)
     res = _gpu([a], chi_max, p, 2, 1e-10)
     _compare([a], res, chi_max, p, 2, 1e-10)
+
+
+def test_size_classes_of_the_parity_shapes():
+    # the shapes above reach every factorisation kernel
+    from paper_1504_00992_amd import _lib
+    assert _lib.tebd_size_class(0, 37, 18) == 0
+    assert _lib.tebd_size_class(0, 190, 33) == 1
+    assert _lib.tebd_size_class(0, 200, 40) == 2
+    assert _lib.tebd_size_class(0, 300, 60) == 3
+    assert _lib.tebd_size_class(1, 0, 18) == 0
+    assert _lib.tebd_size_class(1, 0, 40) == 1
+    assert _lib.tebd_size_class(1, 0, 66) == 2
+    assert _lib.tebd_size_class(1, 0, 74) == 3
 
 
 def test_exact_when_sketch_covers_range():

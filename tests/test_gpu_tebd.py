@@ -46,6 +46,9 @@ def _two_site_block(gammas, lambdas, b):
     ([4, 4, 4, 4], [1, 4, 16, 18, 1], 1, 10, 4),       # RRSVD with l < n
     ([2, 5, 5, 2], [1, 2, 9, 2, 1], 0, 6, 3),          # left edge bond
     ([2, 5, 5, 2], [1, 2, 9, 2, 1], 2, 6, 3),          # right edge bond
+    # d = 10 on both sites, chi_l chi_r = 96: the gate product's matrix-core
+    # path with two 64-row tiles and K = 100 (the spin-boson geometry)
+    ([2, 10, 10, 10, 10], [1, 2, 12, 14, 8, 1], 2, 20, 10),
 ])
 def test_bond_update_matches_oracle(dims, chis, bond, chi_max, p):
     from paper_1504_00992_amd import api
@@ -252,3 +255,63 @@ def test_adaptive_host_skip_mode_matches_device_mode():
         runs.append((dev.gamma.clone(), dev.lam.clone(), dev.chi.clone(), drv.ws.status.clone()))
     for a, b in zip(runs[0], runs[1]):
         assert torch.equal(a, b)
+
+
+def _golden_spin_boson():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "spin_boson_n100_adaptive.txt")
+    margin, obs, chis, lams = {}, {}, {}, {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            t = line.split()
+            if t[0] == "margin":
+                margin[int(t[1])] = float(t[2])
+            elif t[0] == "obs":
+                obs[(int(t[1]), int(t[2]))] = [float(x) for x in t[3:]]
+            elif t[0] == "chi":
+                chis[(int(t[1]), int(t[2]))] = [int(x) for x in t[3:]]
+            elif t[0] == "lam":
+                lams[(int(t[1]), int(t[2]))] = np.array([float(x) for x in t[3:]])
+    return margin, obs, chis, lams
+
+
+def test_spin_boson_headline_run_matches_oracle():
+    # The headline workload at full size and in the launch configuration the
+    # benchmark times: 16 chains, N = 100 (spin + 99 oscillators, d = 10),
+    # chi_max = 100, p = 10, q = 2, w <= 1e-10, two-stage adaptive rank with
+    # the host-skipped second pass, all 200 steps.  Chains 0 and 15 against
+    # the oracle's step-by-step RRSVD run with the same test matrices
+    # (tests/golden/spin_boson_n100_adaptive.txt): bond dimensions exactly,
+    # <sigma_z> and <n_i> to 1e-10 after 50, 100, 150, 200 steps, every
+    # lambda to 1e-10 at the end.  The stored margin (smallest relative
+    # distance of a truncation decision from the threshold) shows that no
+    # cut of the run is a near-tie.
+    from paper_1504_00992_amd import api, models as pm
+    margin, obs, chis, lams = _golden_spin_boson()
+    assert min(margin.values()) > 1e-6
+    n, d = 100, 10
+    dims, hb = pm.spin_boson(n, d, 1.0, 0.5, 1.0, 0.5)
+    dev = api.DeviceMPS.product_state(16, dims, [0] * n, 100)
+    drv = api.TEBD(dev, hb, 0.05, 100, p=10, q=2, trunc_eps=1e-10, seed=SEED, adaptive=2)
+    num = np.diag(np.arange(d)).astype(np.complex128)
+    sites = (1, 2, 5, 10, 20)
+    for s in range(1, 201):
+        drv.step()
+        if s % 50:
+            continue
+        torch.cuda.synchronize()
+        for chain in (0, 15):
+            gam, lam = dev.to_host(chain)
+            gm = omps.MPS(gam, lam)
+            assert gm.chis() == chis[(chain, s)], (chain, s)
+            got = [omps.expectation(gm, om.Z, 0).real]
+            got += [omps.expectation(gm, num, i).real for i in sites]
+            err = np.max(np.abs(np.array(got) - np.array(obs[(chain, s)])))
+            assert err < 1e-10, (chain, s, err)
+            if s == 200:
+                for b in range(n - 1):
+                    assert np.max(np.abs(lam[b] - lams[(chain, b)])) < 1e-10, (chain, b)
+    st = drv.ws.status.cpu().numpy()
+    assert not np.any(st & (1 | 4 | 32))
