@@ -172,6 +172,28 @@ tebd_status rrsvd_truncate(int64_t batch, const int64_t* m, const int64_t* n,
                            double* disc_weight, int32_t* dev_status, void* workspace,
                            size_t ws_bytes, void* stream);
 
+/* rrsvd_truncate for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and random stream as rrsvd_truncate, without the
+ * workspace: scratch is a static device array of the library, 64 MiB per
+ * device, held by every device the library runs on until the process ends.
+ * The call allocates nothing (no hipMalloc, hipFree or pinned host buffer):
+ * problem descriptors are written by a kernel from its arguments, and the
+ * factorisation size classes run in order on `stream`.
+ *  - A batch whose rrsvd_truncate workspace (tebd_workspace_size with
+ *    mps = NULL) exceeds 64 MiB is refused with TEBD_ERR_WORKSPACE before
+ *    anything is enqueued.
+ *  - Every call on one device shares that device's scratch, which keeps the
+ *    last call's contents (no part of it needs to start at zero).  Calls
+ *    that overlap on one device race: serialise them (one stream, or events).
+ *  - Outputs are valid once `stream` has been synchronised. */
+tebd_status rrsvd_truncate_noalloc(int64_t batch, const int64_t* m, const int64_t* n,
+                                   const tebd_z* const* A, const int64_t* lda,
+                                   const tebd_z* const* omega, const tebd_params* prm,
+                                   tebd_z* const* U, int64_t ldu, double* const* S,
+                                   tebd_z* const* VH, int64_t ldvh, int32_t* chi_kept,
+                                   double* disc_weight, int32_t* dev_status, void* stream);
+
 /* One two-site update of bond `bond` (sites bond, bond+1) of chain `chain`
  * (Sec. II.B): Theta from Gamma-lambda-Gamma (Eq. deftheta), the gate
  * (Eq. defupdatetheta), the blocked matrix, its RRSVD truncation to chi',

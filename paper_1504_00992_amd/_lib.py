@@ -28,7 +28,8 @@ DEV_RANK_RETRY = 64
 
 EXPORTED = ("tebd_last_error", "tebd_version", "tebd_workspace_size", "rrsvd_truncate",
             "tebd_bond_update", "tebd_sweep", "tebd_adjoint_workspace_size", "tebd_tape_size", "tebd_sweep_record",
-            "tebd_sweep_adjoint", "tebd_profile_enable", "tebd_profile_read", "tebd_size_class")
+            "tebd_sweep_adjoint", "tebd_profile_enable", "tebd_profile_read", "tebd_size_class",
+            "rrsvd_truncate_noalloc")
 
 
 class TebdParams(ctypes.Structure):
@@ -75,6 +76,10 @@ def load():
     lib.rrsvd_truncate.restype = ctypes.c_int
     lib.rrsvd_truncate.argtypes = [i64, pi64, pi64, pp, pi64, pp, ctypes.POINTER(TebdParams),
                                    pp, i64, pp, pp, i64, vp, vp, vp, vp, sz, vp]
+    lib.rrsvd_truncate_noalloc.restype = ctypes.c_int
+    lib.rrsvd_truncate_noalloc.argtypes = [i64, pi64, pi64, pp, pi64, pp,
+                                           ctypes.POINTER(TebdParams), pp, i64, pp, pp, i64, vp,
+                                           vp, vp, vp]
     lib.tebd_bond_update.restype = ctypes.c_int
     lib.tebd_bond_update.argtypes = [ctypes.POINTER(TebdMps), i32, i32, vp,
                                      ctypes.POINTER(TebdParams), vp, vp, vp, sz, vp]
@@ -158,6 +163,17 @@ def rrsvd_truncate(m, n, a_ptrs, lda, omega_ptrs, prm, u_ptrs, ldu, s_ptrs, vh_p
                               _i64_array(lda), om, ctypes.byref(prm), _ptr_array(u_ptrs), int(ldu),
                               _ptr_array(s_ptrs), _ptr_array(vh_ptrs), int(ldvh), chi_kept_ptr,
                               disc_ptr, status_ptr, ws_ptr, int(ws_bytes), stream)
+
+
+def rrsvd_truncate_noalloc(m, n, a_ptrs, lda, omega_ptrs, prm, u_ptrs, ldu, s_ptrs, vh_ptrs,
+                           ldvh, chi_kept_ptr, disc_ptr, status_ptr, stream):
+    """Raw call of the no-allocation variant (static scratch, no workspace)."""
+    lib = load()
+    om = _ptr_array(omega_ptrs) if omega_ptrs is not None else None
+    return lib.rrsvd_truncate_noalloc(len(m), _i64_array(m), _i64_array(n), _ptr_array(a_ptrs),
+                                      _i64_array(lda), om, ctypes.byref(prm), _ptr_array(u_ptrs),
+                                      int(ldu), _ptr_array(s_ptrs), _ptr_array(vh_ptrs),
+                                      int(ldvh), chi_kept_ptr, disc_ptr, status_ptr, stream)
 
 
 def tebd_bond_update(mps, chain, bond, gate_ptr, prm, disc_ptr, status_ptr, ws_ptr, ws_bytes,

@@ -473,6 +473,271 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   return ok();
 }
 
+// Static scratch of rrsvd_truncate_noalloc, one copy per device (the code
+// object's global), used through the address hipGetSymbolAddress gives on
+// each device: the array's name is not a device address in host code.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Descriptors of the standalone RRSVD written on the device from kernel
+// arguments (by value, so no host buffer outlives the call): up to
+// kDescPerLaunch problems per launch, one lane each, the same fields as
+// the host-built descriptors of rrsvd_truncate.
+constexpr int kDescPerLaunch = 48;
+struct DescArgs {
+  int32_t first, count, chi_max, oversample, precision, om_ext;
+  int64_t ldu, ldvh;
+  Prob* probs;
+  int32_t* chi_out;
+  double* disc;
+  int32_t* status;
+  struct One {
+    int32_t m, n;
+    int64_t lda;
+    const zt* A;
+    const zt* om;
+    zt* U;
+    double* S;
+    zt* VH;
+    char* slab;
+  } prob[kDescPerLaunch];
+};
+static_assert(sizeof(DescArgs) <= 4096, "kernel arguments of k_noalloc_desc");
+
+__global__ void k_noalloc_desc(DescArgs a) {
+  const int i = threadIdx.x;
+  if (i >= a.count) return;
+  const DescArgs::One& o = a.prob[i];
+  const int32_t b = a.first + i;
+  Prob P{};
+  int32_t l = a.chi_max + a.oversample;
+  l = l < o.m ? l : o.m;
+  l = l < o.n ? l : o.n;
+  P.m = o.m;
+  P.n = o.n;
+  P.l = l;
+  P.kcap = a.chi_max;
+  P.k1 = a.chi_max;
+  P.l1 = P.l2 = l;
+  P.pid = b;
+  P.mixed = a.precision;
+  carve_slab(P, o.slab, o.m, o.n, l, 0, a.precision, 0);
+  P.A = const_cast<zt*>(o.A);
+  P.lda = o.lda;
+  if (a.om_ext) {
+    P.om = o.om;
+    P.om_ext = 1;
+  }
+  P.ldom = l;
+  P.U = o.U;
+  P.ldu = a.ldu;
+  P.S = o.S;
+  P.VH = o.VH;
+  P.ldvh = a.ldvh;
+  P.chi_out = a.chi_out + b;
+  P.disc = a.disc + b;
+  P.status = a.status + b;
+  a.probs[b] = P;
+}
+
+// Validation, planning and launch sequence of rrsvd_truncate.  With
+// noalloc set the workspace is the library's static scratch: the
+// descriptors are written on the device from kernel arguments (no host
+// staging buffer) and the size classes run in order on the caller's stream.
+tebd_status rrsvd_enqueue(int64_t batch, const int64_t* m, const int64_t* n,
+                          const tebd_z* const* A, const int64_t* lda, const tebd_z* const* omega,
+                          const tebd_params* prm, tebd_z* const* U, int64_t ldu,
+                          double* const* S, tebd_z* const* VH, int64_t ldvh, int32_t* chi_kept,
+                          double* disc_weight, int32_t* dev_status, void* workspace,
+                          size_t ws_bytes, void* stream, bool noalloc) {
+  tebd_status st = check_params(prm);
+  if (st != TEBD_OK) return st;
+  if (prm->adaptive)
+    return fail(TEBD_ERR_ARG, "prm->adaptive: the two-stage rank needs a bond dimension and is "
+                              "available in the TEBD entry points only");
+  if (batch < 1) return fail(TEBD_ERR_ARG, "argument 1 (batch) = %lld must be >= 1", (long long)batch);
+  if (!m) return fail(TEBD_ERR_ARG, "argument 2 (m) is NULL");
+  if (!n) return fail(TEBD_ERR_ARG, "argument 3 (n) is NULL");
+  if (!A) return fail(TEBD_ERR_ARG, "argument 4 (A) is NULL");
+  if (!lda) return fail(TEBD_ERR_ARG, "argument 5 (lda) is NULL");
+  if (!U) return fail(TEBD_ERR_ARG, "argument 8 (U) is NULL");
+  if (!S) return fail(TEBD_ERR_ARG, "argument 10 (S) is NULL");
+  if (!VH) return fail(TEBD_ERR_ARG, "argument 11 (VH) is NULL");
+  if (!chi_kept) return fail(TEBD_ERR_ARG, "argument 13 (chi_kept) is NULL");
+  if (!disc_weight) return fail(TEBD_ERR_ARG, "argument 14 (disc_weight) is NULL");
+  if (!dev_status) return fail(TEBD_ERR_ARG, "argument 15 (dev_status) is NULL");
+  if (ldu < prm->chi_max)
+    return fail(TEBD_ERR_SHAPE, "argument 9 (ldu) = %lld < chi_max = %d", (long long)ldu, prm->chi_max);
+  int64_t nmax = 0;
+  for (int64_t b = 0; b < batch; ++b) nmax = n[b] > nmax ? n[b] : nmax;
+  if (ldvh < nmax)
+    return fail(TEBD_ERR_SHAPE, "argument 12 (ldvh) = %lld < max n = %lld", (long long)ldvh, (long long)nmax);
+  for (int64_t b = 0; b < batch; ++b) {
+    if (m[b] < 1 || n[b] < 1 || m[b] > kMaxRows || n[b] > kMaxRows)
+      return fail(TEBD_ERR_SHAPE, "problem %lld: m = %lld, n = %lld out of range [1, %d]",
+                  (long long)b, (long long)m[b], (long long)n[b], kMaxRows);
+    if (lda[b] < n[b])
+      return fail(TEBD_ERR_SHAPE, "problem %lld: lda = %lld < n = %lld", (long long)b,
+                  (long long)lda[b], (long long)n[b]);
+    if (!A[b] || !U[b] || !S[b] || !VH[b])
+      return fail(TEBD_ERR_ARG, "problem %lld: a device pointer in A/U/S/VH is NULL", (long long)b);
+    if (omega && !omega[b])
+      return fail(TEBD_ERR_ARG, "problem %lld: omega[b] is NULL", (long long)b);
+  }
+  size_t need = 0;
+  st = tebd_workspace_size(nullptr, batch, m, n, prm, &need);
+  if (st != TEBD_OK) return st;
+  if (noalloc) {
+    if (need > kScratchBytes)
+      return fail(TEBD_ERR_WORKSPACE,
+                  "the batch needs %zu bytes of scratch; rrsvd_truncate_noalloc has %zu "
+                  "(use rrsvd_truncate with a workspace)", need, kScratchBytes);
+    hipError_t e = scratch_address(&workspace);
+    if (e != hipSuccess)
+      return fail(TEBD_ERR_DEVICE, "static scratch address: %s", hipGetErrorString(e));
+    ws_bytes = kScratchBytes;
+  }
+  if (!workspace) return fail(TEBD_ERR_WORKSPACE, "argument 16 (workspace) is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(TEBD_ERR_WORKSPACE, "argument 16 (workspace) must be 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(TEBD_ERR_WORKSPACE, "argument 17 (ws_bytes) = %zu < %zu needed", ws_bytes, need);
+
+  std::vector<Prob> host(noalloc ? 0 : batch);
+  char* base = reinterpret_cast<char*>(workspace);
+  char* slab0 = base + align256(size_t(batch) * sizeof(Prob)) + align256(sched_bytes(batch));
+  char* slab = slab0;
+  Common c;
+  c.nprob = int32_t(batch);
+  c.q = prm->q;
+  c.eps = prm->trunc_eps;
+  c.seed = prm->seed;
+  c.stream_id = prm->stream_id;
+  c.mmax = c.nmax = c.lmax = 0;
+  c.mmin = c.nmin = c.lmin = 1 << 30;
+  c.kcap = prm->chi_max;
+  c.tebd = 0;
+  c.adaptive = 0;
+  c.pass2 = 0;
+  c.mixed = prm->precision;
+  c.record = 0;
+  c.nsites = 0;
+  c.retry_count = nullptr;
+  c.dmax = 0;
+  c.chimax = 0;
+  c.serial = noalloc ? 1 : 0;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  DescArgs da;
+  da.first = 0;
+  da.count = 0;
+  da.chi_max = prm->chi_max;
+  da.oversample = prm->p;
+  da.precision = prm->precision;
+  da.om_ext = omega ? 1 : 0;
+  da.ldu = ldu;
+  da.ldvh = ldvh;
+  da.probs = reinterpret_cast<Prob*>(workspace);
+  da.chi_out = chi_kept;
+  da.disc = disc_weight;
+  da.status = dev_status;
+  int64_t tiles = 0;
+  for (int64_t b = 0; b < batch; ++b) {
+    {
+      const int64_t tm = (m[b] + 63) / 64, tn = (n[b] + 63) / 64;
+      const int64_t tk = (prm->chi_max + 63) / 64;
+      tiles += (tm > tn ? tm : tn) * (tk > 3 ? tk : 3);
+    }
+    if (noalloc) {
+      const int l = sketch_l(prm->chi_max, prm->p, m[b], n[b]);
+      DescArgs::One& o = da.prob[da.count++];
+      o.m = int32_t(m[b]);
+      o.n = int32_t(n[b]);
+      o.lda = lda[b];
+      o.A = reinterpret_cast<const zt*>(A[b]);
+      o.om = omega ? reinterpret_cast<const zt*>(omega[b]) : nullptr;
+      o.U = reinterpret_cast<zt*>(U[b]);
+      o.S = S[b];
+      o.VH = reinterpret_cast<zt*>(VH[b]);
+      o.slab = slab;
+      slab += slab_bytes(m[b], n[b], l, 0, prm->precision, 0);
+      c.mmax = o.m > c.mmax ? o.m : c.mmax;
+      c.nmax = o.n > c.nmax ? o.n : c.nmax;
+      c.lmax = l > c.lmax ? l : c.lmax;
+      c.mmin = o.m < c.mmin ? o.m : c.mmin;
+      c.nmin = o.n < c.nmin ? o.n : c.nmin;
+      c.lmin = l < c.lmin ? l : c.lmin;
+      if (da.count == kDescPerLaunch || b + 1 == batch) {
+        hipLaunchKernelGGL(k_noalloc_desc, dim3(1), dim3(64), 0, s, da);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+          return fail(TEBD_ERR_DEVICE, "HIP error while enqueuing: %s", hipGetErrorString(e));
+        da.first = int32_t(b + 1);
+        da.count = 0;
+      }
+      continue;
+    }
+    Prob& P = host[b];
+    std::memset(&P, 0, sizeof(Prob));
+    P.m = int32_t(m[b]);
+    P.n = int32_t(n[b]);
+    P.l = sketch_l(prm->chi_max, prm->p, m[b], n[b]);
+    P.kcap = prm->chi_max;
+    P.k1 = prm->chi_max;
+    P.l1 = P.l2 = P.l;
+    P.pid = int32_t(b);
+    P.mixed = prm->precision;
+    carve_slab(P, slab, m[b], n[b], P.l, 0, prm->precision, 0);
+    slab += slab_bytes(m[b], n[b], P.l, 0, prm->precision, 0);
+    P.A = const_cast<zt*>(reinterpret_cast<const zt*>(A[b]));
+    P.lda = lda[b];
+    if (omega) {
+      P.om = reinterpret_cast<const zt*>(omega[b]);
+      P.om_ext = 1;
+    }
+    P.ldom = P.l;
+    P.U = reinterpret_cast<zt*>(U[b]);
+    P.ldu = ldu;
+    P.S = S[b];
+    P.VH = reinterpret_cast<zt*>(VH[b]);
+    P.ldvh = ldvh;
+    P.chi_out = chi_kept + b;
+    P.disc = disc_weight + b;
+    P.status = dev_status + b;
+    c.mmax = P.m > c.mmax ? P.m : c.mmax;
+    c.nmax = P.n > c.nmax ? P.n : c.nmax;
+    c.lmax = P.l > c.lmax ? P.l : c.lmax;
+    c.mmin = P.m < c.mmin ? P.m : c.mmin;
+    c.nmin = P.n < c.nmin ? P.n : c.nmin;
+    c.lmin = P.l < c.lmin ? P.l : c.lmin;
+  }
+  c.offs = reinterpret_cast<int32_t*>(base + align256(size_t(batch) * sizeof(Prob)));
+  c.grid = persistent_grid(tiles);
+  hipError_t e = noalloc ? hipSuccess : upload(workspace, host.data(), host.size() * sizeof(Prob), s);
+  if (e == hipSuccess) e = run_pipeline(reinterpret_cast<Prob*>(workspace), c, s);
+  if (e != hipSuccess) return fail(TEBD_ERR_DEVICE, "HIP error while enqueuing: %s", hipGetErrorString(e));
+  return ok();
+}
+
 }  // namespace
 
 extern "C" {
@@ -579,120 +844,18 @@ tebd_status rrsvd_truncate(int64_t batch, const int64_t* m, const int64_t* n,
                            tebd_z* const* VH, int64_t ldvh, int32_t* chi_kept,
                            double* disc_weight, int32_t* dev_status, void* workspace,
                            size_t ws_bytes, void* stream) {
-  tebd_status st = check_params(prm);
-  if (st != TEBD_OK) return st;
-  if (prm->adaptive)
-    return fail(TEBD_ERR_ARG, "prm->adaptive: the two-stage rank needs a bond dimension and is "
-                              "available in the TEBD entry points only");
-  if (batch < 1) return fail(TEBD_ERR_ARG, "argument 1 (batch) = %lld must be >= 1", (long long)batch);
-  if (!m) return fail(TEBD_ERR_ARG, "argument 2 (m) is NULL");
-  if (!n) return fail(TEBD_ERR_ARG, "argument 3 (n) is NULL");
-  if (!A) return fail(TEBD_ERR_ARG, "argument 4 (A) is NULL");
-  if (!lda) return fail(TEBD_ERR_ARG, "argument 5 (lda) is NULL");
-  if (!U) return fail(TEBD_ERR_ARG, "argument 8 (U) is NULL");
-  if (!S) return fail(TEBD_ERR_ARG, "argument 10 (S) is NULL");
-  if (!VH) return fail(TEBD_ERR_ARG, "argument 11 (VH) is NULL");
-  if (!chi_kept) return fail(TEBD_ERR_ARG, "argument 13 (chi_kept) is NULL");
-  if (!disc_weight) return fail(TEBD_ERR_ARG, "argument 14 (disc_weight) is NULL");
-  if (!dev_status) return fail(TEBD_ERR_ARG, "argument 15 (dev_status) is NULL");
-  if (ldu < prm->chi_max)
-    return fail(TEBD_ERR_SHAPE, "argument 9 (ldu) = %lld < chi_max = %d", (long long)ldu, prm->chi_max);
-  int64_t nmax = 0;
-  for (int64_t b = 0; b < batch; ++b) nmax = n[b] > nmax ? n[b] : nmax;
-  if (ldvh < nmax)
-    return fail(TEBD_ERR_SHAPE, "argument 12 (ldvh) = %lld < max n = %lld", (long long)ldvh, (long long)nmax);
-  for (int64_t b = 0; b < batch; ++b) {
-    if (m[b] < 1 || n[b] < 1 || m[b] > kMaxRows || n[b] > kMaxRows)
-      return fail(TEBD_ERR_SHAPE, "problem %lld: m = %lld, n = %lld out of range [1, %d]",
-                  (long long)b, (long long)m[b], (long long)n[b], kMaxRows);
-    if (lda[b] < n[b])
-      return fail(TEBD_ERR_SHAPE, "problem %lld: lda = %lld < n = %lld", (long long)b,
-                  (long long)lda[b], (long long)n[b]);
-    if (!A[b] || !U[b] || !S[b] || !VH[b])
-      return fail(TEBD_ERR_ARG, "problem %lld: a device pointer in A/U/S/VH is NULL", (long long)b);
-    if (omega && !omega[b])
-      return fail(TEBD_ERR_ARG, "problem %lld: omega[b] is NULL", (long long)b);
-  }
-  size_t need = 0;
-  st = tebd_workspace_size(nullptr, batch, m, n, prm, &need);
-  if (st != TEBD_OK) return st;
-  if (!workspace) return fail(TEBD_ERR_WORKSPACE, "argument 16 (workspace) is NULL");
-  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
-    return fail(TEBD_ERR_WORKSPACE, "argument 16 (workspace) must be 256-byte aligned");
-  if (ws_bytes < need)
-    return fail(TEBD_ERR_WORKSPACE, "argument 17 (ws_bytes) = %zu < %zu needed", ws_bytes, need);
+  return rrsvd_enqueue(batch, m, n, A, lda, omega, prm, U, ldu, S, VH, ldvh, chi_kept,
+                       disc_weight, dev_status, workspace, ws_bytes, stream, false);
+}
 
-  std::vector<Prob> host(batch);
-  char* base = reinterpret_cast<char*>(workspace);
-  char* slab = base + align256(size_t(batch) * sizeof(Prob)) + align256(sched_bytes(batch));
-  Common c;
-  c.nprob = int32_t(batch);
-  c.q = prm->q;
-  c.eps = prm->trunc_eps;
-  c.seed = prm->seed;
-  c.stream_id = prm->stream_id;
-  c.mmax = c.nmax = c.lmax = 0;
-  c.mmin = c.nmin = c.lmin = 1 << 30;
-  c.kcap = prm->chi_max;
-  c.tebd = 0;
-  c.adaptive = 0;
-  c.pass2 = 0;
-  c.mixed = prm->precision;
-  c.record = 0;
-  c.nsites = 0;
-  c.retry_count = nullptr;
-  c.dmax = 0;
-  c.chimax = 0;
-  for (int64_t b = 0; b < batch; ++b) {
-    Prob& P = host[b];
-    std::memset(&P, 0, sizeof(Prob));
-    P.m = int32_t(m[b]);
-    P.n = int32_t(n[b]);
-    P.l = sketch_l(prm->chi_max, prm->p, m[b], n[b]);
-    P.kcap = prm->chi_max;
-    P.k1 = prm->chi_max;
-    P.l1 = P.l2 = P.l;
-    P.pid = int32_t(b);
-    P.mixed = prm->precision;
-    carve_slab(P, slab, m[b], n[b], P.l, 0, prm->precision, 0);
-    slab += slab_bytes(m[b], n[b], P.l, 0, prm->precision, 0);
-    P.A = const_cast<zt*>(reinterpret_cast<const zt*>(A[b]));
-    P.lda = lda[b];
-    if (omega) {
-      P.om = reinterpret_cast<const zt*>(omega[b]);
-      P.om_ext = 1;
-    }
-    P.ldom = P.l;
-    P.U = reinterpret_cast<zt*>(U[b]);
-    P.ldu = ldu;
-    P.S = S[b];
-    P.VH = reinterpret_cast<zt*>(VH[b]);
-    P.ldvh = ldvh;
-    P.chi_out = chi_kept + b;
-    P.disc = disc_weight + b;
-    P.status = dev_status + b;
-    c.mmax = P.m > c.mmax ? P.m : c.mmax;
-    c.nmax = P.n > c.nmax ? P.n : c.nmax;
-    c.lmax = P.l > c.lmax ? P.l : c.lmax;
-    c.mmin = P.m < c.mmin ? P.m : c.mmin;
-    c.nmin = P.n < c.nmin ? P.n : c.nmin;
-    c.lmin = P.l < c.lmin ? P.l : c.lmin;
-  }
-  c.offs = reinterpret_cast<int32_t*>(base + align256(size_t(batch) * sizeof(Prob)));
-  {
-    int64_t tiles = 0;
-    for (int64_t b = 0; b < batch; ++b) {
-      const int64_t tm = (host[b].m + 63) / 64, tn = (host[b].n + 63) / 64;
-      const int64_t tk = (prm->chi_max + 63) / 64;
-      tiles += (tm > tn ? tm : tn) * (tk > 3 ? tk : 3);
-    }
-    c.grid = persistent_grid(tiles);
-  }
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  hipError_t e = upload(workspace, host.data(), host.size() * sizeof(Prob), s);
-  if (e == hipSuccess) e = run_pipeline(reinterpret_cast<Prob*>(workspace), c, s);
-  if (e != hipSuccess) return fail(TEBD_ERR_DEVICE, "HIP error while enqueuing: %s", hipGetErrorString(e));
-  return ok();
+tebd_status rrsvd_truncate_noalloc(int64_t batch, const int64_t* m, const int64_t* n,
+                                   const tebd_z* const* A, const int64_t* lda,
+                                   const tebd_z* const* omega, const tebd_params* prm,
+                                   tebd_z* const* U, int64_t ldu, double* const* S,
+                                   tebd_z* const* VH, int64_t ldvh, int32_t* chi_kept,
+                                   double* disc_weight, int32_t* dev_status, void* stream) {
+  return rrsvd_enqueue(batch, m, n, A, lda, omega, prm, U, ldu, S, VH, ldvh, chi_kept,
+                       disc_weight, dev_status, nullptr, 0, stream, true);
 }
 
 tebd_status tebd_bond_update(const tebd_mps* mps, int32_t chain, int32_t bond,

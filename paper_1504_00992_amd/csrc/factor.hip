@@ -903,7 +903,7 @@ template <class L>
 hipError_t fork_join(hipStream_t s, L* launches, int n, const Common& c) {
   if (n == 0) return hipSuccess;
   SideStreams* ss = nullptr;
-  const bool fork = n > 1 && c.nprob >= kForkMinProblems && !c.pass2;
+  const bool fork = n > 1 && c.nprob >= kForkMinProblems && !c.pass2 && !c.serial;
   hipError_t e = fork ? side_streams(ss) : hipSuccess;
   if (e != hipSuccess) return e;
   if (n == 1 || !ss) {

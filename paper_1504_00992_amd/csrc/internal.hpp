@@ -109,6 +109,7 @@ struct Common {
   int32_t ktiles[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
+  int32_t serial = 0;  // 1: size classes run in order on the caller's stream (no side streams)
 };
 
 // Kernel-level event timing for tebd_profile_enable / tebd_profile_read:

@@ -225,3 +225,18 @@ def test_propagator_derivative_matches_finite_differences():
     gbar = gen.standard_normal((4, 4)) + 1j * gen.standard_normal((4, 4))
     assert gradient.coupling_gradient(gbar, h, tau, dh) == pytest.approx(
         float(np.real(np.sum(gbar.conj() * fd))), abs=1e-8)
+
+
+def test_noalloc_refuses_batches_beyond_its_scratch():
+    # 4 problems of 4096 x 4096 at l = 110 need about 86 MB of scratch, more
+    # than the 64 MiB static array: refused on the host, nothing enqueued
+    # (the fake device pointers are never touched)
+    lib = _lib.load()
+    batch = 4
+    m = [4096] * batch
+    prm = _lib.params(100, 10, 2, 1e-10)
+    fake = [0x1000 * (i + 1) for i in range(batch)]
+    st = _lib.rrsvd_truncate_noalloc(m, m, fake, m, None, prm, fake, 100, fake, fake, 4096,
+                                     0x1000, 0x1000, 0x1000, None)
+    assert st == _lib.TEBD_ERR_WORKSPACE
+    assert "64" in _lib.tebd_last_error() or "scratch" in _lib.tebd_last_error()
