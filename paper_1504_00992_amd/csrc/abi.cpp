@@ -259,18 +259,27 @@ struct Profiler {
 Profiler g_prof;
 
 // Run one launcher, bracketed by events when profiling is on.
+// The profiler's lock is not held while `launch` runs: the kernel-level
+// brackets inside it take the same lock.
 template <class F>
 hipError_t timed(int kind, hipStream_t s, F&& launch) {
   if (!g_prof.on) return launch();
-  std::lock_guard<std::mutex> lk(g_prof.mu);
-  hipEvent_t a = g_prof.get(), b = g_prof.get();
+  hipEvent_t a, b;
+  {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    a = g_prof.get();
+    b = g_prof.get();
+  }
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, s);
-  if (e != hipSuccess) return e;
-  e = launch();
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(b, s);
-  if (e != hipSuccess) return e;
+  if (e == hipSuccess) e = launch();
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  if (e != hipSuccess) {
+    g_prof.pool.push_back(a);
+    g_prof.pool.push_back(b);
+    return e;
+  }
   g_prof.recs.push_back({kind, a, b});
   return hipSuccess;
 }
