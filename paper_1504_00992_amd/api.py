@@ -211,3 +211,56 @@ class TEBD:
     def bond_updates_per_step(self):
         n = self.mps.n_sites
         return self.mps.n_chains * (n - 1)
+
+
+class GraphTEBD:
+    """Trotter steps of a TEBD driver captured in HIP graphs and replayed.
+
+    The driver must use a rank mode that never waits for the host (adaptive
+    0 or 1: the second pass of the two-stage rank is skipped on the device),
+    so that every launch of a sweep can be captured.  `steps` steps are
+    captured in graphs of at most `steps_per_graph` steps each; each sweep's
+    Gaussian test matrices follow its position in the run (as in eager
+    stepping from sweeps_done = 0), so a replay from a given state computes
+    exactly what eager stepping from that state does.  Capturing does not
+    run anything: the MPS is left as it was.  replay() runs all graphs in
+    order on the current stream.
+    """
+
+    def __init__(self, drv, steps, steps_per_graph=25):
+        if drv.prm.adaptive not in (0, 1):
+            raise ValueError("graph capture needs adaptive = 0 or 1 (no host round trip)")
+        mps = drv.mps
+        snap = (mps.gamma.clone(), mps.lam.clone(), mps.chi.clone())
+        # one eager step first: the library creates its side streams and sets
+        # kernel attributes on first use, which capture does not allow
+        drv.sweeps_done = 0
+        drv.step()
+        torch.cuda.synchronize()
+        self._restore(mps, snap)
+        drv.sweeps_done = 0
+        self.drv = drv
+        self.steps = int(steps)
+        self.graphs = []
+        stream = torch.cuda.Stream()
+        done = 0
+        while done < self.steps:
+            k = min(int(steps_per_graph), self.steps - done)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=stream):
+                for _ in range(k):
+                    drv.step()
+            self.graphs.append(g)
+            done += k
+        torch.cuda.synchronize()
+        drv.sweeps_done = 0
+
+    @staticmethod
+    def _restore(mps, snap):
+        mps.gamma.copy_(snap[0])
+        mps.lam.copy_(snap[1])
+        mps.chi.copy_(snap[2])
+
+    def replay(self):
+        for g in self.graphs:
+            g.replay()

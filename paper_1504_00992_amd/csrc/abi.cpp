@@ -228,8 +228,6 @@ struct Profiler {
     hipEvent_t a, b;
   };
   std::vector<KRec> krecs;
-  const char* open_name = nullptr;
-  hipEvent_t open_a = nullptr;
   hipEvent_t get() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -251,9 +249,6 @@ struct Profiler {
       pool.push_back(r.b);
     }
     krecs.clear();
-    if (open_a) pool.push_back(open_a);
-    open_a = nullptr;
-    open_name = nullptr;
   }
 };
 Profiler g_prof;
@@ -288,33 +283,25 @@ hipError_t timed(int kind, hipStream_t s, F&& launch) {
 
 namespace tebd {
 
-void prof_kernel_begin(const char* name, hipStream_t s) {
-  if (!g_prof.on) return;
+bool prof_kernel_events(hipEvent_t* start, hipEvent_t* stop) {
+  if (!g_prof.on) return false;
   std::lock_guard<std::mutex> lk(g_prof.mu);
-  hipEvent_t a = g_prof.get();
-  if (!a) return;
-  if (hipEventRecord(a, s) != hipSuccess) {
-    g_prof.pool.push_back(a);
-    return;
-  }
-  if (g_prof.open_a) g_prof.pool.push_back(g_prof.open_a);
-  g_prof.open_a = a;
-  g_prof.open_name = name;
+  *start = g_prof.get();
+  *stop = g_prof.get();
+  if (*start && *stop) return true;
+  if (*start) g_prof.pool.push_back(*start);
+  if (*stop) g_prof.pool.push_back(*stop);
+  return false;
 }
 
-void prof_kernel_end(hipStream_t s) {
-  if (!g_prof.on) return;
+void prof_kernel_done(const char* name, hipEvent_t start, hipEvent_t stop) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
-  if (!g_prof.open_a) return;
-  hipEvent_t b = g_prof.get();
-  if (!b) return;
-  if (hipEventRecord(b, s) != hipSuccess) {
-    g_prof.pool.push_back(b);
+  if (hipGetLastError() != hipSuccess) {
+    g_prof.pool.push_back(start);
+    g_prof.pool.push_back(stop);
     return;
   }
-  g_prof.krecs.push_back({g_prof.open_name, g_prof.open_a, b});
-  g_prof.open_a = nullptr;
-  g_prof.open_name = nullptr;
+  g_prof.krecs.push_back({name, start, stop});
 }
 
 }  // namespace tebd

@@ -596,7 +596,8 @@ hipError_t launch_adjoint(AdjProb* probs, const AdjCommon& c, const tebd_mps& mp
   TRY("k_adj_plan", k_adj_plan, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob, c.nb, c.parity,
       mps_in, gates, c.gate_chain_stride, tape, slot_bytes, mcap, lcap, gamma_bar, lambda_bar,
       gate_bar, status, lambda_floor, slab_base, slab_sz, nchunk_cap);
-  TRY("k_schedule<tebd::AdjProb, false>", k_schedule<AdjProb>, dim3(1), dim3(kScheduleThreads), 0, s, probs, c.nprob, 0, c.offs);
+  TRY("k_schedule<tebd::AdjProb, false>", k_schedule<AdjProb>, dim3(1), dim3(kScheduleThreads), 0, s, probs, c.nprob, 0, c.offs,
+      static_cast<int32_t*>(nullptr));
   TRY("k_adj_prep", k_adj_prep, pb, dim3(256), 0, s, probs);
   TRY("k_adj_m12_theta", k_adj_m12_theta, g, dim3(256), 0, s, probs, c.offs, c.nprob);
   TRY("k_adj_core", k_adj_core, pb, dim3(256), 0, s, probs);

@@ -127,7 +127,7 @@ hipError_t launch_schedule(Prob* probs, const Common& c, hipStream_t s) {
                        c.nprob, c.tebd, c.offs, c.bounds_dev);
   else
     TEBD_LAUNCH("k_schedule<tebd::Prob, false>", (k_schedule<Prob, false>), dim3(1), dim3(kScheduleThreads), 0, s, probs,
-                       c.nprob, c.tebd, c.offs, nullptr);
+                       c.nprob, c.tebd, c.offs, static_cast<int32_t*>(nullptr));
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 // on the device (bond dimensions after truncation) never travel to the host.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -113,19 +114,27 @@ struct Common {
 };
 
 // Kernel-level event timing for tebd_profile_enable / tebd_profile_read:
-// while profiling is on, every launch is bracketed by two events recorded on
-// its stream and keyed by the kernel's name (a string literal naming the
-// instantiation as the profiler tools print it); otherwise both calls return
-// at once.  Launches are made from one host thread at a time.
-void prof_kernel_begin(const char* name, hipStream_t s);
-void prof_kernel_end(hipStream_t s);
+// while profiling is on, every launch goes through hipExtLaunchKernelGGL
+// with a start and a stop event that the dispatch itself records (so the
+// interval is the kernel's execution, as profiler tools report it), keyed
+// by the kernel's name (a string literal naming the instantiation as those
+// tools print it); otherwise it is a plain launch.  prof_kernel_events hands
+// out the two events (false when profiling is off), prof_kernel_done files
+// them under the name.
+bool prof_kernel_events(hipEvent_t* start, hipEvent_t* stop);
+void prof_kernel_done(const char* name, hipEvent_t start, hipEvent_t stop);
 
-#define TEBD_LAUNCH(name, kern, grid, block, shmem, strm, ...)          \
-  do {                                                                  \
-    const hipStream_t tebd_launch_s_ = (strm);                          \
-    ::tebd::prof_kernel_begin(name, tebd_launch_s_);                    \
-    hipLaunchKernelGGL(kern, grid, block, shmem, tebd_launch_s_, __VA_ARGS__); \
-    ::tebd::prof_kernel_end(tebd_launch_s_);                            \
+#define TEBD_LAUNCH(name, kern, grid, block, shmem, strm, ...)                              \
+  do {                                                                                      \
+    const hipStream_t tebd_launch_s_ = (strm);                                              \
+    hipEvent_t tebd_ev_a_ = nullptr, tebd_ev_b_ = nullptr;                                  \
+    if (::tebd::prof_kernel_events(&tebd_ev_a_, &tebd_ev_b_)) {                             \
+      hipExtLaunchKernelGGL(kern, grid, block, shmem, tebd_launch_s_, tebd_ev_a_, tebd_ev_b_, \
+                            0, __VA_ARGS__);                                                \
+      ::tebd::prof_kernel_done(name, tebd_ev_a_, tebd_ev_b_);                               \
+    } else {                                                                                \
+      hipLaunchKernelGGL(kern, grid, block, shmem, tebd_launch_s_, __VA_ARGS__);            \
+    }                                                                                       \
   } while (0)
 
 // Contraction kinds scheduled through a global tile queue: every kind has
