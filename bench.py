@@ -303,7 +303,7 @@ class Evolution:
         chi after, status) of every sweep (device tensors)."""
         d = self.drv
         for _ in range(steps):
-            for parity, gates in ((0, d.g_half), (1, d.g_full), (0, d.g_half)):
+            for parity, gates in d.schedule:
                 before = self.mps.chi.clone() if record is not None else None
                 d.sweep(parity, gates)
                 if record is not None:

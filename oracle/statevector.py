@@ -11,7 +11,7 @@ distance to the circuit shrinks as dt^2 (second-order splitting).
 import numpy as np
 
 from . import models
-from .mps import STEP_SWEEPS
+from .mps import step_sweeps
 
 
 def product_vector(dims, levels):
@@ -33,11 +33,11 @@ def apply_two_site(psi, gate, b, dims):
     return np.einsum("xy,lyr->lxr", gate, t).reshape(-1)
 
 
-def trotter_evolve(psi, bond_hams, dims, dt, steps):
-    """Apply `steps` symmetric Trotter steps gate by gate (same order as TEBD)."""
+def trotter_evolve(psi, bond_hams, dims, dt, steps, order=2):
+    """Apply `steps` Trotter steps gate by gate (same order as TEBD)."""
     n = len(dims)
     for _ in range(steps):
-        for parity, frac in STEP_SWEEPS:
+        for parity, frac in step_sweeps(order):
             tau = frac * dt
             for b in range(parity, n - 1, 2):
                 psi = apply_two_site(psi, models.gate(bond_hams[b], tau), b, dims)

@@ -111,6 +111,50 @@ def test_trotter_error_is_second_order():
     assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
 
 
+def test_fourth_order_composition_error_scales_as_dt4():
+    # Suzuki's fourth-order composition of the symmetric step: global error
+    # O(dt^4), so halving dt divides it by ~16; the coefficients sum to one
+    # (a wrong s, a dropped sub-step or a wrong sign in 1 - 4s breaks both).
+    sw = mps.step_sweeps(4)
+    assert len(sw) == 15
+    assert abs(sum(f for p, f in sw if p == 1) - 1.0) < 1e-15
+    assert abs(sum(f for p, f in sw if p == 0) - 1.0) < 1e-15
+    n, T = 6, 0.8
+    dims, hb = models.tfim(n, 1.0, 1.0)
+    H = models.full_hamiltonian(dims, hb)
+    psi0 = statevector.product_vector(dims, [0] * n)
+    exact = statevector.exact_evolve(psi0, H, T)
+    errs = []
+    for steps in (4, 8, 16):
+        psi = statevector.trotter_evolve(psi0, hb, dims, T / steps, steps, order=4)
+        errs.append(np.linalg.norm(psi - exact))
+    assert 13.0 < errs[0] / errs[1] < 19.0 and 13.0 < errs[1] / errs[2] < 19.0
+    # and it beats the second-order step at the same dt
+    psi2 = statevector.trotter_evolve(psi0, hb, dims, T / 8, 8)
+    assert errs[1] < 0.1 * np.linalg.norm(psi2 - exact)
+
+
+def test_fourth_order_tebd_equals_its_state_vector_circuit():
+    n, dt, steps = 8, 0.1, 4
+    dims, hb = models.tfim(n, 1.0, 1.0)
+    gates = {}
+
+    def gfn(b, tau):
+        if (b, tau) not in gates:
+            gates[(b, tau)] = models.gate(hb[b], tau)
+        return gates[(b, tau)]
+    drv = mps.TEBD(mps.basis_product_state(dims, [0] * n), gfn, dt, 32, 0.0, method="full",
+                   order=4)
+    for _ in range(steps):
+        drv.step()
+    psi_sv = statevector.trotter_evolve(statevector.product_vector(dims, [0] * n), hb, dims, dt,
+                                        steps, order=4)
+    psi = mps.to_statevector(drv.mps)
+    ov = abs(np.vdot(psi_sv, psi)) / (np.linalg.norm(psi_sv) * np.linalg.norm(psi))
+    assert abs(1 - ov) < 1e-12
+    assert drv.sweeps_done == 15 * steps
+
+
 def test_full_hamiltonian_is_sum_of_bond_terms():
     # on-site split sums to one per site: compare with the chain H built directly
     n = 5
