@@ -320,7 +320,7 @@ tebd_status tebd_profile_read(int32_t capacity, const char** names, double* ms, 
  * QR classes: 0 k_qr_reg<512, 8, *>, 1 k_qr_reg<1024, 12, *>, 2 k_qr_lds,
  * 3 k_qr_glb; small-SVD classes: 0 k_svd_pairs<256, 0>, 1 k_svd_pairs<512, 1>,
  * 2 k_small_svd<1024, 2, true>, 3 k_small_svd<1024, 4, false>.  Returns -1
- * for sizes outside [1, 4096] x [1, 256] or an unknown factorization. */
+ * for sizes outside [1, 8192] x [1, 256] or an unknown factorization. */
 int32_t tebd_size_class(int32_t factorization, int32_t rows, int32_t l);
 
 #ifdef __cplusplus

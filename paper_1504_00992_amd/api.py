@@ -206,7 +206,11 @@ class TEBD:
     """
 
     def __init__(self, mps, bond_hams, dt, chi_max, p=10, q=2, trunc_eps=1e-10, seed=1504,
-                 lambda_floor=1e-14, precision=0, adaptive=0, order=2):
+                 lambda_floor=1e-14, precision=0, adaptive=0, order=2, generators=None):
+        """bond_hams: two-site Hamiltonians (gates exp(-i tau h_b)); or, for a
+        density matrix held as an MPO over the operator space (Sec. II, mixed
+        states; models.liouville_generators), generators: the bond
+        generators L_b (gates exp(tau L_b)) and bond_hams unused."""
         self.mps = mps
         self.dt = dt
         dev = mps.gamma.device
@@ -214,8 +218,11 @@ class TEBD:
         stacks = {}
         for parity, frac in trotter_schedule(order):
             if frac not in stacks:
-                stacks[frac] = torch.from_numpy(
-                    models.gate_stack(mps.dims, bond_hams, frac * dt)).to(dev)
+                if generators is not None:
+                    g = models.generator_gate_stack(mps.dims, generators, frac * dt)
+                else:
+                    g = models.gate_stack(mps.dims, bond_hams, frac * dt)
+                stacks[frac] = torch.from_numpy(g).to(dev)
             self.schedule.append((parity, stacks[frac]))
         self.g_half = stacks[0.5] if 0.5 in stacks else None
         self.g_full = stacks[1.0] if 1.0 in stacks else None

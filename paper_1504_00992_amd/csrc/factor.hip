@@ -833,14 +833,19 @@ __global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_
 // Class 3, everything larger, runs on global memory (L2-resident) with
 // 1024 threads, qr_core's column ownership, and each column held in
 // registers between its dot product and its update.
+// The two reflector buffers live in LDS up to kGlbLdsRows rows (147 KiB)
+// and in the problem's slab beyond.
+constexpr int kGlbLdsRows = 4608;
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_r, int pivot) {
-  extern __shared__ zt u_s[];  // 2 * rows
+  extern __shared__ zt u_lds[];  // 2 * min(rows, kGlbLdsRows)
   __shared__ zt rdiag[kMaxL];
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
   if (l == 0 || qr_class(rows, P.l1) != 3) return;
+  zt* u_s = rows <= kGlbLdsRows ? u_lds : P.qru;
   __shared__ double nrm[2 * kMaxL];
   __shared__ int sh_i[2];
   __shared__ int32_t perm_s[kMaxL];
@@ -943,7 +948,7 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pi
   static const hipError_t attr = []() {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_qr_glb<1024>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       int(2 * size_t(kMaxRows) * sizeof(zt)));
+                                       int(2 * size_t(kGlbLdsRows) * sizeof(zt)));
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_qr_lds<1024>),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -975,7 +980,8 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pi
                            t, p, w, r, v);
       },
       [](hipStream_t t, Prob* p, int w, int r, int v, int np, int rw) {
-        TEBD_LAUNCH("k_qr_glb<1024>", k_qr_glb<1024>, dim3(np), dim3(1024), 2 * size_t(rw) * sizeof(zt), t,
+        TEBD_LAUNCH("k_qr_glb<1024>", k_qr_glb<1024>, dim3(np), dim3(1024),
+                    2 * size_t(rw < kGlbLdsRows ? rw : kGlbLdsRows) * sizeof(zt), t,
                            p, w, r, v);
       }};
   // the classes between those of the smallest and the largest possible size

@@ -53,6 +53,7 @@ struct Prob {
   zt* J;         // l x l column-major: accumulated Jacobi rotations
   zt* X;         // l x l column-major: left vectors of the small SVD, sorted
   zt* W;         // l x l column-major: right rotation, sorted
+  zt* qru;       // 2 max(m, n): reflectors of the global-memory QR beyond its LDS rows
   double* sig;   // l: singular values sorted descending
   int32_t* piv;  // l: column order of the pivoted QR of B^H (B^H P = Q_B R_B)
   double* part;  // npart Frobenius partial sums
@@ -224,6 +225,7 @@ __host__ __device__ inline size_t slab_bytes(int64_t m, int64_t n, int64_t l, in
   b += align256(m * l * z);          // Y
   b += align256(n * l * z);          // Yt
   b += 5 * align256(l * l * z);      // Rb, C, J, X, W
+  b += align256(2 * (m > n ? m : n) * z);  // reflector staging of the global-memory QR
   b += align256(l * sizeof(double)); // sig
   b += align256(l * sizeof(int32_t));  // piv
   b += align256(npart * sizeof(double));
@@ -260,6 +262,8 @@ __host__ __device__ inline void carve_slab(Prob& p, char* base, int64_t m, int64
   c += align256(l * l * z);
   p.W = reinterpret_cast<zt*>(c);
   c += align256(l * l * z);
+  p.qru = reinterpret_cast<zt*>(c);
+  c += align256(2 * (m > n ? m : n) * z);
   p.sig = reinterpret_cast<double*>(c);
   c += align256(l * sizeof(double));
   p.piv = reinterpret_cast<int32_t*>(c);
@@ -386,6 +390,6 @@ hipError_t launch_adjoint(AdjProb* probs, const AdjCommon& c, const tebd_mps& mp
 
 // Largest l (sketch width) and m supported by the factorisation kernels.
 constexpr int kMaxL = 256;
-constexpr int kMaxRows = 4096;
+constexpr int kMaxRows = 8192;
 
 }  // namespace tebd

@@ -84,3 +84,51 @@ def gate_stack(dims, bond_hams, tau):
         k = g.shape[0]
         out[b, :k, :k] = g
     return out
+
+
+# ---------------------------------------------------------------------------
+# Mixed states (Sec. II): the density matrix as an MPO, i.e. an MPS over the
+# local operator space of dimension d^2 with local index i * d + j for
+# |i><j|.  A bond's gate is exp(tau L_b) with the two-site Lindblad generator
+# L_b(rho) = -i [h_b, rho] + sum_c (c rho c^+ - {c^+ c, rho} / 2), each
+# site's jump operators shared between its bonds like its on-site terms.
+
+def _lindblad_matrix(h, jumps):
+    """Generator on the row-major vec(rho) of the two-site density matrix:
+    A rho B -> (A kron B^T) vec(rho)."""
+    D = h.shape[0]
+    eye = np.eye(D, dtype=np.complex128)
+    out = -1j * (np.kron(h, eye) - np.kron(eye, h.T))
+    for c in jumps:
+        cdc = c.conj().T @ c
+        out = out + np.kron(c, c.conj()) - 0.5 * (np.kron(cdc, eye) + np.kron(eye, cdc.T))
+    return out
+
+
+def liouville_generators(dims, bond_hams, site_jumps):
+    """Bond generators in the two-site MPO index (i_l d_l + j_l) d_r^2 +
+    (i_r d_r + j_r); site_jumps[k]: jump operators (d_k x d_k) of site k."""
+    n = len(dims)
+    gens = []
+    for b in range(n - 1):
+        dl, dr = dims[b], dims[b + 1]
+        jumps = [np.sqrt(_split(b, n)) * np.kron(c, np.eye(dr)) for c in site_jumps[b]]
+        jumps += [np.sqrt(_split(b + 1, n)) * np.kron(np.eye(dl), c) for c in site_jumps[b + 1]]
+        g = _lindblad_matrix(np.asarray(bond_hams[b], dtype=np.complex128), jumps)
+        # (i_l, i_r, j_l, j_r) x (k_l, k_r, l_l, l_r) -> (i_l, j_l, i_r, j_r) x (k_l, l_l, k_r, l_r)
+        g = g.reshape(dl, dr, dl, dr, dl, dr, dl, dr).transpose(0, 2, 1, 3, 4, 6, 5, 7)
+        gens.append(np.ascontiguousarray(g.reshape(dl * dl * dr * dr, -1)))
+    return gens
+
+
+def generator_gate_stack(local_dims, generators, tau):
+    """exp(tau L_b) of every bond (torch's matrix exponential on the host),
+    padded to (N-1, D_max^2, D_max^2) with D the local (operator) dims."""
+    import torch
+    dmax = max(local_dims)
+    out = np.zeros((len(generators), dmax * dmax, dmax * dmax), dtype=np.complex128)
+    for b, g in enumerate(generators):
+        e = torch.linalg.matrix_exp(torch.from_numpy(tau * np.asarray(g, dtype=np.complex128)))
+        k = e.shape[0]
+        out[b, :k, :k] = e.numpy()
+    return out

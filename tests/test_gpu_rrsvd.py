@@ -177,3 +177,17 @@ def test_batched_workload_full_size_sampled():
         assert np.all(S[i][:64] <= s_true + 1e-12)
         assert np.max(np.abs(S[i][:12] - s_true[:12])) < 1e-10
         assert np.max(np.abs(S[i][:64] - s_true)) < 1e-2
+
+
+@pytest.mark.parametrize("n", [900, 4900])
+def test_table_two_shapes_match_oracle(n):
+    # The mixed-state Theta shapes of the paper's timing table (d^2 chi with
+    # chi = 100: 900 ... 4900) at k = p = 100, q = 2 (l = 200).  n = 4900
+    # runs the global-memory QR with its reflectors in the slab (rows beyond
+    # the LDS budget).  Rank-300 known spectrum s_i = exp(-i/30).
+    from paper_1504_00992_amd import _lib
+    assert _lib.tebd_size_class(0, n, 200) == 3
+    gen = wl.rng(n + 3)
+    a = wl.known_spectrum(n, n, np.exp(-np.arange(300) / 30.0), gen)
+    res = _gpu([a], 100, 100, 2, 1e-10)
+    _compare([a], res, 100, 100, 2, 1e-10)
