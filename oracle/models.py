@@ -100,3 +100,16 @@ def full_hamiltonian(dims, bond_hams):
         right = int(np.prod(dims[b + 2:]))
         H += np.kron(np.kron(np.eye(left), hb), np.eye(right))
     return H
+
+
+def spin_boson_chain_general(dims, omega0, t0, omegas, hops):
+    """Eq. (H_1D) with site-dependent frequencies omegas[k] and hoppings
+    hops[k] (between oscillators k and k+1, 0-based over the oscillators)
+    and oscillator truncations dims[1:] (TEDOPA chains, Sec. III)."""
+    n = len(dims)
+    bs = [boson_annihilation(d) for d in dims[1:]]
+    ons = [0.5 * omega0 * Z] + [omegas[k] * (b.conj().T @ b) for k, b in enumerate(bs)]
+    two = [t0 * np.kron(X, bs[0] + bs[0].conj().T)]
+    for k in range(n - 2):
+        two.append(hops[k] * (np.kron(bs[k].conj().T, bs[k + 1]) + np.kron(bs[k], bs[k + 1].conj().T)))
+    return list(dims), bond_hamiltonians(list(dims), two, ons)

@@ -132,3 +132,18 @@ def generator_gate_stack(local_dims, generators, tau):
         k = e.shape[0]
         out[b, :k, :k] = e.numpy()
     return out
+
+
+def spin_boson_tedopa(dims, t0, omegas, hops, omega0=1.0):
+    """Eq. (H_1D) with site-dependent chain coefficients (from
+    tedopa.chain_coefficients) and oscillator truncations dims[1:]:
+    (omega0/2) sigma_z + t0 sigma_x (b_1 + b_1^dag) + sum_n omega_n b_n^dag b_n
+    + sum_n t_n (b_n^dag b_{n+1} + h.c.)."""
+    n = len(dims)
+    ops = [lowering(d) for d in dims[1:]]
+    site = [0.5 * omega0 * PAULI_Z] + [omegas[k] * b.conj().T @ b for k, b in enumerate(ops)]
+    pair = [t0 * np.kron(PAULI_X, ops[0] + ops[0].conj().T)]
+    for k in range(n - 2):
+        bl, br = ops[k], ops[k + 1]
+        pair.append(hops[k] * (np.kron(bl.conj().T, br) + np.kron(bl, br.conj().T)))
+    return list(dims), _assemble(list(dims), pair, site)

@@ -439,3 +439,46 @@ def test_mixed_state_mpo_tebd_matches_oracle():
         assert abs(zg - zo) < 1e-10
         for i in range(1, n):
             assert abs(mixed.trace_expectation(gm, num, i) - mixed.trace_expectation(ref.mps, num, i)) < 1e-10
+
+
+def test_tedopa_chain_matches_oracle():
+    # A TEDOPA chain (Sec. III): Ohmic bath J = 2 pi alpha omega_c omega /
+    # omega_c, alpha = 0.1, omega_c = 2, mapped to 11 oscillators with
+    # truncations falling from 6 to 3 levels along the chain.  The package
+    # maps the bath by Lanczos, the oracle by the Stieltjes procedure (they
+    # agree to ~1e-13); the runs must agree in bond dimensions, lambda and
+    # <sigma_z>, <n_i> to 1e-10.
+    from paper_1504_00992_amd import api, models as pm, tedopa as pt
+    from oracle import tedopa as ot
+    dims = [2, 6, 6, 5, 5, 4, 4, 4, 3, 3, 3, 3]
+    n, dt, steps, chi_max = len(dims), 0.1, 8, 24
+    t0, om_, hop = pt.chain_coefficients(pt.ohmic(0.1, 1.0, 2.0), 2.0, n - 1)
+    _, hb = pm.spin_boson_tedopa(dims, t0, om_, hop)
+    dev = api.DeviceMPS.product_state(2, dims, [0] * n, chi_max)
+    drv = api.TEBD(dev, hb, dt, chi_max, p=10, q=2, trunc_eps=1e-10, seed=SEED, adaptive=1)
+    for _ in range(steps):
+        drv.step()
+    torch.cuda.synchronize()
+    ot0, oom, ohop = ot.chain_coefficients(ot.ohmic(0.1, 1.0, 2.0), 2.0, n - 1)
+    _, ohb = om.spin_boson_chain_general(dims, 1.0, ot0, oom, ohop)
+    gates = {}
+
+    def gfn(b, tau):
+        if (b, tau) not in gates:
+            gates[(b, tau)] = om.gate(ohb[b], tau)
+        return gates[(b, tau)]
+    for chain in (0, 1):
+        ref = omps.TEBD(omps.basis_product_state(dims, [0] * n), gfn, dt, chi_max, 1e-10,
+                        method="rrsvd_adaptive", p=10, q=2, seed=SEED, chain=chain)
+        for _ in range(steps):
+            ref.step()
+        gam, lam = dev.to_host(chain)
+        gm = omps.MPS(gam, lam)
+        assert gm.chis() == ref.mps.chis()
+        assert max(gm.chis()) > 3
+        for b in range(n - 1):
+            assert np.max(np.abs(lam[b] - ref.mps.lambdas[b])) < 1e-10
+        assert abs(omps.expectation(gm, om.Z, 0).real - omps.expectation(ref.mps, om.Z, 0).real) < 1e-10
+        for i in range(1, n):
+            num = np.diag(np.arange(dims[i])).astype(np.complex128)
+            assert abs(omps.expectation(gm, num, i).real - omps.expectation(ref.mps, num, i).real) < 1e-10
