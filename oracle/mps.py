@@ -120,6 +120,10 @@ def bond_update(mps, b, gate, chi_max, eps, method="full", omega=None, q=2,
     method "rrsvd_adaptive": two-stage adaptive rank; `omega` is then a
     function l -> n x l test matrix, the first-stage rank follows the bond
     dimension before the update (rrsvd.first_stage_rank).
+    method "rrsvd_accuracy": the Accuracy Check of Sec. IV (Alg. 2) from
+    k0 = the bond dimension before the update, probes of r = p columns;
+    `omega` is then a function (c0, w) -> columns c0 .. c0 + w - 1 of the
+    bond's Gaussian stream.
     Returns a dict with chi', discarded weight w, status bits, and the
     singular values before renormalisation.
     """
@@ -134,6 +138,10 @@ def bond_update(mps, b, gate, chi_max, eps, method="full", omega=None, q=2,
     elif method == "rrsvd_adaptive":
         k1 = rr.first_stage_rank(len(mps.lambdas[b]), chi_max)
         u, s, vh, chi, w, status, stage = rr.truncate_rrsvd_adaptive(a, omega, q, chi_max, eps, k1, p)
+    elif method == "rrsvd_accuracy":
+        # start from the bond dimension before the update; probes of p columns
+        u, s, vh, chi, w, status, rounds = rr.truncate_rrsvd_accuracy(
+            a, omega, q, chi_max, eps, len(mps.lambdas[b]), p, p)
     else:
         raise ValueError(method)
     norm = np.sqrt(np.sum(s ** 2))
@@ -218,6 +226,11 @@ class TEBD:
 
                 def omega(l, ncol=ncol, pid=pid, sweep_id=sweep_id):
                     return gaussian_omega(ncol, l, self.seed, pid, sweep_id)
+            elif self.method == "rrsvd_accuracy":
+                sweep_id = self.sweeps_done
+
+                def omega(c0, w, ncol=ncol, pid=pid, sweep_id=sweep_id):
+                    return gaussian_omega(ncol, c0 + w, self.seed, pid, sweep_id)[:, c0:]
             info = bond_update(self.mps, b, self.gate_fn(b, tau), self.chi_max, self.eps,
                                self.method, omega, self.q, self.lambda_floor, self.p)
             info["bond"] = b

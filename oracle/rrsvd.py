@@ -215,3 +215,99 @@ def truncate_rrsvd(a, omega, q, chi_max, eps):
     frob2 = float(np.vdot(a, a).real)
     chi, w, status = truncation_rank(frobenius_weights(s, frob2), chi_max, eps)
     return u[:, :chi], s[:chi], vh[:chi, :], chi, w, status
+
+
+# ---------------------------------------------------------------------------
+# Accuracy Check (Sec. IV, Theorem 2, Alg. 2, Fact 1).
+#
+# Theorem 2: for M = (I - QQ^H) A and r standard Gaussian vectors w_i,
+#   P( ||M|| <= 10 sqrt(2/pi) max_i ||M w_i|| ) >= 1 - 10^-r.
+# Fact 1: if sigma_j <= sigma_1 / j then ||A||_F <= (pi / sqrt 6) ||A||.
+# Together (the paper's combination, with the larger of its two printed
+# constants, (10/3) pi >= 10 sqrt(pi/3)) the Frobenius residual is bounded
+# by ACC_CONST max_i ||M w_i|| with probability 1 - 10^-r.
+
+THEOREM2_CONST = 10.0 * np.sqrt(2.0 / np.pi)
+FACT1_CONST = np.pi / np.sqrt(6.0)
+ACC_CONST = 10.0 * np.pi / 3.0
+
+
+def probe_residual(a, qmat, omega_r):
+    """max_i ||(I - QQ^H) A w_i|| over the columns w_i of omega_r (and B = A Omega_r)."""
+    b = np.asarray(a, dtype=np.complex128) @ omega_r
+    d = b - qmat @ (qmat.conj().T @ b)
+    return float(np.max(np.linalg.norm(d, axis=0))), b
+
+
+def accuracy_check(a, qmat, r, tol, probe_of, l_cap, col0):
+    """Alg. 2: grow the basis Q by blocks of r Gaussian probes.
+
+    Each round draws Omega_r (n x r, columns col0, col0 + 1, ... of the test
+    stream: probe_of(c0, r)), forms B = A Omega_r and D = (I - QQ^H) B and
+    MAX = max_i ||d_i||.  When MAX > tol, Q becomes the Q factor of [Q | B]
+    (l grows by r).  The loop repeats while MAX > tol and l <= n - r.  The
+    basis never passes the capacity l_cap (a workspace bound, not in the
+    paper): a block that would is cut to the columns that still fit, and
+    when none fits the loop stops (returned as capped).  Returns (Q, rounds,
+    capped, history of MAX).
+    """
+    a = np.asarray(a, dtype=np.complex128)
+    n = a.shape[1]
+    l = qmat.shape[1]
+    rounds = 0
+    capped = False
+    hist = []
+    c0 = col0
+    while True:
+        mx, b = probe_residual(a, qmat, probe_of(c0, r))
+        c0 += r
+        hist.append(mx)
+        if mx > tol:
+            w = min(r, l_cap - l)  # the last block fills the capacity
+            if w <= 0:
+                capped = True
+                break
+            qmat = orthonormal_basis(np.hstack([qmat, b[:, :w]]))
+            l += w
+            rounds += 1
+        if not (mx > tol and l <= n - r):
+            break
+    return qmat, rounds, capped, hist
+
+
+def rrsvd_accuracy(a, probe_of, q, k0, p, r, eps, l_cap):
+    """RRSVD with the Accuracy Check, step by step.
+
+    Alg. 1's first three steps with l0 = min(k0 + p, m, n) columns (Y0 =
+    A Omega, the rank-revealing QR), then Alg. 2 with probes of r columns
+    and tol = sqrt(eps) ||A||_F / ACC_CONST (eps: the relative discarded
+    weight, so the Frobenius residual is sqrt(eps) ||A||_F), then the q power
+    iterations of Alg. 1 on the grown basis and steps i-iii.  probe_of(c0, w)
+    returns columns c0 .. c0 + w - 1 of the Gaussian stream (the first l0
+    are Omega).  Returns (U, s, Vh, rounds, capped).
+    """
+    a = np.asarray(a, dtype=np.complex128)
+    m, n = a.shape
+    l0 = sketch_width(k0, p, m, n)
+    qmat = range_basis(a @ probe_of(0, l0))
+    frob = float(np.sqrt(np.vdot(a, a).real))
+    tol = np.sqrt(max(eps, 0.0)) * frob / ACC_CONST
+    qmat, rounds, capped, _ = accuracy_check(a, qmat, r, tol, probe_of, min(l_cap, m, n), l0)
+    for _ in range(q):
+        qt = orthonormal_basis(a.conj().T @ qmat)
+        qmat = orthonormal_basis(a @ qt)
+    b = qmat.conj().T @ a
+    ut, s, vh = lapack_svd(b)
+    return qmat @ ut, s, vh, rounds, capped
+
+
+def truncate_rrsvd_accuracy(a, probe_of, q, chi_max, eps, k0, p, r):
+    """``rrsvd_accuracy`` (capacity chi_max + p) and the truncation rule.
+
+    Returns (U[:, :chi'], s[:chi'], Vh[:chi', :], chi', w, status, rounds).
+    """
+    a = np.asarray(a, dtype=np.complex128)
+    u, s, vh, rounds, capped = rrsvd_accuracy(a, probe_of, q, k0, p, r, eps, chi_max + p)
+    frob2 = float(np.vdot(a, a).real)
+    chi, w, status = truncation_rank(frobenius_weights(s, frob2), chi_max, eps)
+    return u[:, :chi], s[:chi], vh[:chi, :], chi, w, status, rounds
