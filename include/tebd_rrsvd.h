@@ -72,7 +72,10 @@ enum {
   TEBD_DEV_CHI_BOUND = 16,    /* chi_max (or l) binds before w <= trunc_eps  */
   TEBD_DEV_BAD_STATE = 32,    /* chi or d on the device out of range: the
                                  problem was skipped, the MPS left as it was */
-  TEBD_DEV_RANK_RETRY = 64    /* adaptive rank: stage 2 was needed (info)    */
+  TEBD_DEV_RANK_RETRY = 64,   /* adaptive rank: stage 2 was needed (info)    */
+  TEBD_DEV_ACC_CAPPED = 128   /* Accuracy Check: the basis reached its
+                                 capacity min(chi_max + p, m, n) before the
+                                 probes met the tolerance                    */
 };
 
 typedef struct {
@@ -104,7 +107,23 @@ typedef struct {
                            how many bonds need stage 2 and skips that pass
                            when none does: the call then waits for the
                            stream once per sweep and cannot be captured in
-                           a graph                                            */
+                           a graph.
+                           3 (TEBD entry points only, trunc_eps > 0): the
+                           Accuracy Check of Sec. IV (Theorem 2, Alg. 2,
+                           Fact 1).  The sketch starts with l = min(chi + p,
+                           m, n) columns (chi: the bond dimension before the
+                           update); after the first QR, blocks of
+                           r = min(p, 16) Gaussian probes (the next columns
+                           of the bond's test stream) estimate the range
+                           error, max_i ||(I - QQ^H) A w_i||, against
+                           sqrt(trunc_eps) ||A||_F / ((10/3) pi); while it is
+                           larger the basis takes the probe products
+                           A w_i (QR of [Q | A Omega_r]), up to
+                           min(chi_max + p, m, n) columns (then
+                           TEBD_DEV_ACC_CAPPED) and while l <= n - r; then
+                           the power iterations and the truncation (chi' <=
+                           chi_max).  The host waits for the stream once per
+                           probe round                                        */
 } tebd_params;
 
 /* Fixed-capacity batch of MPS chains in Vidal form (Sec. II.A, Eq. defmps).

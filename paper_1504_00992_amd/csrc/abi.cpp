@@ -49,8 +49,10 @@ tebd_status check_params(const tebd_params* prm) {
     return fail(TEBD_ERR_ARG, "prm->trunc_eps must be finite");
   if (!(prm->lambda_floor >= 0.0) || !std::isfinite(prm->lambda_floor))
     return fail(TEBD_ERR_ARG, "prm->lambda_floor must be finite and >= 0");
-  if (prm->adaptive < 0 || prm->adaptive > 2)
-    return fail(TEBD_ERR_ARG, "prm->adaptive = %d must be 0, 1 or 2", prm->adaptive);
+  if (prm->adaptive < 0 || prm->adaptive > 3)
+    return fail(TEBD_ERR_ARG, "prm->adaptive = %d must be 0, 1, 2 or 3", prm->adaptive);
+  if (prm->adaptive == 3 && prm->p < 1)
+    return fail(TEBD_ERR_ARG, "prm->adaptive = 3 (Accuracy Check) needs prm->p >= 1");
   if (prm->adaptive && !(prm->trunc_eps > 0.0))
     return fail(TEBD_ERR_ARG, "prm->adaptive = %d needs prm->trunc_eps > 0", prm->adaptive);
   return TEBD_OK;
@@ -91,7 +93,7 @@ int sketch_l(int64_t k, int64_t p, int64_t m, int64_t n) {
 // one capacity-sized slab per problem.
 struct SweepPlan {
   int64_t pmax;
-  int64_t mcap, lcap, npart;
+  int64_t mcap, lcap, lslab, npart;
   size_t desc_bytes, slab_sz;
   // reverse mode of a sweep (same workspace)
   int64_t nchunk;
@@ -107,10 +109,13 @@ SweepPlan plan_sweep(const tebd_mps& mps, const tebd_params& prm) {
   s.pmax = int64_t(mps.n_chains) * nb;
   s.mcap = int64_t(mps.d_max) * mps.chi_max;
   s.lcap = sketch_l(prm.chi_max, prm.p, s.mcap, s.mcap);
+  // the Accuracy Check writes a probe block of up to p columns after the basis
+  const int64_t lslab = prm.adaptive == 3 ? s.lcap + prm.p : s.lcap;
   s.npart = gate_tiles(mps.d_max * mps.d_max, mps.chi_max * mps.chi_max);
   // descriptors, tile-queue offsets, then 256 bytes of counters
   s.desc_bytes = align256(size_t(s.pmax) * sizeof(Prob)) + align256(sched_bytes(s.pmax)) + 256;
-  s.slab_sz = slab_bytes(s.mcap, s.mcap, s.lcap, 1, prm.precision, s.npart);
+  s.lslab = lslab;
+  s.slab_sz = slab_bytes(s.mcap, s.mcap, lslab, 1, prm.precision, s.npart);
   const int64_t cap = mps.chi_max, d2 = int64_t(mps.d_max) * mps.d_max;
   s.nchunk = (cap * cap + kGateChunk - 1) / kGateChunk;
   s.adj_desc_bytes = align256(size_t(s.pmax) * sizeof(AdjProb)) +
@@ -206,12 +211,12 @@ hipError_t read_counter(const int32_t* dev, int32_t* out, hipStream_t s) {
 enum ProfKind {
   PK_PLAN, PK_SCHEDULE, PK_THETA_GATE, PK_FROB, PK_OMEGA, PK_SKETCH_AOM, PK_SKETCH_AHQ,
   PK_SKETCH_AQT, PK_QR, PK_QR_R, PK_SMALL_SVD, PK_TRUNCATE, PK_FORM_UV, PK_STAGE2, PK_TAPE,
-  PK_ADJOINT, PK_COUNT
+  PK_ADJOINT, PK_ACC, PK_COUNT
 };
 const char* const kProfNames[PK_COUNT] = {
     "plan_sweep", "schedule",  "theta_gate", "frobenius",  "omega",    "sketch_A_Omega",
     "sketch_AH_Q", "sketch_A_Qt", "qr",       "qr_with_r", "small_svd", "truncate",
-    "form_u_vh", "stage2_prep", "tape", "adjoint_sweep"};
+    "form_u_vh", "stage2_prep", "tape", "adjoint_sweep", "accuracy_check"};
 
 struct Profiler {
   std::mutex mu;
@@ -357,6 +362,29 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
   // the first QR reveals the sketch's rank (column pivoting); the power
   // iterations keep that rank and orthonormalise without pivoting
   TIMED(PK_QR, launch_qr(probs, c, 0, 0, 1, s));
+  if (c.acc_count) {
+    // Accuracy Check rounds: probe, decide, orthonormalise the grown bases;
+    // the host reads how many problems still probe after each round
+    Common ca = c;
+    // a grown basis may reach a larger QR class: up to the capacity
+    ca.lmax = std::min(c.acc_lcap, std::min(c.mmax, c.nmax));
+    ca.lmin = 1;
+    for (int round = 0;; ++round) {
+      TIMED(PK_ACC, launch_acc_probe(probs, ca, s));
+      TIMED(PK_ACC, launch_acc_resid(probs, ca, round, s));
+      TIMED(PK_QR, launch_qr(probs, ca, 0, 0, 0, s, 1));
+      int32_t active = 0;
+      TRY(read_counter(c.acc_count + (round & 1), &active, s));
+      if (active == 0) break;
+    }
+    // the sketch widths changed: tile counts anew, QR classes up to the capacity
+    c.lmax = ca.lmax;
+    c.lmin = 1;
+    for (int k = 0; k < TK_COUNT; ++k) c.ktiles[k] = -1;
+    Common cr = c;
+    cr.bounds_dev = nullptr;
+    TIMED(PK_SCHEDULE, launch_schedule(probs, cr, s));
+  }
   for (int j = 0; j < c.q; ++j) {
     TIMED(PK_SKETCH_AHQ, sketch(SK_YT_FROM_Y));
     TIMED(PK_QR, launch_qr(probs, c, 1, 0, 0, s));
@@ -426,16 +454,21 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
     return launch_plan_sweep(probs, c, *mps, reinterpret_cast<const zt*>(gates), gate_chain_stride,
                              parity, single_chain, single_bond, prm->p, slabs, pl.slab_sz, disc,
                              status, prm->lambda_floor, prm->precision, prm->adaptive,
-                             reinterpret_cast<char*>(tape), pl.tape_slot, c.retry_count, s);
+                             reinterpret_cast<char*>(tape), pl.tape_slot, c.retry_count,
+                             pl.lslab, s);
   });
   // The host-synchronising adaptive mode also reads the batch's size bounds
   // and tile totals.  Until they arrive, the grids of the first contractions
   // follow the totals of the previous sweep of this parity on this host
   // thread, with a quarter of headroom: any grid covers every tile (the
   // launches are persistent), so the estimate only affects speed.
-  static thread_local int32_t last_tiles[2][TK_COUNT] = {{-1, -1, -1, -1, -1, -1, -1, -1},
-                                                         {-1, -1, -1, -1, -1, -1, -1, -1}};
-  if (c.adaptive == 2) {
+  static thread_local int32_t last_tiles[2][TK_COUNT] = {{-1, -1, -1, -1, -1, -1, -1, -1, -1},
+                                                         {-1, -1, -1, -1, -1, -1, -1, -1, -1}};
+  if (c.adaptive == 3) {
+    c.acc_count = c.retry_count + kAccCountSlot;
+    c.acc_lcap = int32_t(pl.lcap);
+  }
+  if (c.adaptive == 2 || c.adaptive == 3) {
     c.bounds_dev = c.retry_count + 4;
     for (int k = 0; k < TK_COUNT; ++k) {
       const int32_t t = last_tiles[parity & 1][k];
@@ -452,7 +485,7 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
     c.bounds_dev = nullptr;
     for (int k = 0; k < TK_COUNT; ++k) c.ktiles[k] = -1;  // the second pass schedules anew
   }
-  bool second = c.adaptive != 0;
+  bool second = c.adaptive == 1 || c.adaptive == 2;
   if (e == hipSuccess && c.adaptive == 2) {
     // read the number of rejected first stages back and skip an empty pass
     int32_t n_retry = 0;

@@ -56,7 +56,7 @@ struct TileKinds<Prob> {
   static constexpr int count = TK_COUNT;
   static constexpr bool small_tiles(int kind) {
     return kind == TK_SKM || kind == TK_SKN || kind == TK_FORMU || kind == TK_FORMV ||
-           kind == TK_THETA;
+           kind == TK_THETA || kind == TK_ACB;
   }
   static constexpr int tile_m(int kind) {
     return kind == TK_GATE ? kGateTileM : small_tiles(kind) ? kSketchTileM : 64;
@@ -108,6 +108,12 @@ struct TileKinds<Prob> {
           N = P.n;
         }
         break;
+      case TK_ACB:
+        if (P.ac_r > 0) {
+          M = P.m;
+          N = P.ac_r;
+        }
+        break;
       default:
         break;
     }
@@ -157,6 +163,18 @@ __device__ __forceinline__ void philox10(uint32_t x[4], uint32_t k0, uint32_t k1
   }
 }
 
+// Entry (r, c) of problem pid's Gaussian stream.
+__device__ __forceinline__ zt gauss_entry(int r, int c, int pid, uint32_t sid, uint64_t seed) {
+  uint32_t x[4] = {uint32_t(r), uint32_t(c), uint32_t(pid), sid};
+  philox10(x, uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32));
+  const double u1 = (double(x[0]) + 0.5) * 0x1p-32;
+  const double u2 = (double(x[1]) + 0.5) * 0x1p-32;
+  const double rad = sqrt(-2.0 * log(u1)) * 0.70710678118654752440;
+  double sn, cs;
+  sincos(2.0 * M_PI * u2, &sn, &cs);
+  return make_double2(rad * cs, rad * sn);
+}
+
 __global__ __launch_bounds__(256) void k_omega(Prob* probs, const int32_t* offs, int nprob,
                                                int tebd, uint64_t seed, uint32_t sid) {
   for_each_tile<TK_SKN>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
@@ -166,16 +184,39 @@ __global__ __launch_bounds__(256) void k_omega(Prob* probs, const int32_t* offs,
     for (int e = threadIdx.x; e < TM * TN; e += 256) {
       const int r = m0 + e / TN, c = n0 + e % TN;
       if (r >= M || c >= N) continue;
-      uint32_t x[4] = {uint32_t(r), uint32_t(c), uint32_t(P.pid), sid};
-      philox10(x, uint32_t(seed & 0xffffffffu), uint32_t(seed >> 32));
-      const double u1 = (double(x[0]) + 0.5) * 0x1p-32;
-      const double u2 = (double(x[1]) + 0.5) * 0x1p-32;
-      const double rad = sqrt(-2.0 * log(u1)) * 0.70710678118654752440;
-      double sn, cs;
-      sincos(2.0 * M_PI * u2, &sn, &cs);
-      om[size_t(r) * P.ldom + c] = make_double2(rad * cs, rad * sn);
+      om[size_t(r) * P.ldom + c] = gauss_entry(r, c, P.pid, sid, seed);
     }
   });
+}
+
+// --------------------------------------------------------------------------
+// Accuracy Check probes (Sec. IV, Alg. 2): B = A Omega_r with Omega_r the
+// next r columns (from ac_col) of the problem's Gaussian stream, generated
+// while the operand tile is staged; B lands in the columns of Y after the
+// current basis (Y has room for r more).
+struct LdProbeB {  // (k, c) -> Gaussian entry (k, col0 + c)
+  int col0, pid;
+  uint32_t sid;
+  uint64_t seed;
+  static constexpr bool contig_n = true;
+  __device__ zt operator()(int k, int c) const { return gauss_entry(k, col0 + c, pid, sid, seed); }
+};
+
+__global__ __launch_bounds__(256) void k_acc_probe(Prob* probs, const int32_t* offs, int nprob,
+                                                   int tebd, uint64_t seed, uint32_t sid) {
+  __shared__ zt smem[CfgSk::lds_elems];
+  for_each_tile<TK_ACB>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+    LdRowA la{P.A, P.lda};
+    LdProbeB lb{P.ac_col, P.pid, sid, seed};
+    StCol st{P.Y + size_t(P.l) * P.m, P.m};
+    zgemm_tile<CfgSk>(M, N, P.n, m0, n0, la, lb, st, smem);
+  });
+}
+
+hipError_t launch_acc_probe(Prob* probs, const Common& c, hipStream_t s) {
+  TEBD_LAUNCH("k_acc_probe", k_acc_probe, dim3(grid_for(c, TK_ACB)), dim3(256), 0, s, probs,
+              c.offs, c.nprob, c.tebd, c.seed, c.stream_id);
+  return hipGetLastError();
 }
 
 hipError_t launch_omega(Prob* probs, const Common& c, hipStream_t s) {

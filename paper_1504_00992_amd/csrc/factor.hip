@@ -22,11 +22,15 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
                              int64_t gate_chain_stride, int parity, int single_chain,
                              int single_bond, int kcap, int p_over, char* slab_base,
                              size_t slab_sz, int64_t mcap, int64_t ncap, int64_t lcap,
-                             int64_t npart_cap, double* disc, int32_t* status,
+                             int64_t lslab, int64_t npart_cap, double* disc, int32_t* status,
                              double lambda_floor, int mixed, int adaptive, char* tape,
                              size_t tape_stride, int32_t* retry_count) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p == 0 && retry_count) *retry_count = 0;
+  if (p == 0 && retry_count) {
+    *retry_count = 0;
+    retry_count[kAccCountSlot] = 0;  // the Accuracy Check's two round counters
+    retry_count[kAccCountSlot + 1] = 0;
+  }
   if (p >= nprob) return;
   const int N = mps.n_sites, cap = mps.chi_max, dmax = mps.d_max;
   const int nb = (N - 1 - parity + 1) / 2;
@@ -55,12 +59,24 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
   if (l2 > P.m) l2 = P.m;
   if (l2 > P.n) l2 = P.n;
   int k1 = kcap, l = l2;
-  if (adaptive) {  // first stage: the current bond dimension plus a margin
+  if (adaptive == 1 || adaptive == 2) {  // first stage: the current bond dimension plus a margin
     const int margin = (cm + 1) / 2 > 4 ? (cm + 1) / 2 : 4;
     k1 = cm + margin < kcap ? cm + margin : kcap;
     l = k1 + p_over;
     if (l > P.m) l = P.m;
     if (l > P.n) l = P.n;
+  }
+  P.ac_r = 0;
+  P.ac_col = 0;
+  P.ac_cap = l2;
+  P.ac_grow = 0;
+  if (adaptive == 3) {  // Accuracy Check: from the current bond dimension, probes of p columns
+    l = cm + p_over;
+    if (l > P.m) l = P.m;
+    if (l > P.n) l = P.n;
+    P.ac_r = p_over < 1 ? 1 : (p_over > kAccMaxR ? kAccMaxR : p_over);
+    P.ac_col = l;
+    l2 = l;  // no second stage
   }
   P.l = bad ? 0 : l;
   P.k1 = k1;
@@ -76,7 +92,7 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
   P.om_ext = 0;
   P.pad0 = 0;
   P.frob2 = 0.0;
-  carve_slab(P, slab_base + size_t(p) * slab_sz, mcap, ncap, lcap, 1, mixed, npart_cap);
+  carve_slab(P, slab_base + size_t(p) * slab_sz, mcap, ncap, lslab, 1, mixed, npart_cap);
   P.lda = P.n;
   P.ldom = P.l;
   P.U = nullptr;
@@ -131,14 +147,14 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
                              int32_t single_bond, int32_t p_over, char* slab_base,
                              size_t slab_sz, double* disc, int32_t* status, double lambda_floor,
                              int32_t mixed, int32_t adaptive, char* tape, size_t tape_stride,
-                             int32_t* retry_count, hipStream_t s) {
+                             int32_t* retry_count, int64_t lslab, hipStream_t s) {
   const int64_t mcap = int64_t(c.dmax) * c.chimax;
   const int64_t lcap = c.lmax;
   const int64_t npart_cap = gate_tiles(c.dmax * c.dmax, c.chimax * c.chimax);
   TEBD_LAUNCH("k_plan_sweep", k_plan_sweep, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob, mps,
                      gates, gate_chain_stride, parity, single_chain, single_bond, c.kcap, p_over,
-                     slab_base, slab_sz, mcap, mcap, lcap, npart_cap, disc, status, lambda_floor,
-                     mixed, adaptive, tape, tape_stride, retry_count);
+                     slab_base, slab_sz, mcap, mcap, lcap, lslab, npart_cap, disc, status,
+                     lambda_floor, mixed, adaptive, tape, tape_stride, retry_count);
   return hipGetLastError();
 }
 
@@ -769,13 +785,14 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
 }
 
 template <int NT, int RPL, bool PIV>
-__global__ __launch_bounds__(NT) void k_qr_reg(Prob* probs, int which, int want_r, int cls) {
+__global__ __launch_bounds__(NT) void k_qr_reg(Prob* probs, int which, int want_r, int cls,
+                                                 int grow_only) {
   __shared__ RegQrShared<RPL> sh;
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
   // class from the width the pass started with: P.l shrinks as QRs run
-  if (l == 0 || qr_class(rows, P.l1) != cls) return;
+  if (l == 0 || qr_class(rows, P.l1) != cls || (grow_only && !P.ac_grow)) return;
   zt* Yg = which ? P.Yt : P.Y;
   // l <= kMaxL, so G >= NT / kMaxL
   static_assert(NT / kMaxL >= 2, "group widths below 2 are not instantiated");
@@ -804,13 +821,14 @@ __global__ __launch_bounds__(NT) void k_qr_reg(Prob* probs, int which, int want_
 // qr_core's column ownership with 1024 threads (one wavefront per column at
 // a time), the matrix in up to 150 KiB of LDS.
 template <int NT>
-__global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_r, int pivot) {
+__global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_r, int pivot,
+                                                 int grow_only) {
   extern __shared__ zt lds[];  // rows * l matrix, then 2 * rows for u
   __shared__ zt rdiag[kMaxL];
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
-  if (l == 0 || qr_class(rows, P.l1) != 2) return;
+  if (l == 0 || qr_class(rows, P.l1) != 2 || (grow_only && !P.ac_grow)) return;
   __shared__ double nrm[2 * kMaxL];
   __shared__ int sh_i[2];
   zt* Yg = which ? P.Yt : P.Y;
@@ -838,13 +856,14 @@ __global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_
 constexpr int kGlbLdsRows = 4608;
 
 template <int NT>
-__global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_r, int pivot) {
+__global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_r, int pivot,
+                                                 int grow_only) {
   extern __shared__ zt u_lds[];  // 2 * min(rows, kGlbLdsRows)
   __shared__ zt rdiag[kMaxL];
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
-  if (l == 0 || qr_class(rows, P.l1) != 3) return;
+  if (l == 0 || qr_class(rows, P.l1) != 3 || (grow_only && !P.ac_grow)) return;
   zt* u_s = rows <= kGlbLdsRows ? u_lds : P.qru;
   __shared__ double nrm[2 * kMaxL];
   __shared__ int sh_i[2];
@@ -942,7 +961,7 @@ hipError_t fork_join(hipStream_t s, L* launches, int n, const Common& c) {
 }  // namespace
 
 hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pivot,
-                     hipStream_t s) {
+                     hipStream_t s, int grow_only) {
   const int rows_max = which ? c.nmax : c.mmax;
   const int rows_min = which ? c.nmin : c.mmin;
   static const hipError_t attr = []() {
@@ -955,40 +974,41 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pi
                                int(size_t(kLdsElems) * sizeof(zt)));
   }();
   if (attr != hipSuccess) return attr;
-  typedef void (*Launch)(hipStream_t, Prob*, int, int, int, int, int);
+  typedef void (*Launch)(hipStream_t, Prob*, int, int, int, int, int, int);
   struct Item {
     Launch fn;
     Prob* probs;
-    int which, want_r, pivot, nprob, rows;
-    void operator()(hipStream_t t) const { fn(t, probs, which, want_r, pivot, nprob, rows); }
+    int which, want_r, pivot, nprob, rows, grow;
+    void operator()(hipStream_t t) const { fn(t, probs, which, want_r, pivot, nprob, rows, grow); }
   };
   const Launch fns[4] = {
-      [](hipStream_t t, Prob* p, int w, int r, int v, int np, int) {
+      [](hipStream_t t, Prob* p, int w, int r, int v, int np, int, int g) {
         if (v)
-          TEBD_LAUNCH("k_qr_reg<512, 8, true>", (k_qr_reg<512, 8, true>), dim3(np), dim3(512), 0, t, p, w, r, 0);
+          TEBD_LAUNCH("k_qr_reg<512, 8, true>", (k_qr_reg<512, 8, true>), dim3(np), dim3(512), 0, t, p, w, r, 0, g);
         else
-          TEBD_LAUNCH("k_qr_reg<512, 8, false>", (k_qr_reg<512, 8, false>), dim3(np), dim3(512), 0, t, p, w, r, 0);
+          TEBD_LAUNCH("k_qr_reg<512, 8, false>", (k_qr_reg<512, 8, false>), dim3(np), dim3(512), 0, t, p, w, r, 0, g);
       },
-      [](hipStream_t t, Prob* p, int w, int r, int v, int np, int) {
+      [](hipStream_t t, Prob* p, int w, int r, int v, int np, int, int g) {
         if (v)
-          TEBD_LAUNCH("k_qr_reg<1024, 12, true>", (k_qr_reg<1024, 12, true>), dim3(np), dim3(1024), 0, t, p, w, r, 1);
+          TEBD_LAUNCH("k_qr_reg<1024, 12, true>", (k_qr_reg<1024, 12, true>), dim3(np), dim3(1024), 0, t, p, w, r, 1, g);
         else
-          TEBD_LAUNCH("k_qr_reg<1024, 12, false>", (k_qr_reg<1024, 12, false>), dim3(np), dim3(1024), 0, t, p, w, r, 1);
+          TEBD_LAUNCH("k_qr_reg<1024, 12, false>", (k_qr_reg<1024, 12, false>), dim3(np), dim3(1024), 0, t, p, w, r, 1, g);
       },
-      [](hipStream_t t, Prob* p, int w, int r, int v, int np, int) {
+      [](hipStream_t t, Prob* p, int w, int r, int v, int np, int, int g) {
         TEBD_LAUNCH("k_qr_lds<1024>", k_qr_lds<1024>, dim3(np), dim3(1024), size_t(kLdsElems) * sizeof(zt),
-                           t, p, w, r, v);
+                           t, p, w, r, v, g);
       },
-      [](hipStream_t t, Prob* p, int w, int r, int v, int np, int rw) {
+      [](hipStream_t t, Prob* p, int w, int r, int v, int np, int rw, int g) {
         TEBD_LAUNCH("k_qr_glb<1024>", k_qr_glb<1024>, dim3(np), dim3(1024),
                     2 * size_t(rw < kGlbLdsRows ? rw : kGlbLdsRows) * sizeof(zt), t,
-                           p, w, r, v);
+                           p, w, r, v, g);
       }};
   // the classes between those of the smallest and the largest possible size
   const int lo = qr_class(rows_min, c.lmin), hi = qr_class(rows_max, c.lmax);
   Item items[4];
   int n = 0;
-  for (int k = lo; k <= hi; ++k) items[n++] = {fns[k], probs, which, want_r, pivot, c.nprob, rows_max};
+  for (int k = lo; k <= hi; ++k)
+    items[n++] = {fns[k], probs, which, want_r, pivot, c.nprob, rows_max, grow_only};
   return fork_join(s, items, n, c);
 }
 
@@ -1461,6 +1481,108 @@ __global__ __launch_bounds__(64) void k_truncate(Prob* probs, double eps, int te
 hipError_t launch_truncate(Prob* probs, const Common& c, hipStream_t s) {
   TEBD_LAUNCH("k_truncate", k_truncate, dim3(c.nprob), dim3(64), 0, s, probs, c.eps, c.tebd,
                      c.pass2 ? nullptr : c.retry_count);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Accuracy Check (Sec. IV, Alg. 2), one workgroup per problem still probing:
+// with Q the current basis (columns 0..l-1 of Y) and B = A Omega_r in the
+// next r columns, D = B - Q (Q^H B) and MAX = max_i ||d_i||.  Theorem 2 with
+// Fact 1 bounds the Frobenius residual ||(I - QQ^H) A||_F by (10/3) pi MAX
+// (with probability 1 - 10^-r), so MAX is compared with
+// tol = sqrt(eps) ||A||_F / ((10/3) pi), eps the relative discarded weight.
+// MAX > tol: the basis takes B's first min(r, cap - l) columns (its QR runs
+// next, grow_only), or, with no room left, the check stops with
+// TEBD_DEV_ACC_CAPPED.  The check goes on while MAX > tol and l <= n - r;
+// problems still probing are counted in count[round & 1] for the host, and
+// count[(round + 1) & 1] is cleared for the next round.
+__global__ __launch_bounds__(256) void k_acc_resid(Prob* probs, double eps, int32_t* count,
+                                                   int round) {
+  Prob& P = probs[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (blockIdx.x == 0 && tid == 0) count[(round + 1) & 1] = 0;
+  const int l = P.l, r = P.ac_r;
+  if (l == 0 || r == 0) {
+    if (tid == 0) P.ac_grow = 0;
+    return;
+  }
+  const int m = P.m;
+  const zt* Q = P.Y;
+  const zt* B = P.Y + size_t(l) * m;
+  __shared__ zt cs[kMaxL * kAccMaxR];  // C = Q^H B, l x r, column j of Q in row j
+  __shared__ double part[4][kAccMaxR];
+  for (int j = tid; j < l; j += 256) {
+    double cr[kAccMaxR], ci[kAccMaxR];
+#pragma unroll
+    for (int i = 0; i < kAccMaxR; ++i) cr[i] = ci[i] = 0.0;
+    const zt* qj = Q + size_t(j) * m;
+    for (int row = 0; row < m; ++row) {
+      const zt q = qj[row];
+#pragma unroll
+      for (int i = 0; i < kAccMaxR; ++i)
+        if (i < r) zdot_acc(q, B[size_t(i) * m + row], cr[i], ci[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kAccMaxR; ++i)
+      if (i < r) cs[j * kAccMaxR + i] = make_double2(cr[i], ci[i]);
+  }
+  __syncthreads();
+  double nrm[kAccMaxR];
+#pragma unroll
+  for (int i = 0; i < kAccMaxR; ++i) nrm[i] = 0.0;
+  for (int row = tid; row < m; row += 256) {
+#pragma unroll
+    for (int i = 0; i < kAccMaxR; ++i) {
+      if (i >= r) continue;
+      zt d = B[size_t(i) * m + row];
+      for (int j = 0; j < l; ++j) d = zsub(d, zmul(Q[size_t(j) * m + row], cs[j * kAccMaxR + i]));
+      nrm[i] += zabs2(d);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kAccMaxR; ++i) {
+    const double v = wave_sum(nrm[i]);
+    if (lane == 0) part[wave][i] = v;
+  }
+  __syncthreads();
+  if (tid != 0) return;
+  double mx = 0.0;
+  bool finite = true;
+  for (int i = 0; i < r; ++i) {
+    const double v = (part[0][i] + part[1][i]) + (part[2][i] + part[3][i]);
+    finite = finite && isfinite(v);
+    mx = fmax(mx, sqrt(v));
+  }
+  double frob2 = 0.0;
+  const int npart = gate_tiles(P.dl * P.dr, P.chi_l * P.chi_r);
+  for (int i = 0; i < npart; ++i) frob2 += P.part[i];
+  const double tol = sqrt(eps) * sqrt(frob2) / kAccConst;
+  const bool grow = finite && mx > tol;
+  int lnew = l;
+  P.ac_grow = 0;
+  if (!finite) P.flags |= TEBD_DEV_NONFINITE;
+  if (grow) {
+    const int w = P.ac_cap - l < r ? P.ac_cap - l : r;
+    if (w <= 0) {
+      P.flags |= TEBD_DEV_ACC_CAPPED;
+      P.ac_r = 0;
+      return;
+    }
+    lnew = l + w;
+    P.l = lnew;
+    if (P.l1 < lnew) P.l1 = lnew;
+    P.ac_grow = 1;
+  }
+  P.ac_col += r;
+  if (grow && lnew <= P.n - r)
+    atomicAdd(count + (round & 1), 1);
+  else
+    P.ac_r = 0;
+}
+
+hipError_t launch_acc_resid(Prob* probs, const Common& c, int round, hipStream_t s) {
+  TEBD_LAUNCH("k_acc_resid", k_acc_resid, dim3(c.nprob), dim3(256), 0, s, probs, c.eps,
+              c.acc_count, round);
   return hipGetLastError();
 }
 

@@ -38,6 +38,10 @@ struct Prob {
   int32_t l2;                        // sketch width of the fixed-rank stage
   int32_t retry;                     // 1: stage 1 rejected, stage 2 pending
   int32_t pad0;
+  // Accuracy Check (adaptive rank 3): probe width (0: check finished), next
+  // probe column of the Gaussian stream, capacity of the basis, and 1 while
+  // the basis grew this round (its QR runs)
+  int32_t ac_r, ac_col, ac_cap, ac_grow;
   double frob2;                      // ||A||_F^2, written on the device
   // input matrix (row-major, leading dim lda) and test matrix (row-major n x l)
   zt* A;
@@ -108,10 +112,12 @@ struct Common {
   int32_t* retry_count;  // device: problems whose first stage was rejected (adaptive rank)
   int32_t* bounds_dev = nullptr;  // device: k_schedule writes {min, max} of m, n, l1 there,
                                   // then the tile total of every kind
-  int32_t ktiles[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
+  int32_t ktiles[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
   int32_t serial = 0;  // 1: size classes run in order on the caller's stream (no side streams)
+  int32_t* acc_count = nullptr;  // device: Accuracy Check, two counters of problems still probing
+  int32_t acc_lcap = 0;          // Accuracy Check: largest basis width (QR classes)
 };
 
 // Kernel-level event timing for tebd_profile_enable / tebd_profile_read:
@@ -138,6 +144,13 @@ void prof_kernel_done(const char* name, hipEvent_t start, hipEvent_t stop);
     }                                                                                       \
   } while (0)
 
+// Accuracy Check: widest probe block, the constant of Theorem 2 with Fact 1
+// ((10/3) pi, the larger of the paper's two printed forms), and the slot of
+// its two round counters in the workspace's counter area.
+constexpr int kAccMaxR = 16;
+constexpr double kAccConst = 10.0 * 3.14159265358979323846 / 3.0;
+constexpr int kAccCountSlot = 32;
+
 // Contraction kinds scheduled through a global tile queue: every kind has
 // its own prefix sum over problems of the number of 64 x 64 output tiles.
 enum {
@@ -149,10 +162,11 @@ enum {
   TK_FORMV = 5,  // (kept capacity) x n
   TK_TAPEU = 6,  // recording: m x l, U of every computed triplet
   TK_TAPEV = 7,  // recording: l x n, V^H of every computed triplet
-  TK_COUNT = 8
+  TK_ACB = 8,    // Accuracy Check: m x r probe products A Omega_r
+  TK_COUNT = 9
 };
 
-static_assert(TK_COUNT == 8, "Common::ktiles holds one total per kind");
+static_assert(TK_COUNT == 9, "Common::ktiles holds one total per kind");
 
 // Output tile of the gate product, (dl dr) x (chi_l chi_r): tall and narrow,
 // because the gate side has a few dozen to a few hundred rows while the bond
@@ -186,7 +200,7 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
                              int32_t single_bond, int32_t p_over, char* slab_base,
                              size_t slab_bytes, double* disc, int32_t* status, double lambda_floor,
                              int32_t mixed, int32_t adaptive, char* tape, size_t tape_stride,
-                             int32_t* retry_count, hipStream_t s);
+                             int32_t* retry_count, int64_t lslab, hipStream_t s);
 hipError_t launch_stage2(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_schedule(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s);
@@ -196,7 +210,13 @@ hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s)
 hipError_t launch_sketch_f32(Prob* probs, const Common& c, int which, hipStream_t s);
 // pivot: column pivoting with the rank tolerance (the QR of B^H pivots and
 // keeps every column); 0: plain Householder in column order, every column kept
-hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pivot, hipStream_t s);
+// grow_only: only the problems whose basis the Accuracy Check just grew.
+hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pivot, hipStream_t s,
+                     int grow_only = 0);
+// Accuracy Check round: B = A Omega_r into the columns after the basis, then
+// the probe residual, the decision and the growth of the basis.
+hipError_t launch_acc_probe(Prob* probs, const Common& c, hipStream_t s);
+hipError_t launch_acc_resid(Prob* probs, const Common& c, int round, hipStream_t s);
 hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_truncate(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_form_uv(Prob* probs, const Common& c, hipStream_t s);

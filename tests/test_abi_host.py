@@ -58,9 +58,16 @@ def test_workspace_size_and_validation():
         _ws(prm, [0], [8])
     assert e.value.status == _lib.TEBD_ERR_SHAPE
     bad = _lib.params(8, 10, 2)
-    bad.adaptive = 3
+    bad.adaptive = 4
     with pytest.raises(_lib.TebdError):
         _ws(bad, [8], [8])
+    bad = _lib.params(8, 0, 2, adaptive=3)  # the Accuracy Check probes p >= 1 columns
+    with pytest.raises(_lib.TebdError) as e:
+        _ws(bad, [8], [8])
+    assert "p >= 1" in str(e.value)
+    with pytest.raises(_lib.TebdError) as e:  # rows beyond the supported 8192
+        _ws(prm, [8193], [8])
+    assert e.value.status == _lib.TEBD_ERR_SHAPE
     with pytest.raises(_lib.TebdError) as e:
         _ws(_lib.params(8, trunc_eps=0.0, adaptive=1), [8], [8])
     assert "trunc_eps" in str(e.value)

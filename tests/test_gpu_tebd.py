@@ -482,3 +482,73 @@ def test_tedopa_chain_matches_oracle():
         for i in range(1, n):
             num = np.diag(np.arange(dims[i])).astype(np.complex128)
             assert abs(omps.expectation(gm, num, i).real - omps.expectation(ref.mps, num, i).real) < 1e-10
+
+
+@pytest.mark.parametrize("chis,decay,p,chi_max", [
+    ([1, 4, 3, 16, 1], 0.02, 3, 12),   # nearly flat: the basis grows to its capacity (capped)
+    ([1, 4, 3, 16, 1], 0.9, 3, 16),    # decaying: a few probe rounds, then the target is met
+    ([1, 4, 12, 16, 1], 3.0, 4, 16),   # fast decay: the first basis passes the check
+])
+def test_accuracy_check_bond_update_matches_oracle(chis, decay, p, chi_max):
+    # adaptive = 3: Alg. 2's probe rounds on the GPU against the oracle's
+    # step-by-step Accuracy Check with the same Gaussian stream (the first l0
+    # columns sketch, the next ones probe): bond dimension exactly, lambda to
+    # 1e-10, discarded weight to 1e-12, two-site block to 1e-10.
+    from paper_1504_00992_amd import api
+    dims = [4, 4, 4, 4]
+    bond = 1
+    gen = wl.rng(91)
+    gam = [wl.ginibre(d * chis[k], chis[k + 1], gen).reshape(d, chis[k], chis[k + 1])
+           for k, d in enumerate(dims)]
+    lam = []
+    for b in range(3):
+        v = np.exp(-decay * np.arange(chis[b + 1]))
+        lam.append(v / np.linalg.norm(v))
+    gate = wl.random_unitary(16, wl.rng(5))
+    dev = api.DeviceMPS.from_host([(gam, lam)], dims, 16)
+    prm = api._lib.params(chi_max, p, 2, 1e-10, 1e-14, SEED, 9, adaptive=3)
+    ws = api.BondWorkspace(dev, prm)
+    api.tebd_bond_update(dev, 0, bond, torch.from_numpy(gate).cuda(), prm, ws)
+    torch.cuda.synchronize()
+    ref = omps.MPS(gam, lam)
+    n_cols = dims[bond + 1] * chis[bond + 2]
+    probe = lambda c0, w: philox.gaussian_omega(n_cols, c0 + w, SEED, bond, 9)[:, c0:]
+    info = omps.bond_update(ref, bond, gate, chi_max, 1e-10, "rrsvd_accuracy", probe, 2, p=p)
+    g_gam, g_lam = dev.to_host(0)
+    st = ws.status[0, bond].item()
+    assert (st & ~128) == info["status"]
+    assert len(g_lam[bond]) == info["chi"]
+    assert np.max(np.abs(g_lam[bond] - ref.lambdas[bond])) < 1e-10
+    assert abs(ws.disc[0, bond].item() - info["w"]) < 1e-12
+    blk_g = _two_site_block(g_gam, g_lam, bond)
+    blk_o = _two_site_block(ref.gammas, ref.lambdas, bond)
+    assert np.max(np.abs(blk_g - blk_o)) < 1e-10
+    if decay == 0.02:
+        assert st & 128  # capped at min(chi_max + p, m, n)
+
+
+def test_accuracy_check_tebd_run_matches_oracle():
+    # Whole spin-boson runs (3 chains, N = 10, d = 4) with the Accuracy Check
+    # and probes of p = 2 columns (so entanglement growth triggers probe
+    # rounds) against the oracle's runs: bond dimensions, lambda, <n_i>.
+    from paper_1504_00992_amd import api, models as pm
+    n, d, dt, steps, chi_max, p = 10, 4, 0.1, 8, 16, 2
+    dims, hb = pm.spin_boson(n, d, 1.0, 0.5, 1.0, 0.5)
+    dev = api.DeviceMPS.product_state(3, dims, [0] * n, chi_max)
+    drv = api.TEBD(dev, hb, dt, chi_max, p=p, q=2, trunc_eps=1e-10, seed=SEED, adaptive=3)
+    for _ in range(steps):
+        drv.step()
+    torch.cuda.synchronize()
+    odims, ohb = om.spin_boson_chain(n, d, 1.0, 0.5, 1.0, 0.5)
+    for chain in (0, 2):
+        ref = _oracle_tebd(odims, ohb, [0] * n, dt, steps, chi_max, p, 1e-10, chain=chain,
+                           method="rrsvd_accuracy")
+        gam, lam = dev.to_host(chain)
+        gm = omps.MPS(gam, lam)
+        assert gm.chis() == ref.mps.chis()
+        assert max(gm.chis()) >= 4
+        for b in range(n - 1):
+            assert np.max(np.abs(lam[b] - ref.mps.lambdas[b])) < 1e-10
+        num = np.diag(np.arange(d)).astype(np.complex128)
+        for i in (1, 3, 6):
+            assert abs(omps.expectation(gm, num, i).real - omps.expectation(ref.mps, num, i).real) < 1e-10
