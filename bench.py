@@ -224,8 +224,22 @@ ALU_KERNELS = ("k_qr_", "k_svd_pairs", "k_small_svd", "k_truncate", "k_omega", "
                "k_plan", "k_stage2", "k_frob")
 
 
+def merge_tile_variants(prof):
+    """The two tile variants of a sketch product (k_sketch<i> on 32 x 32,
+    k_sketch_wide<i> on 64 x 64 tiles, picked per launch by the autotune
+    cache) do the same work: count them as one kernel, k_sketch<i>."""
+    out = {}
+    for k, (ms, n) in prof.items():
+        key = k.replace("k_sketch_wide<", "k_sketch<")
+        a = out.get(key, (0.0, 0))
+        out[key] = (a[0] + ms, a[1] + n)
+    return out
+
+
 def kernel_roofline(prof, work, workload):
     """Roofline entry of the kernel with the largest event time."""
+    wide = any(k.startswith("k_sketch_wide<") for k in prof)
+    prof = merge_tile_variants(prof)
     kern = {k: v for k, v in prof.items() if k.startswith("k_")}
     if not kern:
         return None
@@ -233,6 +247,9 @@ def kernel_roofline(prof, work, workload):
     ms, launches = kern[name]
     e = {"kernel": name, "launches": launches, "event_ms_total": round(ms, 3),
          "avg_launch_us": round(1e3 * ms / launches, 3) if launches else None}
+    if wide and name.startswith("k_sketch<"):
+        e["note_variants"] = ("launches of k_sketch<i> and k_sketch_wide<i> (the two tile "
+                              "variants) counted together")
     fl, by = work.k.get(name, (0.0, 0.0))
     f32 = name.startswith("k_sketch_f32")
     if fl > 0 and ms > 0:
@@ -567,7 +584,7 @@ def batched_rrsvd_line(args, torch, api, wl, lib):
     for k in ("k_form_u<1>", "k_form_vh<1>"):   # the standalone call writes plain U, V^H
         if k in w.k:
             w.k[k.replace("<1>", "<0>")] = w.k.pop(k)
-    sk_ms = sum(v[0] for k, v in prof.items() if k.startswith("k_sketch<"))
+    sk_ms = sum(v[0] for k, v in prof.items() if k.startswith(("k_sketch<", "k_sketch_wide<")))
     sk_fl = sum(v[0] for k, v in w.k.items() if k.startswith("k_sketch<"))
     ach = sk_fl / (sk_ms * 1e-3) / 1e12 if sk_ms > 0 else None
     res = {"metric": "RRSVD truncations/s", "value": round(len(sizes) * reps / sum(times), 2),
@@ -799,9 +816,19 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 256 << 20, "copies": 3}))
         return
-    from paper_1504_00992_amd import api, models, _lib
+    from paper_1504_00992_amd import api, autotune, models, _lib
     import workloads as wl
     _lib.load()
+    # tile shapes of the sketch products: the autotune cache (timed once per
+    # box, then read from its JSON file)
+    t0 = time.perf_counter()
+    tuned = autotune.load()
+    source = "cache " + autotune.cache_path()
+    if not tuned:
+        tuned = autotune.tune()
+        source = "timed now, saved to " + autotune.cache_path()
+    tune_entry = {"entries": tuned, "source": source, "seconds": round(time.perf_counter() - t0, 2)}
+    _progress(f"autotune: {[(e['rows'], e['width'], e['variant']) for e in tuned]}")
 
     adaptive = args.rank == "adaptive"
     N, steps = SB["N"], SB["steps"]
@@ -838,6 +865,7 @@ def main():
                    "status_bits_seen": sorted(set(int(x) for x in
                                                   np.unique(ev.drv.ws.status.cpu().numpy())))},
         "rep_ms": [round(1e3 * t, 3) for t in times],
+        "autotune": tune_entry,
     }
     if not args.no_profile:
         prof, hist = ev.profiled(steps, _lib)

@@ -29,7 +29,7 @@ DEV_RANK_RETRY = 64
 EXPORTED = ("tebd_last_error", "tebd_version", "tebd_workspace_size", "rrsvd_truncate",
             "tebd_bond_update", "tebd_sweep", "tebd_adjoint_workspace_size", "tebd_tape_size", "tebd_sweep_record",
             "tebd_sweep_adjoint", "tebd_profile_enable", "tebd_profile_read", "tebd_size_class",
-            "rrsvd_truncate_noalloc")
+            "rrsvd_truncate_noalloc", "tebd_tune_set", "tebd_tune_get")
 
 
 class TebdParams(ctypes.Structure):
@@ -107,6 +107,10 @@ def load():
                                       ctypes.POINTER(ctypes.c_int32)]
     lib.tebd_size_class.restype = ctypes.c_int32
     lib.tebd_size_class.argtypes = [i32, i32, i32]
+    lib.tebd_tune_set.restype = ctypes.c_int
+    lib.tebd_tune_set.argtypes = [i32, i32, i32, i32]
+    lib.tebd_tune_get.restype = ctypes.c_int32
+    lib.tebd_tune_get.argtypes = [i32, i32, i32]
     _lib = lib
     return lib
 
@@ -222,6 +226,15 @@ def tebd_sweep_adjoint(mps_in, gates_ptr, gate_chain_stride, parity, prm, tape_p
 
 def tebd_profile_enable(on):
     check(load().tebd_profile_enable(1 if on else 0))
+
+
+def tebd_tune_set(precision, max_rows, width, variant):
+    """Set one autotune-cache entry (tile variant of the sketch products)."""
+    return int(load().tebd_tune_set(int(precision), int(max_rows), int(width), int(variant)))
+
+
+def tebd_tune_get(precision, max_rows, width):
+    return int(load().tebd_tune_get(int(precision), int(max_rows), int(width)))
 
 
 def tebd_size_class(factorization, rows, l):

@@ -1,0 +1,84 @@
+"""Autotuner of the sketch products' tile shape (the library's autotune cache).
+
+For each (largest rows, sketch width) bucket of the cache, a synthetic batch
+of that shape is truncated with each tile variant of the sketch, power-
+iteration and projection products (32 x 32 or 64 x 64 output tiles), the
+products' kernel time is taken from the library's per-launch events, and
+the faster variant is stored in the library (tebd_tune_set) and in a JSON
+file, which later processes load instead of timing again.  The variants give
+identical results; only speed depends on the choice.
+"""
+import json
+import os
+
+from . import _lib
+
+ROW_BUCKETS = (128, 256, 512, 1024, 2048, 8192)
+WIDTH_BUCKETS = (32, 64, 128, 256)
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "tebd_rrsvd", "tuning.json")
+
+
+def cache_path():
+    return os.environ.get("TEBD_TUNE_CACHE", DEFAULT_CACHE)
+
+
+def load(path=None):
+    """Put the entries of a JSON cache into the library; returns them (or [])."""
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return []
+    entries = data.get("entries", [])
+    for e in entries:
+        _lib.check(_lib.tebd_tune_set(e["precision"], e["rows"], e["width"], e["variant"]))
+    return entries
+
+
+def save(entries, path=None, device=""):
+    path = path or cache_path()
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    with open(path, "w") as f:
+        json.dump({"device": device, "entries": entries}, f, indent=1)
+    return path
+
+
+def _time_variant(torch, api, mats, k, p, variant, rows, width, reps):
+    _lib.check(_lib.tebd_tune_set(0, rows, width, variant))
+    api.rrsvd_truncate(mats, k, p, 2, 1e-10, 1504, 0)      # warm-up
+    torch.cuda.synchronize()
+    _lib.tebd_profile_enable(True)
+    for r in range(reps):
+        api.rrsvd_truncate(mats, k, p, 2, 1e-10, 1504, r + 1)
+    torch.cuda.synchronize()
+    prof = _lib.tebd_profile_read()
+    _lib.tebd_profile_enable(False)
+    return sum(v[0] for name, v in prof.items() if name.startswith("k_sketch")) / reps
+
+
+def tune(buckets=((256, 64), (512, 128), (1024, 128), (2048, 128)), batch=32, reps=3,
+         path=None, seed=1504):
+    """Time both variants for each (rows, width) bucket; store and return the
+    choices.  The batch of each bucket: `batch` square complex Gaussian
+    matrices of the bucket's row count, sketch width = the bucket's width
+    (k = width - 10, p = 10)."""
+    import torch
+    from . import api
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(int(seed))
+    entries = []
+    for rows, width in buckets:
+        n = int(rows)
+        mats = [torch.randn((n, n), dtype=torch.complex128, device="cuda", generator=gen)
+                for _ in range(batch)]
+        k, p = max(1, int(width) - 10), 10
+        ms = [_time_variant(torch, api, mats, k, p, v, rows, width, reps) for v in (0, 1)]
+        best = 0 if ms[0] <= ms[1] else 1
+        _lib.check(_lib.tebd_tune_set(0, rows, width, best))
+        entries.append({"precision": 0, "rows": int(rows), "width": int(width), "variant": best,
+                        "sketch_ms": [round(x, 4) for x in ms]})
+        del mats
+    name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else ""
+    save(entries, path, name)
+    return entries

@@ -61,6 +61,7 @@ struct TileKinds<Prob> {
   static constexpr int tile_m(int kind) {
     return kind == TK_GATE ? kGateTileM : small_tiles(kind) ? kSketchTileM : 64;
   }
+  // TK_SKM_W / TK_SKN_W: the same products on 64 x 64 tiles
   static constexpr int tile_n(int kind) {
     return kind == TK_GATE ? kGateTileN : small_tiles(kind) ? kSketchTileN : 64;
   }
@@ -81,10 +82,12 @@ struct TileKinds<Prob> {
         }
         break;
       case TK_SKM:
+      case TK_SKM_W:
         M = P.m;
         N = P.l;
         break;
       case TK_SKN:
+      case TK_SKN_W:
         M = P.n;
         N = P.l;
         break;
@@ -362,7 +365,71 @@ hipError_t launch_sketch_f32(Prob* probs, const Common& c, int which, hipStream_
   return hipGetLastError();
 }
 
+// The same products on 64 x 64 tiles (fewer operand reloads for large
+// problems; chosen per launch by the autotune cache).
+template <int WHICH>
+__global__ __launch_bounds__(256) void k_sketch_wide(Prob* probs, const int32_t* offs, int nprob,
+                                                     int tebd) {
+  __shared__ zt smem[Cfg64::lds_elems];
+  if (WHICH == SK_Y_FROM_OMEGA) {
+    for_each_tile<TK_SKM_W>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdRowA la{P.A, P.lda};
+      LdRowB lb{P.om, P.ldom};
+      StCol st{P.Y, P.m};
+      zgemm_tile<Cfg64>(M, N, P.n, m0, n0, la, lb, st, smem);
+    });
+  } else if (WHICH == SK_YT_FROM_Y) {
+    for_each_tile<TK_SKN_W>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdAdjA la{P.A, P.lda};
+      LdColB lb{P.Y, P.m};
+      StCol st{P.Yt, P.n};
+      zgemm_tile<Cfg64>(M, N, P.m, m0, n0, la, lb, st, smem);
+    });
+  } else {
+    for_each_tile<TK_SKM_W>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdRowA la{P.A, P.lda};
+      LdColB lb{P.Yt, P.n};
+      StCol st{P.Y, P.m};
+      zgemm_tile<Cfg64>(M, N, P.n, m0, n0, la, lb, st, smem);
+    });
+  }
+}
+
+// Autotune cache: variant per (precision, rows bucket, width bucket); -1
+// (unset) means the 32 x 32 tiles.  Written by tebd_tune_set between calls.
+namespace {
+constexpr int kTuneRows[6] = {128, 256, 512, 1024, 2048, 8192};
+constexpr int kTuneWidth[4] = {32, 64, 128, 256};
+int8_t g_tune[2][6][4] = {};
+bool g_tune_init = false;
+
+int tune_bucket(const int* bounds, int nb, int v) {
+  for (int i = 0; i < nb; ++i)
+    if (v <= bounds[i]) return i;
+  return -1;
+}
+}  // namespace
+
+int sketch_variant(int precision, int max_rows, int width) {
+  if (precision != 0 || !g_tune_init) return 0;
+  const int br = tune_bucket(kTuneRows, 6, max_rows), bw = tune_bucket(kTuneWidth, 4, width);
+  if (br < 0 || bw < 0) return 0;
+  const int v = g_tune[0][br][bw];
+  return v < 0 ? 0 : v;
+}
+
 hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s) {
+  const int rows = c.mmax > c.nmax ? c.mmax : c.nmax;
+  if (sketch_variant(0, rows, c.lmax) == 1) {
+    const dim3 g(grid_for(c, which == SK_YT_FROM_Y ? TK_SKN_W : TK_SKM_W));
+    if (which == SK_Y_FROM_OMEGA)
+      TEBD_LAUNCH("k_sketch_wide<0>", k_sketch_wide<SK_Y_FROM_OMEGA>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+    else if (which == SK_YT_FROM_Y)
+      TEBD_LAUNCH("k_sketch_wide<1>", k_sketch_wide<SK_YT_FROM_Y>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+    else
+      TEBD_LAUNCH("k_sketch_wide<2>", k_sketch_wide<SK_Y_FROM_YT>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+    return hipGetLastError();
+  }
   const dim3 g(grid_for(c, which == SK_YT_FROM_Y ? TK_SKN : TK_SKM));
   if (which == SK_Y_FROM_OMEGA)
     TEBD_LAUNCH("k_sketch<0>", k_sketch<SK_Y_FROM_OMEGA>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
@@ -558,3 +625,29 @@ hipError_t launch_tape(Prob* probs, const Common& c, hipStream_t s) {
 }
 
 }  // namespace tebd
+
+extern "C" tebd_status tebd_tune_set(int32_t precision, int32_t max_rows, int32_t width,
+                                     int32_t variant) {
+  using namespace tebd;
+  if (precision < 0 || precision > 1 || variant < -1 || variant > 1 ||
+      (precision == 1 && variant == 1))
+    return TEBD_ERR_ARG;
+  const int br = tune_bucket(kTuneRows, 6, max_rows), bw = tune_bucket(kTuneWidth, 4, width);
+  if (max_rows < 1 || width < 1 || br < 0 || bw < 0) return TEBD_ERR_SHAPE;
+  if (!g_tune_init) {
+    for (auto& a : g_tune)
+      for (auto& b : a)
+        for (auto& v : b) v = -1;
+    g_tune_init = true;
+  }
+  g_tune[precision][br][bw] = int8_t(variant);
+  return TEBD_OK;
+}
+
+extern "C" int32_t tebd_tune_get(int32_t precision, int32_t max_rows, int32_t width) {
+  using namespace tebd;
+  if (precision < 0 || precision > 1 || max_rows < 1 || width < 1) return -1;
+  const int br = tune_bucket(kTuneRows, 6, max_rows), bw = tune_bucket(kTuneWidth, 4, width);
+  if (br < 0 || bw < 0 || !g_tune_init) return -1;
+  return g_tune[precision][br][bw];
+}

@@ -112,7 +112,7 @@ struct Common {
   int32_t* retry_count;  // device: problems whose first stage was rejected (adaptive rank)
   int32_t* bounds_dev = nullptr;  // device: k_schedule writes {min, max} of m, n, l1 there,
                                   // then the tile total of every kind
-  int32_t ktiles[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
+  int32_t ktiles[11] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
   int32_t serial = 0;  // 1: size classes run in order on the caller's stream (no side streams)
@@ -163,10 +163,17 @@ enum {
   TK_TAPEU = 6,  // recording: m x l, U of every computed triplet
   TK_TAPEV = 7,  // recording: l x n, V^H of every computed triplet
   TK_ACB = 8,    // Accuracy Check: m x r probe products A Omega_r
-  TK_COUNT = 9
+  TK_SKM_W = 9,  // TK_SKM on 64 x 64 tiles (the wide sketch variant)
+  TK_SKN_W = 10, // TK_SKN on 64 x 64 tiles
+  TK_COUNT = 11
 };
 
-static_assert(TK_COUNT == 9, "Common::ktiles holds one total per kind");
+static_assert(TK_COUNT == 11, "Common::ktiles holds one total per kind");
+
+// Autotune cache: tile-shape variant of the sketch, power-iteration and
+// projection products (0: 32 x 32 tiles, 1: 64 x 64) for a launch whose
+// largest problem has max_rows rows and sketch width l (contract.hip).
+int sketch_variant(int precision, int max_rows, int width);
 
 // Output tile of the gate product, (dl dr) x (chi_l chi_r): tall and narrow,
 // because the gate side has a few dozen to a few hundred rows while the bond

@@ -247,3 +247,27 @@ def test_noalloc_refuses_batches_beyond_its_scratch():
                                      0x1000, 0x1000, 0x1000, None)
     assert st == _lib.TEBD_ERR_WORKSPACE
     assert "64" in _lib.tebd_last_error() or "scratch" in _lib.tebd_last_error()
+
+
+def test_autotune_cache_entries_and_json_round_trip(tmp_path):
+    # the cache's bucket mapping and validation (host only), and a JSON file
+    # written by the autotuner's save() loaded back into the library
+    from paper_1504_00992_amd import autotune
+    _lib.load()
+    assert _lib.tebd_tune_set(0, 300, 50, 1) == _lib.TEBD_OK
+    assert _lib.tebd_tune_get(0, 512, 64) == 1      # same bucket (<= 512, <= 64)
+    assert _lib.tebd_tune_get(0, 256, 64) in (-1, 0, 1)
+    assert _lib.tebd_tune_set(1, 300, 50, 1) == _lib.TEBD_ERR_ARG   # FP32 products: variant 0 only
+    assert _lib.tebd_tune_set(0, 9000, 50, 0) == _lib.TEBD_ERR_SHAPE
+    assert _lib.tebd_tune_set(0, 300, 300, 0) == _lib.TEBD_ERR_SHAPE
+    assert _lib.tebd_tune_get(2, 10, 10) == -1
+    path = autotune.save([{"precision": 0, "rows": 2048, "width": 128, "variant": 1},
+                          {"precision": 0, "rows": 100, "width": 20, "variant": 0}],
+                         str(tmp_path / "t.json"), "test")
+    got = autotune.load(path)
+    assert len(got) == 2
+    assert _lib.tebd_tune_get(0, 1500, 100) == 1 and _lib.tebd_tune_get(0, 128, 32) == 0
+    assert autotune.load(str(tmp_path / "absent.json")) == []
+    for rows, width in ((300, 50), (1500, 100), (128, 32)):
+        assert _lib.tebd_tune_set(0, rows, width, -1) == _lib.TEBD_OK
+        assert _lib.tebd_tune_get(0, rows, width) == -1

@@ -191,3 +191,39 @@ def test_table_two_shapes_match_oracle(n):
     a = wl.known_spectrum(n, n, np.exp(-np.arange(300) / 30.0), gen)
     res = _gpu([a], 100, 100, 2, 1e-10)
     _compare([a], res, 100, 100, 2, 1e-10)
+
+
+def test_wide_sketch_tiles_give_the_same_results():
+    # the autotune cache's two tile variants of the sketch, power-iteration
+    # and projection products: both agree with the oracle, and with each
+    # other to rounding (the K order of every output element is the same)
+    from paper_1504_00992_amd import _lib
+    gen = wl.rng(31)
+    shapes = [(300, 200), (700, 650), (64, 90)]
+    mats = [wl.known_spectrum(m, n, np.exp(-np.arange(min(m, n)) / 9.0), gen) for m, n in shapes]
+    outs = []
+    try:
+        for v in (0, 1):
+            assert _lib.tebd_tune_set(0, 700, 74, v) == 0
+            res = _gpu(mats, 64, 10, 2, 1e-10)
+            _compare(mats, res, 64, 10, 2, 1e-10)
+            outs.append(res)
+    finally:
+        _lib.tebd_tune_set(0, 700, 74, -1)
+    for b in range(len(mats)):
+        assert outs[0][3][b] == outs[1][3][b]
+        assert np.max(np.abs(outs[0][1][b] - outs[1][1][b])) <= 1e-13 * outs[0][1][b][0]
+
+
+def test_autotuner_times_both_variants(tmp_path):
+    from paper_1504_00992_amd import _lib, autotune
+    path = str(tmp_path / "tune.json")
+    try:
+        entries = autotune.tune(buckets=((256, 64),), batch=4, reps=1, path=path)
+        assert len(entries) == 1 and entries[0]["variant"] in (0, 1)
+        assert all(ms > 0 for ms in entries[0]["sketch_ms"])
+        assert _lib.tebd_tune_get(0, 256, 64) == entries[0]["variant"]
+        _lib.tebd_tune_set(0, 256, 64, -1)
+        assert autotune.load(path)[0]["variant"] == entries[0]["variant"]
+    finally:
+        _lib.tebd_tune_set(0, 256, 64, -1)
