@@ -65,7 +65,7 @@ def parse():
                     help="the headline evolution only (timed, then one profiled repetition)")
     ap.add_argument("--no-profile", action="store_true", help="skip the profiled repetition")
     for x in ("cpu-baseline", "full-svd", "other-rank", "graph", "tfim", "batched", "mixed",
-              "adjoint"):
+              "adjoint", "table2", "tedopa", "accuracy", "order4"):
         ap.add_argument(f"--no-{x}", action="store_true")
     ap.add_argument("--rank", choices=("adaptive", "fixed"), default="adaptive",
                     help="rank of the timed run: two-stage adaptive (k1 from the bond dimension, "
@@ -73,7 +73,7 @@ def parse():
     a = ap.parse_args()
     if a.headline_only:
         for x in ("cpu_baseline", "full_svd", "other_rank", "graph", "tfim", "batched", "mixed",
-                  "adjoint"):
+                  "adjoint", "table2", "tedopa", "accuracy", "order4"):
             setattr(a, "no_" + x, True)
     return a
 
@@ -794,6 +794,131 @@ def adjoint_line(args, torch, api, models, wl, lib, reps=3):
     return out
 
 
+# Table II of the paper (Sec. V.B): GPU-RRSVD seconds per matrix on a K20s,
+# PCIe copies included, for its mixed-state Theta samples (context only).
+PAPER_TABLE2_GPU_RRSVD_S = {900: 0.25, 1600: 0.41, 2500: 0.61, 3600: 0.88, 4900: 1.48}
+
+
+def table2_line(args, torch, api, wl, lib):
+    """Mixed-state Theta shapes (d^2 chi x d^2 chi, chi = 100, d = 3..7) at
+    k = p = 100, q = 2: seconds per matrix, 8 matrices per call."""
+    import numpy as np
+    out = {"config": {"workload": "the mixed-state Theta shapes of the paper's timing table: "
+                                  "n = 100 d^2 for d = 3..7 (900 ... 4900), 8 square complex128 "
+                                  "matrices per call with the rank-300 spectrum exp(-i/30) "
+                                  "(synthetic: the paper's sampled matrices are not available), "
+                                  "RRSVD k = p = 100, q = 2, w <= 1e-10"},
+           "unit": "s per matrix", "sizes": {}}
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1504)
+    for n in sorted(PAPER_TABLE2_GPU_RRSVD_S):
+        r = 300
+        mats = []
+        s_ = torch.exp(-torch.arange(r, dtype=torch.float64, device="cuda") / 30.0)
+        for _ in range(8):
+            u, _ = torch.linalg.qr(torch.randn((n, r), dtype=torch.complex128, device="cuda",
+                                               generator=gen))
+            v, _ = torch.linalg.qr(torch.randn((n, r), dtype=torch.complex128, device="cuda",
+                                               generator=gen))
+            mats.append(((u * s_[None, :]) @ v.conj().transpose(0, 1)).contiguous())
+        api.rrsvd_truncate(mats, 100, 100, 2, 1e-10, 1504, 0)
+        torch.cuda.synchronize()
+        reps = 2
+        t0 = time.perf_counter()
+        for k in range(reps):
+            res = api.rrsvd_truncate(mats, 100, 100, 2, 1e-10, 1504, k + 1)
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) / (reps * len(mats))
+        lib.tebd_profile_enable(True)
+        api.rrsvd_truncate(mats, 100, 100, 2, 1e-10, 1504, reps + 1)
+        torch.cuda.synchronize()
+        prof = lib.tebd_profile_read()
+        lib.tebd_profile_enable(False)
+        w = Work(lib)
+        chi = res[3].cpu().numpy()
+        for c in chi:
+            w.add("k_frob", 0.0, 16.0 * n * n)
+            w.rrsvd_pass(n, n, 200, 2, False, int(c))
+        for k in ("k_form_u<1>", "k_form_vh<1>"):
+            if k in w.k:
+                w.k[k.replace("<1>", "<0>")] = w.k.pop(k)
+        out["sizes"][str(n)] = {"value": round(per, 5),
+                                "paper_gpu_rrsvd_s_k20s": PAPER_TABLE2_GPU_RRSVD_S[n],
+                                "roofline": kernel_roofline(prof, w, f"table2_{n}")}
+        del mats
+        torch.cuda.empty_cache()
+    return out
+
+
+def tedopa_line(args, torch, api, lib):
+    """A TEDOPA chain (Sec. III): Ohmic bath mapped to 99 oscillators."""
+    from paper_1504_00992_amd import models, tedopa
+    N = 100
+    dims = [2] + [10] * 20 + [8] * 30 + [6] * 49
+    t0, om_, hop = tedopa.chain_coefficients(tedopa.ohmic(0.1, 1.0, 2.0), 2.0, N - 1)
+    _, hb = models.spin_boson_tedopa(dims, t0, om_, hop)
+    ev = Evolution(torch, api, dims, hb, [0] * N, args.chains, 100, 10, 2, 0.05, 1e-10, 1504)
+    times = ev.timed(SB["steps"], 1, 1)
+    upd = SB["steps"] * updates_per_step(N) * args.chains
+    return {"config": {"workload": f"{args.chains} TEDOPA chains: spin + 99 oscillators from the "
+                                   "Ohmic spectral density J = 2 pi alpha omega (alpha = 0.1, "
+                                   "omega_c = 2) mapped by orthogonal polynomials, truncations "
+                                   "10/8/6 along the chain, dt = 0.05, 200 steps, chi_max = 100"},
+            "value": round(upd / times[0], 2), "unit": "bond updates/s",
+            "ms_per_evolution": round(1e3 * times[0], 2),
+            "chain": {"t0": round(t0, 6), "omega_first": [round(x, 6) for x in om_[:3]],
+                      "t_first": [round(x, 6) for x in hop[:3]]},
+            "chi_final_max": int(ev.mps.chi.max().item())}
+
+
+def accuracy_line(args, torch, api, models, lib, ref_ev):
+    """The headline evolution with the Accuracy Check (adaptive rank 3)."""
+    from paper_1504_00992_amd import gradient
+    N = SB["N"]
+    dims, hb = models.spin_boson(N, SB["d"], 1.0, 0.5, 1.0, 0.5)
+    ev = Evolution(torch, api, dims, hb, [0] * N, args.chains, SB["chi_max"], SB["p"], SB["q"],
+                   SB["dt"], SB["eps"], SB["seed"], adaptive=3)
+    times = ev.timed(SB["steps"], 1, 1)
+    upd = SB["steps"] * updates_per_step(N) * args.chains
+    zop = torch.zeros((SB["d"], SB["d"]), dtype=torch.complex128, device="cuda")
+    zop[0, 0], zop[1, 1] = 1.0, -1.0
+    za = float(gradient.expectation(ev.mps.gamma[0], ev.mps.lam[0], zop, 0).item())
+    zb = float(gradient.expectation(ref_ev.mps.gamma[0], ref_ev.mps.lam[0], zop, 0).item())
+    st = ev.drv.ws.status.cpu().numpy()
+    return {"config": {"workload": "the headline evolution (16 spin-boson chains, N=100, d=10, "
+                                   "chi_max=100, 200 steps) with the Accuracy Check of Sec. IV "
+                                   "(Alg. 2): sketch from chi + p columns, probes of p = 10 "
+                                   "columns against sqrt(eps) ||A||_F / ((10/3) pi)"},
+            "value": round(upd / times[0], 2), "unit": "bond updates/s",
+            "ms_per_evolution": round(1e3 * times[0], 2),
+            "chi_final_max": int(ev.mps.chi.max().item()),
+            "capped_bonds_last_sweep": int(((st & 128) != 0).sum()),
+            "sigma_z_chain0_vs_two_stage_rank": abs(za - zb)}
+
+
+def order4_line(args, torch, api, models, lib):
+    """Fourth-order Trotter steps (15 sweeps each) on the headline chains."""
+    from paper_1504_00992_amd import gradient
+    N = SB["N"]
+    dims, hb = models.spin_boson(N, SB["d"], 1.0, 0.5, 1.0, 0.5)
+    steps, dt = 50, 0.2  # the same T = 10 as 200 steps of 0.05
+    mps = api.DeviceMPS.product_state(args.chains, dims, [0] * N, SB["chi_max"])
+    drv = api.TEBD(mps, hb, dt, SB["chi_max"], p=10, q=2, trunc_eps=1e-10, seed=1504,
+                   adaptive=2, order=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        drv.step()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    upd = steps * 5 * updates_per_step(N) * args.chains
+    return {"config": {"workload": "16 spin-boson chains N=100 d=10, chi_max=100, Suzuki "
+                                   "fourth-order steps of dt = 0.2 (15 sweeps each) to T = 10"},
+            "value": round(upd / sec, 2), "unit": "bond updates/s",
+            "ms_per_evolution": round(1e3 * sec, 2),
+            "chi_final_max": int(mps.chi.max().item())}
+
+
 # ---------------------------------------------------------------------------
 def main():
     args = parse()
@@ -945,6 +1070,23 @@ def main():
     if not args.no_adjoint:
         line["adjoint"] = adjoint_line(args, torch, api, models, wl, _lib)
         _progress("adjoint done")
+    if not args.no_accuracy:
+        line["accuracy_check"] = accuracy_line(args, torch, api, models, _lib, ev)
+        line["accuracy_check"]["vs_two_stage_rank"] = round(
+            line["accuracy_check"]["value"] / line["value"], 4)
+        torch.cuda.empty_cache()
+        _progress("accuracy check done")
+    if not args.no_order4:
+        line["order4"] = order4_line(args, torch, api, models, _lib)
+        torch.cuda.empty_cache()
+        _progress("order 4 done")
+    if not args.no_tedopa:
+        line["tedopa"] = tedopa_line(args, torch, api, _lib)
+        torch.cuda.empty_cache()
+        _progress("tedopa done")
+    if not args.no_table2:
+        line["table2_mixed_state"] = table2_line(args, torch, api, wl, _lib)
+        _progress("table 2 shapes done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_spin_boson()
         _progress("cpu baseline done")
