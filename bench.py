@@ -666,6 +666,13 @@ def mixed_line(args, torch, api, models, lib):
             prof, hist = ev.profiled(steps, lib)
             w = history_work(lib, hist, dims, chi_max, SB["p"], SB["q"], True, mixed=True)
             r["roofline"] = kernel_roofline(prof, w, "spin_boson_16x100_chi128_mixed")
+            import numpy as np
+            st = np.concatenate([h[3][:, h[0]::2].ravel() for h in hist])
+            r["gram_qr_fallbacks"] = {"bond_updates_refused": int(((st & 2) != 0).sum()),
+                                      "bond_updates": int(st.size),
+                                      "note": "updates whose QRs tried CholeskyQR2 (problems of "
+                                              "QR size class 2 or 3) and fell back to Householder "
+                                              "(kappa beyond ~1e7)"}
             f32 = {k: v for k, v in prof.items() if k.startswith("k_sketch_f32")}
             ms = sum(v[0] for v in f32.values())
             fl = sum(w.k.get(k, (0, 0))[0] for k in f32)
@@ -679,7 +686,8 @@ def mixed_line(args, torch, api, models, lib):
                                   "sketch and power-iteration products in complex FP32 (FP32 "
                                   "MFMA, FP32 accumulation), QRs, B = Q^H A, small SVD in FP64"},
            "value": res[1]["value"], "fp64_value": res[0]["value"], "unit": "bond updates/s",
-           "roofline": res[1]["roofline"], "f32_sketches": res[1]["f32_sketches"]}
+           "roofline": res[1]["roofline"], "f32_sketches": res[1]["f32_sketches"],
+           "gram_qr_fallbacks": res[1]["gram_qr_fallbacks"]}
     try:
         gz, glam = _golden_mixed()
         chi = res[1]["chi"]

@@ -334,6 +334,8 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
     if (e != hipSuccess) return e; \
   } while (0)
 #define TIMED(kind, call) TRY(timed(kind, s, [&]() { return (call); }))
+  if (c.chol && tebd_size_class(0, std::max(c.mmax, c.nmax), c.lmax) >= 2)
+    TIMED(PK_SCHEDULE, launch_chol_mark(probs, c, s));
   TIMED(PK_SCHEDULE, launch_schedule(probs, c, s));
   if (c.bounds_dev) TRY(counters_async(c.bounds_dev, 6 + TK_COUNT, s));
   if (c.tebd) {
@@ -361,7 +363,20 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
   }
   // the first QR reveals the sketch's rank (column pivoting); the power
   // iterations keep that rank and orthonormalise without pivoting
-  TIMED(PK_QR, launch_qr(probs, c, 0, 0, 1, s));
+  // The large problems may take the Gram-based QR first (when their sketch
+  // is well conditioned every column is kept, as the pivoted QR would);
+  // the Householder kernels then take every problem it did not finish.
+  auto qr_step = [&](int which, int pivot) -> hipError_t {
+    // no problem of the batch can reach the Gram path's size classes: skip it
+    const int rows_max = which ? c.nmax : c.mmax;
+    if (c.chol && tebd_size_class(0, rows_max, c.lmax) >= 2) {
+      hipError_t er = timed(PK_QR, s, [&]() { return launch_chol_qr(probs, c, which, s); });
+      if (er != hipSuccess) return er;
+    }
+    const int gate = c.chol && tebd_size_class(0, rows_max, c.lmax) >= 2 ? 2 : 0;
+    return timed(PK_QR, s, [&]() { return launch_qr(probs, c, which, 0, pivot, s, gate); });
+  };
+  TRY(qr_step(0, 1));
   if (c.acc_count) {
     // Accuracy Check rounds: probe, decide, orthonormalise the grown bases;
     // the host reads how many problems still probe after each round
@@ -387,9 +402,9 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
   }
   for (int j = 0; j < c.q; ++j) {
     TIMED(PK_SKETCH_AHQ, sketch(SK_YT_FROM_Y));
-    TIMED(PK_QR, launch_qr(probs, c, 1, 0, 0, s));
+    TRY(qr_step(1, 0));
     TIMED(PK_SKETCH_AQT, sketch(SK_Y_FROM_YT));
-    TIMED(PK_QR, launch_qr(probs, c, 0, 0, 0, s));
+    TRY(qr_step(0, 0));
   }
   TIMED(PK_SKETCH_AHQ, launch_sketch(probs, c, SK_YT_FROM_Y, s));  // B^H = A^H Q
   TIMED(PK_QR_R, launch_qr(probs, c, 1, 1, 1, s));                 // B^H P = Q_B R_B
@@ -432,6 +447,7 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   c.adaptive = prm->adaptive;
   c.pass2 = 0;
   c.mixed = prm->precision;
+  c.chol = prm->precision == 1 ? 1 : 0;  // the FP32-product path uses CholeskyQR2 where it can
   c.record = tape != nullptr;
   c.nsites = mps->n_sites;
   c.retry_count = prm->adaptive
@@ -463,7 +479,8 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   // thread, with a quarter of headroom: any grid covers every tile (the
   // launches are persistent), so the estimate only affects speed.
   static thread_local int32_t last_tiles[2][TK_COUNT] = {
-      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1}};
+      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1},
+      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1}};
   if (c.adaptive == 3) {
     c.acc_count = c.retry_count + kAccCountSlot;
     c.acc_lcap = int32_t(pl.lcap);
@@ -675,6 +692,7 @@ tebd_status rrsvd_enqueue(int64_t batch, const int64_t* m, const int64_t* n,
   c.dmax = 0;
   c.chimax = 0;
   c.serial = noalloc ? 1 : 0;
+  c.chol = 1;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   DescArgs da;
   da.first = 0;

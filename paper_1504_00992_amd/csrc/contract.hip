@@ -56,7 +56,8 @@ struct TileKinds<Prob> {
   static constexpr int count = TK_COUNT;
   static constexpr bool small_tiles(int kind) {
     return kind == TK_SKM || kind == TK_SKN || kind == TK_FORMU || kind == TK_FORMV ||
-           kind == TK_THETA || kind == TK_ACB;
+           kind == TK_THETA || kind == TK_ACB || kind == TK_GRAM || kind == TK_QAPM ||
+           kind == TK_QAPN;
   }
   static constexpr int tile_m(int kind) {
     return kind == TK_GATE ? kGateTileM : small_tiles(kind) ? kSketchTileM : 64;
@@ -115,6 +116,21 @@ struct TileKinds<Prob> {
         if (P.ac_r > 0) {
           M = P.m;
           N = P.ac_r;
+        }
+        break;
+      case TK_GRAM:
+        if (P.chol) M = N = P.l;
+        break;
+      case TK_QAPM:
+        if (P.chol & 1) {
+          M = P.m;
+          N = P.l;
+        }
+        break;
+      case TK_QAPN:
+        if (P.chol & 2) {
+          M = P.n;
+          N = P.l;
         }
         break;
       default:
@@ -362,6 +378,61 @@ hipError_t launch_sketch_f32(Prob* probs, const Common& c, int which, hipStream_
     TEBD_LAUNCH("k_sketch_f32<1>", k_sketch_f32<SK_YT_FROM_Y>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
   else
     TEBD_LAUNCH("k_sketch_f32<2>", k_sketch_f32<SK_Y_FROM_YT>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Gram-based QR (CholeskyQR2) of the large problems, the tile-queue parts:
+// G = Y^H Y into C (l x l), and Q = Y R^-1 into Qc with R^-1 (upper
+// triangular, from k_chol) in J.  WHICH selects the m x l sketch Y (bit 1 of
+// P.chol) or the n x l sketch Yt (bit 2); in the second pass only the
+// problems whose first pass succeeded take part.
+template <int WHICH>
+__global__ __launch_bounds__(256) void k_gram(Prob* probs, const int32_t* offs, int nprob, int tebd,
+                                              int pass) {
+  __shared__ zt smem[CfgSk::lds_elems];
+  for_each_tile<TK_GRAM>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+    if (!(P.chol & (WHICH ? 2 : 1)) || (pass && !P.chol_ok)) return;
+    const int rows = WHICH ? P.n : P.m;
+    const zt* Yc = WHICH ? P.Yt : P.Y;
+    LdAdjColA la{Yc, rows};
+    LdColB lb{Yc, rows};
+    StCol st{P.C, P.l};
+    zgemm_tile<CfgSk>(M, N, rows, m0, n0, la, lb, st, smem);
+  });
+}
+
+template <int WHICH>
+__global__ __launch_bounds__(256) void k_qapply(Prob* probs, const int32_t* offs, int nprob,
+                                                int tebd) {
+  __shared__ zt smem[CfgSk::lds_elems];
+  for_each_tile<WHICH ? TK_QAPN : TK_QAPM>(probs, offs, nprob, tebd,
+                                           [&](Prob& P, int M, int N, int m0, int n0, int) {
+    if (!P.chol_ok) return;
+    const int rows = WHICH ? P.n : P.m;
+    LdColA la{WHICH ? P.Yt : P.Y, rows};
+    LdColB lb{P.J, P.l};
+    StCol st{P.Qc, rows};
+    zgemm_tile<CfgSk>(M, N, P.l, m0, n0, la, lb, st, smem);
+  });
+}
+
+hipError_t launch_gram(Prob* probs, const Common& c, int which, int pass, hipStream_t s) {
+  const dim3 g(grid_for(c, TK_GRAM));
+  if (which)
+    TEBD_LAUNCH("k_gram<1>", k_gram<1>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd, pass);
+  else
+    TEBD_LAUNCH("k_gram<0>", k_gram<0>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd, pass);
+  return hipGetLastError();
+}
+
+hipError_t launch_qapply(Prob* probs, const Common& c, int which, hipStream_t s) {
+  if (which)
+    TEBD_LAUNCH("k_qapply<1>", k_qapply<1>, dim3(grid_for(c, TK_QAPN)), dim3(256), 0, s, probs,
+                c.offs, c.nprob, c.tebd);
+  else
+    TEBD_LAUNCH("k_qapply<0>", k_qapply<0>, dim3(grid_for(c, TK_QAPM)), dim3(256), 0, s, probs,
+                c.offs, c.nprob, c.tebd);
   return hipGetLastError();
 }
 

@@ -70,6 +70,8 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
   P.ac_col = 0;
   P.ac_cap = l2;
   P.ac_grow = 0;
+  P.chol = 0;
+  P.chol_ok = 0;
   if (adaptive == 3) {  // Accuracy Check: from the current bond dimension, probes of p columns
     l = cm + p_over;
     if (l > P.m) l = P.m;
@@ -465,6 +467,12 @@ __device__ __forceinline__ double col_norm2(const zt* y, int r0, int rows, int G
   return (n0 + n1) + (n2 + n3);
 }
 
+// A problem a gated QR launch leaves alone: gate 1 runs only the bases the
+// Accuracy Check grew; gate 2 only what the Gram-based QR did not finish.
+__device__ __forceinline__ bool qr_gated(const Prob& P, int gate) {
+  return (gate == 1 && !P.ac_grow) || (gate == 2 && P.chol_ok);
+}
+
 // Size classes of the batched QR, by (rows, l): 0 and 1 are register-
 // resident (512 threads with 8 rows per lane, 1024 threads with 12), 2 keeps
 // the matrix in LDS (1024 threads), 3 works on global memory.  The class
@@ -786,13 +794,13 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
 
 template <int NT, int RPL, bool PIV>
 __global__ __launch_bounds__(NT) void k_qr_reg(Prob* probs, int which, int want_r, int cls,
-                                                 int grow_only) {
+                                                 int gate) {
   __shared__ RegQrShared<RPL> sh;
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
   // class from the width the pass started with: P.l shrinks as QRs run
-  if (l == 0 || qr_class(rows, P.l1) != cls || (grow_only && !P.ac_grow)) return;
+  if (l == 0 || qr_class(rows, P.l1) != cls || qr_gated(P, gate)) return;
   zt* Yg = which ? P.Yt : P.Y;
   // l <= kMaxL, so G >= NT / kMaxL
   static_assert(NT / kMaxL >= 2, "group widths below 2 are not instantiated");
@@ -822,13 +830,13 @@ __global__ __launch_bounds__(NT) void k_qr_reg(Prob* probs, int which, int want_
 // a time), the matrix in up to 150 KiB of LDS.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_qr_lds(Prob* probs, int which, int want_r, int pivot,
-                                                 int grow_only) {
+                                                 int gate) {
   extern __shared__ zt lds[];  // rows * l matrix, then 2 * rows for u
   __shared__ zt rdiag[kMaxL];
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
-  if (l == 0 || qr_class(rows, P.l1) != 2 || (grow_only && !P.ac_grow)) return;
+  if (l == 0 || qr_class(rows, P.l1) != 2 || qr_gated(P, gate)) return;
   __shared__ double nrm[2 * kMaxL];
   __shared__ int sh_i[2];
   zt* Yg = which ? P.Yt : P.Y;
@@ -857,13 +865,13 @@ constexpr int kGlbLdsRows = 4608;
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_qr_glb(Prob* probs, int which, int want_r, int pivot,
-                                                 int grow_only) {
+                                                 int gate) {
   extern __shared__ zt u_lds[];  // 2 * min(rows, kGlbLdsRows)
   __shared__ zt rdiag[kMaxL];
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
   const int rows = which ? P.n : P.m;
-  if (l == 0 || qr_class(rows, P.l1) != 3 || (grow_only && !P.ac_grow)) return;
+  if (l == 0 || qr_class(rows, P.l1) != 3 || qr_gated(P, gate)) return;
   zt* u_s = rows <= kGlbLdsRows ? u_lds : P.qru;
   __shared__ double nrm[2 * kMaxL];
   __shared__ int sh_i[2];
@@ -961,7 +969,7 @@ hipError_t fork_join(hipStream_t s, L* launches, int n, const Common& c) {
 }  // namespace
 
 hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pivot,
-                     hipStream_t s, int grow_only) {
+                     hipStream_t s, int gate) {
   const int rows_max = which ? c.nmax : c.mmax;
   const int rows_min = which ? c.nmin : c.mmin;
   static const hipError_t attr = []() {
@@ -1008,8 +1016,168 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pi
   Item items[4];
   int n = 0;
   for (int k = lo; k <= hi; ++k)
-    items[n++] = {fns[k], probs, which, want_r, pivot, c.nprob, rows_max, grow_only};
+    items[n++] = {fns[k], probs, which, want_r, pivot, c.nprob, rows_max, gate};
   return fork_join(s, items, n, c);
+}
+
+// --------------------------------------------------------------------------
+// Gram-based QR (CholeskyQR2) of the large problems (QR classes 2 and 3):
+// two passes of G = Y^H Y (k_gram), G = R^H R by Cholesky, Y <- Y R^-1
+// (k_qapply into Qc, then Qc and Y trade places).  The passes are wide
+// tile-queue products instead of a workgroup's reflector chain, which is
+// what the large problems need.  A Cholesky pivot at or below kCholTol times
+// the Gram's largest diagonal (kappa(Y) beyond about 1e7, where CholeskyQR2
+// loses orthogonality) refuses the problem: TEBD_DEV_QR_FALLBACK, and the
+// Householder kernels (gate 2) take it over from what the passes left in Y,
+// which spans the same space.  Bit 1 of P.chol: the m x l sketch is
+// eligible, bit 2: the n x l sketch.
+constexpr double kCholTol = 1e-14;
+constexpr int kCholLdsL = 96;  // Gram in LDS up to this width (147 KiB), else in global memory
+
+__global__ void k_chol_mark(Prob* probs, int nprob) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  Prob& P = probs[p];
+  int f = 0;
+  if (P.l > 0) {
+    if (qr_class(P.m, P.l1) >= 2) f |= 1;
+    if (qr_class(P.n, P.l1) >= 2) f |= 2;
+  }
+  P.chol = f;
+  P.chol_ok = 0;
+}
+
+hipError_t launch_chol_mark(Prob* probs, const Common& c, hipStream_t s) {
+  TEBD_LAUNCH("k_chol_mark", k_chol_mark, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs,
+              c.nprob);
+  return hipGetLastError();
+}
+
+// Cholesky G = L L^H of the Gram in C (column-major l x l, lower triangle
+// used), then X = R^-1 = (L^-1)^H, upper triangular, into J: column c of
+// L^-1 by forward substitution, one wavefront per column, the column held
+// across the lanes (lane t keeps rows t, t + 64, ...).
+template <int WHICH>
+__global__ __launch_bounds__(1024) void k_chol(Prob* probs, int pass) {
+  Prob& P = probs[blockIdx.x];
+  const int l = P.l, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool elig = l > 0 && (P.chol & (WHICH ? 2 : 1)) && (pass == 0 || P.chol_ok);
+  if (!elig) {
+    if (tid == 0 && pass == 0) P.chol_ok = 0;
+    return;
+  }
+  __shared__ zt g_lds[kCholLdsL * kCholLdsL];
+  __shared__ double dmax_s;
+  __shared__ int fail_s;
+  const bool in_lds = l <= kCholLdsL;
+  zt* G = in_lds ? g_lds : P.C;
+  if (in_lds)
+    for (int e = tid; e < l * l; e += 1024) g_lds[e] = P.C[e];
+  __syncthreads();
+  if (tid == 0) {
+    double dm = 0.0;
+    for (int j = 0; j < l; ++j) dm = fmax(dm, G[j + size_t(j) * l].x);
+    dmax_s = dm;
+    fail_s = !(dm > 0.0) || !isfinite(dm);
+  }
+  __syncthreads();
+  for (int j = 0; j < l && !fail_s; ++j) {
+    if (tid == 0) {
+      const double d = G[j + size_t(j) * l].x;
+      if (!(d > kCholTol * dmax_s) || !isfinite(d))
+        fail_s = 1;
+      else
+        G[j + size_t(j) * l] = make_double2(sqrt(d), 0.0);
+    }
+    __syncthreads();
+    if (fail_s) break;
+    const double inv = 1.0 / G[j + size_t(j) * l].x;
+    for (int i = j + 1 + tid; i < l; i += 1024) G[i + size_t(j) * l] = zscale(G[i + size_t(j) * l], inv);
+    __syncthreads();
+    const int nt = l - j - 1;
+    for (int e = tid; e < nt * nt; e += 1024) {
+      const int kk = e / nt, ii = e - kk * nt;
+      if (ii < kk) continue;
+      const int k = j + 1 + kk, i = j + 1 + ii;
+      const zt lij = G[i + size_t(j) * l], lkj = G[k + size_t(j) * l];
+      G[i + size_t(k) * l] = zsub(G[i + size_t(k) * l], zmul(lij, zconj(lkj)));
+    }
+    __syncthreads();
+  }
+  if (fail_s) {
+    if (tid == 0) {
+      P.chol_ok = 0;
+      P.flags |= TEBD_DEV_QR_FALLBACK;
+    }
+    return;
+  }
+  // X = (L^-1)^H: row c of X holds conj of column c of L^-1
+  zt* X = P.J;
+  for (int c = wave; c < l; c += 16) {
+    zt xr[kMaxL / 64];  // rows lane, lane + 64, ... of column c of L^-1
+#pragma unroll
+    for (int q = 0; q < kMaxL / 64; ++q) xr[q] = make_double2(0.0, 0.0);
+    for (int i = c; i < l; ++i) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int q = 0; q < kMaxL / 64; ++q) {
+        const int k = lane + 64 * q;
+        if (k >= c && k < i) {
+          const zt lik = G[i + size_t(k) * l];
+          sr += lik.x * xr[q].x - lik.y * xr[q].y;
+          si += lik.x * xr[q].y + lik.y * xr[q].x;
+        }
+      }
+      sr = wave_sum(sr);
+      si = wave_sum(si);
+      const double lii = G[i + size_t(i) * l].x;
+      const zt x = i == c ? make_double2(1.0 / lii, 0.0) : make_double2(-sr / lii, -si / lii);
+#pragma unroll
+      for (int q = 0; q < kMaxL / 64; ++q)
+        if (lane + 64 * q == i) xr[q] = x;
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxL / 64; ++q) {
+      const int i = lane + 64 * q;
+      if (i < l) X[c + size_t(i) * l] = i >= c ? zconj(xr[q]) : make_double2(0.0, 0.0);
+    }
+  }
+  if (tid == 0) P.chol_ok = 1;
+}
+
+template <int WHICH>
+__global__ void k_qswap(Prob* probs, int nprob) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  Prob& P = probs[p];
+  if (!P.chol_ok) return;
+  zt* t = WHICH ? P.Yt : P.Y;
+  if (WHICH)
+    P.Yt = P.Qc;
+  else
+    P.Y = P.Qc;
+  P.Qc = t;
+}
+
+hipError_t launch_chol_qr(Prob* probs, const Common& c, int which, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+    e = launch_gram(probs, c, which, pass, s);
+    if (e != hipSuccess) break;
+    if (which)
+      TEBD_LAUNCH("k_chol<1>", k_chol<1>, dim3(c.nprob), dim3(1024), 0, s, probs, pass);
+    else
+      TEBD_LAUNCH("k_chol<0>", k_chol<0>, dim3(c.nprob), dim3(1024), 0, s, probs, pass);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = launch_qapply(probs, c, which, s);
+    if (e != hipSuccess) break;
+    if (which)
+      TEBD_LAUNCH("k_qswap<1>", k_qswap<1>, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob);
+    else
+      TEBD_LAUNCH("k_qswap<0>", k_qswap<0>, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 // --------------------------------------------------------------------------

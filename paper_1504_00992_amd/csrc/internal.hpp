@@ -42,6 +42,9 @@ struct Prob {
   // probe column of the Gaussian stream, capacity of the basis, and 1 while
   // the basis grew this round (its QR runs)
   int32_t ac_r, ac_col, ac_cap, ac_grow;
+  // Gram-based QR (CholeskyQR2) of the large problems: eligible in this
+  // pipeline, and 1 while the current QR's Gram passes have succeeded
+  int32_t chol, chol_ok;
   double frob2;                      // ||A||_F^2, written on the device
   // input matrix (row-major, leading dim lda) and test matrix (row-major n x l)
   zt* A;
@@ -58,6 +61,7 @@ struct Prob {
   zt* X;         // l x l column-major: left vectors of the small SVD, sorted
   zt* W;         // l x l column-major: right rotation, sorted
   zt* qru;       // 2 max(m, n): reflectors of the global-memory QR beyond its LDS rows
+  zt* Qc;        // max(m, n) x l column-major: Q of the Gram-based QR (then swapped with Y or Yt)
   double* sig;   // l: singular values sorted descending
   int32_t* piv;  // l: column order of the pivoted QR of B^H (B^H P = Q_B R_B)
   double* part;  // npart Frobenius partial sums
@@ -91,6 +95,8 @@ struct Prob {
   int32_t tape_ldu, tape_ldvh;
 };
 
+constexpr int TK_COUNT_MAX = 14;  // tile kinds of the forward pipeline (enum below)
+
 // Parameters of a launch sequence that are common to all problems.
 struct Common {
   int32_t nprob;
@@ -112,12 +118,13 @@ struct Common {
   int32_t* retry_count;  // device: problems whose first stage was rejected (adaptive rank)
   int32_t* bounds_dev = nullptr;  // device: k_schedule writes {min, max} of m, n, l1 there,
                                   // then the tile total of every kind
-  int32_t ktiles[11] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
+  int32_t ktiles[TK_COUNT_MAX] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
   int32_t serial = 0;  // 1: size classes run in order on the caller's stream (no side streams)
   int32_t* acc_count = nullptr;  // device: Accuracy Check, two counters of problems still probing
   int32_t acc_lcap = 0;          // Accuracy Check: largest basis width (QR classes)
+  int32_t chol = 0;              // 1: Gram-based QR (CholeskyQR2) for the large problems
 };
 
 // Kernel-level event timing for tebd_profile_enable / tebd_profile_read:
@@ -165,10 +172,13 @@ enum {
   TK_ACB = 8,    // Accuracy Check: m x r probe products A Omega_r
   TK_SKM_W = 9,  // TK_SKM on 64 x 64 tiles (the wide sketch variant)
   TK_SKN_W = 10, // TK_SKN on 64 x 64 tiles
-  TK_COUNT = 11
+  TK_GRAM = 11,  // Gram-based QR: l x l Gram matrices Y^H Y
+  TK_QAPM = 12,  // Gram-based QR: m x l products Y R^-1
+  TK_QAPN = 13,  // Gram-based QR: n x l products Yt R^-1
+  TK_COUNT = 14
 };
 
-static_assert(TK_COUNT == 11, "Common::ktiles holds one total per kind");
+static_assert(TK_COUNT == TK_COUNT_MAX, "Common::ktiles holds one total per kind");
 
 // Autotune cache: tile-shape variant of the sketch, power-iteration and
 // projection products (0: 32 x 32 tiles, 1: 64 x 64) for a launch whose
@@ -217,9 +227,16 @@ hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s)
 hipError_t launch_sketch_f32(Prob* probs, const Common& c, int which, hipStream_t s);
 // pivot: column pivoting with the rank tolerance (the QR of B^H pivots and
 // keeps every column); 0: plain Householder in column order, every column kept
-// grow_only: only the problems whose basis the Accuracy Check just grew.
+// gate 1: only the problems whose basis the Accuracy Check just grew;
+// gate 2: only the problems the Gram-based QR did not finish.
 hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pivot, hipStream_t s,
-                     int grow_only = 0);
+                     int gate = 0);
+// Gram-based QR (CholeskyQR2) of the large problems of a QR step (which: 0
+// the m x l sketch Y, 1 the n x l sketch Yt), before launch_qr(..., gate 2).
+hipError_t launch_chol_qr(Prob* probs, const Common& c, int which, hipStream_t s);
+hipError_t launch_chol_mark(Prob* probs, const Common& c, hipStream_t s);
+hipError_t launch_gram(Prob* probs, const Common& c, int which, int pass, hipStream_t s);
+hipError_t launch_qapply(Prob* probs, const Common& c, int which, hipStream_t s);
 // Accuracy Check round: B = A Omega_r into the columns after the basis, then
 // the probe residual, the decision and the growth of the basis.
 hipError_t launch_acc_probe(Prob* probs, const Common& c, hipStream_t s);
@@ -248,15 +265,18 @@ __host__ __device__ inline size_t slab_bytes(int64_t m, int64_t n, int64_t l, in
     b += align256(m * n * z);  // A
     b += align256(m * n * z);  // T
   }
+  // with the Gram-based QR, Y, Yt and Qc trade places: each holds max(m, n) rows
+  const int64_t rows_y = (!tebd || mixed) && n > m ? n : m;
+  const int64_t rows_yt = (!tebd || mixed) && m > n ? m : n;
   b += align256(n * l * z);          // Omega
-  b += align256(m * l * z);          // Y
-  b += align256(n * l * z);          // Yt
+  b += align256(rows_y * l * z);     // Y
+  b += align256(rows_yt * l * z);    // Yt
   b += 5 * align256(l * l * z);      // Rb, C, J, X, W
   b += align256(2 * (m > n ? m : n) * z);  // reflector staging of the global-memory QR
+  if (!tebd || mixed) b += align256((m > n ? m : n) * l * z);  // Qc of the Gram-based QR
   b += align256(l * sizeof(double)); // sig
   b += align256(l * sizeof(int32_t));  // piv
   b += align256(npart * sizeof(double));
-  (void)mixed;
   return b;
 }
 
@@ -275,10 +295,12 @@ __host__ __device__ inline void carve_slab(Prob& p, char* base, int64_t m, int64
   }
   p.om = reinterpret_cast<const zt*>(c);
   c += align256(n * l * z);
+  const int64_t rows_y = (!tebd || mixed) && n > m ? n : m;
+  const int64_t rows_yt = (!tebd || mixed) && m > n ? m : n;
   p.Y = reinterpret_cast<zt*>(c);
-  c += align256(m * l * z);
+  c += align256(rows_y * l * z);
   p.Yt = reinterpret_cast<zt*>(c);
-  c += align256(n * l * z);
+  c += align256(rows_yt * l * z);
   p.Rb = reinterpret_cast<zt*>(c);
   c += align256(l * l * z);
   p.C = reinterpret_cast<zt*>(c);
@@ -291,13 +313,17 @@ __host__ __device__ inline void carve_slab(Prob& p, char* base, int64_t m, int64
   c += align256(l * l * z);
   p.qru = reinterpret_cast<zt*>(c);
   c += align256(2 * (m > n ? m : n) * z);
+  p.Qc = nullptr;
+  if (!tebd || mixed) {
+    p.Qc = reinterpret_cast<zt*>(c);
+    c += align256((m > n ? m : n) * l * z);
+  }
   p.sig = reinterpret_cast<double*>(c);
   c += align256(l * sizeof(double));
   p.piv = reinterpret_cast<int32_t*>(c);
   c += align256(l * sizeof(int32_t));
   p.part = reinterpret_cast<double*>(c);
   c += align256(npart * sizeof(double));
-  (void)mixed;
   p.Af = nullptr;
   p.Yf = nullptr;
 }

@@ -81,6 +81,20 @@ struct LdColB {  // B[k][c] = p[c*ld + k] (column-major)
   __device__ zt operator()(int k, int c) const { return p[size_t(c) * ld + k]; }
 };
 
+struct LdColA {  // A[r][k] = p[k*ld + r] (column-major)
+  const zt* p;
+  int64_t ld;
+  static constexpr bool contig_k = false;
+  __device__ zt operator()(int r, int k) const { return p[size_t(k) * ld + r]; }
+};
+
+struct LdAdjColA {  // (r, k) -> conj(p[r*ld + k]): the adjoint of a column-major matrix
+  const zt* p;
+  int64_t ld;
+  static constexpr bool contig_k = true;
+  __device__ zt operator()(int r, int k) const { return zconj(p[size_t(r) * ld + k]); }
+};
+
 struct StCol {  // C[r][c] -> p[c*ld + r]
   zt* p;
   int64_t ld;

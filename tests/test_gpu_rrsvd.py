@@ -227,3 +227,18 @@ def test_autotuner_times_both_variants(tmp_path):
         assert autotune.load(path)[0]["variant"] == entries[0]["variant"]
     finally:
         _lib.tebd_tune_set(0, 256, 64, -1)
+
+
+def test_gram_qr_falls_back_on_a_rank_deficient_sketch():
+    # A 300 x 300 matrix of rank 20 with l = 60: the QRs of this size go to
+    # the Gram-based path first; the first sketch is rank deficient, so its
+    # Cholesky refuses (TEBD_DEV_QR_FALLBACK) and the pivoted Householder
+    # QR reveals the rank; the power iterations' QRs of the rank-20 bases
+    # then pass.  Results as the oracle's.
+    from paper_1504_00992_amd import _lib
+    assert _lib.tebd_size_class(0, 300, 60) >= 2
+    gen = wl.rng(41)
+    a = wl.known_spectrum(300, 300, np.exp(-np.arange(20) / 3.0), gen)
+    U, S, VH, chi, w, st = _gpu([a], 50, 10, 2, 1e-10)
+    assert st[0] & _lib.DEV_QR_FALLBACK
+    _compare([a], (U, S, VH, chi, w, st & ~_lib.DEV_QR_FALLBACK), 50, 10, 2, 1e-10)
