@@ -95,6 +95,9 @@ struct SweepPlan {
   int64_t pmax;
   int64_t mcap, lcap, lslab, npart;
   size_t desc_bytes, slab_sz;
+  // Theta of the gate groups: one capacity-sized block per problem after the
+  // slabs; a group's Theta spans the blocks of its members
+  size_t theta_off, theta_sz;
   // reverse mode of a sweep (same workspace)
   int64_t nchunk;
   size_t adj_desc_bytes, adj_slab_sz;
@@ -111,7 +114,7 @@ SweepPlan plan_sweep(const tebd_mps& mps, const tebd_params& prm) {
   s.lcap = sketch_l(prm.chi_max, prm.p, s.mcap, s.mcap);
   // the Accuracy Check writes a probe block of up to p columns after the basis
   const int64_t lslab = prm.adaptive == 3 ? s.lcap + prm.p : s.lcap;
-  s.npart = gate_tiles(mps.d_max * mps.d_max, mps.chi_max * mps.chi_max);
+  s.npart = gate_partials_cap(mps.d_max * mps.d_max, mps.chi_max * mps.chi_max);
   // descriptors, tile-queue offsets, then 256 bytes of counters
   s.desc_bytes = align256(size_t(s.pmax) * sizeof(Prob)) + align256(sched_bytes(s.pmax)) + 256;
   s.lslab = lslab;
@@ -122,7 +125,9 @@ SweepPlan plan_sweep(const tebd_mps& mps, const tebd_params& prm) {
                      align256(size_t(TA_COUNT) * size_t(s.pmax + 1) * sizeof(int32_t));
   s.adj_slab_sz = adj_slab_bytes(s.mcap, s.mcap, s.lcap, cap, d2, s.nchunk);
   s.tape_slot = tape_slot_bytes(s.mcap, s.mcap, s.lcap);
-  s.total = s.desc_bytes + size_t(s.pmax) * s.slab_sz;
+  s.theta_sz = align256(size_t(s.mcap) * size_t(s.mcap) * sizeof(zt));
+  s.theta_off = s.desc_bytes + size_t(s.pmax) * s.slab_sz;
+  s.total = s.theta_off + size_t(s.pmax) * s.theta_sz;
   const size_t adj = s.adj_desc_bytes + size_t(s.pmax) * s.adj_slab_sz;
   s.adj_total = s.total > adj ? s.total : adj;
   return s;
@@ -459,7 +464,7 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
                                       align256(size_t(pl.pmax) * sizeof(Prob)));
   {
     const int64_t t = (pl.mcap + 63) / 64;
-    const int64_t tq = gate_tiles(mps->d_max * mps->d_max, mps->chi_max * mps->chi_max);
+    const int64_t tq = gate_partials_cap(mps->d_max * mps->d_max, mps->chi_max * mps->chi_max);
     c.grid = persistent_grid(int64_t(c.nprob) * (t * t > tq ? t * t : tq));
   }
   if (c.nprob == 0) return ok();
@@ -471,7 +476,8 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
                              parity, single_chain, single_bond, prm->p, slabs, pl.slab_sz, disc,
                              status, prm->lambda_floor, prm->precision, prm->adaptive,
                              reinterpret_cast<char*>(tape), pl.tape_slot, c.retry_count,
-                             pl.lslab, s);
+                             pl.lslab, reinterpret_cast<char*>(ws) + pl.theta_off, pl.theta_sz,
+                             s);
   });
   // The host-synchronising adaptive mode also reads the batch's size bounds
   // and tile totals.  Until they arrive, the grids of the first contractions
@@ -479,8 +485,9 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   // thread, with a quarter of headroom: any grid covers every tile (the
   // launches are persistent), so the estimate only affects speed.
   static thread_local int32_t last_tiles[2][TK_COUNT] = {
-      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1},
-      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1}};
+      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1},
+      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1}};
+  static_assert(TK_COUNT == 15, "one -1 per tile kind above");
   if (c.adaptive == 3) {
     c.acc_count = c.retry_count + kAccCountSlot;
     c.acc_lcap = int32_t(pl.lcap);

@@ -6,7 +6,10 @@
 //   layout T[(i j)][(a c)] that the gate product reads.
 // * Gate update, Eq. (defupdatetheta): A = G T as (dl dr) x (dl dr) times
 //   (dl dr) x (chi_l chi_r), scattered into the blocked matrix of Sec. II.B,
-//   A[(i,a),(j,c)], with per-tile partial sums of |A|^2 for ||A||_F^2.
+//   A[(i,a),(j,c)], with partial sums of |A|^2 for ||A||_F^2.  The chains
+//   that share a bond's gate run as one product over all their columns
+//   (their T side by side), so each output tile reads its gate rows once
+//   for many chains.
 // * Sketch and power iteration, Alg. 1: Y = A Omega, Yt = A^H Q, Y = A Q~.
 // * Singular vectors, Sec. IV steps i-iii: U = Q X and V^H = (Q_B W)^H for the
 //   kept chi' columns, with the lambda^-1 reabsorption of the TEBD update
@@ -14,8 +17,8 @@
 //
 // Scheduling: problem sizes live on the device, so every contraction kind
 // runs as one persistent launch over a global queue of output tiles (32 x 32
-// for Theta, the sketches and U, V^H; 64 x 16 for the gate; 64 x 64 for the
-// others; prefix sums over problems
+// for Theta, the sketches and U, V^H; 64 x 16 or 64 x 64 for the gate
+// groups; 64 x 64 for the others; prefix sums over problems
 // built by k_schedule).  Workgroup i takes the
 // virtual index (i mod 8) * G/8 + i / 8, so the consecutive tiles of one
 // problem, which share operand rows, land on the same XCD and its L2.
@@ -60,26 +63,29 @@ struct TileKinds<Prob> {
            kind == TK_QAPN;
   }
   static constexpr int tile_m(int kind) {
-    return kind == TK_GATE ? kGateTileM : small_tiles(kind) ? kSketchTileM : 64;
+    return kind == TK_GATE || kind == TK_GATE_W ? kGateTileM : small_tiles(kind) ? kSketchTileM : 64;
   }
   // TK_SKM_W / TK_SKN_W: the same products on 64 x 64 tiles
   static constexpr int tile_n(int kind) {
-    return kind == TK_GATE ? kGateTileN : small_tiles(kind) ? kSketchTileN : 64;
+    return kind == TK_GATE ? kGateTileN : kind == TK_GATE_W ? kGateTileW
+                                        : small_tiles(kind) ? kSketchTileN : 64;
   }
   __device__ static __forceinline__ void shape(int kind, const Prob& P, int tebd, int& M, int& N) {
     M = N = 0;
+    if (kind == TK_GATE || kind == TK_GATE_W) {
+      // the group's tiles belong to its first member, whatever its own state
+      if (tebd && P.gn > 0 && P.gtot > 0 && (P.gtw == kGateTileW) == (kind == TK_GATE_W)) {
+        M = P.dl * P.dr;
+        N = P.gtot;
+      }
+      return;
+    }
     if (P.l == 0) return;
     switch (kind) {
       case TK_THETA:
         if (tebd) {
           M = P.dl * P.chi_l;
           N = P.dr * P.chi_r;
-        }
-        break;
-      case TK_GATE:
-        if (tebd) {
-          M = P.dl * P.dr;
-          N = P.chi_l * P.chi_r;
         }
         break;
       case TK_SKM:
@@ -252,7 +258,7 @@ __global__ __launch_bounds__(256) void k_theta(Prob* probs, const int32_t* offs,
   for_each_tile<TK_THETA>(probs, offs, nprob, 1, [&](Prob& P, int M, int N, int m0, int n0, int) {
     LdThetaA la{P.gk, P.lam_l, P.lam_mid, P.chi_l, P.chi_cap};
     LdThetaB lb{P.gk1, P.lam_r, P.chi_r, P.chi_cap};
-    StTheta st{P.T, P.chi_l, P.chi_r, P.dr};
+    StThetaGroup st{P.T, P.gtot, P.gcol0, P.chi_l, P.chi_r, P.dr};
     zgemm_tile<CfgTheta>(M, N, P.chi_m, m0, n0, la, lb, st, smem);
   });
 }
@@ -265,47 +271,117 @@ struct LdGate {
   static constexpr bool contig_k = true;
   __device__ zt operator()(int r, int k) const { return g[size_t(r) * ld + k]; }
 };
-struct StGate {
-  zt* A;
-  int chi_l, chi_r, dr, n;
-  double acc;
+
+// Where the gate product's column c of a group lands: the member that owns
+// it and the address of its entry (i, j) = (0, 0) in the member's A, with
+// the strides of i and j (rows (i j) of the product go to A[(i, a)][(j, b)]).
+struct GateCol {
+  zt* base;
+  int32_t si, sj;
+};
+
+template <int BN>
+struct StGateGroup {
+  const GateCol* col;  // the tile's BN columns
+  double* f2;          // |A|^2 of the tile's entries, BM x BN row-major
+  int m0, n0, dr;
   __device__ void operator()(int r, int c, zt v) {
+    const GateCol& g = col[c - n0];
     const int i = r / dr, j = r - i * dr;
-    const int a = c / chi_r, b = c - a * chi_r;
-    A[(size_t(i) * chi_l + a) * n + size_t(j) * chi_r + b] = v;
-    acc += zabs2(v);
+    g.base[size_t(i) * g.si + size_t(j) * g.sj] = v;
+    f2[(r - m0) * BN + (c - n0)] = zabs2(v);
   }
 };
 
 constexpr int kGateNarrow = 4;  // gate tiles with at most this many columns use the ALU
 
-__global__ __launch_bounds__(256, 3) void k_gate(Prob* probs, const int32_t* offs, int nprob) {
-  __shared__ zt smem[CfgGate::lds_elems];
-  __shared__ double red[4];
-  for_each_tile<TK_GATE>(probs, offs, nprob, 1,
-                         [&](Prob& P, int M, int N, int m0, int n0, int local) {
-                           LdGate la{P.gate, P.gate_ld};
-                           LdRowB lb{P.T, N};
-                           StGate st{P.A, P.chi_l, P.chi_r, P.dr, P.n, 0.0};
-                           // over most of a spin-boson chain chi_l chi_r = 1: the gate
-                           // acts on a vector, and a 16-wide MFMA tile would do 16
-                           // times the useful work
-                           const int ncol = N - n0 < kGateTileN ? N - n0 : kGateTileN;
-                           if (ncol <= kGateNarrow)
-                             zgemm_narrow_tile<CfgGate, kGateNarrow>(M, N, P.dl * P.dr, m0, n0, ncol,
-                                                                     la, lb, st, smem);
-                           else
-                             zgemm_tile<CfgGate>(M, N, P.dl * P.dr, m0, n0, la, lb, st, smem);
-                           const double s = block_sum<256>(st.acc, red);
-                           if (threadIdx.x == 0) P.part[local] = s;
-                         });
+// One output tile (m0, n0) of the gate product of the group whose first
+// member is probs[lead] (member k at lead + k gstride): rows (i j), columns
+// the members' (a b) side by side.  Then one Frobenius partial per member with columns in the tile: the
+// tile's |A|^2 summed over rows, then over the member's columns, in order.
+template <class Cfg, bool NARROW>
+__device__ __forceinline__ void gate_group_tile(Prob* probs, int lead, int M, int N, int m0,
+                                                int n0, zt* smem, GateCol* cols, double* csum) {
+  constexpr int BM = Cfg::BM, BN = Cfg::BN;
+  const Prob& L = probs[lead];
+  const int tid = threadIdx.x, gn = L.gn, gs = L.gstride;
+  if (tid < BN) {
+    const int c = n0 + tid;
+    GateCol g{nullptr, 0, 0};
+    if (c < N) {
+      // the last member starting at or before c owns it (a member without
+      // columns starts where the next one does)
+      int q = 0;
+      for (int k = 1; k < gn; ++k)
+        if (probs[lead + k * gs].gcol0 <= c) q = k;
+      const Prob& Q = probs[lead + q * gs];
+      const int lc = c - Q.gcol0, a = lc / Q.chi_r, b = lc - a * Q.chi_r;
+      g.base = Q.A + size_t(a) * Q.n + b;
+      g.si = Q.chi_l * Q.n;
+      g.sj = Q.chi_r;
+    }
+    cols[tid] = g;
+  }
+  __syncthreads();
+  LdGate la{L.gate, L.gate_ld};
+  LdRowB lb{L.T, L.gtot};
+  double* f2 = reinterpret_cast<double*>(smem);
+  StGateGroup<BN> st{cols, f2, m0, n0, L.dr};
+  const int K = L.dl * L.dr;
+  const int ncol = N - n0 < BN ? N - n0 : BN;
+  if (NARROW && ncol <= kGateNarrow)
+    zgemm_narrow_tile<Cfg, kGateNarrow>(M, N, K, m0, n0, ncol, la, lb, st, smem);
+  else
+    zgemm_tile<Cfg>(M, N, K, m0, n0, la, lb, st, smem);
+  __syncthreads();  // every entry of f2 in range is written
+  const int rows = M - m0 < BM ? M - m0 : BM;
+  if (tid < ncol) {
+    double sum = 0.0;
+    for (int r = 0; r < rows; ++r) sum += f2[r * BN + tid];
+    csum[tid] = sum;
+  }
+  __syncthreads();
+  if (tid < gn) {
+    Prob& Q = probs[lead + tid * gs];
+    const int q0 = Q.gcol0, q1 = tid + 1 < gn ? probs[lead + (tid + 1) * gs].gcol0 : L.gtot;
+    const int lo = q0 > n0 ? q0 : n0, hi = q1 < n0 + ncol ? q1 : n0 + ncol;
+    if (lo < hi) {
+      double sum = 0.0;
+      for (int c = lo; c < hi; ++c) sum += csum[c - n0];
+      const int first = q0 / BN, ntouch = (q1 - 1) / BN - first + 1;
+      Q.part[(m0 / BM) * ntouch + (n0 / BN - first)] = sum;
+    }
+  }
+  __syncthreads();  // the column table and the LDS are free for the next tile
+}
+
+using CfgGateW = ZCfg<kGateTileM, kGateTileW, 16, 2, 2>;
+static_assert(CfgGateW::lds_elems * sizeof(zt) >= kGateTileM * kGateTileW * sizeof(double) &&
+                  CfgGate::lds_elems * sizeof(zt) >= kGateTileM * kGateTileN * sizeof(double),
+              "the |A|^2 tile fits in the operand staging area");
+constexpr size_t kGateLds =
+    CfgGateW::lds_elems > CfgGate::lds_elems ? CfgGateW::lds_elems : CfgGate::lds_elems;
+
+__global__ __launch_bounds__(256, 2) void k_gate(Prob* probs, const int32_t* offs, int nprob) {
+  __shared__ zt smem[kGateLds];
+  __shared__ GateCol cols[kGateTileW];
+  __shared__ double csum[kGateTileW];
+  for_each_tile2<TK_GATE, TK_GATE_W>(
+      probs, offs, nprob, 1,
+      [&](Prob& P, int M, int N, int m0, int n0, int) {
+        gate_group_tile<CfgGate, true>(probs, int(&P - probs), M, N, m0, n0, smem, cols, csum);
+      },
+      [&](Prob& P, int M, int N, int m0, int n0, int) {
+        gate_group_tile<CfgGateW, false>(probs, int(&P - probs), M, N, m0, n0, smem, cols, csum);
+      });
 }
 
 hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s) {
   TEBD_LAUNCH("k_theta", k_theta, dim3(grid_for(c, TK_THETA)), dim3(256), 0, s, probs, c.offs, c.nprob);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  TEBD_LAUNCH("k_gate", k_gate, dim3(grid_for(c, TK_GATE)), dim3(256), 0, s, probs, c.offs, c.nprob);
+  TEBD_LAUNCH("k_gate", k_gate, dim3(grid_for(c, TK_GATE, TK_GATE_W)), dim3(256), 0, s, probs, c.offs,
+              c.nprob);
   return hipGetLastError();
 }
 

@@ -17,14 +17,33 @@
 namespace tebd {
 
 // --------------------------------------------------------------------------
-// TEBD sweep planning: one thread per (chain, bond of the parity).
+// TEBD sweep planning: one thread per (chain, bond of the parity), problems
+// numbered chain-major.  Chains that share a bond's gate form gate groups
+// (up to kGateGroup consecutive chains; their problems nb apart): the
+// group's Theta matrices sit side by side in one row-major block, and one
+// gate product covers all their columns, reading the gate once per output
+// tile instead of once per chain.  The Theta blocks are laid out bond-major.
+//
+// Columns chi_l chi_r of chain ch in its gate group (0 when its bond or
+// local dimensions are out of range: such a problem is skipped, and has no
+// columns in the group).
+__device__ __forceinline__ int group_cols(const tebd_mps& mps, int ch, int bond) {
+  const int32_t* chi = mps.chi + size_t(ch) * (mps.n_sites + 1);
+  const int cl = chi[bond], cm = chi[bond + 1], cr = chi[bond + 2], cap = mps.chi_max;
+  const int dl = mps.d[bond], dr = mps.d[bond + 1];
+  const bool ok = cl >= 1 && cl <= cap && cm >= 1 && cm <= cap && cr >= 1 && cr <= cap &&
+                  dl >= 1 && dl <= mps.d_max && dr >= 1 && dr <= mps.d_max;
+  return ok ? cl * cr : 0;
+}
+
 __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gates,
                              int64_t gate_chain_stride, int parity, int single_chain,
                              int single_bond, int kcap, int p_over, char* slab_base,
                              size_t slab_sz, int64_t mcap, int64_t ncap, int64_t lcap,
                              int64_t lslab, int64_t npart_cap, double* disc, int32_t* status,
                              double lambda_floor, int mixed, int adaptive, char* tape,
-                             size_t tape_stride, int32_t* retry_count) {
+                             size_t tape_stride, int32_t* retry_count, char* theta_base,
+                             size_t theta_stride) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p == 0 && retry_count) {
     *retry_count = 0;
@@ -34,13 +53,30 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
   if (p >= nprob) return;
   const int N = mps.n_sites, cap = mps.chi_max, dmax = mps.d_max;
   const int nb = (N - 1 - parity + 1) / 2;
-  int chain, bond;
+  int chain, bond, bi = 0;
   if (single_chain >= 0) {
     chain = single_chain;
     bond = single_bond;
   } else {
     chain = p / nb;
-    bond = parity + 2 * (p - chain * nb);
+    bi = p - chain * nb;
+    bond = parity + 2 * bi;
+  }
+  // gate group: chains c0 .. c0 + gsz - 1 of this bond when they share the
+  // gate, else this problem alone
+  int c0 = chain, gsz = 1;
+  if (single_chain < 0 && gate_chain_stride == 0) {
+    c0 = chain / kGateGroup * kGateGroup;
+    gsz = mps.n_chains - c0 < kGateGroup ? mps.n_chains - c0 : kGateGroup;
+  }
+  int gcol0 = 0, gtot = 0;
+#pragma unroll 8
+  for (int q = 0; q < kGateGroup; ++q) {
+    if (q < gsz) {
+      const int w = group_cols(mps, c0 + q, bond);
+      if (c0 + q < chain) gcol0 += w;
+      gtot += w;
+    }
   }
   Prob P;
   const int32_t* chi = mps.chi + size_t(chain) * (N + 1);
@@ -92,9 +128,14 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
   P.npart = 0;
   P.mixed = mixed;
   P.om_ext = 0;
-  P.pad0 = 0;
   P.frob2 = 0.0;
   carve_slab(P, slab_base + size_t(p) * slab_sz, mcap, ncap, lslab, 1, mixed, npart_cap);
+  P.gcol0 = gcol0;
+  P.gtot = gtot;
+  P.gn = chain == c0 ? gsz : 0;
+  P.gtw = gtot > kGateWideCols ? kGateTileW : kGateTileN;
+  P.gstride = nb;
+  P.T = reinterpret_cast<zt*>(theta_base + (size_t(bi) * mps.n_chains + c0) * theta_stride);
   P.lda = P.n;
   P.ldom = P.l;
   P.U = nullptr;
@@ -149,14 +190,16 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
                              int32_t single_bond, int32_t p_over, char* slab_base,
                              size_t slab_sz, double* disc, int32_t* status, double lambda_floor,
                              int32_t mixed, int32_t adaptive, char* tape, size_t tape_stride,
-                             int32_t* retry_count, int64_t lslab, hipStream_t s) {
+                             int32_t* retry_count, int64_t lslab, char* theta_base,
+                             size_t theta_stride, hipStream_t s) {
   const int64_t mcap = int64_t(c.dmax) * c.chimax;
   const int64_t lcap = c.lmax;
-  const int64_t npart_cap = gate_tiles(c.dmax * c.dmax, c.chimax * c.chimax);
+  const int64_t npart_cap = gate_partials_cap(c.dmax * c.dmax, c.chimax * c.chimax);
   TEBD_LAUNCH("k_plan_sweep", k_plan_sweep, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob, mps,
                      gates, gate_chain_stride, parity, single_chain, single_bond, c.kcap, p_over,
                      slab_base, slab_sz, mcap, mcap, lcap, lslab, npart_cap, disc, status,
-                     lambda_floor, mixed, adaptive, tape, tape_stride, retry_count);
+                     lambda_floor, mixed, adaptive, tape, tape_stride, retry_count, theta_base,
+                     theta_stride);
   return hipGetLastError();
 }
 
@@ -1576,8 +1619,7 @@ __global__ __launch_bounds__(64) void k_truncate(Prob* probs, double eps, int te
     int flags = P.flags;
     double frob2 = P.frob2;
     if (tebd) {
-      const int N = P.chi_l * P.chi_r, M = P.dl * P.dr;
-      const int npart = gate_tiles(M, N);
+      const int npart = gate_partials(P.dl * P.dr, P.gcol0, P.chi_l * P.chi_r, P.gtw);
       frob2 = 0.0;
       for (int i = 0; i < npart; ++i) frob2 += P.part[i];
       P.frob2 = frob2;
@@ -1722,7 +1764,7 @@ __global__ __launch_bounds__(256) void k_acc_resid(Prob* probs, double eps, int3
     mx = fmax(mx, sqrt(v));
   }
   double frob2 = 0.0;
-  const int npart = gate_tiles(P.dl * P.dr, P.chi_l * P.chi_r);
+  const int npart = gate_partials(P.dl * P.dr, P.gcol0, P.chi_l * P.chi_r, P.gtw);
   for (int i = 0; i < npart; ++i) frob2 += P.part[i];
   const double tol = sqrt(eps) * sqrt(frob2) / kAccConst;
   const bool grow = finite && mx > tol;

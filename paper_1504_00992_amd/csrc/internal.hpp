@@ -37,7 +37,7 @@ struct Prob {
   int32_t l1;                        // sketch width this stage started with
   int32_t l2;                        // sketch width of the fixed-rank stage
   int32_t retry;                     // 1: stage 1 rejected, stage 2 pending
-  int32_t pad0;
+  int32_t gcol0;                     // TEBD: first column of this problem in its gate group
   // Accuracy Check (adaptive rank 3): probe width (0: check finished), next
   // probe column of the Gaussian stream, capacity of the basis, and 1 while
   // the basis grew this round (its QR runs)
@@ -45,6 +45,12 @@ struct Prob {
   // Gram-based QR (CholeskyQR2) of the large problems: eligible in this
   // pipeline, and 1 while the current QR's Gram passes have succeeded
   int32_t chol, chol_ok;
+  // Gate groups (TEBD): consecutive problems of one bond that share its gate
+  // form one product G [Theta_1 | Theta_2 | ...] over all their columns.
+  // gtot: the group's columns (every member), gn: members (the first member
+  // only, else 0), gtw: the group's gate tile width (16 or 64), gstride: the
+  // distance between the descriptors of consecutive members
+  int32_t gtot, gn, gtw, gstride;
   double frob2;                      // ||A||_F^2, written on the device
   // input matrix (row-major, leading dim lda) and test matrix (row-major n x l)
   zt* A;
@@ -52,7 +58,8 @@ struct Prob {
   const zt* om;
   int64_t ldom;
   // scratch (inside the caller's workspace)
-  zt* T;         // TEBD: Theta before the gate, [(i' j')][(alpha beta)]
+  zt* T;         // TEBD: the gate group's Theta before the gate, [(i' j')][group column],
+                 // leading dimension gtot; this problem's columns start at gcol0
   zt* Y;         // m x l column-major (ld m): sketch, then Q
   zt* Yt;        // n x l column-major (ld n): A^H Q, then Q~ / Q_B
   zt* Rb;        // l x l column-major: R factor of B^H
@@ -95,7 +102,7 @@ struct Prob {
   int32_t tape_ldu, tape_ldvh;
 };
 
-constexpr int TK_COUNT_MAX = 14;  // tile kinds of the forward pipeline (enum below)
+constexpr int TK_COUNT_MAX = 15;  // tile kinds of the forward pipeline (enum below)
 
 // Parameters of a launch sequence that are common to all problems.
 struct Common {
@@ -118,7 +125,7 @@ struct Common {
   int32_t* retry_count;  // device: problems whose first stage was rejected (adaptive rank)
   int32_t* bounds_dev = nullptr;  // device: k_schedule writes {min, max} of m, n, l1 there,
                                   // then the tile total of every kind
-  int32_t ktiles[TK_COUNT_MAX] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
+  int32_t ktiles[TK_COUNT_MAX] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
   int32_t serial = 0;  // 1: size classes run in order on the caller's stream (no side streams)
@@ -175,7 +182,8 @@ enum {
   TK_GRAM = 11,  // Gram-based QR: l x l Gram matrices Y^H Y
   TK_QAPM = 12,  // Gram-based QR: m x l products Y R^-1
   TK_QAPN = 13,  // Gram-based QR: n x l products Yt R^-1
-  TK_COUNT = 14
+  TK_GATE_W = 14, // gate groups with many columns: 64 x 64 tiles
+  TK_COUNT = 15
 };
 
 static_assert(TK_COUNT == TK_COUNT_MAX, "Common::ktiles holds one total per kind");
@@ -185,13 +193,27 @@ static_assert(TK_COUNT == TK_COUNT_MAX, "Common::ktiles holds one total per kind
 // largest problem has max_rows rows and sketch width l (contract.hip).
 int sketch_variant(int precision, int max_rows, int width);
 
-// Output tile of the gate product, (dl dr) x (chi_l chi_r): tall and narrow,
-// because the gate side has a few dozen to a few hundred rows while the bond
-// side is often a single column (a 64 x 64 tile would spend almost all of
-// its FP64 matrix-core work on padding).  One Frobenius partial sum per tile.
-constexpr int kGateTileM = 64, kGateTileN = 16;
-__host__ __device__ inline int gate_tiles(int M, int N) {
-  return (M <= 0 || N <= 0) ? 0 : ((M + kGateTileM - 1) / kGateTileM) * ((N + kGateTileN - 1) / kGateTileN);
+// Output tiles of the gate product of a group, (dl dr) x (sum of chi_l chi_r
+// over its members): 64 rows, and 16 columns while the group has few
+// columns (early in an evolution most bonds have chi_l chi_r = 1, and a
+// 64 x 64 tile would spend almost all of its FP64 matrix-core work on
+// padding), else 64.  Members of at most kGateGroup consecutive chains.
+constexpr int kGateTileM = 64, kGateTileN = 16, kGateTileW = 64;
+constexpr int kGateGroup = 32;
+constexpr int kGateWideCols = 48;  // groups with more columns take the 64-wide tiles
+
+// Frobenius partial sums of one problem: one per (row tile, column tile
+// that holds some of its columns) of its group's gate product, in row-tile
+// major order.
+__host__ __device__ inline int gate_partials(int rows, int col0, int cols, int tw) {
+  if (rows <= 0 || cols <= 0 || tw <= 0) return 0;
+  const int rt = (rows + kGateTileM - 1) / kGateTileM;
+  return rt * ((col0 + cols - 1) / tw - col0 / tw + 1);
+}
+// Capacity: a member's columns start anywhere in a 16-wide tile.
+__host__ __device__ inline int gate_partials_cap(int rows, int cols) {
+  if (rows <= 0 || cols <= 0) return 0;
+  return ((rows + kGateTileM - 1) / kGateTileM) * ((cols + kGateTileN - 1) / kGateTileN + 1);
 }
 
 inline size_t sched_bytes(int64_t nprob) { return size_t(TK_COUNT) * size_t(nprob + 1) * sizeof(int32_t); }
@@ -217,7 +239,8 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
                              int32_t single_bond, int32_t p_over, char* slab_base,
                              size_t slab_bytes, double* disc, int32_t* status, double lambda_floor,
                              int32_t mixed, int32_t adaptive, char* tape, size_t tape_stride,
-                             int32_t* retry_count, int64_t lslab, hipStream_t s);
+                             int32_t* retry_count, int64_t lslab, char* theta_base,
+                             size_t theta_stride, hipStream_t s);
 hipError_t launch_stage2(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_schedule(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s);
@@ -261,10 +284,7 @@ __host__ __device__ inline size_t slab_bytes(int64_t m, int64_t n, int64_t l, in
                                              int64_t npart) {
   size_t b = 0;
   const size_t z = sizeof(zt);
-  if (tebd) {
-    b += align256(m * n * z);  // A
-    b += align256(m * n * z);  // T
-  }
+  if (tebd) b += align256(m * n * z);  // A (a TEBD sweep keeps Theta in a region of its own)
   // with the Gram-based QR, Y, Yt and Qc trade places: each holds max(m, n) rows
   const int64_t rows_y = (!tebd || mixed) && n > m ? n : m;
   const int64_t rows_yt = (!tebd || mixed) && m > n ? m : n;
@@ -285,13 +305,10 @@ __host__ __device__ inline void carve_slab(Prob& p, char* base, int64_t m, int64
                                            int tebd, int mixed, int64_t npart) {
   const size_t z = sizeof(zt);
   char* c = base;
+  p.T = nullptr;
   if (tebd) {
     p.A = reinterpret_cast<zt*>(c);
     c += align256(m * n * z);
-    p.T = reinterpret_cast<zt*>(c);
-    c += align256(m * n * z);
-  } else {
-    p.T = nullptr;
   }
   p.om = reinterpret_cast<const zt*>(c);
   c += align256(n * l * z);

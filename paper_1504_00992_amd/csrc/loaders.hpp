@@ -53,6 +53,19 @@ struct StTheta {
   }
 };
 
+// Theta of one member into its gate group's block: row (i j), column
+// col0 + (a chi_r + b), leading dimension ld (the group's columns).
+struct StThetaGroup {
+  zt* T;
+  int64_t ld;
+  int col0, chi_l, chi_r, dr;
+  __device__ void operator()(int r, int c, zt v) {
+    const int i = r / chi_l, a = r - i * chi_l;
+    const int j = c / chi_r, b = c - j * chi_r;
+    T[(size_t(i) * dr + j) * ld + col0 + size_t(a) * chi_r + b] = v;
+  }
+};
+
 struct LdRowB {  // B[k][c] = p[k*ld + c]
   const zt* p;
   int64_t ld;
