@@ -140,8 +140,8 @@ class Work:
         c = chi_new
         if not form:
             return
-        self.add("k_form_u<1>", 8.0 * m * l * c, 16.0 * (m * l + l * c + m * c))
-        self.add("k_form_vh<1>", 8.0 * n * l * c, 16.0 * (n * l + l * c + n * c))
+        self.add("k_form_uv<1>", 8.0 * (m + n) * l * c,
+                 16.0 * (m * l + l * c + m * c) + 16.0 * (n * l + l * c + n * c))
 
 
 def first_stage_rank(chi_mid, chi_max):
@@ -581,9 +581,8 @@ def batched_rrsvd_line(args, torch, api, wl, lib):
     for n, c in zip(sizes, chi):
         w.add("k_frob", 0.0, 16.0 * n * n)
         w.rrsvd_pass(n, n, l, 2, False, int(c))
-    for k in ("k_form_u<1>", "k_form_vh<1>"):   # the standalone call writes plain U, V^H
-        if k in w.k:
-            w.k[k.replace("<1>", "<0>")] = w.k.pop(k)
+    if "k_form_uv<1>" in w.k:   # the standalone call writes plain U, V^H
+        w.k["k_form_uv<0>"] = w.k.pop("k_form_uv<1>")
     sk_ms = sum(v[0] for k, v in prof.items() if k.startswith(("k_sketch<", "k_sketch_wide<")))
     sk_fl = sum(v[0] for k, v in w.k.items() if k.startswith("k_sketch<"))
     ach = sk_fl / (sk_ms * 1e-3) / 1e12 if sk_ms > 0 else None
@@ -847,9 +846,8 @@ def table2_line(args, torch, api, wl, lib):
         for c in chi:
             w.add("k_frob", 0.0, 16.0 * n * n)
             w.rrsvd_pass(n, n, 200, 2, False, int(c))
-        for k in ("k_form_u<1>", "k_form_vh<1>"):
-            if k in w.k:
-                w.k[k.replace("<1>", "<0>")] = w.k.pop(k)
+        if "k_form_uv<1>" in w.k:
+            w.k["k_form_uv<0>"] = w.k.pop("k_form_uv<1>")
         out["sizes"][str(n)] = {"value": round(per, 5),
                                 "paper_gpu_rrsvd_s_k20s": PAPER_TABLE2_GPU_RRSVD_S[n],
                                 "roofline": kernel_roofline(prof, w, f"table2_{n}")}

@@ -176,23 +176,38 @@ hipError_t upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
 }
 
 // Reads of small device counters through pinned host memory (one buffer per
-// host thread): counters_async enqueues the copy of n <= 64 values on s,
+// host thread): counters_async enqueues the copy of n <= 32 values on s,
 // counters_wait blocks until it has landed.  One read at a time per thread.
+// The size bounds and tile totals of a batch take another route: k_schedule
+// stores them straight into slots kBoundsSlot.. of the same (coherent,
+// device-mapped) buffer, and the host waits for an event after it.
 struct PinnedCounters {
-  int32_t* buf = nullptr;
+  int32_t* buf = nullptr;   // host view
+  int32_t* dbuf = nullptr;  // device view of the same memory
   hipEvent_t done = nullptr;
+  hipEvent_t bounds = nullptr;
 };
+constexpr int kBoundsSlot = 32;
 
 PinnedCounters& pinned_counters() {
   static thread_local PinnedCounters pc;
   return pc;
 }
 
+hipError_t pinned_init(PinnedCounters& pc) {
+  hipError_t e = hipSuccess;
+  if (!pc.buf)
+    e = hipHostMalloc(reinterpret_cast<void**>(&pc.buf), 256,
+                      hipHostMallocMapped | hipHostMallocPortable | hipHostMallocCoherent);
+  if (e == hipSuccess && !pc.dbuf) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&pc.dbuf), pc.buf, 0);
+  if (e == hipSuccess && !pc.done) e = hipEventCreateWithFlags(&pc.done, hipEventDisableTiming);
+  if (e == hipSuccess && !pc.bounds) e = hipEventCreateWithFlags(&pc.bounds, hipEventDisableTiming);
+  return e;
+}
+
 hipError_t counters_async(const int32_t* dev, int n, hipStream_t s) {
   PinnedCounters& pc = pinned_counters();
-  hipError_t e = hipSuccess;
-  if (!pc.buf) e = hipHostMalloc(reinterpret_cast<void**>(&pc.buf), 256, hipHostMallocDefault);
-  if (e == hipSuccess && !pc.done) e = hipEventCreateWithFlags(&pc.done, hipEventDisableTiming);
+  hipError_t e = pinned_init(pc);
   if (e == hipSuccess) e = hipMemcpyAsync(pc.buf, dev, size_t(n) * sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipEventRecord(pc.done, s);
   return e;
@@ -203,6 +218,24 @@ hipError_t counters_wait(int32_t* out, int n) {
   hipError_t e = hipEventSynchronize(pc.done);
   if (e == hipSuccess)
     for (int i = 0; i < n; ++i) out[i] = pc.buf[i];
+  return e;
+}
+
+// Device address k_schedule writes the bounds to (host-mapped memory).
+hipError_t bounds_target(int32_t** dev) {
+  PinnedCounters& pc = pinned_counters();
+  hipError_t e = pinned_init(pc);
+  if (e == hipSuccess) *dev = pc.dbuf + kBoundsSlot;
+  return e;
+}
+
+hipError_t bounds_ready(hipStream_t s) { return hipEventRecord(pinned_counters().bounds, s); }
+
+hipError_t bounds_wait(int32_t* out, int n) {
+  PinnedCounters& pc = pinned_counters();
+  hipError_t e = hipEventSynchronize(pc.bounds);
+  if (e == hipSuccess)
+    for (int i = 0; i < n; ++i) out[i] = reinterpret_cast<volatile int32_t*>(pc.buf)[kBoundsSlot + i];
   return e;
 }
 
@@ -342,7 +375,7 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
   if (c.chol && tebd_size_class(0, std::max(c.mmax, c.nmax), c.lmax) >= 2)
     TIMED(PK_SCHEDULE, launch_chol_mark(probs, c, s));
   TIMED(PK_SCHEDULE, launch_schedule(probs, c, s));
-  if (c.bounds_dev) TRY(counters_async(c.bounds_dev, 6 + TK_COUNT, s));
+  if (c.bounds_dev) TRY(bounds_ready(s));
   if (c.tebd) {
     if (!c.pass2) TIMED(PK_THETA_GATE, launch_theta_gate(probs, c, s));
   } else {
@@ -357,7 +390,8 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
   TIMED(PK_SKETCH_AOM, sketch(SK_Y_FROM_OMEGA));
   if (c.bounds_dev) {
     int32_t b[6 + TK_COUNT];
-    TRY(counters_wait(b, 6 + TK_COUNT));
+    static_assert(kBoundsSlot + 6 + TK_COUNT <= 64, "bounds fit the pinned buffer");
+    TRY(bounds_wait(b, 6 + TK_COUNT));
     c.mmin = b[0];
     c.mmax = b[1];
     c.nmin = b[2];
@@ -384,21 +418,26 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
   TRY(qr_step(0, 1));
   if (c.acc_count) {
     // Accuracy Check rounds: probe, decide, orthonormalise the grown bases;
-    // the host reads how many problems still probe after each round
+    // the host reads how many problems still probe after each round, and
+    // the widest basis, which bounds the QR classes of the next launches
+    // (a round grows a basis by at most acc_r columns)
     Common ca = c;
-    // a grown basis may reach a larger QR class: up to the capacity
-    ca.lmax = std::min(c.acc_lcap, std::min(c.mmax, c.nmax));
+    const int32_t cap = std::min(c.acc_lcap, std::min(c.mmax, c.nmax));
+    int32_t widest = c.lmax;
     ca.lmin = 1;
     for (int round = 0;; ++round) {
+      ca.lmax = std::min(cap, widest + c.acc_r);
       TIMED(PK_ACC, launch_acc_probe(probs, ca, s));
       TIMED(PK_ACC, launch_acc_resid(probs, ca, round, s));
       TIMED(PK_QR, launch_qr(probs, ca, 0, 0, 0, s, 1));
-      int32_t active = 0;
-      TRY(read_counter(c.acc_count + (round & 1), &active, s));
-      if (active == 0) break;
+      int32_t cnt[3] = {0, 0, 0};
+      TRY(counters_async(c.acc_count, 3, s));
+      TRY(counters_wait(cnt, 3));
+      widest = std::max(1, std::min(cap, cnt[2]));
+      if (cnt[round & 1] == 0) break;
     }
-    // the sketch widths changed: tile counts anew, QR classes up to the capacity
-    c.lmax = ca.lmax;
+    // the sketch widths changed: tile counts anew, QR classes up to the widest basis
+    c.lmax = widest;
     c.lmin = 1;
     for (int k = 0; k < TK_COUNT; ++k) c.ktiles[k] = -1;
     Common cr = c;
@@ -419,6 +458,8 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
     TIMED(PK_SMALL_SVD, launch_small_svd(probs, cs, s));
   }
   TIMED(PK_TRUNCATE, launch_truncate(probs, c, s));
+  // the host's read of the rejected first stages lands while U and V^H form
+  if (c.retry_read) TRY(counters_async(c.retry_count, 1, s));
   TIMED(PK_FORM_UV, launch_form_uv(probs, c, s));
   if (c.record) TIMED(PK_TAPE, launch_tape(probs, c, s));
 #undef TIMED
@@ -491,15 +532,19 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   if (c.adaptive == 3) {
     c.acc_count = c.retry_count + kAccCountSlot;
     c.acc_lcap = int32_t(pl.lcap);
+    c.acc_r = std::max(1, std::min(prm->p, kAccMaxR));
   }
   if (c.adaptive == 2 || c.adaptive == 3) {
-    c.bounds_dev = c.retry_count + 4;
+    if (bounds_target(&c.bounds_dev) != hipSuccess)
+      return fail(TEBD_ERR_DEVICE, "cannot map the pinned buffer of the size bounds");
     for (int k = 0; k < TK_COUNT; ++k) {
       const int32_t t = last_tiles[parity & 1][k];
       c.ktiles[k] = t < 0 ? -1 : t + t / 4;
     }
   }
+  c.retry_read = c.adaptive == 2;
   if (e == hipSuccess) e = run_pipeline(probs, c, s);
+  c.retry_read = 0;
   if (c.bounds_dev) {
     for (int k = 0; k < TK_COUNT; ++k) last_tiles[parity & 1][k] = c.ktiles[k];
     // the second pass runs the fixed-rank stage: width min(chi_max + p, m, n)
@@ -511,9 +556,10 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   }
   bool second = c.adaptive == 1 || c.adaptive == 2;
   if (e == hipSuccess && c.adaptive == 2) {
-    // read the number of rejected first stages back and skip an empty pass
+    // the number of rejected first stages (its copy was enqueued after the
+    // truncation): an empty second pass is skipped
     int32_t n_retry = 0;
-    e = read_counter(c.retry_count, &n_retry, s);
+    e = counters_wait(&n_retry, 1);
     second = n_retry > 0;
   }
   if (e == hipSuccess && second) {

@@ -660,53 +660,54 @@ struct StGammaR {  // Gamma'_k+1[j][g][b] = V^H[g, (j,b)] / lam_r[b]
 
 // Tiles entirely beyond chi' only write zeros (no contraction).  In TEBD the
 // column range is the padded MPS capacity, so stale entries are cleared.
+// U and V^H are independent: one launch walks the tiles of both.
 template <int TEBD_>
-__global__ __launch_bounds__(256) void k_form_u(Prob* probs, const int32_t* offs, int nprob) {
-  __shared__ zt smem[CfgSk::lds_elems];
-  for_each_tile<TK_FORMU>(probs, offs, nprob, TEBD_, [&](Prob& P, int M, int N, int m0, int n0, int) {
-    if (P.retry) return;  // adaptive rank: stage 2 will write this problem
-    const int chi = P.chi_new;
-    const int Keff = (n0 >= chi) ? 0 : P.l;
-    LdQP la{P.Y, P.m, P.piv};
-    LdSmallColB lb{P.X, P.l};
-    if (TEBD_) {
-      StGammaL st{P.gk, P.lam_l, P.lambda_floor, P.chi_l, P.chi_cap, chi};
-      zgemm_tile<CfgSk>(M, N, Keff, m0, n0, la, lb, st, smem);
-    } else {
-      StU st{P.U, P.ldu, chi};
-      zgemm_tile<CfgSk>(M, N, Keff, m0, n0, la, lb, st, smem);
-    }
-  });
+__device__ __forceinline__ void form_u_tile(Prob& P, int M, int N, int m0, int n0, zt* smem) {
+  if (P.retry) return;  // adaptive rank: stage 2 will write this problem
+  const int chi = P.chi_new;
+  const int Keff = (n0 >= chi) ? 0 : P.l;
+  LdQP la{P.Y, P.m, P.piv};
+  LdSmallColB lb{P.X, P.l};
+  if (TEBD_) {
+    StGammaL st{P.gk, P.lam_l, P.lambda_floor, P.chi_l, P.chi_cap, chi};
+    zgemm_tile<CfgSk>(M, N, Keff, m0, n0, la, lb, st, smem);
+  } else {
+    StU st{P.U, P.ldu, chi};
+    zgemm_tile<CfgSk>(M, N, Keff, m0, n0, la, lb, st, smem);
+  }
 }
 
 template <int TEBD_>
-__global__ __launch_bounds__(256) void k_form_vh(Prob* probs, const int32_t* offs, int nprob) {
+__device__ __forceinline__ void form_vh_tile(Prob& P, int M, int N, int m0, int n0, zt* smem) {
+  if (P.retry) return;
+  const int chi = P.chi_new;
+  const int Keff = (m0 >= chi) ? 0 : P.l;
+  LdSmallAdjA la{P.W, P.l};
+  LdQbAdjB lb{P.Yt, P.n};
+  if (TEBD_) {
+    StGammaR st{P.gk1, P.lam_r, P.lambda_floor, P.chi_r, P.chi_cap, chi};
+    zgemm_tile<CfgSk>(M, N, Keff, m0, n0, la, lb, st, smem);
+  } else {
+    StVH st{P.VH, P.ldvh, chi};
+    zgemm_tile<CfgSk>(M, N, Keff, m0, n0, la, lb, st, smem);
+  }
+}
+
+template <int TEBD_>
+__global__ __launch_bounds__(256) void k_form_uv(Prob* probs, const int32_t* offs, int nprob) {
   __shared__ zt smem[CfgSk::lds_elems];
-  for_each_tile<TK_FORMV>(probs, offs, nprob, TEBD_, [&](Prob& P, int M, int N, int m0, int n0, int) {
-    if (P.retry) return;  // adaptive rank: stage 2 will write this problem
-    const int chi = P.chi_new;
-    const int Keff = (m0 >= chi) ? 0 : P.l;
-    LdSmallAdjA la{P.W, P.l};
-    LdQbAdjB lb{P.Yt, P.n};
-    if (TEBD_) {
-      StGammaR st{P.gk1, P.lam_r, P.lambda_floor, P.chi_r, P.chi_cap, chi};
-      zgemm_tile<CfgSk>(M, N, Keff, m0, n0, la, lb, st, smem);
-    } else {
-      StVH st{P.VH, P.ldvh, chi};
-      zgemm_tile<CfgSk>(M, N, Keff, m0, n0, la, lb, st, smem);
-    }
-  });
+  for_each_tile2<TK_FORMU, TK_FORMV>(
+      probs, offs, nprob, TEBD_,
+      [&](Prob& P, int M, int N, int m0, int n0, int) { form_u_tile<TEBD_>(P, M, N, m0, n0, smem); },
+      [&](Prob& P, int M, int N, int m0, int n0, int) { form_vh_tile<TEBD_>(P, M, N, m0, n0, smem); });
 }
 
 hipError_t launch_form_uv(Prob* probs, const Common& c, hipStream_t s) {
-  const dim3 gu(grid_for(c, TK_FORMU)), gv(grid_for(c, TK_FORMV));
-  if (c.tebd) {
-    TEBD_LAUNCH("k_form_u<1>", k_form_u<1>, gu, dim3(256), 0, s, probs, c.offs, c.nprob);
-    TEBD_LAUNCH("k_form_vh<1>", k_form_vh<1>, gv, dim3(256), 0, s, probs, c.offs, c.nprob);
-  } else {
-    TEBD_LAUNCH("k_form_u<0>", k_form_u<0>, gu, dim3(256), 0, s, probs, c.offs, c.nprob);
-    TEBD_LAUNCH("k_form_vh<0>", k_form_vh<0>, gv, dim3(256), 0, s, probs, c.offs, c.nprob);
-  }
+  const dim3 g(grid_for(c, TK_FORMU, TK_FORMV));
+  if (c.tebd)
+    TEBD_LAUNCH("k_form_uv<1>", k_form_uv<1>, g, dim3(256), 0, s, probs, c.offs, c.nprob);
+  else
+    TEBD_LAUNCH("k_form_uv<0>", k_form_uv<0>, g, dim3(256), 0, s, probs, c.offs, c.nprob);
   return hipGetLastError();
 }
 

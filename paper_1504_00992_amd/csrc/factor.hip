@@ -44,40 +44,52 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
                              double lambda_floor, int mixed, int adaptive, char* tape,
                              size_t tape_stride, int32_t* retry_count, char* theta_base,
                              size_t theta_stride) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p == 0 && retry_count) {
+  // Threads run group by group: a group's chains are the lanes of one
+  // aligned kGateGroup-lane segment of a wavefront, so its column offsets
+  // are a segmented prefix sum over the lanes.
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0 && retry_count) {
     *retry_count = 0;
     retry_count[kAccCountSlot] = 0;  // the Accuracy Check's two round counters
     retry_count[kAccCountSlot + 1] = 0;
+    retry_count[kAccCountSlot + 2] = 0;  // and its widest basis
   }
-  if (p >= nprob) return;
   const int N = mps.n_sites, cap = mps.chi_max, dmax = mps.d_max;
   const int nb = (N - 1 - parity + 1) / 2;
-  int chain, bond, bi = 0;
+  int chain, bond, bi = 0, p = 0;
+  bool live;
   if (single_chain >= 0) {
     chain = single_chain;
     bond = single_bond;
+    live = t == 0;
   } else {
-    chain = p / nb;
-    bi = p - chain * nb;
+    const int ncb = (mps.n_chains + kGateGroup - 1) / kGateGroup;
+    const int g = t / kGateGroup;
+    bi = g / ncb;
+    chain = (g - bi * ncb) * kGateGroup + (t - g * kGateGroup);
     bond = parity + 2 * bi;
+    live = bi < nb && chain < mps.n_chains;
+    p = chain * nb + bi;
   }
+  const int w = live ? group_cols(mps, chain, bond) : 0;
+  int incl = w;
+#pragma unroll
+  for (int off = 1; off < kGateGroup; off <<= 1) {
+    const int v = __shfl_up(incl, off, kGateGroup);
+    if ((threadIdx.x & (kGateGroup - 1)) >= off) incl += v;
+  }
+  int gtot = __shfl(incl, kGateGroup - 1, kGateGroup), gcol0 = incl - w;
   // gate group: chains c0 .. c0 + gsz - 1 of this bond when they share the
   // gate, else this problem alone
   int c0 = chain, gsz = 1;
   if (single_chain < 0 && gate_chain_stride == 0) {
     c0 = chain / kGateGroup * kGateGroup;
     gsz = mps.n_chains - c0 < kGateGroup ? mps.n_chains - c0 : kGateGroup;
+  } else {
+    gcol0 = 0;
+    gtot = w;
   }
-  int gcol0 = 0, gtot = 0;
-#pragma unroll 8
-  for (int q = 0; q < kGateGroup; ++q) {
-    if (q < gsz) {
-      const int w = group_cols(mps, c0 + q, bond);
-      if (c0 + q < chain) gcol0 += w;
-      gtot += w;
-    }
-  }
+  if (!live || p >= nprob) return;
   Prob P;
   const int32_t* chi = mps.chi + size_t(chain) * (N + 1);
   const int cl = chi[bond], cm = chi[bond + 1], cr = chi[bond + 2];
@@ -195,7 +207,14 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
   const int64_t mcap = int64_t(c.dmax) * c.chimax;
   const int64_t lcap = c.lmax;
   const int64_t npart_cap = gate_partials_cap(c.dmax * c.dmax, c.chimax * c.chimax);
-  TEBD_LAUNCH("k_plan_sweep", k_plan_sweep, dim3((c.nprob + 63) / 64), dim3(64), 0, s, probs, c.nprob, mps,
+  // one kGateGroup-lane segment per (bond, block of kGateGroup chains)
+  int64_t threads = 1;
+  if (single_chain < 0) {
+    const int64_t nb = c.nprob / mps.n_chains, ncb = (mps.n_chains + kGateGroup - 1) / kGateGroup;
+    threads = nb * ncb * kGateGroup;
+  }
+  static_assert(64 % kGateGroup == 0, "segments do not straddle wavefronts");
+  TEBD_LAUNCH("k_plan_sweep", k_plan_sweep, dim3((threads + 63) / 64), dim3(64), 0, s, probs, c.nprob, mps,
                      gates, gate_chain_stride, parity, single_chain, single_bond, c.kcap, p_over,
                      slab_base, slab_sz, mcap, mcap, lcap, lslab, npart_cap, disc, status,
                      lambda_floor, mixed, adaptive, tape, tape_stride, retry_count, theta_base,
@@ -1721,33 +1740,43 @@ __global__ __launch_bounds__(256) void k_acc_resid(Prob* probs, double eps, int3
   const zt* B = P.Y + size_t(l) * m;
   __shared__ zt cs[kMaxL * kAccMaxR];  // C = Q^H B, l x r, column j of Q in row j
   __shared__ double part[4][kAccMaxR];
-  for (int j = tid; j < l; j += 256) {
+  // one wavefront per column of Q, its lanes over the rows
+  for (int j = wave; j < l; j += 4) {
     double cr[kAccMaxR], ci[kAccMaxR];
 #pragma unroll
     for (int i = 0; i < kAccMaxR; ++i) cr[i] = ci[i] = 0.0;
     const zt* qj = Q + size_t(j) * m;
-    for (int row = 0; row < m; ++row) {
+    for (int row = lane; row < m; row += 64) {
       const zt q = qj[row];
 #pragma unroll
       for (int i = 0; i < kAccMaxR; ++i)
         if (i < r) zdot_acc(q, B[size_t(i) * m + row], cr[i], ci[i]);
     }
 #pragma unroll
-    for (int i = 0; i < kAccMaxR; ++i)
-      if (i < r) cs[j * kAccMaxR + i] = make_double2(cr[i], ci[i]);
+    for (int i = 0; i < kAccMaxR; ++i) {
+      if (i >= r) break;  // uniform
+      const double xr = wave_sum(cr[i]), xi = wave_sum(ci[i]);
+      if (lane == 0) cs[j * kAccMaxR + i] = make_double2(xr, xi);
+    }
   }
   __syncthreads();
   double nrm[kAccMaxR];
 #pragma unroll
   for (int i = 0; i < kAccMaxR; ++i) nrm[i] = 0.0;
   for (int row = tid; row < m; row += 256) {
+    zt d[kAccMaxR];  // row `row` of B - Q C, every Q entry read once
 #pragma unroll
-    for (int i = 0; i < kAccMaxR; ++i) {
-      if (i >= r) continue;
-      zt d = B[size_t(i) * m + row];
-      for (int j = 0; j < l; ++j) d = zsub(d, zmul(Q[size_t(j) * m + row], cs[j * kAccMaxR + i]));
-      nrm[i] += zabs2(d);
+    for (int i = 0; i < kAccMaxR; ++i)
+      d[i] = i < r ? B[size_t(i) * m + row] : make_double2(0.0, 0.0);
+    for (int j = 0; j < l; ++j) {
+      const zt q = Q[size_t(j) * m + row];
+#pragma unroll
+      for (int i = 0; i < kAccMaxR; ++i)
+        if (i < r) d[i] = zsub(d[i], zmul(q, cs[j * kAccMaxR + i]));
     }
+#pragma unroll
+    for (int i = 0; i < kAccMaxR; ++i)
+      if (i < r) nrm[i] += zabs2(d[i]);
   }
 #pragma unroll
   for (int i = 0; i < kAccMaxR; ++i) {
@@ -1776,6 +1805,7 @@ __global__ __launch_bounds__(256) void k_acc_resid(Prob* probs, double eps, int3
     if (w <= 0) {
       P.flags |= TEBD_DEV_ACC_CAPPED;
       P.ac_r = 0;
+      atomicMax(count + 2, P.l1);
       return;
     }
     lnew = l + w;
@@ -1784,6 +1814,7 @@ __global__ __launch_bounds__(256) void k_acc_resid(Prob* probs, double eps, int3
     P.ac_grow = 1;
   }
   P.ac_col += r;
+  atomicMax(count + 2, P.l1);  // the widest pass so far (it sets the QR classes of later launches)
   if (grow && lnew <= P.n - r)
     atomicAdd(count + (round & 1), 1);
   else

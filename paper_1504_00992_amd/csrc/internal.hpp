@@ -123,14 +123,18 @@ struct Common {
   int32_t record;    // 1: write the adjoint's tape
   int32_t nsites;    // TEBD: sites per chain
   int32_t* retry_count;  // device: problems whose first stage was rejected (adaptive rank)
-  int32_t* bounds_dev = nullptr;  // device: k_schedule writes {min, max} of m, n, l1 there,
-                                  // then the tile total of every kind
+  int32_t* bounds_dev = nullptr;  // host-mapped pinned memory: k_schedule writes {min, max}
+                                  // of m, n, l1 there, then the tile total of every kind
   int32_t ktiles[TK_COUNT_MAX] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
   int32_t serial = 0;  // 1: size classes run in order on the caller's stream (no side streams)
-  int32_t* acc_count = nullptr;  // device: Accuracy Check, two counters of problems still probing
+  // device: Accuracy Check, two counters of problems still probing (the
+  // rounds alternate), then the widest basis so far
+  int32_t* acc_count = nullptr;
   int32_t acc_lcap = 0;          // Accuracy Check: largest basis width (QR classes)
+  int32_t acc_r = 0;             // Accuracy Check: probe width
+  int32_t retry_read = 0;        // enqueue the host read of *retry_count after the truncation
   int32_t chol = 0;              // 1: Gram-based QR (CholeskyQR2) for the large problems
 };
 

@@ -51,8 +51,7 @@ def test_first_stage_width_and_kernel_counts():
     assert piv[0] == b.qr_flops(m, l) + b.qr_flops(n, l)
     assert unp[0] == 2 * (b.qr_flops(m, l) + b.qr_flops(n, l))
     assert piv[1] == b.qr_bytes(m, l) + b.qr_bytes(n, l, with_r=True)
-    assert k["k_form_u<1>"][0] == 8.0 * m * l * 21
-    assert k["k_form_vh<1>"][0] == 8.0 * n * l * 21
+    assert k["k_form_uv<1>"][0] == 8.0 * (m + n) * l * 21
 
 
 def test_second_pass_and_fixed_rank_widths():
@@ -67,7 +66,7 @@ def test_second_pass_and_fixed_rank_widths():
     assert k["k_sketch<0>"][0] == 8.0 * m * n * (l1 + l2)
     assert k["k_omega"][1] == 16.0 * n * (l1 + l2)
     # U and V^H are formed once, by the pass whose result is kept
-    assert k["k_form_u<1>"][0] == 8.0 * m * l2 * 19
+    assert k["k_form_uv<1>"][0] == 8.0 * (m + n) * l2 * 19
     fixed = _sweep(b, before, after, np.zeros(3, dtype=np.int32), 1, adaptive=False)
     assert fixed["k_sketch<0>"][0] == 8.0 * m * n * l2
     # small bonds: chi = 1 -> k1 = 5 -> l1 = 10 (capped by m = n = 10 here)
