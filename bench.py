@@ -220,7 +220,7 @@ def measured_traffic(kernel, workload):
     return None, os.path.basename(path)
 
 
-ALU_KERNELS = ("k_qr_", "k_svd_pairs", "k_small_svd", "k_truncate", "k_omega", "k_schedule",
+ALU_KERNELS = ("k_qr_", "k_svd_pairs", "k_small_svd", "k_omega", "k_schedule",
                "k_plan", "k_stage2", "k_frob")
 
 

@@ -248,12 +248,12 @@ hipError_t read_counter(const int32_t* dev, int32_t* out, hipStream_t s) {
 // Optional per-kernel event timing (tebd_profile_enable / tebd_profile_read).
 enum ProfKind {
   PK_PLAN, PK_SCHEDULE, PK_THETA_GATE, PK_FROB, PK_OMEGA, PK_SKETCH_AOM, PK_SKETCH_AHQ,
-  PK_SKETCH_AQT, PK_QR, PK_QR_R, PK_SMALL_SVD, PK_TRUNCATE, PK_FORM_UV, PK_STAGE2, PK_TAPE,
+  PK_SKETCH_AQT, PK_QR, PK_QR_R, PK_SMALL_SVD, PK_FORM_UV, PK_STAGE2, PK_TAPE,
   PK_ADJOINT, PK_ACC, PK_COUNT
 };
 const char* const kProfNames[PK_COUNT] = {
     "plan_sweep", "schedule",  "theta_gate", "frobenius",  "omega",    "sketch_A_Omega",
-    "sketch_AH_Q", "sketch_A_Qt", "qr",       "qr_with_r", "small_svd", "truncate",
+    "sketch_AH_Q", "sketch_A_Qt", "qr",       "qr_with_r", "small_svd",
     "form_u_vh", "stage2_prep", "tape", "adjoint_sweep", "accuracy_check"};
 
 struct Profiler {
@@ -372,7 +372,8 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
     if (e != hipSuccess) return e; \
   } while (0)
 #define TIMED(kind, call) TRY(timed(kind, s, [&]() { return (call); }))
-  if (c.chol && tebd_size_class(0, std::max(c.mmax, c.nmax), c.lmax) >= 2)
+  // (the sweep planner marks the large problems of a sweep's first pass itself)
+  if ((c.pass2 || !c.tebd) && c.chol && tebd_size_class(0, std::max(c.mmax, c.nmax), c.lmax) >= 2)
     TIMED(PK_SCHEDULE, launch_chol_mark(probs, c, s));
   TIMED(PK_SCHEDULE, launch_schedule(probs, c, s));
   if (c.bounds_dev) TRY(bounds_ready(s));
@@ -453,11 +454,12 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
   TIMED(PK_SKETCH_AHQ, launch_sketch(probs, c, SK_YT_FROM_Y, s));  // B^H = A^H Q
   TIMED(PK_QR_R, launch_qr(probs, c, 1, 1, 1, s));                 // B^H P = Q_B R_B
   {
-    Common cs = c;  // the small SVD works on the revealed rank, anywhere in [1, l1]
+    // the small SVD works on the revealed rank, anywhere in [1, l1]; each
+    // launch ends with the truncation of its problems
+    Common cs = c;
     cs.lmin = 1;
     TIMED(PK_SMALL_SVD, launch_small_svd(probs, cs, s));
   }
-  TIMED(PK_TRUNCATE, launch_truncate(probs, c, s));
   // the host's read of the rejected first stages lands while U and V^H form
   if (c.retry_read) TRY(counters_async(c.retry_count, 1, s));
   TIMED(PK_FORM_UV, launch_form_uv(probs, c, s));
@@ -512,14 +514,6 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   Prob* probs = reinterpret_cast<Prob*>(ws);
   char* slabs = reinterpret_cast<char*>(ws) + pl.desc_bytes;
-  hipError_t e = timed(PK_PLAN, s, [&]() {
-    return launch_plan_sweep(probs, c, *mps, reinterpret_cast<const zt*>(gates), gate_chain_stride,
-                             parity, single_chain, single_bond, prm->p, slabs, pl.slab_sz, disc,
-                             status, prm->lambda_floor, prm->precision, prm->adaptive,
-                             reinterpret_cast<char*>(tape), pl.tape_slot, c.retry_count,
-                             pl.lslab, reinterpret_cast<char*>(ws) + pl.theta_off, pl.theta_sz,
-                             s);
-  });
   // The host-synchronising adaptive mode also reads the batch's size bounds
   // and tile totals.  Until they arrive, the grids of the first contractions
   // follow the totals of the previous sweep of this parity on this host
@@ -542,6 +536,14 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
       c.ktiles[k] = t < 0 ? -1 : t + t / 4;
     }
   }
+  hipError_t e = timed(PK_PLAN, s, [&]() {
+    return launch_plan_sweep(probs, c, *mps, reinterpret_cast<const zt*>(gates), gate_chain_stride,
+                             parity, single_chain, single_bond, prm->p, slabs, pl.slab_sz, disc,
+                             status, prm->lambda_floor, prm->precision, prm->adaptive,
+                             reinterpret_cast<char*>(tape), pl.tape_slot, c.retry_count,
+                             pl.lslab, reinterpret_cast<char*>(ws) + pl.theta_off, pl.theta_sz,
+                             s);
+  });
   c.retry_read = c.adaptive == 2;
   if (e == hipSuccess) e = run_pipeline(probs, c, s);
   c.retry_read = 0;

@@ -22,135 +22,19 @@
 // built by k_schedule).  Workgroup i takes the
 // virtual index (i mod 8) * G/8 + i / 8, so the consecutive tiles of one
 // problem, which share operand rows, land on the same XCD and its L2.
+#include "kinds.hpp"
 #include "loaders.hpp"
-#include "tilequeue.hpp"
 
 namespace tebd {
 
 using Cfg64 = ZCfg<64, 64, 16, 2, 2>;
 using CfgGate = ZCfg<kGateTileM, kGateTileN, 16, 4, 1>;
-// Sketch and power-iteration products (m x l, n x l): the sketch width l is
-// a few dozen in a TEBD sweep, so 32-wide tiles halve the FP64 matrix-core
-// work spent on padding (FP64 MFMA runs at the vector rate on this chip).
-// 32 x 32 tiles (one 16 x 16 block per wavefront): the largest problems of a
-// batch set the duration of the launch, and their K loop over the full
-// contraction depth is the critical path, so smaller tiles spread it over
-// more compute units.
-constexpr int kSketchTileM = 32, kSketchTileN = 32;
+// Sketch and power-iteration products: 32 x 32 tiles (kSketchTileM/N).
 using CfgSk = ZCfg<kSketchTileM, kSketchTileN, 16, 2, 2>;
 // Theta's contraction depth is the old bond dimension chi_m, often 1 to a
 // few dozen: K slabs of 8 instead of 16 (the least that 32 x 32 tiles of
 // 256 threads stage evenly), and 32 x 32 tiles like the sketches.
 using CfgTheta = ZCfg<32, 32, 8, 2, 2>;
-
-// Extent of the updated bond index that a TEBD update writes in Gamma^[k]
-// (columns) and Gamma^[k+1] (rows): the new dimension chi' <= min(l, chi_max)
-// and, cleared to zero, the old one chi_m; beyond both the arrays are
-// already zero, so the padding up to the capacity is not rewritten.
-__device__ __forceinline__ int updated_bond_extent(const Prob& P) {
-  const int kept = P.l < P.kcap ? P.l : P.kcap;
-  const int e = kept > P.chi_m ? kept : P.chi_m;
-  return e < P.chi_cap ? e : P.chi_cap;
-}
-
-// Output shape of each contraction kind for problem P (0 x 0 when skipped).
-template <>
-struct TileKinds<Prob> {
-  static constexpr int count = TK_COUNT;
-  static constexpr bool small_tiles(int kind) {
-    return kind == TK_SKM || kind == TK_SKN || kind == TK_FORMU || kind == TK_FORMV ||
-           kind == TK_THETA || kind == TK_ACB || kind == TK_GRAM || kind == TK_QAPM ||
-           kind == TK_QAPN;
-  }
-  static constexpr int tile_m(int kind) {
-    return kind == TK_GATE || kind == TK_GATE_W ? kGateTileM : small_tiles(kind) ? kSketchTileM : 64;
-  }
-  // TK_SKM_W / TK_SKN_W: the same products on 64 x 64 tiles
-  static constexpr int tile_n(int kind) {
-    return kind == TK_GATE ? kGateTileN : kind == TK_GATE_W ? kGateTileW
-                                        : small_tiles(kind) ? kSketchTileN : 64;
-  }
-  __device__ static __forceinline__ void shape(int kind, const Prob& P, int tebd, int& M, int& N) {
-    M = N = 0;
-    if (kind == TK_GATE || kind == TK_GATE_W) {
-      // the group's tiles belong to its first member, whatever its own state
-      if (tebd && P.gn > 0 && P.gtot > 0 && (P.gtw == kGateTileW) == (kind == TK_GATE_W)) {
-        M = P.dl * P.dr;
-        N = P.gtot;
-      }
-      return;
-    }
-    if (P.l == 0) return;
-    switch (kind) {
-      case TK_THETA:
-        if (tebd) {
-          M = P.dl * P.chi_l;
-          N = P.dr * P.chi_r;
-        }
-        break;
-      case TK_SKM:
-      case TK_SKM_W:
-        M = P.m;
-        N = P.l;
-        break;
-      case TK_SKN:
-      case TK_SKN_W:
-        M = P.n;
-        N = P.l;
-        break;
-      case TK_FORMU:  // TEBD: the new bond's columns, and the old ones beyond it (cleared)
-        M = P.m;
-        N = tebd ? updated_bond_extent(P) : P.kcap;
-        break;
-      case TK_FORMV:
-        M = tebd ? updated_bond_extent(P) : P.kcap;
-        N = P.n;
-        break;
-      case TK_TAPEU:
-        if (P.tape_u) {
-          M = P.m;
-          N = P.l;
-        }
-        break;
-      case TK_TAPEV:
-        if (P.tape_u) {
-          M = P.l;
-          N = P.n;
-        }
-        break;
-      case TK_ACB:
-        if (P.ac_r > 0) {
-          M = P.m;
-          N = P.ac_r;
-        }
-        break;
-      case TK_GRAM:
-        if (P.chol) M = N = P.l;
-        break;
-      case TK_QAPM:
-        if (P.chol & 1) {
-          M = P.m;
-          N = P.l;
-        }
-        break;
-      case TK_QAPN:
-        if (P.chol & 2) {
-          M = P.n;
-          N = P.l;
-        }
-        break;
-      default:
-        break;
-    }
-  }
-  // rows of the two sketches and the width of the pass (the QR size classes)
-  __device__ static __forceinline__ bool dims(const Prob& P, int d[3]) {
-    d[0] = P.m;
-    d[1] = P.n;
-    d[2] = P.l1;
-    return P.l > 0;
-  }
-};
 
 hipError_t launch_schedule(Prob* probs, const Common& c, hipStream_t s) {
   if (c.bounds_dev)
@@ -200,17 +84,22 @@ __device__ __forceinline__ zt gauss_entry(int r, int c, int pid, uint32_t sid, u
   return make_double2(rad * cs, rad * sn);
 }
 
+__device__ __forceinline__ void omega_tile(Prob& P, int M, int N, int m0, int n0, uint64_t seed,
+                                           uint32_t sid) {
+  if (P.om_ext) return;
+  zt* om = const_cast<zt*>(P.om);
+  constexpr int TM = kSketchTileM, TN = kSketchTileN;  // the n x l queue's tiles
+  for (int e = threadIdx.x; e < TM * TN; e += 256) {
+    const int r = m0 + e / TN, c = n0 + e % TN;
+    if (r >= M || c >= N) continue;
+    om[size_t(r) * P.ldom + c] = gauss_entry(r, c, P.pid, sid, seed);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_omega(Prob* probs, const int32_t* offs, int nprob,
                                                int tebd, uint64_t seed, uint32_t sid) {
   for_each_tile<TK_SKN>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
-    if (P.om_ext) return;
-    zt* om = const_cast<zt*>(P.om);
-    constexpr int TM = kSketchTileM, TN = kSketchTileN;  // the n x l queue's tiles
-    for (int e = threadIdx.x; e < TM * TN; e += 256) {
-      const int r = m0 + e / TN, c = n0 + e % TN;
-      if (r >= M || c >= N) continue;
-      om[size_t(r) * P.ldom + c] = gauss_entry(r, c, P.pid, sid, seed);
-    }
+    omega_tile(P, M, N, m0, n0, seed, sid);
   });
 }
 
@@ -380,8 +269,8 @@ hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s) {
   TEBD_LAUNCH("k_theta", k_theta, dim3(grid_for(c, TK_THETA)), dim3(256), 0, s, probs, c.offs, c.nprob);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  TEBD_LAUNCH("k_gate", k_gate, dim3(grid_for(c, TK_GATE, TK_GATE_W)), dim3(256), 0, s, probs, c.offs,
-              c.nprob);
+  TEBD_LAUNCH("k_gate", k_gate, dim3(grid_for(c, TK_GATE, TK_GATE_W)), dim3(256), 0, s, probs,
+              c.offs, c.nprob);
   return hipGetLastError();
 }
 

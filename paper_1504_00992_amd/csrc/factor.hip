@@ -12,7 +12,7 @@
 #include <cfloat>
 #include <type_traits>
 
-#include "zdev.hpp"
+#include "kinds.hpp"
 
 namespace tebd {
 
@@ -36,24 +36,22 @@ __device__ __forceinline__ int group_cols(const tebd_mps& mps, int ch, int bond)
   return ok ? cl * cr : 0;
 }
 
-__global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gates,
-                             int64_t gate_chain_stride, int parity, int single_chain,
-                             int single_bond, int kcap, int p_over, char* slab_base,
-                             size_t slab_sz, int64_t mcap, int64_t ncap, int64_t lcap,
-                             int64_t lslab, int64_t npart_cap, double* disc, int32_t* status,
-                             double lambda_floor, int mixed, int adaptive, char* tape,
-                             size_t tape_stride, int32_t* retry_count, char* theta_base,
-                             size_t theta_stride) {
-  // Threads run group by group: a group's chains are the lanes of one
-  // aligned kGateGroup-lane segment of a wavefront, so its column offsets
-  // are a segmented prefix sum over the lanes.
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0 && retry_count) {
-    *retry_count = 0;
-    retry_count[kAccCountSlot] = 0;  // the Accuracy Check's two round counters
-    retry_count[kAccCountSlot + 1] = 0;
-    retry_count[kAccCountSlot + 2] = 0;  // and its widest basis
-  }
+__host__ __device__ __forceinline__ int qr_class(int rows, int l);
+
+// Plan item t (the thread layout below) of a sweep: writes one descriptor.
+// Called by whole wavefronts (the group sums are lane shuffles).
+__device__ __forceinline__ void plan_item(int t, Prob* probs, int nprob, const tebd_mps& mps,
+                                          const zt* gates, int64_t gate_chain_stride, int parity,
+                                          int single_chain, int single_bond, int kcap, int p_over,
+                                          char* slab_base, size_t slab_sz, int64_t mcap,
+                                          int64_t ncap, int64_t lcap, int64_t lslab,
+                                          int64_t npart_cap, double* disc, int32_t* status,
+                                          double lambda_floor, int mixed, int adaptive, char* tape,
+                                          size_t tape_stride, char* theta_base,
+                                          size_t theta_stride, int chol) {
+  // Items run group by group: a group's chains are the lanes of one aligned
+  // kGateGroup-lane segment of a wavefront, so its column offsets are a
+  // segmented prefix sum over the lanes.
   const int N = mps.n_sites, cap = mps.chi_max, dmax = mps.d_max;
   const int nb = (N - 1 - parity + 1) / 2;
   int chain, bond, bi = 0, p = 0;
@@ -118,7 +116,6 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
   P.ac_col = 0;
   P.ac_cap = l2;
   P.ac_grow = 0;
-  P.chol = 0;
   P.chol_ok = 0;
   if (adaptive == 3) {  // Accuracy Check: from the current bond dimension, probes of p columns
     l = cm + p_over;
@@ -131,6 +128,8 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
   P.l = bad ? 0 : l;
   P.k1 = k1;
   P.l1 = l;
+  // the Gram-based QR (where the pipeline has it) for the large sketches
+  P.chol = chol && !bad ? (qr_class(P.m, l) >= 2 ? 1 : 0) | (qr_class(P.n, l) >= 2 ? 2 : 0) : 0;
   P.l2 = l2;
   P.retry = 0;
   P.kcap = kcap;
@@ -197,6 +196,24 @@ __global__ void k_plan_sweep(Prob* probs, int nprob, tebd_mps mps, const zt* gat
   }
 }
 
+__global__ __launch_bounds__(64) void k_plan_sweep(
+    Prob* probs, int nprob, tebd_mps mps, const zt* gates, int64_t gate_chain_stride, int parity,
+    int single_chain, int single_bond, int kcap, int p_over, char* slab_base, size_t slab_sz,
+    int64_t mcap, int64_t ncap, int64_t lcap, int64_t lslab, int64_t npart_cap, double* disc,
+    int32_t* status, double lambda_floor, int mixed, int adaptive, char* tape, size_t tape_stride,
+    int32_t* retry_count, char* theta_base, size_t theta_stride, int chol) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0 && retry_count) {
+    *retry_count = 0;
+    retry_count[kAccCountSlot] = 0;  // the Accuracy Check's two round counters
+    retry_count[kAccCountSlot + 1] = 0;
+    retry_count[kAccCountSlot + 2] = 0;  // and its widest pass
+  }
+  plan_item(t, probs, nprob, mps, gates, gate_chain_stride, parity, single_chain, single_bond,
+            kcap, p_over, slab_base, slab_sz, mcap, ncap, lcap, lslab, npart_cap, disc, status,
+            lambda_floor, mixed, adaptive, tape, tape_stride, theta_base, theta_stride, chol);
+}
+
 hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, const zt* gates,
                              int64_t gate_chain_stride, int32_t parity, int32_t single_chain,
                              int32_t single_bond, int32_t p_over, char* slab_base,
@@ -208,17 +225,17 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
   const int64_t lcap = c.lmax;
   const int64_t npart_cap = gate_partials_cap(c.dmax * c.dmax, c.chimax * c.chimax);
   // one kGateGroup-lane segment per (bond, block of kGateGroup chains)
-  int64_t threads = 1;
+  int64_t items = 1;
   if (single_chain < 0) {
     const int64_t nb = c.nprob / mps.n_chains, ncb = (mps.n_chains + kGateGroup - 1) / kGateGroup;
-    threads = nb * ncb * kGateGroup;
+    items = nb * ncb * kGateGroup;
   }
   static_assert(64 % kGateGroup == 0, "segments do not straddle wavefronts");
-  TEBD_LAUNCH("k_plan_sweep", k_plan_sweep, dim3((threads + 63) / 64), dim3(64), 0, s, probs, c.nprob, mps,
-                     gates, gate_chain_stride, parity, single_chain, single_bond, c.kcap, p_over,
-                     slab_base, slab_sz, mcap, mcap, lcap, lslab, npart_cap, disc, status,
-                     lambda_floor, mixed, adaptive, tape, tape_stride, retry_count, theta_base,
-                     theta_stride);
+  TEBD_LAUNCH("k_plan_sweep", k_plan_sweep, dim3((items + 63) / 64), dim3(64), 0, s, probs,
+              c.nprob, mps, gates, gate_chain_stride, parity, single_chain, single_bond, c.kcap,
+              p_over, slab_base, slab_sz, mcap, mcap, lcap, lslab, npart_cap, disc, status,
+              lambda_floor, mixed, adaptive, tape, tape_stride, retry_count, theta_base,
+              theta_stride, c.chol);
   return hipGetLastError();
 }
 
@@ -1405,6 +1422,91 @@ __device__ __forceinline__ void jacobi_finish(Prob& P, const zt* C, const zt* J,
   for (int c = tid; c < l; c += NT) P.sig[c] = sig_s[perm_s[c]];
 }
 
+// --------------------------------------------------------------------------
+// Truncation: chi' = min(chi_max, smallest c with w(c) <= eps), where
+// w(c) = (||A||_F^2 - sum_{j<=c} s_j^2) / ||A||_F^2; eps <= 0 keeps
+// min(chi_max, l).  TEBD: lambda' = s / ||s_{1..chi'}|| and chi' are written
+// into the MPS.  Run by the whole workgroup of the problem's small SVD after
+// it (sorted(c): the c-th largest singular value, from LDS); the scans run
+// on thread 0 so the summation order is fixed.
+template <int NT, class Sorted>
+__device__ __forceinline__ void truncate_tail(Prob& P, int l, double eps, int tebd,
+                                              int32_t* retry_count, Sorted sorted) {
+  __shared__ int chi_s;
+  __shared__ double norm_s;
+  __syncthreads();  // the singular values are in place
+  if (threadIdx.x == 0) {
+    int flags = P.flags;
+    double frob2 = P.frob2;
+    if (tebd) {
+      const int npart = gate_partials(P.dl * P.dr, P.gcol0, P.chi_l * P.chi_r, P.gtw);
+      frob2 = 0.0;
+      for (int i = 0; i < npart; ++i) frob2 += P.part[i];
+      P.frob2 = frob2;
+    }
+    // A first stage that may still be retried only accepts a rank <= k1.
+    const bool can_retry = P.l2 > P.l1;
+    int cap = P.kcap < l ? P.kcap : l;
+    if (can_retry && P.k1 < cap) cap = P.k1;
+    double kept = 0.0;
+    int chi = cap;
+    double w = 0.0;
+    bool found = false;
+    bool finite = isfinite(frob2);
+    for (int c = 1; c <= l; ++c) {
+      const double sv = sorted(c - 1);
+      finite = finite && isfinite(sv);
+      kept += sv * sv;
+      const double wc = frob2 > 0.0 ? (frob2 - kept) / frob2 : 0.0;
+      if (eps > 0.0 && !found && c <= cap && wc <= eps) {
+        chi = c;
+        w = wc;
+        found = true;
+      }
+      if (c == cap && !found) w = wc;
+    }
+    int out = chi;
+    if (can_retry && !(eps > 0.0 && found)) {
+      // stage 1 rejected: leave every output untouched, run stage 2
+      P.retry = 1;
+      if (retry_count) atomicAdd(retry_count, 1);
+      out = -1;
+    }
+    if (eps > 0.0 && !found) flags |= TEBD_DEV_CHI_BOUND;
+    if (!finite) flags |= TEBD_DEV_NONFINITE;
+    if (w < 0.0) w = 0.0;
+    double nk = 0.0;
+    for (int c = 0; c < chi; ++c) nk += sorted(c) * sorted(c);
+    if (tebd) {
+      bool floor_hit = false;
+      if (P.lam_l)
+        for (int a = 0; a < P.chi_l; ++a) floor_hit |= !(P.lam_l[a] > P.lambda_floor);
+      if (P.lam_r)
+        for (int b = 0; b < P.chi_r; ++b) floor_hit |= !(P.lam_r[b] > P.lambda_floor);
+      if (floor_hit) flags |= TEBD_DEV_LAMBDA_FLOOR;
+    }
+    if (out >= 0) {
+      P.chi_new = chi;
+      P.flags = flags;
+      *P.disc = w;
+      *P.status = flags;
+      if (P.chi_out) *P.chi_out = chi;
+    }
+    chi_s = out;
+    norm_s = sqrt(nk);
+  }
+  __syncthreads();
+  const int chi = chi_s;
+  if (chi < 0) return;
+  if (tebd) {
+    const double inv = norm_s > 0.0 ? 1.0 / norm_s : 0.0;
+    for (int j = threadIdx.x; j < P.chi_cap; j += NT) P.lam_mid[j] = j < chi ? sorted(j) * inv : 0.0;
+    if (threadIdx.x == 0) *P.chi_slot = chi;
+  } else {
+    for (int j = threadIdx.x; j < P.kcap; j += NT) P.S[j] = j < chi ? sorted(j) : 0.0;
+  }
+}
+
 // Size classes of the small SVD, by l: 0 (l <= 32, 256 threads) and 1
 // (l <= 64, 512 threads) rotate every pair of a round at once (k_svd_pairs);
 // 2 (C and J in LDS) and 3 (global memory) rotate one pair per wavefront at
@@ -1427,7 +1529,8 @@ __host__ __device__ __forceinline__ int svd_class(int l) {
 constexpr int kPairGroupMax = 16;
 
 template <int NT, int CLS>
-__global__ __launch_bounds__(NT) void k_svd_pairs(Prob* probs) {
+__global__ __launch_bounds__(NT) void k_svd_pairs(Prob* probs, double eps, int tebd,
+                                                  int32_t* retry_count) {
   extern __shared__ zt lds[];  // C, then J: l columns of stride l | 1 each
   __shared__ double nrm[64];
   __shared__ double sig_s[64];
@@ -1549,12 +1652,14 @@ __global__ __launch_bounds__(NT) void k_svd_pairs(Prob* probs) {
     P.W[e] = Js[src * S + r];
   }
   if (tid < l) P.sig[tid] = sig_s[perm_s[tid]];
+  truncate_tail<NT>(P, l, eps, tebd, retry_count, [&](int c) { return sig_s[perm_s[c]]; });
 }
 
 // Classes 2 and 3: one pair per wavefront at a time (jacobi_core), C and J
 // in LDS (LDS_CJ) or in the problem's global scratch.
 template <int NT, int REGS, bool LDS_CJ>
-__global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
+__global__ __launch_bounds__(NT) void k_small_svd(Prob* probs, double eps, int tebd,
+                                                  int32_t* retry_count) {
   extern __shared__ zt lds[];
   __shared__ double sig_s[kMaxL];
   __shared__ int perm_s[kMaxL];
@@ -1575,6 +1680,7 @@ __global__ __launch_bounds__(NT) void k_small_svd(Prob* probs) {
   jacobi_core<NT, REGS>(C, J, l, converged, &rotated, nrm);
   if (!converged && threadIdx.x == 0) P.flags |= TEBD_DEV_JACOBI_NOCONV;
   jacobi_finish<NT>(P, C, J, l, sig_s, perm_s);
+  truncate_tail<NT>(P, l, eps, tebd, retry_count, [&](int c) { return sig_s[perm_s[c]]; });
 }
 
 hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s) {
@@ -1588,129 +1694,40 @@ hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s) {
                                int(2 * 64 * 65 * sizeof(zt)));
   }();
   if (attr != hipSuccess) return attr;
-  typedef void (*Launch)(hipStream_t, Prob*, int);
+  typedef void (*Launch)(hipStream_t, Prob*, int, double, int, int32_t*);
   struct Item {
     Launch fn;
     Prob* probs;
     int nprob;
-    void operator()(hipStream_t t) const { fn(t, probs, nprob); }
+    double eps;
+    int tebd;
+    int32_t* retry;
+    void operator()(hipStream_t t) const { fn(t, probs, nprob, eps, tebd, retry); }
   };
   const Launch fns[4] = {
-      [](hipStream_t t, Prob* p, int np) {
-        TEBD_LAUNCH("k_svd_pairs<256, 0>", (k_svd_pairs<256, 0>), dim3(np), dim3(256), 2 * 32 * 33 * sizeof(zt), t,
-                           p);
+      [](hipStream_t t, Prob* p, int np, double e, int tb, int32_t* rc) {
+        TEBD_LAUNCH("k_svd_pairs<256, 0>", (k_svd_pairs<256, 0>), dim3(np), dim3(256),
+                    2 * 32 * 33 * sizeof(zt), t, p, e, tb, rc);
       },
-      [](hipStream_t t, Prob* p, int np) {
-        TEBD_LAUNCH("k_svd_pairs<512, 1>", (k_svd_pairs<512, 1>), dim3(np), dim3(512), 2 * 64 * 65 * sizeof(zt), t,
-                           p);
+      [](hipStream_t t, Prob* p, int np, double e, int tb, int32_t* rc) {
+        TEBD_LAUNCH("k_svd_pairs<512, 1>", (k_svd_pairs<512, 1>), dim3(np), dim3(512),
+                    2 * 64 * 65 * sizeof(zt), t, p, e, tb, rc);
       },
-      [](hipStream_t t, Prob* p, int np) {
+      [](hipStream_t t, Prob* p, int np, double e, int tb, int32_t* rc) {
         TEBD_LAUNCH("k_small_svd<1024, 2, true>", (k_small_svd<1024, 2, true>), dim3(np), dim3(1024),
-                           size_t(kLdsElems) * sizeof(zt), t, p);
+                    size_t(kLdsElems) * sizeof(zt), t, p, e, tb, rc);
       },
-      [](hipStream_t t, Prob* p, int np) {
-        TEBD_LAUNCH("k_small_svd<1024, 4, false>", (k_small_svd<1024, 4, false>), dim3(np), dim3(1024), 0, t, p);
+      [](hipStream_t t, Prob* p, int np, double e, int tb, int32_t* rc) {
+        TEBD_LAUNCH("k_small_svd<1024, 4, false>", (k_small_svd<1024, 4, false>), dim3(np), dim3(1024), 0,
+                    t, p, e, tb, rc);
       }};
   // the problem's l here is the rank the range finder revealed
   const int lo = svd_class(c.lmin < 1 ? 1 : c.lmin), hi = svd_class(c.lmax);
   Item items[4];
   int n = 0;
-  for (int k = lo; k <= hi; ++k) items[n++] = {fns[k], probs, c.nprob};
+  int32_t* retry = c.pass2 ? nullptr : c.retry_count;
+  for (int k = lo; k <= hi; ++k) items[n++] = {fns[k], probs, c.nprob, c.eps, c.tebd, retry};
   return fork_join(s, items, n, c);
-}
-
-// --------------------------------------------------------------------------
-// Truncation: chi' = min(chi_max, smallest c with w(c) <= eps), where
-// w(c) = (||A||_F^2 - sum_{j<=c} s_j^2) / ||A||_F^2; eps <= 0 keeps
-// min(chi_max, l).  TEBD: lambda' = s / ||s_{1..chi'}|| and chi' are written
-// into the MPS.  One wavefront per problem; the scans run on lane 0 so the
-// summation order is fixed.
-__global__ __launch_bounds__(64) void k_truncate(Prob* probs, double eps, int tebd,
-                                                 int32_t* retry_count) {
-  Prob& P = probs[blockIdx.x];
-  const int l = P.l;
-  if (l == 0) return;
-  const int lane = threadIdx.x;
-  __shared__ int chi_s;
-  __shared__ double norm_s;
-  __shared__ int flags_s;
-  if (lane == 0) {
-    int flags = P.flags;
-    double frob2 = P.frob2;
-    if (tebd) {
-      const int npart = gate_partials(P.dl * P.dr, P.gcol0, P.chi_l * P.chi_r, P.gtw);
-      frob2 = 0.0;
-      for (int i = 0; i < npart; ++i) frob2 += P.part[i];
-      P.frob2 = frob2;
-    }
-    // A first stage that may still be retried only accepts a rank <= k1.
-    const bool can_retry = P.l2 > P.l1;
-    int cap = P.kcap < l ? P.kcap : l;
-    if (can_retry && P.k1 < cap) cap = P.k1;
-    double kept = 0.0;
-    int chi = cap;
-    double w = 0.0;
-    bool found = false;
-    bool finite = isfinite(frob2);
-    for (int c = 1; c <= l; ++c) {
-      const double s = P.sig[c - 1];
-      finite = finite && isfinite(s);
-      kept += s * s;
-      const double wc = frob2 > 0.0 ? (frob2 - kept) / frob2 : 0.0;
-      if (eps > 0.0 && !found && c <= cap && wc <= eps) {
-        chi = c;
-        w = wc;
-        found = true;
-      }
-      if (c == cap && !found) w = wc;
-    }
-    if (can_retry && !(eps > 0.0 && found)) {
-      // stage 1 rejected: leave every output untouched, run stage 2
-      P.retry = 1;
-      if (retry_count) atomicAdd(retry_count, 1);
-      chi_s = -1;
-    }
-    if (eps > 0.0 && !found) flags |= TEBD_DEV_CHI_BOUND;
-    if (!finite) flags |= TEBD_DEV_NONFINITE;
-    if (w < 0.0) w = 0.0;
-    double nk = 0.0;
-    for (int c = 0; c < chi; ++c) nk += P.sig[c] * P.sig[c];
-    if (tebd) {
-      bool floor_hit = false;
-      if (P.lam_l)
-        for (int a = 0; a < P.chi_l; ++a) floor_hit |= !(P.lam_l[a] > P.lambda_floor);
-      if (P.lam_r)
-        for (int b = 0; b < P.chi_r; ++b) floor_hit |= !(P.lam_r[b] > P.lambda_floor);
-      if (floor_hit) flags |= TEBD_DEV_LAMBDA_FLOOR;
-    }
-    if (!P.retry) {
-      P.chi_new = chi;
-      P.flags = flags;
-      *P.disc = w;
-      *P.status = flags;
-      if (P.chi_out) *P.chi_out = chi;
-      chi_s = chi;
-    }
-    norm_s = sqrt(nk);
-    flags_s = flags;
-  }
-  __syncthreads();
-  const int chi = chi_s;
-  if (chi < 0) return;
-  if (tebd) {
-    const double inv = norm_s > 0.0 ? 1.0 / norm_s : 0.0;
-    for (int j = lane; j < P.chi_cap; j += 64) P.lam_mid[j] = j < chi ? P.sig[j] * inv : 0.0;
-    if (lane == 0) *P.chi_slot = chi;
-  } else {
-    for (int j = lane; j < P.kcap; j += 64) P.S[j] = j < chi ? P.sig[j] : 0.0;
-  }
-  (void)flags_s;
-}
-
-hipError_t launch_truncate(Prob* probs, const Common& c, hipStream_t s) {
-  TEBD_LAUNCH("k_truncate", k_truncate, dim3(c.nprob), dim3(64), 0, s, probs, c.eps, c.tebd,
-                     c.pass2 ? nullptr : c.retry_count);
-  return hipGetLastError();
 }
 
 // --------------------------------------------------------------------------

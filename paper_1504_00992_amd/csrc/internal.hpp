@@ -268,8 +268,8 @@ hipError_t launch_qapply(Prob* probs, const Common& c, int which, hipStream_t s)
 // the probe residual, the decision and the growth of the basis.
 hipError_t launch_acc_probe(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_acc_resid(Prob* probs, const Common& c, int round, hipStream_t s);
+// Small SVD of every problem, then its truncation (chi', lambda', w, status).
 hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s);
-hipError_t launch_truncate(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_form_uv(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_tape(Prob* probs, const Common& c, hipStream_t s);
 

@@ -48,10 +48,11 @@ __device__ __forceinline__ int kind_tiles(int kind, const PT& P, int flag) {
 // the tile total of every kind to bounds[6..6 + count).
 constexpr int kScheduleThreads = 1024;
 
+// The body, for a workgroup of kScheduleThreads threads (also run at the end
+// of a kernel that has just written the descriptors, after a barrier).
 template <class PT, bool BOUNDS = false>
-__global__ __launch_bounds__(kScheduleThreads) void k_schedule(const PT* probs, int nprob,
-                                                               int flag, int32_t* offs,
-                                                               int32_t* bounds = nullptr) {
+__device__ __forceinline__ void schedule_body(const PT* probs, int nprob, int flag, int32_t* offs,
+                                              int32_t* bounds) {
   constexpr int NK = TileKinds<PT>::count, NT = kScheduleThreads, NW = NT / 64;
   __shared__ int32_t wsum[NK][NW];
   __shared__ int32_t wext[6][NW];  // per-wavefront {min, max} of the three sizes
@@ -142,6 +143,13 @@ __global__ __launch_bounds__(kScheduleThreads) void k_schedule(const PT* probs, 
       run[k] += kind_tiles(k, P, flag);
     }
   }
+}
+
+template <class PT, bool BOUNDS = false>
+__global__ __launch_bounds__(kScheduleThreads) void k_schedule(const PT* probs, int nprob,
+                                                               int flag, int32_t* offs,
+                                                               int32_t* bounds = nullptr) {
+  schedule_body<PT, BOUNDS>(probs, nprob, flag, offs, bounds);
 }
 
 // Problem owning global tile t: the largest p with off[p] <= t (off is
