@@ -614,13 +614,14 @@ struct RegQrShared {
   int32_t piv_grp[kMaxL];
 };
 
-// The body for one group width G (a compile-time constant, so the row
-// offsets of the register loops are immediates); SLOTS: every reflector
-// keeps its own slot (G * RPL * l <= RegQrShared<RPL>::kBuf); PIV: column
-// pivoting.
-template <int NT, int RPL, int G, bool SLOTS, bool PIV>
+// The body for one group width G and RPL rows per lane (compile-time
+// constants, so the row offsets of the register loops are immediates; RPL
+// may be below the class's RS when the rows fit, which shortens every
+// register loop); SLOTS: every reflector keeps its own slot
+// (G * RPL * l <= RegQrShared<RS>::kBuf); PIV: column pivoting.
+template <int NT, int RPL, int G, bool SLOTS, bool PIV, int RS>
 __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, int want_r,
-                                            RegQrShared<RPL>& sh) {
+                                            RegQrShared<RS>& sh) {
   constexpr bool piv = PIV;
   constexpr int UST = G * RPL;               // rows a group can hold
   constexpr int KEEP = RPL <= 8 ? RPL : 1;  // reflector rows kept in registers
@@ -885,12 +886,19 @@ __global__ __launch_bounds__(NT) void k_qr_reg(Prob* probs, int which, int want_
   static_assert(NT / kMaxL >= 2, "group widths below 2 are not instantiated");
   const int G = reg_group(NT, l);
   auto run = [&](auto gc) {
-    constexpr int GC = decltype(gc)::value;
-    // 512 x 8: G * 8 * l <= 4096 for every l (G * l <= 512, or G = 32 and l <= 16)
-    if (RPL <= 8 || GC * RPL * l <= RegQrShared<RPL>::kBuf)
+    constexpr int GC = decltype(gc)::value, HALF = RPL / 2;
+    // the revealed rank of the later QRs of a pass is often below the width
+    // that set the class: G doubles, and half the rows per lane may do
+    if (rows <= GC * HALF) {
+      // G * HALF * l <= NT * HALF <= kBuf: every reflector has its slot
+      static_assert(NT * HALF <= RegQrShared<RPL>::kBuf, "slots for the half-height body");
+      qr_reg_body<NT, HALF, GC, true, PIV>(P, rows, l, Yg, want_r, sh);
+    } else if (RPL <= 8 || GC * RPL * l <= RegQrShared<RPL>::kBuf) {
+      // 512 x 8: G * 8 * l <= 4096 for every l (G * l <= 512, or G = 32 and l <= 16)
       qr_reg_body<NT, RPL, GC, true, PIV>(P, rows, l, Yg, want_r, sh);
-    else
+    } else {
       qr_reg_body<NT, RPL, GC, (RPL <= 8), PIV>(P, rows, l, Yg, want_r, sh);
+    }
   };
   if (G == 32)
     run(std::integral_constant<int, 32>());
