@@ -30,9 +30,9 @@
  *   rows).  Two-site gates are indexed row = i_k * d_{k+1} + i_{k+1}
  *   (Kronecker order); the blocked Theta has row i_k * chi_l + alpha and
  *   column i_{k+1} * chi_r + beta.
- * Sketch width: l = min(k + p, m, n).  The QR steps of Alg. 1 pivot columns
- *   and keep the numerical range of the sketch (|R_jj| > 1e-13 |R_00|), so
- *   at most that many singular values are returned.
+ * Sketch width: l = min(k + p, m, n).  The first QR step of Alg. 1 pivots
+ *   columns and keeps the numerical range of the sketch (|R_jj| >
+ *   1e-13 |R_00|), so at most that many singular values are returned.
  * Randomness: the Gaussian test matrix Omega (Sec. IV, Alg. 1, first step)
  *   is drawn by Philox4x32-10 (Salmon et al., SC'11).  Entry (r, c) of
  *   problem `pid` uses counter (r, c, pid, params.stream_id) and key

@@ -452,7 +452,9 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
     TRY(qr_step(0, 0));
   }
   TIMED(PK_SKETCH_AHQ, launch_sketch(probs, c, SK_YT_FROM_Y, s));  // B^H = A^H Q
-  TIMED(PK_QR_R, launch_qr(probs, c, 1, 1, 1, s));                 // B^H P = Q_B R_B
+  // B^H = Q_B R_B in column order: the one-sided Jacobi on R_B^H that follows
+  // converges in as many sweeps as after a pivoted QR, and the QR is cheaper
+  TIMED(PK_QR_R, launch_qr(probs, c, 1, 1, 0, s));
   {
     // the small SVD works on the revealed rank, anywhere in [1, l1]; each
     // launch ends with the truncation of its problems

@@ -478,7 +478,7 @@ hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s)
 
 // --------------------------------------------------------------------------
 // Kept singular vectors and lambda^-1 reabsorption
-struct LdQP {  // (r, k) -> Q[piv[k]*ld + r]: the columns of Q in the order P of B^H P = Q_B R_B
+struct LdQP {  // (r, k) -> Q[piv[k]*ld + r]: the columns of Q in the order P of B^H P = Q_B R_B (P = I when the QR of B^H keeps column order)
   const zt* p;
   int64_t ld;
   const int32_t* piv;

@@ -70,7 +70,7 @@ struct Prob {
   zt* qru;       // 2 max(m, n): reflectors of the global-memory QR beyond its LDS rows
   zt* Qc;        // max(m, n) x l column-major: Q of the Gram-based QR (then swapped with Y or Yt)
   double* sig;   // l: singular values sorted descending
-  int32_t* piv;  // l: column order of the pivoted QR of B^H (B^H P = Q_B R_B)
+  int32_t* piv;  // l: column order of the QR of B^H (B^H P = Q_B R_B; P = I unless pivoted)
   double* part;  // npart Frobenius partial sums
   float2* Af;    // mixed: complex64 copy of A (row-major, ld n)
   float2* Yf;    // mixed: complex64 copy of the current Q or Q~ (column-major)
@@ -252,8 +252,8 @@ hipError_t launch_frob(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_omega(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s);
 hipError_t launch_sketch_f32(Prob* probs, const Common& c, int which, hipStream_t s);
-// pivot: column pivoting with the rank tolerance (the QR of B^H pivots and
-// keeps every column); 0: plain Householder in column order, every column kept
+// pivot: column pivoting with the rank tolerance (with want_r it would keep
+// every column); 0: plain Householder in column order, every column kept
 // gate 1: only the problems whose basis the Accuracy Check just grew;
 // gate 2: only the problems the Gram-based QR did not finish.
 hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pivot, hipStream_t s,
