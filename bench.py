@@ -136,7 +136,7 @@ class Work:
             self.add(sk.format(2), f, mn + 16.0 * (n * l + m * l))
             self.qr(m, lc, l, False)
         self.add("k_sketch<1>", f, mn + 16.0 * (m * l + n * l))   # B^H = A^H Q (FP64)
-        self.qr(n, lc, l, True, with_r=True)
+        self.qr(n, lc, l, False, with_r=True)   # B^H = Q_B R_B, column order
         c = chi_new
         if not form:
             return

@@ -46,11 +46,12 @@ def test_first_stage_width_and_kernel_counts():
     assert k["k_theta"][0] == 8.0 * 10 * 19 * 19 * 10 * 14
     assert k["k_gate"][0] == 8.0 * 100 ** 2 * 19 * 14
     # rows 190 and 140 both fall in class 1 of the stand-in: pivoted first QR
-    # (of Y, m rows) and QR of B^H (n rows, with R); unpivoted power iterations
+    # (of Y, m rows); unpivoted power iterations and QR of B^H (n rows, with R)
     piv, unp = k["k_qr_reg<1024, 12, true>"], k["k_qr_reg<1024, 12, false>"]
-    assert piv[0] == b.qr_flops(m, l) + b.qr_flops(n, l)
-    assert unp[0] == 2 * (b.qr_flops(m, l) + b.qr_flops(n, l))
-    assert piv[1] == b.qr_bytes(m, l) + b.qr_bytes(n, l, with_r=True)
+    assert piv[0] == b.qr_flops(m, l)
+    assert unp[0] == 2 * (b.qr_flops(m, l) + b.qr_flops(n, l)) + b.qr_flops(n, l)
+    assert piv[1] == b.qr_bytes(m, l)
+    assert unp[1] == 2 * (b.qr_bytes(m, l) + b.qr_bytes(n, l)) + b.qr_bytes(n, l, with_r=True)
     assert k["k_form_uv<1>"][0] == 8.0 * (m + n) * l * 21
 
 
