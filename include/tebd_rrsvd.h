@@ -337,13 +337,13 @@ tebd_status tebd_profile_read(int32_t capacity, const char** names, double* ms, 
  * another thread enqueues work).  It picks the tile shape of the sketch,
  * power-iteration and projection products of Alg. 1 and Sec. IV step i per
  * launch, from the largest problem of the batch: its row count (bucketed
- * as <= 128, 256, 512, 1024, 2048, 8192) and sketch width (<= 32, 64, 128,
- * 256).  variant 0: 32 x 32 output tiles (the default, also for unset
+ * as <= 128, 256, 512, 1024, 2048, 8192) and sketch width (<= 32, 64, 80,
+ * 128, 256).  variant 0: 32 x 32 output tiles (the default, also for unset
  * entries); 1: 64 x 64 tiles; -1 unsets.  precision 1 (complex FP32
- * products) has variant 0 only.  The results do not depend on the variant
- * (the same K order per output element).  The package's autotune module
- * times both variants on synthetic batches and keeps its choices in a JSON
- * file.
+ * products) has variant 0 only.  The results do not depend
+ * on the variant (the same K order per output element).  The package's
+ * autotune module times the variants on synthetic batches and keeps its
+ * choices in a JSON file.
  * tebd_tune_set: TEBD_ERR_ARG for an unknown precision or variant,
  * TEBD_ERR_SHAPE for sizes outside the buckets.
  * tebd_tune_get: the entry (-1: unset), or -1 for invalid arguments. */

@@ -14,7 +14,8 @@ import os
 from . import _lib
 
 ROW_BUCKETS = (128, 256, 512, 1024, 2048, 8192)
-WIDTH_BUCKETS = (32, 64, 128, 256)
+WIDTH_BUCKETS = (32, 64, 80, 128, 256)
+VARIANTS = (0, 1)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "tebd_rrsvd", "tuning.json")
 
 
@@ -57,24 +58,26 @@ def _time_variant(torch, api, mats, k, p, variant, rows, width, reps):
     return sum(v[0] for name, v in prof.items() if name.startswith("k_sketch")) / reps
 
 
-def tune(buckets=((256, 64), (512, 128), (1024, 128), (2048, 128)), batch=32, reps=3,
-         path=None, seed=1504):
-    """Time both variants for each (rows, width) bucket; store and return the
-    choices.  The batch of each bucket: `batch` square complex Gaussian
-    matrices of the bucket's row count, sketch width = the bucket's width
-    (k = width - 10, p = 10)."""
+def tune(buckets=((256, 64), (512, 80), (1024, 80), (2048, 80), (512, 128), (1024, 128),
+                  (2048, 128), (4900, 256, 4)), batch=32, reps=3, path=None, seed=1504):
+    """Time every variant for each (rows, width[, batch]) bucket; store and
+    return the choices.  The batch of each bucket: `batch` (or the bucket's
+    own count) square complex Gaussian matrices of the bucket's row count,
+    sketch width = the bucket's width (k = width - 10, p = 10)."""
     import torch
     from . import api
     gen = torch.Generator(device="cuda")
     gen.manual_seed(int(seed))
     entries = []
-    for rows, width in buckets:
+    for bucket in buckets:
+        rows, width = bucket[0], bucket[1]
+        count = bucket[2] if len(bucket) > 2 else batch
         n = int(rows)
         mats = [torch.randn((n, n), dtype=torch.complex128, device="cuda", generator=gen)
-                for _ in range(batch)]
+                for _ in range(count)]
         k, p = max(1, int(width) - 10), 10
-        ms = [_time_variant(torch, api, mats, k, p, v, rows, width, reps) for v in (0, 1)]
-        best = 0 if ms[0] <= ms[1] else 1
+        ms = [_time_variant(torch, api, mats, k, p, v, rows, width, reps) for v in VARIANTS]
+        best = VARIANTS[min(range(len(ms)), key=lambda i: ms[i])]
         _lib.check(_lib.tebd_tune_set(0, rows, width, best))
         entries.append({"precision": 0, "rows": int(rows), "width": int(width), "variant": best,
                         "sketch_ms": [round(x, 4) for x in ms]})

@@ -401,42 +401,48 @@ hipError_t launch_qapply(Prob* probs, const Common& c, int which, hipStream_t s)
   return hipGetLastError();
 }
 
-// The same products on 64 x 64 tiles (fewer operand reloads for large
-// problems; chosen per launch by the autotune cache).
+// The FP64 sketch products on 64 x 64 output tiles (fewer operand reloads
+// for large problems; chosen per launch by the autotune cache).
+template <int WHICH, class Cfg, int KM, int KN>
+__device__ __forceinline__ void sketch_tiles(Prob* probs, const int32_t* offs, int nprob, int tebd,
+                                             zt* smem) {
+  if (WHICH == SK_Y_FROM_OMEGA) {
+    for_each_tile<KM>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdRowA la{P.A, P.lda};
+      LdRowB lb{P.om, P.ldom};
+      StCol st{P.Y, P.m};
+      zgemm_tile<Cfg>(M, N, P.n, m0, n0, la, lb, st, smem);
+    });
+  } else if (WHICH == SK_YT_FROM_Y) {
+    for_each_tile<KN>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdAdjA la{P.A, P.lda};
+      LdColB lb{P.Y, P.m};
+      StCol st{P.Yt, P.n};
+      zgemm_tile<Cfg>(M, N, P.m, m0, n0, la, lb, st, smem);
+    });
+  } else {
+    for_each_tile<KM>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdRowA la{P.A, P.lda};
+      LdColB lb{P.Yt, P.n};
+      StCol st{P.Y, P.m};
+      zgemm_tile<Cfg>(M, N, P.n, m0, n0, la, lb, st, smem);
+    });
+  }
+}
+
 template <int WHICH>
 __global__ __launch_bounds__(256) void k_sketch_wide(Prob* probs, const int32_t* offs, int nprob,
                                                      int tebd) {
   __shared__ zt smem[Cfg64::lds_elems];
-  if (WHICH == SK_Y_FROM_OMEGA) {
-    for_each_tile<TK_SKM_W>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
-      LdRowA la{P.A, P.lda};
-      LdRowB lb{P.om, P.ldom};
-      StCol st{P.Y, P.m};
-      zgemm_tile<Cfg64>(M, N, P.n, m0, n0, la, lb, st, smem);
-    });
-  } else if (WHICH == SK_YT_FROM_Y) {
-    for_each_tile<TK_SKN_W>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
-      LdAdjA la{P.A, P.lda};
-      LdColB lb{P.Y, P.m};
-      StCol st{P.Yt, P.n};
-      zgemm_tile<Cfg64>(M, N, P.m, m0, n0, la, lb, st, smem);
-    });
-  } else {
-    for_each_tile<TK_SKM_W>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
-      LdRowA la{P.A, P.lda};
-      LdColB lb{P.Yt, P.n};
-      StCol st{P.Y, P.m};
-      zgemm_tile<Cfg64>(M, N, P.n, m0, n0, la, lb, st, smem);
-    });
-  }
+  sketch_tiles<WHICH, Cfg64, TK_SKM_W, TK_SKN_W>(probs, offs, nprob, tebd, smem);
 }
 
 // Autotune cache: variant per (precision, rows bucket, width bucket); -1
 // (unset) means the 32 x 32 tiles.  Written by tebd_tune_set between calls.
 namespace {
 constexpr int kTuneRows[6] = {128, 256, 512, 1024, 2048, 8192};
-constexpr int kTuneWidth[4] = {32, 64, 128, 256};
-int8_t g_tune[2][6][4] = {};
+constexpr int kTuneWidth[5] = {32, 64, 80, 128, 256};
+int8_t g_tune[2][6][5] = {};
 bool g_tune_init = false;
 
 int tune_bucket(const int* bounds, int nb, int v) {
@@ -448,7 +454,7 @@ int tune_bucket(const int* bounds, int nb, int v) {
 
 int sketch_variant(int precision, int max_rows, int width) {
   if (precision != 0 || !g_tune_init) return 0;
-  const int br = tune_bucket(kTuneRows, 6, max_rows), bw = tune_bucket(kTuneWidth, 4, width);
+  const int br = tune_bucket(kTuneRows, 6, max_rows), bw = tune_bucket(kTuneWidth, 5, width);
   if (br < 0 || bw < 0) return 0;
   const int v = g_tune[0][br][bw];
   return v < 0 ? 0 : v;
@@ -456,7 +462,8 @@ int sketch_variant(int precision, int max_rows, int width) {
 
 hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s) {
   const int rows = c.mmax > c.nmax ? c.mmax : c.nmax;
-  if (sketch_variant(0, rows, c.lmax) == 1) {
+  const int variant = sketch_variant(0, rows, c.lmax);
+  if (variant == 1) {
     const dim3 g(grid_for(c, which == SK_YT_FROM_Y ? TK_SKN_W : TK_SKM_W));
     if (which == SK_Y_FROM_OMEGA)
       TEBD_LAUNCH("k_sketch_wide<0>", k_sketch_wide<SK_Y_FROM_OMEGA>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
@@ -667,9 +674,9 @@ extern "C" tebd_status tebd_tune_set(int32_t precision, int32_t max_rows, int32_
                                      int32_t variant) {
   using namespace tebd;
   if (precision < 0 || precision > 1 || variant < -1 || variant > 1 ||
-      (precision == 1 && variant == 1))
+      (precision == 1 && variant > 0))
     return TEBD_ERR_ARG;
-  const int br = tune_bucket(kTuneRows, 6, max_rows), bw = tune_bucket(kTuneWidth, 4, width);
+  const int br = tune_bucket(kTuneRows, 6, max_rows), bw = tune_bucket(kTuneWidth, 5, width);
   if (max_rows < 1 || width < 1 || br < 0 || bw < 0) return TEBD_ERR_SHAPE;
   if (!g_tune_init) {
     for (auto& a : g_tune)
@@ -684,7 +691,7 @@ extern "C" tebd_status tebd_tune_set(int32_t precision, int32_t max_rows, int32_
 extern "C" int32_t tebd_tune_get(int32_t precision, int32_t max_rows, int32_t width) {
   using namespace tebd;
   if (precision < 0 || precision > 1 || max_rows < 1 || width < 1) return -1;
-  const int br = tune_bucket(kTuneRows, 6, max_rows), bw = tune_bucket(kTuneWidth, 4, width);
+  const int br = tune_bucket(kTuneRows, 6, max_rows), bw = tune_bucket(kTuneWidth, 5, width);
   if (br < 0 || bw < 0 || !g_tune_init) return -1;
   return g_tune[precision][br][bw];
 }

@@ -125,7 +125,8 @@ struct Common {
   int32_t* retry_count;  // device: problems whose first stage was rejected (adaptive rank)
   int32_t* bounds_dev = nullptr;  // host-mapped pinned memory: k_schedule writes {min, max}
                                   // of m, n, l1 there, then the tile total of every kind
-  int32_t ktiles[TK_COUNT_MAX] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
+  int32_t ktiles[TK_COUNT_MAX] = {-1, -1, -1, -1, -1, -1, -1, -1,
+                                  -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
   int32_t serial = 0;  // 1: size classes run in order on the caller's stream (no side streams)

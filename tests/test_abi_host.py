@@ -258,6 +258,10 @@ def test_autotune_cache_entries_and_json_round_trip(tmp_path):
     assert _lib.tebd_tune_get(0, 512, 64) == 1      # same bucket (<= 512, <= 64)
     assert _lib.tebd_tune_get(0, 256, 64) in (-1, 0, 1)
     assert _lib.tebd_tune_set(1, 300, 50, 1) == _lib.TEBD_ERR_ARG   # FP32 products: variant 0 only
+    assert _lib.tebd_tune_set(0, 300, 70, 1) == _lib.TEBD_OK
+    assert _lib.tebd_tune_get(0, 512, 80) == 1                      # width bucket (64, 80]
+    assert _lib.tebd_tune_get(0, 512, 81) != 1                      # the next bucket, (80, 128]
+    assert _lib.tebd_tune_set(0, 300, 70, 2) == _lib.TEBD_ERR_ARG
     assert _lib.tebd_tune_set(0, 9000, 50, 0) == _lib.TEBD_ERR_SHAPE
     assert _lib.tebd_tune_set(0, 300, 300, 0) == _lib.TEBD_ERR_SHAPE
     assert _lib.tebd_tune_get(2, 10, 10) == -1
@@ -268,6 +272,6 @@ def test_autotune_cache_entries_and_json_round_trip(tmp_path):
     assert len(got) == 2
     assert _lib.tebd_tune_get(0, 1500, 100) == 1 and _lib.tebd_tune_get(0, 128, 32) == 0
     assert autotune.load(str(tmp_path / "absent.json")) == []
-    for rows, width in ((300, 50), (1500, 100), (128, 32)):
+    for rows, width in ((300, 50), (300, 70), (1500, 100), (128, 32)):
         assert _lib.tebd_tune_set(0, rows, width, -1) == _lib.TEBD_OK
         assert _lib.tebd_tune_get(0, rows, width) == -1
