@@ -453,8 +453,13 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
   }
   TIMED(PK_SKETCH_AHQ, launch_sketch(probs, c, SK_YT_FROM_Y, s));  // B^H = A^H Q
   // B^H = Q_B R_B in column order: the one-sided Jacobi on R_B^H that follows
-  // converges in as many sweeps as after a pivoted QR, and the QR is cheaper
-  TIMED(PK_QR_R, launch_qr(probs, c, 1, 1, 0, s));
+  // converges in as many sweeps as after a pivoted QR, and the QR is cheaper.
+  // The large problems try the Gram-based QR first (R_B = R_2 R_1).
+  {
+    const bool gram_r = c.chol && tebd_size_class(0, c.nmax, c.lmax) >= 2;
+    if (gram_r) TIMED(PK_QR_R, launch_chol_qr(probs, c, 1, s, 1));
+    TIMED(PK_QR_R, launch_qr(probs, c, 1, 1, 0, s, gram_r ? 2 : 0));
+  }
   {
     // the small SVD works on the revealed rank, anywhere in [1, l1]; each
     // launch ends with the truncation of its problems

@@ -1144,8 +1144,13 @@ hipError_t launch_chol_mark(Prob* probs, const Common& c, hipStream_t s) {
 // used), then X = R^-1 = (L^-1)^H, upper triangular, into J: column c of
 // L^-1 by forward substitution, one wavefront per column, the column held
 // across the lanes (lane t keeps rows t, t + 64, ...).
+// With want_r (the QR of B^H, whose R_B the small SVD takes): pass 0 writes
+// R_1 = L_1^H into Rb, pass 1 replaces it by R_2 R_1 = L_2^H R_1 (so that
+// B^H = Q_2 R_2 R_1) and the identity column order into piv.  A pass-1
+// refusal puts B^H back into Yt (pass 0 left it in Qc), so that the
+// Householder fallback factors B^H itself.
 template <int WHICH>
-__global__ __launch_bounds__(1024) void k_chol(Prob* probs, int pass) {
+__global__ __launch_bounds__(1024) void k_chol(Prob* probs, int pass, int want_r) {
   Prob& P = probs[blockIdx.x];
   const int l = P.l, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool elig = l > 0 && (P.chol & (WHICH ? 2 : 1)) && (pass == 0 || P.chol_ok);
@@ -1195,8 +1200,41 @@ __global__ __launch_bounds__(1024) void k_chol(Prob* probs, int pass) {
     if (tid == 0) {
       P.chol_ok = 0;
       P.flags |= TEBD_DEV_QR_FALLBACK;
+      if (want_r && pass == 1) {  // back to B^H (the first pass swapped it into Qc)
+        zt* t = WHICH ? P.Yt : P.Y;
+        if (WHICH)
+          P.Yt = P.Qc;
+        else
+          P.Y = P.Qc;
+        P.Qc = t;
+      }
     }
     return;
+  }
+  if (want_r) {
+    // R_B (column-major, upper): pass 0 R_1 = L^H; pass 1 L^H R_1, through X
+    zt* Rb = P.Rb;
+    if (pass == 0) {
+      for (int e = tid; e < l * l; e += 1024) {
+        const int c = e / l, r = e - c * l;
+        Rb[e] = r <= c ? zconj(G[c + size_t(r) * l]) : make_double2(0.0, 0.0);
+      }
+    } else {
+      zt* T = P.X;
+      for (int e = tid; e < l * l; e += 1024) {
+        const int c = e / l, r = e - c * l;
+        double sr = 0.0, si = 0.0;
+        for (int k = r; k <= c; ++k) {  // (L^H)[r][k] = conj(L[k][r])
+          const zt a = G[k + size_t(r) * l], b = Rb[k + size_t(c) * l];
+          sr += a.x * b.x + a.y * b.y;
+          si += a.x * b.y - a.y * b.x;
+        }
+        T[e] = make_double2(sr, si);
+      }
+      __syncthreads();
+      for (int e = tid; e < l * l; e += 1024) Rb[e] = T[e];
+      for (int c = tid; c < l; c += 1024) P.piv[c] = c;
+    }
   }
   // X = (L^-1)^H: row c of X holds conj of column c of L^-1
   zt* X = P.J;
@@ -1246,15 +1284,15 @@ __global__ void k_qswap(Prob* probs, int nprob) {
   P.Qc = t;
 }
 
-hipError_t launch_chol_qr(Prob* probs, const Common& c, int which, hipStream_t s) {
+hipError_t launch_chol_qr(Prob* probs, const Common& c, int which, hipStream_t s, int want_r) {
   hipError_t e = hipSuccess;
   for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
     e = launch_gram(probs, c, which, pass, s);
     if (e != hipSuccess) break;
     if (which)
-      TEBD_LAUNCH("k_chol<1>", k_chol<1>, dim3(c.nprob), dim3(1024), 0, s, probs, pass);
+      TEBD_LAUNCH("k_chol<1>", k_chol<1>, dim3(c.nprob), dim3(1024), 0, s, probs, pass, want_r);
     else
-      TEBD_LAUNCH("k_chol<0>", k_chol<0>, dim3(c.nprob), dim3(1024), 0, s, probs, pass);
+      TEBD_LAUNCH("k_chol<0>", k_chol<0>, dim3(c.nprob), dim3(1024), 0, s, probs, pass, want_r);
     e = hipGetLastError();
     if (e == hipSuccess) e = launch_qapply(probs, c, which, s);
     if (e != hipSuccess) break;

@@ -261,7 +261,8 @@ hipError_t launch_qr(Prob* probs, const Common& c, int which, int want_r, int pi
                      int gate = 0);
 // Gram-based QR (CholeskyQR2) of the large problems of a QR step (which: 0
 // the m x l sketch Y, 1 the n x l sketch Yt), before launch_qr(..., gate 2).
-hipError_t launch_chol_qr(Prob* probs, const Common& c, int which, hipStream_t s);
+// want_r: also R (into Rb, column order) for the QR of B^H.
+hipError_t launch_chol_qr(Prob* probs, const Common& c, int which, hipStream_t s, int want_r = 0);
 hipError_t launch_chol_mark(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_gram(Prob* probs, const Common& c, int which, int pass, hipStream_t s);
 hipError_t launch_qapply(Prob* probs, const Common& c, int which, hipStream_t s);
