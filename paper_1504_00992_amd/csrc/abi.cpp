@@ -649,7 +649,7 @@ __global__ void k_noalloc_desc(DescArgs a) {
   P.l1 = P.l2 = l;
   P.pid = b;
   P.mixed = a.precision;
-  carve_slab(P, o.slab, o.m, o.n, l, 0, a.precision, 0);
+  carve_slab(P, o.slab, o.m, o.n, l, 0, a.precision, kFrobSlices);
   P.A = const_cast<zt*>(o.A);
   P.lda = o.lda;
   if (a.om_ext) {
@@ -788,7 +788,7 @@ tebd_status rrsvd_enqueue(int64_t batch, const int64_t* m, const int64_t* n,
       o.S = S[b];
       o.VH = reinterpret_cast<zt*>(VH[b]);
       o.slab = slab;
-      slab += slab_bytes(m[b], n[b], l, 0, prm->precision, 0);
+      slab += slab_bytes(m[b], n[b], l, 0, prm->precision, kFrobSlices);
       c.mmax = o.m > c.mmax ? o.m : c.mmax;
       c.nmax = o.n > c.nmax ? o.n : c.nmax;
       c.lmax = l > c.lmax ? l : c.lmax;
@@ -815,8 +815,8 @@ tebd_status rrsvd_enqueue(int64_t batch, const int64_t* m, const int64_t* n,
     P.l1 = P.l2 = P.l;
     P.pid = int32_t(b);
     P.mixed = prm->precision;
-    carve_slab(P, slab, m[b], n[b], P.l, 0, prm->precision, 0);
-    slab += slab_bytes(m[b], n[b], P.l, 0, prm->precision, 0);
+    carve_slab(P, slab, m[b], n[b], P.l, 0, prm->precision, kFrobSlices);
+    slab += slab_bytes(m[b], n[b], P.l, 0, prm->precision, kFrobSlices);
     P.A = const_cast<zt*>(reinterpret_cast<const zt*>(A[b]));
     P.lda = lda[b];
     if (omega) {
@@ -940,7 +940,7 @@ tebd_status tebd_workspace_size(const tebd_mps* mps, int64_t batch, const int64_
                   (long long)b, (long long)m[b], (long long)n[b], kMaxRows);
     const int l = sketch_l(prm->chi_max, prm->p, m[b], n[b]);
     if (l > kMaxL) return fail(TEBD_ERR_SHAPE, "problem %lld: sketch width %d > %d", (long long)b, l, kMaxL);
-    total += slab_bytes(m[b], n[b], l, 0, prm->precision, 0);
+    total += slab_bytes(m[b], n[b], l, 0, prm->precision, kFrobSlices);
   }
   *bytes = total;
   return ok();

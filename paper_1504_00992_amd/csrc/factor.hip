@@ -240,23 +240,27 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
 }
 
 // --------------------------------------------------------------------------
-// ||A||_F^2 for caller-supplied matrices (fixed summation order).
+// ||A||_F^2 for caller-supplied matrices (fixed summation order): workgroup
+// (problem, slice) sums |A|^2 over its slice of rows (threads along the
+// columns) into part[slice].
 __global__ __launch_bounds__(256) void k_frob(Prob* probs) {
   __shared__ double red[4];
-  Prob& P = probs[blockIdx.x];
+  const int pi = blockIdx.x / kFrobSlices, sl = blockIdx.x - pi * kFrobSlices;
+  Prob& P = probs[pi];
   if (P.l == 0) return;
+  const int rs = (P.m + kFrobSlices - 1) / kFrobSlices;
+  const int r0 = sl * rs, r1 = r0 + rs < P.m ? r0 + rs : P.m;
   double s = 0.0;
-  const int64_t total = int64_t(P.m) * P.n;
-  for (int64_t e = threadIdx.x; e < total; e += 256) {
-    const int64_t r = e / P.n, c = e - r * P.n;
-    s += zabs2(P.A[r * P.lda + c]);
+  for (int r = r0; r < r1; ++r) {
+    const zt* row = P.A + size_t(r) * P.lda;
+    for (int c = threadIdx.x; c < P.n; c += 256) s += zabs2(row[c]);
   }
   s = block_sum<256>(s, red);
-  if (threadIdx.x == 0) P.frob2 = s;
+  if (threadIdx.x == 0) P.part[sl] = s;
 }
 
 hipError_t launch_frob(Prob* probs, const Common& c, hipStream_t s) {
-  TEBD_LAUNCH("k_frob", k_frob, dim3(c.nprob), dim3(256), 0, s, probs);
+  TEBD_LAUNCH("k_frob", k_frob, dim3(c.nprob * kFrobSlices), dim3(256), 0, s, probs);
   return hipGetLastError();
 }
 
@@ -1483,13 +1487,12 @@ __device__ __forceinline__ void truncate_tail(Prob& P, int l, double eps, int te
   __syncthreads();  // the singular values are in place
   if (threadIdx.x == 0) {
     int flags = P.flags;
-    double frob2 = P.frob2;
-    if (tebd) {
-      const int npart = gate_partials(P.dl * P.dr, P.gcol0, P.chi_l * P.chi_r, P.gtw);
-      frob2 = 0.0;
-      for (int i = 0; i < npart; ++i) frob2 += P.part[i];
-      P.frob2 = frob2;
-    }
+    // ||A||_F^2 from the partial sums: the gate product's (TEBD) or k_frob's
+    const int npart =
+        tebd ? gate_partials(P.dl * P.dr, P.gcol0, P.chi_l * P.chi_r, P.gtw) : kFrobSlices;
+    double frob2 = 0.0;
+    for (int i = 0; i < npart; ++i) frob2 += P.part[i];
+    P.frob2 = frob2;
     // A first stage that may still be retried only accepts a rank <= k1.
     const bool can_retry = P.l2 > P.l1;
     int cap = P.kcap < l ? P.kcap : l;

@@ -249,6 +249,10 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
 hipError_t launch_stage2(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_schedule(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s);
+// ||A||_F^2 of caller-supplied matrices: kFrobSlices partial sums per
+// problem (row slices, one workgroup each) into part; the truncation adds
+// them up in order.
+constexpr int kFrobSlices = 32;
 hipError_t launch_frob(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_omega(Prob* probs, const Common& c, hipStream_t s);
 hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s);
