@@ -597,6 +597,28 @@ def batched_rrsvd_line(args, torch, api, wl, lib):
                             "frac": round(ach / PEAK_FP64_TFLOPS, 4) if ach else None,
                             "event_ms": round(sk_ms, 3)},
            "kernel_ms": kernel_table(prof)}
+    # the same batch with the sketch and power-iteration products in complex
+    # FP32 (precision 1): rate and the change of the singular values
+    api.rrsvd_truncate(mats, 64, 10, 2, 1e-10, 1504, 0, precision=1)
+    torch.cuda.synchronize()
+    tm = []
+    for r in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outm = api.rrsvd_truncate(mats, 64, 10, 2, 1e-10, 1504, r + 1, precision=1)
+        torch.cuda.synchronize()
+        tm.append(time.perf_counter() - t0)
+    s64, s32 = torch.stack(out[1]), torch.stack(outm[1])
+    res["mixed_precision"] = {
+        "value": round(len(sizes) * reps / sum(tm), 2), "unit": "truncations/s",
+        "ms_per_batch": round(1e3 * sum(tm) / reps, 3),
+        "vs_fp64": round(sum(times) / sum(tm), 3),
+        "max_rel_sigma_diff_vs_fp64": float(((s64 - s32).abs().max(dim=1).values
+                                             / s64[:, 0]).max().item()),
+        "chi_identical": bool((out[3] == outm[3]).all().item()),
+        "note": "precision 1: the sketch and power-iteration products on complex FP32 matrix "
+                "cores (A read from its complex64 copy, the other operand rounded when "
+                "staged), the QRs, B and the small SVD in FP64"}
     if not args.no_cpu_baseline:
         from oracle import philox, rrsvd as orr
         per = {}

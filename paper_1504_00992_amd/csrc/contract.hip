@@ -166,6 +166,7 @@ struct LdGate {
 // the strides of i and j (rows (i j) of the product go to A[(i, a)][(j, b)]).
 struct GateCol {
   zt* base;
+  float2* basef;  // the same entry of the member's complex64 copy of A (FP32 products), or null
   int32_t si, sj;
 };
 
@@ -177,7 +178,9 @@ struct StGateGroup {
   __device__ void operator()(int r, int c, zt v) {
     const GateCol& g = col[c - n0];
     const int i = r / dr, j = r - i * dr;
-    g.base[size_t(i) * g.si + size_t(j) * g.sj] = v;
+    const size_t o = size_t(i) * g.si + size_t(j) * g.sj;
+    g.base[o] = v;
+    if (g.basef) g.basef[o] = make_float2(float(v.x), float(v.y));
     f2[(r - m0) * BN + (c - n0)] = zabs2(v);
   }
 };
@@ -196,7 +199,7 @@ __device__ __forceinline__ void gate_group_tile(Prob* probs, int lead, int M, in
   const int tid = threadIdx.x, gn = L.gn, gs = L.gstride;
   if (tid < BN) {
     const int c = n0 + tid;
-    GateCol g{nullptr, 0, 0};
+    GateCol g{nullptr, nullptr, 0, 0};
     if (c < N) {
       // the last member starting at or before c owns it (a member without
       // columns starts where the next one does)
@@ -206,6 +209,7 @@ __device__ __forceinline__ void gate_group_tile(Prob* probs, int lead, int M, in
       const Prob& Q = probs[lead + q * gs];
       const int lc = c - Q.gcol0, a = lc / Q.chi_r, b = lc - a * Q.chi_r;
       g.base = Q.A + size_t(a) * Q.n + b;
+      g.basef = Q.Af ? Q.Af + size_t(a) * Q.n + b : nullptr;
       g.si = Q.chi_l * Q.n;
       g.sj = Q.chi_r;
     }
@@ -311,26 +315,34 @@ template <int WHICH>
 __global__ __launch_bounds__(256) void k_sketch_f32(Prob* probs, const int32_t* offs, int nprob,
                                                     int tebd) {
   __shared__ float2 smem[CfgSk::lds_elems];
+  // A from its complex64 copy when there is one (half the bytes), else
+  // rounded from complex128 when staged
   if (WHICH == SK_Y_FROM_OMEGA) {
     for_each_tile<TK_SKM>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
-      LdRowA la{P.A, P.lda};
       LdRowB lb{P.om, P.ldom};
       StCol st{P.Y, P.m};
-      cgemm_tile<CfgSk>(M, N, P.n, m0, n0, la, lb, st, smem);
+      if (P.Af)
+        cgemm_tile<CfgSk>(M, N, P.n, m0, n0, LdRowAf{P.Af, P.n}, lb, st, smem);
+      else
+        cgemm_tile<CfgSk>(M, N, P.n, m0, n0, LdRowA{P.A, P.lda}, lb, st, smem);
     });
   } else if (WHICH == SK_YT_FROM_Y) {
     for_each_tile<TK_SKN>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
-      LdAdjA la{P.A, P.lda};
       LdColB lb{P.Y, P.m};
       StCol st{P.Yt, P.n};
-      cgemm_tile<CfgSk>(M, N, P.m, m0, n0, la, lb, st, smem);
+      if (P.Af)
+        cgemm_tile<CfgSk>(M, N, P.m, m0, n0, LdAdjAf{P.Af, P.n}, lb, st, smem);
+      else
+        cgemm_tile<CfgSk>(M, N, P.m, m0, n0, LdAdjA{P.A, P.lda}, lb, st, smem);
     });
   } else {
     for_each_tile<TK_SKM>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
-      LdRowA la{P.A, P.lda};
       LdColB lb{P.Yt, P.n};
       StCol st{P.Y, P.m};
-      cgemm_tile<CfgSk>(M, N, P.n, m0, n0, la, lb, st, smem);
+      if (P.Af)
+        cgemm_tile<CfgSk>(M, N, P.n, m0, n0, LdRowAf{P.Af, P.n}, lb, st, smem);
+      else
+        cgemm_tile<CfgSk>(M, N, P.n, m0, n0, LdRowA{P.A, P.lda}, lb, st, smem);
     });
   }
 }

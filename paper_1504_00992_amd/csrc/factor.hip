@@ -242,7 +242,8 @@ hipError_t launch_plan_sweep(Prob* probs, const Common& c, const tebd_mps& mps, 
 // --------------------------------------------------------------------------
 // ||A||_F^2 for caller-supplied matrices (fixed summation order): workgroup
 // (problem, slice) sums |A|^2 over its slice of rows (threads along the
-// columns) into part[slice].
+// columns) into part[slice].  With the FP32 products it also writes the
+// complex64 copy of A they read.
 __global__ __launch_bounds__(256) void k_frob(Prob* probs) {
   __shared__ double red[4];
   const int pi = blockIdx.x / kFrobSlices, sl = blockIdx.x - pi * kFrobSlices;
@@ -253,7 +254,12 @@ __global__ __launch_bounds__(256) void k_frob(Prob* probs) {
   double s = 0.0;
   for (int r = r0; r < r1; ++r) {
     const zt* row = P.A + size_t(r) * P.lda;
-    for (int c = threadIdx.x; c < P.n; c += 256) s += zabs2(row[c]);
+    float2* rowf = P.Af ? P.Af + size_t(r) * P.n : nullptr;
+    for (int c = threadIdx.x; c < P.n; c += 256) {
+      const zt v = row[c];
+      s += zabs2(v);
+      if (rowf) rowf[c] = make_float2(float(v.x), float(v.y));
+    }
   }
   s = block_sum<256>(s, red);
   if (threadIdx.x == 0) P.part[sl] = s;

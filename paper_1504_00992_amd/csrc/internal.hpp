@@ -72,8 +72,7 @@ struct Prob {
   double* sig;   // l: singular values sorted descending
   int32_t* piv;  // l: column order of the QR of B^H (B^H P = Q_B R_B; P = I unless pivoted)
   double* part;  // npart Frobenius partial sums
-  float2* Af;    // mixed: complex64 copy of A (row-major, ld n)
-  float2* Yf;    // mixed: complex64 copy of the current Q or Q~ (column-major)
+  float2* Af;    // mixed: complex64 copy of A (row-major, ld n), read by the FP32 products
   // outputs of the standalone RRSVD
   zt* U;
   int64_t ldu;
@@ -307,6 +306,7 @@ __host__ __device__ inline size_t slab_bytes(int64_t m, int64_t n, int64_t l, in
   b += align256(l * sizeof(double)); // sig
   b += align256(l * sizeof(int32_t));  // piv
   b += align256(npart * sizeof(double));
+  if (mixed) b += align256(m * n * sizeof(float2));  // complex64 copy of A
   return b;
 }
 
@@ -352,7 +352,10 @@ __host__ __device__ inline void carve_slab(Prob& p, char* base, int64_t m, int64
   p.part = reinterpret_cast<double*>(c);
   c += align256(npart * sizeof(double));
   p.Af = nullptr;
-  p.Yf = nullptr;
+  if (mixed) {
+    p.Af = reinterpret_cast<float2*>(c);
+    c += align256(m * n * sizeof(float2));
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -108,6 +108,24 @@ struct LdAdjColA {  // (r, k) -> conj(p[r*ld + k]): the adjoint of a column-majo
   __device__ zt operator()(int r, int k) const { return zconj(p[size_t(r) * ld + k]); }
 };
 
+// complex64 copies of A for the FP32 products
+struct LdRowAf {  // A[r][k] = p[r*ld + k]
+  const float2* p;
+  int64_t ld;
+  static constexpr bool contig_k = true;
+  __device__ float2 operator()(int r, int k) const { return p[size_t(r) * ld + k]; }
+};
+
+struct LdAdjAf {  // (r, k) -> conj(p[k*ld + r])
+  const float2* p;
+  int64_t ld;
+  static constexpr bool contig_k = false;
+  __device__ float2 operator()(int r, int k) const {
+    const float2 v = p[size_t(k) * ld + r];
+    return make_float2(v.x, -v.y);
+  }
+};
+
 struct StCol {  // C[r][c] -> p[c*ld + r]
   zt* p;
   int64_t ld;

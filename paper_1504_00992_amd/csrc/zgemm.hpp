@@ -223,9 +223,23 @@ __device__ void zgemm_narrow_tile(int M, int N, int K, int m0, int n0, int ncol,
 // FP64 when stored.
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-template <class Cfg, class LA, class LB>
-__device__ __forceinline__ void cgemm_stage(float2* As, float2* Bs, const zt (&ra)[Cfg::NA],
-                                            const zt (&rb)[Cfg::NB]) {
+__device__ __forceinline__ float2 to_f32(zt v) { return make_float2(float(v.x), float(v.y)); }
+__device__ __forceinline__ float2 to_f32(float2 v) { return v; }
+
+template <class T>
+__device__ __forceinline__ T zero_of() {
+  T z;
+  z.x = 0;
+  z.y = 0;
+  return z;
+}
+
+// Operand registers of the FP32 engine: the loader's element type (complex128
+// operands are rounded when staged, complex64 ones pass through).
+template <class Cfg, class LA, class LB, class TA, class TB>
+__device__ __forceinline__ void cgemm_load(int M, int N, int K, int m0, int n0, int k0,
+                                           const LA& la, const LB& lb, TA (&ra)[Cfg::NA],
+                                           TB (&rb)[Cfg::NB]) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int s = 0; s < Cfg::NA; ++s) {
@@ -238,7 +252,8 @@ __device__ __forceinline__ void cgemm_stage(float2* As, float2* Bs, const zt (&r
       r = e % Cfg::BM;
       k = e / Cfg::BM;
     }
-    As[k * Cfg::LDA + r] = make_float2(float(ra[s].x), float(ra[s].y));
+    const int gr = m0 + r, gk = k0 + k;
+    ra[s] = (gr < M && gk < K) ? la(gr, gk) : zero_of<TA>();
   }
 #pragma unroll
   for (int s = 0; s < Cfg::NB; ++s) {
@@ -251,7 +266,40 @@ __device__ __forceinline__ void cgemm_stage(float2* As, float2* Bs, const zt (&r
       k = e % Cfg::BK;
       c = e / Cfg::BK;
     }
-    Bs[k * Cfg::LDB + c] = make_float2(float(rb[s].x), float(rb[s].y));
+    const int gk = k0 + k, gc = n0 + c;
+    rb[s] = (gk < K && gc < N) ? lb(gk, gc) : zero_of<TB>();
+  }
+}
+
+template <class Cfg, class LA, class LB, class TA, class TB>
+__device__ __forceinline__ void cgemm_stage(float2* As, float2* Bs, const TA (&ra)[Cfg::NA],
+                                            const TB (&rb)[Cfg::NB]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < Cfg::NA; ++s) {
+    const int e = tid + s * Cfg::NT;
+    int r, k;
+    if (LA::contig_k) {
+      k = e % Cfg::BK;
+      r = e / Cfg::BK;
+    } else {
+      r = e % Cfg::BM;
+      k = e / Cfg::BM;
+    }
+    As[k * Cfg::LDA + r] = to_f32(ra[s]);
+  }
+#pragma unroll
+  for (int s = 0; s < Cfg::NB; ++s) {
+    const int e = tid + s * Cfg::NT;
+    int k, c;
+    if (LB::contig_n) {
+      c = e % Cfg::BN;
+      k = e / Cfg::BN;
+    } else {
+      k = e % Cfg::BK;
+      c = e / Cfg::BK;
+    }
+    Bs[k * Cfg::LDB + c] = to_f32(rb[s]);
   }
 }
 
@@ -270,12 +318,15 @@ __device__ void cgemm_tile(int M, int N, int K, int m0, int n0, const LA& la, co
       accr[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
       acci[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
     }
-  zt ra[Cfg::NA], rb[Cfg::NB];
-  if (K > 0) zgemm_load<Cfg>(M, N, K, m0, n0, 0, la, lb, ra, rb);
+  using TA = decltype(la(0, 0));
+  using TB = decltype(lb(0, 0));
+  TA ra[Cfg::NA];
+  TB rb[Cfg::NB];
+  if (K > 0) cgemm_load<Cfg>(M, N, K, m0, n0, 0, la, lb, ra, rb);
   for (int k0 = 0; k0 < K; k0 += Cfg::BK) {
     cgemm_stage<Cfg, LA, LB>(As, Bs, ra, rb);
     __syncthreads();
-    if (k0 + Cfg::BK < K) zgemm_load<Cfg>(M, N, K, m0, n0, k0 + Cfg::BK, la, lb, ra, rb);
+    if (k0 + Cfg::BK < K) cgemm_load<Cfg>(M, N, K, m0, n0, k0 + Cfg::BK, la, lb, ra, rb);
 #pragma unroll
     for (int kk = 0; kk < Cfg::BK; kk += 4) {
       const int ka = kk + (lane >> 4);
