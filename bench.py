@@ -67,6 +67,17 @@ def parse():
     for x in ("cpu-baseline", "full-svd", "other-rank", "graph", "tfim", "batched", "mixed",
               "adjoint", "table2", "tedopa", "accuracy", "order4"):
         ap.add_argument(f"--no-{x}", action="store_true")
+    # host-only post-processing of rocprofv3 output into the summaries under
+    # profiles/ (no GPU): a kernel-trace database, or the FETCH_SIZE and
+    # WRITE_SIZE counter CSVs of a run and of the copy probe
+    ap.add_argument("--summarize-trace", metavar="RESULTS_DB",
+                    help="write a per-kernel summary of a rocprofv3 --kernel-trace database")
+    ap.add_argument("--summarize-traffic", nargs=4,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "PROBE_FETCH_CSV", "PROBE_WRITE_CSV"),
+                    help="write profiles/<workload>_hbm_traffic.txt from counter collections")
+    ap.add_argument("--workload", default="spin_boson_16x100")
+    ap.add_argument("--command", default="", help="the command the rocprofv3 output came from")
+    ap.add_argument("--out", default=None)
     ap.add_argument("--rank", choices=("adaptive", "fixed"), default="adaptive",
                     help="rank of the timed run: two-stage adaptive (k1 from the bond dimension, "
                          "k = chi_max when needed) or fixed k = chi_max")
@@ -948,8 +959,100 @@ def order4_line(args, torch, api, models, lib):
 
 
 # ---------------------------------------------------------------------------
+# rocprofv3 post-processing (host only)
+COPY_PROBE_BYTES = 256 << 20
+
+
+def short_kernel_name(n):
+    """Kernel name without 'void', the tebd:: namespace and the argument list."""
+    n = re.sub(r"^void ", "", n)
+    if n.startswith("tebd::"):
+        n = n[6:]
+    depth = 0
+    for i, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return n[:i]
+    return n
+
+
+def summarize_trace(db, command):
+    """Per-kernel calls, total and mean duration (us) from a rocprofv3
+    --kernel-trace results database (its `kernels` view)."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, count(*), sum(duration), avg(duration) from kernels "
+                       "group by name order by sum(duration) desc").fetchall()
+    merged = {}
+    for name, n, tot, _ in rows:
+        k = short_kernel_name(name)
+        a = merged.get(k, (0, 0.0))
+        merged[k] = (a[0] + n, a[1] + tot)
+    total = sum(v[1] for v in merged.values()) or 1.0
+    out = ["# rocprofv3 --kernel-trace --stats summary (durations in microseconds; kernel names "
+           "without namespace and arguments)", f"# command: {command}",
+           f"# {'kernel':<44} {'calls':>7} {'total_us':>12} {'avg_us':>9} {'pct':>6}"]
+    for k, (n, tot) in sorted(merged.items(), key=lambda kv: -kv[1][1]):
+        nm = k if len(k) <= 46 else k[:43] + "..."
+        out.append(f"{nm:<46} {n:>7} {tot / 1e3:>12.1f} {tot / 1e3 / n:>9.2f} "
+                   f"{100 * tot / total:>6.2f}")
+    return "\n".join(out) + "\n"
+
+
+def _counter_means(path, counter):
+    """Per-kernel (dispatches, mean value) of one counter from a rocprofv3
+    counter-collection CSV."""
+    import csv
+    acc = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row["Counter_Name"] != counter:
+                continue
+            k = short_kernel_name(row["Kernel_Name"])
+            a = acc.get(k, (0, 0.0))
+            acc[k] = (a[0] + 1, a[1] + float(row["Counter_Value"]))
+    return {k: (n, s / n) for k, (n, s) in acc.items()}
+
+
+def summarize_traffic(fetch_csv, write_csv, probe_fetch_csv, probe_write_csv, command):
+    """HBM bytes per launch of every kernel: FETCH_SIZE and WRITE_SIZE (KiB
+    per dispatch), each scaled by COPY_PROBE_BYTES over what the same counter
+    reads for the copy probe's kernel (the dispatch with the largest value)."""
+    pf = max(_counter_means(probe_fetch_csv, "FETCH_SIZE").values(), key=lambda v: v[1])[1]
+    pw = max(_counter_means(probe_write_csv, "WRITE_SIZE").values(), key=lambda v: v[1])[1]
+    sf, sw = COPY_PROBE_BYTES / (1024.0 * pf), COPY_PROBE_BYTES / (1024.0 * pw)
+    fe, wr = _counter_means(fetch_csv, "FETCH_SIZE"), _counter_means(write_csv, "WRITE_SIZE")
+    out = ["# HBM traffic per kernel launch from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE "
+           "(two runs of the command below), KiB per dispatch, scaled by the copy probe",
+           f"# command: {command}",
+           f"# copy probe (bench.py --copy-probe, {COPY_PROBE_BYTES} bytes read and written): "
+           f"FETCH_SIZE {pf:.1f} KiB, WRITE_SIZE {pw:.1f} KiB per dispatch; scale factors "
+           f"{sf:.4f} (fetch), {sw:.4f} (write)",
+           f"# kernel sources sha256: {code_digest()}",
+           "# kernel dispatches FETCH_KiB WRITE_KiB bytes_per_launch"]
+    for k in sorted(fe, key=lambda k: -fe[k][0] * fe[k][1]):
+        n, f = fe[k]
+        w = wr.get(k, (0, 0.0))[1]
+        out.append(f"{k} {n} {f:.2f} {w:.2f} {1024.0 * (f * sf + w * sw):.0f}")
+    return "\n".join(out) + "\n"
+
+
 def main():
     args = parse()
+    if args.summarize_trace or args.summarize_traffic:
+        text = (summarize_trace(args.summarize_trace, args.command) if args.summarize_trace
+                else summarize_traffic(*args.summarize_traffic, args.command))
+        path = args.out or (os.path.join(ROOT, "profiles", f"{args.workload}_hbm_traffic.txt")
+                            if args.summarize_traffic else None)
+        if path:
+            with open(path, "w") as f:
+                f.write(text)
+        else:
+            sys.stdout.write(text)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build measures one "
               f"GPU's share of the workload; the multi-GPU layout is described, not launched.",
@@ -965,9 +1068,9 @@ def main():
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)  # an elementwise kernel: reads and writes 256 MiB
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes": 256 << 20, "copies": 3}))
+        print(json.dumps({"copy_probe_bytes": COPY_PROBE_BYTES, "copies": 3}))
         return
     from paper_1504_00992_amd import api, autotune, models, _lib
     import workloads as wl

@@ -118,3 +118,31 @@ def test_size_class_query_of_the_library():
     assert _lib.tebd_size_class(0, 2048, 74) == 3
     assert _lib.tebd_size_class(1, 0, 66) == 2
     assert _lib.tebd_size_class(0, 0, 5) == -1 and _lib.tebd_size_class(2, 5, 5) == -1
+
+
+def _counter_csv(path, rows):
+    cols = ["Correlation_Id", "Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    with open(path, "w") as f:
+        f.write(",".join(cols) + "\n")
+        for i, (k, c, v) in enumerate(rows):
+            f.write(f'{i},{i},"{k}",{c},{v}\n')
+
+
+def test_traffic_summary_round_trip(tmp_path, monkeypatch):
+    # counter CSVs -> profiles/<workload>_hbm_traffic.txt -> measured_traffic
+    b = _bench()
+    fe, wr, pf, pw = (str(tmp_path / x) for x in ("f.csv", "w.csv", "pf.csv", "pw.csv"))
+    k = "void tebd::k_qr_reg<512, 8, false>(tebd::Prob*, int, int, int, int)"
+    _counter_csv(fe, [(k, "FETCH_SIZE", 10.0), (k, "FETCH_SIZE", 30.0), ("void tebd::k_gate(x)", "FETCH_SIZE", 5.0)])
+    _counter_csv(wr, [(k, "WRITE_SIZE", 4.0), (k, "WRITE_SIZE", 4.0)])
+    half = b.COPY_PROBE_BYTES / 1024 / 2          # the probe's counters read half the bytes moved
+    _counter_csv(pf, [("copy", "FETCH_SIZE", half)])
+    _counter_csv(pw, [("copy", "WRITE_SIZE", half)])
+    text = b.summarize_traffic(fe, wr, pf, pw, "cmd")
+    line = [l for l in text.splitlines() if l.startswith("k_qr_reg<512, 8, false> ")][0]
+    assert line.split()[-1] == str(int(1024 * (20.0 * 2 + 4.0 * 2)))
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "wl_hbm_traffic.txt").write_text(text)
+    monkeypatch.setattr(b, "ROOT", str(tmp_path))
+    assert b.measured_traffic("k_qr_reg<512, 8, false>", "wl")[0] == 1024 * 48.0
