@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--headline-only", action="store_true",
                     help="the headline evolution only (timed, then one profiled repetition)")
     ap.add_argument("--no-profile", action="store_true", help="skip the profiled repetition")
+    ap.add_argument("--only", choices=("tfim", "batched", "mixed", "adjoint", "table2"),
+                    help="run one secondary workload alone (no headline) and print its entry; "
+                         "for profiling that workload by itself")
     for x in ("cpu-baseline", "full-svd", "other-rank", "graph", "tfim", "batched", "mixed",
               "adjoint", "table2", "tedopa", "accuracy", "order4"):
         ap.add_argument(f"--no-{x}", action="store_true")
@@ -1085,6 +1088,15 @@ def main():
         source = "timed now, saved to " + autotune.cache_path()
     tune_entry = {"entries": tuned, "source": source, "seconds": round(time.perf_counter() - t0, 2)}
     _progress(f"autotune: {[(e['rows'], e['width'], e['variant']) for e in tuned]}")
+    if args.only:
+        args.no_cpu_baseline = True
+        fn = {"tfim": lambda: tfim_line(args, torch, api, models, _lib),
+              "batched": lambda: batched_rrsvd_line(args, torch, api, wl, _lib),
+              "mixed": lambda: mixed_line(args, torch, api, models, _lib),
+              "adjoint": lambda: adjoint_line(args, torch, api, models, wl, _lib),
+              "table2": lambda: table2_line(args, torch, api, wl, _lib)}[args.only]
+        print(json.dumps({"only": args.only, args.only: fn()}), flush=True)
+        return
 
     adaptive = args.rank == "adaptive"
     N, steps = SB["N"], SB["steps"]
