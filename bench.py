@@ -1139,6 +1139,17 @@ def main():
         prof, hist = ev.profiled(steps, _lib)
         w = history_work(_lib, hist, dims, SB["chi_max"], SB["p"], SB["q"], adaptive)
         line["roofline"] = kernel_roofline(prof, w, "spin_boson_16x100")
+        # the gate product (one per group of chains sharing a gate): HBM bytes
+        # per launch, algorithmic against the counters' (when taken on these
+        # kernel sources)
+        gl = prof.get("k_gate", (0.0, 0))[1]
+        if gl:
+            alg = w.k.get("k_gate", (0.0, 0.0))[1] / gl
+            meas, _ = measured_traffic("k_gate", "spin_boson_16x100")
+            line["gate_hbm"] = {"algorithmic_bytes_per_launch": round(alg),
+                                "measured_bytes_per_launch": round(meas) if meas else None,
+                                "measured_over_algorithmic": round(meas / alg, 3)
+                                if meas and alg else None}
         line["phase_ms"] = phase_table(prof)
         line["kernel_ms"] = kernel_table(prof)
         line["profiled_phase_ms_total"] = round(sum(v[0] for k, v in prof.items()
