@@ -984,7 +984,9 @@ def short_kernel_name(n):
 
 def summarize_trace(db, command):
     """Per-kernel calls, total and mean duration (us) from a rocprofv3
-    --kernel-trace results database (its `kernels` view)."""
+    --kernel-trace results database (its `kernels` view): the library's
+    kernels (k_*) one by one, every other kernel (input generation and copies
+    by torch or its libraries, outside the timed regions) in one line."""
     import sqlite3
     con = sqlite3.connect(db)
     rows = con.execute("select name, count(*), sum(duration), avg(duration) from kernels "
@@ -994,14 +996,21 @@ def summarize_trace(db, command):
         k = short_kernel_name(name)
         a = merged.get(k, (0, 0.0))
         merged[k] = (a[0] + n, a[1] + tot)
-    total = sum(v[1] for v in merged.values()) or 1.0
+    ours = {k: v for k, v in merged.items() if k.startswith("k_")}
+    rest = [v for k, v in merged.items() if not k.startswith("k_")]
+    total = sum(v[1] for v in ours.values()) or 1.0
     out = ["# rocprofv3 --kernel-trace --stats summary (durations in microseconds; kernel names "
-           "without namespace and arguments)", f"# command: {command}",
+           "without namespace and arguments; pct of the library's kernel time)",
+           f"# command: {command}",
            f"# {'kernel':<44} {'calls':>7} {'total_us':>12} {'avg_us':>9} {'pct':>6}"]
-    for k, (n, tot) in sorted(merged.items(), key=lambda kv: -kv[1][1]):
+    for k, (n, tot) in sorted(ours.items(), key=lambda kv: -kv[1][1]):
         nm = k if len(k) <= 46 else k[:43] + "..."
         out.append(f"{nm:<46} {n:>7} {tot / 1e3:>12.1f} {tot / 1e3 / n:>9.2f} "
                    f"{100 * tot / total:>6.2f}")
+    if rest:
+        n, tot = sum(v[0] for v in rest), sum(v[1] for v in rest)
+        out.append(f"# other kernels (inputs, copies; not the library's): {n} calls, "
+                   f"{tot / 1e3:.1f} us")
     return "\n".join(out) + "\n"
 
 
