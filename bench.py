@@ -159,7 +159,7 @@ class Work:
 
 
 def first_stage_rank(chi_mid, chi_max):
-    return min(chi_max, chi_mid + max(4, (chi_mid + 1) // 2))
+    return min(chi_max, chi_mid + max(4, (chi_mid + 3) // 4))
 
 
 def sweep_work(work, chi_before, chi_after, status, parity, dims, chi_max, p, q, adaptive,
@@ -1134,7 +1134,7 @@ def main():
                                "chi_max=100, RRSVD p=10 q=2, w<=1e-10 per bond; one step = the "
                                "whole evolution, Trotter steps 1..200 from the product state "
                                f"({per_rep} bond updates)",
-                   "rank": ("two-stage adaptive: k1 = chi + max(4, chi/2), k = chi_max when the "
+                   "rank": ("two-stage adaptive: k1 = chi + max(4, chi/4), k = chi_max when the "
                             "Frobenius residual needs it (second pass skipped on the host when no "
                             "bond needs it)" if adaptive else "fixed k = chi_max"),
                    "chains": args.chains, "trotter_steps": steps,

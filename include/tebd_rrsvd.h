@@ -95,7 +95,7 @@ typedef struct {
   int32_t adaptive;     /* 0: fixed rank k = chi_max (Sec. IV, fixed-rank
                            problem).  1 (TEBD entry points only, trunc_eps > 0):
                            two-stage rank.  Stage 1 uses k1 = min(chi_max,
-                           chi + max(4, ceil(chi/2))) with chi the bond
+                           chi + max(4, ceil(chi/4))) with chi the bond
                            dimension before the update, and is kept when some
                            c <= k1 has w(c) <= trunc_eps; otherwise stage 2
                            repeats with k = chi_max, reusing the first Omega

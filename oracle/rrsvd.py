@@ -154,10 +154,12 @@ def rrsvd(a, omega, q):
 def first_stage_rank(chi_mid, chi_max):
     """Target rank of the first stage of the adaptive scheme.
 
-    The bond dimension before the update plus a margin of max(4, chi_mid/2)
-    (rounded up), capped by chi_max.
+    The bond dimension before the update plus a margin of max(4, chi_mid/4)
+    (rounded up), capped by chi_max.  A bond whose new dimension exceeds it
+    takes the second stage; in TEBD steps of a small time step the bond
+    dimension grows by a few per update at most.
     """
-    return int(min(chi_max, chi_mid + max(4, (chi_mid + 1) // 2)))
+    return int(min(chi_max, chi_mid + max(4, (chi_mid + 3) // 4)))
 
 
 def adaptive_factors(a, omega_of, q, chi_max, eps, k1, p):

@@ -106,7 +106,7 @@ __device__ __forceinline__ void plan_item(int t, Prob* probs, int nprob, const t
   if (l2 > P.n) l2 = P.n;
   int k1 = kcap, l = l2;
   if (adaptive == 1 || adaptive == 2) {  // first stage: the current bond dimension plus a margin
-    const int margin = (cm + 1) / 2 > 4 ? (cm + 1) / 2 : 4;
+    const int margin = (cm + 3) / 4 > 4 ? (cm + 3) / 4 : 4;
     k1 = cm + margin < kcap ? cm + margin : kcap;
     l = k1 + p_over;
     if (l > P.m) l = P.m;

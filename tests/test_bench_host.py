@@ -38,7 +38,7 @@ def test_first_stage_width_and_kernel_counts():
     before = np.array([1, 19, 19, 14, 1])
     after = np.array([1, 19, 21, 14, 1])
     k = _sweep(b, before, after, np.zeros(3, dtype=np.int32), 1)
-    m, n, l = 190, 140, 19 + 10 + 10            # k1 = chi + ceil(chi / 2), l1 = k1 + p
+    m, n, l = 190, 140, 19 + 5 + 10             # k1 = chi + ceil(chi / 4), l1 = k1 + p
     f = 8.0 * m * n * l
     assert k["k_sketch<0>"][0] == f
     assert k["k_sketch<2>"][0] == 2 * f          # q = 2
@@ -63,7 +63,7 @@ def test_second_pass_and_fixed_rank_widths():
     st[1] = 64                                   # the bond ran the fixed-rank second pass
     k = _sweep(b, before, after, st, 1)
     m, n = 190, 140
-    l1, l2 = 39, 110
+    l1, l2 = 34, 110                             # k1 = 19 + 5; k = chi_max = 100
     assert k["k_sketch<0>"][0] == 8.0 * m * n * (l1 + l2)
     assert k["k_omega"][1] == 16.0 * n * (l1 + l2)
     # U and V^H are formed once, by the pass whose result is kept
@@ -81,7 +81,7 @@ def test_qr_bytes_and_first_stage_rank():
     assert b.qr_bytes(10, 3) == 16 * 2 * 10 * 3
     assert b.qr_bytes(10, 3, with_r=True) == 16 * (2 * 10 * 3 + 9)
     assert b.first_stage_rank(1, 100) == 5
-    assert b.first_stage_rank(19, 100) == 29
+    assert b.first_stage_rank(19, 100) == 24
     assert b.first_stage_rank(90, 100) == 100
 
 

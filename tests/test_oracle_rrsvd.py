@@ -151,6 +151,7 @@ def test_adaptive_two_stage_rule():
     assert stage2 == 2
     fixed = rrsvd.truncate_rrsvd(a, omega_of(50), 2, 40, eps)
     assert chi2 == fixed[3] and np.array_equal(sv2, fixed[1]) and w2 == fixed[4]
-    # first-stage rank: chi + max(4, ceil(chi/2)), capped
-    assert rrsvd.first_stage_rank(1, 100) == 5 and rrsvd.first_stage_rank(19, 100) == 29
+    # first-stage rank: chi + max(4, ceil(chi/4)), capped
+    assert rrsvd.first_stage_rank(1, 100) == 5 and rrsvd.first_stage_rank(19, 100) == 24
+    assert rrsvd.first_stage_rank(40, 100) == 50
     assert rrsvd.first_stage_rank(90, 100) == 100
