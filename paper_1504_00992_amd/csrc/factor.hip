@@ -1484,42 +1484,84 @@ __device__ __forceinline__ void jacobi_finish(Prob& P, const zt* C, const zt* J,
 // min(chi_max, l).  TEBD: lambda' = s / ||s_{1..chi'}|| and chi' are written
 // into the MPS.  Run by the whole workgroup of the problem's small SVD after
 // it (sorted(c): the c-th largest singular value, from LDS); the scans run
-// on thread 0 so the summation order is fixed.
+// on thread 0 so the summation order is fixed.  The global reads (partial
+// sums, outer lambdas) are spread over the workgroup first: one thread
+// reading them one after another waited for each.
+constexpr int kTailChunk = 64;
+
 template <int NT, class Sorted>
 __device__ __forceinline__ void truncate_tail(Prob& P, int l, double eps, int tebd,
-                                              int32_t* retry_count, Sorted sorted) {
-  __shared__ int chi_s;
-  __shared__ double norm_s;
+                                              int32_t* retry_count, Sorted sorted, double* scan) {
+  __shared__ int chi_s, first_s;
+  __shared__ double norm_s, frob_s;
+  __shared__ double part_s[kTailChunk];
+  const int tid = threadIdx.x;
+  // ||A||_F^2 from the partial sums, the gate product's (TEBD) or k_frob's:
+  // loaded kTailChunk at a time, added by thread 0 in index order
+  const int npart =
+      tebd ? gate_partials(P.dl * P.dr, P.gcol0, P.chi_l * P.chi_r, P.gtw) : kFrobSlices;
   __syncthreads();  // the singular values are in place
-  if (threadIdx.x == 0) {
-    int flags = P.flags;
-    // ||A||_F^2 from the partial sums: the gate product's (TEBD) or k_frob's
-    const int npart =
-        tebd ? gate_partials(P.dl * P.dr, P.gcol0, P.chi_l * P.chi_r, P.gtw) : kFrobSlices;
-    double frob2 = 0.0;
-    for (int i = 0; i < npart; ++i) frob2 += P.part[i];
-    P.frob2 = frob2;
-    // A first stage that may still be retried only accepts a rank <= k1.
-    const bool can_retry = P.l2 > P.l1;
-    int cap = P.kcap < l ? P.kcap : l;
-    if (can_retry && P.k1 < cap) cap = P.k1;
-    double kept = 0.0;
-    int chi = cap;
-    double w = 0.0;
-    bool found = false;
-    bool finite = isfinite(frob2);
-    for (int c = 1; c <= l; ++c) {
-      const double sv = sorted(c - 1);
-      finite = finite && isfinite(sv);
-      kept += sv * sv;
-      const double wc = frob2 > 0.0 ? (frob2 - kept) / frob2 : 0.0;
-      if (eps > 0.0 && !found && c <= cap && wc <= eps) {
-        chi = c;
-        w = wc;
-        found = true;
-      }
-      if (c == cap && !found) w = wc;
+  // one round of global reads: the first chunk of partial sums, and whether
+  // an outer lambda is at or below the floor (its inverse was taken as 0)
+  if (tid < kTailChunk && tid < npart) part_s[tid] = P.part[tid];
+  bool floor_hit = false;
+  if (tebd) {
+    if (P.lam_l)
+      for (int a = tid; a < P.chi_l; a += NT) floor_hit |= !(P.lam_l[a] > P.lambda_floor);
+    if (P.lam_r)
+      for (int b = tid; b < P.chi_r; b += NT) floor_hit |= !(P.lam_r[b] > P.lambda_floor);
+  }
+  floor_hit = __syncthreads_or(floor_hit) != 0;
+  double frob2 = 0.0;
+  for (int i0 = 0; i0 < npart; i0 += kTailChunk) {
+    if (i0 > 0) {
+      __syncthreads();  // the previous chunk is summed
+      if (tid < kTailChunk && i0 + tid < npart) part_s[tid] = P.part[i0 + tid];
+      __syncthreads();
     }
+    if (tid == 0) {
+      const int n = npart - i0 < kTailChunk ? npart - i0 : kTailChunk;
+      for (int i = 0; i < n; ++i) frob2 += part_s[i];
+    }
+  }
+  // kept(c) = s_1^2 + ... + s_c^2 in index order (thread 0, into scan[c - 1]);
+  // then every c at once: w(c) = (||A||_F^2 - kept(c)) / ||A||_F^2, and chi'
+  // the smallest c <= cap with w(c) <= eps.  The same operations as one
+  // thread scanning c = 1, 2, ..., without its chain of divisions.
+  // A first stage that may still be retried only accepts a rank <= k1.
+  const bool can_retry = P.l2 > P.l1;
+  int cap = P.kcap < l ? P.kcap : l;
+  if (can_retry && P.k1 < cap) cap = P.k1;
+  if (tid == 0) {
+    double kept = 0.0;
+    for (int c = 0; c < l; ++c) {
+      const double sv = sorted(c);
+      kept += sv * sv;
+      scan[c] = kept;
+    }
+    frob_s = frob2;
+    first_s = INT32_MAX;
+  }
+  __syncthreads();
+  const double fr = frob_s;
+  int first = INT32_MAX;
+  bool nonfinite = false;
+  for (int c = tid + 1; c <= l; c += NT) {
+    nonfinite |= !isfinite(sorted(c - 1));
+    const double wc = fr > 0.0 ? (fr - scan[c - 1]) / fr : 0.0;
+    if (eps > 0.0 && c <= cap && wc <= eps && c < first) first = c;
+  }
+  if (first != INT32_MAX) atomicMin(&first_s, first);
+  nonfinite = __syncthreads_or(nonfinite) != 0;
+  if (tid == 0) {
+    int flags = P.flags;
+    P.frob2 = frob2;
+    const bool found = first_s != INT32_MAX;
+    const int chi = found ? first_s : cap;
+    // the discarded weight at chi' (or at cap when no c qualifies)
+    double w = fr > 0.0 ? (fr - scan[chi - 1]) / fr : 0.0;
+    const double nk = scan[chi - 1];  // the kept squares summed up to chi'
+    const bool finite = isfinite(frob2) && !nonfinite;
     int out = chi;
     if (can_retry && !(eps > 0.0 && found)) {
       // stage 1 rejected: leave every output untouched, run stage 2
@@ -1530,16 +1572,7 @@ __device__ __forceinline__ void truncate_tail(Prob& P, int l, double eps, int te
     if (eps > 0.0 && !found) flags |= TEBD_DEV_CHI_BOUND;
     if (!finite) flags |= TEBD_DEV_NONFINITE;
     if (w < 0.0) w = 0.0;
-    double nk = 0.0;
-    for (int c = 0; c < chi; ++c) nk += sorted(c) * sorted(c);
-    if (tebd) {
-      bool floor_hit = false;
-      if (P.lam_l)
-        for (int a = 0; a < P.chi_l; ++a) floor_hit |= !(P.lam_l[a] > P.lambda_floor);
-      if (P.lam_r)
-        for (int b = 0; b < P.chi_r; ++b) floor_hit |= !(P.lam_r[b] > P.lambda_floor);
-      if (floor_hit) flags |= TEBD_DEV_LAMBDA_FLOOR;
-    }
+    if (floor_hit) flags |= TEBD_DEV_LAMBDA_FLOOR;
     if (out >= 0) {
       P.chi_new = chi;
       P.flags = flags;
@@ -1583,12 +1616,63 @@ __host__ __device__ __forceinline__ int svd_class(int l) {
 // sweep limit as jacobi_core.
 constexpr int kPairGroupMax = 16;
 
+// A sweep whose rotations all turned by less than about 1e-7 rad (|g|^2 <=
+// kSmallTurn a b) leaves the columns so close to orthogonal that the next
+// sweep would likely rotate nothing; instead of running that sweep,
+// pairs_converged tests every pair of the current C at once.
+constexpr double kSmallTurn = 1e-14;
+
+// True when no pair of columns of C (stride S) would be rotated: every
+// |c_p^H c_q| <= tol |c_p| |c_q| (the test of jacobi_rotation), with the norms
+// recomputed.  The verdict of a sweep that rotates nothing, from l (l - 1) / 2
+// independent dot products instead of l - 1 dependent rounds.  Whole
+// workgroup (barriers inside); uses nrm[0..l).
+template <int NT>
+__device__ __forceinline__ bool pairs_converged(const zt* Cs, int S, int l, double tol,
+                                                double* nrm, int cn, int hn, int GN) {
+  double s = 0.0;
+  if (cn < l) s = col_norm2(Cs + cn * S, hn, l, GN);
+  s = group_sum(s, GN);
+  if (cn < l && hn == 0) nrm[cn] = s;
+  __syncthreads();
+  // thread t: columns {2a, 2a + 1} x {2b, 2b + 1}, a <= b, four dot products
+  // per pass over the rows (a missing last column repeats the one before)
+  const int nh = (l + 1) / 2;
+  int bad = 0;
+  for (int t = threadIdx.x; t < nh * nh; t += NT) {
+    const int a = t / nh, b = t - a * nh;
+    if (a > b) continue;
+    const int p0 = 2 * a, q0 = 2 * b;
+    const int p1 = p0 + 1 < l ? p0 + 1 : p0, q1 = q0 + 1 < l ? q0 + 1 : q0;
+    const zt* x0 = Cs + p0 * S;
+    const zt* x1 = Cs + p1 * S;
+    const zt* y0 = Cs + q0 * S;
+    const zt* y1 = Cs + q1 * S;
+    double g[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    for (int r = 0; r < l; ++r) {
+      const zt u0 = x0[r], u1 = x1[r], v0 = y0[r], v1 = y1[r];
+      zdot_acc(u0, v0, g[0][0], g[0][1]);
+      zdot_acc(u0, v1, g[1][0], g[1][1]);
+      zdot_acc(u1, v0, g[2][0], g[2][1]);
+      zdot_acc(u1, v1, g[3][0], g[3][1]);
+    }
+    const int ps[4] = {p0, p0, p1, p1}, qs[4] = {q0, q1, q0, q1};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double g2 = g[i][0] * g[i][0] + g[i][1] * g[i][1];
+      if (ps[i] < qs[i] && g2 > tol * tol * (nrm[ps[i]] * nrm[qs[i]]) && g2 != 0.0) bad = 1;
+    }
+  }
+  return __syncthreads_or(bad) == 0;
+}
+
 template <int NT, int CLS>
 __global__ __launch_bounds__(NT) void k_svd_pairs(Prob* probs, double eps, int tebd,
                                                   int32_t* retry_count) {
   extern __shared__ zt lds[];  // C, then J: l columns of stride l | 1 each
   __shared__ double nrm[64];
   __shared__ double sig_s[64];
+  __shared__ double srt_s[64];  // singular values in descending order
   __shared__ int perm_s[64];
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
@@ -1622,7 +1706,7 @@ __global__ __launch_bounds__(NT) void k_svd_pairs(Prob* probs, double eps, int t
     s = group_sum(s, GN);
     if (cn < l && hn == 0) nrm[cn] = s;
     __syncthreads();
-    int any = 0;
+    int any = 0, large = 0;
     for (int round = 0; round < lp - 1; ++round) {
       int p = 0, q = 0;
       bool act = k < lp / 2;
@@ -1673,11 +1757,14 @@ __global__ __launch_bounds__(NT) void k_svd_pairs(Prob* probs, double eps, int t
             nrm[q] = aqq + t * ag;
           }
           any = 1;
+          if (ag * ag > kSmallTurn * (app * aqq)) large = 1;
         }
       }
       __syncthreads();
     }
-    converged = __syncthreads_or(any) == 0;
+    const bool rotated = __syncthreads_or(any) != 0;
+    const bool turned_far = __syncthreads_or(large) != 0;
+    converged = !rotated || (!turned_far && pairs_converged<NT>(Cs, S, l, tol, nrm, cn, hn, GN));
   }
   if (!converged && tid == 0) P.flags |= TEBD_DEV_JACOBI_NOCONV;
   // singular values, descending order, sorted outputs
@@ -1706,8 +1793,12 @@ __global__ __launch_bounds__(NT) void k_svd_pairs(Prob* probs, double eps, int t
     P.X[e] = sv > 0.0 ? zscale(x, 1.0 / sv) : zero;
     P.W[e] = Js[src * S + r];
   }
-  if (tid < l) P.sig[tid] = sig_s[perm_s[tid]];
-  truncate_tail<NT>(P, l, eps, tebd, retry_count, [&](int c) { return sig_s[perm_s[c]]; });
+  if (tid < l) {
+    const double v = sig_s[perm_s[tid]];
+    srt_s[tid] = v;
+    P.sig[tid] = v;
+  }
+  truncate_tail<NT>(P, l, eps, tebd, retry_count, [&](int c) { return srt_s[c]; }, nrm);
 }
 
 // Classes 2 and 3: one pair per wavefront at a time (jacobi_core), C and J
@@ -1735,7 +1826,7 @@ __global__ __launch_bounds__(NT) void k_small_svd(Prob* probs, double eps, int t
   jacobi_core<NT, REGS>(C, J, l, converged, &rotated, nrm);
   if (!converged && threadIdx.x == 0) P.flags |= TEBD_DEV_JACOBI_NOCONV;
   jacobi_finish<NT>(P, C, J, l, sig_s, perm_s);
-  truncate_tail<NT>(P, l, eps, tebd, retry_count, [&](int c) { return sig_s[perm_s[c]]; });
+  truncate_tail<NT>(P, l, eps, tebd, retry_count, [&](int c) { return sig_s[perm_s[c]]; }, nrm);
 }
 
 hipError_t launch_small_svd(Prob* probs, const Common& c, hipStream_t s) {
