@@ -861,9 +861,41 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
       }
   };
   if constexpr (slots) {
-    if (have && mine < rank) start_q(nullptr);
-    for (int j = rank - 2; j >= 0; --j)
-      if (have && mine > j && mine < rank) apply(slot(j), j, false, nullptr);
+    // Every reflector keeps its slot, so any group can accumulate any column,
+    // and column c costs c applications.  The columns go out in blocks of the
+    // 64 / G groups of a wavefront, costliest block first, dealt to the four
+    // SIMDs back and forth (SIMD 0 1 2 3 3 2 1 0 0 1 ..., wavefront w on SIMD
+    // w mod 4, the k-th block of a SIMD to its k-th wavefront), so that the
+    // SIMDs carry similar sums.  The start H_c e_c comes from slot c: its
+    // rows > c are the column as it was when reflector c was built, row c
+    // holds v_c[c].  The same operations, in the same order, as when the
+    // group of column c accumulates it.
+    constexpr int GPW = 64 / G;
+    const int nblk = (rank + GPW - 1) / GPW;
+    const int wv = tid >> 6, kq = wv >> 2, sq = wv & 3;
+    const int dq = 4 * kq + ((kq & 1) ? 3 - sq : sq);  // deal position of this wavefront
+    const int qc = dq < nblk ? (nblk - 1 - dq) * GPW + g % GPW : rank;
+    if (qc < rank) {
+      const zt* vs = slot(qc);
+      const zt v0 = vs[qc];
+      const double tau = sh.tau_s[qc];
+      const zt m = make_double2(-tau * v0.x, tau * v0.y);  // -tau_c conj(v_c[c])
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = h + G * i;
+        y[i] = zmul(zload_if(r > qc && r < rows, vs + r), m);
+        if (r == qc) {
+          y[i] = zmul(v0, m);
+          y[i].x += 1.0;
+        }
+      }
+      for (int j = qc - 1; j >= 0; --j) apply(slot(j), j, false, nullptr);
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = h + G * i;
+        if (r < rows) Yg[size_t(qc) * rows + r] = y[i];
+      }
+    }
   } else {
     if (rank > 0 && mine == rank - 1) start_q(slot(rank - 1));
     for (int j = rank - 1; j >= 0; --j) {
@@ -871,12 +903,12 @@ __device__ __forceinline__ void qr_reg_body(Prob& P, int rows, int l, zt* Yg, in
       if (j > 0 && mine == j - 1) start_q(slot(j - 1));
       if (have && mine > j && mine < rank) apply(slot(j), j, false, nullptr);
     }
-  }
-  if (have && mine < rank) {
+    if (have && mine < rank) {
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-      const int r = h + G * i;
-      if (r < rows) Yg[size_t(mine) * rows + r] = y[i];
+      for (int i = 0; i < RPL; ++i) {
+        const int r = h + G * i;
+        if (r < rows) Yg[size_t(mine) * rows + r] = y[i];
+      }
     }
   }
   if (tid == 0) P.l = rank;
@@ -1364,9 +1396,57 @@ __device__ __forceinline__ int circle_player(int pos, int round, int lp) {
 // Column norms are recomputed exactly at the start of every sweep and then
 // carried through the rotations analytically (a' = a - t|g|, b' = b + t|g|),
 // so each pair needs a single complex reduction, g = c_p^H c_q.
-template <int NT, int REGS>
+// A sweep whose rotations all turned by less than about 1e-7 rad (|g|^2 <=
+// kSmallTurn a b) leaves the columns so close to orthogonal that the next
+// sweep would likely rotate nothing; instead of running that sweep,
+// pairs_below_tol tests every pair of the current C at once.
+constexpr double kSmallTurn = 1e-14;
+
+// True when no pair of columns of C (column c at C + c S) would be rotated:
+// every |c_p^H c_q| <= tol |c_p| |c_q| with nrm[c] = |c_c|^2 recomputed and
+// visible to the workgroup (the test of jacobi_rotation).  The verdict of a
+// sweep that rotates nothing, from l (l - 1) / 2 independent dot products
+// instead of l - 1 dependent rounds.  Whole workgroup (one barrier).
+template <int NT>
+__device__ __forceinline__ bool pairs_below_tol(const zt* C, int S, int l, double tol,
+                                                const double* nrm) {
+  // thread t: columns {2a, 2a + 1} x {2b, 2b + 1}, a <= b, four dot products
+  // per pass over the rows (a missing last column repeats the one before)
+  const int nh = (l + 1) / 2;
+  int bad = 0;
+  for (int t = threadIdx.x; t < nh * nh; t += NT) {
+    const int a = t / nh, b = t - a * nh;
+    if (a > b) continue;
+    const int p0 = 2 * a, q0 = 2 * b;
+    const int p1 = p0 + 1 < l ? p0 + 1 : p0, q1 = q0 + 1 < l ? q0 + 1 : q0;
+    const zt* x0 = C + size_t(p0) * S;
+    const zt* x1 = C + size_t(p1) * S;
+    const zt* y0 = C + size_t(q0) * S;
+    const zt* y1 = C + size_t(q1) * S;
+    double g[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    for (int r = 0; r < l; ++r) {
+      const zt u0 = x0[r], u1 = x1[r], v0 = y0[r], v1 = y1[r];
+      zdot_acc(u0, v0, g[0][0], g[0][1]);
+      zdot_acc(u0, v1, g[1][0], g[1][1]);
+      zdot_acc(u1, v0, g[2][0], g[2][1]);
+      zdot_acc(u1, v1, g[3][0], g[3][1]);
+    }
+    const int ps[4] = {p0, p0, p1, p1}, qs[4] = {q0, q1, q0, q1};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double g2 = g[i][0] * g[i][0] + g[i][1] * g[i][1];
+      if (ps[i] < qs[i] && g2 > tol * tol * (nrm[ps[i]] * nrm[qs[i]]) && g2 != 0.0) bad = 1;
+    }
+  }
+  return __syncthreads_or(bad) == 0;
+}
+
+// One pair per wavefront at a time; ALL_PAIRS: after a sweep of small turns,
+// pairs_below_tol may end the iteration without the sweep that rotates
+// nothing.
+template <int NT, int REGS, bool ALL_PAIRS>
 __device__ __forceinline__ void jacobi_core(zt* C, zt* J, int l, int& converged_out,
-                                            int* rotated, double* nrm) {
+                                            int* rotated, int* large, double* nrm) {
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lp = l + (l & 1);
@@ -1384,7 +1464,10 @@ __device__ __forceinline__ void jacobi_core(zt* C, zt* J, int l, int& converged_
       s = wave_sum(s);
       if (lane == 0) nrm[c] = s;
     }
-    if (tid == 0) *rotated = 0;
+    if (tid == 0) {
+      *rotated = 0;
+      *large = 0;
+    }
     __syncthreads();
     for (int round = 0; round < lp - 1; ++round) {
       for (int pr = wave; pr < lp / 2; pr += NW) {
@@ -1434,12 +1517,28 @@ __device__ __forceinline__ void jacobi_core(zt* C, zt* J, int l, int& converged_
           nrm[p] = fmax(app - t * ag, 0.0);
           nrm[q] = aqq + t * ag;
           *rotated = 1;
+          if (ag * ag > kSmallTurn * (app * aqq)) *large = 1;
         }
       }
       __syncthreads();
     }
     converged = (*rotated == 0);
+    const bool turned_far = (*large != 0);
     __syncthreads();
+    if (ALL_PAIRS && !converged && !turned_far) {
+      for (int c = wave; c < l; c += NW) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < REGS; ++i) {
+          const int r = lane + 64 * i;
+          if (r < l) s += zabs2(C[size_t(c) * l + r]);
+        }
+        s = wave_sum(s);
+        if (lane == 0) nrm[c] = s;
+      }
+      __syncthreads();
+      converged = pairs_below_tol<NT>(C, l, l, tol, nrm);
+    }
   }
   converged_out = converged ? 1 : 0;
 }
@@ -1616,55 +1715,6 @@ __host__ __device__ __forceinline__ int svd_class(int l) {
 // sweep limit as jacobi_core.
 constexpr int kPairGroupMax = 16;
 
-// A sweep whose rotations all turned by less than about 1e-7 rad (|g|^2 <=
-// kSmallTurn a b) leaves the columns so close to orthogonal that the next
-// sweep would likely rotate nothing; instead of running that sweep,
-// pairs_converged tests every pair of the current C at once.
-constexpr double kSmallTurn = 1e-14;
-
-// True when no pair of columns of C (stride S) would be rotated: every
-// |c_p^H c_q| <= tol |c_p| |c_q| (the test of jacobi_rotation), with the norms
-// recomputed.  The verdict of a sweep that rotates nothing, from l (l - 1) / 2
-// independent dot products instead of l - 1 dependent rounds.  Whole
-// workgroup (barriers inside); uses nrm[0..l).
-template <int NT>
-__device__ __forceinline__ bool pairs_converged(const zt* Cs, int S, int l, double tol,
-                                                double* nrm, int cn, int hn, int GN) {
-  double s = 0.0;
-  if (cn < l) s = col_norm2(Cs + cn * S, hn, l, GN);
-  s = group_sum(s, GN);
-  if (cn < l && hn == 0) nrm[cn] = s;
-  __syncthreads();
-  // thread t: columns {2a, 2a + 1} x {2b, 2b + 1}, a <= b, four dot products
-  // per pass over the rows (a missing last column repeats the one before)
-  const int nh = (l + 1) / 2;
-  int bad = 0;
-  for (int t = threadIdx.x; t < nh * nh; t += NT) {
-    const int a = t / nh, b = t - a * nh;
-    if (a > b) continue;
-    const int p0 = 2 * a, q0 = 2 * b;
-    const int p1 = p0 + 1 < l ? p0 + 1 : p0, q1 = q0 + 1 < l ? q0 + 1 : q0;
-    const zt* x0 = Cs + p0 * S;
-    const zt* x1 = Cs + p1 * S;
-    const zt* y0 = Cs + q0 * S;
-    const zt* y1 = Cs + q1 * S;
-    double g[4][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-    for (int r = 0; r < l; ++r) {
-      const zt u0 = x0[r], u1 = x1[r], v0 = y0[r], v1 = y1[r];
-      zdot_acc(u0, v0, g[0][0], g[0][1]);
-      zdot_acc(u0, v1, g[1][0], g[1][1]);
-      zdot_acc(u1, v0, g[2][0], g[2][1]);
-      zdot_acc(u1, v1, g[3][0], g[3][1]);
-    }
-    const int ps[4] = {p0, p0, p1, p1}, qs[4] = {q0, q1, q0, q1};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const double g2 = g[i][0] * g[i][0] + g[i][1] * g[i][1];
-      if (ps[i] < qs[i] && g2 > tol * tol * (nrm[ps[i]] * nrm[qs[i]]) && g2 != 0.0) bad = 1;
-    }
-  }
-  return __syncthreads_or(bad) == 0;
-}
 
 template <int NT, int CLS>
 __global__ __launch_bounds__(NT) void k_svd_pairs(Prob* probs, double eps, int tebd,
@@ -1764,7 +1814,15 @@ __global__ __launch_bounds__(NT) void k_svd_pairs(Prob* probs, double eps, int t
     }
     const bool rotated = __syncthreads_or(any) != 0;
     const bool turned_far = __syncthreads_or(large) != 0;
-    converged = !rotated || (!turned_far && pairs_converged<NT>(Cs, S, l, tol, nrm, cn, hn, GN));
+    converged = !rotated;
+    if (rotated && !turned_far) {
+      double s2 = 0.0;
+      if (cn < l) s2 = col_norm2(Cs + cn * S, hn, l, GN);
+      s2 = group_sum(s2, GN);
+      if (cn < l && hn == 0) nrm[cn] = s2;
+      __syncthreads();
+      converged = pairs_below_tol<NT>(Cs, S, l, tol, nrm);
+    }
   }
   if (!converged && tid == 0) P.flags |= TEBD_DEV_JACOBI_NOCONV;
   // singular values, descending order, sorted outputs
@@ -1809,7 +1867,7 @@ __global__ __launch_bounds__(NT) void k_small_svd(Prob* probs, double eps, int t
   extern __shared__ zt lds[];
   __shared__ double sig_s[kMaxL];
   __shared__ int perm_s[kMaxL];
-  __shared__ int rotated;
+  __shared__ int rotated, large_turn;
   __shared__ double nrm[kMaxL];
   Prob& P = probs[blockIdx.x];
   const int l = P.l;
@@ -1823,7 +1881,9 @@ __global__ __launch_bounds__(NT) void k_small_svd(Prob* probs, double eps, int t
   }
   __syncthreads();
   int converged;
-  jacobi_core<NT, REGS>(C, J, l, converged, &rotated, nrm);
+  // the all-pairs test only where C is in LDS (from global memory it costs
+  // about the sweep it would save)
+  jacobi_core<NT, REGS, LDS_CJ>(C, J, l, converged, &rotated, &large_turn, nrm);
   if (!converged && threadIdx.x == 0) P.flags |= TEBD_DEV_JACOBI_NOCONV;
   jacobi_finish<NT>(P, C, J, l, sig_s, perm_s);
   truncate_tail<NT>(P, l, eps, tebd, retry_count, [&](int c) { return sig_s[perm_s[c]]; }, nrm);
