@@ -250,14 +250,15 @@ def merge_tile_variants(prof):
     return out
 
 
-def kernel_roofline(prof, work, workload):
-    """Roofline entry of the kernel with the largest event time."""
+def kernel_roofline(prof, work, workload, name=None):
+    """Roofline entry of one kernel: `name`, or the one with the largest event time."""
     wide = any(k.startswith("k_sketch_wide<") for k in prof)
     prof = merge_tile_variants(prof)
     kern = {k: v for k, v in prof.items() if k.startswith("k_")}
     if not kern:
         return None
-    name = max(kern, key=lambda k: kern[k][0])
+    if name is None:
+        name = max(kern, key=lambda k: kern[k][0])
     ms, launches = kern[name]
     e = {"kernel": name, "launches": launches, "event_ms_total": round(ms, 3),
          "avg_launch_us": round(1e3 * ms / launches, 3) if launches else None}
@@ -290,6 +291,20 @@ def kernel_roofline(prof, work, workload):
                                                    " (taken on other kernel sources: not used)")
     e["measured"] = "HIP events around every launch of a profiled repetition, on its stream"
     return e
+
+
+def kernel_rooflines(prof, work, workload):
+    """The roofline position of every library kernel of a run, by event time
+    (achieved, peak and fraction as in the roofline entry; traffic = measured
+    HBM bytes per launch where the counters match the kernel sources)."""
+    merged = merge_tile_variants(prof)
+    out = {}
+    for name in sorted((k for k in merged if k.startswith("k_")), key=lambda k: -merged[k][0]):
+        e = kernel_roofline(prof, work, workload, name)
+        out[name] = {k: e.get(k) for k in ("launches", "avg_launch_us", "bound", "achieved",
+                                            "peak", "unit", "frac", "algorithmic_bytes_per_launch",
+                                            "traffic")}
+    return out
 
 
 def kernel_table(prof):
@@ -1148,6 +1163,7 @@ def main():
         prof, hist = ev.profiled(steps, _lib)
         w = history_work(_lib, hist, dims, SB["chi_max"], SB["p"], SB["q"], adaptive)
         line["roofline"] = kernel_roofline(prof, w, "spin_boson_16x100")
+        line["kernel_rooflines"] = kernel_rooflines(prof, w, "spin_boson_16x100")
         # the gate product (one per group of chains sharing a gate): HBM bytes
         # per launch, algorithmic against the counters' (when taken on these
         # kernel sources)

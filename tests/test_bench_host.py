@@ -146,3 +146,25 @@ def test_traffic_summary_round_trip(tmp_path, monkeypatch):
     (prof / "wl_hbm_traffic.txt").write_text(text)
     monkeypatch.setattr(b, "ROOT", str(tmp_path))
     assert b.measured_traffic("k_qr_reg<512, 8, false>", "wl")[0] == 1024 * 48.0
+
+
+def test_every_kernel_gets_its_roofline_position():
+    b = _bench()
+    before = np.array([1, 19, 19, 14, 1])
+    after = np.array([1, 19, 21, 14, 1])
+    w = b.Work(_Classes())
+    b.sweep_work(w, before[None, :], after[None, :], np.zeros((1, 3), dtype=np.int32), 1,
+                 [10, 10, 10, 10], 100, 10, 2, True)
+    prof = {"k_sketch<1>": (2.0, 3), "k_sketch_wide<1>": (1.0, 1), "k_gate": (0.5, 1),
+            "k_qr_reg<1024, 12, false>": (4.0, 5), "k_omega": (0.1, 1), "sketch_AH_Q": (3.0, 4)}
+    table = b.kernel_rooflines(prof, w, "no_such_workload")
+    # phases are not kernels; the two tile variants count as one kernel; order by event time
+    assert list(table) == ["k_qr_reg<1024, 12, false>", "k_sketch<1>", "k_gate", "k_omega"]
+    sk = table["k_sketch<1>"]
+    assert sk["launches"] == 4 and sk["bound"] == "mfma" and sk["unit"] == "TFLOP/s"
+    assert abs(sk["achieved"] - w.k["k_sketch<1>"][0] / 3.0e-3 / 1e12) < 1e-4
+    assert abs(sk["frac"] - sk["achieved"] / b.PEAK_FP64_TFLOPS) < 1e-5
+    assert table["k_qr_reg<1024, 12, false>"]["bound"] == "alu"
+    assert table["k_gate"]["traffic"] is None      # no counters for this workload
+    # the dominant kernel's entry is the headline roofline
+    assert b.kernel_roofline(prof, w, "no_such_workload")["kernel"] == "k_qr_reg<1024, 12, false>"
