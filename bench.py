@@ -239,12 +239,13 @@ ALU_KERNELS = ("k_qr_", "k_svd_pairs", "k_small_svd", "k_omega", "k_schedule",
 
 
 def merge_tile_variants(prof):
-    """The two tile variants of a sketch product (k_sketch<i> on 32 x 32,
-    k_sketch_wide<i> on 64 x 64 tiles, picked per launch by the autotune
-    cache) do the same work: count them as one kernel, k_sketch<i>."""
+    """The tile variants of a sketch product (k_sketch<i> on 32 x 32,
+    k_sketch_wide<i> on 64 x 64, k_sketch_split<i> on split-depth 16 x 16
+    tiles, picked per launch by the autotune cache) do the same work: count
+    them as one kernel, k_sketch<i>."""
     out = {}
     for k, (ms, n) in prof.items():
-        key = k.replace("k_sketch_wide<", "k_sketch<")
+        key = k.replace("k_sketch_wide<", "k_sketch<").replace("k_sketch_split<", "k_sketch<")
         a = out.get(key, (0.0, 0))
         out[key] = (a[0] + ms, a[1] + n)
     return out
@@ -252,7 +253,7 @@ def merge_tile_variants(prof):
 
 def kernel_roofline(prof, work, workload, name=None):
     """Roofline entry of one kernel: `name`, or the one with the largest event time."""
-    wide = any(k.startswith("k_sketch_wide<") for k in prof)
+    wide = any(k.startswith(("k_sketch_wide<", "k_sketch_split<")) for k in prof)
     prof = merge_tile_variants(prof)
     kern = {k: v for k, v in prof.items() if k.startswith("k_")}
     if not kern:
@@ -263,8 +264,8 @@ def kernel_roofline(prof, work, workload, name=None):
     e = {"kernel": name, "launches": launches, "event_ms_total": round(ms, 3),
          "avg_launch_us": round(1e3 * ms / launches, 3) if launches else None}
     if wide and name.startswith("k_sketch<"):
-        e["note_variants"] = ("launches of k_sketch<i> and k_sketch_wide<i> (the two tile "
-                              "variants) counted together")
+        e["note_variants"] = ("launches of the tile variants k_sketch<i>, k_sketch_wide<i> "
+                              "and k_sketch_split<i> counted together")
     fl, by = work.k.get(name, (0.0, 0.0))
     f32 = name.startswith("k_sketch_f32")
     if fl > 0 and ms > 0:
@@ -612,7 +613,8 @@ def batched_rrsvd_line(args, torch, api, wl, lib):
         w.rrsvd_pass(n, n, l, 2, False, int(c))
     if "k_form_uv<1>" in w.k:   # the standalone call writes plain U, V^H
         w.k["k_form_uv<0>"] = w.k.pop("k_form_uv<1>")
-    sk_ms = sum(v[0] for k, v in prof.items() if k.startswith(("k_sketch<", "k_sketch_wide<")))
+    sk_ms = sum(v[0] for k, v in prof.items()
+                if k.startswith(("k_sketch<", "k_sketch_wide<", "k_sketch_split<")))
     sk_fl = sum(v[0] for k, v in w.k.items() if k.startswith("k_sketch<"))
     ach = sk_fl / (sk_ms * 1e-3) / 1e12 if sk_ms > 0 else None
     res = {"metric": "RRSVD truncations/s", "value": round(len(sizes) * reps / sum(times), 2),
@@ -1127,6 +1129,14 @@ def main():
     dims, hb = models.spin_boson(N, SB["d"], 1.0, 0.5, 1.0, 0.5)
     ev = Evolution(torch, api, dims, hb, [0] * N, args.chains, SB["chi_max"], SB["p"], SB["q"],
                    SB["dt"], SB["eps"], SB["seed"], adaptive=2 if adaptive else 0)
+    # the TEBD buckets of the cache are tuned on this evolution (untimed runs)
+    if not any(e.get("workload") == "spin_boson_16x100" for e in tuned):
+        t1 = time.perf_counter()
+        wl_entries = autotune.tune_workload(lambda: ev.timed(steps, 1, 0), "spin_boson_16x100")
+        tune_entry["workload_entries"] = wl_entries
+        tune_entry["workload_seconds"] = round(time.perf_counter() - t1, 2)
+        _progress(f"autotune on the evolution: variant {wl_entries[0]['variant']} "
+                  f"({wl_entries[0]['workload_s']} s per evolution for variants {list(autotune.VARIANTS)})")
     times = ev.timed(steps, args.steps, args.warmup)
     sec = sum(times)
     per_rep = steps * updates_per_step(N) * args.chains

@@ -339,9 +339,12 @@ tebd_status tebd_profile_read(int32_t capacity, const char** names, double* ms, 
  * launch, from the largest problem of the batch: its row count (bucketed
  * as <= 128, 256, 512, 1024, 2048, 8192) and sketch width (<= 32, 64, 80,
  * 128, 256).  variant 0: 32 x 32 output tiles (the default, also for unset
- * entries); 1: 64 x 64 tiles; -1 unsets.  precision 1 (complex FP32
- * products) has variant 0 only.  The results do not depend
- * on the variant (the same K order per output element).  The package's
+ * entries); 1: 64 x 64 tiles; 2: 16 x 16 tiles, each split over the
+ * contraction depth between the four wavefronts of its workgroup; -1
+ * unsets.  precision 1 (complex FP32 products) has variant 0 only.
+ * Variants 0 and 1 give identical results (the same K order per output
+ * element); variant 2 adds four partial sums over interleaved k-steps, so
+ * its results differ from theirs by rounding only.  The package's
  * autotune module times the variants on synthetic batches and keeps its
  * choices in a JSON file.
  * tebd_tune_set: TEBD_ERR_ARG for an unknown precision or variant,

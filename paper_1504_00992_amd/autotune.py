@@ -2,11 +2,12 @@
 
 For each (largest rows, sketch width) bucket of the cache, a synthetic batch
 of that shape is truncated with each tile variant of the sketch, power-
-iteration and projection products (32 x 32 or 64 x 64 output tiles), the
-products' kernel time is taken from the library's per-launch events, and
-the faster variant is stored in the library (tebd_tune_set) and in a JSON
-file, which later processes load instead of timing again.  The variants give
-identical results; only speed depends on the choice.
+iteration and projection products (32 x 32 or 64 x 64 output tiles, or
+16 x 16 tiles split over the contraction depth), the products' kernel time
+is taken from the library's per-launch events, and the fastest variant is
+stored in the library (tebd_tune_set) and in a JSON file, which later
+processes load instead of timing again.  The variants agree to rounding
+(the first two exactly); only speed depends on the choice.
 """
 import json
 import os
@@ -15,7 +16,7 @@ from . import _lib
 
 ROW_BUCKETS = (128, 256, 512, 1024, 2048, 8192)
 WIDTH_BUCKETS = (32, 64, 80, 128, 256)
-VARIANTS = (0, 1)
+VARIANTS = (0, 1, 2)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "tebd_rrsvd", "tuning.json")
 
 
@@ -84,4 +85,49 @@ def tune(buckets=((256, 64), (512, 80), (1024, 80), (2048, 80), (512, 128), (102
         del mats
     name = torch.cuda.get_device_name(0) if torch.cuda.is_available() else ""
     save(entries, path, name)
+    return entries
+
+
+# Buckets of the TEBD sweeps (bond problems of at most 256 rows, sketch width
+# at most 64): a sweep batches a few large problems with many small ones, so
+# its sketch products are bound by the longest tile's chain of matrix-core
+# steps, which a batch of equal synthetic matrices does not show.  These are
+# tuned on the workload itself.
+SMALL_BUCKETS = ((128, 32), (128, 64), (256, 32), (256, 64))
+
+
+def tune_workload(run, workload, buckets=SMALL_BUCKETS, reps=2, path=None):
+    """Tune `buckets` on a real workload: `run()` executes it once (device work
+    included).  Each variant is assigned to every bucket in turn and timed
+    over `reps` runs after one warm-up; the fastest is kept for all of them,
+    stored in the library and merged into the JSON cache (entries of other
+    buckets are kept).  Returns the new entries."""
+    import time
+    import torch
+    times = []
+    for v in VARIANTS:
+        for rows, width in buckets:
+            _lib.check(_lib.tebd_tune_set(0, rows, width, v))
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run()
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) / reps)
+    best = VARIANTS[min(range(len(times)), key=lambda i: times[i])]
+    entries = [{"precision": 0, "rows": int(r), "width": int(w), "variant": best,
+                "workload": workload, "workload_s": [round(t, 5) for t in times]}
+               for r, w in buckets]
+    for e in entries:
+        _lib.check(_lib.tebd_tune_set(0, e["rows"], e["width"], best))
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        data = {"device": "", "entries": []}
+    keys = {(e["precision"], e["rows"], e["width"]) for e in entries}
+    kept = [e for e in data.get("entries", []) if (e["precision"], e["rows"], e["width"]) not in keys]
+    save(kept + entries, path, data.get("device", ""))
     return entries

@@ -362,8 +362,9 @@ int32_t persistent_grid(int64_t cap_tiles) {
 }
 
 // With c.bounds_dev set, the size bounds that k_schedule writes are read back
-// while the contractions before the first QR run, and replace c's bounds, so
-// that only the QR size classes the batch reaches are launched.
+// while Theta, the gate and Omega run, and replace c's bounds, so that the
+// products take the tile variant and grid of the batch's real sizes and only
+// the QR size classes the batch reaches are launched.
 hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
   hipError_t e;
 #define TRY(x)                     \
@@ -388,7 +389,8 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
   auto sketch = [&](int which) {
     return c.mixed ? launch_sketch_f32(probs, c, which, s) : launch_sketch(probs, c, which, s);
   };
-  TIMED(PK_SKETCH_AOM, sketch(SK_Y_FROM_OMEGA));
+  // the bounds arrive while Theta, the gate and Omega run: the first sketch
+  // product already takes the tile variant and grid of the batch's real sizes
   if (c.bounds_dev) {
     int32_t b[6 + TK_COUNT];
     static_assert(kBoundsSlot + 6 + TK_COUNT <= 64, "bounds fit the pinned buffer");
@@ -401,6 +403,7 @@ hipError_t run_pipeline(Prob* probs, Common& c, hipStream_t s) {
     c.lmax = b[5];
     for (int k = 0; k < TK_COUNT; ++k) c.ktiles[k] = b[6 + k];
   }
+  TIMED(PK_SKETCH_AOM, sketch(SK_Y_FROM_OMEGA));
   // the first QR reveals the sketch's rank (column pivoting); the power
   // iterations keep that rank and orthonormalise without pivoting
   // The large problems may take the Gram-based QR first (when their sketch
@@ -527,9 +530,9 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   // thread, with a quarter of headroom: any grid covers every tile (the
   // launches are persistent), so the estimate only affects speed.
   static thread_local int32_t last_tiles[2][TK_COUNT] = {
-      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1},
-      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1}};
-  static_assert(TK_COUNT == 15, "one -1 per tile kind above");
+      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1},
+      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1}};
+  static_assert(TK_COUNT == 17, "one -1 per tile kind above");
   if (c.adaptive == 3) {
     c.acc_count = c.retry_count + kAccCountSlot;
     c.acc_lcap = int32_t(pl.lcap);

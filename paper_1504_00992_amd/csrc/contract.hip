@@ -449,7 +449,39 @@ __global__ __launch_bounds__(256) void k_sketch_wide(Prob* probs, const int32_t*
   sketch_tiles<WHICH, Cfg64, TK_SKM_W, TK_SKN_W>(probs, offs, nprob, tebd, smem);
 }
 
-// Autotune cache: variant per (precision, rows bucket, width bucket); -1
+// The FP64 sketch products on 16 x 16 tiles, each split over the depth
+// between the four wavefronts (zgemm_tile_split16; chosen per launch by the
+// autotune cache).
+template <int WHICH>
+__global__ __launch_bounds__(256) void k_sketch_split(Prob* probs, const int32_t* offs, int nprob,
+                                                      int tebd) {
+  __shared__ double red[2048];
+  if (WHICH == SK_Y_FROM_OMEGA) {
+    for_each_tile<TK_SKM_S>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdRowA la{P.A, P.lda};
+      LdRowB lb{P.om, P.ldom};
+      StCol st{P.Y, P.m};
+      zgemm_tile_split16(M, N, P.n, m0, n0, la, lb, st, red);
+    });
+  } else if (WHICH == SK_YT_FROM_Y) {
+    for_each_tile<TK_SKN_S>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdAdjA la{P.A, P.lda};
+      LdColB lb{P.Y, P.m};
+      StCol st{P.Yt, P.n};
+      zgemm_tile_split16(M, N, P.m, m0, n0, la, lb, st, red);
+    });
+  } else {
+    for_each_tile<TK_SKM_S>(probs, offs, nprob, tebd, [&](Prob& P, int M, int N, int m0, int n0, int) {
+      LdRowA la{P.A, P.lda};
+      LdColB lb{P.Yt, P.n};
+      StCol st{P.Y, P.m};
+      zgemm_tile_split16(M, N, P.n, m0, n0, la, lb, st, red);
+    });
+  }
+}
+
+// Autotune cache: variant per (precision, rows bucket, width bucket): 0 the
+// 32 x 32 tiles, 1 the 64 x 64 tiles, 2 the split-depth 16 x 16 tiles; -1
 // (unset) means the 32 x 32 tiles.  Written by tebd_tune_set between calls.
 namespace {
 constexpr int kTuneRows[6] = {128, 256, 512, 1024, 2048, 8192};
@@ -483,6 +515,16 @@ hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s)
       TEBD_LAUNCH("k_sketch_wide<1>", k_sketch_wide<SK_YT_FROM_Y>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
     else
       TEBD_LAUNCH("k_sketch_wide<2>", k_sketch_wide<SK_Y_FROM_YT>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+    return hipGetLastError();
+  }
+  if (variant == 2) {
+    const dim3 g(grid_for(c, which == SK_YT_FROM_Y ? TK_SKN_S : TK_SKM_S));
+    if (which == SK_Y_FROM_OMEGA)
+      TEBD_LAUNCH("k_sketch_split<0>", k_sketch_split<SK_Y_FROM_OMEGA>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+    else if (which == SK_YT_FROM_Y)
+      TEBD_LAUNCH("k_sketch_split<1>", k_sketch_split<SK_YT_FROM_Y>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
+    else
+      TEBD_LAUNCH("k_sketch_split<2>", k_sketch_split<SK_Y_FROM_YT>, g, dim3(256), 0, s, probs, c.offs, c.nprob, c.tebd);
     return hipGetLastError();
   }
   const dim3 g(grid_for(c, which == SK_YT_FROM_Y ? TK_SKN : TK_SKM));
@@ -685,7 +727,7 @@ hipError_t launch_tape(Prob* probs, const Common& c, hipStream_t s) {
 extern "C" tebd_status tebd_tune_set(int32_t precision, int32_t max_rows, int32_t width,
                                      int32_t variant) {
   using namespace tebd;
-  if (precision < 0 || precision > 1 || variant < -1 || variant > 1 ||
+  if (precision < 0 || precision > 1 || variant < -1 || variant > 2 ||
       (precision == 1 && variant > 0))
     return TEBD_ERR_ARG;
   const int br = tune_bucket(kTuneRows, 6, max_rows), bw = tune_bucket(kTuneWidth, 5, width);

@@ -101,7 +101,7 @@ struct Prob {
   int32_t tape_ldu, tape_ldvh;
 };
 
-constexpr int TK_COUNT_MAX = 15;  // tile kinds of the forward pipeline (enum below)
+constexpr int TK_COUNT_MAX = 17;  // tile kinds of the forward pipeline (enum below)
 
 // Parameters of a launch sequence that are common to all problems.
 struct Common {
@@ -124,8 +124,8 @@ struct Common {
   int32_t* retry_count;  // device: problems whose first stage was rejected (adaptive rank)
   int32_t* bounds_dev = nullptr;  // host-mapped pinned memory: k_schedule writes {min, max}
                                   // of m, n, l1 there, then the tile total of every kind
-  int32_t ktiles[TK_COUNT_MAX] = {-1, -1, -1, -1, -1, -1, -1, -1,
-                                  -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
+  int32_t ktiles[TK_COUNT_MAX] = {-1, -1, -1, -1, -1, -1, -1, -1, -1,
+                                  -1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
   int32_t serial = 0;  // 1: size classes run in order on the caller's stream (no side streams)
@@ -187,7 +187,9 @@ enum {
   TK_QAPM = 12,  // Gram-based QR: m x l products Y R^-1
   TK_QAPN = 13,  // Gram-based QR: n x l products Yt R^-1
   TK_GATE_W = 14, // gate groups with many columns: 64 x 64 tiles
-  TK_COUNT = 15
+  TK_SKM_S = 15, // TK_SKM on 16 x 16 tiles (the split-depth sketch variant)
+  TK_SKN_S = 16, // TK_SKN on 16 x 16 tiles
+  TK_COUNT = 17
 };
 
 static_assert(TK_COUNT == TK_COUNT_MAX, "Common::ktiles holds one total per kind");

@@ -16,6 +16,11 @@ namespace tebd {
 // contraction depth is the critical path, so smaller tiles spread it over
 // more compute units.
 constexpr int kSketchTileM = 32, kSketchTileN = 32;
+// The split-depth variant: 16 x 16 tiles, each computed by the four
+// wavefronts of a workgroup over a quarter of the contraction depth, so
+// that a tile's chain of matrix-core steps is four times shorter and the
+// largest problems spread over four times as many compute units.
+constexpr int kSketchTileS = 16;
 
 // Extent of the updated bond index that a TEBD update writes in Gamma^[k]
 // (columns) and Gamma^[k+1] (rows): the new dimension chi' <= min(l, chi_max)
@@ -37,12 +42,18 @@ struct TileKinds<Prob> {
            kind == TK_QAPN;
   }
   static constexpr int tile_m(int kind) {
-    return kind == TK_GATE || kind == TK_GATE_W ? kGateTileM : small_tiles(kind) ? kSketchTileM : 64;
+    return kind == TK_GATE || kind == TK_GATE_W       ? kGateTileM
+           : kind == TK_SKM_S || kind == TK_SKN_S     ? kSketchTileS
+           : small_tiles(kind)                        ? kSketchTileM
+                                                      : 64;
   }
   // TK_SKM_W / TK_SKN_W: the same products on 64 x 64 tiles
   static constexpr int tile_n(int kind) {
-    return kind == TK_GATE ? kGateTileN : kind == TK_GATE_W ? kGateTileW
-                                        : small_tiles(kind) ? kSketchTileN : 64;
+    return kind == TK_GATE                        ? kGateTileN
+           : kind == TK_GATE_W                    ? kGateTileW
+           : kind == TK_SKM_S || kind == TK_SKN_S ? kSketchTileS
+           : small_tiles(kind)                    ? kSketchTileN
+                                                  : 64;
   }
   __device__ static __forceinline__ void shape(int kind, const Prob& P, int tebd, int& M, int& N) {
     M = N = 0;
@@ -64,11 +75,13 @@ struct TileKinds<Prob> {
         break;
       case TK_SKM:
       case TK_SKM_W:
+      case TK_SKM_S:
         M = P.m;
         N = P.l;
         break;
       case TK_SKN:
       case TK_SKN_W:
+      case TK_SKN_S:
         M = P.n;
         N = P.l;
         break;

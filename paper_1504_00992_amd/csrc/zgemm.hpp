@@ -173,6 +173,61 @@ __device__ void zgemm_tile(int M, int N, int K, int m0, int n0, const LA& la, co
       }
 }
 
+// 16 x 16 tile of C = op(A) op(B) by the four wavefronts of a 256-thread
+// workgroup, each over every fourth k-step of 4 (wavefront w: k in
+// [4w, 4w + 4), [4w + 16, 4w + 20), ...), with the operands read by each
+// lane straight into its matrix-core registers (lane t: A[t % 16][k + t / 16]
+// and B[k + t / 16][t % 16]), four k-steps in flight.  No LDS staging and no
+// barrier in the loop; the four partial tiles meet in LDS (red: 2048
+// doubles) and are added in wavefront order.  The chain of dependent matrix-
+// core steps is a quarter of a single wavefront's over the full depth.
+template <class LA, class LB, class ST>
+__device__ void zgemm_tile_split16(int M, int N, int K, int m0, int n0, const LA& la,
+                                   const LB& lb, ST& st, double* red) {
+  constexpr int U = 4;  // k-steps loaded ahead
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = m0 + (lane & 15), c = n0 + (lane & 15), kl = lane >> 4;
+  const bool rin = r < M, cin = c < N;
+  const zt zero = make_double2(0.0, 0.0);
+  v4d accr = {0.0, 0.0, 0.0, 0.0}, acci = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 4 * wave; k0 < K; k0 += 16 * U) {
+    zt a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + 16 * u + kl;
+      a[u] = (rin && k < K) ? la(r, k) : zero;
+      b[u] = (cin && k < K) ? lb(k, c) : zero;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      accr = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].x, accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].y, acci, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[u].y, b[u].y, accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b[u].x, acci, 0, 0, 0);
+    }
+  }
+  // red[((w * 4 + i) * 2 + part) * 64 + lane]: element i of lane's
+  // accumulators, C[lane / 16 + 4 i][lane % 16]
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    red[((wave * 4 + i) * 2 + 0) * 64 + lane] = accr[i];
+    red[((wave * 4 + i) * 2 + 1) * 64 + lane] = acci[i];
+  }
+  __syncthreads();
+  {
+    const int e = threadIdx.x, row = e >> 4, col = e & 15;
+    const int t = (row & 3) * 16 + col, i = row >> 2;
+    double vr = 0.0, vi = 0.0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      vr += red[((w * 4 + i) * 2 + 0) * 64 + t];
+      vi += red[((w * 4 + i) * 2 + 1) * 64 + t];
+    }
+    if (m0 + row < M && n0 + col < N) st(m0 + row, n0 + col, make_double2(vr, vi));
+  }
+  __syncthreads();  // red is read before the next tile writes it
+}
+
 // Narrow tiles (at most NC of the BN columns in range): the same staging,
 // with the product formed on the vector ALU (thread t < BM owns row
 // m0 + t, reading its column of the A slab and broadcast B entries from

@@ -194,16 +194,17 @@ def test_table_two_shapes_match_oracle(n):
 
 
 def test_wide_sketch_tiles_give_the_same_results():
-    # the autotune cache's two tile variants of the sketch, power-iteration
-    # and projection products: both agree with the oracle, and with each
-    # other to rounding (the K order of every output element is the same)
+    # the autotune cache's tile variants of the sketch, power-iteration and
+    # projection products: all agree with the oracle; 32 x 32 and 64 x 64
+    # tiles with each other exactly (the K order of every output element is
+    # the same), the split-depth 16 x 16 tiles to rounding
     from paper_1504_00992_amd import _lib
     gen = wl.rng(31)
     shapes = [(300, 200), (700, 650), (64, 90)]
     mats = [wl.known_spectrum(m, n, np.exp(-np.arange(min(m, n)) / 9.0), gen) for m, n in shapes]
     outs = []
     try:
-        for v in (0, 1):
+        for v in (0, 1, 2):
             assert _lib.tebd_tune_set(0, 700, 74, v) == 0
             res = _gpu(mats, 64, 10, 2, 1e-10)
             _compare(mats, res, 64, 10, 2, 1e-10)
@@ -229,6 +230,41 @@ def test_autotuner_times_every_variant(tmp_path):
         assert autotune.load(path)[0]["variant"] == entries[0]["variant"]
     finally:
         _lib.tebd_tune_set(0, 256, 64, -1)
+
+
+def test_workload_tuning_sets_its_buckets_and_keeps_the_others(tmp_path):
+    # tune_workload: every variant timed on the given run, the fastest stored
+    # for all its buckets, merged into an existing cache file
+    import json
+    import torch
+    from paper_1504_00992_amd import _lib, autotune
+    path = str(tmp_path / "tune.json")
+    autotune.save([{"precision": 0, "rows": 2048, "width": 128, "variant": 1},
+                   {"precision": 0, "rows": 256, "width": 64, "variant": 0}], path)
+    gen = wl.rng(5)
+    mats = [wl.known_spectrum(200, 180, np.exp(-np.arange(180) / 12.0), gen) for _ in range(3)]
+    calls = []
+
+    def run():
+        calls.append(1)
+        _gpu(mats, 24, 10, 2, 1e-10)
+        torch.cuda.synchronize()
+    buckets = ((256, 32), (256, 64))
+    try:
+        entries = autotune.tune_workload(run, "test_batch", buckets=buckets, reps=1, path=path)
+        assert len(calls) == 2 * len(autotune.VARIANTS)   # a warm-up and one timed run each
+        best = entries[0]["variant"]
+        assert best in autotune.VARIANTS and all(e["variant"] == best for e in entries)
+        assert len(entries[0]["workload_s"]) == len(autotune.VARIANTS)
+        assert _lib.tebd_tune_get(0, 256, 64) == best and _lib.tebd_tune_get(0, 200, 20) == best
+        with open(path) as f:
+            stored = {(e["rows"], e["width"]): e for e in json.load(f)["entries"]}
+        assert stored[(2048, 128)]["variant"] == 1                 # other buckets kept
+        assert stored[(256, 64)]["variant"] == best and stored[(256, 64)]["workload"] == "test_batch"
+        assert len(stored) == 3
+    finally:
+        for r, w in buckets:
+            _lib.tebd_tune_set(0, r, w, -1)
 
 
 def test_gram_qr_falls_back_on_a_rank_deficient_sketch():
