@@ -136,12 +136,22 @@ def test_tfim_sweeps_match_oracle_and_state_vector(adaptive):
     assert abs(omps.norm2(gm) - 1.0) < 1e-10
 
 
-@pytest.mark.parametrize("adaptive", [0, 1])
-def test_spin_boson_two_chains_match_oracle(adaptive):
+@pytest.mark.parametrize("adaptive,variant", [(0, -1), (1, -1), (1, 2), (0, 1)])
+def test_spin_boson_two_chains_match_oracle(adaptive, variant):
+    # variant: the sketch products' tile variant for the buckets these bonds
+    # fall in (-1: unset, the 32 x 32 tiles; 1: 64 x 64; 2: split-depth 16 x 16)
+    from paper_1504_00992_amd import _lib
     n, d, dt, steps, chi_max = 8, 4, 0.05, 6, 20
     dims, hb = om.spin_boson_chain(n, d, 1.0, 0.5, 1.0, 0.5)
     method = "rrsvd_adaptive" if adaptive else "rrsvd"
-    g = _gpu_tebd(2, dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10, adaptive)
+    buckets = ((128, 32), (128, 64))
+    try:
+        for r, w in buckets:
+            assert _lib.tebd_tune_set(0, r, w, variant) == 0
+        g = _gpu_tebd(2, dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10, adaptive)
+    finally:
+        for r, w in buckets:
+            _lib.tebd_tune_set(0, r, w, -1)
     for c in range(2):
         o = _oracle_tebd(dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10, chain=c, method=method)
         gam, lam = g.mps.to_host(c)
