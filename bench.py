@@ -1129,10 +1129,13 @@ def main():
     dims, hb = models.spin_boson(N, SB["d"], 1.0, 0.5, 1.0, 0.5)
     ev = Evolution(torch, api, dims, hb, [0] * N, args.chains, SB["chi_max"], SB["p"], SB["q"],
                    SB["dt"], SB["eps"], SB["seed"], adaptive=2 if adaptive else 0)
-    # the TEBD buckets of the cache are tuned on this evolution (untimed runs)
+    # the sweep table's entry for this evolution's capacities (d chi_max rows,
+    # chi_max + p width) is tuned on the evolution itself (untimed runs)
     if not any(e.get("workload") == "spin_boson_16x100" for e in tuned):
         t1 = time.perf_counter()
-        wl_entries = autotune.tune_workload(lambda: ev.timed(steps, 1, 0), "spin_boson_16x100")
+        cap = ((SB["d"] * SB["chi_max"], SB["chi_max"] + SB["p"]),)
+        wl_entries = autotune.tune_workload(lambda: ev.timed(steps, 1, 0), "spin_boson_16x100",
+                                            buckets=cap, precision=autotune.SWEEP_TABLE)
         tune_entry["workload_entries"] = wl_entries
         tune_entry["workload_seconds"] = round(time.perf_counter() - t1, 2)
         _progress(f"autotune on the evolution: variant {wl_entries[0]['variant']} "

@@ -342,6 +342,10 @@ tebd_status tebd_profile_read(int32_t capacity, const char** names, double* ms, 
  * entries); 1: 64 x 64 tiles; 2: 16 x 16 tiles, each split over the
  * contraction depth between the four wavefronts of its workgroup; -1
  * unsets.  precision 1 (complex FP32 products) has variant 0 only.
+ * precision 2 is the table of the TEBD entry points' FP64 products: it is
+ * read under the MPS capacities (d_max * chi_max rows, chi_max + p width)
+ * instead of a batch's bounds, so that every rank mode, graph capture
+ * included, takes the same variant (precision 0 serves rrsvd_truncate).
  * Variants 0 and 1 give identical results (the same K order per output
  * element); variant 2 adds four partial sums over interleaved k-steps, so
  * its results differ from theirs by rounding only.  The package's

@@ -88,26 +88,27 @@ def tune(buckets=((256, 64), (512, 80), (1024, 80), (2048, 80), (512, 128), (102
     return entries
 
 
-# Buckets of the TEBD sweeps (bond problems of at most 256 rows, sketch width
-# at most 64): a sweep batches a few large problems with many small ones, so
-# its sketch products are bound by the longest tile's chain of matrix-core
-# steps, which a batch of equal synthetic matrices does not show.  These are
-# tuned on the workload itself.
-SMALL_BUCKETS = ((128, 32), (128, 64), (256, 32), (256, 64))
+# TEBD sweeps read a table of their own (precision 2), bucketed by the MPS
+# capacities (d_max chi_max rows, chi_max + p width), so that every rank mode
+# takes the same variant.  A sweep batches a few large bond problems with
+# many small ones: its sketch products are bound by the longest tile's chain
+# of matrix-core steps, which a batch of equal synthetic matrices does not
+# show, so these entries are tuned on the workload itself.
+SWEEP_TABLE = 2
 
 
-def tune_workload(run, workload, buckets=SMALL_BUCKETS, reps=2, path=None):
-    """Tune `buckets` on a real workload: `run()` executes it once (device work
-    included).  Each variant is assigned to every bucket in turn and timed
-    over `reps` runs after one warm-up; the fastest is kept for all of them,
-    stored in the library and merged into the JSON cache (entries of other
-    buckets are kept).  Returns the new entries."""
+def tune_workload(run, workload, buckets, reps=2, path=None, precision=0):
+    """Tune `buckets` of table `precision` on a real workload: `run()` executes
+    it once (device work included).  Each variant is assigned to every bucket
+    in turn and timed over `reps` runs after one warm-up; the fastest is kept
+    for all of them, stored in the library and merged into the JSON cache
+    (entries of other buckets are kept).  Returns the new entries."""
     import time
     import torch
     times = []
     for v in VARIANTS:
         for rows, width in buckets:
-            _lib.check(_lib.tebd_tune_set(0, rows, width, v))
+            _lib.check(_lib.tebd_tune_set(precision, rows, width, v))
         run()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -116,11 +117,11 @@ def tune_workload(run, workload, buckets=SMALL_BUCKETS, reps=2, path=None):
         torch.cuda.synchronize()
         times.append((time.perf_counter() - t0) / reps)
     best = VARIANTS[min(range(len(times)), key=lambda i: times[i])]
-    entries = [{"precision": 0, "rows": int(r), "width": int(w), "variant": best,
+    entries = [{"precision": int(precision), "rows": int(r), "width": int(w), "variant": best,
                 "workload": workload, "workload_s": [round(t, 5) for t in times]}
                for r, w in buckets]
     for e in entries:
-        _lib.check(_lib.tebd_tune_set(0, e["rows"], e["width"], best))
+        _lib.check(_lib.tebd_tune_set(precision, e["rows"], e["width"], best))
     path = path or cache_path()
     try:
         with open(path) as f:

@@ -500,6 +500,8 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   c.nmax = int32_t(pl.mcap);
   c.lmax = int32_t(pl.lcap);
   c.mmin = c.nmin = c.lmin = 1;  // bond dimensions are only known on the device
+  c.tune_rows = int32_t(pl.mcap);
+  c.tune_width = int32_t(pl.lcap);
   c.kcap = prm->chi_max;
   c.tebd = 1;
   c.adaptive = prm->adaptive;

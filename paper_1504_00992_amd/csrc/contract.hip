@@ -486,7 +486,7 @@ __global__ __launch_bounds__(256) void k_sketch_split(Prob* probs, const int32_t
 namespace {
 constexpr int kTuneRows[6] = {128, 256, 512, 1024, 2048, 8192};
 constexpr int kTuneWidth[5] = {32, 64, 80, 128, 256};
-int8_t g_tune[2][6][5] = {};
+int8_t g_tune[3][6][5] = {};
 bool g_tune_init = false;
 
 int tune_bucket(const int* bounds, int nb, int v) {
@@ -496,17 +496,20 @@ int tune_bucket(const int* bounds, int nb, int v) {
 }
 }  // namespace
 
-int sketch_variant(int precision, int max_rows, int width) {
-  if (precision != 0 || !g_tune_init) return 0;
+int sketch_variant(int table, int max_rows, int width) {
+  if (table == 1 || !g_tune_init) return 0;
   const int br = tune_bucket(kTuneRows, 6, max_rows), bw = tune_bucket(kTuneWidth, 5, width);
   if (br < 0 || bw < 0) return 0;
-  const int v = g_tune[0][br][bw];
+  const int v = g_tune[table][br][bw];
   return v < 0 ? 0 : v;
 }
 
 hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s) {
-  const int rows = c.mmax > c.nmax ? c.mmax : c.nmax;
-  const int variant = sketch_variant(0, rows, c.lmax);
+  // a TEBD sweep reads its own table under the MPS capacities, so that every
+  // rank mode (host bounds or none, graph capture) takes the same variant
+  const bool sweep = c.tune_rows > 0;
+  const int rows = sweep ? c.tune_rows : (c.mmax > c.nmax ? c.mmax : c.nmax);
+  const int variant = sketch_variant(sweep ? 2 : 0, rows, sweep ? c.tune_width : c.lmax);
   if (variant == 1) {
     const dim3 g(grid_for(c, which == SK_YT_FROM_Y ? TK_SKN_W : TK_SKM_W));
     if (which == SK_Y_FROM_OMEGA)
@@ -727,7 +730,7 @@ hipError_t launch_tape(Prob* probs, const Common& c, hipStream_t s) {
 extern "C" tebd_status tebd_tune_set(int32_t precision, int32_t max_rows, int32_t width,
                                      int32_t variant) {
   using namespace tebd;
-  if (precision < 0 || precision > 1 || variant < -1 || variant > 2 ||
+  if (precision < 0 || precision > 2 || variant < -1 || variant > 2 ||
       (precision == 1 && variant > 0))
     return TEBD_ERR_ARG;
   const int br = tune_bucket(kTuneRows, 6, max_rows), bw = tune_bucket(kTuneWidth, 5, width);
@@ -744,7 +747,7 @@ extern "C" tebd_status tebd_tune_set(int32_t precision, int32_t max_rows, int32_
 
 extern "C" int32_t tebd_tune_get(int32_t precision, int32_t max_rows, int32_t width) {
   using namespace tebd;
-  if (precision < 0 || precision > 1 || max_rows < 1 || width < 1) return -1;
+  if (precision < 0 || precision > 2 || max_rows < 1 || width < 1) return -1;
   const int br = tune_bucket(kTuneRows, 6, max_rows), bw = tune_bucket(kTuneWidth, 5, width);
   if (br < 0 || bw < 0 || !g_tune_init) return -1;
   return g_tune[precision][br][bw];

@@ -128,6 +128,10 @@ struct Common {
                                   -1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
+  // TEBD sweeps: the capacity sizes (d_max chi_cap rows, the fixed-rank sketch
+  // width) under which the sweep table of the autotune cache is read, the same
+  // in every rank mode; 0 elsewhere (the launch's own bounds, table 0)
+  int32_t tune_rows = 0, tune_width = 0;
   int32_t serial = 0;  // 1: size classes run in order on the caller's stream (no side streams)
   // device: Accuracy Check, two counters of problems still probing (the
   // rounds alternate), then the widest basis so far
@@ -195,9 +199,12 @@ enum {
 static_assert(TK_COUNT == TK_COUNT_MAX, "Common::ktiles holds one total per kind");
 
 // Autotune cache: tile-shape variant of the sketch, power-iteration and
-// projection products (0: 32 x 32 tiles, 1: 64 x 64) for a launch whose
-// largest problem has max_rows rows and sketch width l (contract.hip).
-int sketch_variant(int precision, int max_rows, int width);
+// projection products (0: 32 x 32 tiles, 1: 64 x 64, 2: split-depth 16 x 16)
+// for a launch whose largest problem has max_rows rows and sketch width l;
+// table 0 the FP64 products of independent matrices, 1 the FP32 products,
+// 2 the FP64 products of TEBD sweeps (read under the MPS capacities)
+// (contract.hip).
+int sketch_variant(int table, int max_rows, int width);
 
 // Output tiles of the gate product of a group, (dl dr) x (sum of chi_l chi_r
 // over its members): 64 rows, and 16 columns while the group has few

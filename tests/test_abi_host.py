@@ -264,6 +264,10 @@ def test_autotune_cache_entries_and_json_round_trip(tmp_path):
     assert _lib.tebd_tune_set(0, 300, 70, 2) == _lib.TEBD_OK       # split-depth 16 x 16 tiles
     assert _lib.tebd_tune_get(0, 512, 80) == 2
     assert _lib.tebd_tune_set(0, 300, 70, 3) == _lib.TEBD_ERR_ARG
+    assert _lib.tebd_tune_set(2, 1000, 110, 2) == _lib.TEBD_OK      # the TEBD sweep table
+    assert _lib.tebd_tune_get(2, 1024, 128) == 2 and _lib.tebd_tune_get(0, 1024, 128) != 2
+    assert _lib.tebd_tune_set(2, 1000, 110, -1) == _lib.TEBD_OK
+    assert _lib.tebd_tune_set(3, 1000, 110, 0) == _lib.TEBD_ERR_ARG
     assert _lib.tebd_tune_set(0, 9000, 50, 0) == _lib.TEBD_ERR_SHAPE
     assert _lib.tebd_tune_set(0, 300, 300, 0) == _lib.TEBD_ERR_SHAPE
     assert _lib.tebd_tune_get(2, 10, 10) == -1

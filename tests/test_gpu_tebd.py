@@ -138,20 +138,18 @@ def test_tfim_sweeps_match_oracle_and_state_vector(adaptive):
 
 @pytest.mark.parametrize("adaptive,variant", [(0, -1), (1, -1), (1, 2), (0, 1)])
 def test_spin_boson_two_chains_match_oracle(adaptive, variant):
-    # variant: the sketch products' tile variant for the buckets these bonds
-    # fall in (-1: unset, the 32 x 32 tiles; 1: 64 x 64; 2: split-depth 16 x 16)
+    # variant: the sketch products' tile variant in the sweep table (2) at
+    # this MPS's capacities, d chi_max = 80 rows and chi_max + p = 30 columns
+    # (-1: unset, the 32 x 32 tiles; 1: 64 x 64; 2: split-depth 16 x 16)
     from paper_1504_00992_amd import _lib
     n, d, dt, steps, chi_max = 8, 4, 0.05, 6, 20
     dims, hb = om.spin_boson_chain(n, d, 1.0, 0.5, 1.0, 0.5)
     method = "rrsvd_adaptive" if adaptive else "rrsvd"
-    buckets = ((128, 32), (128, 64))
     try:
-        for r, w in buckets:
-            assert _lib.tebd_tune_set(0, r, w, variant) == 0
+        assert _lib.tebd_tune_set(2, d * chi_max, chi_max + 10, variant) == 0
         g = _gpu_tebd(2, dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10, adaptive)
     finally:
-        for r, w in buckets:
-            _lib.tebd_tune_set(0, r, w, -1)
+        _lib.tebd_tune_set(2, d * chi_max, chi_max + 10, -1)
     for c in range(2):
         o = _oracle_tebd(dims, hb, [0] * n, dt, steps, chi_max, 10, 1e-10, chain=c, method=method)
         gam, lam = g.mps.to_host(c)
