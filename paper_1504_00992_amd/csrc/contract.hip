@@ -542,12 +542,14 @@ hipError_t launch_sketch(Prob* probs, const Common& c, int which, hipStream_t s)
 
 // --------------------------------------------------------------------------
 // Kept singular vectors and lambda^-1 reabsorption
-struct LdQP {  // (r, k) -> Q[piv[k]*ld + r]: the columns of Q in the order P of B^H P = Q_B R_B (P = I when the QR of B^H keeps column order)
+// (r, k) -> Q[k*ld + r]: the range finder's Q, whose columns pair with those
+// of B^H = A^H Q; the QR of B^H keeps column order (its recorded permutation
+// is the identity), so no permutation is applied here.
+struct LdQP {
   const zt* p;
   int64_t ld;
-  const int32_t* piv;
   static constexpr bool contig_k = false;
-  __device__ zt operator()(int r, int k) const { return p[size_t(piv[k]) * ld + r]; }
+  __device__ zt operator()(int r, int k) const { return p[size_t(k) * ld + r]; }
 };
 struct LdSmallColB {  // B[k][c] = X[c*l + k], zero for c >= l
   const zt* p;
@@ -619,7 +621,7 @@ __device__ __forceinline__ void form_u_tile(Prob& P, int M, int N, int m0, int n
   if (P.retry) return;  // adaptive rank: stage 2 will write this problem
   const int chi = P.chi_new;
   const int Keff = (n0 >= chi) ? 0 : P.l;
-  LdQP la{P.Y, P.m, P.piv};
+  LdQP la{P.Y, P.m};
   LdSmallColB lb{P.X, P.l};
   if (TEBD_) {
     StGammaL st{P.gk, P.lam_l, P.lambda_floor, P.chi_l, P.chi_cap, chi};
@@ -672,7 +674,7 @@ __global__ __launch_bounds__(256) void k_tape_uv(Prob* probs, const int32_t* off
   __shared__ zt smem[Cfg64::lds_elems];
   auto tape_u = [&](Prob& P, int M, int N, int m0, int n0, int) {
     if (P.retry) return;
-    LdQP la{P.Y, P.m, P.piv};
+    LdQP la{P.Y, P.m};
     LdSmallColB lb{P.X, P.l};
     StRow st{P.tape_u, P.tape_ldu};
     zgemm_tile<Cfg64>(M, N, P.l, m0, n0, la, lb, st, smem);

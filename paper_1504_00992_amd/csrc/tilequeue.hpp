@@ -38,7 +38,7 @@ __device__ __forceinline__ int kind_tiles(int kind, const PT& P, int flag) {
 
 // Exclusive prefix sums of tile counts for every kind (one workgroup of
 // kScheduleThreads): thread t reads its contiguous chunk of problems once
-// and sums the tiles of every kind; a block-wide scan per kind (shuffle scan
+// and sums the tiles of every kind; a block-wide scan per kind (DPP scan
 // inside each wavefront, then one thread per kind scans the wavefront
 // totals) gives every chunk its starts; a second pass writes the chunk's
 // offsets (from the counts kept in registers when the chunk is one problem).
@@ -77,26 +77,21 @@ __device__ __forceinline__ void schedule_body(const PT* probs, int nprob, int fl
         }
     }
   }
+  const auto add = [](int32_t a, int32_t b) { return a + b; };
 #pragma unroll
   for (int k = 0; k < NK; ++k) {
-    int32_t v = own[k];
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int32_t t = __shfl_up(v, off, 64);
-      if (lane >= off) v += t;
-    }
+    const int32_t v = wave_scan_i32(own[k], 0, add);
     incl[k] = v;
     if (lane == 63) wsum[k][wave] = v;
   }
-  if constexpr (BOUNDS) {  // wavefront minima and maxima (empty lanes: INT32_MAX, 0)
+  if constexpr (BOUNDS) {  // wavefront minima and maxima (empty lanes: INT32_MAX, 0), in lane 63
+    const auto mn = [](int32_t a, int32_t b) { return a < b ? a : b; };
+    const auto mx = [](int32_t a, int32_t b) { return a > b ? a : b; };
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        lo[i] = min(lo[i], __shfl_xor(lo[i], off, 64));
-        hi[i] = max(hi[i], __shfl_xor(hi[i], off, 64));
-      }
-      if (lane == 0) {
+      lo[i] = wave_scan_i32(lo[i], INT32_MAX, mn);
+      hi[i] = wave_scan_i32(hi[i], INT32_MIN, mx);
+      if (lane == 63) {
         wext[2 * i][wave] = lo[i];
         wext[2 * i + 1][wave] = hi[i];
       }

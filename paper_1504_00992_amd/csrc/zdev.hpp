@@ -105,6 +105,22 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Inclusive scan of int32 values over the wavefront with an associative op
+// and its identity: DPP row_shr 1, 2, 4, 8 within each 16-lane row (a lane
+// whose source lies before its row's start reads the identity), then
+// row_bcast15 into rows 1 and 3 and row_bcast31 into rows 2 and 3 (the other
+// rows read the identity).  Lane 63 ends with the reduction of all 64.
+template <class Op>
+__device__ __forceinline__ int32_t wave_scan_i32(int32_t v, int32_t identity, Op op) {
+  v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x111, 0xf, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x112, 0xf, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x114, 0xf, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x118, 0xf, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x142, 0xa, 0xf, false));
+  v = op(v, __builtin_amdgcn_update_dpp(identity, v, 0x143, 0xc, 0xf, false));
+  return v;
+}
+
 // Uniform read of lane `src` (src uniform across the wavefront).
 __device__ __forceinline__ double read_lane(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
