@@ -532,9 +532,9 @@ tebd_status enqueue_sweep(const tebd_mps* mps, const tebd_z* gates, int64_t gate
   // thread, with a quarter of headroom: any grid covers every tile (the
   // launches are persistent), so the estimate only affects speed.
   static thread_local int32_t last_tiles[2][TK_COUNT] = {
-      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1},
-      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1}};
-  static_assert(TK_COUNT == 17, "one -1 per tile kind above");
+      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1},
+      {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1}};
+  static_assert(TK_COUNT == 16, "one -1 per tile kind above");
   if (c.adaptive == 3) {
     c.acc_count = c.retry_count + kAccCountSlot;
     c.acc_lcap = int32_t(pl.lcap);

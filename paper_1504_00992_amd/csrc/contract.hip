@@ -28,7 +28,6 @@
 namespace tebd {
 
 using Cfg64 = ZCfg<64, 64, 16, 2, 2>;
-using CfgGate = ZCfg<kGateTileM, kGateTileN, 16, 4, 1>;
 // Sketch and power-iteration products: 32 x 32 tiles (kSketchTileM/N).
 using CfgSk = ZCfg<kSketchTileM, kSketchTileN, 16, 2, 2>;
 // Theta's contraction depth is the old bond dimension chi_m, often 1 to a
@@ -185,24 +184,18 @@ struct StGateGroup {
   }
 };
 
-constexpr int kGateNarrow = 4;  // gate tiles with at most this many columns use the ALU
-
-// One output tile (m0, n0) of the gate product of the group whose first
-// member is probs[lead] (member k at lead + k gstride): rows (i j), columns
-// the members' (a b) side by side.  Then one Frobenius partial per member with columns in the tile: the
-// tile's |A|^2 summed over rows, then over the member's columns, in order.
-template <class Cfg, bool NARROW>
+// One 16 x 16 tile of the group product, its depth d_l d_r split
+// between the workgroup's four wavefronts (zgemm_tile_split16).
 __device__ __forceinline__ void gate_group_tile(Prob* probs, int lead, int M, int N, int m0,
-                                                int n0, zt* smem, GateCol* cols, double* csum) {
-  constexpr int BM = Cfg::BM, BN = Cfg::BN;
+                                                      int n0, double* f2, double* red,
+                                                      GateCol* cols, double* csum) {
+  constexpr int BM = kGateTileM, BN = kGateTileN;
   const Prob& L = probs[lead];
   const int tid = threadIdx.x, gn = L.gn, gs = L.gstride;
   if (tid < BN) {
     const int c = n0 + tid;
     GateCol g{nullptr, nullptr, 0, 0};
     if (c < N) {
-      // the last member starting at or before c owns it (a member without
-      // columns starts where the next one does)
       int q = 0;
       for (int k = 1; k < gn; ++k)
         if (probs[lead + k * gs].gcol0 <= c) q = k;
@@ -218,15 +211,10 @@ __device__ __forceinline__ void gate_group_tile(Prob* probs, int lead, int M, in
   __syncthreads();
   LdGate la{L.gate, L.gate_ld};
   LdRowB lb{L.T, L.gtot};
-  double* f2 = reinterpret_cast<double*>(smem);
   StGateGroup<BN> st{cols, f2, m0, n0, L.dr};
   const int K = L.dl * L.dr;
   const int ncol = N - n0 < BN ? N - n0 : BN;
-  if (NARROW && ncol <= kGateNarrow)
-    zgemm_narrow_tile<Cfg, kGateNarrow>(M, N, K, m0, n0, ncol, la, lb, st, smem);
-  else
-    zgemm_tile<Cfg>(M, N, K, m0, n0, la, lb, st, smem);
-  __syncthreads();  // every entry of f2 in range is written
+  zgemm_tile_split16(M, N, K, m0, n0, la, lb, st, red);  // ends with a barrier: f2 is written
   const int rows = M - m0 < BM ? M - m0 : BM;
   if (tid < ncol) {
     double sum = 0.0;
@@ -248,32 +236,21 @@ __device__ __forceinline__ void gate_group_tile(Prob* probs, int lead, int M, in
   __syncthreads();  // the column table and the LDS are free for the next tile
 }
 
-using CfgGateW = ZCfg<kGateTileM, kGateTileW, 16, 2, 2>;
-static_assert(CfgGateW::lds_elems * sizeof(zt) >= kGateTileM * kGateTileW * sizeof(double) &&
-                  CfgGate::lds_elems * sizeof(zt) >= kGateTileM * kGateTileN * sizeof(double),
-              "the |A|^2 tile fits in the operand staging area");
-constexpr size_t kGateLds =
-    CfgGateW::lds_elems > CfgGate::lds_elems ? CfgGateW::lds_elems : CfgGate::lds_elems;
-
-__global__ __launch_bounds__(256, 2) void k_gate(Prob* probs, const int32_t* offs, int nprob) {
-  __shared__ zt smem[kGateLds];
-  __shared__ GateCol cols[kGateTileW];
-  __shared__ double csum[kGateTileW];
-  for_each_tile2<TK_GATE, TK_GATE_W>(
-      probs, offs, nprob, 1,
-      [&](Prob& P, int M, int N, int m0, int n0, int) {
-        gate_group_tile<CfgGate, true>(probs, int(&P - probs), M, N, m0, n0, smem, cols, csum);
-      },
-      [&](Prob& P, int M, int N, int m0, int n0, int) {
-        gate_group_tile<CfgGateW, false>(probs, int(&P - probs), M, N, m0, n0, smem, cols, csum);
-      });
+__global__ __launch_bounds__(256) void k_gate(Prob* probs, const int32_t* offs, int nprob) {
+  __shared__ double f2[kGateTileM * kGateTileN];
+  __shared__ double red[2048];
+  __shared__ GateCol cols[kGateTileN];
+  __shared__ double csum[kGateTileN];
+  for_each_tile<TK_GATE>(probs, offs, nprob, 1, [&](Prob& P, int M, int N, int m0, int n0, int) {
+    gate_group_tile(probs, int(&P - probs), M, N, m0, n0, f2, red, cols, csum);
+  });
 }
 
 hipError_t launch_theta_gate(Prob* probs, const Common& c, hipStream_t s) {
   TEBD_LAUNCH("k_theta", k_theta, dim3(grid_for(c, TK_THETA)), dim3(256), 0, s, probs, c.offs, c.nprob);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  TEBD_LAUNCH("k_gate", k_gate, dim3(grid_for(c, TK_GATE, TK_GATE_W)), dim3(256), 0, s, probs,
+  TEBD_LAUNCH("k_gate", k_gate, dim3(grid_for(c, TK_GATE)), dim3(256), 0, s, probs,
               c.offs, c.nprob);
   return hipGetLastError();
 }

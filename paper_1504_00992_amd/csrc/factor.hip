@@ -144,7 +144,6 @@ __device__ __forceinline__ void plan_item(int t, Prob* probs, int nprob, const t
   P.gcol0 = gcol0;
   P.gtot = gtot;
   P.gn = chain == c0 ? gsz : 0;
-  P.gtw = gtot > kGateWideCols ? kGateTileW : kGateTileN;
   P.gstride = nb;
   P.T = reinterpret_cast<zt*>(theta_base + (size_t(bi) * mps.n_chains + c0) * theta_stride);
   P.lda = P.n;
@@ -1598,7 +1597,7 @@ __device__ __forceinline__ void truncate_tail(Prob& P, int l, double eps, int te
   // ||A||_F^2 from the partial sums, the gate product's (TEBD) or k_frob's:
   // loaded kTailChunk at a time, added by thread 0 in index order
   const int npart =
-      tebd ? gate_partials(P.dl * P.dr, P.gcol0, P.chi_l * P.chi_r, P.gtw) : kFrobSlices;
+      tebd ? gate_partials(P.dl * P.dr, P.gcol0, P.chi_l * P.chi_r) : kFrobSlices;
   __syncthreads();  // the singular values are in place
   // one round of global reads: the first chunk of partial sums, and whether
   // an outer lambda is at or below the floor (its inverse was taken as 0)
@@ -2016,7 +2015,7 @@ __global__ __launch_bounds__(256) void k_acc_resid(Prob* probs, double eps, int3
     mx = fmax(mx, sqrt(v));
   }
   double frob2 = 0.0;
-  const int npart = gate_partials(P.dl * P.dr, P.gcol0, P.chi_l * P.chi_r, P.gtw);
+  const int npart = gate_partials(P.dl * P.dr, P.gcol0, P.chi_l * P.chi_r);
   for (int i = 0; i < npart; ++i) frob2 += P.part[i];
   const double tol = sqrt(eps) * sqrt(frob2) / kAccConst;
   const bool grow = finite && mx > tol;

@@ -48,9 +48,9 @@ struct Prob {
   // Gate groups (TEBD): consecutive problems of one bond that share its gate
   // form one product G [Theta_1 | Theta_2 | ...] over all their columns.
   // gtot: the group's columns (every member), gn: members (the first member
-  // only, else 0), gtw: the group's gate tile width (16 or 64), gstride: the
-  // distance between the descriptors of consecutive members
-  int32_t gtot, gn, gtw, gstride;
+  // only, else 0), gstride: the distance between the descriptors of
+  // consecutive members
+  int32_t gtot, gn, gstride;
   double frob2;                      // ||A||_F^2, written on the device
   // input matrix (row-major, leading dim lda) and test matrix (row-major n x l)
   zt* A;
@@ -101,7 +101,7 @@ struct Prob {
   int32_t tape_ldu, tape_ldvh;
 };
 
-constexpr int TK_COUNT_MAX = 17;  // tile kinds of the forward pipeline (enum below)
+constexpr int TK_COUNT_MAX = 16;  // tile kinds of the forward pipeline (enum below)
 
 // Parameters of a launch sequence that are common to all problems.
 struct Common {
@@ -124,7 +124,7 @@ struct Common {
   int32_t* retry_count;  // device: problems whose first stage was rejected (adaptive rank)
   int32_t* bounds_dev = nullptr;  // host-mapped pinned memory: k_schedule writes {min, max}
                                   // of m, n, l1 there, then the tile total of every kind
-  int32_t ktiles[TK_COUNT_MAX] = {-1, -1, -1, -1, -1, -1, -1, -1, -1,
+  int32_t ktiles[TK_COUNT_MAX] = {-1, -1, -1, -1, -1, -1, -1, -1,
                                   -1, -1, -1, -1, -1, -1, -1, -1};  // host copy of the totals (-1: unknown)
   int32_t* offs;     // device: per tile kind, exclusive prefix sums of tile counts [nprob + 1]
   int32_t grid;      // workgroups of the persistent contraction launches (multiple of 8)
@@ -190,10 +190,9 @@ enum {
   TK_GRAM = 11,  // Gram-based QR: l x l Gram matrices Y^H Y
   TK_QAPM = 12,  // Gram-based QR: m x l products Y R^-1
   TK_QAPN = 13,  // Gram-based QR: n x l products Yt R^-1
-  TK_GATE_W = 14, // gate groups with many columns: 64 x 64 tiles
-  TK_SKM_S = 15, // TK_SKM on 16 x 16 tiles (the split-depth sketch variant)
-  TK_SKN_S = 16, // TK_SKN on 16 x 16 tiles
-  TK_COUNT = 17
+  TK_SKM_S = 14, // TK_SKM on 16 x 16 tiles (the split-depth sketch variant)
+  TK_SKN_S = 15, // TK_SKN on 16 x 16 tiles
+  TK_COUNT = 16
 };
 
 static_assert(TK_COUNT == TK_COUNT_MAX, "Common::ktiles holds one total per kind");
@@ -207,21 +206,21 @@ static_assert(TK_COUNT == TK_COUNT_MAX, "Common::ktiles holds one total per kind
 int sketch_variant(int table, int max_rows, int width);
 
 // Output tiles of the gate product of a group, (dl dr) x (sum of chi_l chi_r
-// over its members): 64 rows, and 16 columns while the group has few
-// columns (early in an evolution most bonds have chi_l chi_r = 1, and a
-// 64 x 64 tile would spend almost all of its FP64 matrix-core work on
-// padding), else 64.  Members of at most kGateGroup consecutive chains.
-constexpr int kGateTileM = 64, kGateTileN = 16, kGateTileW = 64;
+// over its members): 16 x 16, each tile's depth dl dr split over the four
+// wavefronts of its workgroup.  The product is short and wide (dl dr rows,
+// the members' columns), so small tiles give the launch enough workgroups
+// and waste little FP64 matrix-core work on padding when most bonds have
+// chi_l chi_r = 1.  Members of at most kGateGroup consecutive chains.
+constexpr int kGateTileM = 16, kGateTileN = 16;
 constexpr int kGateGroup = 32;
-constexpr int kGateWideCols = 48;  // groups with more columns take the 64-wide tiles
 
 // Frobenius partial sums of one problem: one per (row tile, column tile
 // that holds some of its columns) of its group's gate product, in row-tile
 // major order.
-__host__ __device__ inline int gate_partials(int rows, int col0, int cols, int tw) {
-  if (rows <= 0 || cols <= 0 || tw <= 0) return 0;
+__host__ __device__ inline int gate_partials(int rows, int col0, int cols) {
+  if (rows <= 0 || cols <= 0) return 0;
   const int rt = (rows + kGateTileM - 1) / kGateTileM;
-  return rt * ((col0 + cols - 1) / tw - col0 / tw + 1);
+  return rt * ((col0 + cols - 1) / kGateTileN - col0 / kGateTileN + 1);
 }
 // Capacity: a member's columns start anywhere in a 16-wide tile.
 __host__ __device__ inline int gate_partials_cap(int rows, int cols) {

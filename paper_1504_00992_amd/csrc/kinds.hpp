@@ -42,24 +42,23 @@ struct TileKinds<Prob> {
            kind == TK_QAPN;
   }
   static constexpr int tile_m(int kind) {
-    return kind == TK_GATE || kind == TK_GATE_W       ? kGateTileM
-           : kind == TK_SKM_S || kind == TK_SKN_S     ? kSketchTileS
-           : small_tiles(kind)                        ? kSketchTileM
-                                                      : 64;
+    return kind == TK_GATE                      ? kGateTileM
+           : kind == TK_SKM_S || kind == TK_SKN_S ? kSketchTileS
+           : small_tiles(kind)                    ? kSketchTileM
+                                                  : 64;
   }
   // TK_SKM_W / TK_SKN_W: the same products on 64 x 64 tiles
   static constexpr int tile_n(int kind) {
     return kind == TK_GATE                        ? kGateTileN
-           : kind == TK_GATE_W                    ? kGateTileW
            : kind == TK_SKM_S || kind == TK_SKN_S ? kSketchTileS
            : small_tiles(kind)                    ? kSketchTileN
                                                   : 64;
   }
   __device__ static __forceinline__ void shape(int kind, const Prob& P, int tebd, int& M, int& N) {
     M = N = 0;
-    if (kind == TK_GATE || kind == TK_GATE_W) {
+    if (kind == TK_GATE) {
       // the group's tiles belong to its first member, whatever its own state
-      if (tebd && P.gn > 0 && P.gtot > 0 && (P.gtw == kGateTileW) == (kind == TK_GATE_W)) {
+      if (tebd && P.gn > 0 && P.gtot > 0) {
         M = P.dl * P.dr;
         N = P.gtot;
       }

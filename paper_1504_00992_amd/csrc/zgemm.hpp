@@ -228,48 +228,6 @@ __device__ void zgemm_tile_split16(int M, int N, int K, int m0, int n0, const LA
   __syncthreads();  // red is read before the next tile writes it
 }
 
-// Narrow tiles (at most NC of the BN columns in range): the same staging,
-// with the product formed on the vector ALU (thread t < BM owns row
-// m0 + t, reading its column of the A slab and broadcast B entries from
-// LDS), since a 16 x 16 MFMA block would spend most of its work on padding.
-template <class Cfg, int NC, class LA, class LB, class ST>
-__device__ void zgemm_narrow_tile(int M, int N, int K, int m0, int n0, int ncol, const LA& la,
-                                  const LB& lb, ST& st, zt* smem) {
-  static_assert(Cfg::BM <= Cfg::NT && NC <= Cfg::BN, "one thread per row");
-  zt* As = smem;
-  zt* Bs = smem + Cfg::BK * Cfg::LDA;
-  const int tid = threadIdx.x;
-  double acr[NC], aci[NC];
-#pragma unroll
-  for (int c = 0; c < NC; ++c) acr[c] = aci[c] = 0.0;
-  zt ra[Cfg::NA], rb[Cfg::NB];
-  if (K > 0) zgemm_load<Cfg>(M, N, K, m0, n0, 0, la, lb, ra, rb);
-  for (int k0 = 0; k0 < K; k0 += Cfg::BK) {
-    zgemm_stage<Cfg, LA, LB>(As, Bs, ra, rb);
-    __syncthreads();
-    if (k0 + Cfg::BK < K) zgemm_load<Cfg>(M, N, K, m0, n0, k0 + Cfg::BK, la, lb, ra, rb);
-    if (tid < Cfg::BM) {
-#pragma unroll
-      for (int kk = 0; kk < Cfg::BK; ++kk) {
-        const zt a = As[kk * Cfg::LDA + tid];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          const zt b = Bs[kk * Cfg::LDB + c];
-          acr[c] = fma(a.x, b.x, fma(-a.y, b.y, acr[c]));
-          aci[c] = fma(a.x, b.y, fma(a.y, b.x, aci[c]));
-        }
-      }
-    }
-    __syncthreads();
-  }
-  const int row = m0 + tid;
-  if (tid < Cfg::BM && row < M) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (c < ncol) st(row, n0 + c, make_double2(acr[c], aci[c]));
-  }
-}
-
 // Complex FP32 variant for the mixed-precision sketch and power-iteration
 // products: the same tiles and loaders (FP64 operands are rounded to FP32
 // when staged into LDS), v_mfma_f32_16x16x4_f32 with FP32 accumulation.
