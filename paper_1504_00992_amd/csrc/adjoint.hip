@@ -43,6 +43,7 @@ struct TileKinds<AdjProb> {
   static constexpr int count = TA_COUNT;
   static constexpr int tile_m(int) { return 64; }
   static constexpr int tile_n(int) { return 64; }
+  static constexpr bool col_major(int) { return false; }
   __device__ static __forceinline__ void shape(int kind, const AdjProb& P, int, int& M, int& N) {
     M = N = 0;
     if (P.L == 0) return;

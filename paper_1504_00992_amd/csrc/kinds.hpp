@@ -54,6 +54,10 @@ struct TileKinds<Prob> {
            : small_tiles(kind)                    ? kSketchTileN
                                                   : 64;
   }
+  // The gate product is short and wide (d_l d_r rows): the row tiles of a
+  // column block run one after another, on one XCD, and share its Theta
+  // columns in that XCD's L2; the whole gate matrix stays there too.
+  static constexpr bool col_major(int kind) { return kind == TK_GATE; }
   __device__ static __forceinline__ void shape(int kind, const Prob& P, int tebd, int& M, int& N) {
     M = N = 0;
     if (kind == TK_GATE) {

@@ -13,7 +13,10 @@
 //   static __device__ void shape(int kind, const PT&, int flag, int& M, int& N);
 // (M x N = 0 x 0 when the problem has no tiles of that kind),
 //   static constexpr int tile_m(int kind), tile_n(int kind);   the kind's tile
-// (64 x 64 unless a kind's shapes call for another), and, for
+// (64 x 64 unless a kind's shapes call for another),
+//   static constexpr bool col_major(int kind);   tiles of a problem numbered
+// down the columns (the row tiles of one column block consecutive) instead
+// of along the rows, and, for
 // k_schedule<PT, true>, static __device__ bool dims(const PT&, int d[3])
 // (false for an inactive problem).
 #pragma once
@@ -187,11 +190,19 @@ __device__ __forceinline__ void run_tile(PT* probs, const int32_t* off, int npro
   // a size may have shrunk since the queue was built (the range finder
   // lowers l): tiles of the old shape that now lie outside are skipped
   constexpr int TM = TileKinds<PT>::tile_m(KIND), TN = TileKinds<PT>::tile_n(KIND);
-  const int tiles_n = (N + TN - 1) / TN;
-  if (tiles_n == 0) return;
-  const int tm = local / tiles_n, tn = local - tm * tiles_n;
-  if (tm * TM >= M) return;
-  body(P, M, N, tm * TM, tn * TN, local);
+  if constexpr (TileKinds<PT>::col_major(KIND)) {
+    const int tiles_m = (M + TM - 1) / TM;
+    if (tiles_m == 0) return;
+    const int tn = local / tiles_m, tm = local - tn * tiles_m;
+    if (tn * TN >= N) return;
+    body(P, M, N, tm * TM, tn * TN, local);
+  } else {
+    const int tiles_n = (N + TN - 1) / TN;
+    if (tiles_n == 0) return;
+    const int tm = local / tiles_n, tn = local - tm * tiles_n;
+    if (tm * TM >= M) return;
+    body(P, M, N, tm * TM, tn * TN, local);
+  }
 }
 
 // Iterate over this workgroup's tiles of one kind.
